@@ -1,0 +1,16 @@
+"""Seeded synthetic input generators shared by the tests, the benchmark and the oracle.
+
+This package holds no arithmetic of the method: it only produces meshes (element
+vertex coordinates), initial velocity fields and seeded random data.  Both the
+CPU oracle (``oracle/``) and the GPU library consume what it produces; neither
+side's computations live here.
+"""
+from .meshes import periodic_split_square, element_order  # noqa: F401
+from .fields import (  # noqa: F401
+    taylor_green_2d,
+    double_shear_layer,
+    RandomStreamField,
+    random_broken_poly,
+    eval_broken_poly,
+    n_monomials,
+)
