@@ -1,0 +1,218 @@
+/*
+ * dfdg.h — C ABI of the MI355X explicit divergence-free DG library.
+ *
+ * Method: G. Fu, "An explicit divergence-free DG method for incompressible flow".
+ * The library advances the velocity-only semi-discrete system
+ *      M du/dt = L(u),   u in V_h^{k,-1} = { v in BDM_k : div v = 0 }          (Sec. 2.3)
+ * with L(u)(v) = -C_h(u; u, v) - B_h(u, v): upwind convection (Sec. 2.2, eq. (adv))
+ * plus symmetric interior-penalty viscosity with penalty nu*alpha*k^2/h (Sec. 3,
+ * eq. (viscous)).  The divergence-free mass inversion M^{-1} is done as the
+ * hybrid-mixed Poisson problem of eq. (FE3): element-local static condensation onto
+ * facet multipliers, a global symmetric positive semi-definite facet system solved by
+ * preconditioned CG, and element-local recovery (Theorem 2).  Time stepping is
+ * TVD-RK3 (eq. (rk3)).  Two-dimensional periodic triangle meshes are supported.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Ownership.  Pointers named *_dev are device pointers owned by the caller.  The
+ *   library never allocates device memory: dfdg_ctx_workspace_bytes() reports the
+ *   size of one workspace the caller allocates and hands over with
+ *   dfdg_ctx_bind_workspace(); it must stay alive and untouched until
+ *   dfdg_ctx_destroy().  Pointers named *_host are host pointers, read or written
+ *   during the call only.  The library keeps one pinned host buffer per context.
+ * Streams.  All device work of a context is enqueued on the HIP stream given to
+ *   dfdg_ctx_create() (or dfdg_ctx_set_stream()).  Calls that return numbers to the
+ *   host (solve/step info, diagnostics) synchronise that stream; the others return
+ *   as soon as their work is enqueued.
+ * Errors.  Every int-returning function returns DFDG_OK (0) or a negative status.
+ *   Arguments, mesh and workspace are validated on the host before any device work;
+ *   dfdg_last_error() gives a message for the last failing call on a context,
+ *   dfdg_mesh_last_error() for mesh creation.  A context is not thread safe.
+ * Layouts (all FP64 unless stated).
+ *   T elements, E facets, P = (k+1)(k+2)/2, n_f = k+1.
+ *   Velocity-like vectors (U, L, F, adjoints): [2][P][T] — component c, basis
+ *   function i, element t at index (c*P + i)*T + t.  The basis of element t is
+ *   psi_i(x) = psihat_i(xhat)/sqrt(|det J_t|) e_c, with psihat_i the L2-orthonormal
+ *   Dubiner polynomials of the reference triangle, so the element mass matrix is the
+ *   identity, kinetic energy is 0.5*sum(U^2), and a functional F is stored by its
+ *   values F(psi_i e_c).  xhat are the reference coordinates with respect to the
+ *   element's vertices as passed to dfdg_mesh_create: x = v0 + xi (v1-v0) + eta (v2-v0).
+ *   Facet multipliers lambda: [E][n_f], Legendre coefficients along the facet (the
+ *   facet numbering is the library's; see dfdg_mesh_facets).
+ */
+#ifndef DFDG_H
+#define DFDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DFDG_OK = 0,
+  DFDG_E_INVALID_ARG = -1,  /* null pointer, out-of-range parameter, bad size */
+  DFDG_E_MESH = -2,         /* unmatched facet, inverted or degenerate element */
+  DFDG_E_WORKSPACE = -3,    /* workspace missing, too small or misaligned */
+  DFDG_E_HIP = -4,          /* a HIP runtime call failed */
+  DFDG_E_NOT_CONVERGED = -5,/* PCG hit its iteration limit (result still written) */
+  DFDG_E_NONFINITE = -6,    /* NaN/Inf met in a reduction */
+  DFDG_E_BREAKDOWN = -7,    /* non-positive curvature (p, S p) <= 0 in PCG */
+  DFDG_E_UNSUPPORTED = -8   /* valid request this build does not implement */
+};
+
+enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
+enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1 };   /* dfdg_params.precond */
+
+typedef struct dfdg_mesh dfdg_mesh;
+typedef struct dfdg_ctx dfdg_ctx;
+
+typedef struct {
+  int k;             /* polynomial degree of BDM_k, 1..3 */
+  double nu;         /* viscosity >= 0 (0: Euler) */
+  double alpha;      /* SIPG penalty constant, > 0 (the paper uses 2, Sec. 4) */
+  int precision;     /* DFDG_FP64 or DFDG_MIXED */
+  double cg_rtol;    /* PCG stop: ||g - S lambda||_2 <= cg_rtol ||g||_2 (FP64 path) */
+  int cg_maxit;      /* PCG iteration limit per solve */
+  int precond;       /* DFDG_JACOBI or DFDG_BLOCK_JACOBI */
+  double ir_rtol;    /* MIXED: outer FP64 refinement target (relative residual) */
+  double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
+  int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,
+                        1..2 = polynomial extrapolation of that order in time */
+} dfdg_params;
+
+typedef struct {
+  int32_t T, E, k, P, n_f, n_p;
+  int64_t n_broken;   /* 2*P*T, length of velocity-like vectors */
+  int64_t n_lambda;   /* n_f*E */
+  int64_t n_bdm;      /* dim BDM_k = E*n_f + T*(2P - 3 n_f) */
+  int32_t nq_proj;    /* points of the projection rule (dfdg_proj_rule) */
+} dfdg_sizes;
+
+typedef struct {
+  int iterations;      /* PCG iterations (FP64) or total inner FP32 iterations (MIXED) */
+  int refinements;     /* MIXED: FP64 refinement steps; FP64: 0 */
+  double rel_residual; /* final ||g - S lambda|| / ||g|| (FP64 recomputed for MIXED) */
+  int status;          /* DFDG_OK, DFDG_E_NOT_CONVERGED, ... */
+} dfdg_solve_info;
+
+typedef struct {
+  int iterations[3];   /* PCG iterations of the three stages */
+  int max_refinements;
+  double max_rel_residual;
+  int status;
+} dfdg_step_info;
+
+typedef struct {
+  double energy;         /* 0.5 ||u_h||^2 */
+  double enstrophy;      /* ||curl_h u_h||^2 (element-wise curl) */
+  double max_div;        /* max |div u_h| over element quadrature points */
+  double max_normal_jump;/* max |[[u_h . n]]| over facet quadrature points */
+} dfdg_diag;
+
+/* ---- mesh (host only; a0 of the hot path) ---------------------------------------
+ * dfdg_mesh_create: elem_xyz_host[T][3][2] vertex coordinates of each triangle,
+ * counter-clockwise and non-degenerate; period_host[2] > 0 (both directions
+ * periodic; every facet must match another one modulo the period).  Facets are
+ * identified by their midpoints modulo the period.  Copies its inputs. */
+int dfdg_mesh_create(int dim, int n_elem, const double* elem_xyz_host,
+                     const double* period_host, dfdg_mesh** out);
+void dfdg_mesh_destroy(dfdg_mesh* mesh);
+const char* dfdg_mesh_last_error(void);
+/* facets_host[E][4]: element L, local facet of L, element R, local facet of R. */
+int dfdg_mesh_counts(const dfdg_mesh* mesh, int* T, int* E);
+int dfdg_mesh_facets(const dfdg_mesh* mesh, int32_t* facets_host);
+
+/* ---- context --------------------------------------------------------------------
+ * dfdg_ctx_create validates the parameters and does the host part of setup
+ * (reference tabulations, geometry, condensation matrices, facet matrix).
+ * hip_stream is a hipStream_t (NULL = default stream).  The mesh may be destroyed
+ * afterwards. */
+void dfdg_params_default(dfdg_params* p);
+int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* params, void* hip_stream,
+                    dfdg_ctx** out);
+int dfdg_ctx_set_stream(dfdg_ctx* ctx, void* hip_stream);
+int dfdg_ctx_sizes(const dfdg_ctx* ctx, dfdg_sizes* out);
+int dfdg_ctx_workspace_bytes(const dfdg_ctx* ctx, size_t* bytes);
+/* dev_ptr: 256-byte aligned device memory of at least the reported size.  Uploads
+ * the setup data (synchronous). */
+int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev_ptr, size_t bytes);
+const char* dfdg_last_error(const dfdg_ctx* ctx);
+void dfdg_ctx_destroy(dfdg_ctx* ctx);
+
+/* ---- initial data (a2) ------------------------------------------------------------
+ * dfdg_proj_rule: reference points ref_pts_host[nq_proj][2] and weights
+ * w_host[nq_proj] of the projection rule (exact for degree 2k+4).
+ * dfdg_load_vector: F(psi_i e_c) = int_T f . psi_i e_c for f given by its values
+ * f_at_q_dev[2][nq_proj][T] at those points (element t's point q is
+ * v0 + J xhat_q).  dfdg_project: load vector followed by dfdg_hdiv_mass_solve, i.e.
+ * the L2 projection onto V_h^{k,-1} (Sec. 2.3, with u0 divergence free). */
+int dfdg_proj_rule(const dfdg_ctx* ctx, double* ref_pts_host, double* w_host);
+int dfdg_load_vector(dfdg_ctx* ctx, const double* f_at_q_dev, double* F_dev);
+int dfdg_project(dfdg_ctx* ctx, const double* f_at_q_dev, double* U_dev,
+                 dfdg_solve_info* info);
+
+/* ---- hot path (a3-a7) -------------------------------------------------------------
+ * dfdg_dg_residual: L_dev = L(U) on the broken basis, L(u)(v) = -C_h(u;u,v) -
+ *   B_h(u,v) (eqs. (adv), (viscous)); upwinding per facet quadrature point on the
+ *   averaged normal velocity.
+ * dfdg_hdiv_mass_solve: U_dev = the u of eq. (FE3) for the functional F_dev, i.e. the
+ *   divergence-free mass inversion of F (Theorem 2).  lambda_io_dev ([E][n_f]) is
+ *   the PCG start on entry and the facet multiplier on exit; NULL = cold start.
+ *   Returns DFDG_E_NOT_CONVERGED/DFDG_E_BREAKDOWN if PCG failed (U_dev still written).
+ * dfdg_rk3_step: one TVD-RK3 step of size dt, in place on U_io_dev (eq. (rk3));
+ *   each stage is u + dt*M^{-1}L(u) combined as in the Shu-Osher form.  Multipliers of
+ *   earlier steps warm-start the PCG of the same stage. */
+int dfdg_dg_residual(dfdg_ctx* ctx, const double* U_dev, double* L_dev);
+int dfdg_hdiv_mass_solve(dfdg_ctx* ctx, const double* F_dev, double* U_dev,
+                         double* lambda_io_dev, dfdg_solve_info* info);
+int dfdg_rk3_step(dfdg_ctx* ctx, double* U_io_dev, double dt, dfdg_step_info* info);
+/* Forget the warm-start history of rk3_step (e.g. after changing U externally). */
+int dfdg_reset_history(dfdg_ctx* ctx);
+
+/* ---- adjoint form ------------------------------------------------------------------
+ * dfdg_dg_residual_vjp: Ubar_dev = J_L(U)^T Lbar_dev, the transpose of the
+ *   derivative of dfdg_dg_residual at U (upwind side frozen, the a.e. derivative).
+ * dfdg_rk3_step_vjp: given U^n (Un_dev) and the cotangent of U^{n+1}, writes the
+ *   cotangent of U^n (Ubar_io_dev in place) for one dfdg_rk3_step of size dt.
+ *   Recomputes the stage states; the mass solve is self-adjoint. */
+int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U_dev, const double* Lbar_dev,
+                         double* Ubar_dev);
+int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un_dev, double* Ubar_io_dev, double dt,
+                      dfdg_step_info* info);
+
+/* ---- diagnostics and evaluation (a10) -----------------------------------------------
+ * dfdg_eval: values out_dev[2][npts][T] of U at reference points ref_pts_host[npts][2]
+ *   (npts <= 1024) of every element. */
+int dfdg_diagnostics(dfdg_ctx* ctx, const double* U_dev, dfdg_diag* out_host);
+int dfdg_eval(dfdg_ctx* ctx, const double* U_dev, int npts, const double* ref_pts_host,
+              double* out_dev);
+
+/* ---- measurement -------------------------------------------------------------------
+ * dfdg_time_kernel: launches kernel `which` `reps` times back to back on the context
+ * stream between two HIP events and returns the mean time per launch in ms.
+ *   which = 0: facet SpMV + (p, S p) partials (FP64);  1: PCG vector update (FP64);
+ *   2: DG residual (FP64); 3: facet SpMV (FP32, MIXED contexts only).
+ * Inputs are the context's current PCG/stage vectors; the PCG state is left
+ * unchanged in meaning (the kernels are run in a no-op-free "timing" mode that does
+ * not advance the iteration).  bytes_out (may be NULL) receives the algorithmic
+ * bytes one launch moves. */
+int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms_per_launch,
+                     double* bytes_out);
+
+/* ---- host inspection (no device work; used by the CPU test-suite) ----------------------
+ * dfdg_debug_basis: the reference orthonormal basis psihat_i (i < P(k)) and its reference
+ *   gradients at npts points pts_host[npts][2]: vals_host[npts][P],
+ *   grads_host[npts][2][P] (may be NULL).
+ * dfdg_debug_facet_matrix: the facet matrix S assembled on the host at context creation,
+ *   as BSR: cols_host[5][E] (column facets) and vals_host[5][n_f][n_f][E]
+ *   (slot, row mode, column mode, facet row).  Repeated columns of a row are merged into
+ *   their first slot, the others hold zeros. */
+int dfdg_debug_basis(int k, int npts, const double* pts_host, double* vals_host, double* grads_host);
+int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols_host, double* vals_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFDG_H */

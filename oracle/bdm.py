@@ -93,5 +93,17 @@ class BDMSpace:
         vals, _ = poly_basis(self.k, pts[:, 0], pts[:, 1])
         return np.einsum("q,t,tcq,qa->tca", w, self.mesh.detJ, f_at_q, vals)
 
+    def broken_project(self, f_at_q, rule):
+        """Local coefficients cU[T, 2, nm] of the element-wise L2 projection onto [P^k]^2.
+
+        Reproduces broken polynomial data of degree <= k exactly when the rule is exact
+        for degree 2k.
+        """
+        pts, w = rule
+        vals, _ = poly_basis(self.k, pts[:, 0], pts[:, 1])
+        Mref = np.einsum("q,qa,qb->ab", w, vals, vals)
+        rhs = np.einsum("q,tcq,qa->tca", w, f_at_q, vals)
+        return np.linalg.solve(Mref, rhs.reshape(-1, self.nm).T).T.reshape(f_at_q.shape[0], 2, self.nm)
+
     def volume_rule(self, degree):
         return triangle_rule(degree)

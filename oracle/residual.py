@@ -61,16 +61,20 @@ class Residual:
             gv = np.einsum("qra,trj->tqja", self.vdm, Jinv)          # d m_a/dx_j
             out[sl] += np.einsum("q,t,tqcj,tqja->tca", self.vw, m.detJ[sl], flux, gv)
 
-    def facets(self, cU, out):
-        """Facet integrals of -C_h (upwind) and of -B_h (consistency, symmetry, penalty)."""
+    def facet_terms(self, cUA, cUB):
+        """Facet integrals of -C_h (upwind) and -B_h (consistency, symmetry, penalty).
+
+        cUA[E, 2, nm], cUB[E, 2, nm]: coefficients of the two sides of every facet.
+        Returns the contributions (RA, RB) to the test functions of sides A and B.
+        """
         m = self.mesh
         A, B = m.fA_elem, m.fB_elem
         n = m.normal                      # A's outward normal, [E, 2]
         nA, nB = n, -n
-        uA = np.einsum("eca,era->erc", cU[A], self.fmA)
-        uB = np.einsum("eca,era->erc", cU[B], self.fmB)
-        gA = np.einsum("eca,ersa,esj->ercj", cU[A], self.fdmA, m.Jinv[A])
-        gB = np.einsum("eca,ersa,esj->ercj", cU[B], self.fdmB, m.Jinv[B])
+        uA = np.einsum("eca,era->erc", cUA, self.fmA)
+        uB = np.einsum("eca,era->erc", cUB, self.fmB)
+        gA = np.einsum("eca,ersa,esj->ercj", cUA, self.fdmA, m.Jinv[A])
+        gB = np.einsum("eca,ersa,esj->ercj", cUB, self.fdmB, m.Jinv[B])
         # test-function gradients on each side
         tgA = np.einsum("ersa,esj->erja", self.fdmA, m.Jinv[A])
         tgB = np.einsum("ersa,esj->erja", self.fdmB, m.Jinv[B])
@@ -98,9 +102,13 @@ class Residual:
         # -nu alpha k^2/h [[u (x) n]] : [[v (x) n]]
         viscA -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nA, self.fmA)
         viscB -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nB, self.fmB)
+        return convA + viscA, convB + viscB
 
-        np.add.at(out, A, convA + viscA)
-        np.add.at(out, B, convB + viscB)
+    def facets(self, cU, out):
+        m = self.mesh
+        RA, RB = self.facet_terms(cU[m.fA_elem], cU[m.fB_elem])
+        np.add.at(out, m.fA_elem, RA)
+        np.add.at(out, m.fB_elem, RB)
 
     def broken(self, cU):
         """R[T, 2, nm] = L(u)(Phi_(c,a)) for the field with local coefficients cU."""

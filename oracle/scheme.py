@@ -179,15 +179,13 @@ class Oracle:
         return float(np.einsum("q,t,tq->", w, self.mesh.detJ, om * om))
 
 
-def hybrid_solve_dense(orc, Fbroken):
-    """Hybrid-mixed solve of eq. (FE3), written out densely (tiny meshes only).
+def hybrid_system_dense(orc):
+    """Dense matrix of the hybrid-mixed system of eq. (FE3) (tiny meshes only).
 
-    Unknowns: broken [P^k]^2 velocity (monomial basis per element), broken
-    P^{k-1} pressure w, facet multiplier lambda in P^k(F) (Legendre basis in the
-    facet parameter).  Fbroken[T, 2, nm] holds the functional on the broken
-    local basis.  The system is singular only by the constant (w, lambda) = (c, c);
-    it is solved in the least-squares sense.  Returns the velocity's local
-    coefficients cU[T, 2, nm].
+    Unknown order: broken velocity [T][2][nm] (local basis), broken pressure
+    [T][npr], facet multipliers [E][k+1] in the Legendre basis P_j(2s-1) of the
+    facet parameter s (side A's direction).  Rows: the three equations of (FE3),
+    signed so that the matrix is symmetric.  Returns (K, nU, nW).
     """
     m, sp_, k = orc.mesh, orc.space, orc.k
     T, E, nu, npr, nf = m.T, m.E, sp_.nu, sp_.np_, sp_.nf
@@ -221,7 +219,21 @@ def hybrid_solve_dense(orc, Fbroken):
                 for c in range(2):
                     K[t * nu + c * nm: t * nu + (c + 1) * nm, row] += mom * nT[c]
                     K[row, t * nu + c * nm: t * nu + (c + 1) * nm] += mom * nT[c]
+    return K, nU, nW
+
+
+def hybrid_solve_dense(orc, Fbroken):
+    """Hybrid-mixed solve of eq. (FE3), written out densely (tiny meshes only).
+
+    Unknowns: broken [P^k]^2 velocity (monomial basis per element), broken
+    P^{k-1} pressure w, facet multiplier lambda in P^k(F) (Legendre basis in the
+    facet parameter).  Fbroken[T, 2, nm] holds the functional on the broken
+    local basis.  The system is singular only by the constant (w, lambda) = (c, c);
+    it is solved in the least-squares sense.  Returns the velocity's local
+    coefficients cU[T, 2, nm].
+    """
+    K, nU, _ = hybrid_system_dense(orc)
     rhs = np.zeros(K.shape[0])
     rhs[:nU] = Fbroken.reshape(-1)
     sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
-    return sol[:nU].reshape(T, 2, nm)
+    return sol[:nU].reshape(orc.mesh.T, 2, orc.space.nm)

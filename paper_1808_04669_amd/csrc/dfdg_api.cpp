@@ -1,0 +1,767 @@
+// C ABI of the library (declared in include/dfdg.h): context management, workspace
+// layout, and the host-side orchestration of the hot path (residual -> condensation ->
+// facet PCG -> recovery, inside TVD-RK3).  Kernels are enqueued on the context stream;
+// the host only reads back PCG scalars every few iterations.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "dfdg.h"
+#include "dfdg_kernels.h"
+#include "dfdg_setup.h"
+
+using namespace dfdg;
+
+struct dfdg_mesh {
+  MeshHost m;
+};
+
+struct dfdg_ctx {
+  dfdg_params prm{};
+  hipStream_t stream = nullptr;
+  HostSetup hs;
+  int K = 0, P = 0, NF = 0, T = 0, E = 0;
+  long nU = 0, nL = 0;
+  size_t ws_need = 0;
+  char* ws = nullptr;
+  bool bound = false;
+  DevGeo g{};
+  DevTabs tb{};
+  DevBsr A{};
+  // work buffers
+  double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *z = nullptr,
+         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[3][3] = {}, *evaltab = nullptr,
+         *partials = nullptr, *diagres = nullptr, *r64 = nullptr;
+  float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
+        *Sp32 = nullptr;
+  PcgScalars *sc = nullptr, *sc32 = nullptr, *sct = nullptr;
+  // adjoint buffers
+  double *Ustages[3] = {nullptr, nullptr, nullptr}, *Ybar = nullptr, *Wbuf = nullptr;
+  int hist_count[3] = {0, 0, 0};
+  PcgScalars* pinned = nullptr;
+  std::string err;
+};
+
+static thread_local std::string g_mesh_err;
+
+static int fail(dfdg_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPC(x)                                                                           \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define NEED_BOUND(ctx)                                                                   \
+  do {                                                                                    \
+    if (!(ctx)) return DFDG_E_INVALID_ARG;                                                \
+    if (!(ctx)->bound) return fail(ctx, DFDG_E_WORKSPACE, "no workspace bound");          \
+  } while (0)
+
+// ---------------------------------------------------------------------------------------
+// mesh
+// ---------------------------------------------------------------------------------------
+extern "C" int dfdg_mesh_create(int dim, int n_elem, const double* xyz, const double* period, dfdg_mesh** out) {
+  if (!out) { g_mesh_err = "out is NULL"; return DFDG_E_INVALID_ARG; }
+  *out = nullptr;
+  if (dim == 3) { g_mesh_err = "three-dimensional meshes are not implemented"; return DFDG_E_UNSUPPORTED; }
+  if (dim != 2) { g_mesh_err = "dim must be 2"; return DFDG_E_INVALID_ARG; }
+  if (n_elem < 2 || !xyz || !period) { g_mesh_err = "need >= 2 elements, coordinates and a period"; return DFDG_E_INVALID_ARG; }
+  if (!(period[0] > 0) || !(period[1] > 0)) { g_mesh_err = "period must be positive"; return DFDG_E_INVALID_ARG; }
+  for (long i = 0; i < 6L * n_elem; ++i)
+    if (!std::isfinite(xyz[i])) { g_mesh_err = "non-finite vertex coordinate"; return DFDG_E_INVALID_ARG; }
+  auto* m = new dfdg_mesh;
+  std::string err;
+  int rc = build_mesh(n_elem, xyz, period, m->m, err);
+  if (rc) { g_mesh_err = err; delete m; return DFDG_E_MESH; }
+  *out = m;
+  return DFDG_OK;
+}
+extern "C" void dfdg_mesh_destroy(dfdg_mesh* m) { delete m; }
+extern "C" const char* dfdg_mesh_last_error(void) { return g_mesh_err.c_str(); }
+extern "C" int dfdg_mesh_counts(const dfdg_mesh* m, int* T, int* E) {
+  if (!m || !T || !E) return DFDG_E_INVALID_ARG;
+  *T = m->m.T;
+  *E = m->m.E;
+  return DFDG_OK;
+}
+extern "C" int dfdg_mesh_facets(const dfdg_mesh* m, int32_t* f) {
+  if (!m || !f) return DFDG_E_INVALID_ARG;
+  for (int F = 0; F < m->m.E; ++F) {
+    f[4 * F + 0] = m->m.fL[F];
+    f[4 * F + 1] = m->m.fLloc[F];
+    f[4 * F + 2] = m->m.fR[F];
+    f[4 * F + 3] = m->m.fRloc[F];
+  }
+  return DFDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// context and workspace
+// ---------------------------------------------------------------------------------------
+extern "C" void dfdg_params_default(dfdg_params* p) {
+  if (!p) return;
+  p->k = 2;
+  p->nu = 0.0;
+  p->alpha = 2.0;
+  p->precision = DFDG_FP64;
+  p->cg_rtol = 1e-12;
+  p->cg_maxit = 20000;
+  p->precond = DFDG_JACOBI;
+  p->ir_rtol = 1e-10;
+  p->inner_rtol = 1e-4;
+  p->extrapolate = 0;
+}
+
+static int check_params(const dfdg_params* p, std::string& e) {
+  if (p->k < 1 || p->k > kMaxK) { e = "k must be in 1..3"; return -1; }
+  if (!(p->nu >= 0) || !std::isfinite(p->nu)) { e = "nu must be finite and >= 0"; return -1; }
+  if (!(p->alpha > 0) || !std::isfinite(p->alpha)) { e = "alpha must be finite and > 0"; return -1; }
+  if (p->precision != DFDG_FP64 && p->precision != DFDG_MIXED) { e = "precision must be DFDG_FP64 or DFDG_MIXED"; return -1; }
+  if (!(p->cg_rtol > 0 && p->cg_rtol < 1)) { e = "cg_rtol must be in (0,1)"; return -1; }
+  if (p->cg_maxit < 1) { e = "cg_maxit must be >= 1"; return -1; }
+  if (p->precond != DFDG_JACOBI && p->precond != DFDG_BLOCK_JACOBI) { e = "unknown preconditioner"; return -1; }
+  if (p->precision == DFDG_MIXED) {
+    if (!(p->ir_rtol > 0 && p->ir_rtol < 1)) { e = "ir_rtol must be in (0,1)"; return -1; }
+    if (!(p->inner_rtol > 0 && p->inner_rtol < 1)) { e = "inner_rtol must be in (0,1)"; return -1; }
+  }
+  if (p->extrapolate < 0 || p->extrapolate > 2) { e = "extrapolate must be 0, 1 or 2"; return -1; }
+  return 0;
+}
+
+extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, void* stream, dfdg_ctx** out) {
+  if (!out) return DFDG_E_INVALID_ARG;
+  *out = nullptr;
+  if (!mesh || !prm) return DFDG_E_INVALID_ARG;
+  auto* ctx = new dfdg_ctx;
+  ctx->prm = *prm;
+  ctx->stream = (hipStream_t)stream;
+  std::string e;
+  if (check_params(prm, e)) {
+    g_mesh_err = e;
+    delete ctx;
+    return DFDG_E_INVALID_ARG;
+  }
+  if (build_setup(mesh->m, prm->k, prm->alpha, ctx->hs, e)) {
+    g_mesh_err = e;
+    delete ctx;
+    return DFDG_E_MESH;
+  }
+  ctx->K = prm->k;
+  ctx->P = nP(ctx->K);
+  ctx->NF = nF(ctx->K);
+  ctx->T = mesh->m.T;
+  ctx->E = mesh->m.E;
+  ctx->nU = 2L * ctx->P * ctx->T;
+  ctx->nL = (long)ctx->NF * ctx->E;
+  *out = ctx;
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_ctx_set_stream(dfdg_ctx* ctx, void* stream) {
+  if (!ctx) return DFDG_E_INVALID_ARG;
+  ctx->stream = (hipStream_t)stream;
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_ctx_sizes(const dfdg_ctx* ctx, dfdg_sizes* s) {
+  if (!ctx || !s) return DFDG_E_INVALID_ARG;
+  s->T = ctx->T;
+  s->E = ctx->E;
+  s->k = ctx->K;
+  s->P = ctx->P;
+  s->n_f = ctx->NF;
+  s->n_p = nPp(ctx->K);
+  s->n_broken = ctx->nU;
+  s->n_lambda = ctx->nL;
+  s->n_bdm = (long)ctx->E * ctx->NF + (long)ctx->T * (2 * ctx->P - 3 * ctx->NF);
+  s->nq_proj = ctx->hs.tabs.nqp;
+  return DFDG_OK;
+}
+
+// Workspace carving: a first pass with base == nullptr only counts bytes.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+static void carve(dfdg_ctx* ctx, char* base) {
+  Carver c{base};
+  const HostSetup& h = ctx->hs;
+  const long T = ctx->T, E = ctx->E, NF = ctx->NF, nU = ctx->nU, nL = ctx->nL;
+  const RefTables& tb = h.tabs;
+  DevGeo& g = ctx->g;
+  g.T = (int)T;
+  g.E = (int)E;
+  g.Jinv = c.take<double>(4 * T);
+  g.detJ = c.take<double>(T);
+  g.nbr = c.take<int>(3 * T);
+  g.code = c.take<int>(3 * T);
+  g.efacet = c.take<int>(3 * T);
+  g.nx = c.take<double>(3 * T);
+  g.ny = c.take<double>(3 * T);
+  g.flen = c.take<double>(3 * T);
+  g.sig = c.take<double>(3 * T);
+  g.sF = c.take<double>(3 * T);
+  g.G = c.take<double>(h.G.size());
+  g.qL = c.take<int>(E);
+  g.qR = c.take<int>(E);
+  g.zdef = c.take<double>(E);
+  DevTabs& d = ctx->tb;
+  d.Vv = c.take<double>(tb.Vv.size());
+  d.Gv = c.take<double>(tb.Gv.size());
+  d.Wv = c.take<double>(tb.vw.size());
+  d.Vf = c.take<double>(tb.Vf.size());
+  d.Gf = c.take<double>(tb.Gf.size());
+  d.Wf = c.take<double>(tb.fw.size());
+  d.Vp = c.take<double>(tb.Vp.size());
+  d.Wp = c.take<double>(tb.pw.size());
+  d.Dh = c.take<double>(tb.Dh.size());
+  d.Ch = c.take<double>(tb.Ch.size());
+  DevBsr& A = ctx->A;
+  A.cols = c.take<int>(h.cols.size());
+  A.vals = c.take<double>(h.vals.size());
+  A.dinv = c.take<double>(h.dinv.size());
+  A.binv = c.take<double>(h.binv.size());
+  const bool mixed = ctx->prm.precision == DFDG_MIXED;
+  A.vals32 = mixed ? c.take<float>(h.vals.size()) : nullptr;
+  A.dinv32 = mixed ? c.take<float>(h.dinv.size()) : nullptr;
+  A.binv32 = mixed ? c.take<float>(h.binv.size()) : nullptr;
+  // work
+  ctx->Lbuf = c.take<double>(nU);
+  ctx->q = c.take<double>(3 * NF * T);
+  ctx->gv = c.take<double>(nL);
+  ctx->lamw = c.take<double>(nL);
+  ctx->r = c.take<double>(nL);
+  ctx->z = c.take<double>(nL);
+  ctx->p[0] = c.take<double>(nL);
+  ctx->p[1] = c.take<double>(nL);
+  ctx->Sp = c.take<double>(nL);
+  ctx->Ustage = c.take<double>(nU);
+  for (int s = 0; s < 3; ++s)
+    for (int j = 0; j < 3; ++j) ctx->hist[s][j] = c.take<double>(nL);
+  ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
+  const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
+  ctx->partials = c.take<double>(4 * maxblk);
+  ctx->diagres = c.take<double>(4);
+  ctx->sc = c.take<PcgScalars>(1);
+  ctx->sc32 = c.take<PcgScalars>(1);
+  ctx->sct = c.take<PcgScalars>(1);
+  if (mixed) {
+    ctx->L32 = c.take<float>(nU);
+    ctx->x32 = c.take<float>(nL);
+    ctx->r32 = c.take<float>(nL);
+    ctx->z32 = c.take<float>(nL);
+    ctx->p32[0] = c.take<float>(nL);
+    ctx->p32[1] = c.take<float>(nL);
+    ctx->Sp32 = c.take<float>(nL);
+    ctx->r64 = c.take<double>(nL);
+  }
+  for (int s = 0; s < 3; ++s) ctx->Ustages[s] = c.take<double>(nU);
+  ctx->Ybar = c.take<double>(nU);
+  ctx->Wbuf = c.take<double>(nU);
+  ctx->ws_need = c.off + 256;
+}
+
+extern "C" int dfdg_ctx_workspace_bytes(const dfdg_ctx* cctx, size_t* bytes) {
+  if (!cctx || !bytes) return DFDG_E_INVALID_ARG;
+  auto* ctx = const_cast<dfdg_ctx*>(cctx);
+  if (!ctx->bound) carve(ctx, nullptr);
+  *bytes = ctx->ws_need;
+  return DFDG_OK;
+}
+
+template <typename T>
+static hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (src.empty()) return hipSuccess;
+  return hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s);
+}
+
+extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
+  if (!ctx || !dev) return DFDG_E_INVALID_ARG;
+  if (((uintptr_t)dev & 255) != 0) return fail(ctx, DFDG_E_WORKSPACE, "workspace must be 256-byte aligned");
+  carve(ctx, nullptr);
+  if (bytes < ctx->ws_need)
+    return fail(ctx, DFDG_E_WORKSPACE, "workspace too small: need " + std::to_string(ctx->ws_need) + " bytes");
+  ctx->ws = (char*)dev;
+  carve(ctx, ctx->ws);
+  const HostSetup& h = ctx->hs;
+  hipStream_t s = ctx->stream;
+  HIPC(hipMemsetAsync(ctx->ws, 0, ctx->ws_need - 256, s));
+  HIPC(up(const_cast<double*>(ctx->g.Jinv), h.Jinv, s));
+  HIPC(up(const_cast<double*>(ctx->g.detJ), h.detJ, s));
+  HIPC(up(const_cast<int*>(ctx->g.nbr), h.nbr, s));
+  HIPC(up(const_cast<int*>(ctx->g.code), h.code, s));
+  HIPC(up(const_cast<int*>(ctx->g.efacet), h.efacet, s));
+  HIPC(up(const_cast<double*>(ctx->g.nx), h.nx, s));
+  HIPC(up(const_cast<double*>(ctx->g.ny), h.ny, s));
+  HIPC(up(const_cast<double*>(ctx->g.flen), h.flen, s));
+  HIPC(up(const_cast<double*>(ctx->g.sig), h.sig, s));
+  HIPC(up(const_cast<double*>(ctx->g.sF), h.sF, s));
+  HIPC(up(const_cast<double*>(ctx->g.G), h.G, s));
+  HIPC(up(const_cast<int*>(ctx->g.qL), h.qL, s));
+  HIPC(up(const_cast<int*>(ctx->g.qR), h.qR, s));
+  HIPC(up(const_cast<double*>(ctx->g.zdef), h.zdef, s));
+  const RefTables& tb = h.tabs;
+  HIPC(up(const_cast<double*>(ctx->tb.Vv), tb.Vv, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Gv), tb.Gv, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Wv), tb.vw, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Vf), tb.Vf, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Gf), tb.Gf, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Wf), tb.fw, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Vp), tb.Vp, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Wp), tb.pw, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Dh), tb.Dh, s));
+  HIPC(up(const_cast<double*>(ctx->tb.Ch), tb.Ch, s));
+  HIPC(up(const_cast<int*>(ctx->A.cols), h.cols, s));
+  HIPC(up(const_cast<double*>(ctx->A.vals), h.vals, s));
+  HIPC(up(const_cast<double*>(ctx->A.dinv), h.dinv, s));
+  HIPC(up(const_cast<double*>(ctx->A.binv), h.binv, s));
+  if (ctx->prm.precision == DFDG_MIXED) {
+    std::vector<float> v(h.vals.begin(), h.vals.end()), d(h.dinv.begin(), h.dinv.end()),
+        b(h.binv.begin(), h.binv.end());
+    HIPC(up(const_cast<float*>(ctx->A.vals32), v, s));
+    HIPC(up(const_cast<float*>(ctx->A.dinv32), d, s));
+    HIPC(up(const_cast<float*>(ctx->A.binv32), b, s));
+    HIPC(hipStreamSynchronize(s));
+  }
+  HIPC(hipStreamSynchronize(s));
+  if (!ctx->pinned) HIPC(hipHostMalloc((void**)&ctx->pinned, 4 * sizeof(PcgScalars), hipHostMallocDefault));
+  ctx->bound = true;
+  for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+  return DFDG_OK;
+}
+
+extern "C" const char* dfdg_last_error(const dfdg_ctx* ctx) {
+  if (!ctx) return g_mesh_err.c_str();
+  return ctx->err.c_str();
+}
+
+extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->pinned) {
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipHostFree(ctx->pinned);
+  }
+  delete ctx;
+}
+
+// ---------------------------------------------------------------------------------------
+// facet solve
+// ---------------------------------------------------------------------------------------
+static int status_of(int done) {
+  switch (done) {
+    case PCG_CONVERGED: return DFDG_OK;
+    case PCG_MAXIT: return DFDG_E_NOT_CONVERGED;
+    case PCG_BREAKDOWN: return DFDG_E_BREAKDOWN;
+    case PCG_NONFINITE: return DFDG_E_NONFINITE;
+    default: return DFDG_E_NOT_CONVERGED;
+  }
+}
+
+static int read_scalars(dfdg_ctx* ctx, PcgScalars* dev, PcgScalars& out) {
+  HIPC(hipMemcpyAsync(ctx->pinned, dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  out = *ctx->pinned;
+  return DFDG_OK;
+}
+
+// Run PCG iterations (already initialised on the device) until the device flags an end.
+// The host enqueues chunks of iterations and reads the scalars after each chunk; the
+// chunk length follows the observed convergence rate so that few empty launches remain.
+template <typename Step>
+static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, PcgScalars& fin) {
+  int rc = read_scalars(ctx, sc, fin);
+  if (rc) return rc;
+  int host_it = 0;
+  int chunk = 16;
+  double last_rr = fin.rr;
+  int last_it = 0;
+  while (fin.done == PCG_RUNNING) {
+    for (int c = 0; c < chunk; ++c, ++host_it) {
+      hipError_t e = step(host_it);
+      if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
+    }
+    rc = read_scalars(ctx, sc, fin);
+    if (rc) return rc;
+    if (fin.done != PCG_RUNNING) break;
+    if (host_it > maxit + 8) return fail(ctx, DFDG_E_NOT_CONVERGED, "PCG did not stop at its iteration limit");
+    // predict the remaining iterations from the contraction of rr over the last chunk
+    int next = 2 * chunk;
+    if (fin.iters > last_it && fin.rr > 0 && last_rr > 0 && fin.rr < last_rr && fin.tol2 > 0) {
+      const double rate = std::log(fin.rr / last_rr) / (fin.iters - last_it);  // < 0
+      const double remain = std::log(fin.tol2 / fin.rr) / rate;
+      next = (int)std::ceil(remain * 1.05) + 2;
+    }
+    chunk = std::min(std::max(next, 4), 1024);
+    last_rr = fin.rr;
+    last_it = fin.iters;
+  }
+  return DFDG_OK;
+}
+
+// Solve S lam = g for the q currently in ctx->q; lam holds the start on entry.
+static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
+  const int NF = ctx->NF;
+  const bool bj = ctx->prm.precond == DFDG_BLOCK_JACOBI;
+  hipStream_t s = ctx->stream;
+  const DevGeo& g = ctx->g;
+  const DevBsr& A = ctx->A;
+  PcgScalars fin{};
+  dfdg_solve_info inf{};
+  if (ctx->prm.precision == DFDG_FP64) {
+    HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, ctx->sc, ctx->partials, ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
+    HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, lam, ctx->r, ctx->z, ctx->p[0], ctx->sc, ctx->partials, s));
+    int rc = pcg_loop(ctx, ctx->sc, ctx->prm.cg_maxit, [&](int it) {
+      double* pin = ctx->p[it & 1];
+      double* pout = ctx->p[(it + 1) & 1];
+      hipError_t e = launch_pcg_spmv(NF, g, A, ctx->z, pin, pout, ctx->Sp, ctx->sc, ctx->partials, s);
+      if (e != hipSuccess) return e;
+      return launch_pcg_update(NF, bj, g, A, pout, ctx->Sp, lam, ctx->r, ctx->z, ctx->sc, ctx->partials, s);
+    }, fin);
+    if (rc) return rc;
+    inf.iterations = fin.iters;
+    inf.refinements = 0;
+    inf.rel_residual = fin.gg > 0 ? std::sqrt(std::max(fin.rr, 0.0) / fin.gg) : 0.0;
+    inf.status = status_of(fin.done);
+  } else {
+    // mixed: FP64 refinement around FP32 inner PCG (S in FP32), FP64 residuals
+    HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, ctx->sc, ctx->partials, ctx->prm.ir_rtol, ctx->prm.cg_maxit, s));
+    HIPC(launch_ir_residual(NF, g, A, ctx->gv, lam, nullptr, 0, ctx->r64, ctx->sc, ctx->partials, s));
+    PcgScalars o{};
+    int rc = read_scalars(ctx, ctx->sc, o);
+    if (rc) return rc;
+    int total = 0, nref = 0, st = DFDG_OK;
+    const double target = ctx->prm.ir_rtol * ctx->prm.ir_rtol * o.gg;
+    while (o.gg > 0 && o.rr > target) {
+      if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
+      HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], ctx->sc32,
+                             ctx->partials, ctx->prm.inner_rtol, ctx->prm.cg_maxit - total, s));
+      rc = pcg_loop(ctx, ctx->sc32, ctx->prm.cg_maxit - total, [&](int it) {
+        float* pin = ctx->p32[it & 1];
+        float* pout = ctx->p32[(it + 1) & 1];
+        hipError_t e = launch_pcg32_spmv(NF, g, A, ctx->z32, pin, pout, ctx->Sp32, ctx->sc32, ctx->partials, s);
+        if (e != hipSuccess) return e;
+        return launch_pcg32_update(NF, bj, g, A, pout, ctx->Sp32, ctx->x32, ctx->r32, ctx->z32, ctx->sc32,
+                                   ctx->partials, s);
+      }, fin);
+      if (rc) return rc;
+      total += fin.iters;
+      ++nref;
+      if (fin.done == PCG_NONFINITE || fin.done == PCG_BREAKDOWN) { st = status_of(fin.done); }
+      HIPC(launch_ir_residual(NF, g, A, ctx->gv, lam, ctx->x32, 1, ctx->r64, ctx->sc, ctx->partials, s));
+      rc = read_scalars(ctx, ctx->sc, o);
+      if (rc) return rc;
+      if (st != DFDG_OK) break;
+      if (!std::isfinite(o.rr)) { st = DFDG_E_NONFINITE; break; }
+    }
+    inf.iterations = total;
+    inf.refinements = nref;
+    inf.rel_residual = o.gg > 0 ? std::sqrt(std::max(o.rr, 0.0) / o.gg) : 0.0;
+    inf.status = st;
+  }
+  if (info) *info = inf;
+  return DFDG_OK;
+}
+
+static int mass_solve_impl(dfdg_ctx* ctx, const void* F, bool f32, double* U, double* lam, bool cold,
+                           dfdg_solve_info* info, int mode, double ca, const double* Un, double cb,
+                           const double* Us, double dt) {
+  hipStream_t s = ctx->stream;
+  HIPC(launch_cond_rhs(ctx->K, f32, ctx->g, ctx->tb, F, ctx->q, s));
+  if (cold) HIPC(launch_fill(ctx->nL, 0.0, lam, s));
+  dfdg_solve_info inf{};
+  int rc = solve_facets(ctx, lam, &inf);
+  if (rc) return rc;
+  HIPC(launch_recover(ctx->K, f32, ctx->g, ctx->tb, F, lam, U, mode, ca, Un, cb, Us, dt, s));
+  if (info) *info = inf;
+  return DFDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// public hot-path entry points
+// ---------------------------------------------------------------------------------------
+extern "C" int dfdg_proj_rule(const dfdg_ctx* ctx, double* pts, double* w) {
+  if (!ctx || !pts || !w) return DFDG_E_INVALID_ARG;
+  std::memcpy(pts, ctx->hs.tabs.pq.data(), ctx->hs.tabs.pq.size() * sizeof(double));
+  std::memcpy(w, ctx->hs.tabs.pw.data(), ctx->hs.tabs.pw.size() * sizeof(double));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_load_vector(dfdg_ctx* ctx, const double* fq, double* F) {
+  NEED_BOUND(ctx);
+  if (!fq || !F) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(launch_load_vector(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, F, ctx->stream));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_hdiv_mass_solve(dfdg_ctx* ctx, const double* F, double* U, double* lam_io,
+                                    dfdg_solve_info* info) {
+  NEED_BOUND(ctx);
+  if (!F || !U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  double* lam = lam_io ? lam_io : ctx->lamw;
+  dfdg_solve_info inf{};
+  int rc = mass_solve_impl(ctx, F, false, U, lam, lam_io == nullptr, &inf, 0, 0, nullptr, 0, nullptr, 0);
+  if (rc) return rc;
+  if (info) *info = inf;
+  if (inf.status != DFDG_OK) return fail(ctx, inf.status, "facet PCG did not converge");
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_project(dfdg_ctx* ctx, const double* fq, double* U, dfdg_solve_info* info) {
+  NEED_BOUND(ctx);
+  if (!fq || !U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(launch_load_vector(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, ctx->Lbuf, ctx->stream));
+  dfdg_solve_info inf{};
+  int rc = mass_solve_impl(ctx, ctx->Lbuf, false, U, ctx->lamw, true, &inf, 0, 0, nullptr, 0, nullptr, 0);
+  if (rc) return rc;
+  if (info) *info = inf;
+  if (inf.status != DFDG_OK) return fail(ctx, inf.status, "facet PCG did not converge");
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_dg_residual(dfdg_ctx* ctx, const double* U, double* L) {
+  NEED_BOUND(ctx);
+  if (!U || !L) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(launch_residual(ctx->K, false, ctx->g, ctx->tb, U, L, ctx->prm.nu, ctx->stream));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_reset_history(dfdg_ctx* ctx) {
+  if (!ctx) return DFDG_E_INVALID_ARG;
+  for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+  return DFDG_OK;
+}
+
+// Start value of stage s's facet solve from its history; returns whether it is a cold start.
+static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
+  const int n = ctx->hist_count[s];
+  *cold = (n == 0);
+  if (n == 0) return DFDG_OK;
+  const int order = std::min(ctx->prm.extrapolate, n - 1);
+  HIPC(launch_extrapolate(ctx->nL, order, ctx->hist[s][0], ctx->hist[s][1], ctx->hist[s][2], ctx->lamw,
+                          ctx->stream));
+  return DFDG_OK;
+}
+static void stage_push(dfdg_ctx* ctx, int s) {
+  double* old = ctx->hist[s][2];
+  ctx->hist[s][2] = ctx->hist[s][1];
+  ctx->hist[s][1] = ctx->hist[s][0];
+  ctx->hist[s][0] = ctx->lamw;
+  ctx->lamw = old;
+  ctx->hist_count[s] = std::min(ctx->hist_count[s] + 1, 3);
+}
+
+// One stage: out = a Un + b (Us + dt M^{-1} L(Us)).
+static int rk_stage(dfdg_ctx* ctx, int s, const double* Us, const double* Un, double a, double b, double dt,
+                    double* out, dfdg_solve_info* inf) {
+  const bool mixed = ctx->prm.precision == DFDG_MIXED;
+  void* L = mixed ? (void*)ctx->L32 : (void*)ctx->Lbuf;
+  HIPC(launch_residual(ctx->K, mixed, ctx->g, ctx->tb, Us, L, ctx->prm.nu, ctx->stream));
+  bool cold;
+  int rc = stage_guess(ctx, s, &cold);
+  if (rc) return rc;
+  rc = mass_solve_impl(ctx, L, mixed, out, ctx->lamw, cold, inf, 1, a, Un, b, Us, dt);
+  if (rc) return rc;
+  stage_push(ctx, s);
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_rk3_step(dfdg_ctx* ctx, double* U, double dt, dfdg_step_info* info) {
+  NEED_BOUND(ctx);
+  if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  dfdg_step_info st{};
+  dfdg_solve_info si[3];
+  // Shu-Osher TVD-RK3 (eq. (rk3)) with each bracket u + dt M^{-1} L(u) done by one solve
+  int rc = rk_stage(ctx, 0, U, U, 0.0, 1.0, dt, ctx->Ustage, &si[0]);
+  if (!rc) rc = rk_stage(ctx, 1, ctx->Ustage, U, 0.75, 0.25, dt, ctx->Ustage, &si[1]);
+  if (!rc) rc = rk_stage(ctx, 2, ctx->Ustage, U, 1.0 / 3.0, 2.0 / 3.0, dt, U, &si[2]);
+  if (rc) return rc;
+  st.status = DFDG_OK;
+  for (int s = 0; s < 3; ++s) {
+    st.iterations[s] = si[s].iterations;
+    st.max_refinements = std::max(st.max_refinements, si[s].refinements);
+    st.max_rel_residual = std::max(st.max_rel_residual, si[s].rel_residual);
+    if (si[s].status != DFDG_OK) st.status = si[s].status;
+  }
+  if (info) *info = st;
+  if (st.status != DFDG_OK) return fail(ctx, st.status, "a stage's facet solve did not converge");
+  return DFDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// adjoint form
+// ---------------------------------------------------------------------------------------
+extern "C" int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U, const double* Lbar, double* Ubar) {
+  NEED_BOUND(ctx);
+  if (!U || !Lbar || !Ubar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, U, Lbar, Ubar, ctx->prm.nu, ctx->stream));
+  return DFDG_OK;
+}
+
+// Reverse of dfdg_rk3_step.  With FE(u) = u + dt P L(u), P the mass solve (symmetric):
+//   U1 = FE(Un),  U2 = 3/4 Un + 1/4 FE(U1),  U3 = 1/3 Un + 2/3 FE(U2),
+// and J_FE(u)^T y = y + dt J_L(u)^T P y.  Given Y3 = Ubar_{n+1}:
+//   Y2 = 2/3 J_FE(U2)^T Y3,  Y1 = 1/4 J_FE(U1)^T Y2,
+//   Ubar_n = 1/3 Y3 + 3/4 Y2 + J_FE(Un)^T Y1.
+static int fe_transpose(dfdg_ctx* ctx, const double* u, const double* y, double* out, double dt,
+                        dfdg_solve_info* si) {
+  hipStream_t s = ctx->stream;
+  // P y: adjoint right-hand sides have no history; start from zero
+  int rc = mass_solve_impl(ctx, y, false, ctx->Wbuf, ctx->lamw, true, si, 0, 0, nullptr, 0, nullptr, 0);
+  if (rc) return rc;
+  HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, u, ctx->Wbuf, out, ctx->prm.nu, s));
+  HIPC(launch_axpby(ctx->nU, 1.0, y, dt, out, s));  // out = y + dt J^T P y
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un, double* Ybar, double dt, dfdg_step_info* info) {
+  NEED_BOUND(ctx);
+  if (!Un || !Ybar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  hipStream_t s = ctx->stream;
+  const long n = ctx->nU;
+  double* U1 = ctx->Ustages[0];
+  double* U2 = ctx->Ustages[1];
+  double* tmp = ctx->Ustages[2];
+  double* Yk = ctx->Ybar;
+  dfdg_solve_info fw[2]{}, si[3]{};
+  int rc = rk_stage(ctx, 0, Un, Un, 0.0, 1.0, dt, U1, &fw[0]);
+  if (!rc) rc = rk_stage(ctx, 1, U1, Un, 0.75, 0.25, dt, U2, &fw[1]);
+  if (rc) return rc;
+  rc = fe_transpose(ctx, U2, Ybar, tmp, dt, &si[2]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 2.0 / 3.0, tmp, 0.0, Yk, s));       // Y2
+  HIPC(launch_axpby(n, 0.75, Yk, 1.0 / 3.0, Ybar, s));     // Ubar = 1/3 Y3 + 3/4 Y2
+  rc = fe_transpose(ctx, U1, Yk, tmp, dt, &si[1]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 0.25, tmp, 0.0, Yk, s));            // Y1
+  rc = fe_transpose(ctx, Un, Yk, tmp, dt, &si[0]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 1.0, tmp, 1.0, Ybar, s));           // Ubar += J_FE(Un)^T Y1
+  dfdg_step_info st{};
+  st.status = DFDG_OK;
+  for (int i = 0; i < 3; ++i) {
+    st.iterations[i] = si[i].iterations;
+    st.max_rel_residual = std::max(st.max_rel_residual, si[i].rel_residual);
+    if (si[i].status != DFDG_OK) st.status = si[i].status;
+    if (i < 2 && fw[i].status != DFDG_OK) st.status = fw[i].status;
+  }
+  if (info) *info = st;
+  if (st.status != DFDG_OK) return fail(ctx, st.status, "a facet solve of the adjoint step did not converge");
+  return DFDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// diagnostics, evaluation, measurement
+// ---------------------------------------------------------------------------------------
+extern "C" int dfdg_diagnostics(dfdg_ctx* ctx, const double* U, dfdg_diag* out) {
+  NEED_BOUND(ctx);
+  if (!U || !out) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(launch_diagnostics(ctx->K, ctx->g, ctx->tb, U, ctx->partials, ctx->diagres, ctx->stream));
+  double res[4];
+  HIPC(hipMemcpyAsync(ctx->pinned, ctx->diagres, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  std::memcpy(res, ctx->pinned, sizeof(res));
+  out->energy = res[0];
+  out->enstrophy = res[1];
+  out->max_div = res[2];
+  out->max_normal_jump = res[3];
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_eval(dfdg_ctx* ctx, const double* U, int npts, const double* ref, double* out) {
+  NEED_BOUND(ctx);
+  if (!U || !ref || !out) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (npts < 1 || npts > kMaxEvalPts) return fail(ctx, DFDG_E_INVALID_ARG, "npts must be in 1..1024");
+  const int P = ctx->P;
+  std::vector<double> tab((size_t)npts * P);
+  for (int p = 0; p < npts; ++p) dubiner(ctx->K, ref[2 * p], ref[2 * p + 1], &tab[(size_t)p * P], nullptr);
+  HIPC(hipMemcpyAsync(ctx->evaltab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPC(launch_eval(ctx->K, npts, ctx->g, ctx->evaltab, U, out, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));  // tab is a host temporary
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, double* bytes) {
+  NEED_BOUND(ctx);
+  if (!ms || reps < 1) return fail(ctx, DFDG_E_INVALID_ARG, "bad arguments");
+  if (which == 3 && ctx->prm.precision != DFDG_MIXED) return fail(ctx, DFDG_E_INVALID_ARG, "FP32 SpMV needs a MIXED context");
+  if (which < 0 || which > 3) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
+  hipStream_t s = ctx->stream;
+  const long T = ctx->T, E = ctx->E, NF = ctx->NF, P = ctx->P;
+  // a running PCG state with harmless scalars for the reducing kernels
+  PcgScalars st{};
+  st.rz = 1.0; st.alpha = 1e-30; st.beta = 0.5; st.rr = 1.0; st.gg = 1.0; st.tol2 = 0.0; st.maxit = 1 << 30;
+  HIPC(hipMemcpyAsync(ctx->sct, &st, sizeof(st), hipMemcpyHostToDevice, s));
+  auto launch = [&]() -> hipError_t {
+    switch (which) {
+      case 0: return launch_pcg_spmv(NF, ctx->g, ctx->A, ctx->z, ctx->p[0], ctx->p[1], ctx->Sp, ctx->sct, ctx->partials, s);
+      case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
+                                       ctx->gv, ctx->r, ctx->z, ctx->sct, ctx->partials, s);
+      case 2: return launch_residual(ctx->K, false, ctx->g, ctx->tb, ctx->Ustage, ctx->Lbuf, ctx->prm.nu, s);
+      default: return launch_pcg32_spmv(NF, ctx->g, ctx->A, ctx->z32, ctx->p32[0], ctx->p32[1], ctx->Sp32, ctx->sct,
+                                        ctx->partials, s);
+    }
+  };
+  HIPC(launch());  // warm-up
+  hipEvent_t e0, e1;
+  HIPC(hipEventCreate(&e0));
+  HIPC(hipEventCreate(&e1));
+  HIPC(hipEventRecord(e0, s));
+  for (int i = 0; i < reps; ++i) HIPC(launch());
+  HIPC(hipEventRecord(e1, s));
+  HIPC(hipEventSynchronize(e1));
+  float tot = 0;
+  HIPC(hipEventElapsedTime(&tot, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = tot / reps;
+  if (bytes) {
+    double b = 0;
+    switch (which) {
+      case 0: b = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0 + 4.0 * NF * 8.0); break;       // S, cols, z, p_old, p_new, Sp
+      case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
+      case 2: b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (3 * 4.0 + 4 * 8.0)); break;         // U in, L out, geometry
+      default: b = E * (kSlots * NF * NF * 4.0 + kSlots * 4.0 + 4.0 * NF * 4.0); break;
+    }
+    *bytes = b;
+  }
+  return DFDG_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// host inspection
+// ---------------------------------------------------------------------------------------
+extern "C" int dfdg_debug_basis(int k, int npts, const double* pts, double* vals, double* grads) {
+  if (k < 1 || k > kMaxK || npts < 1 || !pts || !vals) return DFDG_E_INVALID_ARG;
+  const int P = nP(k);
+  std::vector<double> g(2 * P);
+  for (int p = 0; p < npts; ++p) {
+    dubiner(k, pts[2 * p], pts[2 * p + 1], vals + (size_t)p * P, g.data());
+    if (grads) std::memcpy(grads + (size_t)p * 2 * P, g.data(), 2 * P * sizeof(double));
+  }
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols, double* vals) {
+  if (!ctx || !cols || !vals) return DFDG_E_INVALID_ARG;
+  std::memcpy(cols, ctx->hs.cols.data(), ctx->hs.cols.size() * sizeof(int32_t));
+  std::memcpy(vals, ctx->hs.vals.data(), ctx->hs.vals.size() * sizeof(double));
+  return DFDG_OK;
+}

@@ -1,0 +1,66 @@
+// Launchers of the HIP kernels (implemented in dfdg_kernels.hip).  All launches are
+// asynchronous on `stream`; every launcher checks nothing and returns the launch status.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "dfdg_internal.h"
+
+namespace dfdg {
+
+// Residual L(U) on the broken basis (a3).  Real = double (FP64) or float (MIXED, output
+// in FP32).  U is always FP64.
+hipError_t launch_residual(int K, bool fp32, const DevGeo& g, const DevTabs& tb, const double* U, void* L,
+                           double nu, hipStream_t s);
+// Residual VJP: Ubar = J_L(U)^T Lbar.
+hipError_t launch_residual_vjp(int K, const DevGeo& g, const DevTabs& tb, const double* U, const double* Lbar,
+                               double* Ubar, double nu, hipStream_t s);
+// q[3][NF][T] = C_T W_T F_T per element and local facet (a4, element part).  F is FP64
+// or FP32 (fp32in); q is written in FP64 or FP32 (fp32out).
+hipError_t launch_cond_rhs(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, double* q,
+                           hipStream_t s);
+// g[E][NF] = facet sums of q, plus the reduction of (g,g) and (zdef, g) into sc; sets the
+// stopping threshold tol2 = rtol^2 (g,g)_deflated.
+hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, PcgScalars* sc, double* partials,
+                           double rtol, int maxit, hipStream_t s);
+// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0, rz, rr reductions; sets done if already converged.
+hipError_t launch_pcg_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* gv, double* x,
+                           double* r, double* z, double* p_old, PcgScalars* sc, double* partials, hipStream_t s);
+// p_new = z + beta p_old, q = S p_new, alpha = rz / (p_new, q).
+hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
+                           double* p_new, double* Sp, PcgScalars* sc, double* partials, hipStream_t s);
+// x += alpha p, r -= alpha q, z = M^{-1} r, beta = rz_new / rz, convergence test.
+hipError_t launch_pcg_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* p,
+                             const double* Sp, double* x, double* r, double* z, PcgScalars* sc, double* partials,
+                             hipStream_t s);
+// FP32 inner PCG (MIXED): same kernels on float vectors and the FP32 copy of S.
+hipError_t launch_pcg32_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* r64,
+                             float* x, float* r, float* z, float* p_old, PcgScalars* sc, double* partials,
+                             double rtol, int maxit, hipStream_t s);
+hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
+                             float* p_new, float* Sp, PcgScalars* sc, double* partials, hipStream_t s);
+hipError_t launch_pcg32_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const float* p,
+                               const float* Sp, float* x, float* r, float* z, PcgScalars* sc, double* partials,
+                               hipStream_t s);
+// FP64 refinement residual r64 = g - zg zdef - S lambda (and (r,r)); lambda += x32 first if add.
+hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const double* gv, double* lam,
+                              const float* x32, int add, double* r64, PcgScalars* sc, double* partials,
+                              hipStream_t s);
+// Recovery (a6): u = W_T (F_T - C_T^T lambda_T); out = u (mode 0) or
+// out = a Un + b (Us + dt u) (mode 1).  F is FP64 or FP32.
+hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, const double* lam,
+                          double* out, int mode, double a, const double* Un, double b, const double* Us, double dt,
+                          hipStream_t s);
+hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
+                              hipStream_t s);
+hipError_t launch_eval(int K, int npts, const DevGeo& g, const double* tab, const double* U, double* out,
+                       hipStream_t s);
+// Diagnostics: per-block partials then a one-block finish into res[4].
+hipError_t launch_diagnostics(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* partials,
+                              double* res, hipStream_t s);
+// Linear combination y = a x + b y on n doubles.
+hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
+hipError_t launch_extrapolate(long n, int order, const double* h0, const double* h1, const double* h2, double* out,
+                              hipStream_t s);
+hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
+
+}  // namespace dfdg

@@ -1,0 +1,1163 @@
+// HIP kernels of the hot path for gfx950 (CDNA4, 64-wide wavefronts).
+//
+// Element-centred kernels run one thread per element and read the SoA velocity layout
+// [2][P][T] (consecutive lanes, consecutive elements: coalesced).  Facet-centred kernels
+// run one thread per facet row of the BSR facet matrix S (n_f x n_f blocks, 5 per row),
+// whose values are stored SoA [slot][a][b][E] so that every load instruction of a wave is
+// one contiguous 512-byte segment.  Facet vectors are [E][n_f].
+//
+// Reductions (PCG dot products) are deterministic: each block reduces its lanes with
+// wavefront shuffles and LDS, writes one partial per block, and the last block to finish
+// (found with one device-scope atomic counter) sums the partials in a fixed order and
+// updates the PCG scalars.  Nobody waits on anybody, so no kernel can hang on it.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dfdg_internal.h"
+#include "dfdg_kernels.h"
+
+namespace dfdg {
+
+static constexpr int kBlk = 256;     // facet kernels
+static constexpr int kEBlk = 128;    // element kernels
+
+// ---------------------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------------------
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ inline double wave_max(double x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+__device__ inline void store_agent(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double load_agent(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Block-sum NV values; every block writes its partials, the last block to arrive sums all
+// partials in block order and returns true with the totals in tot (valid in thread 0).
+template <int NV>
+__device__ bool reduce_last_block(const double (&v)[NV], double* partials, unsigned int* counter,
+                                  double (&tot)[NV]) {
+  __shared__ double sh[NV][kBlk / 64];
+  __shared__ int am_last;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(v[i]);
+    if (lane == 0) sh[i][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += sh[i][w];
+      store_agent(&partials[blockIdx.x * NV + i], s);
+    }
+    __atomic_thread_fence(__ATOMIC_RELEASE);  // partials visible before the count
+    const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    am_last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!am_last) return false;
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += load_agent(&partials[b * NV + i]);
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    const double s = wave_sum(acc[i]);
+    if (lane == 0) sh[i][wid] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double s = 0;
+      for (int w = 0; w < nw; ++w) s += sh[i][w];
+      tot[i] = s;
+    }
+    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------------------
+// element helpers
+// ---------------------------------------------------------------------------------------
+
+// Apply W_T = I - D_T^T (D_T D_T^T)^{-1} D_T (the divergence-free projector of the
+// element, eq. (FE3) with the orthonormal basis) in place to y[2][P].
+template <int K, typename R>
+__device__ inline void apply_W(R (&y)[2][nP(K)], const R (&Ji)[2][2], const double* __restrict__ G, int T, int t,
+                               const double* __restrict__ Dh) {
+  constexpr int P = nP(K), NP = nPp(K);
+  R d[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    R s = 0;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      R a0 = 0, a1 = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        a0 += (R)Dh[(0 * NP + j) * P + i] * y[c][i];
+        a1 += (R)Dh[(1 * NP + j) * P + i] * y[c][i];
+      }
+      s += Ji[0][c] * a0 + Ji[1][c] * a1;
+    }
+    d[j] = s;
+  }
+  R e[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) e[j] = 0;
+#pragma unroll
+  for (int j = 0, p = 0; j < NP; ++j)
+#pragma unroll
+    for (int l = 0; l <= j; ++l, ++p) {
+      const R gv = (R)G[(size_t)p * T + t];
+      e[j] += gv * d[l];
+      if (l != j) e[l] += gv * d[j];
+    }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      R s = 0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        s += (Ji[0][c] * (R)Dh[(0 * NP + j) * P + i] + Ji[1][c] * (R)Dh[(1 * NP + j) * P + i]) * e[j];
+      y[c][i] -= s;
+    }
+  }
+}
+
+template <typename R>
+__device__ inline void load_Jinv(const DevGeo& g, int t, R (&Ji)[2][2]) {
+  Ji[0][0] = (R)g.Jinv[t];
+  Ji[0][1] = (R)g.Jinv[(size_t)g.T + t];
+  Ji[1][0] = (R)g.Jinv[2 * (size_t)g.T + t];
+  Ji[1][1] = (R)g.Jinv[3 * (size_t)g.T + t];
+}
+
+// Stage the reference tables of the residual into LDS.
+template <int K>
+struct ResTabs {
+  static constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
+  double Vv[NQV][P], Gv[NQV][2][P], Wv[NQV];
+  double Vf[3][NQF][P], Gf[3][NQF][2][P], Wf[NQF];
+};
+template <int K>
+__device__ inline void stage_tabs(ResTabs<K>& s, const DevTabs& tb) {
+  constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
+  double* d;
+  d = &s.Vv[0][0];
+  for (int i = threadIdx.x; i < NQV * P; i += blockDim.x) d[i] = tb.Vv[i];
+  d = &s.Gv[0][0][0];
+  for (int i = threadIdx.x; i < NQV * 2 * P; i += blockDim.x) d[i] = tb.Gv[i];
+  for (int i = threadIdx.x; i < NQV; i += blockDim.x) s.Wv[i] = tb.Wv[i];
+  d = &s.Vf[0][0][0];
+  for (int i = threadIdx.x; i < 3 * NQF * P; i += blockDim.x) d[i] = tb.Vf[i];
+  d = &s.Gf[0][0][0][0];
+  for (int i = threadIdx.x; i < 3 * NQF * 2 * P; i += blockDim.x) d[i] = tb.Gf[i];
+  for (int i = threadIdx.x; i < NQF; i += blockDim.x) s.Wf[i] = tb.Wf[i];
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------------
+// a3: DG residual L(u)(v) = -C_h(u;u,v) - B_h(u,v) on the broken basis
+// ---------------------------------------------------------------------------------------
+// Each element integrates its volume term and its three facet terms, reading the
+// neighbour's coefficients; a facet's flux is thus evaluated by both neighbours with the
+// same operations in mirrored order (no atomics, bitwise symmetric).  With n the own
+// outward normal, un = {u}.n, u_up the outflow-side value (un >= 0: own side),
+// du = u_own - u_nbr, the facet contributes to the own test function v
+//     -(un u_up - nu {grad u} n + nu sigma du) . v  +  (nu/2) (du (x) n) : grad v
+// (upwind convection, consistency, penalty, symmetry terms of eqs. (adv), (viscous)).
+template <int K, typename R>
+__global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                    R* __restrict__ Lout, double nu_d) {
+  constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
+  __shared__ ResTabs<K> s;
+  stage_tabs<K>(s, tb);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const R nu = (R)nu_d;
+  R u[2][P], acc[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      u[c][i] = (R)U[(size_t)(c * P + i) * T + t];
+      acc[c][i] = 0;
+    }
+  R Ji[2][2];
+  load_Jinv(g, t, Ji);
+  const R det = (R)g.detJ[t];
+  const R isq = (R)(1.0 / sqrt((double)det));
+  const R sq = det * isq;
+
+  // volume: int (u (x) u - nu grad u) : grad v
+  for (int q = 0; q < NQV; ++q) {
+    R uq[2], gr[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      R a = 0, b0 = 0, b1 = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        a += u[c][i] * (R)s.Vv[q][i];
+        b0 += u[c][i] * (R)s.Gv[q][0][i];
+        b1 += u[c][i] * (R)s.Gv[q][1][i];
+      }
+      uq[c] = a * isq;
+      gr[c][0] = b0;
+      gr[c][1] = b1;
+    }
+    R Gt[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      R fl[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) fl[j] = uq[c] * uq[j] - nu * isq * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j]);
+#pragma unroll
+      for (int a = 0; a < 2; ++a) Gt[c][a] = fl[0] * Ji[a][0] + fl[1] * Ji[a][1];
+    }
+    const R w = (R)s.Wv[q] * sq;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) acc[c][i] += w * (Gt[c][0] * (R)s.Gv[q][0][i] + Gt[c][1] * (R)s.Gv[q][1][i]);
+  }
+
+  // facets
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int nb = g.nbr[idx];
+    const int code = g.code[idx];
+    const int fn = code & 3;
+    const bool rev = (code >> 2) & 1;
+    const R n0 = (R)g.nx[idx], n1 = (R)g.ny[idx];
+    const R len = (R)g.flen[idx];
+    const R sig = (R)g.sig[idx];
+    R v[2][P];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) v[c][i] = (R)U[(size_t)(c * P + i) * T + nb];
+    R Jn[2][2];
+    load_Jinv(g, nb, Jn);
+    const R isqn = (R)(1.0 / sqrt(g.detJ[nb]));
+    R nJ[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) nJ[a] = n0 * Ji[a][0] + n1 * Ji[a][1];
+    for (int r = 0; r < NQF; ++r) {
+      const int rn = rev ? NQF - 1 - r : r;
+      R uo[2], un[2], go[2][2], gn[2][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        R a = 0, b0 = 0, b1 = 0, an = 0, bn0 = 0, bn1 = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          a += u[c][i] * (R)s.Vf[f][r][i];
+          b0 += u[c][i] * (R)s.Gf[f][r][0][i];
+          b1 += u[c][i] * (R)s.Gf[f][r][1][i];
+          an += v[c][i] * (R)s.Vf[fn][rn][i];
+          bn0 += v[c][i] * (R)s.Gf[fn][rn][0][i];
+          bn1 += v[c][i] * (R)s.Gf[fn][rn][1][i];
+        }
+        uo[c] = a * isq;
+        un[c] = an * isqn;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          go[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
+          gn[c][j] = isqn * (bn0 * Jn[0][j] + bn1 * Jn[1][j]);
+        }
+      }
+      const R unrm = (R)0.5 * ((uo[0] + un[0]) * n0 + (uo[1] + un[1]) * n1);
+      const bool own_up = unrm >= (R)0;
+      R Qv[2], du[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const R up = own_up ? uo[c] : un[c];
+        du[c] = uo[c] - un[c];
+        const R avgn = (R)0.5 * ((go[c][0] + gn[c][0]) * n0 + (go[c][1] + gn[c][1]) * n1);
+        Qv[c] = unrm * up - nu * avgn + nu * sig * du[c];
+      }
+      const R w = (R)s.Wf[r] * len * isq;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const R h = (R)0.5 * nu * du[c];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          acc[c][i] += w * (-Qv[c] * (R)s.Vf[f][r][i] + h * (nJ[0] * (R)s.Gf[f][r][0][i] + nJ[1] * (R)s.Gf[f][r][1][i]));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) Lout[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+// ---------------------------------------------------------------------------------------
+// adjoint form: Ubar = J_L(U)^T Lbar
+// ---------------------------------------------------------------------------------------
+// With y the broken field of coefficients Lbar, (J_L^T Lbar)_j = d/dU_j [L(u)(y)].
+// Viscous part: -B_h(phi_j, y) = -B_h(y, phi_j) (symmetric), i.e. the viscous residual of
+// y.  Convective part (upwind side frozen): volume  +int (phi (x) u + u (x) phi) : grad y,
+// i.e. phi . (grad y u + grad y^T u); facet (own-side test function phi, n own normal,
+// dy = y_own - y_nbr)  -int [ 1/2 (phi.n)(u_up.dy) + un (phi.dy) [own side upwind] ].
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                        const double* __restrict__ Y, double* __restrict__ Ubar,
+                                                        double nu) {
+  constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
+  __shared__ ResTabs<K> s;
+  stage_tabs<K>(s, tb);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double u[2][P], y[2][P], acc[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      u[c][i] = U[(size_t)(c * P + i) * T + t];
+      y[c][i] = Y[(size_t)(c * P + i) * T + t];
+      acc[c][i] = 0;
+    }
+  double Ji[2][2];
+  load_Jinv(g, t, Ji);
+  const double det = g.detJ[t];
+  const double isq = 1.0 / sqrt(det);
+  const double sq = det * isq;
+  for (int q = 0; q < NQV; ++q) {
+    double uq[2], gy[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double a = 0, b0 = 0, b1 = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        a += u[c][i] * s.Vv[q][i];
+        b0 += y[c][i] * s.Gv[q][0][i];
+        b1 += y[c][i] * s.Gv[q][1][i];
+      }
+      uq[c] = a * isq;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) gy[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
+    }
+    double av[2], Gt[2][2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      av[c] = gy[c][0] * uq[0] + gy[c][1] * uq[1] + gy[0][c] * uq[0] + gy[1][c] * uq[1];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) Gt[c][a] = -nu * (gy[c][0] * Ji[a][0] + gy[c][1] * Ji[a][1]);
+    }
+    const double w = s.Wv[q] * sq;
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        acc[c][i] += w * (av[c] * s.Vv[q][i] + Gt[c][0] * s.Gv[q][0][i] + Gt[c][1] * s.Gv[q][1][i]);
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int nb = g.nbr[idx];
+    const int code = g.code[idx];
+    const int fn = code & 3;
+    const bool rev = (code >> 2) & 1;
+    const double n0 = g.nx[idx], n1 = g.ny[idx], len = g.flen[idx], sig = g.sig[idx];
+    double v[2][P], yn[2][P];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        v[c][i] = U[(size_t)(c * P + i) * T + nb];
+        yn[c][i] = Y[(size_t)(c * P + i) * T + nb];
+      }
+    double Jn[2][2];
+    load_Jinv(g, nb, Jn);
+    const double isqn = 1.0 / sqrt(g.detJ[nb]);
+    double nJ[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) nJ[a] = n0 * Ji[a][0] + n1 * Ji[a][1];
+    for (int r = 0; r < NQF; ++r) {
+      const int rn = rev ? NQF - 1 - r : r;
+      double uo[2], un[2], yo[2], ynb[2], go[2][2], gn[2][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double a = 0, an = 0, ya = 0, yan = 0, b0 = 0, b1 = 0, bn0 = 0, bn1 = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          a += u[c][i] * s.Vf[f][r][i];
+          an += v[c][i] * s.Vf[fn][rn][i];
+          ya += y[c][i] * s.Vf[f][r][i];
+          yan += yn[c][i] * s.Vf[fn][rn][i];
+          b0 += y[c][i] * s.Gf[f][r][0][i];
+          b1 += y[c][i] * s.Gf[f][r][1][i];
+          bn0 += yn[c][i] * s.Gf[fn][rn][0][i];
+          bn1 += yn[c][i] * s.Gf[fn][rn][1][i];
+        }
+        uo[c] = a * isq;
+        un[c] = an * isqn;
+        yo[c] = ya * isq;
+        ynb[c] = yan * isqn;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          go[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
+          gn[c][j] = isqn * (bn0 * Jn[0][j] + bn1 * Jn[1][j]);
+        }
+      }
+      const double unrm = 0.5 * ((uo[0] + un[0]) * n0 + (uo[1] + un[1]) * n1);
+      const bool own_up = unrm >= 0.0;
+      double dy[2], upv[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        dy[c] = yo[c] - ynb[c];
+        upv[c] = own_up ? uo[c] : un[c];
+      }
+      const double updy = upv[0] * dy[0] + upv[1] * dy[1];
+      const double nn[2] = {n0, n1};
+      double Av[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double avgn = 0.5 * ((go[c][0] + gn[c][0]) * n0 + (go[c][1] + gn[c][1]) * n1);
+        const double conv = -(0.5 * nn[c] * updy + (own_up ? unrm * dy[c] : 0.0));
+        Av[c] = conv + nu * avgn - nu * sig * dy[c];  // minus the viscous flux Q(y)
+      }
+      const double w = s.Wf[r] * len * isq;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const double h = 0.5 * nu * dy[c];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          acc[c][i] += w * (Av[c] * s.Vf[f][r][i] + h * (nJ[0] * s.Gf[f][r][0][i] + nJ[1] * s.Gf[f][r][1][i]));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) Ubar[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+// ---------------------------------------------------------------------------------------
+// a4: condensation right-hand side, element part: q_{T,f} = C_{T,f} W_T F_T
+// ---------------------------------------------------------------------------------------
+// C_{T,f}: (C y)_m = sgn_m sqrt(|F|/detJ) sum_c n_c sum_i Chat_f[m][i] y[c][i], with
+// sgn_m = (-1)^m when the element traverses the facet against the facet's parameter.
+template <int K, typename FT>
+__global__ __launch_bounds__(kEBlk) void k_cond_rhs(DevGeo g, DevTabs tb, const FT* __restrict__ F,
+                                                    double* __restrict__ q) {
+  constexpr int P = nP(K), NF = nF(K);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double y[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[c][i] = (double)F[(size_t)(c * P + i) * T + t];
+  double Ji[2][2];
+  load_Jinv(g, t, Ji);
+  apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int code = g.code[idx];
+    const bool flip = ((code >> 3) & 1) && ((code >> 2) & 1);
+    const double sc = g.sF[idx], n0 = g.nx[idx], n1 = g.ny[idx];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      double a0 = 0, a1 = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const double ch = tb.Ch[(f * NF + m) * P + i];
+        a0 += ch * y[0][i];
+        a1 += ch * y[1][i];
+      }
+      double val = sc * (n0 * a0 + n1 * a1);
+      if (flip && (m & 1)) val = -val;
+      q[(size_t)(f * NF + m) * T + t] = val;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// a6: recovery u_T = W_T (F_T - C_T^T lambda_T) with the RK3 combination epilogue
+// ---------------------------------------------------------------------------------------
+template <int K, typename FT>
+// out may alias Un or Us: each thread reads its own entries before writing them.
+__global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const FT* __restrict__ F,
+                                                   const double* __restrict__ lam, double* out, int mode, double ca,
+                                                   const double* Un, double cb, const double* Us, double dt) {
+  constexpr int P = nP(K), NF = nF(K);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double y[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[c][i] = (double)F[(size_t)(c * P + i) * T + t];
+#pragma unroll
+  for (int f = 0; f < 3; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int code = g.code[idx];
+    const bool flip = ((code >> 3) & 1) && ((code >> 2) & 1);
+    const double sc = g.sF[idx], n0 = g.nx[idx], n1 = g.ny[idx];
+    const int Fi = g.efacet[idx];
+    double lm[NF];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const double l = lam[(size_t)Fi * NF + m];
+      lm[m] = (flip && (m & 1)) ? -l : l;
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int m = 0; m < NF; ++m) s += lm[m] * tb.Ch[(f * NF + m) * P + i];
+      y[0][i] -= sc * n0 * s;
+      y[1][i] -= sc * n1 * s;
+    }
+  }
+  double Ji[2][2];
+  load_Jinv(g, t, Ji);
+  apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const size_t o = (size_t)(c * P + i) * T + t;
+      if (mode == 0) out[o] = y[c][i];
+      else out[o] = ca * Un[o] + cb * (Us[o] + dt * y[c][i]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// a5: facet PCG
+// ---------------------------------------------------------------------------------------
+
+// g_F = q_{L,f_L} + q_{R,f_R}; reductions (g,g), (zdef,g).
+template <int NF>
+__global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __restrict__ q, double* __restrict__ gv,
+                                                   PcgScalars* sc, double* partials, double rtol, int maxit) {
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int T = g.T;
+  double v[2] = {0, 0};
+  if (F < g.E) {
+    const int a = g.qL[F], b = g.qR[F];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const double x = q[a + (size_t)m * T] + q[b + (size_t)m * T];
+      gv[(size_t)F * NF + m] = x;
+      v[0] += x * x;
+      if (m == 0) v[1] += g.zdef[F] * x;
+    }
+  }
+  double tot[2];
+  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
+    const double gg = tot[0] - tot[1] * tot[1];  // ||g - (z.g) z||^2 with ||z|| = 1
+    sc->gg = gg;
+    sc->zg = tot[1];
+    sc->tol2 = rtol * rtol * gg;
+    sc->maxit = maxit;
+    sc->zero_rhs = !(gg > 0.0);
+    sc->done = isfinite(gg) ? PCG_RUNNING : PCG_NONFINITE;
+  }
+}
+
+template <int NF, bool BJ, typename V, typename M>
+__device__ inline void precond(const DevBsr& A, int F, const V (&r)[NF], V (&z)[NF]) {
+  if (BJ) {
+    const M* B = (sizeof(V) == 8) ? (const M*)A.binv : (const M*)A.binv32;
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      V s = 0;
+#pragma unroll
+      for (int b = 0; b < NF; ++b) s += (V)B[((size_t)F * NF + a) * NF + b] * r[b];
+      z[a] = s;
+    }
+  } else {
+    const M* d = (sizeof(V) == 8) ? (const M*)A.dinv : (const M*)A.dinv32;
+#pragma unroll
+    for (int a = 0; a < NF; ++a) z[a] = (V)d[(size_t)F * NF + a] * r[a];
+  }
+}
+
+// y = S x for row F (x given by a functor returning the NF-vector of a column facet).
+template <int NF, typename V, typename M, typename Getter>
+__device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
+  const M* vals = (sizeof(M) == 8) ? (const M*)A.vals : (const M*)A.vals32;
+#pragma unroll
+  for (int a = 0; a < NF; ++a) y[a] = 0;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const int c = A.cols[(size_t)s * E + F];
+    V xc[NF];
+    get(c, xc);
+#pragma unroll
+    for (int a = 0; a < NF; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) y[a] += (V)vals[(((size_t)s * NF + a) * NF + b) * E + F] * xc[b];
+  }
+}
+
+// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0.
+template <int NF, bool BJ>
+__global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
+                                                   double* __restrict__ x, double* __restrict__ r,
+                                                   double* __restrict__ z, double* __restrict__ p_old,
+                                                   PcgScalars* sc, double* partials) {
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int E = g.E;
+  if (sc->done != PCG_RUNNING) return;
+  if (sc->zero_rhs) {
+    if (F < E)
+#pragma unroll
+      for (int m = 0; m < NF; ++m) {
+        const size_t o = (size_t)F * NF + m;
+        x[o] = 0; r[o] = 0; z[o] = 0; p_old[o] = 0;
+      }
+    if (F == 0) { sc->rz = 0; sc->rr = 0; sc->beta = 0; sc->iters = 0; sc->done = PCG_CONVERGED; }
+    return;
+  }
+  const double zg = sc->zg;
+  double v[2] = {0, 0};
+  if (F < E) {
+    double Sx[NF];
+    spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
+#pragma unroll
+      for (int b = 0; b < NF; ++b) xc[b] = x[(size_t)c * NF + b];
+    }, Sx);
+    double rr[NF], zz[NF];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      double gm = gv[(size_t)F * NF + m];
+      if (m == 0) gm -= zg * g.zdef[F];
+      rr[m] = gm - Sx[m];
+    }
+    precond<NF, BJ, double, double>(A, F, rr, zz);
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const size_t o = (size_t)F * NF + m;
+      r[o] = rr[m];
+      z[o] = zz[m];
+      p_old[o] = 0;
+      v[0] += rr[m] * zz[m];
+      v[1] += rr[m] * rr[m];
+    }
+  }
+  double tot[2];
+  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    sc->beta = 0;
+    sc->iters = 0;
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->done = PCG_NONFINITE;
+    else if (tot[1] <= sc->tol2) sc->done = PCG_CONVERGED;
+  }
+}
+
+// p_new = z + beta p_old (own row, and on the fly for the columns), Sp = S p_new,
+// alpha = rz / (p_new, Sp).
+template <int NF, typename V, typename M>
+__global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* __restrict__ z,
+                                                   const V* __restrict__ p_old, V* __restrict__ p_new,
+                                                   V* __restrict__ Sp, PcgScalars* sc, double* partials) {
+  if (sc->done != PCG_RUNNING) return;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int E = g.E;
+  const V beta = (V)sc->beta;
+  double v[1] = {0};
+  if (F < E) {
+    V y[NF];
+    spmv_row<NF, V, M>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int b = 0; b < NF; ++b) xc[b] = z[(size_t)c * NF + b] + beta * p_old[(size_t)c * NF + b];
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      const V pn = z[o] + beta * p_old[o];
+      p_new[o] = pn;
+      Sp[o] = y[a];
+      v[0] += (double)pn * (double)y[a];
+    }
+  }
+  double tot[1];
+  if (reduce_last_block<1>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
+    sc->pq = tot[0];
+    if (!isfinite(tot[0])) sc->done = PCG_NONFINITE;
+    else if (!(tot[0] > 0)) sc->done = PCG_BREAKDOWN;
+    else sc->alpha = sc->rz / tot[0];
+  }
+}
+
+template <int NF, bool BJ, typename V, typename M>
+__global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V* __restrict__ p,
+                                                     const V* __restrict__ Sp, V* __restrict__ x, V* __restrict__ r,
+                                                     V* __restrict__ z, PcgScalars* sc, double* partials) {
+  if (sc->done != PCG_RUNNING) return;
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int E = g.E;
+  const V alpha = (V)sc->alpha;
+  double v[2] = {0, 0};
+  if (F < E) {
+    V rr[NF], zz[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      x[o] += alpha * p[o];
+      rr[a] = r[o] - alpha * Sp[o];
+      r[o] = rr[a];
+    }
+    precond<NF, BJ, V, M>(A, F, rr, zz);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      z[(size_t)F * NF + a] = zz[a];
+      v[0] += (double)rr[a] * (double)zz[a];
+      v[1] += (double)rr[a] * (double)rr[a];
+    }
+  }
+  double tot[2];
+  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
+    const int it = sc->iters + 1;
+    sc->iters = it;
+    sc->beta = tot[0] / sc->rz;
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->done = PCG_NONFINITE;
+    else if (tot[1] <= sc->tol2) sc->done = PCG_CONVERGED;
+    else if (it >= sc->maxit) sc->done = PCG_MAXIT;
+  }
+}
+
+// Inner FP32 PCG start for S d = r64 (x = 0): r = (float) r64, tolerance relative to ||r64||.
+template <int NF, bool BJ>
+__global__ __launch_bounds__(kBlk) void k_pcg32_init(DevGeo g, DevBsr A, const double* __restrict__ r64,
+                                                     float* __restrict__ x, float* __restrict__ r,
+                                                     float* __restrict__ z, float* __restrict__ p_old,
+                                                     PcgScalars* sc, double* partials, double rtol, int maxit) {
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int E = g.E;
+  double v[3] = {0, 0, 0};
+  if (F < E) {
+    float rr[NF], zz[NF];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) rr[m] = (float)r64[(size_t)F * NF + m];
+    precond<NF, BJ, float, float>(A, F, rr, zz);
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const size_t o = (size_t)F * NF + m;
+      x[o] = 0; r[o] = rr[m]; z[o] = zz[m]; p_old[o] = 0;
+      v[0] += (double)rr[m] * zz[m];
+      v[1] += (double)rr[m] * rr[m];
+    }
+    v[2] = v[1];
+  }
+  double tot[3];
+  if (reduce_last_block<3>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
+    sc->rz = tot[0];
+    sc->rr = tot[1];
+    sc->gg = tot[2];
+    sc->tol2 = rtol * rtol * tot[2];
+    sc->beta = 0;
+    sc->iters = 0;
+    sc->maxit = maxit;
+    sc->done = (!isfinite(tot[0]) || !isfinite(tot[1])) ? PCG_NONFINITE
+               : (tot[1] <= sc->tol2 ? PCG_CONVERGED : PCG_RUNNING);
+  }
+}
+
+// FP64 refinement residual r64 = g - zg zdef - S lam and (r64, r64).
+template <int NF>
+__global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const double* __restrict__ gv,
+                                                      const double* __restrict__ lam, double* __restrict__ r64,
+                                                      PcgScalars* sc, double* partials) {
+  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+  const int E = g.E;
+  const double zg = sc->zg;
+  double v[1] = {0};
+  if (F < E) {
+    double Sx[NF];
+    spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
+#pragma unroll
+      for (int b = 0; b < NF; ++b) xc[b] = lam[(size_t)c * NF + b];
+    }, Sx);
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      double gm = gv[(size_t)F * NF + m];
+      if (m == 0) gm -= zg * g.zdef[F];
+      const double rm = gm - Sx[m];
+      r64[(size_t)F * NF + m] = rm;
+      v[0] += rm * rm;
+    }
+  }
+  double tot[1];
+  if (reduce_last_block<1>(v, partials, &sc->counter, tot) && threadIdx.x == 0) sc->rr = tot[0];
+}
+
+__global__ void k_add_f32(long n, const float* __restrict__ x, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += (double)x[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// a2: load vector of data given at the projection points; evaluation; diagnostics
+// ---------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_load_vector(DevGeo g, DevTabs tb, int nqp, const double* __restrict__ fq,
+                                                       double* __restrict__ F) {
+  constexpr int P = nP(K);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double sq = sqrt(g.detJ[t]);
+  double acc[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc[c][i] = 0;
+  for (int q = 0; q < nqp; ++q) {
+    const double w = tb.Wp[q] * sq;
+    const double f0 = fq[(size_t)q * T + t] * w, f1 = fq[(size_t)(nqp + q) * T + t] * w;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const double v = tb.Vp[q * P + i];
+      acc[0][i] += f0 * v;
+      acc[1][i] += f1 * v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) F[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_eval(DevGeo g, int npts, const double* __restrict__ tab,
+                                                const double* __restrict__ U, double* __restrict__ out) {
+  constexpr int P = nP(K);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double isq = 1.0 / sqrt(g.detJ[t]);
+  double u[2][P];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[c][i] = U[(size_t)(c * P + i) * T + t];
+  for (int p = 0; p < npts; ++p)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) s += u[c][i] * tab[p * P + i];
+      out[(size_t)(c * npts + p) * T + t] = s * isq;
+    }
+}
+
+// Per block: sum 0.5 U^2, sum curl^2 (volume rule), max |div u| (volume points),
+// max |[[u.n]]| (facet points, facets this element owns as L side).
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                double* __restrict__ partials) {
+  constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
+  const int T = g.T;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double en = 0, ens = 0, dmax = 0, jmax = 0;
+  if (t < T) {
+    double u[2][P];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        u[c][i] = U[(size_t)(c * P + i) * T + t];
+        en += 0.5 * u[c][i] * u[c][i];
+      }
+    double Ji[2][2];
+    load_Jinv(g, t, Ji);
+    const double det = g.detJ[t], isq = 1.0 / sqrt(det);
+    for (int q = 0; q < NQV; ++q) {
+      double gr[2][2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double b0 = 0, b1 = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          b0 += u[c][i] * tb.Gv[(q * 2 + 0) * P + i];
+          b1 += u[c][i] * tb.Gv[(q * 2 + 1) * P + i];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) gr[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
+      }
+      const double curl = gr[1][0] - gr[0][1];
+      ens += tb.Wv[q] * det * curl * curl;
+      dmax = fmax(dmax, fabs(gr[0][0] + gr[1][1]));
+    }
+    for (int f = 0; f < 3; ++f) {
+      const size_t idx = (size_t)f * T + t;
+      const int code = g.code[idx];
+      if ((code >> 3) & 1) continue;  // the L side measures the facet
+      const int nb = g.nbr[idx], fn = code & 3;
+      const bool rev = (code >> 2) & 1;
+      const double n0 = g.nx[idx], n1 = g.ny[idx], isqn = 1.0 / sqrt(g.detJ[nb]);
+      for (int r = 0; r < NQF; ++r) {
+        const int rn = rev ? NQF - 1 - r : r;
+        double jo = 0, jn = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const double vo = tb.Vf[(f * NQF + r) * P + i], vn = tb.Vf[(fn * NQF + rn) * P + i];
+          jo += (u[0][i] * n0 + u[1][i] * n1) * vo;
+          jn += (U[(size_t)i * T + nb] * n0 + U[(size_t)(P + i) * T + nb] * n1) * vn;
+        }
+        jmax = fmax(jmax, fabs(jo * isq - jn * isqn));
+      }
+    }
+  }
+  __shared__ double sh[4][kEBlk / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  en = wave_sum(en);
+  ens = wave_sum(ens);
+  dmax = wave_max(dmax);
+  jmax = wave_max(jmax);
+  if (lane == 0) { sh[0][wid] = en; sh[1][wid] = ens; sh[2][wid] = dmax; sh[3][wid] = jmax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0, c = 0, d = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += sh[0][w]; b += sh[1][w]; c = fmax(c, sh[2][w]); d = fmax(d, sh[3][w]);
+    }
+    partials[4 * blockIdx.x + 0] = a;
+    partials[4 * blockIdx.x + 1] = b;
+    partials[4 * blockIdx.x + 2] = c;
+    partials[4 * blockIdx.x + 3] = d;
+  }
+}
+
+__global__ __launch_bounds__(kBlk) void k_diag_finish(int nblk, const double* __restrict__ partials,
+                                                      double* __restrict__ res) {
+  double a = 0, b = 0, c = 0, d = 0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
+    a += partials[4 * i]; b += partials[4 * i + 1];
+    c = fmax(c, partials[4 * i + 2]); d = fmax(d, partials[4 * i + 3]);
+  }
+  __shared__ double sh[4][kBlk / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  a = wave_sum(a); b = wave_sum(b); c = wave_max(c); d = wave_max(d);
+  if (lane == 0) { sh[0][wid] = a; sh[1][wid] = b; sh[2][wid] = c; sh[3][wid] = d; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      sh[0][0] += sh[0][w]; sh[1][0] += sh[1][w];
+      sh[2][0] = fmax(sh[2][0], sh[2][w]); sh[3][0] = fmax(sh[3][0], sh[3][w]);
+    }
+    res[0] = sh[0][0]; res[1] = sh[1][0]; res[2] = sh[2][0]; res[3] = sh[3][0];
+  }
+}
+
+__global__ void k_axpby(long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (b == 0.0) ? a * x[i] : a * x[i] + b * y[i];  // b = 0: y may be uninitialised
+}
+__global__ void k_fill(long n, double v, double* __restrict__ y) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = v;
+}
+// Polynomial extrapolation in time from h0 (newest), h1, h2 (oldest), equal spacing.
+__global__ void k_extrapolate(long n, int order, const double* __restrict__ h0, const double* __restrict__ h1,
+                              const double* __restrict__ h2, double* __restrict__ out) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v;
+  if (order >= 2) v = 3.0 * h0[i] - 3.0 * h1[i] + h2[i];
+  else if (order == 1) v = 2.0 * h0[i] - h1[i];
+  else v = h0[i];
+  out[i] = v;
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+#define DFDG_DISPATCH_K(K, ...)                                   \
+  switch (K) {                                                    \
+    case 1: { constexpr int KK = 1; __VA_ARGS__; } break;         \
+    case 2: { constexpr int KK = 2; __VA_ARGS__; } break;         \
+    case 3: { constexpr int KK = 3; __VA_ARGS__; } break;         \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+hipError_t launch_residual(int K, bool fp32, const DevGeo& g, const DevTabs& tb, const double* U, void* L,
+                           double nu, hipStream_t s) {
+  DFDG_DISPATCH_K(K, {
+    if (fp32) hipLaunchKernelGGL((k_residual<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (float*)L, nu);
+    else hipLaunchKernelGGL((k_residual<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (double*)L, nu);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_vjp(int K, const DevGeo& g, const DevTabs& tb, const double* U, const double* Lbar,
+                               double* Ubar, double nu, hipStream_t s) {
+  DFDG_DISPATCH_K(K, hipLaunchKernelGGL((k_residual_vjp<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, Lbar,
+                                        Ubar, nu));
+  return hipGetLastError();
+}
+
+hipError_t launch_cond_rhs(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, double* q,
+                           hipStream_t s) {
+  DFDG_DISPATCH_K(K, {
+    if (fp32in) hipLaunchKernelGGL((k_cond_rhs<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const float*)F, q);
+    else hipLaunchKernelGGL((k_cond_rhs<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const double*)F, q);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, const double* lam,
+                          double* out, int mode, double a, const double* Un, double b, const double* Us, double dt,
+                          hipStream_t s) {
+  DFDG_DISPATCH_K(K, {
+    if (fp32in)
+      hipLaunchKernelGGL((k_recover<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const float*)F, lam, out,
+                         mode, a, Un, b, Us, dt);
+    else
+      hipLaunchKernelGGL((k_recover<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const double*)F, lam,
+                         out, mode, a, Un, b, Us, dt);
+  });
+  return hipGetLastError();
+}
+
+#define DFDG_DISPATCH_NF(NF, ...)                                 \
+  switch (NF) {                                                   \
+    case 2: { constexpr int NN = 2; __VA_ARGS__; } break;         \
+    case 3: { constexpr int NN = 3; __VA_ARGS__; } break;         \
+    case 4: { constexpr int NN = 4; __VA_ARGS__; } break;         \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, PcgScalars* sc, double* partials,
+                           double rtol, int maxit, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_gather_g<NN>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, q, gv, sc,
+                                          partials, rtol, maxit));
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
+                           double* z, double* p_old, PcgScalars* sc, double* partials, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, true>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, sc, partials);
+    else hipLaunchKernelGGL((k_pcg_init<NN, false>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, sc, partials);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
+                           double* p_new, double* Sp, PcgScalars* sc, double* partials, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g,
+                                          A, z, p_old, p_new, Sp, sc, partials));
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* p, const double* Sp,
+                             double* x, double* r, double* z, PcgScalars* sc, double* partials, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
+    else hipLaunchKernelGGL((k_pcg_update<NN, false, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg32_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* r64, float* x, float* r,
+                             float* z, float* p_old, PcgScalars* sc, double* partials, double rtol, int maxit,
+                             hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg32_init<NN, true>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, sc, partials, rtol, maxit);
+    else hipLaunchKernelGGL((k_pcg32_init<NN, false>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, sc, partials, rtol, maxit);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
+                             float* p_new, float* Sp, PcgScalars* sc, double* partials, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g,
+                                          A, z, p_old, p_new, Sp, sc, partials));
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg32_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const float* p, const float* Sp,
+                               float* x, float* r, float* z, PcgScalars* sc, double* partials, hipStream_t s) {
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
+    else hipLaunchKernelGGL((k_pcg_update<NN, false, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const double* gv, double* lam,
+                              const float* x32, int add, double* r64, PcgScalars* sc, double* partials,
+                              hipStream_t s) {
+  if (add) {
+    const long n = (long)g.E * NF;
+    hipLaunchKernelGGL(k_add_f32, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, x32, lam);
+  }
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_ir_residual<NN>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, lam,
+                                          r64, sc, partials));
+  return hipGetLastError();
+}
+
+hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
+                              hipStream_t s) {
+  DFDG_DISPATCH_K(K, hipLaunchKernelGGL((k_load_vector<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, nqp, fq, F));
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int K, int npts, const DevGeo& g, const double* tab, const double* U, double* out,
+                       hipStream_t s) {
+  DFDG_DISPATCH_K(K, hipLaunchKernelGGL((k_eval<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, npts, tab, U, out));
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* partials,
+                              double* res, hipStream_t s) {
+  const unsigned nb = nblk(g.T, kEBlk);
+  DFDG_DISPATCH_K(K, hipLaunchKernelGGL((k_diag<KK>), dim3(nb), dim3(kEBlk), 0, s, g, tb, U, partials));
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kBlk), 0, s, (int)nb, partials, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, v, y);
+  return hipGetLastError();
+}
+hipError_t launch_extrapolate(long n, int order, const double* h0, const double* h1, const double* h2, double* out,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_extrapolate, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, order, h0, h1, h2, out);
+  return hipGetLastError();
+}
+
+}  // namespace dfdg

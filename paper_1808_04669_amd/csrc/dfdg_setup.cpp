@@ -1,0 +1,513 @@
+// Host part of the set-up: quadrature, the orthonormal Dubiner basis and its reference
+// tabulations, periodic facet matching, element geometry, the element condensation
+// data and the facet matrix S of the hybrid-mixed system (eq. (FE3) after static
+// condensation).  Everything here runs once per context, in FP64, on the CPU.
+#include "dfdg_setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+
+namespace dfdg {
+
+// ---------------------------------------------------------------------------------------
+// Quadrature
+// ---------------------------------------------------------------------------------------
+
+// Gauss-Legendre on [0,1] by Newton's method on P_n (long double), nodes mirrored so that
+// x[n-1-i] == 1 - x[i] exactly: the facet integrals of two neighbours traverse the same
+// points in opposite order.
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    long double z = std::cos(pi * (i + 0.75L) / (n + 0.5L));
+    long double dp = 0;
+    for (int it = 0; it < 100; ++it) {
+      long double p0 = 1, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      long double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-19L) break;
+    }
+    {
+      long double p0 = 1, p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        long double p2 = ((2 * j - 1) * z * p1 - (j - 1) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = z; p0 = 1; }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+    }
+    long double wt = 2.0L / ((1 - z * z) * dp * dp);
+    // z is the i-th largest root in (-1,1): map to [0,1]
+    long double s_hi = 0.5L * (1 + z);
+    x[n - 1 - i] = (double)s_hi;
+    x[i] = (double)(1.0L - s_hi);
+    w[i] = w[n - 1 - i] = (double)(0.5L * wt);
+  }
+  if (n % 2 == 1) x[n / 2] = 0.5;
+}
+
+// Collapsed rule on {xi, eta >= 0, xi + eta <= 1}: xi = u (1 - v), eta = v, with the
+// Jacobian (1 - v) folded into the weights; Gauss-Legendre in u and v.  Exact for total
+// degree p (the v-integrand has degree p + 1).
+void triangle_rule(int p, std::vector<double>& pts, std::vector<double>& w) {
+  std::vector<double> xu, wu, xv, wv;
+  gauss_legendre01(triNu(p), xu, wu);
+  gauss_legendre01(triNv(p), xv, wv);
+  pts.clear();
+  w.clear();
+  for (size_t i = 0; i < xu.size(); ++i)
+    for (size_t j = 0; j < xv.size(); ++j) {
+      pts.push_back(xu[i] * (1.0 - xv[j]));
+      pts.push_back(xv[j]);
+      w.push_back(wu[i] * wv[j] * (1.0 - xv[j]));
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Orthonormal Dubiner basis of P^K on the reference triangle
+// ---------------------------------------------------------------------------------------
+// psi_pq = Q_p(s, t) R_q(eta) * sqrt((2p+1)(2p+2q+2)) with s = 2 xi - 1 + eta, t = 1 - eta,
+// Q_p(s, t) = t^p Legendre_p(s / t) (a polynomial, computed by the homogenised Legendre
+// recurrence so that the collapsed-coordinate singularity at eta = 1 never appears) and
+// R_q(eta) = Jacobi_q^{(2p+1, 0)}(2 eta - 1).  Ordered by total degree d = p + q, then q:
+// the first dim P^j functions span P^j.
+
+static void jacobi(int n, double a, double b, double x, double* val, double* der) {
+  // P_n^{(a,b)}(x) and its derivative by the three-term recurrence.
+  auto eval = [](int n, double a, double b, double x) {
+    if (n == 0) return 1.0;
+    double p0 = 1.0, p1 = 0.5 * ((a + b + 2) * x + (a - b));
+    for (int k = 2; k <= n; ++k) {
+      double c = 2 * k + a + b;
+      double a1 = 2 * k * (k + a + b) * (c - 2);
+      double a2 = (c - 1) * (c * (c - 2) * x + a * a - b * b);
+      double a3 = 2 * (k + a - 1) * (k + b - 1) * c;
+      double p2 = (a2 * p1 - a3 * p0) / a1;
+      p0 = p1;
+      p1 = p2;
+    }
+    return p1;
+  };
+  *val = eval(n, a, b, x);
+  if (der) *der = (n == 0) ? 0.0 : 0.5 * (n + a + b + 1) * eval(n - 1, a + 1, b + 1, x);
+}
+
+void dubiner(int K, double xi, double eta, double* vals, double* grads) {
+  const int P = nP(K);
+  const double s = 2 * xi - 1 + eta, t = 1 - eta;
+  // Q_p and partial derivatives wrt s and t
+  double Q[kMaxK + 2], Qs[kMaxK + 2], Qt[kMaxK + 2];
+  Q[0] = 1; Qs[0] = 0; Qt[0] = 0;
+  Q[1] = s; Qs[1] = 1; Qt[1] = 0;
+  for (int p = 1; p < K; ++p) {
+    Q[p + 1] = ((2 * p + 1) * s * Q[p] - p * t * t * Q[p - 1]) / (p + 1);
+    Qs[p + 1] = ((2 * p + 1) * (Q[p] + s * Qs[p]) - p * t * t * Qs[p - 1]) / (p + 1);
+    Qt[p + 1] = ((2 * p + 1) * s * Qt[p] - p * (2 * t * Q[p - 1] + t * t * Qt[p - 1])) / (p + 1);
+  }
+  int idx = 0;
+  for (int d = 0; d <= K; ++d)
+    for (int q = 0; q <= d; ++q, ++idx) {
+      const int p = d - q;
+      double R, Rd;
+      jacobi(q, 2 * p + 1, 0, 2 * eta - 1, &R, &Rd);
+      const double c = std::sqrt((2.0 * p + 1) * (2.0 * p + 2.0 * q + 2));
+      vals[idx] = c * Q[p] * R;
+      if (grads) {
+        // d/dxi = 2 dQ/ds R ;  d/deta = (dQ/ds - dQ/dt) R + Q * 2 R'
+        grads[0 * P + idx] = c * 2 * Qs[p] * R;
+        grads[1 * P + idx] = c * ((Qs[p] - Qt[p]) * R + Q[p] * 2 * Rd);
+      }
+    }
+}
+
+double legendre01_orthonormal(int m, double s) {
+  double x = 2 * s - 1, p0 = 1, p1 = x;
+  if (m == 0) return 1.0;
+  for (int j = 2; j <= m; ++j) {
+    double p2 = ((2 * j - 1) * x * p1 - (j - 1) * p0) / j;
+    p0 = p1;
+    p1 = p2;
+  }
+  return std::sqrt(2.0 * m + 1) * p1;
+}
+
+// Local facet f joins reference vertices (f+1)%3 -> (f+2)%3.
+static const double kRefV[3][2] = {{0, 0}, {1, 0}, {0, 1}};
+static void ref_facet_point(int f, double s, double* xh) {
+  const double* a = kRefV[(f + 1) % 3];
+  const double* b = kRefV[(f + 2) % 3];
+  xh[0] = a[0] + s * (b[0] - a[0]);
+  xh[1] = a[1] + s * (b[1] - a[1]);
+}
+
+void build_ref_tables(int K, RefTables& t) {
+  t.K = K;
+  t.P = nP(K);
+  t.NP = nPp(K);
+  t.NF = nF(K);
+  const int P = t.P;
+  triangle_rule(3 * K - 1, t.vq, t.vw);
+  gauss_legendre01(nQF(K), t.fs, t.fw);
+  triangle_rule(projDeg(K), t.pq, t.pw);
+  t.nqv = (int)t.vw.size();
+  t.nqf = (int)t.fw.size();
+  t.nqp = (int)t.pw.size();
+  std::vector<double> v(P), g(2 * P);
+  t.Vv.assign(t.nqv * P, 0);
+  t.Gv.assign(t.nqv * 2 * P, 0);
+  for (int q = 0; q < t.nqv; ++q) {
+    dubiner(K, t.vq[2 * q], t.vq[2 * q + 1], v.data(), g.data());
+    for (int i = 0; i < P; ++i) {
+      t.Vv[q * P + i] = v[i];
+      t.Gv[(q * 2 + 0) * P + i] = g[i];
+      t.Gv[(q * 2 + 1) * P + i] = g[P + i];
+    }
+  }
+  t.Vf.assign(3 * t.nqf * P, 0);
+  t.Gf.assign(3 * t.nqf * 2 * P, 0);
+  for (int f = 0; f < 3; ++f)
+    for (int r = 0; r < t.nqf; ++r) {
+      double xh[2];
+      ref_facet_point(f, t.fs[r], xh);
+      dubiner(K, xh[0], xh[1], v.data(), g.data());
+      for (int i = 0; i < P; ++i) {
+        t.Vf[(f * t.nqf + r) * P + i] = v[i];
+        t.Gf[((f * t.nqf + r) * 2 + 0) * P + i] = g[i];
+        t.Gf[((f * t.nqf + r) * 2 + 1) * P + i] = g[P + i];
+      }
+    }
+  t.Vp.assign(t.nqp * P, 0);
+  for (int q = 0; q < t.nqp; ++q) {
+    dubiner(K, t.pq[2 * q], t.pq[2 * q + 1], v.data(), nullptr);
+    for (int i = 0; i < P; ++i) t.Vp[q * P + i] = v[i];
+  }
+  // Dh[a][j][i] = int_That dpsi_i/dxi_a psi_j  (degree 2K-1: the volume rule is exact)
+  t.Dh.assign(2 * t.NP * P, 0);
+  for (int q = 0; q < t.nqv; ++q)
+    for (int a = 0; a < 2; ++a)
+      for (int j = 0; j < t.NP; ++j)
+        for (int i = 0; i < P; ++i)
+          t.Dh[(a * t.NP + j) * P + i] += t.vw[q] * t.Gv[(q * 2 + a) * P + i] * t.Vv[q * P + j];
+  // Ch[f][m][i] = int_0^1 l_m(s) psi_i(xhat_f(s)) ds  (degree 2K: K+1 Gauss points)
+  std::vector<double> cs, cw;
+  gauss_legendre01(K + 1, cs, cw);
+  t.Ch.assign(3 * t.NF * P, 0);
+  for (int f = 0; f < 3; ++f)
+    for (size_t r = 0; r < cs.size(); ++r) {
+      double xh[2];
+      ref_facet_point(f, cs[r], xh);
+      dubiner(K, xh[0], xh[1], v.data(), nullptr);
+      for (int m = 0; m < t.NF; ++m) {
+        const double l = legendre01_orthonormal(m, cs[r]);
+        for (int i = 0; i < P; ++i) t.Ch[(f * t.NF + m) * P + i] += cw[r] * l * v[i];
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Mesh: periodic facet matching
+// ---------------------------------------------------------------------------------------
+
+static bool same_mod(const double* a, const double* b, const double* per, double tol) {
+  for (int d = 0; d < 2; ++d) {
+    double x = (a[d] - b[d]) / per[d];
+    x -= std::nearbyint(x);
+    if (std::fabs(x) > tol) return false;
+  }
+  return true;
+}
+
+int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std::string& err) {
+  m.T = T;
+  m.xyz.assign(xyz, xyz + 6 * (size_t)T);
+  m.period[0] = period[0];
+  m.period[1] = period[1];
+  double scale = 0;
+  for (size_t i = 0; i < m.xyz.size(); ++i) scale = std::max(scale, std::fabs(m.xyz[i]));
+  scale = std::max(scale, std::max(period[0], period[1]));
+  for (int t = 0; t < T; ++t) {
+    const double* v = &m.xyz[6 * (size_t)t];
+    double det = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
+    if (!(det > 1e-14 * scale * scale)) {
+      err = "element " + std::to_string(t) + " is inverted or degenerate (det J = " + std::to_string(det) +
+            "); vertices must be counter-clockwise";
+      return -2;
+    }
+  }
+  m.efacet.assign(3 * (size_t)T, -1);
+  m.fL.clear(); m.fLloc.clear(); m.fR.clear(); m.fRloc.clear(); m.frev.clear();
+  std::unordered_map<uint64_t, int> first;
+  first.reserve(3 * (size_t)T);
+  const double Q = 1073741824.0;  // 2^30
+  for (int t = 0; t < T; ++t)
+    for (int f = 0; f < 3; ++f) {
+      const double* a = &m.xyz[6 * (size_t)t + 2 * ((f + 1) % 3)];
+      const double* b = &m.xyz[6 * (size_t)t + 2 * ((f + 2) % 3)];
+      uint64_t key = 0;
+      for (int d = 0; d < 2; ++d) {
+        double mid = 0.5 * (a[d] + b[d]) / period[d];
+        mid -= std::floor(mid);
+        long long q = std::llround(mid * Q) % (long long)Q;
+        key = (key << 32) | (uint64_t)q;
+      }
+      auto it = first.find(key);
+      if (it == first.end()) {
+        const int F = (int)m.fL.size();
+        first.emplace(key, F);
+        m.fL.push_back(t); m.fLloc.push_back(f);
+        m.fR.push_back(-1); m.fRloc.push_back(-1); m.frev.push_back(0);
+        m.efacet[3 * t + f] = F;
+      } else {
+        const int F = it->second;
+        if (m.fR[F] >= 0) {
+          err = "facet matched by more than two elements (element " + std::to_string(t) + ")";
+          return -2;
+        }
+        const int L = m.fL[F], fl = m.fLloc[F];
+        if (L == t) {
+          err = "element " + std::to_string(t) + " is adjacent to itself across the periodic boundary";
+          return -2;
+        }
+        const double* la = &m.xyz[6 * (size_t)L + 2 * ((fl + 1) % 3)];
+        const double* lb = &m.xyz[6 * (size_t)L + 2 * ((fl + 2) % 3)];
+        int rev;
+        if (same_mod(a, lb, period, 1e-9) && same_mod(b, la, period, 1e-9)) rev = 1;
+        else if (same_mod(a, la, period, 1e-9) && same_mod(b, lb, period, 1e-9)) rev = 0;
+        else {
+          err = "facet endpoints of elements " + std::to_string(L) + " and " + std::to_string(t) +
+                " do not match modulo the period";
+          return -2;
+        }
+        m.fR[F] = t; m.fRloc[F] = f; m.frev[F] = (uint8_t)rev;
+        m.efacet[3 * t + f] = F;
+        first.erase(it);
+      }
+    }
+  if (!first.empty()) {
+    err = std::to_string(first.size()) + " facets have no periodic partner (boundary facets are not supported)";
+    return -2;
+  }
+  m.E = (int)m.fL.size();
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Geometry, condensation and the facet matrix
+// ---------------------------------------------------------------------------------------
+
+// Cholesky inverse of a small SPD matrix (row-major n x n) in place; false if not SPD.
+static bool spd_inverse(int n, double* A) {
+  std::vector<double> L(n * n, 0.0), Li(n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = A[i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+      if (i == j) {
+        if (!(s > 0)) return false;
+        L[i * n + i] = std::sqrt(s);
+      } else {
+        L[i * n + j] = s / L[j * n + j];
+      }
+    }
+  for (int i = 0; i < n; ++i) {
+    Li[i * n + i] = 1.0 / L[i * n + i];
+    for (int j = 0; j < i; ++j) {
+      double s = 0;
+      for (int k = j; k < i; ++k) s -= L[i * n + k] * Li[k * n + j];
+      Li[i * n + j] = s / L[i * n + i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int k = std::max(i, j); k < n; ++k) s += Li[k * n + i] * Li[k * n + j];
+      A[i * n + j] = s;
+    }
+  return true;
+}
+
+int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::string& err) {
+  build_ref_tables(K, h.tabs);
+  const RefTables& tb = h.tabs;
+  const int T = m.T, E = m.E, P = tb.P, NP = tb.NP, NF = tb.NF, NU = 2 * P;
+  h.T = T;
+  h.E = E;
+  h.K = K;
+  h.Jinv.assign(4 * (size_t)T, 0);
+  h.detJ.assign(T, 0);
+  h.nbr.assign(3 * (size_t)T, 0);
+  h.code.assign(3 * (size_t)T, 0);
+  h.efacet.assign(3 * (size_t)T, 0);
+  h.nx.assign(3 * (size_t)T, 0);
+  h.ny.assign(3 * (size_t)T, 0);
+  h.flen.assign(3 * (size_t)T, 0);
+  h.sig.assign(3 * (size_t)T, 0);
+  h.sF.assign(3 * (size_t)T, 0);
+  h.G.assign((size_t)nGpk(K) * T, 0);
+  h.qL.assign(E, 0);
+  h.qR.assign(E, 0);
+  h.zdef.assign(E, 0);
+  h.cols.assign((size_t)kSlots * E, 0);
+  h.vals.assign((size_t)kSlots * NF * NF * E, 0);
+  h.dinv.assign((size_t)E * NF, 0);
+  h.binv.assign((size_t)E * NF * NF, 0);
+
+  std::vector<double> hT(T);
+  for (int t = 0; t < T; ++t) {
+    const double* v = &m.xyz[6 * (size_t)t];
+    const double J00 = v[2] - v[0], J01 = v[4] - v[0], J10 = v[3] - v[1], J11 = v[5] - v[1];
+    const double det = J00 * J11 - J01 * J10;
+    h.detJ[t] = det;
+    h.Jinv[0 * (size_t)T + t] = J11 / det;   // dxi/dx
+    h.Jinv[1 * (size_t)T + t] = -J01 / det;  // dxi/dy
+    h.Jinv[2 * (size_t)T + t] = -J10 / det;  // deta/dx
+    h.Jinv[3 * (size_t)T + t] = J00 / det;   // deta/dy
+    hT[t] = std::sqrt(det);  // (d! |T|)^(1/d) with |T| = det/2
+  }
+  for (int t = 0; t < T; ++t) {
+    const double* v = &m.xyz[6 * (size_t)t];
+    for (int f = 0; f < 3; ++f) {
+      const int F = m.efacet[3 * t + f];
+      const bool isR = (m.fR[F] == t && m.fRloc[F] == f);
+      const int nb = isR ? m.fL[F] : m.fR[F];
+      const int nbf = isR ? m.fLloc[F] : m.fRloc[F];
+      const double* a = v + 2 * ((f + 1) % 3);
+      const double* b = v + 2 * ((f + 2) % 3);
+      const double tx = b[0] - a[0], ty = b[1] - a[1];
+      const double len = std::sqrt(tx * tx + ty * ty);
+      const size_t idx = (size_t)f * T + t;
+      h.nbr[idx] = nb;
+      h.code[idx] = nbf | (m.frev[F] << 2) | ((isR ? 1 : 0) << 3);
+      h.efacet[idx] = F;
+      h.nx[idx] = ty / len;
+      h.ny[idx] = -tx / len;
+      h.flen[idx] = len;
+      h.sig[idx] = alpha * K * K / std::min(hT[t], hT[nb]);
+      h.sF[idx] = std::sqrt(len / h.detJ[t]);
+    }
+  }
+  double zz = 0;
+  for (int F = 0; F < E; ++F) {
+    h.qL[F] = m.fLloc[F] * NF * T + m.fL[F];
+    h.qR[F] = m.fRloc[F] * NF * T + m.fR[F];
+    const double len = h.flen[(size_t)m.fLloc[F] * T + m.fL[F]];
+    h.zdef[F] = std::sqrt(len);
+    zz += len;
+  }
+  for (int F = 0; F < E; ++F) h.zdef[F] /= std::sqrt(zz);
+
+  // Element condensation.  With the orthonormal basis the element mass matrix is I and
+  //   W_T = I - D_T^T (D_T D_T^T)^{-1} D_T          (velocity block of K_T^{-1})
+  //   S_T = C_T W_T C_T^T,   S = sum_T S_T            (eq. (FE3) condensed)
+  std::vector<double> D(NP * NU), DDt(NP * NP), W(NU * NU), C(3 * NF * NU), CW(3 * NF * NU),
+      ST(9 * NF * NF);
+  for (int t = 0; t < T; ++t) {
+    const double Ji[2][2] = {{h.Jinv[0 * (size_t)T + t], h.Jinv[1 * (size_t)T + t]},
+                             {h.Jinv[2 * (size_t)T + t], h.Jinv[3 * (size_t)T + t]}};
+    for (int j = 0; j < NP; ++j)
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < P; ++i)
+          D[j * NU + c * P + i] =
+              Ji[0][c] * tb.Dh[(0 * NP + j) * P + i] + Ji[1][c] * tb.Dh[(1 * NP + j) * P + i];
+    for (int j = 0; j < NP; ++j)
+      for (int l = 0; l < NP; ++l) {
+        double s = 0;
+        for (int x = 0; x < NU; ++x) s += D[j * NU + x] * D[l * NU + x];
+        DDt[j * NP + l] = s;
+      }
+    if (!spd_inverse(NP, DDt.data())) {
+      err = "divergence matrix of element " + std::to_string(t) + " is rank deficient";
+      return -2;
+    }
+    for (int j = 0, p = 0; j < NP; ++j)
+      for (int l = 0; l <= j; ++l, ++p) h.G[(size_t)p * T + t] = DDt[j * NP + l];
+    for (int x = 0; x < NU; ++x)
+      for (int y = 0; y < NU; ++y) {
+        double s = (x == y) ? 1.0 : 0.0;
+        for (int j = 0; j < NP; ++j)
+          for (int l = 0; l < NP; ++l) s -= D[j * NU + x] * DDt[j * NP + l] * D[l * NU + y];
+        W[x * NU + y] = s;
+      }
+    for (int f = 0; f < 3; ++f) {
+      const size_t idx = (size_t)f * T + t;
+      const bool flip = ((h.code[idx] >> 3) & 1) && ((h.code[idx] >> 2) & 1);
+      const double n[2] = {h.nx[idx], h.ny[idx]};
+      for (int mm = 0; mm < NF; ++mm) {
+        const double sg = (flip && (mm & 1)) ? -1.0 : 1.0;
+        for (int c = 0; c < 2; ++c)
+          for (int i = 0; i < P; ++i)
+            C[(f * NF + mm) * NU + c * P + i] = sg * h.sF[idx] * n[c] * tb.Ch[(f * NF + mm) * P + i];
+      }
+    }
+    for (int r = 0; r < 3 * NF; ++r)
+      for (int y = 0; y < NU; ++y) {
+        double s = 0;
+        for (int x = 0; x < NU; ++x) s += C[r * NU + x] * W[x * NU + y];
+        CW[r * NU + y] = s;
+      }
+    for (int r = 0; r < 3 * NF; ++r)
+      for (int c2 = 0; c2 < 3 * NF; ++c2) {
+        double s = 0;
+        for (int y = 0; y < NU; ++y) s += CW[r * NU + y] * C[c2 * NU + y];
+        ST[r * 3 * NF + c2] = s;
+      }
+    // scatter into the facet rows: slot 0 = the facet itself, slots 1-2 the other facets
+    // of its L element, slots 3-4 those of its R element (in local order f+1, f+2)
+    for (int f = 0; f < 3; ++f) {
+      const int F = h.efacet[(size_t)f * T + t];
+      const bool isR = (h.code[(size_t)f * T + t] >> 3) & 1;
+      for (int f2 = 0; f2 < 3; ++f2) {
+        const int F2 = h.efacet[(size_t)f2 * T + t];
+        int slot = 0;
+        if (f2 != f) slot = (isR ? 3 : 1) + ((f2 - f + 3) % 3) - 1;
+        h.cols[(size_t)slot * E + F] = F2;
+        for (int a = 0; a < NF; ++a)
+          for (int b = 0; b < NF; ++b)
+            h.vals[(((size_t)slot * NF + a) * NF + b) * E + F] += ST[(f * NF + a) * 3 * NF + f2 * NF + b];
+      }
+    }
+  }
+  // merge repeated columns of a row (tiny periodic meshes) into their first slot
+  for (int F = 0; F < E; ++F)
+    for (int s = 1; s < kSlots; ++s)
+      for (int s2 = 0; s2 < s; ++s2)
+        if (h.cols[(size_t)s * E + F] == h.cols[(size_t)s2 * E + F]) {
+          for (int a = 0; a < NF * NF; ++a) {
+            h.vals[((size_t)s2 * NF * NF + a) * E + F] += h.vals[((size_t)s * NF * NF + a) * E + F];
+            h.vals[((size_t)s * NF * NF + a) * E + F] = 0.0;
+          }
+          break;
+        }
+  std::vector<double> B(NF * NF);
+  for (int F = 0; F < E; ++F) {
+    for (int a = 0; a < NF; ++a) {
+      const double d = h.vals[(((size_t)0 * NF + a) * NF + a) * E + F];
+      if (!(d > 0)) {
+        err = "facet matrix has a non-positive diagonal at facet " + std::to_string(F);
+        return -2;
+      }
+      h.dinv[(size_t)F * NF + a] = 1.0 / d;
+      for (int b = 0; b < NF; ++b) B[a * NF + b] = h.vals[(((size_t)0 * NF + a) * NF + b) * E + F];
+    }
+    if (!spd_inverse(NF, B.data())) {
+      err = "facet diagonal block " + std::to_string(F) + " is not positive definite";
+      return -2;
+    }
+    for (int a = 0; a < NF * NF; ++a) h.binv[(size_t)F * NF * NF + a] = B[a];
+  }
+  return 0;
+}
+
+}  // namespace dfdg

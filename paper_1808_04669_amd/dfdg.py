@@ -1,0 +1,286 @@
+"""Thin ctypes binding of libdfdg.so (the C ABI in include/dfdg.h).
+
+Only argument marshalling lives here: every step of the method runs in the HIP
+kernels of the library.  PyTorch provides device memory (the workspace and the
+vectors) and the stream.  Loading fails loudly if the library is missing; there
+is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfdg.so")
+
+DFDG_OK = 0
+STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_MESH", -3: "E_WORKSPACE", -4: "E_HIP",
+          -5: "E_NOT_CONVERGED", -6: "E_NONFINITE", -7: "E_BREAKDOWN", -8: "E_UNSUPPORTED"}
+FP64, MIXED = 0, 1
+JACOBI, BLOCK_JACOBI = 0, 1
+
+
+class DfdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dfdg {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("nu", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
+                ("precond", ctypes.c_int), ("ir_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("extrapolate", ctypes.c_int)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("E", ctypes.c_int32), ("k", ctypes.c_int32), ("P", ctypes.c_int32),
+                ("n_f", ctypes.c_int32), ("n_p", ctypes.c_int32), ("n_broken", ctypes.c_int64),
+                ("n_lambda", ctypes.c_int64), ("n_bdm", ctypes.c_int64), ("nq_proj", ctypes.c_int32)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int * 3), ("max_refinements", ctypes.c_int),
+                ("max_rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("energy", ctypes.c_double), ("enstrophy", ctypes.c_double), ("max_div", ctypes.c_double),
+                ("max_normal_jump", ctypes.c_double)]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_SIGS = {
+    "dfdg_mesh_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, ctypes.POINTER(_P)]),
+    "dfdg_mesh_destroy": (None, [_P]),
+    "dfdg_mesh_last_error": (ctypes.c_char_p, []),
+    "dfdg_mesh_counts": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "dfdg_mesh_facets": (ctypes.c_int, [_P, _P]),
+    "dfdg_params_default": (None, [ctypes.POINTER(Params)]),
+    "dfdg_ctx_create": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
+    "dfdg_ctx_set_stream": (ctypes.c_int, [_P, _P]),
+    "dfdg_ctx_sizes": (ctypes.c_int, [_P, ctypes.POINTER(Sizes)]),
+    "dfdg_ctx_workspace_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
+    "dfdg_ctx_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "dfdg_last_error": (ctypes.c_char_p, [_P]),
+    "dfdg_ctx_destroy": (None, [_P]),
+    "dfdg_proj_rule": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_load_vector": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_project": (ctypes.c_int, [_P, _P, _P, ctypes.POINTER(SolveInfo)]),
+    "dfdg_dg_residual": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_hdiv_mass_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
+    "dfdg_rk3_step": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
+    "dfdg_reset_history": (ctypes.c_int, [_P]),
+    "dfdg_dg_residual_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
+    "dfdg_rk3_step_vjp": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
+    "dfdg_diagnostics": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
+    "dfdg_eval": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
+    "dfdg_time_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
+                                        ctypes.POINTER(ctypes.c_double)]),
+    "dfdg_debug_basis": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
+    "dfdg_debug_facet_matrix": (ctypes.c_int, [_P, _P, _P]),
+}
+EXPORTED = tuple(_SIGS)
+
+
+def load_library(path=LIB_PATH):
+    """Load libdfdg.so and declare every entry point (raises if anything is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libdfdg.so not found at {path}: build it with `python -m paper_1808_04669_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    """A periodic triangle mesh (host object of the library)."""
+
+    def __init__(self, xyz, period):
+        lib = load_library()
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        per = np.ascontiguousarray(period, dtype=np.float64)
+        h = ctypes.c_void_p()
+        rc = lib.dfdg_mesh_create(2, xyz.shape[0], xyz.ctypes.data_as(_P), per.ctypes.data_as(_P), ctypes.byref(h))
+        if rc != DFDG_OK:
+            raise DfdgError(rc, lib.dfdg_mesh_last_error().decode())
+        self._h = h
+        self._lib = lib
+        T, E = ctypes.c_int(), ctypes.c_int()
+        lib.dfdg_mesh_counts(h, ctypes.byref(T), ctypes.byref(E))
+        self.T, self.E = T.value, E.value
+
+    def facets(self):
+        out = np.empty((self.E, 4), dtype=np.int32)
+        self._lib.dfdg_mesh_facets(self._h, out.ctypes.data_as(_P))
+        return out
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.dfdg_mesh_destroy(self._h)
+            self._h = None
+
+
+class Solver:
+    """One discretisation context on one GPU: mesh + parameters + bound workspace.
+
+    Vectors are torch float64 CUDA tensors of length n_broken (velocity-like,
+    layout [2][P][T]) or n_lambda (facet multipliers, [E][n_f]).
+    """
+
+    def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
+                 precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, device="cuda:0", stream=None):
+        lib = load_library()
+        self._lib = lib
+        self.device = torch.device(device)
+        self.mesh = Mesh(xyz, period)
+        p = Params()
+        lib.dfdg_params_default(ctypes.byref(p))
+        p.k, p.nu, p.alpha = int(k), float(nu), float(alpha)
+        p.precision = {"fp64": FP64, "mixed": MIXED}[precision]
+        p.cg_rtol, p.cg_maxit = float(cg_rtol), int(cg_maxit)
+        p.precond = {"jacobi": JACOBI, "block_jacobi": BLOCK_JACOBI}[precond]
+        p.ir_rtol, p.inner_rtol, p.extrapolate = float(ir_rtol), float(inner_rtol), int(extrapolate)
+        self.params = p
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        rc = lib.dfdg_ctx_create(self.mesh._h, ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(h))
+        if rc != DFDG_OK:
+            raise DfdgError(rc, lib.dfdg_last_error(None).decode())
+        self._h = h
+        s = Sizes()
+        self._check(lib.dfdg_ctx_sizes(h, ctypes.byref(s)))
+        self.sizes = s
+        self.T, self.E, self.k, self.P = s.T, s.E, s.k, s.P
+        self.n_broken, self.n_lambda, self.n_bdm, self.nq_proj = s.n_broken, s.n_lambda, s.n_bdm, s.nq_proj
+        nb = ctypes.c_size_t()
+        self._check(lib.dfdg_ctx_workspace_bytes(h, ctypes.byref(nb)))
+        self.workspace = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._check(lib.dfdg_ctx_bind_workspace(h, ctypes.c_void_p(base + off), nb.value))
+
+    # ---- helpers ------------------------------------------------------------------
+    def _check(self, rc):
+        if rc != DFDG_OK:
+            raise DfdgError(rc, self._lib.dfdg_last_error(self._h if hasattr(self, "_h") else None).decode())
+
+    def _vec(self, t, n, name):
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.device == self.device
+                and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"{name}: expected a contiguous float64 tensor of {n} elements on {self.device}")
+        return _ptr(t)
+
+    def new_vector(self, kind="broken"):
+        n = self.n_broken if kind == "broken" else self.n_lambda
+        return torch.zeros(n, dtype=torch.float64, device=self.device)
+
+    def proj_rule(self):
+        pts = np.empty((self.nq_proj, 2))
+        w = np.empty(self.nq_proj)
+        self._check(self._lib.dfdg_proj_rule(self._h, pts.ctypes.data_as(_P), w.ctypes.data_as(_P)))
+        return pts, w
+
+    # ---- entry points -----------------------------------------------------------------
+    def load_vector(self, f_at_q, F=None):
+        F = self.new_vector() if F is None else F
+        fq = f_at_q.contiguous()
+        self._check(self._lib.dfdg_load_vector(self._h, self._vec(fq, 2 * self.nq_proj * self.T, "f_at_q"),
+                                               self._vec(F, self.n_broken, "F")))
+        return F
+
+    def project(self, f_at_q, U=None):
+        U = self.new_vector() if U is None else U
+        info = SolveInfo()
+        fq = f_at_q.contiguous()
+        self._check(self._lib.dfdg_project(self._h, self._vec(fq, 2 * self.nq_proj * self.T, "f_at_q"),
+                                           self._vec(U, self.n_broken, "U"), ctypes.byref(info)))
+        return U, info
+
+    def residual(self, U, L=None):
+        L = self.new_vector() if L is None else L
+        self._check(self._lib.dfdg_dg_residual(self._h, self._vec(U, self.n_broken, "U"),
+                                               self._vec(L, self.n_broken, "L")))
+        return L
+
+    def mass_solve(self, F, U=None, lam=None):
+        U = self.new_vector() if U is None else U
+        info = SolveInfo()
+        lp = None if lam is None else self._vec(lam, self.n_lambda, "lambda")
+        self._check(self._lib.dfdg_hdiv_mass_solve(self._h, self._vec(F, self.n_broken, "F"),
+                                                   self._vec(U, self.n_broken, "U"), lp, ctypes.byref(info)))
+        return U, info
+
+    def rk3_step(self, U, dt):
+        info = StepInfo()
+        self._check(self._lib.dfdg_rk3_step(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(dt),
+                                            ctypes.byref(info)))
+        return info
+
+    def reset_history(self):
+        self._check(self._lib.dfdg_reset_history(self._h))
+
+    def residual_vjp(self, U, Lbar, Ubar=None):
+        Ubar = self.new_vector() if Ubar is None else Ubar
+        self._check(self._lib.dfdg_dg_residual_vjp(self._h, self._vec(U, self.n_broken, "U"),
+                                                   self._vec(Lbar, self.n_broken, "Lbar"),
+                                                   self._vec(Ubar, self.n_broken, "Ubar")))
+        return Ubar
+
+    def rk3_step_vjp(self, Un, Ubar, dt):
+        """In place: Ubar (cotangent of U^{n+1}) becomes the cotangent of U^n."""
+        info = StepInfo()
+        self._check(self._lib.dfdg_rk3_step_vjp(self._h, self._vec(Un, self.n_broken, "Un"),
+                                                self._vec(Ubar, self.n_broken, "Ubar"), ctypes.c_double(dt),
+                                                ctypes.byref(info)))
+        return info
+
+    def diagnostics(self, U):
+        d = Diag()
+        self._check(self._lib.dfdg_diagnostics(self._h, self._vec(U, self.n_broken, "U"), ctypes.byref(d)))
+        return {"energy": d.energy, "enstrophy": d.enstrophy, "max_div": d.max_div,
+                "max_normal_jump": d.max_normal_jump}
+
+    def eval(self, U, ref_pts):
+        ref = np.ascontiguousarray(ref_pts, dtype=np.float64)
+        n = ref.shape[0]
+        out = torch.empty(2 * n * self.T, dtype=torch.float64, device=self.device)
+        self._check(self._lib.dfdg_eval(self._h, self._vec(U, self.n_broken, "U"), n, ref.ctypes.data_as(_P),
+                                        _ptr(out)))
+        return out.view(2, n, self.T)
+
+    def time_kernel(self, which, reps=50):
+        ms = ctypes.c_float()
+        b = ctypes.c_double()
+        self._check(self._lib.dfdg_time_kernel(self._h, int(which), int(reps), ctypes.byref(ms), ctypes.byref(b)))
+        return ms.value, b.value
+
+    # ---- layout helpers -----------------------------------------------------------------
+    def to_tcp(self, U):
+        """View [2, P, T] of a broken vector."""
+        return U.view(2, self.P, self.T)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            self._lib.dfdg_ctx_destroy(self._h)
+            self._h = None

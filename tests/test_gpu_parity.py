@@ -1,0 +1,147 @@
+"""GPU parity of the HIP library against the CPU oracle (FP64 path).
+
+Tolerance: relative L2 difference 1e-10 for velocities (the FP64 target), with the
+facet PCG run at rtol 1e-13 so that the iterative solve is not the limiting error.
+Element-local quantities (the residual) are compared entry by entry at 1e-11.
+"""
+import numpy as np
+import pytest
+import torch
+
+from inputs import (RandomStreamField, double_shear_layer, eval_broken_poly, random_broken_poly,
+                    taylor_green_2d)
+from oracle.quadrature import triangle_rule
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import (broken_residual_on_oracle_basis, make_pair, rel_l2, to_dev, transfer,  # noqa: E402
+                      values_to_lib)
+
+CASES = [(1, 3, "lex"), (1, 8, "morton"), (2, 5, "random"), (2, 8, "morton"), (3, 4, "random"), (3, 7, "morton")]
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("k,N,order", CASES)
+def test_mass_solve_parity(k, N, order):
+    """Divergence-free mass inversion of a random broken polynomial functional (Theorems 1-2)."""
+    _log("mass_solve", k, N, order)
+    orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13)
+    coef = random_broken_poly(s.T, k, seed=10 + k)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U, info = s.mass_solve(F)
+    assert info.status == 0 and info.rel_residual <= 1e-13 and info.iterations > 0
+    rule = triangle_rule(2 * k)
+    R = orc.space.load_vector(eval_broken_poly(coef, rule[0]), rule)
+    U_orc = orc.mass_solve(orc.space.assemble(R))
+    err = rel_l2(orc, s, U, U_orc)
+    _log("  iters", info.iterations, "rel L2", err)
+    assert err < 1e-10
+    d = s.diagnostics(U)
+    scale = np.abs(U.cpu().numpy()).max() * N
+    assert d["max_div"] < 1e-12 * scale
+    assert d["max_normal_jump"] < 1e-10 * scale
+    assert abs(d["energy"] - orc.energy(U_orc)) < 1e-10 * orc.energy(U_orc)
+
+
+@pytest.mark.parametrize("k,N,order", CASES)
+@pytest.mark.parametrize("nu", [0.0, 0.05])
+def test_residual_parity(k, N, order, nu):
+    """L(u)(v) on every broken test function, for a divergence-free u (eqs. (adv), (viscous))."""
+    _log("residual", k, N, order, nu)
+    orc, s, _, _ = make_pair(N, k, nu=nu, order=order, seed=N)
+    U_orc = orc.project(RandomStreamField(seed=k + N, kmax=3))
+    U = transfer(orc, U_orc, s)
+    L = s.residual(U)
+    R_gpu = broken_residual_on_oracle_basis(orc, s, L)
+    R_orc = orc.res.broken(orc.space.local_coeffs(U_orc))
+    err = np.abs(R_gpu - R_orc).max() / np.abs(R_orc).max()
+    _log("  max rel", err)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("k,N", [(1, 4), (2, 3), (3, 3)])
+def test_residual_parity_broken_field(k, N):
+    """The residual of a discontinuous (broken, random) field, where upwinding matters."""
+    orc, s, _, _ = make_pair(N, k, nu=0.02, order="random", seed=3)
+    coef = random_broken_poly(s.T, k, seed=21)
+    U = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    rule = triangle_rule(2 * k)
+    cU = orc.space.broken_project(eval_broken_poly(coef, rule[0]), rule)
+    R_orc = orc.res.broken(cU)
+    R_gpu = broken_residual_on_oracle_basis(orc, s, s.residual(U))
+    assert np.abs(R_gpu - R_orc).max() < 1e-11 * np.abs(R_orc).max()
+
+
+@pytest.mark.parametrize("k,N,nu,field,steps", [
+    (1, 8, 1e-2, "tg", 10),          # 8x8 Taylor-Green, BDM_1, nu = 1e-2, 10 steps
+    (2, 8, 0.0, "dsl", 6),           # double shear layer, inviscid
+    (2, 6, 1e-3, "rand", 5),         # random stream-function field
+    (3, 4, 1e-2, "tg", 4),
+])
+def test_rk3_trajectory_parity(k, N, nu, field, steps):
+    """TVD-RK3 trajectories from the same (oracle-projected) initial data (eq. (rk3))."""
+    _log("rk3", k, N, nu, field, steps)
+    orc, s, _, _ = make_pair(N, k, nu=nu, order="morton", cg_rtol=1e-13)
+    f = {"tg": taylor_green_2d, "dsl": lambda x, y: double_shear_layer(x, y, sharpness=20.0),
+         "rand": RandomStreamField(seed=0, kmax=4)}[field]
+    U0 = orc.project(f)
+    U = transfer(orc, U0, s)
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for n in range(steps):
+        info = s.rk3_step(U, dt)
+        assert info.status == 0
+        Uo = orc.rk3_step(Uo, dt)
+    err = rel_l2(orc, s, U, Uo)
+    _log("  rel L2 after", steps, "steps:", err, "iters", list(info.iterations))
+    assert err < 1e-10
+    d = s.diagnostics(U)
+    assert d["max_div"] < 1e-11
+    assert abs(d["energy"] - orc.energy(Uo)) < 1e-10 * orc.energy(Uo)
+
+
+def test_projection_reproduces_divergence_free_data():
+    """dfdg_project of a field already in V^{k,-1} returns it (L2 projection, Sec. 2.3)."""
+    orc, s, _, _ = make_pair(5, 2, order="random", seed=2, cg_rtol=1e-13)
+    U0 = orc.project(RandomStreamField(seed=5, kmax=3))
+    pts, _ = s.proj_rule()
+    U, info = s.project(to_dev(s, orc.eval_ref(U0, pts)))
+    assert info.status == 0
+    assert rel_l2(orc, s, U, U0) < 1e-11
+
+
+def test_warm_start_and_determinism():
+    """A warm-started solve gives the same velocity; identical runs are bitwise equal."""
+    _, s, _, _ = make_pair(8, 2, oracle=False, cg_rtol=1e-13)
+    coef = random_broken_poly(s.T, 2, seed=4)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U1, i1 = s.mass_solve(F)
+    U2, i2 = s.mass_solve(F)
+    assert torch.equal(U1, U2) and i1.iterations == i2.iterations
+    lam = s.new_vector("lambda")
+    U3, i3 = s.mass_solve(F, lam=lam)      # cold start, lambda returned
+    U4, i4 = s.mass_solve(F, lam=lam)      # warm start from the solution
+    assert i4.iterations < i3.iterations
+    assert (U4 - U3).abs().max().item() < 1e-11 * U3.abs().max().item()
+
+
+def test_mass_solve_symmetric_and_idempotent_full_size():
+    """256x256 BDM_2 (the benchmark mesh): g.P f = f.P g and P(P f) = P f."""
+    _, s, _, _ = make_pair(256, 2, oracle=False, cg_rtol=1e-12)
+    _log("full size: T", s.T, "E", s.E)
+    g0 = torch.Generator(device="cpu").manual_seed(0)
+    f = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
+    g = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
+    Pf, i1 = s.mass_solve(f)
+    Pg, _ = s.mass_solve(g)
+    _log("  iterations", i1.iterations, "rel res", i1.rel_residual)
+    a, b = torch.dot(g, Pf).item(), torch.dot(f, Pg).item()
+    assert abs(a - b) < 1e-9 * abs(a)
+    PPf, _ = s.mass_solve(Pf)
+    assert (PPf - Pf).norm().item() < 1e-9 * Pf.norm().item()
+    d = s.diagnostics(Pf)
+    _log("  diag", d)
+    assert d["max_div"] < 1e-11 * Pf.abs().max().item() * 256
