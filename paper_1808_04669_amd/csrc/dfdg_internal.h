@@ -31,7 +31,6 @@ __host__ __device__ constexpr int nQP(int K) { return triN(projDeg(K)); }
 constexpr int kMaxK = 3;
 constexpr int kSlots = 5;           // BSR blocks per facet row: itself + 2 + 2 neighbours
 constexpr int kMaxEvalPts = 1024;
-constexpr int kRedBlocks = 1024;    // max blocks of a reducing kernel
 
 // ---- reference tabulations (host, FP64) ---------------------------------------------
 struct RefTables {
@@ -86,12 +85,11 @@ struct DevBsr {
   const float* binv32;  // [E][NF][NF]
 };
 
-// Scalars of one PCG run (device memory, one cache line apart from the partials).
+// Scalars of one PCG run (device memory).  Written by block 0 of a kernel (or by a
+// one-block finishing kernel) and read by later kernels and by the host.
 struct PcgScalars {
-  double rz, alpha, beta, rr, gg, tol2, pq, zg;
+  double rz, rr, gg, tol2, zg;
   int iters, done, maxit, zero_rhs;
-  unsigned int counter;  // last-block-done counter of the reducing kernels
-  int pad[3];
 };
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXIT = 3, PCG_NONFINITE = 4 };
 

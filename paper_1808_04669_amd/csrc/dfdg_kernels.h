@@ -18,33 +18,43 @@ hipError_t launch_residual_vjp(int K, const DevGeo& g, const DevTabs& tb, const 
 // or FP32 (fp32in); q is written in FP64 or FP32 (fp32out).
 hipError_t launch_cond_rhs(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, double* q,
                            hipStream_t s);
-// g[E][NF] = facet sums of q, plus the reduction of (g,g) and (zdef, g) into sc; sets the
-// stopping threshold tol2 = rtol^2 (g,g)_deflated.
-hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, PcgScalars* sc, double* partials,
-                           double rtol, int maxit, hipStream_t s);
-// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0, rz, rr reductions; sets done if already converged.
+// Partial-sum buffers and scalars of one PCG run.  Every reducing kernel writes one
+// partial per block; the following kernel sums them (no atomics, no fences).
+struct PcgBufs {
+  PcgScalars* sc;
+  double* gg;      // [G][2] (g,g),(z,g) partials; reused for the FP64 refinement residual
+  double* rz[2];   // [G][2] (r,z),(r,r) partials of even / odd iterations
+  double* pq;      // [G]    (p,Sp) partials
+};
+int facet_grid_size(int E);  // G: blocks of the facet kernels
+
+// g[E][NF] = facet sums of q, then (one block) the deflated (g,g) and the stopping
+// threshold tol2 = rtol^2 (g,g) into pb.sc (done = RUNNING, or CONVERGED for g = 0).
+hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
+                           int maxit, hipStream_t s);
+// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials of iteration 0.
 hipError_t launch_pcg_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* gv, double* x,
-                           double* r, double* z, double* p_old, PcgScalars* sc, double* partials, hipStream_t s);
-// p_new = z + beta p_old, q = S p_new, alpha = rz / (p_new, q).
+                           double* r, double* z, double* p_old, const PcgBufs& pb, hipStream_t s);
+// Iteration it >= 1: stopping test on iteration it-1, beta, p_new = z + beta p_old, Sp = S p_new.
 hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
-                           double* p_new, double* Sp, PcgScalars* sc, double* partials, hipStream_t s);
-// x += alpha p, r -= alpha q, z = M^{-1} r, beta = rz_new / rz, convergence test.
+                           double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s);
+// x += alpha p, r -= alpha Sp, z = M^{-1} r.
 hipError_t launch_pcg_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* p,
-                             const double* Sp, double* x, double* r, double* z, PcgScalars* sc, double* partials,
+                             const double* Sp, double* x, double* r, double* z, const PcgBufs& pb, int it,
                              hipStream_t s);
-// FP32 inner PCG (MIXED): same kernels on float vectors and the FP32 copy of S.
+// FP32 inner PCG (MIXED): the same kernels on float vectors and the FP32 copy of S.
 hipError_t launch_pcg32_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* r64,
-                             float* x, float* r, float* z, float* p_old, PcgScalars* sc, double* partials,
-                             double rtol, int maxit, hipStream_t s);
+                             float* x, float* r, float* z, float* p_old, const PcgBufs& pb, hipStream_t s);
 hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
-                             float* p_new, float* Sp, PcgScalars* sc, double* partials, hipStream_t s);
+                             float* p_new, float* Sp, const PcgBufs& pb, int it, hipStream_t s);
 hipError_t launch_pcg32_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const float* p,
-                               const float* Sp, float* x, float* r, float* z, PcgScalars* sc, double* partials,
+                               const float* Sp, float* x, float* r, float* z, const PcgBufs& pb, int it,
                                hipStream_t s);
-// FP64 refinement residual r64 = g - zg zdef - S lambda (and (r,r)); lambda += x32 first if add.
+// FP64 refinement residual r64 = g - zg zdef - S lam (lam += x32 first if add), its norm
+// into pb64.sc->rr, and the inner solve's threshold (inner_rtol relative to ||r64||) into sc32.
 hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const double* gv, double* lam,
-                              const float* x32, int add, double* r64, PcgScalars* sc, double* partials,
-                              hipStream_t s);
+                              const float* x32, int add, double* r64, const PcgBufs& pb64, PcgScalars* sc32,
+                              double inner_rtol, int inner_maxit, hipStream_t s);
 // Recovery (a6): u = W_T (F_T - C_T^T lambda_T); out = u (mode 0) or
 // out = a Un + b (Us + dt u) (mode 1).  F is FP64 or FP32.
 hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, const double* lam,

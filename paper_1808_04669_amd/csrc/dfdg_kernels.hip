@@ -6,10 +6,10 @@
 // whose values are stored SoA [slot][a][b][E] so that every load instruction of a wave is
 // one contiguous 512-byte segment.  Facet vectors are [E][n_f].
 //
-// Reductions (PCG dot products) are deterministic: each block reduces its lanes with
-// wavefront shuffles and LDS, writes one partial per block, and the last block to finish
-// (found with one device-scope atomic counter) sums the partials in a fixed order and
-// updates the PCG scalars.  Nobody waits on anybody, so no kernel can hang on it.
+// Reductions (PCG dot products) are deterministic and use neither atomics nor fences: each
+// block reduces its lanes with wavefront shuffles and LDS and writes one partial; the next
+// kernel's blocks each sum all partials in the same fixed order.  (A per-block device-scope
+// release fence would write back the XCD's whole L2 on every block.)
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,20 +37,12 @@ __device__ inline double wave_max(double x) {
   return x;
 }
 
-__device__ inline void store_agent(double* p, double v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ inline double load_agent(const double* p) {
-  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Block-sum NV values; every block writes its partials, the last block to arrive sums all
-// partials in block order and returns true with the totals in tot (valid in thread 0).
+// Reductions without atomics or fences: a kernel writes one partial per block; the next
+// kernel on the stream (after the kernel boundary has made them visible) sums all partials
+// redundantly in every block, in a fixed order, so every block gets the same bits.
 template <int NV>
-__device__ bool reduce_last_block(const double (&v)[NV], double* partials, unsigned int* counter,
-                                  double (&tot)[NV]) {
+__device__ inline void block_write_partial(const double (&v)[NV], double* __restrict__ buf) {
   __shared__ double sh[NV][kBlk / 64];
-  __shared__ int am_last;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
@@ -63,38 +55,35 @@ __device__ bool reduce_last_block(const double (&v)[NV], double* partials, unsig
     for (int i = 0; i < NV; ++i) {
       double s = 0;
       for (int w = 0; w < nw; ++w) s += sh[i][w];
-      store_agent(&partials[blockIdx.x * NV + i], s);
+      buf[blockIdx.x * NV + i] = s;
     }
-    __atomic_thread_fence(__ATOMIC_RELEASE);  // partials visible before the count
-    const unsigned int prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    am_last = (prev == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!am_last) return false;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+}
+
+// Sum n partials of NV values each; every thread of the block receives the totals.
+template <int NV>
+__device__ inline void block_sum_partials(const double* __restrict__ buf, int n, double (&out)[NV]) {
+  __shared__ double sh[NV][kBlk / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   double acc[NV];
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+  for (int b = threadIdx.x; b < n; b += blockDim.x)
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += load_agent(&partials[b * NV + i]);
-  __syncthreads();
+    for (int i = 0; i < NV; ++i) acc[i] += buf[b * NV + i];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double s = wave_sum(acc[i]);
     if (lane == 0) sh[i][wid] = s;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
 #pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0;
-      for (int w = 0; w < nw; ++w) s += sh[i][w];
-      tot[i] = s;
-    }
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (int i = 0; i < NV; ++i) {
+    double s = 0;
+    for (int w = 0; w < nw; ++w) s += sh[i][w];
+    out[i] = s;
   }
-  return true;
+  __syncthreads();
 }
 
 // ---------------------------------------------------------------------------------------
@@ -557,14 +546,21 @@ __global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const F
 // a5: facet PCG
 // ---------------------------------------------------------------------------------------
 
-// g_F = q_{L,f_L} + q_{R,f_R}; reductions (g,g), (zdef,g).
+// Facet kernels run a grid-stride loop over facet rows on a grid of at most kMaxFacetGrid
+// blocks, so that the partial buffers (and the redundant reductions) stay small.
+static constexpr int kMaxFacetGrid = 1024;
+__host__ __device__ inline int facet_grid(int E) {
+  const int g = (E + kBlk - 1) / kBlk;
+  return g < kMaxFacetGrid ? g : kMaxFacetGrid;
+}
+
+// g_F = q_{L,f_L} + q_{R,f_R}; partials (g,g), (zdef,g).
 template <int NF>
 __global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __restrict__ q, double* __restrict__ gv,
-                                                   PcgScalars* sc, double* partials, double rtol, int maxit) {
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   double* __restrict__ part) {
   const int T = g.T;
   double v[2] = {0, 0};
-  if (F < g.E) {
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x) {
     const int a = g.qL[F], b = g.qR[F];
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
@@ -574,15 +570,24 @@ __global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __res
       if (m == 0) v[1] += g.zdef[F] * x;
     }
   }
-  double tot[2];
-  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
-    const double gg = tot[0] - tot[1] * tot[1];  // ||g - (z.g) z||^2 with ||z|| = 1
+  block_write_partial<2>(v, part);
+}
+
+// One block: the deflated (g,g) and the PCG stopping threshold.
+__global__ __launch_bounds__(kBlk) void k_finalize_gather(const double* __restrict__ part, int n, PcgScalars* sc,
+                                                          double rtol, int maxit) {
+  double t[2];
+  block_sum_partials<2>(part, n, t);
+  if (threadIdx.x == 0) {
+    const double gg = t[0] - t[1] * t[1];  // ||g - (z.g) z||^2 with ||z|| = 1
     sc->gg = gg;
-    sc->zg = tot[1];
+    sc->zg = t[1];
     sc->tol2 = rtol * rtol * gg;
     sc->maxit = maxit;
     sc->zero_rhs = !(gg > 0.0);
-    sc->done = isfinite(gg) ? PCG_RUNNING : PCG_NONFINITE;
+    sc->iters = 0;
+    sc->rr = 0;
+    sc->done = !isfinite(gg) ? PCG_NONFINITE : (!(gg > 0.0) ? PCG_CONVERGED : PCG_RUNNING);
   }
 }
 
@@ -622,28 +627,26 @@ __device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y
   }
 }
 
-// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0.
+// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
 template <int NF, bool BJ>
 __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
                                                    double* __restrict__ x, double* __restrict__ r,
                                                    double* __restrict__ z, double* __restrict__ p_old,
-                                                   PcgScalars* sc, double* partials) {
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+                                                   const PcgScalars* sc, double* __restrict__ rz0) {
   const int E = g.E;
-  if (sc->done != PCG_RUNNING) return;
-  if (sc->zero_rhs) {
-    if (F < E)
+  const int done = sc->done;
+  if (done != PCG_RUNNING && !sc->zero_rhs) return;
+  const double zg = sc->zg;
+  double v[2] = {0, 0};
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+    if (sc->zero_rhs) {
 #pragma unroll
       for (int m = 0; m < NF; ++m) {
         const size_t o = (size_t)F * NF + m;
         x[o] = 0; r[o] = 0; z[o] = 0; p_old[o] = 0;
       }
-    if (F == 0) { sc->rz = 0; sc->rr = 0; sc->beta = 0; sc->iters = 0; sc->done = PCG_CONVERGED; }
-    return;
-  }
-  const double zg = sc->zg;
-  double v[2] = {0, 0};
-  if (F < E) {
+      continue;
+    }
     double Sx[NF];
     spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
 #pragma unroll
@@ -667,62 +670,85 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
       v[1] += rr[m] * rr[m];
     }
   }
-  double tot[2];
-  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
-    sc->rz = tot[0];
-    sc->rr = tot[1];
-    sc->beta = 0;
-    sc->iters = 0;
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->done = PCG_NONFINITE;
-    else if (tot[1] <= sc->tol2) sc->done = PCG_CONVERGED;
-  }
+  block_write_partial<2>(v, rz0);
 }
 
-// p_new = z + beta p_old (own row, and on the fly for the columns), Sp = S p_new,
-// alpha = rz / (p_new, Sp).
+// Iteration it >= 1.  From the partials of the previous update (rz_{it-1}, rr_{it-1}) and
+// of the one before (rz_{it-2}): stopping test, beta; then p_new = z + beta p_old,
+// Sp = S p_new and partials (p_new, Sp).
 template <int NF, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* __restrict__ z,
                                                    const V* __restrict__ p_old, V* __restrict__ p_new,
-                                                   V* __restrict__ Sp, PcgScalars* sc, double* partials) {
+                                                   V* __restrict__ Sp, PcgScalars* sc,
+                                                   const double* __restrict__ rz_prev,
+                                                   const double* __restrict__ rz_prev2, double* __restrict__ pq,
+                                                   int it) {
   if (sc->done != PCG_RUNNING) return;
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
   const int E = g.E;
-  const V beta = (V)sc->beta;
+  const int G = gridDim.x;
+  double t1[2];
+  block_sum_partials<2>(rz_prev, G, t1);
+  double beta = 0;
+  if (it >= 2) {
+    double t2[2];
+    block_sum_partials<2>(rz_prev2, G, t2);
+    beta = t1[0] / t2[0];
+  }
+  int status = PCG_RUNNING;
+  if (!isfinite(t1[0]) || !isfinite(t1[1]) || !isfinite(beta)) status = PCG_NONFINITE;
+  else if (t1[1] <= sc->tol2) status = PCG_CONVERGED;
+  else if (it - 1 >= sc->maxit) status = PCG_MAXIT;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->iters = it - 1;
+    sc->rr = t1[1];
+    sc->rz = t1[0];
+    if (status != PCG_RUNNING) sc->done = status;
+  }
+  if (status != PCG_RUNNING) return;
+  const V b = (V)beta;
   double v[1] = {0};
-  if (F < E) {
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, M>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
-      for (int b = 0; b < NF; ++b) xc[b] = z[(size_t)c * NF + b] + beta * p_old[(size_t)c * NF + b];
+      for (int bb = 0; bb < NF; ++bb) xc[bb] = z[(size_t)c * NF + bb] + b * p_old[(size_t)c * NF + bb];
     }, y);
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
-      const V pn = z[o] + beta * p_old[o];
+      const V pn = z[o] + b * p_old[o];
       p_new[o] = pn;
       Sp[o] = y[a];
       v[0] += (double)pn * (double)y[a];
     }
   }
-  double tot[1];
-  if (reduce_last_block<1>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
-    sc->pq = tot[0];
-    if (!isfinite(tot[0])) sc->done = PCG_NONFINITE;
-    else if (!(tot[0] > 0)) sc->done = PCG_BREAKDOWN;
-    else sc->alpha = sc->rz / tot[0];
-  }
+  block_write_partial<1>(v, pq);
 }
 
+// x += alpha p, r -= alpha Sp, z = M^{-1} r with alpha = rz_{it-1} / (p, Sp); partials
+// (r,z), (r,r) of iteration it.
 template <int NF, bool BJ, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V* __restrict__ p,
                                                      const V* __restrict__ Sp, V* __restrict__ x, V* __restrict__ r,
-                                                     V* __restrict__ z, PcgScalars* sc, double* partials) {
+                                                     V* __restrict__ z, PcgScalars* sc,
+                                                     const double* __restrict__ rz_prev,
+                                                     const double* __restrict__ pq, double* __restrict__ rz_out) {
   if (sc->done != PCG_RUNNING) return;
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
   const int E = g.E;
-  const V alpha = (V)sc->alpha;
+  const int G = gridDim.x;
+  double t1[2], t2[1];
+  block_sum_partials<2>(rz_prev, G, t1);
+  block_sum_partials<1>(pq, G, t2);
+  int status = PCG_RUNNING;
+  if (!isfinite(t2[0])) status = PCG_NONFINITE;
+  else if (!(t2[0] > 0)) status = PCG_BREAKDOWN;
+  if (status != PCG_RUNNING) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = status;
+    return;
+  }
+  const V alpha = (V)(t1[0] / t2[0]);
   double v[2] = {0, 0};
-  if (F < E) {
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V rr[NF], zz[NF];
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
@@ -739,29 +765,18 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
       v[1] += (double)rr[a] * (double)rr[a];
     }
   }
-  double tot[2];
-  if (reduce_last_block<2>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
-    const int it = sc->iters + 1;
-    sc->iters = it;
-    sc->beta = tot[0] / sc->rz;
-    sc->rz = tot[0];
-    sc->rr = tot[1];
-    if (!isfinite(tot[0]) || !isfinite(tot[1])) sc->done = PCG_NONFINITE;
-    else if (tot[1] <= sc->tol2) sc->done = PCG_CONVERGED;
-    else if (it >= sc->maxit) sc->done = PCG_MAXIT;
-  }
+  block_write_partial<2>(v, rz_out);
 }
 
-// Inner FP32 PCG start for S d = r64 (x = 0): r = (float) r64, tolerance relative to ||r64||.
+// Inner FP32 PCG start for S d = r64 (d = 0): r = (float) r64; partials (r,z), (r,r).
 template <int NF, bool BJ>
 __global__ __launch_bounds__(kBlk) void k_pcg32_init(DevGeo g, DevBsr A, const double* __restrict__ r64,
                                                      float* __restrict__ x, float* __restrict__ r,
                                                      float* __restrict__ z, float* __restrict__ p_old,
-                                                     PcgScalars* sc, double* partials, double rtol, int maxit) {
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+                                                     double* __restrict__ rz0) {
   const int E = g.E;
-  double v[3] = {0, 0, 0};
-  if (F < E) {
+  double v[2] = {0, 0};
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     float rr[NF], zz[NF];
 #pragma unroll
     for (int m = 0; m < NF; ++m) rr[m] = (float)r64[(size_t)F * NF + m];
@@ -773,32 +788,19 @@ __global__ __launch_bounds__(kBlk) void k_pcg32_init(DevGeo g, DevBsr A, const d
       v[0] += (double)rr[m] * zz[m];
       v[1] += (double)rr[m] * rr[m];
     }
-    v[2] = v[1];
   }
-  double tot[3];
-  if (reduce_last_block<3>(v, partials, &sc->counter, tot) && threadIdx.x == 0) {
-    sc->rz = tot[0];
-    sc->rr = tot[1];
-    sc->gg = tot[2];
-    sc->tol2 = rtol * rtol * tot[2];
-    sc->beta = 0;
-    sc->iters = 0;
-    sc->maxit = maxit;
-    sc->done = (!isfinite(tot[0]) || !isfinite(tot[1])) ? PCG_NONFINITE
-               : (tot[1] <= sc->tol2 ? PCG_CONVERGED : PCG_RUNNING);
-  }
+  block_write_partial<2>(v, rz0);
 }
 
-// FP64 refinement residual r64 = g - zg zdef - S lam and (r64, r64).
+// FP64 refinement residual r64 = g - zg zdef - S lam; partials (r64, r64).
 template <int NF>
 __global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const double* __restrict__ gv,
                                                       const double* __restrict__ lam, double* __restrict__ r64,
-                                                      PcgScalars* sc, double* partials) {
-  const int F = blockIdx.x * blockDim.x + threadIdx.x;
+                                                      const PcgScalars* sc, double* __restrict__ part) {
   const int E = g.E;
   const double zg = sc->zg;
   double v[1] = {0};
-  if (F < E) {
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     double Sx[NF];
     spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
 #pragma unroll
@@ -813,8 +815,23 @@ __global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const 
       v[0] += rm * rm;
     }
   }
-  double tot[1];
-  if (reduce_last_block<1>(v, partials, &sc->counter, tot) && threadIdx.x == 0) sc->rr = tot[0];
+  block_write_partial<1>(v, part);
+}
+
+// One block: (r64, r64) into the outer scalars; set up the inner FP32 solve's stopping test.
+__global__ __launch_bounds__(kBlk) void k_finalize_ir(const double* __restrict__ part, int n, PcgScalars* sc64,
+                                                      PcgScalars* sc32, double inner_rtol, int maxit) {
+  double t[1];
+  block_sum_partials<1>(part, n, t);
+  if (threadIdx.x == 0) {
+    sc64->rr = t[0];
+    sc32->gg = t[0];
+    sc32->tol2 = inner_rtol * inner_rtol * t[0];
+    sc32->maxit = maxit;
+    sc32->iters = 0;
+    sc32->zero_rhs = 0;
+    sc32->done = isfinite(t[0]) ? PCG_RUNNING : PCG_NONFINITE;
+  }
 }
 
 __global__ void k_add_f32(long n, const float* __restrict__ x, double* __restrict__ y) {
@@ -1056,75 +1073,91 @@ hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb
     default: return hipErrorInvalidValue;                         \
   }
 
-hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, PcgScalars* sc, double* partials,
-                           double rtol, int maxit, hipStream_t s) {
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_gather_g<NN>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, q, gv, sc,
-                                          partials, rtol, maxit));
+hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
+                           int maxit, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_gather_g<NN>), dim3(G), dim3(kBlk), 0, s, g, q, gv, pb.gg));
+  hipLaunchKernelGGL(k_finalize_gather, dim3(1), dim3(kBlk), 0, s, (const double*)pb.gg, G, pb.sc, rtol, maxit);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
-                           double* z, double* p_old, PcgScalars* sc, double* partials, hipStream_t s) {
+                           double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
+  const int G = facet_grid(g.E);
   DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, true>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, sc, partials);
-    else hipLaunchKernelGGL((k_pcg_init<NN, false>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, sc, partials);
+    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
+    else hipLaunchKernelGGL((k_pcg_init<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
+  });
+  return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z, const V* p_old, V* p_new, V* Sp,
+                           const PcgBufs& pb, int it, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  const double* prev = pb.rz[(it - 1) & 1];
+  const double* prev2 = pb.rz[it & 1];
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
+                                          pb.sc, prev, prev2, pb.pq, it));
+  return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t update_any(int NF, bool bj, const DevGeo& g, const DevBsr& A, const V* p, const V* Sp, V* x, V* r,
+                             V* z, const PcgBufs& pb, int it, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  const double* prev = pb.rz[(it - 1) & 1];
+  double* out = pb.rz[it & 1];
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
+    else hipLaunchKernelGGL((k_pcg_update<NN, false, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
-                           double* p_new, double* Sp, PcgScalars* sc, double* partials, hipStream_t s) {
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g,
-                                          A, z, p_old, p_new, Sp, sc, partials));
-  return hipGetLastError();
+                           double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s) {
+  return spmv_any<double>(NF, g, A, z, p_old, p_new, Sp, pb, it, s);
 }
-
 hipError_t launch_pcg_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* p, const double* Sp,
-                             double* x, double* r, double* z, PcgScalars* sc, double* partials, hipStream_t s) {
-  DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
-    else hipLaunchKernelGGL((k_pcg_update<NN, false, double, double>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
-  });
-  return hipGetLastError();
+                             double* x, double* r, double* z, const PcgBufs& pb, int it, hipStream_t s) {
+  return update_any<double>(NF, bj, g, A, p, Sp, x, r, z, pb, it, s);
+}
+hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
+                             float* p_new, float* Sp, const PcgBufs& pb, int it, hipStream_t s) {
+  return spmv_any<float>(NF, g, A, z, p_old, p_new, Sp, pb, it, s);
+}
+hipError_t launch_pcg32_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const float* p, const float* Sp,
+                               float* x, float* r, float* z, const PcgBufs& pb, int it, hipStream_t s) {
+  return update_any<float>(NF, bj, g, A, p, Sp, x, r, z, pb, it, s);
 }
 
 hipError_t launch_pcg32_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* r64, float* x, float* r,
-                             float* z, float* p_old, PcgScalars* sc, double* partials, double rtol, int maxit,
-                             hipStream_t s) {
+                             float* z, float* p_old, const PcgBufs& pb, hipStream_t s) {
+  const int G = facet_grid(g.E);
   DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg32_init<NN, true>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, sc, partials, rtol, maxit);
-    else hipLaunchKernelGGL((k_pcg32_init<NN, false>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, sc, partials, rtol, maxit);
-  });
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
-                             float* p_new, float* Sp, PcgScalars* sc, double* partials, hipStream_t s) {
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g,
-                                          A, z, p_old, p_new, Sp, sc, partials));
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg32_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const float* p, const float* Sp,
-                               float* x, float* r, float* z, PcgScalars* sc, double* partials, hipStream_t s) {
-  DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
-    else hipLaunchKernelGGL((k_pcg_update<NN, false, float, float>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, sc, partials);
+    if (bj) hipLaunchKernelGGL((k_pcg32_init<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, pb.rz[0]);
+    else hipLaunchKernelGGL((k_pcg32_init<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, pb.rz[0]);
   });
   return hipGetLastError();
 }
 
 hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const double* gv, double* lam,
-                              const float* x32, int add, double* r64, PcgScalars* sc, double* partials,
-                              hipStream_t s) {
+                              const float* x32, int add, double* r64, const PcgBufs& pb64, PcgScalars* sc32,
+                              double inner_rtol, int inner_maxit, hipStream_t s) {
+  const int G = facet_grid(g.E);
   if (add) {
     const long n = (long)g.E * NF;
     hipLaunchKernelGGL(k_add_f32, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, x32, lam);
   }
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_ir_residual<NN>), dim3(nblk(g.E, kBlk)), dim3(kBlk), 0, s, g, A, gv, lam,
-                                          r64, sc, partials));
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_ir_residual<NN>), dim3(G), dim3(kBlk), 0, s, g, A, gv, lam, r64,
+                                          (const PcgScalars*)pb64.sc, pb64.gg));
+  hipLaunchKernelGGL(k_finalize_ir, dim3(1), dim3(kBlk), 0, s, (const double*)pb64.gg, G, pb64.sc, sc32, inner_rtol,
+                     inner_maxit);
   return hipGetLastError();
 }
+
+int facet_grid_size(int E) { return facet_grid(E); }
 
 hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
                               hipStream_t s) {

@@ -1,0 +1,131 @@
+"""GPU tests of the two extra forms: mixed precision and the adjoint."""
+import numpy as np
+import pytest
+import torch
+
+from inputs import RandomStreamField, double_shear_layer, eval_broken_poly, random_broken_poly
+from oracle.adjoint import energy_and_gradient, residual_jacobian
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import make_pair, rel_l2, transfer, values_to_lib  # noqa: E402
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------------------
+# mixed precision: FP32 residual and inner PCG, FP64 refinement / recovery
+# ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("k,N", [(1, 6), (2, 8), (3, 5)])
+def test_mixed_mass_solve_parity(k, N):
+    orc, s, _, _ = make_pair(N, k, order="random", seed=1, precision="mixed", ir_rtol=1e-11, inner_rtol=1e-3)
+    coef = random_broken_poly(s.T, k, seed=7)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U, info = s.mass_solve(F)
+    _log("mixed mass", k, N, "refinements", info.refinements, "inner its", info.iterations, "res", info.rel_residual)
+    assert info.status == 0 and info.refinements >= 1 and info.rel_residual <= 1e-11
+    from oracle.quadrature import triangle_rule
+    rule = triangle_rule(2 * k)
+    U_orc = orc.mass_solve(orc.space.assemble(orc.space.load_vector(eval_broken_poly(coef, rule[0]), rule)))
+    err = rel_l2(orc, s, U, U_orc)
+    _log("  rel L2", err)
+    assert err < 1e-9
+    d = s.diagnostics(U)
+    assert d["max_div"] < 1e-11 * np.sqrt(d["enstrophy"])
+
+
+@pytest.mark.parametrize("k,N,steps", [(2, 8, 6), (3, 6, 4)])
+def test_mixed_trajectory_within_1e6_of_oracle(k, N, steps):
+    orc, s, _, _ = make_pair(N, k, order="morton", precision="mixed", ir_rtol=1e-10, inner_rtol=1e-3)
+    U0 = orc.project(lambda x, y: double_shear_layer(x, y, sharpness=20.0))
+    U = transfer(orc, U0, s)
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for _ in range(steps):
+        info = s.rk3_step(U, dt)
+        assert info.status == 0
+        Uo = orc.rk3_step(Uo, dt)
+    err = rel_l2(orc, s, U, Uo)
+    d = s.diagnostics(U)
+    _log("mixed rk3", k, N, "rel L2", err, "diag", d)
+    assert err < 1e-6
+    assert d["max_div"] < 1e-11
+
+
+# ---------------------------------------------------------------------------------------
+# adjoint
+# ---------------------------------------------------------------------------------------
+def _div_free_dirs(orc, n, seed=1):
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        d = orc.mass_solve(rng.standard_normal(orc.space.ndof))
+        out.append(d / np.sqrt(d @ (orc.M @ d)))
+    return out
+
+
+@pytest.mark.parametrize("k,N", [(1, 5), (2, 6), (3, 4)])
+def test_residual_vjp_parity(k, N):
+    """y . (J_L(u) d) through dfdg_dg_residual_vjp equals the oracle's Jacobian product."""
+    orc, s, _, _ = make_pair(N, k, nu=0.01, order="random", seed=2)
+    U0 = orc.project(RandomStreamField(seed=1, kmax=3))
+    U = transfer(orc, U0, s)
+    J = residual_jacobian(orc, U0)
+    for y_g, d_g in zip(_div_free_dirs(orc, 2, seed=5), _div_free_dirs(orc, 2, seed=6)):
+        y, d = transfer(orc, y_g, s), transfer(orc, d_g, s)
+        gpu = torch.dot(s.residual_vjp(U, y), d).item()
+        ref = float(y_g @ (J @ d_g))
+        _log("vjp", k, N, gpu, ref)
+        assert abs(gpu - ref) < 1e-10 * (abs(ref) + 1e-3)
+
+
+def test_rk3_step_vjp_matches_finite_differences():
+    orc, s, _, _ = make_pair(6, 2, nu=1e-3, order="morton", cg_rtol=1e-14)
+    U0 = transfer(orc, orc.project(RandomStreamField(seed=0, kmax=3)), s)
+    dt = 0.1 / 6 / 4
+    w = transfer(orc, _div_free_dirs(orc, 1, seed=9)[0], s)
+    for d_g in _div_free_dirs(orc, 3, seed=4):
+        d = transfer(orc, d_g, s)
+        h = 1e-6
+
+        def step(u):
+            v = u.clone()
+            s.reset_history()
+            s.rk3_step(v, dt)
+            return v
+
+        fd = torch.dot(w, step(U0 + h * d) - step(U0 - h * d)).item() / (2 * h)
+        Ub = w.clone()
+        s.rk3_step_vjp(U0, Ub, dt)
+        adj = torch.dot(Ub, d).item()
+        _log("step vjp", adj, fd)
+        assert abs(adj - fd) < 1e-6 * abs(fd) + 1e-10
+
+
+def test_energy_gradient_vs_oracle_and_fd():
+    """Gradient of the final kinetic energy w.r.t. U0 through checkpointed RK3 steps."""
+    from paper_1808_04669_amd.adjoint import final_energy
+    N, k, steps, every = 6, 2, 6, 2
+    orc, s, _, _ = make_pair(N, k, nu=1e-3, order="random", seed=3, cg_rtol=1e-14)
+    U0o = orc.project(RandomStreamField(seed=0, kmax=3))
+    dt = 0.1 / N / k ** 2
+    E_o, g_o = energy_and_gradient(orc, U0o, dt, steps, checkpoint_every=every)
+    U0 = transfer(orc, U0o, s).requires_grad_(True)
+    E = final_energy(s, U0, dt, steps, checkpoint_every=every)
+    E.backward()
+    g = U0.grad
+    _log("E gpu", E.item(), "E oracle", E_o)
+    assert abs(E.item() - E_o) < 1e-10 * E_o
+    for d_g in _div_free_dirs(orc, 4, seed=11):
+        d = transfer(orc, d_g, s)
+        gpu = torch.dot(g, d).item()
+        ref = float(g_o @ d_g)
+        h = 1e-6
+        with torch.no_grad():
+            fd = (final_energy(s, U0.detach() + h * d, dt, steps, every)
+                  - final_energy(s, U0.detach() - h * d, dt, steps, every)).item() / (2 * h)
+        _log("  dE.d gpu", gpu, "oracle", ref, "fd", fd)
+        assert abs(gpu - ref) < 1e-8 * abs(ref) + 1e-12
+        assert abs(gpu - fd) < 1e-6 * abs(fd) + 1e-10
