@@ -190,14 +190,14 @@ int dfdg_eval(dfdg_ctx* ctx, const double* U_dev, int npts, const double* ref_pt
               double* out_dev);
 
 /* ---- measurement -------------------------------------------------------------------
- * dfdg_time_kernel: launches kernel `which` `reps` times back to back on the context
- * stream between two HIP events and returns the mean time per launch in ms.
+ * dfdg_time_kernel: launches kernel `which` `reps` times on the context stream, each
+ * between its own pair of HIP events, and returns the mean launch duration in ms.
  *   which = 0: facet SpMV + (p, S p) partials (FP64);  1: PCG vector update (FP64);
  *   2: DG residual (FP64); 3: facet SpMV (FP32, MIXED contexts only).
- * Inputs are the context's current PCG/stage vectors; the PCG state is left
- * unchanged in meaning (the kernels are run in a no-op-free "timing" mode that does
- * not advance the iteration).  bytes_out (may be NULL) receives the algorithmic
- * bytes one launch moves. */
+ * The kernels run on the context's current work vectors with a separate set of PCG
+ * scalars whose stopping test never fires; the work vectors (not the warm-start
+ * history) are clobbered.  bytes_out (may be NULL) receives the algorithmic bytes one
+ * launch moves. */
 int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms_per_launch,
                      double* bytes_out);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "dfdg.h"
 #include "dfdg_kernels.h"
@@ -739,18 +740,24 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
     }
   };
   HIPC(launch());  // warm-up
-  hipEvent_t e0, e1;
-  HIPC(hipEventCreate(&e0));
-  HIPC(hipEventCreate(&e1));
-  HIPC(hipEventRecord(e0, s));
-  for (int i = 0; i < reps; ++i) HIPC(launch());
-  HIPC(hipEventRecord(e1, s));
-  HIPC(hipEventSynchronize(e1));
-  float tot = 0;
-  HIPC(hipEventElapsedTime(&tot, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  *ms = tot / reps;
+  // one event pair per launch: the mean of (end - start) is the kernel's own duration on
+  // the stream, without the gaps between back-to-back dispatches
+  std::vector<hipEvent_t> ev(2 * (size_t)reps);
+  for (auto& e : ev) HIPC(hipEventCreate(&e));
+  for (int i = 0; i < reps; ++i) {
+    HIPC(hipEventRecord(ev[2 * i], s));
+    HIPC(launch());
+    HIPC(hipEventRecord(ev[2 * i + 1], s));
+  }
+  HIPC(hipEventSynchronize(ev.back()));
+  double tot = 0;
+  for (int i = 0; i < reps; ++i) {
+    float t = 0;
+    HIPC(hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]));
+    tot += t;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  *ms = (float)(tot / reps);
   if (bytes) {
     double b = 0;
     switch (which) {
