@@ -63,7 +63,7 @@ enum {
 };
 
 enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
-enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1 };   /* dfdg_params.precond */
+enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1, DFDG_AMG = 2 };  /* dfdg_params.precond */
 
 typedef struct dfdg_mesh dfdg_mesh;
 typedef struct dfdg_ctx dfdg_ctx;
@@ -75,11 +75,16 @@ typedef struct {
   int precision;     /* DFDG_FP64 or DFDG_MIXED */
   double cg_rtol;    /* PCG stop: ||g - S lambda||_2 <= cg_rtol ||g||_2 (FP64 path) */
   int cg_maxit;      /* PCG iteration limit per solve */
-  int precond;       /* DFDG_JACOBI or DFDG_BLOCK_JACOBI */
+  int precond;       /* DFDG_JACOBI, DFDG_BLOCK_JACOBI, or DFDG_AMG: one smoothed-
+                        aggregation multigrid V-cycle (Chebyshev(2) smoothing, coarse
+                        space spanned by the constant multiplier, built on the host at
+                        context creation) */
   double ir_rtol;    /* MIXED: outer FP64 refinement target (relative residual) */
   double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
   int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,
                         1..2 = polynomial extrapolation of that order in time */
+  int graphs;        /* 1: replay PCG iterations from captured HIP graphs (default);
+                        0: launch every kernel individually.  Same results bit for bit. */
 } dfdg_params;
 
 typedef struct {

@@ -35,7 +35,7 @@ def build(verbose=True):
     inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
     objs = []
     cxx = shutil.which("g++") or "g++"
-    for src in ("dfdg_setup.cpp", "dfdg_api.cpp"):
+    for src in ("dfdg_setup.cpp", "dfdg_amg.cpp", "dfdg_api.cpp"):
         obj = os.path.join(objdir, src.replace(".cpp", ".o"))
         _run([cxx, *CXX_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

@@ -1,0 +1,352 @@
+// Smoothed-aggregation AMG set-up for the facet matrix S (host, FP64, deterministic).
+//
+// S is the statically condensed hybrid-mixed operator (eq. (FE3)); on a periodic mesh its
+// kernel is the constant multiplier, which is also the near-null space the coarse levels
+// must represent.  Each level: a strength graph (|a_ij| >= theta sqrt(a_ii a_jj), on the
+// mode-0 entries of the facet blocks for the finest level), greedy aggregation (roots whose
+// neighbourhood is free, then attachment, then leftovers), a tentative prolongator carrying
+// the near-null vector aggregate by aggregate, one damped-Jacobi smoothing step of the
+// prolongator (weight 4/(3 rho(D^{-1}A))), and the Galerkin product R A P with R = P^T.
+// The coarsest operator is inverted densely after adding its (near-)kernel direction.
+#include "dfdg_amg.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+namespace dfdg {
+
+static Csr bsr_to_csr(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals) {
+  Csr A;
+  A.n = A.m = E * NF;
+  A.ptr.assign(A.n + 1, 0);
+  std::vector<int> cs(5);
+  for (int F = 0; F < E; ++F) {
+    int nu = 0;
+    for (int s = 0; s < 5; ++s) {
+      const int c = cols[(size_t)s * E + F];
+      bool seen = false;
+      for (int t = 0; t < nu; ++t) seen |= (cs[t] == c);
+      if (!seen) cs[nu++] = c;
+    }
+    std::sort(cs.begin(), cs.begin() + nu);
+    for (int a = 0; a < NF; ++a) {
+      const int row = F * NF + a;
+      for (int t = 0; t < nu; ++t)
+        for (int b = 0; b < NF; ++b) {
+          double v = 0;
+          for (int s = 0; s < 5; ++s)
+            if (cols[(size_t)s * E + F] == cs[t]) v += vals[(((size_t)s * NF + a) * NF + b) * E + F];
+          A.col.push_back(cs[t] * NF + b);
+          A.val.push_back(v);
+        }
+      A.ptr[row + 1] = (int)A.col.size();
+    }
+  }
+  return A;
+}
+
+static void spmv(const Csr& A, const std::vector<double>& x, std::vector<double>& y) {
+  y.assign(A.n, 0.0);
+  for (int i = 0; i < A.n; ++i) {
+    double s = 0;
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+    y[i] = s;
+  }
+}
+
+static std::vector<double> diag_inv(const Csr& A) {
+  std::vector<double> d(A.n, 0.0);
+  for (int i = 0; i < A.n; ++i)
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+      if (A.col[k] == i) d[i] = 1.0 / A.val[k];
+  return d;
+}
+
+// Spectral radius of D^{-1} A by power iteration from a fixed pseudo-random start.
+static double rho_dinv_a(const Csr& A, const std::vector<double>& dinv, int iters = 40) {
+  std::vector<double> x(A.n), y;
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  for (int i = 0; i < A.n; ++i) {
+    s ^= s << 13; s ^= s >> 7; s ^= s << 17;
+    x[i] = (double)(s >> 11) / 9007199254740992.0 - 0.5;
+  }
+  double lam = 0;
+  for (int it = 0; it < iters; ++it) {
+    spmv(A, x, y);
+    double ny = 0, nx = 0;
+    for (int i = 0; i < A.n; ++i) {
+      y[i] *= dinv[i];
+      ny += y[i] * y[i];
+      nx += x[i] * x[i];
+    }
+    lam = std::sqrt(ny / nx);
+    const double inv = 1.0 / std::sqrt(ny);
+    for (int i = 0; i < A.n; ++i) x[i] = y[i] * inv;
+  }
+  return lam;
+}
+
+static Csr transpose(const Csr& A) {
+  Csr T;
+  T.n = A.m;
+  T.m = A.n;
+  T.ptr.assign(T.n + 1, 0);
+  for (int c : A.col) T.ptr[c + 1]++;
+  for (int i = 0; i < T.n; ++i) T.ptr[i + 1] += T.ptr[i];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int> pos(T.ptr.begin(), T.ptr.end() - 1);
+  for (int i = 0; i < A.n; ++i)
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int p = pos[A.col[k]]++;
+      T.col[p] = i;
+      T.val[p] = A.val[k];
+    }
+  return T;
+}
+
+// C = A B (Gustavson with a dense accumulator); columns of each row sorted.
+static Csr matmul(const Csr& A, const Csr& B) {
+  Csr C;
+  C.n = A.n;
+  C.m = B.m;
+  C.ptr.assign(C.n + 1, 0);
+  std::vector<double> acc(B.m, 0.0);
+  std::vector<int> mark(B.m, -1), touched;
+  for (int i = 0; i < A.n; ++i) {
+    touched.clear();
+    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+      const int j = A.col[k];
+      const double a = A.val[k];
+      for (int l = B.ptr[j]; l < B.ptr[j + 1]; ++l) {
+        const int c = B.col[l];
+        if (mark[c] != i) {
+          mark[c] = i;
+          acc[c] = 0;
+          touched.push_back(c);
+        }
+        acc[c] += a * B.val[l];
+      }
+    }
+    std::sort(touched.begin(), touched.end());
+    for (int c : touched) {
+      C.col.push_back(c);
+      C.val.push_back(acc[c]);
+    }
+    C.ptr[i + 1] = (int)C.col.size();
+  }
+  return C;
+}
+
+// Greedy aggregation of the nodes of a symmetric strength graph (adjacency lists).
+static int aggregate(int n, const std::vector<int>& gptr, const std::vector<int>& gadj, std::vector<int>& agg) {
+  agg.assign(n, -1);
+  int na = 0;
+  for (int i = 0; i < n; ++i) {  // 1: roots with a free neighbourhood
+    if (agg[i] >= 0) continue;
+    bool free = true;
+    for (int k = gptr[i]; k < gptr[i + 1] && free; ++k) free = agg[gadj[k]] < 0;
+    if (!free) continue;
+    agg[i] = na;
+    for (int k = gptr[i]; k < gptr[i + 1]; ++k) agg[gadj[k]] = na;
+    ++na;
+  }
+  std::vector<int> pending(n, -1);
+  for (int i = 0; i < n; ++i) {  // 2: attach to a neighbouring aggregate
+    if (agg[i] >= 0) continue;
+    for (int k = gptr[i]; k < gptr[i + 1]; ++k)
+      if (agg[gadj[k]] >= 0) {
+        pending[i] = agg[gadj[k]];
+        break;
+      }
+  }
+  for (int i = 0; i < n; ++i)
+    if (pending[i] >= 0) agg[i] = pending[i];
+  for (int i = 0; i < n; ++i) {  // 3: leftovers with their free neighbours
+    if (agg[i] >= 0) continue;
+    agg[i] = na;
+    for (int k = gptr[i]; k < gptr[i + 1]; ++k)
+      if (agg[gadj[k]] < 0) agg[gadj[k]] = na;
+    ++na;
+  }
+  return na;
+}
+
+static bool dense_spd_inverse(int n, std::vector<double>& A) {
+  std::vector<double> L((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double s = A[(size_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      if (i == j) {
+        if (!(s > 0)) return false;
+        L[(size_t)i * n + i] = std::sqrt(s);
+      } else {
+        L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
+      }
+    }
+  // inverse of L (lower), then A^{-1} = L^{-T} L^{-1}
+  std::vector<double> Li((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    Li[(size_t)i * n + i] = 1.0 / L[(size_t)i * n + i];
+    for (int j = 0; j < i; ++j) {
+      double s = 0;
+      for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * Li[(size_t)k * n + j];
+      Li[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+    }
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0;
+      for (int k = std::max(i, j); k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
+      A[(size_t)i * n + j] = s;
+    }
+  return true;
+}
+
+int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals,
+              const std::vector<double>& z, double theta, int max_coarse, AmgHierarchy& H, std::string& err) {
+  H.lv.clear();
+  AmgLevel L0;
+  L0.A = bsr_to_csr(E, NF, cols, vals);
+  std::vector<double> B = z;  // near-null vector on the current level
+  int nf = NF;                // unknowns per node on the current level
+  H.lv.push_back(std::move(L0));
+  for (int level = 0; level < 20; ++level) {
+    AmgLevel& L = H.lv.back();
+    L.dinv = diag_inv(L.A);
+    for (double d : L.dinv)
+      if (!(d > 0) || !std::isfinite(d)) {
+        err = "multigrid: non-positive diagonal on level " + std::to_string(level);
+        return -1;
+      }
+    L.lmax = rho_dinv_a(L.A, L.dinv);
+    const int n = L.A.n;
+    if (n <= max_coarse) break;
+    // strength graph on nodes
+    const int nn = n / nf;
+    std::vector<int> gptr(nn + 1, 0), gadj;
+    std::vector<double> dd(nn);
+    for (int i = 0; i < nn; ++i) dd[i] = std::fabs(1.0 / L.dinv[i * nf]);
+    for (int i = 0; i < nn; ++i) {
+      const int row = i * nf;  // mode-0 row of the node
+      std::vector<int> nb;
+      for (int k = L.A.ptr[row]; k < L.A.ptr[row + 1]; ++k) {
+        const int c = L.A.col[k];
+        if (c % nf != 0) continue;
+        const int j = c / nf;
+        if (j == i) continue;
+        if (std::fabs(L.A.val[k]) >= theta * std::sqrt(dd[i] * dd[j])) nb.push_back(j);
+      }
+      std::sort(nb.begin(), nb.end());
+      nb.erase(std::unique(nb.begin(), nb.end()), nb.end());
+      gadj.insert(gadj.end(), nb.begin(), nb.end());
+      gptr[i + 1] = (int)gadj.size();
+    }
+    // symmetrise the graph (strength measure is symmetric for symmetric A; be safe)
+    {
+      std::vector<std::vector<int>> adj(nn);
+      for (int i = 0; i < nn; ++i)
+        for (int k = gptr[i]; k < gptr[i + 1]; ++k) {
+          adj[i].push_back(gadj[k]);
+          adj[gadj[k]].push_back(i);
+        }
+      gadj.clear();
+      for (int i = 0; i < nn; ++i) {
+        std::sort(adj[i].begin(), adj[i].end());
+        adj[i].erase(std::unique(adj[i].begin(), adj[i].end()), adj[i].end());
+        gadj.insert(gadj.end(), adj[i].begin(), adj[i].end());
+        gptr[i + 1] = (int)gadj.size();
+      }
+    }
+    std::vector<int> agg;
+    const int na = aggregate(nn, gptr, gadj, agg);
+    if (na >= nn) break;  // no coarsening possible
+    // tentative prolongator: the near-null vector, normalised per aggregate
+    std::vector<double> nrm(na, 0.0);
+    for (int r = 0; r < n; ++r) nrm[agg[r / nf]] += B[r] * B[r];
+    for (double& v : nrm) v = std::sqrt(v);
+    Csr Pt;
+    Pt.n = n;
+    Pt.m = na;
+    Pt.ptr.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+      const int a = agg[r / nf];
+      if (B[r] != 0.0 && nrm[a] > 0) {
+        Pt.col.push_back(a);
+        Pt.val.push_back(B[r] / nrm[a]);
+      }
+      Pt.ptr[r + 1] = (int)Pt.col.size();
+    }
+    // smoothed prolongator P = (I - omega D^{-1} A) Pt
+    const double omega = 4.0 / (3.0 * L.lmax);
+    Csr APt = matmul(L.A, Pt);
+    Csr P;
+    P.n = n;
+    P.m = na;
+    P.ptr.assign(n + 1, 0);
+    for (int r = 0; r < n; ++r) {
+      // merge row r of Pt and -omega dinv_r (A Pt)_r (both sorted)
+      int a = Pt.ptr[r], b = APt.ptr[r];
+      while (a < Pt.ptr[r + 1] || b < APt.ptr[r + 1]) {
+        int c;
+        double v = 0;
+        if (b >= APt.ptr[r + 1] || (a < Pt.ptr[r + 1] && Pt.col[a] < APt.col[b])) {
+          c = Pt.col[a];
+          v = Pt.val[a++];
+        } else if (a >= Pt.ptr[r + 1] || APt.col[b] < Pt.col[a]) {
+          c = APt.col[b];
+          v = -omega * L.dinv[r] * APt.val[b++];
+        } else {
+          c = Pt.col[a];
+          v = Pt.val[a++] - omega * L.dinv[r] * APt.val[b++];
+        }
+        if (v != 0.0) {
+          P.col.push_back(c);
+          P.val.push_back(v);
+        }
+      }
+      P.ptr[r + 1] = (int)P.col.size();
+    }
+    Csr R = transpose(P);
+    Csr AP = matmul(L.A, P);
+    Csr Ac = matmul(R, AP);
+    L.P = std::move(P);
+    L.R = std::move(R);
+    AmgLevel next;
+    next.A = std::move(Ac);
+    H.lv.push_back(std::move(next));
+    B = nrm;
+    nf = 1;
+  }
+  // coarsest: dense inverse of A_c + s B B^T / (B.B) (adds the kernel direction)
+  AmgLevel& C = H.lv.back();
+  const int nc = C.A.n;
+  if (nc > 4096) {
+    err = "multigrid: coarsest level too large (" + std::to_string(nc) + ")";
+    return -1;
+  }
+  std::vector<double> D((size_t)nc * nc, 0.0);
+  double tr = 0;
+  for (int i = 0; i < nc; ++i)
+    for (int k = C.A.ptr[i]; k < C.A.ptr[i + 1]; ++k) {
+      D[(size_t)i * nc + C.A.col[k]] = C.A.val[k];
+      if (C.A.col[k] == i) tr += C.A.val[k];
+    }
+  double bb = 0;
+  for (int i = 0; i < nc; ++i) bb += B[i] * B[i];
+  const double s = tr / nc;
+  if (bb > 0)
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j) D[(size_t)i * nc + j] += s * B[i] * B[j] / bb;
+  if (!dense_spd_inverse(nc, D)) {
+    err = "multigrid: coarsest operator is not positive definite";
+    return -1;
+  }
+  H.coarse_inv = std::move(D);
+  H.n_coarse = nc;
+  return 0;
+}
+
+}  // namespace dfdg

@@ -1,0 +1,37 @@
+// Smoothed-aggregation algebraic multigrid hierarchy for the facet matrix S (host set-up).
+#pragma once
+#include <string>
+#include <vector>
+
+namespace dfdg {
+
+struct Csr {
+  int n = 0, m = 0;              // rows, columns
+  std::vector<int> ptr, col;     // ptr[n+1]
+  std::vector<double> val;
+  long nnz() const { return (long)col.size(); }
+};
+
+// One level below the finest: its operator A (scalar CSR), the prolongator P from it to
+// the finer level (rows: finer unknowns) and R = P^T.  Level 0 is S itself (BSR on the
+// device, given as CSR here).
+struct AmgLevel {
+  Csr A;            // operator of this level
+  std::vector<double> dinv;
+  double lmax = 0;  // spectral radius estimate of D^{-1} A (Chebyshev upper bound)
+  Csr P;            // prolongator from the next coarser level to this one (empty on the coarsest)
+  Csr R;            // restriction = P^T
+};
+
+struct AmgHierarchy {
+  std::vector<AmgLevel> lv;          // lv[0] = fine operator S
+  std::vector<double> coarse_inv;    // dense inverse (n_c x n_c) of the regularised coarsest operator
+  int n_coarse = 0;
+};
+
+// Builds the hierarchy for the BSR facet matrix (cols [5][E], vals [5][NF][NF][E]) with the
+// near-null vector z (the constant multiplier, scalar length E*NF).  theta: strength threshold.
+int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals,
+              const std::vector<double>& z, double theta, int max_coarse, AmgHierarchy& H, std::string& err);
+
+}  // namespace dfdg

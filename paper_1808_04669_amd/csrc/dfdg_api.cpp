@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "dfdg.h"
+#include "dfdg_amg.h"
 #include "dfdg_kernels.h"
 #include "dfdg_setup.h"
 
@@ -42,6 +43,14 @@ struct dfdg_ctx {
   // adjoint buffers
   double *Ustages[3] = {nullptr, nullptr, nullptr}, *Ybar = nullptr, *Wbuf = nullptr;
   int hist_count[3] = {0, 0, 0};
+  // multigrid preconditioner
+  AmgHierarchy H;
+  MgDev mg;
+  // PCG iterations captured as HIP graphs (kernel arguments fixed: the solve runs in lamx)
+  double* lamx = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
+  int graph_iters = 0;
   PcgScalars* pinned = nullptr;
   std::string err;
 };
@@ -118,6 +127,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->ir_rtol = 1e-10;
   p->inner_rtol = 1e-4;
   p->extrapolate = 0;
+  p->graphs = 1;
 }
 
 static int check_params(const dfdg_params* p, std::string& e) {
@@ -127,12 +137,16 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->precision != DFDG_FP64 && p->precision != DFDG_MIXED) { e = "precision must be DFDG_FP64 or DFDG_MIXED"; return -1; }
   if (!(p->cg_rtol > 0 && p->cg_rtol < 1)) { e = "cg_rtol must be in (0,1)"; return -1; }
   if (p->cg_maxit < 1) { e = "cg_maxit must be >= 1"; return -1; }
-  if (p->precond != DFDG_JACOBI && p->precond != DFDG_BLOCK_JACOBI) { e = "unknown preconditioner"; return -1; }
+  if (p->precond != DFDG_JACOBI && p->precond != DFDG_BLOCK_JACOBI && p->precond != DFDG_AMG) {
+    e = "unknown preconditioner";
+    return -1;
+  }
   if (p->precision == DFDG_MIXED) {
     if (!(p->ir_rtol > 0 && p->ir_rtol < 1)) { e = "ir_rtol must be in (0,1)"; return -1; }
     if (!(p->inner_rtol > 0 && p->inner_rtol < 1)) { e = "inner_rtol must be in (0,1)"; return -1; }
   }
   if (p->extrapolate < 0 || p->extrapolate > 2) { e = "extrapolate must be 0, 1 or 2"; return -1; }
+  if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   return 0;
 }
 
@@ -153,6 +167,22 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     g_mesh_err = e;
     delete ctx;
     return DFDG_E_MESH;
+  }
+  if (prm->precond == DFDG_AMG) {
+    const HostSetup& h = ctx->hs;
+    const int NFk = nF(prm->k);
+    std::vector<double> z((size_t)h.E * NFk, 0.0);
+    for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.zdef[F];
+    if (build_amg(h.E, NFk, h.cols, h.vals, z, 0.08, 500, ctx->H, e)) {
+      g_mesh_err = e;
+      delete ctx;
+      return DFDG_E_MESH;
+    }
+    if ((int)ctx->H.lv.size() > kMaxLev) {
+      g_mesh_err = "multigrid: too many levels";
+      delete ctx;
+      return DFDG_E_UNSUPPORTED;
+    }
   }
   ctx->K = prm->k;
   ctx->P = nP(ctx->K);
@@ -246,6 +276,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->q = c.take<double>(3 * NF * T);
   ctx->gv = c.take<double>(nL);
   ctx->lamw = c.take<double>(nL);
+  ctx->lamx = c.take<double>(nL);
   ctx->r = c.take<double>(nL);
   ctx->z = c.take<double>(nL);
   ctx->p[0] = c.take<double>(nL);
@@ -279,6 +310,63 @@ static void carve(dfdg_ctx* ctx, char* base) {
   for (int s = 0; s < 3; ++s) ctx->Ustages[s] = c.take<double>(nU);
   ctx->Ybar = c.take<double>(nU);
   ctx->Wbuf = c.take<double>(nU);
+  // multigrid hierarchy: operators of levels >= 1, transfer operators, level vectors
+  MgDev& mg = ctx->mg;
+  mg = MgDev{};
+  const AmgHierarchy& H = ctx->H;
+  mg.nlev = (int)H.lv.size();
+  auto take_csr = [&](const Csr& M, DevCsr& D) {
+    D.n = M.n;
+    // lanes per row: the largest power of two not above the mean row length (<= 64)
+    const double avg = M.n ? (double)M.nnz() / M.n : 1.0;
+    D.lpr = 1;
+    while (D.lpr < 64 && 2 * D.lpr <= avg) D.lpr *= 2;
+    D.ptr = c.take<int>(M.ptr.size());
+    D.col = c.take<int>(M.col.size());
+    D.val = c.take<double>(M.val.size());
+    D.val32 = mixed ? c.take<float>(M.val.size()) : nullptr;
+  };
+  for (int l = 0; l < mg.nlev; ++l) {
+    const AmgLevel& L = H.lv[l];
+    const long n = L.A.n;
+    if (l > 0) {
+      take_csr(L.A, mg.A[l]);
+      mg.dinv[l] = c.take<double>(n);
+      mg.dinv32[l] = mixed ? c.take<float>(n) : nullptr;
+    }
+    if (l < mg.nlev - 1) {
+      take_csr(L.P, mg.P[l]);
+      take_csr(L.R, mg.R[l]);
+    }
+    MgVec<double>& v = mg.v64[l];
+    v.b = (l > 0) ? c.take<double>(n) : nullptr;
+    v.z = (l > 0) ? c.take<double>(n) : nullptr;
+    const bool coarsest = (l == mg.nlev - 1);
+    v.x = coarsest ? nullptr : c.take<double>(n);
+    v.y = coarsest ? nullptr : c.take<double>(n);
+    v.d = coarsest ? nullptr : c.take<double>(n);
+    v.r = coarsest ? nullptr : c.take<double>(n);
+    MgVec<float>& w = mg.v32[l];
+    w = MgVec<float>{};
+    if (mixed) {
+      w.b = (l > 0) ? c.take<float>(n) : nullptr;
+      w.z = (l > 0) ? c.take<float>(n) : nullptr;
+      w.x = coarsest ? nullptr : c.take<float>(n);
+      w.y = coarsest ? nullptr : c.take<float>(n);
+      w.d = coarsest ? nullptr : c.take<float>(n);
+      w.r = coarsest ? nullptr : c.take<float>(n);
+    }
+    // Chebyshev(2) on [lmax/30, lmax], lmax = 1.05 rho(D^{-1} A)
+    const double lmax = 1.05 * L.lmax, lmin = lmax / 30.0;
+    const double th = 0.5 * (lmax + lmin), de = 0.5 * (lmax - lmin);
+    const double sig = th / de, rho0 = 1.0 / sig, rho1 = 1.0 / (2.0 * sig - rho0);
+    mg.cheb[l] = CheB{th, rho1 * rho0, 2.0 * rho1 / de};
+  }
+  if (mg.nlev > 0) {
+    mg.n_coarse = H.n_coarse;
+    mg.coarse_inv = c.take<double>(H.coarse_inv.size());
+    mg.coarse_inv32 = mixed ? c.take<float>(H.coarse_inv.size()) : nullptr;
+  }
   ctx->ws_need = c.off + 256;
 }
 
@@ -344,6 +432,41 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     HIPC(up(const_cast<float*>(ctx->A.binv32), b, s));
     HIPC(hipStreamSynchronize(s));
   }
+  {
+    const bool mixed = ctx->prm.precision == DFDG_MIXED;
+    const AmgHierarchy& H = ctx->H;
+    MgDev& mg = ctx->mg;
+    std::vector<std::vector<float>> keep;  // float staging buffers stay alive until the sync below
+    auto f32 = [&](const std::vector<double>& v) -> const std::vector<float>& {
+      keep.emplace_back(v.begin(), v.end());
+      return keep.back();
+    };
+    auto up_csr = [&](const Csr& M, const DevCsr& D) -> int {
+      HIPC(up(const_cast<int*>(D.ptr), M.ptr, s));
+      HIPC(up(const_cast<int*>(D.col), M.col, s));
+      HIPC(up(const_cast<double*>(D.val), M.val, s));
+      if (mixed) HIPC(up(const_cast<float*>(D.val32), f32(M.val), s));
+      return DFDG_OK;
+    };
+    keep.reserve(4 * kMaxLev + 2);
+    for (int l = 0; l < mg.nlev; ++l) {
+      const AmgLevel& L = H.lv[l];
+      if (l > 0) {
+        if (int rc = up_csr(L.A, mg.A[l])) return rc;
+        HIPC(up(const_cast<double*>(mg.dinv[l]), L.dinv, s));
+        if (mixed) HIPC(up(const_cast<float*>(mg.dinv32[l]), f32(L.dinv), s));
+      }
+      if (l < mg.nlev - 1) {
+        if (int rc = up_csr(L.P, mg.P[l])) return rc;
+        if (int rc = up_csr(L.R, mg.R[l])) return rc;
+      }
+    }
+    if (mg.nlev > 0) {
+      HIPC(up(const_cast<double*>(mg.coarse_inv), H.coarse_inv, s));
+      if (mixed) HIPC(up(const_cast<float*>(mg.coarse_inv32), f32(H.coarse_inv), s));
+    }
+    HIPC(hipStreamSynchronize(s));
+  }
   HIPC(hipStreamSynchronize(s));
   if (!ctx->pinned) HIPC(hipHostMalloc((void**)&ctx->pinned, 4 * sizeof(PcgScalars), hipHostMallocDefault));
   ctx->bound = true;
@@ -358,6 +481,9 @@ extern "C" const char* dfdg_last_error(const dfdg_ctx* ctx) {
 
 extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
   if (!ctx) return;
+  if (ctx->graph64) (void)hipGraphExecDestroy(ctx->graph64);
+  if (ctx->graph32) (void)hipGraphExecDestroy(ctx->graph32);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->pinned) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipHostFree(ctx->pinned);
@@ -388,31 +514,65 @@ static int read_scalars(dfdg_ctx* ctx, PcgScalars* dev, PcgScalars& out) {
 // Run PCG iterations (already initialised on the device) until the device flags an end.
 // The host enqueues chunks of iterations and reads the scalars after each chunk; the
 // chunk length follows the observed convergence rate so that few empty launches remain.
+// Capture `iters` PCG iterations (an even number, the first one odd: the partial-buffer
+// parity is part of the launch arguments) into an executable graph.
 template <typename Step>
-static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, PcgScalars& fin) {
+static int capture_iterations(dfdg_ctx* ctx, int iters, Step step, hipGraphExec_t* out) {
+  if (!ctx->cap_stream) HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  HIPC(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+  for (int it = 1; it <= iters; ++it) {
+    hipError_t e = step(it, ctx->cap_stream);
+    if (e != hipSuccess) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(ctx->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ctx, DFDG_E_HIP, std::string("PCG capture: ") + hipGetErrorString(e));
+    }
+  }
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamEndCapture(ctx->cap_stream, &g));
+  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return DFDG_OK;
+}
+
+// Run PCG iterations (already initialised on the device) until the device flags an end.
+// Iterations are enqueued in chunks (one graph launch = graph_iters iterations, or eager
+// launches), and the host reads the scalars after each chunk; the chunk length follows
+// the observed convergence rate so that few idle iterations remain.  Iterations past
+// the end exit at their first instruction.
+template <typename Step>
+static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t* graph, PcgScalars& fin) {
   int rc = read_scalars(ctx, sc, fin);
   if (rc) return rc;
-  int it = 1;  // next iteration to launch
-  int chunk = 16;
+  const bool use_graph = ctx->prm.graphs != 0;
+  const int gi = ctx->prm.precond == DFDG_AMG ? 4 : 32;  // iterations per graph
+  if (use_graph && fin.done == PCG_RUNNING && !*graph) {
+    rc = capture_iterations(ctx, gi, step, graph);
+    if (rc) return rc;
+  }
+  int launched = 0;
+  int chunk = ctx->prm.precond == DFDG_AMG ? 16 : 64;
   double last_rr = -1;
   int last_it = 0;
   while (fin.done == PCG_RUNNING) {
-    for (int c = 0; c < chunk; ++c, ++it) {
-      hipError_t e = step(it);
-      if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
+    if (use_graph) {
+      const int n = std::max(1, (chunk + gi - 1) / gi);
+      for (int c = 0; c < n; ++c) HIPC(hipGraphLaunch(*graph, ctx->stream));
+      launched += n * gi;
+    } else {
+      for (int c = 0; c < chunk; ++c) {
+        hipError_t e = step(launched + 1 + c, ctx->stream);
+        if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
+      }
+      launched += chunk;
     }
     rc = read_scalars(ctx, sc, fin);
     if (rc) return rc;
     if (fin.done != PCG_RUNNING) break;
-    if (it > maxit + 2) {
-      // the device stops at maxit: one more launch lets it record that
-      hipError_t e = step(it++);
-      if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, hipGetErrorString(e));
-      rc = read_scalars(ctx, sc, fin);
-      if (rc) return rc;
-      if (fin.done == PCG_RUNNING) return fail(ctx, DFDG_E_NOT_CONVERGED, "PCG did not stop at its iteration limit");
-      break;
-    }
+    if (launched > maxit + gi + 2)
+      return fail(ctx, DFDG_E_NOT_CONVERGED, "PCG did not stop at its iteration limit");
     // predict the remaining iterations from the contraction of rr over the last chunk
     int next = 2 * chunk;
     if (last_rr > 0 && fin.iters > last_it && fin.rr > 0 && fin.rr < last_rr && fin.tol2 > 0) {
@@ -427,26 +587,35 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, PcgScal
   return DFDG_OK;
 }
 
-// Solve S lam = g for the q currently in ctx->q; lam holds the start on entry.
+// Solve S lam = g for the q currently in ctx->q; lam holds the start on entry.  The PCG
+// runs in the fixed buffer lamx (captured graphs keep their arguments).
 static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
   const int NF = ctx->NF;
   const bool bj = ctx->prm.precond == DFDG_BLOCK_JACOBI;
   hipStream_t s = ctx->stream;
   const DevGeo& g = ctx->g;
   const DevBsr& A = ctx->A;
+  double* x = ctx->lamx;
+  if (lam != x) HIPC(hipMemcpyAsync(x, lam, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
   PcgScalars fin{};
   dfdg_solve_info inf{};
+  const bool amg = ctx->prm.precond == DFDG_AMG;
+  const int pc = amg ? 2 : (bj ? 1 : 0);
   if (ctx->prm.precision == DFDG_FP64) {
     const PcgBufs& pb = ctx->pb;
     HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
-    HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, lam, ctx->r, ctx->z, ctx->p[0], pb, s));
-    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, [&](int it) {
+    HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
+    if (amg) HIPC(launch_vcycle<double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], s));
+    auto step = [&](int it, hipStream_t st) -> hipError_t {
       double* pin = ctx->p[(it - 1) & 1];
       double* pout = ctx->p[it & 1];
-      hipError_t e = launch_pcg_spmv(NF, g, A, ctx->z, pin, pout, ctx->Sp, pb, it, s);
+      hipError_t e = launch_pcg_spmv(NF, g, A, ctx->z, pin, pout, ctx->Sp, pb, it, st);
       if (e != hipSuccess) return e;
-      return launch_pcg_update(NF, bj, g, A, pout, ctx->Sp, lam, ctx->r, ctx->z, pb, it, s);
-    }, fin);
+      e = launch_pcg_update(NF, pc, g, A, pout, ctx->Sp, x, ctx->r, ctx->z, pb, it, st);
+      if (e != hipSuccess || !amg) return e;
+      return launch_vcycle<double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], st);
+    };
+    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, &ctx->graph64, fin);
     if (rc) return rc;
     inf.iterations = fin.iters;
     inf.refinements = 0;
@@ -458,27 +627,30 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     const PcgBufs& pi = ctx->pb32;
     const double inner = ctx->prm.inner_rtol;
     HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, ctx->prm.ir_rtol, ctx->prm.cg_maxit, s));
-    HIPC(launch_ir_residual(NF, g, A, ctx->gv, lam, nullptr, 0, ctx->r64, pb, pi.sc, inner, ctx->prm.cg_maxit, s));
+    HIPC(launch_ir_residual(NF, g, A, ctx->gv, x, nullptr, 0, ctx->r64, pb, pi.sc, inner, ctx->prm.cg_maxit, s));
     PcgScalars o{};
     int rc = read_scalars(ctx, pb.sc, o);
     if (rc) return rc;
     int total = 0, nref = 0, st = DFDG_OK;
+    auto step = [&](int it, hipStream_t sm) -> hipError_t {
+      float* pin = ctx->p32[(it - 1) & 1];
+      float* pout = ctx->p32[it & 1];
+      hipError_t e = launch_pcg32_spmv(NF, g, A, ctx->z32, pin, pout, ctx->Sp32, pi, it, sm);
+      if (e != hipSuccess) return e;
+      e = launch_pcg32_update(NF, pc, g, A, pout, ctx->Sp32, ctx->x32, ctx->r32, ctx->z32, pi, it, sm);
+      if (e != hipSuccess || !amg) return e;
+      return launch_vcycle<float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[it & 1], sm);
+    };
     while (o.gg > 0 && o.rr > o.tol2) {
       if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
       HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], pi, s));
-      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, [&](int it) {
-        float* pin = ctx->p32[(it - 1) & 1];
-        float* pout = ctx->p32[it & 1];
-        hipError_t e = launch_pcg32_spmv(NF, g, A, ctx->z32, pin, pout, ctx->Sp32, pi, it, s);
-        if (e != hipSuccess) return e;
-        return launch_pcg32_update(NF, bj, g, A, pout, ctx->Sp32, ctx->x32, ctx->r32, ctx->z32, pi, it, s);
-      }, fin);
+      if (amg) HIPC(launch_vcycle<float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], s));
+      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, &ctx->graph32, fin);
       if (rc) return rc;
       total += fin.iters;
       ++nref;
       if (fin.done == PCG_NONFINITE || fin.done == PCG_BREAKDOWN) st = status_of(fin.done);
-      HIPC(launch_ir_residual(NF, g, A, ctx->gv, lam, ctx->x32, 1, ctx->r64, pb, pi.sc, inner,
-                              ctx->prm.cg_maxit, s));
+      HIPC(launch_ir_residual(NF, g, A, ctx->gv, x, ctx->x32, 1, ctx->r64, pb, pi.sc, inner, ctx->prm.cg_maxit, s));
       rc = read_scalars(ctx, pb.sc, o);
       if (rc) return rc;
       if (st != DFDG_OK) break;
@@ -489,6 +661,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     inf.rel_residual = o.gg > 0 ? std::sqrt(std::max(o.rr, 0.0) / o.gg) : 0.0;
     inf.status = st;
   }
+  if (lam != x) HIPC(hipMemcpyAsync(lam, x, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (info) *info = inf;
   return DFDG_OK;
 }
@@ -718,13 +891,14 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   NEED_BOUND(ctx);
   if (!ms || reps < 1) return fail(ctx, DFDG_E_INVALID_ARG, "bad arguments");
   if (which == 3 && ctx->prm.precision != DFDG_MIXED) return fail(ctx, DFDG_E_INVALID_ARG, "FP32 SpMV needs a MIXED context");
-  if (which < 0 || which > 3) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
+  if (which == 4 && ctx->prm.precond != DFDG_AMG) return fail(ctx, DFDG_E_INVALID_ARG, "V-cycle needs an AMG context");
+  if (which < 0 || which > 4) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
   hipStream_t s = ctx->stream;
   const long T = ctx->T, E = ctx->E, NF = ctx->NF, P = ctx->P;
   // a running PCG state whose stopping test never fires, and finite partials
   const PcgBufs& pb = ctx->pbt;
   PcgScalars st{};
-  st.rz = 1.0; st.rr = 1.0; st.gg = 1.0; st.tol2 = -1.0; st.maxit = 1 << 30;
+  st.rz = 1.0; st.rr = 1.0; st.gg = 1.0; st.tol2 = -1.0; st.maxit = 1 << 30; st.it = 2;
   HIPC(hipMemcpyAsync(pb.sc, &st, sizeof(st), hipMemcpyHostToDevice, s));
   const long G = facet_grid_size((int)E);
   HIPC(launch_fill(2 * G, 1.0, pb.rz[0], s));
@@ -733,9 +907,10 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   auto launch = [&]() -> hipError_t {
     switch (which) {
       case 0: return launch_pcg_spmv(NF, ctx->g, ctx->A, ctx->z, ctx->p[0], ctx->p[1], ctx->Sp, pb, 2, s);
-      case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
+      case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI ? 1 : 0, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
                                        ctx->gv, ctx->r, ctx->z, pb, 1, s);  // writes rz[1], reads rz[0]
       case 2: return launch_residual(ctx->K, false, ctx->g, ctx->tb, ctx->Ustage, ctx->Lbuf, ctx->prm.nu, s);
+      case 4: return launch_vcycle<double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], s);
       default: return launch_pcg32_spmv(NF, ctx->g, ctx->A, ctx->z32, ctx->p32[0], ctx->p32[1], ctx->Sp32, pb, 2, s);
     }
   };
@@ -764,6 +939,20 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
       case 0: b = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0 + 4.0 * NF * 8.0); break;       // S, cols, z, p_old, p_new, Sp
       case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
       case 2: b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (3 * 4.0 + 4 * 8.0)); break;         // U in, L out, geometry
+      case 4: {
+        // finest level: 4 BSR sweeps + 17 vector passes; transfers and coarse levels:
+        // every CSR entry (8-byte value, 4-byte column) once per use, vectors once
+        const double sbytes = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0);
+        b = 4 * sbytes + 17.0 * E * NF * 8.0;
+        const AmgHierarchy& H = ctx->H;
+        for (size_t l = 0; l < H.lv.size(); ++l) {
+          const AmgLevel& L = H.lv[l];
+          if (l > 0 && l + 1 < H.lv.size()) b += 4 * L.A.nnz() * 12.0 + 17.0 * L.A.n * 8.0;
+          if (l + 1 < H.lv.size()) b += (L.P.nnz() + L.R.nnz()) * 12.0 + 4.0 * L.A.n * 8.0;
+        }
+        b += H.n_coarse * (double)H.n_coarse * 8.0;
+        break;
+      }
       default: b = E * (kSlots * NF * NF * 4.0 + kSlots * 4.0 + 4.0 * NF * 4.0); break;
     }
     *bytes = b;

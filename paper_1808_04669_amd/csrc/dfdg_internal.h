@@ -90,6 +90,8 @@ struct DevBsr {
 struct PcgScalars {
   double rz, rr, gg, tol2, zg;
   int iters, done, maxit, zero_rhs;
+  int it;      // index of the next iteration (set to 1 at the start, advanced by the update kernel)
+  int pad;
 };
 enum { PCG_RUNNING = 0, PCG_CONVERGED = 1, PCG_BREAKDOWN = 2, PCG_MAXIT = 3, PCG_NONFINITE = 4 };
 

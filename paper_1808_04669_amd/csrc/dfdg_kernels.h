@@ -28,6 +28,47 @@ struct PcgBufs {
 };
 int facet_grid_size(int E);  // G: blocks of the facet kernels
 
+// Multigrid hierarchy on the device (level 0 = the BSR facet matrix itself).
+constexpr int kMaxLev = 16;
+struct CheB { double th, c1, c2; };  // Chebyshev(2) smoothing constants of a level
+struct DevCsr {
+  int n;
+  int lpr;  // lanes per row of the kernels that walk it (power of two <= 64)
+  const int* ptr;
+  const int* col;
+  const double* val;
+  const float* val32;
+};
+template <typename V>
+struct MgVec { V *b, *x, *y, *d, *r, *z; };
+struct MgDev {
+  int nlev = 0;
+  DevCsr A[kMaxLev];   // A[0] unused (the BSR facet matrix)
+  DevCsr P[kMaxLev];   // prolongation from level l+1 to level l (rows: level l)
+  DevCsr R[kMaxLev];   // restriction P^T
+  const double* dinv[kMaxLev];
+  const float* dinv32[kMaxLev];
+  CheB cheb[kMaxLev];
+  MgVec<double> v64[kMaxLev];
+  MgVec<float> v32[kMaxLev];
+  int n_coarse = 0;
+  const double* coarse_inv = nullptr;
+  const float* coarse_inv32 = nullptr;
+};
+template <typename V>
+inline const MgVec<V>& mg_vec(const MgDev& m, int l) {
+  if constexpr (sizeof(V) == 8) return m.v64[l]; else return m.v32[l];
+}
+template <typename V>
+inline const V* mg_dinv(const MgDev& m, int l) {
+  if constexpr (sizeof(V) == 8) return m.dinv[l]; else return m.dinv32[l];
+}
+// z = V-cycle(b) (one smoothed-aggregation multigrid cycle); writes the (b, z) partial of
+// each facet block into rz[2*block].
+template <typename V>
+hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const V* b, V* z, double* rz,
+                         hipStream_t s);
+
 // g[E][NF] = facet sums of q, then (one block) the deflated (g,g) and the stopping
 // threshold tol2 = rtol^2 (g,g) into pb.sc (done = RUNNING, or CONVERGED for g = 0).
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
@@ -36,10 +77,12 @@ hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv,
 hipError_t launch_pcg_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* gv, double* x,
                            double* r, double* z, double* p_old, const PcgBufs& pb, hipStream_t s);
 // Iteration it >= 1: stopping test on iteration it-1, beta, p_new = z + beta p_old, Sp = S p_new.
+// `it` selects the parity of the partial buffers (the kernels read the iteration count
+// itself from pb.sc, so a captured launch sequence can be replayed).
 hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
                            double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s);
-// x += alpha p, r -= alpha Sp, z = M^{-1} r.
-hipError_t launch_pcg_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* p,
+// x += alpha p, r -= alpha Sp, z = M^{-1} r (pc: 0 Jacobi, 1 block Jacobi, 2 none).
+hipError_t launch_pcg_update(int NF, int pc, const DevGeo& g, const DevBsr& A, const double* p,
                              const double* Sp, double* x, double* r, double* z, const PcgBufs& pb, int it,
                              hipStream_t s);
 // FP32 inner PCG (MIXED): the same kernels on float vectors and the FP32 copy of S.
@@ -47,7 +90,7 @@ hipError_t launch_pcg32_init(int NF, bool block_jacobi, const DevGeo& g, const D
                              float* x, float* r, float* z, float* p_old, const PcgBufs& pb, hipStream_t s);
 hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
                              float* p_new, float* Sp, const PcgBufs& pb, int it, hipStream_t s);
-hipError_t launch_pcg32_update(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const float* p,
+hipError_t launch_pcg32_update(int NF, int pc, const DevGeo& g, const DevBsr& A, const float* p,
                                const float* Sp, float* x, float* r, float* z, const PcgBufs& pb, int it,
                                hipStream_t s);
 // FP64 refinement residual r64 = g - zg zdef - S lam (lam += x32 first if add), its norm

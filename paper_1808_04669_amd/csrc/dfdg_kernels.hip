@@ -586,6 +586,7 @@ __global__ __launch_bounds__(kBlk) void k_finalize_gather(const double* __restri
     sc->maxit = maxit;
     sc->zero_rhs = !(gg > 0.0);
     sc->iters = 0;
+    sc->it = 1;
     sc->rr = 0;
     sc->done = !isfinite(gg) ? PCG_NONFINITE : (!(gg > 0.0) ? PCG_CONVERGED : PCG_RUNNING);
   }
@@ -673,17 +674,18 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
   block_write_partial<2>(v, rz0);
 }
 
-// Iteration it >= 1.  From the partials of the previous update (rz_{it-1}, rr_{it-1}) and
-// of the one before (rz_{it-2}): stopping test, beta; then p_new = z + beta p_old,
+// Iteration it >= 1 (it read from the scalars, so that the same launch sequence can be
+// replayed from a graph).  From the partials of the previous update (rz_{it-1}, rr_{it-1})
+// and of the one before (rz_{it-2}): stopping test, beta; then p_new = z + beta p_old,
 // Sp = S p_new and partials (p_new, Sp).
 template <int NF, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* __restrict__ z,
                                                    const V* __restrict__ p_old, V* __restrict__ p_new,
                                                    V* __restrict__ Sp, PcgScalars* sc,
                                                    const double* __restrict__ rz_prev,
-                                                   const double* __restrict__ rz_prev2, double* __restrict__ pq,
-                                                   int it) {
+                                                   const double* __restrict__ rz_prev2, double* __restrict__ pq) {
   if (sc->done != PCG_RUNNING) return;
+  const int it = sc->it;  // advanced only by the update kernel
   const int E = g.E;
   const int G = gridDim.x;
   double t1[2];
@@ -727,7 +729,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
 
 // x += alpha p, r -= alpha Sp, z = M^{-1} r with alpha = rz_{it-1} / (p, Sp); partials
 // (r,z), (r,r) of iteration it.
-template <int NF, bool BJ, typename V, typename M>
+// PC: 0 point Jacobi, 1 facet-block Jacobi, 2 none (z comes from the multigrid V-cycle,
+// which then overwrites the (r,z) partial).
+template <int NF, int PC, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V* __restrict__ p,
                                                      const V* __restrict__ Sp, V* __restrict__ x, V* __restrict__ r,
                                                      V* __restrict__ z, PcgScalars* sc,
@@ -757,15 +761,21 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
       rr[a] = r[o] - alpha * Sp[o];
       r[o] = rr[a];
     }
-    precond<NF, BJ, V, M>(A, F, rr, zz);
+    if (PC == 2) {
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      z[(size_t)F * NF + a] = zz[a];
-      v[0] += (double)rr[a] * (double)zz[a];
-      v[1] += (double)rr[a] * (double)rr[a];
+      for (int a = 0; a < NF; ++a) v[1] += (double)rr[a] * (double)rr[a];
+    } else {
+      precond<NF, PC == 1, V, M>(A, F, rr, zz);
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        z[(size_t)F * NF + a] = zz[a];
+        v[0] += (double)rr[a] * (double)zz[a];
+        v[1] += (double)rr[a] * (double)rr[a];
+      }
     }
   }
   block_write_partial<2>(v, rz_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->it = sc->it + 1;  // no other block reads it here
 }
 
 // Inner FP32 PCG start for S d = r64 (d = 0): r = (float) r64; partials (r,z), (r,r).
@@ -829,9 +839,227 @@ __global__ __launch_bounds__(kBlk) void k_finalize_ir(const double* __restrict__
     sc32->tol2 = inner_rtol * inner_rtol * t[0];
     sc32->maxit = maxit;
     sc32->iters = 0;
+    sc32->it = 1;
     sc32->zero_rhs = 0;
     sc32->done = isfinite(t[0]) ? PCG_RUNNING : PCG_NONFINITE;
   }
+}
+
+// ---------------------------------------------------------------------------------------
+// a5: multigrid V-cycle preconditioner for the facet PCG (smoothed aggregation)
+// ---------------------------------------------------------------------------------------
+// Per level: Chebyshev(2) smoothing with the point-Jacobi scaling D^{-1}, residual,
+// restriction R = P^T, coarse correction, prolongation, Chebyshev(2) post-smoothing.
+// With th, de the centre and half-width of the smoothing interval, c1 = rho1 rho0 and
+// c2 = 2 rho1 / de (rho0 = de/th, rho1 = 1/(2 th/de - rho0)):
+//   pre  (x0 = 0):  x1 = D^{-1} b / th,  x2 = (1 + c1) x1 + c2 D^{-1} (b - A x1)
+//   post (from x3): d = D^{-1}(b - A x3) / th, x4 = x3 + d,
+//                   z  = x4 + c1 d + c2 D^{-1} (b - A x4)
+// The finest level uses the BSR facet matrix (grid-stride over facet rows, like the PCG
+// kernels, so that the last post-smoothing kernel can emit the (r, z) partials).
+
+template <int NF, typename V>
+__device__ inline const V* bsr_vals(const DevBsr& A) { return (sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32; }
+template <int NF, typename V>
+__device__ inline const V* bsr_dinv(const DevBsr& A) { return (sizeof(V) == 8) ? (const V*)A.dinv : (const V*)A.dinv32; }
+
+template <int NF, typename V>
+__global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const V* __restrict__ b, V* __restrict__ x2,
+                                                  CheB cb) {
+  const V* dinv = bsr_dinv<NF, V>(A);
+  const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
+  const int E = g.E;
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+    V y[NF];
+    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * b[(size_t)c * NF + q] * ith;
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      const V x1 = dinv[o] * b[o] * ith;
+      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (b[o] - y[a]);
+    }
+  }
+}
+
+template <int NF, typename V>
+__global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const V* __restrict__ b,
+                                                    const V* __restrict__ x, V* __restrict__ r) {
+  const int E = g.E;
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+    V y[NF];
+    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) r[(size_t)F * NF + a] = b[(size_t)F * NF + a] - y[a];
+  }
+}
+
+template <int NF, typename V>
+__global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const V* __restrict__ b,
+                                                    const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
+                                                    CheB cb) {
+  const V* dinv = bsr_dinv<NF, V>(A);
+  const V ith = (V)(1.0 / cb.th);
+  const int E = g.E;
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+    V y[NF];
+    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) xc[q] = x3[(size_t)c * NF + q];
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      const V dd = dinv[o] * (b[o] - y[a]) * ith;
+      d[o] = dd;
+      x4[o] = x3[o] + dd;
+    }
+  }
+}
+
+// Last post-smoothing step; z is the preconditioned PCG residual b.  Writes the (b, z)
+// partial of this block into rz[2*block] (the (r,r) slot rz[2*block+1] is left alone).
+template <int NF, typename V>
+__global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const V* __restrict__ b,
+                                                    const V* __restrict__ x4, const V* __restrict__ d,
+                                                    V* __restrict__ z, CheB cb, double* __restrict__ rz) {
+  const V* dinv = bsr_dinv<NF, V>(A);
+  const V c1 = (V)cb.c1, c2 = (V)cb.c2;
+  const int E = g.E;
+  double v[1] = {0};
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+    V y[NF];
+    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) xc[q] = x4[(size_t)c * NF + q];
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      const V zz = x4[o] + c1 * d[o] + c2 * dinv[o] * (b[o] - y[a]);
+      z[o] = zz;
+      v[0] += (double)b[o] * (double)zz;
+    }
+  }
+  __shared__ double sh[kBlk / 64];
+  const double s = wave_sum(v[0]);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    rz[2 * blockIdx.x] = t;
+  }
+}
+
+// Coarse levels: scalar CSR, LPR lanes (a power of two <= 64, chosen on the host from the
+// mean row length) share a row: lane j of the group takes entries j, j+LPR, ..., and the
+// group reduces with shuffles in a fixed order.
+template <typename V>
+__device__ inline const V* csr_vals(const DevCsr& A) { return (sizeof(V) == 8) ? (const V*)A.val : (const V*)A.val32; }
+
+template <int LPR, typename V, typename X>
+__device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, int i, int sub, X x) {
+  V s = 0;
+  if (i < A.n)
+    for (int k = A.ptr[i] + sub; k < A.ptr[i + 1]; k += LPR) s += vals[k] * x(A.col[k]);
+#pragma unroll
+  for (int off = LPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPR);
+  return s;
+}
+
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
+                                                  V* __restrict__ x2, CheB cb) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  const V ith = (V)(1.0 / cb.th);
+  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return dinv[c] * b[c] * ith; });
+  if (i < A.n && sub == 0) {
+    const V x1 = dinv[i] * b[i] * ith;
+    x2[i] = (1 + (V)cb.c1) * x1 + (V)cb.c2 * dinv[i] * (b[i] - s);
+  }
+}
+
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_resid(DevCsr A, const V* __restrict__ b, const V* __restrict__ x,
+                                                    V* __restrict__ r) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x[c]; });
+  if (i < A.n && sub == 0) r[i] = b[i] - s;
+}
+
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_post1(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
+                                                    const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
+                                                    CheB cb) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x3[c]; });
+  if (i < A.n && sub == 0) {
+    const V dd = dinv[i] * (b[i] - s) * (V)(1.0 / cb.th);
+    d[i] = dd;
+    x4[i] = x3[i] + dd;
+  }
+}
+
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
+                                                    const V* __restrict__ x4, const V* __restrict__ d,
+                                                    V* __restrict__ z, CheB cb) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x4[c]; });
+  if (i < A.n && sub == 0) z[i] = x4[i] + (V)cb.c1 * d[i] + (V)cb.c2 * dinv[i] * (b[i] - s);
+}
+
+// y = M x (restriction with M = R), or y = y0 + M x (prolongation-add, add != 0).
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restrict__ x, const V* __restrict__ y0,
+                                                    V* __restrict__ y, int add) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  const V s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
+  if (i < M.n && sub == 0) y[i] = add ? y0[i] + s : s;
+}
+
+// (b, z) partials into rz[2*block] (grid-stride over n).
+template <typename V>
+__global__ __launch_bounds__(kBlk) void k_partial_dot(long n, const V* __restrict__ b, const V* __restrict__ z,
+                                                      double* __restrict__ rz) {
+  double v = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    v += (double)b[i] * (double)z[i];
+  __shared__ double sh[kBlk / 64];
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
+    rz[2 * blockIdx.x] = t;
+  }
+}
+
+// Coarsest level: x = Ainv b with the dense (regularised) inverse; a wavefront per row.
+template <typename V>
+__global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restrict__ Ainv, const float* __restrict__ Ainv32,
+                                                   const V* __restrict__ b, V* __restrict__ x) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g >> 6, lane = g & 63;
+  const V* M = (sizeof(V) == 8) ? (const V*)Ainv : (const V*)Ainv32;
+  V s = 0;
+  if (i < n)
+    for (int j = lane; j < n; j += 64) s += M[(size_t)i * n + j] * b[j];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (i < n && lane == 0) x[i] = s;
 }
 
 __global__ void k_add_f32(long n, const float* __restrict__ x, double* __restrict__ y) {
@@ -1098,19 +1326,20 @@ static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z,
   const double* prev = pb.rz[(it - 1) & 1];
   const double* prev2 = pb.rz[it & 1];
   DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
-                                          pb.sc, prev, prev2, pb.pq, it));
+                                          pb.sc, prev, prev2, pb.pq));
   return hipGetLastError();
 }
 
 template <typename V>
-static hipError_t update_any(int NF, bool bj, const DevGeo& g, const DevBsr& A, const V* p, const V* Sp, V* x, V* r,
+static hipError_t update_any(int NF, int pc, const DevGeo& g, const DevBsr& A, const V* p, const V* Sp, V* x, V* r,
                              V* z, const PcgBufs& pb, int it, hipStream_t s) {
   const int G = facet_grid(g.E);
   const double* prev = pb.rz[(it - 1) & 1];
   double* out = pb.rz[it & 1];
   DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg_update<NN, true, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
-    else hipLaunchKernelGGL((k_pcg_update<NN, false, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
+    if (pc == 1) hipLaunchKernelGGL((k_pcg_update<NN, 1, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
+    else if (pc == 2) hipLaunchKernelGGL((k_pcg_update<NN, 2, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
+    else hipLaunchKernelGGL((k_pcg_update<NN, 0, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, p, Sp, x, r, z, pb.sc, prev, (const double*)pb.pq, out);
   });
   return hipGetLastError();
 }
@@ -1119,17 +1348,17 @@ hipError_t launch_pcg_spmv(int NF, const DevGeo& g, const DevBsr& A, const doubl
                            double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s) {
   return spmv_any<double>(NF, g, A, z, p_old, p_new, Sp, pb, it, s);
 }
-hipError_t launch_pcg_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* p, const double* Sp,
+hipError_t launch_pcg_update(int NF, int pc, const DevGeo& g, const DevBsr& A, const double* p, const double* Sp,
                              double* x, double* r, double* z, const PcgBufs& pb, int it, hipStream_t s) {
-  return update_any<double>(NF, bj, g, A, p, Sp, x, r, z, pb, it, s);
+  return update_any<double>(NF, pc, g, A, p, Sp, x, r, z, pb, it, s);
 }
 hipError_t launch_pcg32_spmv(int NF, const DevGeo& g, const DevBsr& A, const float* z, const float* p_old,
                              float* p_new, float* Sp, const PcgBufs& pb, int it, hipStream_t s) {
   return spmv_any<float>(NF, g, A, z, p_old, p_new, Sp, pb, it, s);
 }
-hipError_t launch_pcg32_update(int NF, bool bj, const DevGeo& g, const DevBsr& A, const float* p, const float* Sp,
+hipError_t launch_pcg32_update(int NF, int pc, const DevGeo& g, const DevBsr& A, const float* p, const float* Sp,
                                float* x, float* r, float* z, const PcgBufs& pb, int it, hipStream_t s) {
-  return update_any<float>(NF, bj, g, A, p, Sp, x, r, z, pb, it, s);
+  return update_any<float>(NF, pc, g, A, p, Sp, x, r, z, pb, it, s);
 }
 
 hipError_t launch_pcg32_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* r64, float* x, float* r,
@@ -1158,6 +1387,84 @@ hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const do
 }
 
 int facet_grid_size(int E) { return facet_grid(E); }
+
+// ---- multigrid launchers -------------------------------------------------------------
+#define DFDG_DISPATCH_LPR(L, ...)                                  \
+  switch (L) {                                                     \
+    case 1: { constexpr int LP = 1; __VA_ARGS__; } break;          \
+    case 2: { constexpr int LP = 2; __VA_ARGS__; } break;          \
+    case 4: { constexpr int LP = 4; __VA_ARGS__; } break;          \
+    case 8: { constexpr int LP = 8; __VA_ARGS__; } break;          \
+    case 16: { constexpr int LP = 16; __VA_ARGS__; } break;        \
+    case 32: { constexpr int LP = 32; __VA_ARGS__; } break;        \
+    default: { constexpr int LP = 64; __VA_ARGS__; } break;        \
+  }
+
+template <typename V>
+static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, hipStream_t s) {
+  DFDG_DISPATCH_LPR(M.lpr, hipLaunchKernelGGL((k_csr_apply<LP, V>), dim3(nblk((long)M.n * LP, kBlk)), dim3(kBlk), 0, s,
+                                              M, x, y0, y, add));
+}
+
+template <typename V>
+hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const V* b, V* z, double* rz,
+                         hipStream_t s) {
+  const int G = facet_grid(g.E);
+  const int L = mg.nlev;
+  const MgVec<V>& v0 = mg_vec<V>(mg, 0);
+  if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve
+    hipLaunchKernelGGL((k_dense_mv<V>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
+                       mg.coarse_inv, mg.coarse_inv32, b, z);
+    hipLaunchKernelGGL((k_partial_dot<V>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const V*)z, rz);
+    return hipGetLastError();
+  }
+  DFDG_DISPATCH_NF(NF, {
+    hipLaunchKernelGGL((k_mg0_pre<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x, mg.cheb[0]);
+    hipLaunchKernelGGL((k_mg0_resid<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.r);
+  });
+  csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, s);
+  for (int l = 1; l < L - 1; ++l) {
+    const MgVec<V>& v = mg_vec<V>(mg, l);
+    const DevCsr& Al = mg.A[l];
+    const V* dinv = mg_dinv<V>(mg, l);
+    const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
+    DFDG_DISPATCH_LPR(Al.lpr, {
+      hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, v.x, mg.cheb[l]);
+      hipLaunchKernelGGL((k_mgc_resid<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, (const V*)v.b, (const V*)v.x, v.r);
+    });
+    csr_apply<V>(mg.R[l], (const V*)v.r, (const V*)nullptr, mg_vec<V>(mg, l + 1).b, 0, s);
+  }
+  {
+    const MgVec<V>& vc = mg_vec<V>(mg, L - 1);
+    hipLaunchKernelGGL((k_dense_mv<V>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
+                       mg.coarse_inv, mg.coarse_inv32, (const V*)vc.b, vc.z);
+  }
+  for (int l = L - 2; l >= 1; --l) {
+    const MgVec<V>& v = mg_vec<V>(mg, l);
+    const DevCsr& Al = mg.A[l];
+    const V* dinv = mg_dinv<V>(mg, l);
+    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, s);
+    const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
+    DFDG_DISPATCH_LPR(Al.lpr, {
+      hipLaunchKernelGGL((k_mgc_post1<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.x, v.y,
+                         v.d, mg.cheb[l]);
+      hipLaunchKernelGGL((k_mgc_post2<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.y,
+                         (const V*)v.d, v.z, mg.cheb[l]);
+    });
+  }
+  csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, s);
+  DFDG_DISPATCH_NF(NF, {
+    hipLaunchKernelGGL((k_mg0_post1<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d, mg.cheb[0]);
+    hipLaunchKernelGGL((k_mg0_post2<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y, (const V*)v0.d, z,
+                       mg.cheb[0], rz);
+  });
+  return hipGetLastError();
+}
+template hipError_t launch_vcycle<double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*, double*,
+                                          double*, hipStream_t);
+template hipError_t launch_vcycle<float>(int, const DevGeo&, const DevBsr&, const MgDev&, const float*, float*,
+                                         double*, hipStream_t);
+
 
 hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
                               hipStream_t s) {

@@ -18,7 +18,7 @@ DFDG_OK = 0
 STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_MESH", -3: "E_WORKSPACE", -4: "E_HIP",
           -5: "E_NOT_CONVERGED", -6: "E_NONFINITE", -7: "E_BREAKDOWN", -8: "E_UNSUPPORTED"}
 FP64, MIXED = 0, 1
-JACOBI, BLOCK_JACOBI = 0, 1
+JACOBI, BLOCK_JACOBI, AMG = 0, 1, 2
 
 
 class DfdgError(RuntimeError):
@@ -31,7 +31,7 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("nu", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ir_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("extrapolate", ctypes.c_int)]
+                ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int)]
 
 
 class Sizes(ctypes.Structure):
@@ -148,7 +148,8 @@ class Solver:
     """
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
-                 precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, device="cuda:0", stream=None):
+                 precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, device="cuda:0",
+                 stream=None):
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
@@ -158,8 +159,9 @@ class Solver:
         p.k, p.nu, p.alpha = int(k), float(nu), float(alpha)
         p.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         p.cg_rtol, p.cg_maxit = float(cg_rtol), int(cg_maxit)
-        p.precond = {"jacobi": JACOBI, "block_jacobi": BLOCK_JACOBI}[precond]
+        p.precond = {"jacobi": JACOBI, "block_jacobi": BLOCK_JACOBI, "amg": AMG}[precond]
         p.ir_rtol, p.inner_rtol, p.extrapolate = float(ir_rtol), float(inner_rtol), int(extrapolate)
+        p.graphs = 1 if graphs else 0
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()

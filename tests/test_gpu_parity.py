@@ -24,11 +24,12 @@ def _log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("k,N,order", CASES)
-def test_mass_solve_parity(k, N, order):
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+@pytest.mark.parametrize("k,N,order", CASES + [(1, 1, "lex"), (2, 2, "morton")])
+def test_mass_solve_parity(k, N, order, precond):
     """Divergence-free mass inversion of a random broken polynomial functional (Theorems 1-2)."""
-    _log("mass_solve", k, N, order)
-    orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13)
+    _log("mass_solve", k, N, order, precond)
+    orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13, precond=precond)
     coef = random_broken_poly(s.T, k, seed=10 + k)
     F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
     U, info = s.mass_solve(F)
@@ -75,16 +76,19 @@ def test_residual_parity_broken_field(k, N):
     assert np.abs(R_gpu - R_orc).max() < 1e-11 * np.abs(R_orc).max()
 
 
-@pytest.mark.parametrize("k,N,nu,field,steps", [
-    (1, 8, 1e-2, "tg", 10),          # 8x8 Taylor-Green, BDM_1, nu = 1e-2, 10 steps
-    (2, 8, 0.0, "dsl", 6),           # double shear layer, inviscid
-    (2, 6, 1e-3, "rand", 5),         # random stream-function field
-    (3, 4, 1e-2, "tg", 4),
+@pytest.mark.parametrize("k,N,nu,field,steps,precond", [
+    (1, 8, 1e-2, "tg", 10, "jacobi"),    # 8x8 Taylor-Green, BDM_1, nu = 1e-2, 10 steps
+    (1, 8, 1e-2, "tg", 10, "amg"),
+    (2, 8, 0.0, "dsl", 6, "jacobi"),     # double shear layer, inviscid
+    (2, 16, 0.0, "dsl", 6, "amg"),
+    (2, 6, 1e-3, "rand", 5, "block_jacobi"),  # random stream-function field
+    (3, 4, 1e-2, "tg", 4, "jacobi"),
+    (3, 12, 1e-3, "rand", 3, "amg"),
 ])
-def test_rk3_trajectory_parity(k, N, nu, field, steps):
+def test_rk3_trajectory_parity(k, N, nu, field, steps, precond):
     """TVD-RK3 trajectories from the same (oracle-projected) initial data (eq. (rk3))."""
-    _log("rk3", k, N, nu, field, steps)
-    orc, s, _, _ = make_pair(N, k, nu=nu, order="morton", cg_rtol=1e-13)
+    _log("rk3", k, N, nu, field, steps, precond)
+    orc, s, _, _ = make_pair(N, k, nu=nu, order="morton", cg_rtol=1e-13, precond=precond)
     f = {"tg": taylor_green_2d, "dsl": lambda x, y: double_shear_layer(x, y, sharpness=20.0),
          "rand": RandomStreamField(seed=0, kmax=4)}[field]
     U0 = orc.project(f)
@@ -128,16 +132,43 @@ def test_warm_start_and_determinism():
     assert (U4 - U3).abs().max().item() < 1e-11 * U3.abs().max().item()
 
 
-def test_mass_solve_symmetric_and_idempotent_full_size():
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_graph_replay_equals_eager_launches(precond, precision):
+    """PCG iterations replayed from captured HIP graphs give the eager result bit for bit,
+    over several solves and RK3 steps with other work and synchronisations in between."""
+    outs = []
+    for graphs in (False, True):
+        orc, s, _, _ = make_pair(12, 2, nu=1e-3, oracle=(not graphs), order="morton", precond=precond,
+                                 precision=precision, graphs=graphs)
+        if not graphs:
+            U0o = orc.project(RandomStreamField(seed=2, kmax=4))
+            U0 = transfer(orc, U0o, s)
+        U = U0.clone()
+        infos = []
+        for _ in range(3):
+            infos.append(list(s.rk3_step(U, 0.002).iterations))
+            torch.cuda.synchronize()
+        F = s.residual(U)
+        V, _ = s.mass_solve(F)
+        outs.append((U.clone(), V.clone(), infos))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+    assert outs[0][2] == outs[1][2]
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_mass_solve_symmetric_and_idempotent_full_size(precond):
     """256x256 BDM_2 (the benchmark mesh): g.P f = f.P g and P(P f) = P f."""
-    _, s, _, _ = make_pair(256, 2, oracle=False, cg_rtol=1e-12)
+    _, s, _, _ = make_pair(256, 2, oracle=False, cg_rtol=1e-12, precond=precond)
     _log("full size: T", s.T, "E", s.E)
     g0 = torch.Generator(device="cpu").manual_seed(0)
     f = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
     g = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
     Pf, i1 = s.mass_solve(f)
     Pg, _ = s.mass_solve(g)
-    _log("  iterations", i1.iterations, "rel res", i1.rel_residual)
+    _log("  iterations", precond, i1.iterations, "rel res", i1.rel_residual)
+    if precond == "amg":
+        assert i1.iterations < 100
     a, b = torch.dot(g, Pf).item(), torch.dot(f, Pg).item()
     assert abs(a - b) < 1e-9 * abs(a)
     PPf, _ = s.mass_solve(Pf)
