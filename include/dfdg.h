@@ -85,6 +85,8 @@ typedef struct {
                         1..2 = polynomial extrapolation of that order in time */
   int graphs;        /* 1: replay PCG iterations from captured HIP graphs (default);
                         0: launch every kernel individually.  Same results bit for bit. */
+  int mg_fp32;       /* DFDG_AMG with DFDG_FP64: 1 = run the V-cycle in FP32 (default; the
+                        PCG vectors, residuals and stopping test stay FP64), 0 = FP64 */
 } dfdg_params;
 
 typedef struct {

@@ -128,6 +128,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->inner_rtol = 1e-4;
   p->extrapolate = 0;
   p->graphs = 1;
+  p->mg_fp32 = 1;
 }
 
 static int check_params(const dfdg_params* p, std::string& e) {
@@ -147,6 +148,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   }
   if (p->extrapolate < 0 || p->extrapolate > 2) { e = "extrapolate must be 0, 1 or 2"; return -1; }
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
+  if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   return 0;
 }
 
@@ -173,7 +175,7 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     const int NFk = nF(prm->k);
     std::vector<double> z((size_t)h.E * NFk, 0.0);
     for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.zdef[F];
-    if (build_amg(h.E, NFk, h.cols, h.vals, z, 0.08, 500, ctx->H, e)) {
+    if (build_amg(h.E, NFk, h.cols, h.vals, z, 0.08, 1000, ctx->H, e)) {
       g_mesh_err = e;
       delete ctx;
       return DFDG_E_MESH;
@@ -268,9 +270,11 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.dinv = c.take<double>(h.dinv.size());
   A.binv = c.take<double>(h.binv.size());
   const bool mixed = ctx->prm.precision == DFDG_MIXED;
-  A.vals32 = mixed ? c.take<float>(h.vals.size()) : nullptr;
-  A.dinv32 = mixed ? c.take<float>(h.dinv.size()) : nullptr;
-  A.binv32 = mixed ? c.take<float>(h.binv.size()) : nullptr;
+  // FP32 copies of S (and of the multigrid data) for the mixed form or an FP32 V-cycle
+  const bool f32 = mixed || (ctx->prm.precond == DFDG_AMG && ctx->prm.mg_fp32);
+  A.vals32 = f32 ? c.take<float>(h.vals.size()) : nullptr;
+  A.dinv32 = f32 ? c.take<float>(h.dinv.size()) : nullptr;
+  A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
   ctx->q = c.take<double>(3 * NF * T);
@@ -324,7 +328,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
     D.ptr = c.take<int>(M.ptr.size());
     D.col = c.take<int>(M.col.size());
     D.val = c.take<double>(M.val.size());
-    D.val32 = mixed ? c.take<float>(M.val.size()) : nullptr;
+    D.val32 = f32 ? c.take<float>(M.val.size()) : nullptr;
   };
   for (int l = 0; l < mg.nlev; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -332,7 +336,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
     if (l > 0) {
       take_csr(L.A, mg.A[l]);
       mg.dinv[l] = c.take<double>(n);
-      mg.dinv32[l] = mixed ? c.take<float>(n) : nullptr;
+      mg.dinv32[l] = f32 ? c.take<float>(n) : nullptr;
     }
     if (l < mg.nlev - 1) {
       take_csr(L.P, mg.P[l]);
@@ -348,7 +352,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
     v.r = coarsest ? nullptr : c.take<double>(n);
     MgVec<float>& w = mg.v32[l];
     w = MgVec<float>{};
-    if (mixed) {
+    if (f32) {
       w.b = (l > 0) ? c.take<float>(n) : nullptr;
       w.z = (l > 0) ? c.take<float>(n) : nullptr;
       w.x = coarsest ? nullptr : c.take<float>(n);
@@ -365,7 +369,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   if (mg.nlev > 0) {
     mg.n_coarse = H.n_coarse;
     mg.coarse_inv = c.take<double>(H.coarse_inv.size());
-    mg.coarse_inv32 = mixed ? c.take<float>(H.coarse_inv.size()) : nullptr;
+    mg.coarse_inv32 = f32 ? c.take<float>(H.coarse_inv.size()) : nullptr;
   }
   ctx->ws_need = c.off + 256;
 }
@@ -424,7 +428,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<double*>(ctx->A.vals), h.vals, s));
   HIPC(up(const_cast<double*>(ctx->A.dinv), h.dinv, s));
   HIPC(up(const_cast<double*>(ctx->A.binv), h.binv, s));
-  if (ctx->prm.precision == DFDG_MIXED) {
+  if (ctx->A.vals32) {
     std::vector<float> v(h.vals.begin(), h.vals.end()), d(h.dinv.begin(), h.dinv.end()),
         b(h.binv.begin(), h.binv.end());
     HIPC(up(const_cast<float*>(ctx->A.vals32), v, s));
@@ -433,7 +437,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     HIPC(hipStreamSynchronize(s));
   }
   {
-    const bool mixed = ctx->prm.precision == DFDG_MIXED;
+    const bool mixed = ctx->A.vals32 != nullptr;  // FP32 copies were carved
     const AmgHierarchy& H = ctx->H;
     MgDev& mg = ctx->mg;
     std::vector<std::vector<float>> keep;  // float staging buffers stay alive until the sync below
@@ -605,7 +609,11 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     const PcgBufs& pb = ctx->pb;
     HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
     HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
-    if (amg) HIPC(launch_vcycle<double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], s));
+    const bool c32 = ctx->prm.mg_fp32 != 0;
+    if (amg) {
+      if (c32) HIPC((launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
+      else HIPC((launch_vcycle<double, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
+    }
     auto step = [&](int it, hipStream_t st) -> hipError_t {
       double* pin = ctx->p[(it - 1) & 1];
       double* pout = ctx->p[it & 1];
@@ -613,7 +621,8 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (e != hipSuccess) return e;
       e = launch_pcg_update(NF, pc, g, A, pout, ctx->Sp, x, ctx->r, ctx->z, pb, it, st);
       if (e != hipSuccess || !amg) return e;
-      return launch_vcycle<double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], st);
+      if (c32) return launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
+      return launch_vcycle<double, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
     };
     int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, &ctx->graph64, fin);
     if (rc) return rc;
@@ -639,12 +648,12 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (e != hipSuccess) return e;
       e = launch_pcg32_update(NF, pc, g, A, pout, ctx->Sp32, ctx->x32, ctx->r32, ctx->z32, pi, it, sm);
       if (e != hipSuccess || !amg) return e;
-      return launch_vcycle<float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[it & 1], sm);
+      return launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[it & 1], pi.sc, sm);
     };
     while (o.gg > 0 && o.rr > o.tol2) {
       if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
       HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], pi, s));
-      if (amg) HIPC(launch_vcycle<float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], s));
+      if (amg) HIPC((launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], pi.sc, s)));
       rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, &ctx->graph32, fin);
       if (rc) return rc;
       total += fin.iters;
@@ -910,7 +919,9 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
       case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI ? 1 : 0, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
                                        ctx->gv, ctx->r, ctx->z, pb, 1, s);  // writes rz[1], reads rz[0]
       case 2: return launch_residual(ctx->K, false, ctx->g, ctx->tb, ctx->Ustage, ctx->Lbuf, ctx->prm.nu, s);
-      case 4: return launch_vcycle<double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], s);
+      case 4:
+        if (ctx->prm.mg_fp32) return launch_vcycle<float, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
+        return launch_vcycle<double, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
       default: return launch_pcg32_spmv(NF, ctx->g, ctx->A, ctx->z32, ctx->p32[0], ctx->p32[1], ctx->Sp32, pb, 2, s);
     }
   };

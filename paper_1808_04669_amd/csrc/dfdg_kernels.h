@@ -63,11 +63,12 @@ template <typename V>
 inline const V* mg_dinv(const MgDev& m, int l) {
   if constexpr (sizeof(V) == 8) return m.dinv[l]; else return m.dinv32[l];
 }
-// z = V-cycle(b) (one smoothed-aggregation multigrid cycle); writes the (b, z) partial of
-// each facet block into rz[2*block].
-template <typename V>
-hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const V* b, V* z, double* rz,
-                         hipStream_t s);
+// z = V-cycle(b) (one smoothed-aggregation multigrid cycle run in type V on PCG vectors
+// of type VB); writes the (b, z) partial of each facet block into rz[2*block].  Every
+// kernel returns at once when sc->done says the PCG has stopped.
+template <typename V, typename VB>
+hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
+                         const PcgScalars* sc, hipStream_t s);
 
 // g[E][NF] = facet sums of q, then (one block) the deflated (g,g) and the stopping
 // threshold tol2 = rtol^2 (g,g) into pb.sc (done = RUNNING, or CONVERGED for g = 0).

@@ -863,9 +863,13 @@ __device__ inline const V* bsr_vals(const DevBsr& A) { return (sizeof(V) == 8) ?
 template <int NF, typename V>
 __device__ inline const V* bsr_dinv(const DevBsr& A) { return (sizeof(V) == 8) ? (const V*)A.dinv : (const V*)A.dinv32; }
 
-template <int NF, typename V>
-__global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const V* __restrict__ b, V* __restrict__ x2,
-                                                  CheB cb) {
+// V: arithmetic and storage type of the cycle; VB: type of the PCG vectors b (in) and z
+// (out), so that an FP32 cycle can precondition an FP64 PCG.  Every kernel of the cycle
+// returns at once when the PCG has already stopped (iterations replayed past the end).
+template <int NF, typename V, typename VB>
+__global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ b, V* __restrict__ x2,
+                                                  CheB cb, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -873,20 +877,22 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const V* _
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
-      for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * b[(size_t)c * NF + q] * ith;
+      for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * (V)b[(size_t)c * NF + q] * ith;
     }, y);
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
-      const V x1 = dinv[o] * b[o] * ith;
-      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (b[o] - y[a]);
+      const V bo = (V)b[o];
+      const V x1 = dinv[o] * bo * ith;
+      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
     }
   }
 }
 
-template <int NF, typename V>
-__global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const V* __restrict__ b,
-                                                    const V* __restrict__ x, V* __restrict__ r) {
+template <int NF, typename V, typename VB>
+__global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB* __restrict__ b,
+                                                    const V* __restrict__ x, V* __restrict__ r, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int E = g.E;
   for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
@@ -895,14 +901,15 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const V*
       for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a) r[(size_t)F * NF + a] = b[(size_t)F * NF + a] - y[a];
+    for (int a = 0; a < NF; ++a) r[(size_t)F * NF + a] = (V)b[(size_t)F * NF + a] - y[a];
   }
 }
 
-template <int NF, typename V>
-__global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const V* __restrict__ b,
+template <int NF, typename V, typename VB>
+__global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
-                                                    CheB cb) {
+                                                    CheB cb, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th);
   const int E = g.E;
@@ -915,7 +922,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const V*
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
-      const V dd = dinv[o] * (b[o] - y[a]) * ith;
+      const V dd = dinv[o] * ((V)b[o] - y[a]) * ith;
       d[o] = dd;
       x4[o] = x3[o] + dd;
     }
@@ -924,10 +931,12 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const V*
 
 // Last post-smoothing step; z is the preconditioned PCG residual b.  Writes the (b, z)
 // partial of this block into rz[2*block] (the (r,r) slot rz[2*block+1] is left alone).
-template <int NF, typename V>
-__global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const V* __restrict__ b,
+template <int NF, typename V, typename VB>
+__global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
-                                                    V* __restrict__ z, CheB cb, double* __restrict__ rz) {
+                                                    VB* __restrict__ z, CheB cb, double* __restrict__ rz,
+                                                    const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const V* dinv = bsr_dinv<NF, V>(A);
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -941,9 +950,9 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const V*
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
-      const V zz = x4[o] + c1 * d[o] + c2 * dinv[o] * (b[o] - y[a]);
-      z[o] = zz;
-      v[0] += (double)b[o] * (double)zz;
+      const V zz = x4[o] + c1 * d[o] + c2 * dinv[o] * ((V)b[o] - y[a]);
+      z[o] = (VB)zz;
+      v[0] += (double)b[o] * (double)(VB)zz;
     }
   }
   __shared__ double sh[kBlk / 64];
@@ -975,7 +984,8 @@ __device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, i
 
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
-                                                  V* __restrict__ x2, CheB cb) {
+                                                  V* __restrict__ x2, CheB cb, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V ith = (V)(1.0 / cb.th);
@@ -988,7 +998,8 @@ __global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict_
 
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_resid(DevCsr A, const V* __restrict__ b, const V* __restrict__ x,
-                                                    V* __restrict__ r) {
+                                                    V* __restrict__ r, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x[c]; });
@@ -998,7 +1009,8 @@ __global__ __launch_bounds__(kBlk) void k_mgc_resid(DevCsr A, const V* __restric
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_post1(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                     const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
-                                                    CheB cb) {
+                                                    CheB cb, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x3[c]; });
@@ -1012,7 +1024,8 @@ __global__ __launch_bounds__(kBlk) void k_mgc_post1(DevCsr A, const V* __restric
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
-                                                    V* __restrict__ z, CheB cb) {
+                                                    V* __restrict__ z, CheB cb, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x4[c]; });
@@ -1022,7 +1035,8 @@ __global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restric
 // y = M x (restriction with M = R), or y = y0 + M x (prolongation-add, add != 0).
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restrict__ x, const V* __restrict__ y0,
-                                                    V* __restrict__ y, int add) {
+                                                    V* __restrict__ y, int add, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
@@ -1032,7 +1046,8 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
 // (b, z) partials into rz[2*block] (grid-stride over n).
 template <typename V>
 __global__ __launch_bounds__(kBlk) void k_partial_dot(long n, const V* __restrict__ b, const V* __restrict__ z,
-                                                      double* __restrict__ rz) {
+                                                      double* __restrict__ rz, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   double v = 0;
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     v += (double)b[i] * (double)z[i];
@@ -1050,7 +1065,8 @@ __global__ __launch_bounds__(kBlk) void k_partial_dot(long n, const V* __restric
 // Coarsest level: x = Ainv b with the dense (regularised) inverse; a wavefront per row.
 template <typename V>
 __global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restrict__ Ainv, const float* __restrict__ Ainv32,
-                                                   const V* __restrict__ b, V* __restrict__ x) {
+                                                   const V* __restrict__ b, V* __restrict__ x, const PcgScalars* sc) {
+  if (sc->done != PCG_RUNNING) return;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g >> 6, lane = g & 63;
   const V* M = (sizeof(V) == 8) ? (const V*)Ainv : (const V*)Ainv32;
@@ -1401,69 +1417,72 @@ int facet_grid_size(int E) { return facet_grid(E); }
   }
 
 template <typename V>
-static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, hipStream_t s) {
+static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, const PcgScalars* sc, hipStream_t s) {
   DFDG_DISPATCH_LPR(M.lpr, hipLaunchKernelGGL((k_csr_apply<LP, V>), dim3(nblk((long)M.n * LP, kBlk)), dim3(kBlk), 0, s,
-                                              M, x, y0, y, add));
+                                              M, x, y0, y, add, sc));
 }
 
-template <typename V>
-hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const V* b, V* z, double* rz,
-                         hipStream_t s) {
+template <typename V, typename VB>
+hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
+                         const PcgScalars* sc, hipStream_t s) {
   const int G = facet_grid(g.E);
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
-  if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve
-    hipLaunchKernelGGL((k_dense_mv<V>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
-                       mg.coarse_inv, mg.coarse_inv32, b, z);
-    hipLaunchKernelGGL((k_partial_dot<V>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const V*)z, rz);
+  if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve in VB
+    hipLaunchKernelGGL((k_dense_mv<VB>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
+                       mg.coarse_inv, mg.coarse_inv32, b, z, sc);
+    hipLaunchKernelGGL((k_partial_dot<VB>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const VB*)z, rz, sc);
     return hipGetLastError();
   }
   DFDG_DISPATCH_NF(NF, {
-    hipLaunchKernelGGL((k_mg0_pre<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x, mg.cheb[0]);
-    hipLaunchKernelGGL((k_mg0_resid<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.r);
+    hipLaunchKernelGGL((k_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x, mg.cheb[0], sc);
+    hipLaunchKernelGGL((k_mg0_resid<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.r, sc);
   });
-  csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, s);
+  csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, sc, s);
   for (int l = 1; l < L - 1; ++l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
     const DevCsr& Al = mg.A[l];
     const V* dinv = mg_dinv<V>(mg, l);
     const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
     DFDG_DISPATCH_LPR(Al.lpr, {
-      hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, v.x, mg.cheb[l]);
-      hipLaunchKernelGGL((k_mgc_resid<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, (const V*)v.b, (const V*)v.x, v.r);
+      hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, v.x, mg.cheb[l], sc);
+      hipLaunchKernelGGL((k_mgc_resid<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, (const V*)v.b, (const V*)v.x, v.r, sc);
     });
-    csr_apply<V>(mg.R[l], (const V*)v.r, (const V*)nullptr, mg_vec<V>(mg, l + 1).b, 0, s);
+    csr_apply<V>(mg.R[l], (const V*)v.r, (const V*)nullptr, mg_vec<V>(mg, l + 1).b, 0, sc, s);
   }
   {
     const MgVec<V>& vc = mg_vec<V>(mg, L - 1);
     hipLaunchKernelGGL((k_dense_mv<V>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
-                       mg.coarse_inv, mg.coarse_inv32, (const V*)vc.b, vc.z);
+                       mg.coarse_inv, mg.coarse_inv32, (const V*)vc.b, vc.z, sc);
   }
   for (int l = L - 2; l >= 1; --l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
     const DevCsr& Al = mg.A[l];
     const V* dinv = mg_dinv<V>(mg, l);
-    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, s);
+    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, sc, s);
     const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
     DFDG_DISPATCH_LPR(Al.lpr, {
       hipLaunchKernelGGL((k_mgc_post1<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.x, v.y,
-                         v.d, mg.cheb[l]);
+                         v.d, mg.cheb[l], sc);
       hipLaunchKernelGGL((k_mgc_post2<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.y,
-                         (const V*)v.d, v.z, mg.cheb[l]);
+                         (const V*)v.d, v.z, mg.cheb[l], sc);
     });
   }
-  csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, s);
+  csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, sc, s);
   DFDG_DISPATCH_NF(NF, {
-    hipLaunchKernelGGL((k_mg0_post1<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d, mg.cheb[0]);
-    hipLaunchKernelGGL((k_mg0_post2<NN, V>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y, (const V*)v0.d, z,
-                       mg.cheb[0], rz);
+    hipLaunchKernelGGL((k_mg0_post1<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d,
+                       mg.cheb[0], sc);
+    hipLaunchKernelGGL((k_mg0_post2<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y, (const V*)v0.d, z,
+                       mg.cheb[0], rz, sc);
   });
   return hipGetLastError();
 }
-template hipError_t launch_vcycle<double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*, double*,
-                                          double*, hipStream_t);
-template hipError_t launch_vcycle<float>(int, const DevGeo&, const DevBsr&, const MgDev&, const float*, float*,
-                                         double*, hipStream_t);
+template hipError_t launch_vcycle<double, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
+                                                  double*, double*, const PcgScalars*, hipStream_t);
+template hipError_t launch_vcycle<float, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
+                                                 double*, double*, const PcgScalars*, hipStream_t);
+template hipError_t launch_vcycle<float, float>(int, const DevGeo&, const DevBsr&, const MgDev&, const float*, float*,
+                                                double*, const PcgScalars*, hipStream_t);
 
 
 hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
