@@ -34,10 +34,10 @@ struct dfdg_ctx {
   DevTabs tb{};
   DevBsr A{};
   // work buffers
-  double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *z = nullptr,
+  double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
          *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[3][3] = {}, *evaltab = nullptr,
          *partials = nullptr, *diagres = nullptr, *r64 = nullptr;
-  float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
+  float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *r32b = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
         *Sp32 = nullptr;
   PcgBufs pb{}, pb32{}, pbt{};  // FP64 PCG / refinement, FP32 inner PCG, kernel timing
   // adjoint buffers
@@ -49,8 +49,9 @@ struct dfdg_ctx {
   // PCG iterations captured as HIP graphs (kernel arguments fixed: the solve runs in lamx)
   double* lamx = nullptr;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t graph64 = nullptr, graph32 = nullptr;
-  int graph_iters = 0;
+  // one graph per iteration parity ([1]: odd iterations, [0]: even), FP64 and FP32 PCG
+  hipGraphExec_t graph64[2] = {nullptr, nullptr}, graph32[2] = {nullptr, nullptr};
+  int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
   std::string err;
 };
@@ -282,6 +283,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->lamw = c.take<double>(nL);
   ctx->lamx = c.take<double>(nL);
   ctx->r = c.take<double>(nL);
+  ctx->rb = c.take<double>(nL);  // second residual buffer (multigrid PCG alternates)
   ctx->z = c.take<double>(nL);
   ctx->p[0] = c.take<double>(nL);
   ctx->p[1] = c.take<double>(nL);
@@ -305,6 +307,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
     ctx->L32 = c.take<float>(nU);
     ctx->x32 = c.take<float>(nL);
     ctx->r32 = c.take<float>(nL);
+    ctx->r32b = c.take<float>(nL);
     ctx->z32 = c.take<float>(nL);
     ctx->p32[0] = c.take<float>(nL);
     ctx->p32[1] = c.take<float>(nL);
@@ -485,8 +488,10 @@ extern "C" const char* dfdg_last_error(const dfdg_ctx* ctx) {
 
 extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->graph64) (void)hipGraphExecDestroy(ctx->graph64);
-  if (ctx->graph32) (void)hipGraphExecDestroy(ctx->graph32);
+  for (int j = 0; j < 2; ++j) {
+    if (ctx->graph64[j]) (void)hipGraphExecDestroy(ctx->graph64[j]);
+    if (ctx->graph32[j]) (void)hipGraphExecDestroy(ctx->graph32[j]);
+  }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   if (ctx->pinned) {
     (void)hipStreamSynchronize(ctx->stream);
@@ -515,79 +520,74 @@ static int read_scalars(dfdg_ctx* ctx, PcgScalars* dev, PcgScalars& out) {
   return DFDG_OK;
 }
 
-// Run PCG iterations (already initialised on the device) until the device flags an end.
-// The host enqueues chunks of iterations and reads the scalars after each chunk; the
-// chunk length follows the observed convergence rate so that few empty launches remain.
-// Capture `iters` PCG iterations (an even number, the first one odd: the partial-buffer
-// parity is part of the launch arguments) into an executable graph.
+// Capture one PCG iteration of the given parity (the buffer and partial-slot choice
+// alternates between odd and even iterations and is part of the launch arguments; the
+// iteration index itself is read by the kernels from the device scalars).
 template <typename Step>
-static int capture_iterations(dfdg_ctx* ctx, int iters, Step step, hipGraphExec_t* out) {
+static int capture_iteration(dfdg_ctx* ctx, int parity, Step step, hipGraphExec_t* out) {
   if (!ctx->cap_stream) HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   HIPC(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-  for (int it = 1; it <= iters; ++it) {
-    hipError_t e = step(it, ctx->cap_stream);
-    if (e != hipSuccess) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(ctx->cap_stream, &g);
-      if (g) (void)hipGraphDestroy(g);
-      return fail(ctx, DFDG_E_HIP, std::string("PCG capture: ") + hipGetErrorString(e));
-    }
+  hipError_t e = step(parity ? 1 : 2, ctx->cap_stream);
+  if (e != hipSuccess) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(ctx->cap_stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    return fail(ctx, DFDG_E_HIP, std::string("PCG capture: ") + hipGetErrorString(e));
   }
   hipGraph_t g = nullptr;
   HIPC(hipStreamEndCapture(ctx->cap_stream, &g));
-  hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("graph instantiate: ") + hipGetErrorString(e));
   return DFDG_OK;
 }
 
 // Run PCG iterations (already initialised on the device) until the device flags an end.
-// Iterations are enqueued in chunks (one graph launch = graph_iters iterations, or eager
-// launches), and the host reads the scalars after each chunk; the chunk length follows
-// the observed convergence rate so that few idle iterations remain.  Iterations past
-// the end exit at their first instruction.
+// The host enqueues chunks of iterations (graph replays or eager launches) and reads the
+// scalars after each chunk.  The first chunk is the length of the previous run (*hint);
+// later chunks follow the mean contraction of (r, r) observed so far, so that few
+// iterations run past the end (those exit at their first instruction).
 template <typename Step>
-static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t* graph, PcgScalars& fin) {
+static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[2], int* hint,
+                    PcgScalars& fin) {
   int rc = read_scalars(ctx, sc, fin);
   if (rc) return rc;
   const bool use_graph = ctx->prm.graphs != 0;
-  const int gi = ctx->prm.precond == DFDG_AMG ? 4 : 32;  // iterations per graph
-  if (use_graph && fin.done == PCG_RUNNING && !*graph) {
-    rc = capture_iterations(ctx, gi, step, graph);
-    if (rc) return rc;
-  }
+  if (use_graph && fin.done == PCG_RUNNING)
+    for (int j = 0; j < 2; ++j)
+      if (!graph[j]) {
+        rc = capture_iteration(ctx, j, step, &graph[j]);
+        if (rc) return rc;
+      }
+  const bool amg = ctx->prm.precond == DFDG_AMG;
+  // a run of n iterations takes n + 1 launches: the last one finds the stopping test met
+  int chunk = *hint > 0 ? *hint + 1 : (amg ? 16 : 64);
   int launched = 0;
-  int chunk = ctx->prm.precond == DFDG_AMG ? 16 : 64;
-  double last_rr = -1;
-  int last_it = 0;
   while (fin.done == PCG_RUNNING) {
-    if (use_graph) {
-      const int n = std::max(1, (chunk + gi - 1) / gi);
-      for (int c = 0; c < n; ++c) HIPC(hipGraphLaunch(*graph, ctx->stream));
-      launched += n * gi;
-    } else {
-      for (int c = 0; c < chunk; ++c) {
-        hipError_t e = step(launched + 1 + c, ctx->stream);
+    for (int c = 0; c < chunk; ++c) {
+      const int it = launched + 1 + c;
+      if (use_graph) {
+        HIPC(hipGraphLaunch(graph[it & 1], ctx->stream));
+      } else {
+        hipError_t e = step(it, ctx->stream);
         if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
       }
-      launched += chunk;
     }
+    launched += chunk;
     rc = read_scalars(ctx, sc, fin);
     if (rc) return rc;
     if (fin.done != PCG_RUNNING) break;
-    if (launched > maxit + gi + 2)
-      return fail(ctx, DFDG_E_NOT_CONVERGED, "PCG did not stop at its iteration limit");
-    // predict the remaining iterations from the contraction of rr over the last chunk
-    int next = 2 * chunk;
-    if (last_rr > 0 && fin.iters > last_it && fin.rr > 0 && fin.rr < last_rr && fin.tol2 > 0) {
-      const double rate = std::log(fin.rr / last_rr) / (fin.iters - last_it);  // < 0
-      const double remain = std::log(fin.tol2 / fin.rr) / rate;
-      next = (int)std::ceil(remain * 1.05) + 2;
+    if (launched > maxit + 2) return fail(ctx, DFDG_E_NOT_CONVERGED, "PCG did not stop at its iteration limit");
+    // fin.rr is (r, r) after launched - 1 iterations; one more iteration has run and one
+    // further launch applies the test, so the estimate from fin.rr counts both
+    int next = std::max(chunk / 2, 2);
+    if (fin.iters > 0 && fin.rr > 0 && fin.rr0 > fin.rr && fin.tol2 > 0) {
+      const double rate = std::log(fin.rr / fin.rr0) / fin.iters;  // < 0
+      next = (int)std::ceil(std::log(fin.tol2 / fin.rr) / rate);
     }
-    chunk = std::min(std::max(next, 4), 1024);
-    last_rr = fin.rr;
-    last_it = fin.iters;
+    chunk = std::min(std::max(next, 1), 1024);
   }
+  *hint = fin.iters;
   return DFDG_OK;
 }
 
@@ -610,6 +610,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
     HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
     const bool c32 = ctx->prm.mg_fp32 != 0;
+    const bool fused = amg && ctx->mg.nlev >= 2;
     if (amg) {
       if (c32) HIPC((launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
       else HIPC((launch_vcycle<double, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
@@ -617,6 +618,15 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     auto step = [&](int it, hipStream_t st) -> hipError_t {
       double* pin = ctx->p[(it - 1) & 1];
       double* pout = ctx->p[it & 1];
+      if (fused) {  // residual alternates between r (even iterations) and rb (odd)
+        double* rin = (it & 1) ? ctx->r : ctx->rb;
+        double* rout = (it & 1) ? ctx->rb : ctx->r;
+        if (c32)
+          return launch_pcg_iteration_mg<float, double>(NF, g, A, ctx->mg, pb, it, ctx->z, pin, pout, ctx->Sp, x,
+                                                        rin, rout, ctx->z, st);
+        return launch_pcg_iteration_mg<double, double>(NF, g, A, ctx->mg, pb, it, ctx->z, pin, pout, ctx->Sp, x, rin,
+                                                       rout, ctx->z, st);
+      }
       hipError_t e = launch_pcg_spmv(NF, g, A, ctx->z, pin, pout, ctx->Sp, pb, it, st);
       if (e != hipSuccess) return e;
       e = launch_pcg_update(NF, pc, g, A, pout, ctx->Sp, x, ctx->r, ctx->z, pb, it, st);
@@ -624,7 +634,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (c32) return launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
       return launch_vcycle<double, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
     };
-    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, &ctx->graph64, fin);
+    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, ctx->graph64, &ctx->iters_hint[0], fin);
     if (rc) return rc;
     inf.iterations = fin.iters;
     inf.refinements = 0;
@@ -641,9 +651,16 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     int rc = read_scalars(ctx, pb.sc, o);
     if (rc) return rc;
     int total = 0, nref = 0, st = DFDG_OK;
+    const bool fused = amg && ctx->mg.nlev >= 2;
     auto step = [&](int it, hipStream_t sm) -> hipError_t {
       float* pin = ctx->p32[(it - 1) & 1];
       float* pout = ctx->p32[it & 1];
+      if (fused) {
+        float* rin = (it & 1) ? ctx->r32 : ctx->r32b;
+        float* rout = (it & 1) ? ctx->r32b : ctx->r32;
+        return launch_pcg_iteration_mg<float, float>(NF, g, A, ctx->mg, pi, it, ctx->z32, pin, pout, ctx->Sp32,
+                                                     ctx->x32, rin, rout, ctx->z32, sm);
+      }
       hipError_t e = launch_pcg32_spmv(NF, g, A, ctx->z32, pin, pout, ctx->Sp32, pi, it, sm);
       if (e != hipSuccess) return e;
       e = launch_pcg32_update(NF, pc, g, A, pout, ctx->Sp32, ctx->x32, ctx->r32, ctx->z32, pi, it, sm);
@@ -654,7 +671,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
       HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], pi, s));
       if (amg) HIPC((launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], pi.sc, s)));
-      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, &ctx->graph32, fin);
+      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, ctx->graph32, &ctx->iters_hint[1], fin);
       if (rc) return rc;
       total += fin.iters;
       ++nref;

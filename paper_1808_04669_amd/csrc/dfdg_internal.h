@@ -89,6 +89,7 @@ struct DevBsr {
 // one-block finishing kernel) and read by later kernels and by the host.
 struct PcgScalars {
   double rz, rr, gg, tol2, zg;
+  double rr0;  // (r, r) at the start of the run (written with the first iteration)
   int iters, done, maxit, zero_rhs;
   int it;      // index of the next iteration (set to 1 at the start, advanced by the update kernel)
   int pad;

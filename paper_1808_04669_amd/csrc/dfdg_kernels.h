@@ -69,6 +69,13 @@ inline const V* mg_dinv(const MgDev& m, int l) {
 template <typename V, typename VB>
 hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
                          const PcgScalars* sc, hipStream_t s);
+// One multigrid-preconditioned PCG iteration (needs at least two levels): p_new = z_in +
+// beta p_old, Sp = S p_new; x += alpha p_new, r_new = r_old - alpha Sp fused with the
+// first smoothing step; the rest of the cycle writes z = cycle(r_new) and its partials.
+template <typename V, typename VB>
+hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const PcgBufs& pb,
+                                   int it, const VB* z_in, const VB* p_old, VB* p_new, VB* Sp, VB* x,
+                                   const VB* r_old, VB* r_new, VB* z, hipStream_t s);
 
 // g[E][NF] = facet sums of q, then (one block) the deflated (g,g) and the stopping
 // threshold tol2 = rtol^2 (g,g) into pb.sc (done = RUNNING, or CONVERGED for g = 0).

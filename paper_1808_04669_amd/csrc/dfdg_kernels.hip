@@ -704,6 +704,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
     sc->iters = it - 1;
     sc->rr = t1[1];
     sc->rz = t1[0];
+    if (it == 1) sc->rr0 = t1[1];
     if (status != PCG_RUNNING) sc->done = status;
   }
   if (status != PCG_RUNNING) return;
@@ -1043,6 +1044,60 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
   if (i < M.n && sub == 0) y[i] = add ? y0[i] + s : s;
 }
 
+// ---- PCG update fused with the first smoothing step of the cycle ----------------------
+// PCG update fused with the first pre-smoothing step of the cycle.  The residual is
+// double-buffered: r_new = r_old - alpha Sp for the own rows, and the neighbours' new
+// residual, needed by S x1, is formed on the fly from r_old and Sp.  Also x += alpha p,
+// the (r,r) partial, and the iteration counter.
+template <int NF, typename V, typename VB>
+__global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ p,
+                                                          const VB* __restrict__ Sp, VB* __restrict__ x,
+                                                          const VB* __restrict__ r_old, VB* __restrict__ r_new,
+                                                          V* __restrict__ x2, CheB cb, PcgScalars* sc,
+                                                          const double* __restrict__ rz_prev,
+                                                          const double* __restrict__ pq, double* __restrict__ rz_out) {
+  if (sc->done != PCG_RUNNING) return;
+  const int E = g.E;
+  const int G = gridDim.x;
+  double t1[2], t2[1];
+  block_sum_partials<2>(rz_prev, G, t1);
+  block_sum_partials<1>(pq, G, t2);
+  int status = PCG_RUNNING;
+  if (!isfinite(t2[0])) status = PCG_NONFINITE;
+  else if (!(t2[0] > 0)) status = PCG_BREAKDOWN;
+  if (status != PCG_RUNNING) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = status;
+    return;
+  }
+  const VB alpha = (VB)(t1[0] / t2[0]);
+  const V* dinv = bsr_dinv<NF, V>(A);
+  const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
+  double v[2] = {0, 0};
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
+    V y[NF];
+    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const size_t o = (size_t)c * NF + q;
+        xc[q] = dinv[o] * (V)(r_old[o] - alpha * Sp[o]) * ith;
+      }
+    }, y);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      const size_t o = (size_t)F * NF + a;
+      x[o] += alpha * p[o];
+      const VB rn = r_old[o] - alpha * Sp[o];
+      r_new[o] = rn;
+      v[1] += (double)rn * (double)rn;
+      const V bo = (V)rn;
+      const V x1 = dinv[o] * bo * ith;
+      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
+    }
+  }
+  block_write_partial<2>(v, rz_out);
+  if (blockIdx.x == 0 && threadIdx.x == 0) sc->it = sc->it + 1;
+}
+
 // (b, z) partials into rz[2*block] (grid-stride over n).
 template <typename V>
 __global__ __launch_bounds__(kBlk) void k_partial_dot(long n, const V* __restrict__ b, const V* __restrict__ z,
@@ -1309,6 +1364,13 @@ hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb
   return hipGetLastError();
 }
 
+#define DFDG_DISPATCH_NF_VOID(NF, ...)                            \
+  switch (NF) {                                                   \
+    case 2: { constexpr int NN = 2; __VA_ARGS__; } break;         \
+    case 3: { constexpr int NN = 3; __VA_ARGS__; } break;         \
+    default: { constexpr int NN = 4; __VA_ARGS__; } break;        \
+  }
+
 #define DFDG_DISPATCH_NF(NF, ...)                                 \
   switch (NF) {                                                   \
     case 2: { constexpr int NN = 2; __VA_ARGS__; } break;         \
@@ -1422,22 +1484,15 @@ static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, c
                                               M, x, y0, y, add, sc));
 }
 
+// Everything of a cycle after the first pre-smoothing step (x2 = pre(b) already in v0.x).
 template <typename V, typename VB>
-hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
-                         const PcgScalars* sc, hipStream_t s) {
+static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
+                        const PcgScalars* sc, hipStream_t s) {
   const int G = facet_grid(g.E);
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
-  if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve in VB
-    hipLaunchKernelGGL((k_dense_mv<VB>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
-                       mg.coarse_inv, mg.coarse_inv32, b, z, sc);
-    hipLaunchKernelGGL((k_partial_dot<VB>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const VB*)z, rz, sc);
-    return hipGetLastError();
-  }
-  DFDG_DISPATCH_NF(NF, {
-    hipLaunchKernelGGL((k_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x, mg.cheb[0], sc);
-    hipLaunchKernelGGL((k_mg0_resid<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.r, sc);
-  });
+  DFDG_DISPATCH_NF_VOID(NF, hipLaunchKernelGGL((k_mg0_resid<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b,
+                                               (const V*)v0.x, v0.r, sc));
   csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, sc, s);
   for (int l = 1; l < L - 1; ++l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
@@ -1459,8 +1514,8 @@ hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& 
     const MgVec<V>& v = mg_vec<V>(mg, l);
     const DevCsr& Al = mg.A[l];
     const V* dinv = mg_dinv<V>(mg, l);
-    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, sc, s);
     const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
+    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, sc, s);
     DFDG_DISPATCH_LPR(Al.lpr, {
       hipLaunchKernelGGL((k_mgc_post1<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.x, v.y,
                          v.d, mg.cheb[l], sc);
@@ -1469,14 +1524,61 @@ hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& 
     });
   }
   csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, sc, s);
-  DFDG_DISPATCH_NF(NF, {
+  DFDG_DISPATCH_NF_VOID(NF, {
     hipLaunchKernelGGL((k_mg0_post1<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d,
                        mg.cheb[0], sc);
     hipLaunchKernelGGL((k_mg0_post2<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y, (const V*)v0.d, z,
                        mg.cheb[0], rz, sc);
   });
+}
+
+template <typename V, typename VB>
+hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
+                         const PcgScalars* sc, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  const int L = mg.nlev;
+  const MgVec<V>& v0 = mg_vec<V>(mg, 0);
+  if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve in VB
+    hipLaunchKernelGGL((k_dense_mv<VB>), dim3(nblk((long)mg.n_coarse * 64, kBlk)), dim3(kBlk), 0, s, mg.n_coarse,
+                       mg.coarse_inv, mg.coarse_inv32, b, z, sc);
+    hipLaunchKernelGGL((k_partial_dot<VB>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const VB*)z, rz, sc);
+    return hipGetLastError();
+  }
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x,
+                                          mg.cheb[0], sc));
+  vcycle_body<V, VB>(NF, g, A, mg, b, z, rz, sc, s);
   return hipGetLastError();
 }
+
+// One PCG iteration with the multigrid preconditioner, residual double-buffered:
+// spmv (p, S p), fused update + pre-smoothing, rest of the cycle (z, (r,z) partial).
+template <typename V, typename VB>
+hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const PcgBufs& pb,
+                                   int it, const VB* z_in, const VB* p_old, VB* p_new, VB* Sp, VB* x,
+                                   const VB* r_old, VB* r_new, VB* z, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  hipError_t e = spmv_any<VB>(NF, g, A, z_in, p_old, p_new, Sp, pb, it, s);
+  if (e != hipSuccess) return e;
+  const double* prev = pb.rz[(it - 1) & 1];
+  double* out = pb.rz[it & 1];
+  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_upd_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A,
+                                          (const VB*)p_new, (const VB*)Sp, x, r_old, r_new, mg_vec<V>(mg, 0).x,
+                                          mg.cheb[0], pb.sc, prev, (const double*)pb.pq, out));
+  vcycle_body<V, VB>(NF, g, A, mg, (const VB*)r_new, z, out, pb.sc, s);
+  return hipGetLastError();
+}
+template hipError_t launch_pcg_iteration_mg<float, double>(int, const DevGeo&, const DevBsr&, const MgDev&,
+                                                           const PcgBufs&, int, const double*, const double*, double*,
+                                                           double*, double*, const double*, double*, double*,
+                                                           hipStream_t);
+template hipError_t launch_pcg_iteration_mg<double, double>(int, const DevGeo&, const DevBsr&, const MgDev&,
+                                                            const PcgBufs&, int, const double*, const double*, double*,
+                                                            double*, double*, const double*, double*, double*,
+                                                            hipStream_t);
+template hipError_t launch_pcg_iteration_mg<float, float>(int, const DevGeo&, const DevBsr&, const MgDev&,
+                                                          const PcgBufs&, int, const float*, const float*, float*,
+                                                          float*, float*, const float*, float*, float*, hipStream_t);
+
 template hipError_t launch_vcycle<double, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
                                                   double*, double*, const PcgScalars*, hipStream_t);
 template hipError_t launch_vcycle<float, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
