@@ -7,8 +7,11 @@ initial field), projected on the GPU.  One step = one TVD-RK3 step = three passe
 hot path (residual -> condensation -> facet PCG -> recovery).
 
 Prints one JSON line.  Extra objects: "roofline" (PCG SpMV kernel, timed live with HIP
-events), "cpu_baseline" (the CPU oracle on a bounded sample), "accuracy" (FP64 GPU vs the
-oracle on a reduced copy of the workload), "mixed" (mixed-precision form, optional).
+events), "cpu_baseline" (the CPU oracle on a bounded sample), "accuracy" (FP64 and mixed
+GPU paths vs the oracle on that sample), "random_numbering" (the same workload on a
+randomly numbered mesh), "mixed" (mixed-precision form vs FP64 on the 512x512 BDM_3
+double shear layer), "adjoint" (gradient of the final kinetic energy on the 128x128
+BDM_2 random field: reverse sweep and whole gradient over the forward rollout).
 """
 import argparse
 import json
@@ -54,9 +57,18 @@ def parse():
     ap.add_argument("--precond", default="amg", choices=["jacobi", "block_jacobi", "amg"])
     ap.add_argument("--extrapolate", type=int, default=2)
     ap.add_argument("--order", default="morton")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-accuracy", action="store_true")
-    ap.add_argument("--mixed", action="store_true", help="also time the mixed-precision form")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing and the accuracy check against the oracle")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-random-order", action="store_true", help="skip the randomly numbered mesh run")
+    ap.add_argument("--mixed-N", type=int, default=512)
+    ap.add_argument("--mixed-k", type=int, default=3)
+    ap.add_argument("--mixed-steps", type=int, default=20)
+    ap.add_argument("--mixed-ir-rtol", type=float, default=1e-10)
+    ap.add_argument("--mixed-inner-rtol", type=float, default=1e-3)
+    ap.add_argument("--adjoint-N", type=int, default=128)
+    ap.add_argument("--adjoint-steps", type=int, default=100)
     ap.add_argument("--cpu-sample-N", type=int, default=64)
     ap.add_argument("--cpu-sample-steps", type=int, default=3)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -81,12 +93,12 @@ def project_field(s, field):
     return U, vmax, info
 
 
-def make_solver(N, k, precision, args, order=None):
+def make_solver(N, k, precision, args, order=None, rtol=None, nu=0.0, **kw):
     from inputs import periodic_split_square
     from paper_1808_04669_amd import Solver
     xyz, per = periodic_split_square(N, order or args.order)
-    s = Solver(xyz, per, k, nu=0.0, precision=precision, cg_rtol=args.rtol, precond=args.precond,
-               extrapolate=args.extrapolate, ir_rtol=1e-10, inner_rtol=1e-3)
+    s = Solver(xyz, per, k, nu=nu, precision=precision, cg_rtol=rtol or args.rtol, precond=args.precond,
+               extrapolate=args.extrapolate, **kw)
     s._xyz = xyz
     return s
 
@@ -106,17 +118,20 @@ def timed_run(s, U, dt, steps, warmup):
 
 
 def cpu_baseline(args):
-    """The oracle (global mixed BDM solve with SuperLU) on the same workload at N = 64."""
+    """The oracle (global mixed BDM solve with SuperLU) on the same workload at a reduced
+    size; returns the timing and the oracle's final state (for the accuracy check)."""
     from inputs import double_shear_layer, periodic_split_square
     from oracle import Oracle
     N, k = args.cpu_sample_N, args.k
-    xyz, per = periodic_split_square(N)
+    xyz, per = periodic_split_square(N, args.order)
     orc = Oracle(xyz, per, k, nu=0.0)
     t0 = time.perf_counter()
     orc.factor()
     t_factor = time.perf_counter() - t0
-    U = orc.project(double_shear_layer)
-    dt = 0.1 / N / k ** 2
+    U0 = orc.project(double_shear_layer)
+    vmax = sample_vmax(orc, U0)
+    dt = 0.1 / N / (k ** 2 * vmax)
+    U = U0
     t0 = time.perf_counter()
     for _ in range(args.cpu_sample_steps):
         U = orc.rk3_step(U, dt)
@@ -126,12 +141,106 @@ def cpu_baseline(args):
         threads = len(os.sched_getaffinity(0))
     except Exception:
         threads = os.cpu_count()
-    return {"value": n_u * 3 * args.cpu_sample_steps / t, "unit": "velocity DOF-stages/s", "cores": 1,
-            "kind": "oracle",
-            "sample": (f"double shear layer, BDM_{k}, {N}x{N} split mesh ({2 * N * N} triangles, N_u={n_u}), "
-                       f"{args.cpu_sample_steps} TVD-RK3 steps timed after a {t_factor:.1f} s SuperLU factorisation "
-                       f"(excluded, like the GPU set-up); SuperLU and the NumPy residual run on one core "
-                       f"({threads} host threads visible)")}
+    out = {"value": n_u * 3 * args.cpu_sample_steps / t, "unit": "velocity DOF-stages/s", "cores": 1,
+           "kind": "oracle",
+           "sample": (f"double shear layer, BDM_{k}, {N}x{N} split mesh ({2 * N * N} triangles, N_u={n_u}), "
+                      f"{args.cpu_sample_steps} TVD-RK3 steps timed after a {t_factor:.1f} s SuperLU factorisation "
+                      f"(excluded, like the GPU set-up); SuperLU and the NumPy residual run on one core "
+                      f"({threads} host threads visible)")}
+    return out, (orc, U0, U, dt)
+
+
+def sample_vmax(orc, U):
+    from oracle.quadrature import triangle_rule
+    pts, _ = triangle_rule(2 * orc.k + 2)
+    v = orc.eval_ref(U, pts)  # [T, 2, nq]
+    return float(np.sqrt((v ** 2).sum(axis=1)).max())
+
+
+def accuracy_vs_oracle(args, orc, U0_orc, U_orc, dt):
+    """Relative L2 difference between the GPU paths and the oracle after the same steps on
+    the sample mesh, both starting from the oracle's projected initial field (a piecewise
+    polynomial, which the library takes over exactly through its orthonormal basis)."""
+    import torch
+    from oracle.quadrature import triangle_rule
+    pts, w = triangle_rule(2 * orc.k + 2)
+    o = orc.eval_ref(U_orc, pts)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        kw = dict(ir_rtol=args.mixed_ir_rtol, inner_rtol=args.mixed_inner_rtol) if prec == "mixed" else {}
+        s = make_solver(args.cpu_sample_N, orc.k, prec, args, **kw)
+        qp, _ = s.proj_rule()
+        vals = np.ascontiguousarray(np.transpose(orc.eval_ref(U0_orc, qp), (1, 2, 0)))  # [2, nq, T]
+        U = s.load_vector(torch.from_numpy(vals).to(s.device).reshape(-1))
+        for _ in range(args.cpu_sample_steps):
+            s.rk3_step(U, dt)
+        g = s.eval(U, pts).cpu().numpy().transpose(2, 0, 1)
+        out[prec] = orc.l2_diff(g, o, (pts, w)) / orc.l2_diff(o, 0 * o, (pts, w))
+        if prec == "fp64":
+            out["max_div_fp64"] = s.diagnostics(U)["max_div"]
+        del s
+    return {"rel_l2_fp64_vs_oracle": out["fp64"], "rel_l2_mixed_vs_oracle": out["mixed"],
+            "max_div_fp64": out["max_div_fp64"], "max_div_oracle": orc.divergence_max(U_orc),
+            "sample": f"{args.cpu_sample_N}x{args.cpu_sample_N} mesh, BDM_{orc.k}, {args.cpu_sample_steps} steps"}
+
+
+def mixed_vs_fp64(args):
+    """Mixed-precision form against the FP64 path on the 512x512 BDM_3 double shear layer
+    (facet solves to relative residual 1e-10 in both)."""
+    import torch
+    from inputs import double_shear_layer
+    N, k, steps = args.mixed_N, args.mixed_k, args.mixed_steps
+    res = {}
+    for prec in ("fp64", "mixed"):
+        kw = dict(ir_rtol=args.mixed_ir_rtol, inner_rtol=args.mixed_inner_rtol) if prec == "mixed" else {}
+        s = make_solver(N, k, prec, args, rtol=args.mixed_ir_rtol, **kw)
+        U, vmax, _ = project_field(s, double_shear_layer)
+        dt = 0.1 / N / (k ** 2 * vmax)
+        t, its = timed_run(s, U, dt, steps, 2)
+        res[prec] = (t, its, U, s.n_bdm)
+        del s
+        torch.cuda.empty_cache()
+    t64, it64, U64, n_u = res["fp64"]
+    tm, itm, Um, _ = res["mixed"]
+    return {"workload": f"double shear layer {N}x{N} split mesh, BDM_{k}, {steps} TVD-RK3 steps, "
+                        f"FP64 PCG rtol {args.mixed_ir_rtol:g} vs mixed (FP32 residual and inner PCG, "
+                        f"inner rtol {args.mixed_inner_rtol:g}, FP64 refinement to {args.mixed_ir_rtol:g})",
+            "value": n_u * 3 * steps / tm, "fp64_value": n_u * 3 * steps / t64, "unit": "velocity DOF-stages/s",
+            "speedup_vs_fp64": t64 / tm, "rel_l2_vs_fp64_gpu": ((Um - U64).norm() / U64.norm()).item(),
+            "iterations_per_stage": {"fp64": float(it64.mean()), "mixed_inner_total": float(itm.mean())}}
+
+
+def adjoint_cost(args):
+    """Gradient of the final kinetic energy through checkpointed TVD-RK3 steps (random
+    divergence-free field, nu = 1e-3): time of the plain forward rollout, of the forward
+    pass with checkpoints and of the reverse sweep."""
+    import torch
+    from inputs import RandomStreamField
+    from paper_1808_04669_amd.adjoint import final_energy
+    N, k, steps, every = args.adjoint_N, 2, args.adjoint_steps, 10
+    s = make_solver(N, k, "fp64", args, nu=1e-3)
+    U0, vmax, _ = project_field(s, RandomStreamField(seed=0, kmax=8))
+    dt = 0.1 / N / (k ** 2 * vmax)
+    U = U0.clone()
+    s.reset_history()
+    s.rk3_step(U, dt)  # first use: graph capture
+    s.reset_history()  # both timed runs start from a fresh state without warm-start history
+    torch.cuda.synchronize()
+    t_fwd, _ = timed_run(s, U0.clone(), dt, steps, 0)
+    U0r = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    E = final_energy(s, U0r, dt, steps, checkpoint_every=every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": f"random stream-function field (|k|<=8, seed 0), {N}x{N} split mesh, BDM_{k}, nu=1e-3, "
+                        f"{steps} TVD-RK3 steps, checkpoints every {every} steps, FP64",
+            "forward_s": t_fwd, "forward_with_checkpoints_s": t1 - t0, "backward_s": t2 - t1,
+            "backward_over_forward": (t2 - t1) / t_fwd, "gradient_over_forward": (t2 - t0) / t_fwd,
+            "final_energy": E.item(), "grad_norm": U0r.grad.norm().item()}
 
 
 def main():
@@ -164,6 +273,7 @@ def main():
     ms_spmv, bytes_spmv = s.time_kernel(0, reps=200)
     ms_upd, bytes_upd = s.time_kernel(1, reps=200)
     ms_res, bytes_res = s.time_kernel(2, reps=50)
+    ms_vc, bytes_vc = s.time_kernel(4, reps=50) if args.precond == "amg" else (None, None)
     achieved = bytes_spmv / (ms_spmv * 1e-3) / 1e9
     roof = {"kernel": "k_pcg_spmv (facet BSR SpMV + p update + (p,Sp) partials)", "bound": "hbm",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -171,6 +281,8 @@ def main():
             "avg_launch_us": round(ms_spmv * 1e3, 3), "bytes_per_launch": bytes_spmv,
             "others": {"k_pcg_update": {"us": round(ms_upd * 1e3, 3), "GB/s": round(bytes_upd / ms_upd / 1e6, 1)},
                        "k_residual": {"us": round(ms_res * 1e3, 3), "GB/s": round(bytes_res / ms_res / 1e6, 1)}}}
+    if ms_vc is not None:
+        roof["others"]["vcycle"] = {"us": round(ms_vc * 1e3, 3), "GB/s": round(bytes_vc / ms_vc / 1e6, 1)}
     out = {"metric": "velocity DOF-stages/sec at stated L2 err vs FP64 oracle; mixed/FP64 speedup",
            "value": value, "unit": "velocity DOF-stages/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1e3 * t / args.steps, "higher_is_better": True,
@@ -182,17 +294,26 @@ def main():
            "pcg_iterations_per_stage": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min())},
            "diagnostics_final": d,
            "roofline": roof}
-    if args.mixed:
-        sm = make_solver(N, k, "mixed", args)
-        Um, _, _ = project_field(sm, double_shear_layer)
-        tm, itm = timed_run(sm, Um, dt, args.steps, args.warmup)
-        diff = (Um - U).norm().item() / U.norm().item()
-        out["mixed"] = {"value": sm.n_bdm * 3 * args.steps / tm, "speedup_vs_fp64": t / tm,
-                        "rel_l2_vs_fp64_gpu": diff, "inner_iterations_mean": float(itm.mean())}
-        log(f"mixed: {tm:.3f} s, speedup {t / tm:.3f}, rel diff vs fp64 {diff:.3e}")
+    if not args.no_random_order:
+        sr = make_solver(N, k, "fp64", args, order="random")
+        Ur, _, _ = project_field(sr, double_shear_layer)
+        tr, itr = timed_run(sr, Ur, dt, min(args.steps, 50), 1)
+        out["random_numbering"] = {"value": sr.n_bdm * 3 * min(args.steps, 50) / tr,
+                                   "steps": min(args.steps, 50),
+                                   "pcg_iterations_per_stage": float(itr.mean())}
+        log("random numbering", out["random_numbering"])
+        del sr
+    if not args.no_mixed:
+        out["mixed"] = mixed_vs_fp64(args)
+        log("mixed", out["mixed"])
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_cost(args)
+        log("adjoint", out["adjoint"])
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args)
+        out["cpu_baseline"], (orc, U0_orc, U_orc, dt_s) = cpu_baseline(args)
         log("cpu baseline", out["cpu_baseline"])
+        out["accuracy"] = accuracy_vs_oracle(args, orc, U0_orc, U_orc, dt_s)
+        log("accuracy", out["accuracy"])
     print(json.dumps(out), flush=True)
 
 

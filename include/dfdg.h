@@ -166,7 +166,8 @@ int dfdg_project(dfdg_ctx* ctx, const double* f_at_q_dev, double* U_dev,
  *   averaged normal velocity.
  * dfdg_hdiv_mass_solve: U_dev = the u of eq. (FE3) for the functional F_dev, i.e. the
  *   divergence-free mass inversion of F (Theorem 2).  lambda_io_dev ([E][n_f]) is
- *   the PCG start on entry and the facet multiplier on exit; NULL = cold start.
+ *   the PCG start on entry and the facet multiplier on exit, which is fixed up to a
+ *   constant multiplier and returned orthogonal to it; NULL = cold start.
  *   Returns DFDG_E_NOT_CONVERGED/DFDG_E_BREAKDOWN if PCG failed (U_dev still written).
  * dfdg_rk3_step: one TVD-RK3 step of size dt, in place on U_io_dev (eq. (rk3));
  *   each stage is u + dt*M^{-1}L(u) combined as in the Shu-Osher form.  Multipliers of
@@ -175,19 +176,43 @@ int dfdg_dg_residual(dfdg_ctx* ctx, const double* U_dev, double* L_dev);
 int dfdg_hdiv_mass_solve(dfdg_ctx* ctx, const double* F_dev, double* U_dev,
                          double* lambda_io_dev, dfdg_solve_info* info);
 int dfdg_rk3_step(dfdg_ctx* ctx, double* U_io_dev, double dt, dfdg_step_info* info);
-/* Forget the warm-start history of rk3_step (e.g. after changing U externally). */
+/* dfdg_rk3_step_stages: dfdg_rk3_step that also leaves the states entering the second
+ *   and third stages in U1_dev and U2_dev (caller-owned, length n_broken, distinct from
+ *   U_io_dev and from each other), for dfdg_rk3_step_vjp_stages. */
+int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U_io_dev, double dt, double* U1_dev, double* U2_dev,
+                         dfdg_step_info* info);
+/* Forget the warm-start history of the forward stage solves (e.g. after changing U
+ * externally, or before recomputing an earlier segment of a trajectory). */
 int dfdg_reset_history(dfdg_ctx* ctx);
+/* Forget the warm-start history of the adjoint stage solves (start of a reverse sweep). */
+int dfdg_reset_adjoint_history(dfdg_ctx* ctx);
+/* dfdg_history_save: copies the forward warm-start history (per stage, the multipliers
+ *   of up to three earlier steps, newest first) into hist_dev ([3 stages][3][n_lambda],
+ *   caller-owned device memory; unused entries are left alone) and the number of valid
+ *   entries per stage into counts_host[3].  Asynchronous on the context stream.
+ * dfdg_history_restore: the inverse (counts in 0..3), e.g. at a checkpoint before a
+ *   trajectory segment is recomputed, which then repeats the original solves exactly. */
+int dfdg_history_save(dfdg_ctx* ctx, double* hist_dev, int* counts_host);
+int dfdg_history_restore(dfdg_ctx* ctx, const double* hist_dev, const int* counts_host);
 
 /* ---- adjoint form ------------------------------------------------------------------
  * dfdg_dg_residual_vjp: Ubar_dev = J_L(U)^T Lbar_dev, the transpose of the
  *   derivative of dfdg_dg_residual at U (upwind side frozen, the a.e. derivative).
  * dfdg_rk3_step_vjp: given U^n (Un_dev) and the cotangent of U^{n+1}, writes the
  *   cotangent of U^n (Ubar_io_dev in place) for one dfdg_rk3_step of size dt.
- *   Recomputes the stage states; the mass solve is self-adjoint. */
+ *   Recomputes the stage states (two forward stage solves, which update the forward
+ *   warm-start history); the mass solve is self-adjoint.
+ * dfdg_rk3_step_vjp_stages: the same with the stage states U1_dev, U2_dev given (as
+ *   left by dfdg_rk3_step_stages from U^n), so only the three adjoint solves run.
+ *   Ubar_io_dev must not alias a state.
+ * The adjoint solves are warm-started from those of the same stage in the previously
+ * processed step (see dfdg_reset_adjoint_history); FP64 contexts only. */
 int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U_dev, const double* Lbar_dev,
                          double* Ubar_dev);
 int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un_dev, double* Ubar_io_dev, double dt,
                       dfdg_step_info* info);
+int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un_dev, const double* U1_dev,
+                             const double* U2_dev, double* Ubar_io_dev, double dt, dfdg_step_info* info);
 
 /* ---- diagnostics and evaluation (a10) -----------------------------------------------
  * dfdg_eval: values out_dev[2][npts][T] of U at reference points ref_pts_host[npts][2]
@@ -197,10 +222,13 @@ int dfdg_eval(dfdg_ctx* ctx, const double* U_dev, int npts, const double* ref_pt
               double* out_dev);
 
 /* ---- measurement -------------------------------------------------------------------
- * dfdg_time_kernel: launches kernel `which` `reps` times on the context stream, each
- * between its own pair of HIP events, and returns the mean launch duration in ms.
+ * dfdg_time_kernel: launches kernel `which` `reps` times on the context stream and
+ * returns the mean duration in ms.  Single kernels (which = 0, 2, 3) carry their own
+ * start/stop events in the dispatch (kernel execution time, as a profiler reports it);
+ * 1 and 4 are bracketed by a pair of events recorded on the stream.
  *   which = 0: facet SpMV + (p, S p) partials (FP64);  1: PCG vector update (FP64);
- *   2: DG residual (FP64); 3: facet SpMV (FP32, MIXED contexts only).
+ *   2: DG residual (FP64); 3: facet SpMV (FP32, MIXED contexts only);
+ *   4: multigrid V-cycle (AMG contexts only).
  * The kernels run on the context's current work vectors with a separate set of PCG
  * scalars whose stopping test never fires; the work vectors (not the warm-start
  * history) are clobbered.  bytes_out (may be NULL) receives the algorithmic bytes one

@@ -35,14 +35,15 @@ struct dfdg_ctx {
   DevBsr A{};
   // work buffers
   double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
-         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[3][3] = {}, *evaltab = nullptr,
+         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][3] = {}, *evaltab = nullptr,
          *partials = nullptr, *diagres = nullptr, *r64 = nullptr;
   float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *r32b = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
         *Sp32 = nullptr;
   PcgBufs pb{}, pb32{}, pbt{};  // FP64 PCG / refinement, FP32 inner PCG, kernel timing
   // adjoint buffers
   double *Ustages[3] = {nullptr, nullptr, nullptr}, *Ybar = nullptr, *Wbuf = nullptr;
-  int hist_count[3] = {0, 0, 0};
+  // multiplier history per slot: 0-2 the forward stages, 3-5 the adjoint stage solves
+  int hist_count[6] = {0, 0, 0, 0, 0, 0};
   // multigrid preconditioner
   AmgHierarchy H;
   MgDev mg;
@@ -289,7 +290,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->p[1] = c.take<double>(nL);
   ctx->Sp = c.take<double>(nL);
   ctx->Ustage = c.take<double>(nU);
-  for (int s = 0; s < 3; ++s)
+  for (int s = 0; s < 6; ++s)
     for (int j = 0; j < 3; ++j) ctx->hist[s][j] = c.take<double>(nL);
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
@@ -675,7 +676,10 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (rc) return rc;
       total += fin.iters;
       ++nref;
-      if (fin.done == PCG_NONFINITE || fin.done == PCG_BREAKDOWN) st = status_of(fin.done);
+      // an inner run that meets (p, S p) <= 0 in FP32 (rounding near the null space of S)
+      // after some progress ends with its last iterate; the FP64 refinement residual
+      // decides whether more is needed
+      if (fin.done == PCG_NONFINITE || (fin.done == PCG_BREAKDOWN && fin.iters < 1)) st = status_of(fin.done);
       HIPC(launch_ir_residual(NF, g, A, ctx->gv, x, ctx->x32, 1, ctx->r64, pb, pi.sc, inner, ctx->prm.cg_maxit, s));
       rc = read_scalars(ctx, pb.sc, o);
       if (rc) return rc;
@@ -687,6 +691,9 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     inf.rel_residual = o.gg > 0 ? std::sqrt(std::max(o.rr, 0.0) / o.gg) : 0.0;
     inf.status = st;
   }
+  // the multiplier is fixed up to the kernel of S: keep the representative orthogonal to
+  // it, so that warm starts built from earlier solutions cannot let it drift
+  HIPC(launch_deflate(NF, g, x, ctx->pb.gg, s));
   if (lam != x) HIPC(hipMemcpyAsync(lam, x, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
   if (info) *info = inf;
   return DFDG_OK;
@@ -761,7 +768,41 @@ extern "C" int dfdg_reset_history(dfdg_ctx* ctx) {
   return DFDG_OK;
 }
 
-// Start value of stage s's facet solve from its history; returns whether it is a cold start.
+extern "C" int dfdg_reset_adjoint_history(dfdg_ctx* ctx) {
+  if (!ctx) return DFDG_E_INVALID_ARG;
+  for (int i = 3; i < 6; ++i) ctx->hist_count[i] = 0;
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_history_save(dfdg_ctx* ctx, double* hist, int* counts) {
+  NEED_BOUND(ctx);
+  if (!hist || !counts) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  const size_t nb = ctx->nL * sizeof(double);
+  for (int st = 0; st < 3; ++st) {
+    counts[st] = ctx->hist_count[st];
+    for (int j = 0; j < ctx->hist_count[st]; ++j)
+      HIPC(hipMemcpyAsync(hist + (size_t)(3 * st + j) * ctx->nL, ctx->hist[st][j], nb, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+  }
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_history_restore(dfdg_ctx* ctx, const double* hist, const int* counts) {
+  NEED_BOUND(ctx);
+  if (!hist || !counts) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  for (int st = 0; st < 3; ++st)
+    if (counts[st] < 0 || counts[st] > 3) return fail(ctx, DFDG_E_INVALID_ARG, "history counts must be in 0..3");
+  const size_t nb = ctx->nL * sizeof(double);
+  for (int st = 0; st < 3; ++st) {
+    for (int j = 0; j < counts[st]; ++j)
+      HIPC(hipMemcpyAsync(ctx->hist[st][j], hist + (size_t)(3 * st + j) * ctx->nL, nb, hipMemcpyDeviceToDevice,
+                          ctx->stream));
+    ctx->hist_count[st] = counts[st];
+  }
+  return DFDG_OK;
+}
+
+// Start value (in lamw) of the facet solve of history slot s; returns whether it is a cold start.
 static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
   const int n = ctx->hist_count[s];
   *cold = (n == 0);
@@ -795,16 +836,14 @@ static int rk_stage(dfdg_ctx* ctx, int s, const double* Us, const double* Un, do
   return DFDG_OK;
 }
 
-extern "C" int dfdg_rk3_step(dfdg_ctx* ctx, double* U, double dt, dfdg_step_info* info) {
-  NEED_BOUND(ctx);
-  if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+// Shu-Osher TVD-RK3 (eq. (rk3)), each bracket u + dt M^{-1} L(u) done by one solve; the
+// states entering stages 1 and 2 are left in U1 and U2.
+static int rk3_core(dfdg_ctx* ctx, double* U, double dt, double* U1, double* U2, dfdg_step_info* info) {
   dfdg_step_info st{};
   dfdg_solve_info si[3];
-  // Shu-Osher TVD-RK3 (eq. (rk3)) with each bracket u + dt M^{-1} L(u) done by one solve
-  int rc = rk_stage(ctx, 0, U, U, 0.0, 1.0, dt, ctx->Ustage, &si[0]);
-  if (!rc) rc = rk_stage(ctx, 1, ctx->Ustage, U, 0.75, 0.25, dt, ctx->Ustage, &si[1]);
-  if (!rc) rc = rk_stage(ctx, 2, ctx->Ustage, U, 1.0 / 3.0, 2.0 / 3.0, dt, U, &si[2]);
+  int rc = rk_stage(ctx, 0, U, U, 0.0, 1.0, dt, U1, &si[0]);
+  if (!rc) rc = rk_stage(ctx, 1, U1, U, 0.75, 0.25, dt, U2, &si[1]);
+  if (!rc) rc = rk_stage(ctx, 2, U2, U, 1.0 / 3.0, 2.0 / 3.0, dt, U, &si[2]);
   if (rc) return rc;
   st.status = DFDG_OK;
   for (int s = 0; s < 3; ++s) {
@@ -816,6 +855,22 @@ extern "C" int dfdg_rk3_step(dfdg_ctx* ctx, double* U, double dt, dfdg_step_info
   if (info) *info = st;
   if (st.status != DFDG_OK) return fail(ctx, st.status, "a stage's facet solve did not converge");
   return DFDG_OK;
+}
+
+extern "C" int dfdg_rk3_step(dfdg_ctx* ctx, double* U, double dt, dfdg_step_info* info) {
+  NEED_BOUND(ctx);
+  if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  return rk3_core(ctx, U, dt, ctx->Ustage, ctx->Ustage, info);
+}
+
+extern "C" int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U, double dt, double* U1, double* U2,
+                                    dfdg_step_info* info) {
+  NEED_BOUND(ctx);
+  if (!U || !U1 || !U2) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (U1 == U || U2 == U || U1 == U2) return fail(ctx, DFDG_E_INVALID_ARG, "U, U1 and U2 must be distinct buffers");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  return rk3_core(ctx, U, dt, U1, U2, info);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -833,14 +888,54 @@ extern "C" int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U, const double
 // and J_FE(u)^T y = y + dt J_L(u)^T P y.  Given Y3 = Ubar_{n+1}:
 //   Y2 = 2/3 J_FE(U2)^T Y3,  Y1 = 1/4 J_FE(U1)^T Y2,
 //   Ubar_n = 1/3 Y3 + 3/4 Y2 + J_FE(Un)^T Y1.
-static int fe_transpose(dfdg_ctx* ctx, const double* u, const double* y, double* out, double dt,
+static int fe_transpose(dfdg_ctx* ctx, int stage, const double* u, const double* y, double* out, double dt,
                         dfdg_solve_info* si) {
   hipStream_t s = ctx->stream;
-  // P y: adjoint right-hand sides have no history; start from zero
-  int rc = mass_solve_impl(ctx, y, false, ctx->Wbuf, ctx->lamw, true, si, 0, 0, nullptr, 0, nullptr, 0);
+  // P y, warm-started from the same stage's adjoint solves of the steps processed before
+  bool cold;
+  int rc = stage_guess(ctx, 3 + stage, &cold);
   if (rc) return rc;
+  rc = mass_solve_impl(ctx, y, false, ctx->Wbuf, ctx->lamw, cold, si, 0, 0, nullptr, 0, nullptr, 0);
+  if (rc) return rc;
+  stage_push(ctx, 3 + stage);
   HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, u, ctx->Wbuf, out, ctx->prm.nu, s));
   HIPC(launch_axpby(ctx->nU, 1.0, y, dt, out, s));  // out = y + dt J^T P y
+  return DFDG_OK;
+}
+
+// Reverse sweep of one TVD-RK3 step given its stage states U^n, U1, U2; Ybar in place.
+static int rk3_vjp_core(dfdg_ctx* ctx, const double* Un, const double* U1, const double* U2, double* Ybar,
+                        double dt, dfdg_solve_info (&si)[3]) {
+  hipStream_t s = ctx->stream;
+  const long n = ctx->nU;
+  double* tmp = ctx->Ustages[2];
+  double* Yk = ctx->Ybar;
+  int rc = fe_transpose(ctx, 2, U2, Ybar, tmp, dt, &si[2]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 2.0 / 3.0, tmp, 0.0, Yk, s));       // Y2
+  HIPC(launch_axpby(n, 0.75, Yk, 1.0 / 3.0, Ybar, s));     // Ubar = 1/3 Y3 + 3/4 Y2
+  rc = fe_transpose(ctx, 1, U1, Yk, tmp, dt, &si[1]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 0.25, tmp, 0.0, Yk, s));            // Y1
+  rc = fe_transpose(ctx, 0, Un, Yk, tmp, dt, &si[0]);
+  if (rc) return rc;
+  HIPC(launch_axpby(n, 1.0, tmp, 1.0, Ybar, s));           // Ubar += J_FE(Un)^T Y1
+  return DFDG_OK;
+}
+
+static int vjp_info(dfdg_ctx* ctx, const dfdg_solve_info (&si)[3], const dfdg_solve_info* fw, int nfw,
+                    dfdg_step_info* info) {
+  dfdg_step_info st{};
+  st.status = DFDG_OK;
+  for (int i = 0; i < 3; ++i) {
+    st.iterations[i] = si[i].iterations;
+    st.max_rel_residual = std::max(st.max_rel_residual, si[i].rel_residual);
+    if (si[i].status != DFDG_OK) st.status = si[i].status;
+  }
+  for (int i = 0; i < nfw; ++i)
+    if (fw[i].status != DFDG_OK) st.status = fw[i].status;
+  if (info) *info = st;
+  if (st.status != DFDG_OK) return fail(ctx, st.status, "a facet solve of the adjoint step did not converge");
   return DFDG_OK;
 }
 
@@ -849,37 +944,28 @@ extern "C" int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un, double* Ybar, 
   if (!Un || !Ybar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
-  hipStream_t s = ctx->stream;
-  const long n = ctx->nU;
   double* U1 = ctx->Ustages[0];
   double* U2 = ctx->Ustages[1];
-  double* tmp = ctx->Ustages[2];
-  double* Yk = ctx->Ybar;
   dfdg_solve_info fw[2]{}, si[3]{};
   int rc = rk_stage(ctx, 0, Un, Un, 0.0, 1.0, dt, U1, &fw[0]);
   if (!rc) rc = rk_stage(ctx, 1, U1, Un, 0.75, 0.25, dt, U2, &fw[1]);
   if (rc) return rc;
-  rc = fe_transpose(ctx, U2, Ybar, tmp, dt, &si[2]);
+  rc = rk3_vjp_core(ctx, Un, U1, U2, Ybar, dt, si);
   if (rc) return rc;
-  HIPC(launch_axpby(n, 2.0 / 3.0, tmp, 0.0, Yk, s));       // Y2
-  HIPC(launch_axpby(n, 0.75, Yk, 1.0 / 3.0, Ybar, s));     // Ubar = 1/3 Y3 + 3/4 Y2
-  rc = fe_transpose(ctx, U1, Yk, tmp, dt, &si[1]);
+  return vjp_info(ctx, si, fw, 2, info);
+}
+
+extern "C" int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un, const double* U1, const double* U2,
+                                        double* Ybar, double dt, dfdg_step_info* info) {
+  NEED_BOUND(ctx);
+  if (!Un || !U1 || !U2 || !Ybar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (Ybar == Un || Ybar == U1 || Ybar == U2) return fail(ctx, DFDG_E_INVALID_ARG, "Ybar must not alias a state");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  dfdg_solve_info si[3]{};
+  int rc = rk3_vjp_core(ctx, Un, U1, U2, Ybar, dt, si);
   if (rc) return rc;
-  HIPC(launch_axpby(n, 0.25, tmp, 0.0, Yk, s));            // Y1
-  rc = fe_transpose(ctx, Un, Yk, tmp, dt, &si[0]);
-  if (rc) return rc;
-  HIPC(launch_axpby(n, 1.0, tmp, 1.0, Ybar, s));           // Ubar += J_FE(Un)^T Y1
-  dfdg_step_info st{};
-  st.status = DFDG_OK;
-  for (int i = 0; i < 3; ++i) {
-    st.iterations[i] = si[i].iterations;
-    st.max_rel_residual = std::max(st.max_rel_residual, si[i].rel_residual);
-    if (si[i].status != DFDG_OK) st.status = si[i].status;
-    if (i < 2 && fw[i].status != DFDG_OK) st.status = fw[i].status;
-  }
-  if (info) *info = st;
-  if (st.status != DFDG_OK) return fail(ctx, st.status, "a facet solve of the adjoint step did not converge");
-  return DFDG_OK;
+  return vjp_info(ctx, si, nullptr, 0, info);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -943,14 +1029,23 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
     }
   };
   HIPC(launch());  // warm-up
-  // one event pair per launch: the mean of (end - start) is the kernel's own duration on
-  // the stream, without the gaps between back-to-back dispatches
+  // single-kernel measurements (SpMV, residual) attach the events to the dispatch itself,
+  // so that end - start is the kernel's execution; the V-cycle (several kernels) is
+  // bracketed by events recorded on the stream
+  const bool single = which != 1 && which != 4;
   std::vector<hipEvent_t> ev(2 * (size_t)reps);
   for (auto& e : ev) HIPC(hipEventCreate(&e));
   for (int i = 0; i < reps; ++i) {
-    HIPC(hipEventRecord(ev[2 * i], s));
-    HIPC(launch());
-    HIPC(hipEventRecord(ev[2 * i + 1], s));
+    if (single) {
+      set_dispatch_events(ev[2 * i], ev[2 * i + 1]);
+      hipError_t e = launch();
+      set_dispatch_events(nullptr, nullptr);
+      HIPC(e);
+    } else {
+      HIPC(hipEventRecord(ev[2 * i], s));
+      HIPC(launch());
+      HIPC(hipEventRecord(ev[2 * i + 1], s));
+    }
   }
   HIPC(hipEventSynchronize(ev.back()));
   double tot = 0;

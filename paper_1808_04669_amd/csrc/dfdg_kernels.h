@@ -79,6 +79,11 @@ hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, con
 
 // g[E][NF] = facet sums of q, then (one block) the deflated (g,g) and the stopping
 // threshold tol2 = rtol^2 (g,g) into pb.sc (done = RUNNING, or CONVERGED for g = 0).
+// Start/stop events for the dispatch packet of the next SpMV or residual launch (kernel
+// execution only; nullptr restores plain launches).
+void set_dispatch_events(hipEvent_t start, hipEvent_t stop);
+// x_{.,0} -= (zdef, x_{.,0}) zdef (part: scratch for one partial per facet block).
+hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipStream_t s);
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
                            int maxit, hipStream_t s);
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials of iteration 0.

@@ -11,6 +11,7 @@
 // kernel's blocks each sum all partials in the same fixed order.  (A per-block device-scope
 // release fence would write back the XCD's whole L2 on every block.)
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 
@@ -573,6 +574,25 @@ __global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __res
   block_write_partial<2>(v, part);
 }
 
+// (zdef, x_{.,0}) partials, one per block.
+template <int NF>
+__global__ __launch_bounds__(kBlk) void k_zdot(DevGeo g, const double* __restrict__ x, double* __restrict__ part) {
+  double v[1] = {0};
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x)
+    v[0] += g.zdef[F] * x[(size_t)F * NF];
+  block_write_partial<1>(v, part);
+}
+
+// x_{F,0} -= (zdef, x) zdef_F: removes the component of x along the kernel of S.
+template <int NF>
+__global__ __launch_bounds__(kBlk) void k_zdeflate(DevGeo g, double* __restrict__ x, const double* __restrict__ part,
+                                                   int n) {
+  double t[1];
+  block_sum_partials<1>(part, n, t);
+  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x)
+    x[(size_t)F * NF] -= t[0] * g.zdef[F];
+}
+
 // One block: the deflated (g,g) and the PCG stopping threshold.
 __global__ __launch_bounds__(kBlk) void k_finalize_gather(const double* __restrict__ part, int n, PcgScalars* sc,
                                                           double rtol, int maxit) {
@@ -829,7 +849,8 @@ __global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const 
   block_write_partial<1>(v, part);
 }
 
-// One block: (r64, r64) into the outer scalars; set up the inner FP32 solve's stopping test.
+// One block: (r64, r64) into the outer scalars; set up the inner FP32 solve's stopping test
+// (sc64->tol2 holds the outer threshold, ir_rtol^2 (g, g)).
 __global__ __launch_bounds__(kBlk) void k_finalize_ir(const double* __restrict__ part, int n, PcgScalars* sc64,
                                                       PcgScalars* sc32, double inner_rtol, int maxit) {
   double t[1];
@@ -837,7 +858,8 @@ __global__ __launch_bounds__(kBlk) void k_finalize_ir(const double* __restrict__
   if (threadIdx.x == 0) {
     sc64->rr = t[0];
     sc32->gg = t[0];
-    sc32->tol2 = inner_rtol * inner_rtol * t[0];
+    // relative to the refinement residual, but never below half the outer target
+    sc32->tol2 = fmax(inner_rtol * inner_rtol * t[0], 0.25 * sc64->tol2);
     sc32->maxit = maxit;
     sc32->iters = 0;
     sc32->it = 1;
@@ -1317,6 +1339,19 @@ __global__ void k_extrapolate(long n, int order, const double* __restrict__ h0, 
 // ---------------------------------------------------------------------------------------
 static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Events attached to the dispatch packet of the next single-kernel launch of the SpMV or
+// the residual (kernel-only start and end times, for the measurement entry point).
+static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
+void set_dispatch_events(hipEvent_t start, hipEvent_t stop) {
+  t_ev0 = start;
+  t_ev1 = stop;
+}
+#define DFDG_LAUNCH_TIMED(KER, GRID, BLK, SH, S, ...)                                   \
+  do {                                                                                  \
+    if (t_ev0) hipExtLaunchKernelGGL(KER, GRID, BLK, SH, S, t_ev0, t_ev1, 0, __VA_ARGS__); \
+    else hipLaunchKernelGGL(KER, GRID, BLK, SH, S, __VA_ARGS__);                        \
+  } while (0)
+
 #define DFDG_DISPATCH_K(K, ...)                                   \
   switch (K) {                                                    \
     case 1: { constexpr int KK = 1; __VA_ARGS__; } break;         \
@@ -1328,8 +1363,8 @@ static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b);
 hipError_t launch_residual(int K, bool fp32, const DevGeo& g, const DevTabs& tb, const double* U, void* L,
                            double nu, hipStream_t s) {
   DFDG_DISPATCH_K(K, {
-    if (fp32) hipLaunchKernelGGL((k_residual<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (float*)L, nu);
-    else hipLaunchKernelGGL((k_residual<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (double*)L, nu);
+    if (fp32) DFDG_LAUNCH_TIMED((k_residual<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (float*)L, nu);
+    else DFDG_LAUNCH_TIMED((k_residual<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (double*)L, nu);
   });
   return hipGetLastError();
 }
@@ -1387,6 +1422,15 @@ hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv,
   return hipGetLastError();
 }
 
+hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipStream_t s) {
+  const int G = facet_grid(g.E);
+  DFDG_DISPATCH_NF(NF, {
+    hipLaunchKernelGGL((k_zdot<NN>), dim3(G), dim3(kBlk), 0, s, g, (const double*)x, part);
+    hipLaunchKernelGGL((k_zdeflate<NN>), dim3(G), dim3(kBlk), 0, s, g, x, (const double*)part, G);
+  });
+  return hipGetLastError();
+}
+
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
                            double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
   const int G = facet_grid(g.E);
@@ -1403,8 +1447,8 @@ static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z,
   const int G = facet_grid(g.E);
   const double* prev = pb.rz[(it - 1) & 1];
   const double* prev2 = pb.rz[it & 1];
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
-                                          pb.sc, prev, prev2, pb.pq));
+  DFDG_DISPATCH_NF(NF, DFDG_LAUNCH_TIMED((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
+                                         pb.sc, prev, prev2, pb.pq));
   return hipGetLastError();
 }
 

@@ -79,9 +79,14 @@ _SIGS = {
     "dfdg_dg_residual": (ctypes.c_int, [_P, _P, _P]),
     "dfdg_hdiv_mass_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "dfdg_rk3_step": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
+    "dfdg_rk3_step_stages": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(StepInfo)]),
     "dfdg_reset_history": (ctypes.c_int, [_P]),
+    "dfdg_reset_adjoint_history": (ctypes.c_int, [_P]),
+    "dfdg_history_save": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_history_restore": (ctypes.c_int, [_P, _P, _P]),
     "dfdg_dg_residual_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "dfdg_rk3_step_vjp": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
+    "dfdg_rk3_step_vjp_stages": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
     "dfdg_diagnostics": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
     "dfdg_eval": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
     "dfdg_time_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
@@ -240,8 +245,31 @@ class Solver:
                                             ctypes.byref(info)))
         return info
 
+    def rk3_step_stages(self, U, dt, U1, U2):
+        """rk3_step that also leaves the states entering stages 2 and 3 in U1 and U2."""
+        info = StepInfo()
+        self._check(self._lib.dfdg_rk3_step_stages(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(dt),
+                                                   self._vec(U1, self.n_broken, "U1"),
+                                                   self._vec(U2, self.n_broken, "U2"), ctypes.byref(info)))
+        return info
+
     def reset_history(self):
         self._check(self._lib.dfdg_reset_history(self._h))
+
+    def reset_adjoint_history(self):
+        self._check(self._lib.dfdg_reset_adjoint_history(self._h))
+
+    def history_save(self):
+        """Snapshot of the forward warm-start history: (device tensor, counts)."""
+        buf = torch.empty(9 * self.n_lambda, dtype=torch.float64, device=self.device)
+        counts = (ctypes.c_int * 3)()
+        self._check(self._lib.dfdg_history_save(self._h, _ptr(buf), counts))
+        return buf, tuple(counts)
+
+    def history_restore(self, snap):
+        buf, counts = snap
+        c = (ctypes.c_int * 3)(*counts)
+        self._check(self._lib.dfdg_history_restore(self._h, self._vec(buf, 9 * self.n_lambda, "history"), c))
 
     def residual_vjp(self, U, Lbar, Ubar=None):
         Ubar = self.new_vector() if Ubar is None else Ubar
@@ -256,6 +284,16 @@ class Solver:
         self._check(self._lib.dfdg_rk3_step_vjp(self._h, self._vec(Un, self.n_broken, "Un"),
                                                 self._vec(Ubar, self.n_broken, "Ubar"), ctypes.c_double(dt),
                                                 ctypes.byref(info)))
+        return info
+
+    def rk3_step_vjp_stages(self, Un, U1, U2, Ubar, dt):
+        """rk3_step_vjp with the stage states given (from rk3_step_stages)."""
+        info = StepInfo()
+        self._check(self._lib.dfdg_rk3_step_vjp_stages(self._h, self._vec(Un, self.n_broken, "Un"),
+                                                       self._vec(U1, self.n_broken, "U1"),
+                                                       self._vec(U2, self.n_broken, "U2"),
+                                                       self._vec(Ubar, self.n_broken, "Ubar"), ctypes.c_double(dt),
+                                                       ctypes.byref(info)))
         return info
 
     def diagnostics(self, U):

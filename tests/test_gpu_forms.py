@@ -107,11 +107,84 @@ def test_rk3_step_vjp_matches_finite_differences():
         assert abs(adj - fd) < 1e-6 * abs(fd) + 1e-10
 
 
-def test_energy_gradient_vs_oracle_and_fd():
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_step_vjp_with_given_stages_equals_recomputing_vjp(precond):
+    """rk3_step_vjp_stages(U^n, U1, U2) with the stage states left by rk3_step_stages gives
+    the same cotangent as rk3_step_vjp (which recomputes them), and rk3_step_stages
+    advances U exactly like rk3_step; several steps in a row exercise the warm-started
+    adjoint solves."""
+    orc, s, _, _ = make_pair(12, 2, nu=1e-3, order="random", seed=2, cg_rtol=1e-13, precond=precond,
+                             extrapolate=2)
+    U = transfer(orc, orc.project(RandomStreamField(seed=1, kmax=4)), s)
+    dt = 0.1 / 12 / 4
+    states, stages = [U.clone()], []
+    s.reset_history()
+    for _ in range(4):
+        u = states[-1].clone()
+        v = states[-1].clone()
+        U1, U2 = torch.empty_like(u), torch.empty_like(u)
+        s.rk3_step_stages(u, dt, U1, U2)
+        states.append(u)
+        stages.append((U1, U2))
+    s.reset_history()
+    ref = states[0].clone()
+    for _ in range(4):
+        s.rk3_step(ref, dt)
+    assert (ref - states[-1]).norm().item() < 1e-11 * ref.norm().item()
+    w = transfer(orc, _div_free_dirs(orc, 1, seed=5)[0], s)
+    Ya, Yb = w.clone(), w.clone()
+    s.reset_adjoint_history()
+    for n in range(3, -1, -1):
+        s.rk3_step_vjp_stages(states[n], stages[n][0], stages[n][1], Ya, dt)
+        s.rk3_step_vjp(states[n], Yb, dt)
+    err = (Ya - Yb).norm().item() / Yb.norm().item()
+    _log("vjp stages vs recompute", precond, err)
+    assert err < 1e-10
+    with pytest.raises(Exception):
+        s.rk3_step_vjp_stages(states[0], stages[0][0], stages[0][1], states[0], dt)  # Ubar aliases U^n
+
+
+def test_history_restore_repeats_the_trajectory_bitwise():
+    """With the state and the warm-start history restored at a checkpoint, the next steps
+    repeat the original ones bit for bit (the kernels are deterministic and the PCG start
+    is the same), which the checkpointed reverse sweep relies on."""
+    _, s, xyz, _ = make_pair(16, 2, nu=1e-3, order="morton", oracle=False, cg_rtol=1e-12, precond="amg",
+                             extrapolate=2)
+    f = RandomStreamField(seed=3, kmax=4)
+
+    def vals(pts):  # [T, 2, nq] values of f at reference points of every element
+        x = xyz[:, None, 0, :] + (pts[None, :, 0, None] * (xyz[:, None, 1, :] - xyz[:, None, 0, :])
+                                  + pts[None, :, 1, None] * (xyz[:, None, 2, :] - xyz[:, None, 0, :]))
+        u1, u2 = f(x[..., 0], x[..., 1])
+        return np.stack([u1, u2], axis=1)
+
+    U = s.mass_solve(values_to_lib(s, vals))[0]
+    dt = 0.1 / 16 / 4
+    s.reset_history()
+    for _ in range(4):
+        s.rk3_step(U, dt)
+    snap, U_ck = s.history_save(), U.clone()
+    assert snap[1] == (3, 3, 3)
+    its_a = [list(s.rk3_step(U, dt).iterations) for _ in range(3)]
+    s.reset_history()  # a cold step in between must not matter after the restore
+    V = U_ck.clone()
+    s.rk3_step(V, dt)
+    s.history_restore(snap)
+    V = U_ck.clone()
+    its_b = [list(s.rk3_step(V, dt).iterations) for _ in range(3)]
+    _log("history restore", its_a, its_b)
+    assert its_a == its_b
+    assert torch.equal(U, V)
+    with pytest.raises(Exception):
+        s.history_restore((snap[0], (4, 0, 0)))
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_energy_gradient_vs_oracle_and_fd(precond):
     """Gradient of the final kinetic energy w.r.t. U0 through checkpointed RK3 steps."""
     from paper_1808_04669_amd.adjoint import final_energy
     N, k, steps, every = 6, 2, 6, 2
-    orc, s, _, _ = make_pair(N, k, nu=1e-3, order="random", seed=3, cg_rtol=1e-14)
+    orc, s, _, _ = make_pair(N, k, nu=1e-3, order="random", seed=3, cg_rtol=1e-14, precond=precond, extrapolate=2)
     U0o = orc.project(RandomStreamField(seed=0, kmax=3))
     dt = 0.1 / N / k ** 2
     E_o, g_o = energy_and_gradient(orc, U0o, dt, steps, checkpoint_every=every)

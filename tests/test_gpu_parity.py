@@ -119,7 +119,7 @@ def test_projection_reproduces_divergence_free_data():
 
 def test_warm_start_and_determinism():
     """A warm-started solve gives the same velocity; identical runs are bitwise equal."""
-    _, s, _, _ = make_pair(8, 2, oracle=False, cg_rtol=1e-13)
+    _, s, xyz, _ = make_pair(8, 2, oracle=False, cg_rtol=1e-13)
     coef = random_broken_poly(s.T, 2, seed=4)
     F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
     U1, i1 = s.mass_solve(F)
@@ -130,6 +130,26 @@ def test_warm_start_and_determinism():
     U4, i4 = s.mass_solve(F, lam=lam)      # warm start from the solution
     assert i4.iterations < i3.iterations
     assert (U4 - U3).abs().max().item() < 1e-11 * U3.abs().max().item()
+    # the returned multiplier has no component along the constant multiplier (the kernel
+    # of the facet system): in the orthonormal facet basis its coefficients are sqrt|F| on
+    # mode 0; a start with a large constant part does not change the velocity
+    z = _constant_multiplier(s, xyz)
+    assert abs(float(z @ lam.cpu().numpy())) < 1e-12 * lam.norm().item() * np.sqrt(s.E)
+    lam2 = lam + 1e3 * torch.from_numpy(z).to(lam.device)
+    U5, _ = s.mass_solve(F, lam=lam2)
+    assert (U5 - U3).abs().max().item() < 1e-10 * U3.abs().max().item()
+    assert abs(float(z @ lam2.cpu().numpy())) < 1e-12 * lam2.norm().item() * np.sqrt(s.E)
+
+
+def _constant_multiplier(s, xyz):
+    """Unit vector of the constant facet multiplier in the library layout [E][n_f]."""
+    fac = s.mesh.facets()  # [E, 4]: left element, local facet, right element, local facet
+    a = xyz[fac[:, 0], (fac[:, 1] + 1) % 3]
+    b = xyz[fac[:, 0], (fac[:, 1] + 2) % 3]
+    z = np.zeros((s.E, s.n_lambda // s.E))
+    z[:, 0] = np.sqrt(np.linalg.norm(b - a, axis=1))
+    z = z.ravel()
+    return z / np.linalg.norm(z)
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "amg"])
