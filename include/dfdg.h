@@ -246,6 +246,12 @@ int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms_per_launch,
  *   their first slot, the others hold zeros. */
 int dfdg_debug_basis(int k, int npts, const double* pts_host, double* vals_host, double* grads_host);
 int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols_host, double* vals_host);
+/* dfdg_debug_multigrid: the multigrid hierarchy built at context creation (DFDG_AMG):
+ *   *n_levels (0 for other preconditioners) and, for the first min(n_levels, max_levels)
+ *   levels, rows_host[l], nnz_host[l] and the spectral radius estimate of D^{-1} A_l in
+ *   rho_host[l].  The last level is inverted densely. */
+int dfdg_debug_multigrid(const dfdg_ctx* ctx, int max_levels, int* n_levels, int64_t* rows_host,
+                         int64_t* nnz_host, double* rho_host);
 
 #ifdef __cplusplus
 }

@@ -173,35 +173,52 @@ static int aggregate(int n, const std::vector<int>& gptr, const std::vector<int>
   return na;
 }
 
+// In-place inverse of a dense SPD matrix (row-major) by Cholesky; every inner loop runs
+// along contiguous rows.
 static bool dense_spd_inverse(int n, std::vector<double>& A) {
-  std::vector<double> L((size_t)n * n, 0.0);
-  for (int i = 0; i < n; ++i)
+  const size_t N = (size_t)n;
+  std::vector<double> L(N * N, 0.0);
+  for (int i = 0; i < n; ++i) {
+    const double* Li = &L[i * N];
     for (int j = 0; j <= i; ++j) {
-      double s = A[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+      const double* Lj = &L[j * N];
+      double s = A[i * N + j];
+      for (int k = 0; k < j; ++k) s -= Li[k] * Lj[k];
       if (i == j) {
         if (!(s > 0)) return false;
-        L[(size_t)i * n + i] = std::sqrt(s);
+        L[i * N + i] = std::sqrt(s);
       } else {
-        L[(size_t)i * n + j] = s / L[(size_t)j * n + j];
+        L[i * N + j] = s / L[j * N + j];
       }
     }
-  // inverse of L (lower), then A^{-1} = L^{-T} L^{-1}
-  std::vector<double> Li((size_t)n * n, 0.0);
+  }
+  // M = L^{-1}, row by row: row_i(M) = (e_i - sum_{k<i} L_ik row_k(M)) / L_ii
+  std::vector<double> M(N * N, 0.0);
   for (int i = 0; i < n; ++i) {
-    Li[(size_t)i * n + i] = 1.0 / L[(size_t)i * n + i];
-    for (int j = 0; j < i; ++j) {
-      double s = 0;
-      for (int k = j; k < i; ++k) s -= L[(size_t)i * n + k] * Li[(size_t)k * n + j];
-      Li[(size_t)i * n + j] = s / L[(size_t)i * n + i];
+    double* Mi = &M[i * N];
+    Mi[i] = 1.0;
+    for (int k = 0; k < i; ++k) {
+      const double l = L[i * N + k];
+      if (l == 0.0) continue;
+      const double* Mk = &M[k * N];
+      for (int j = 0; j <= k; ++j) Mi[j] -= l * Mk[j];
+    }
+    const double d = 1.0 / L[i * N + i];
+    for (int j = 0; j <= i; ++j) Mi[j] *= d;
+  }
+  // A^{-1} = M^T M = sum_k row_k(M)^T row_k(M)
+  std::fill(A.begin(), A.end(), 0.0);
+  for (int k = 0; k < n; ++k) {
+    const double* Mk = &M[k * N];
+    for (int i = 0; i <= k; ++i) {
+      const double a = Mk[i];
+      if (a == 0.0) continue;
+      double* Ai = &A[i * N];
+      for (int j = 0; j <= i; ++j) Ai[j] += a * Mk[j];
     }
   }
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) {
-      double s = 0;
-      for (int k = std::max(i, j); k < n; ++k) s += Li[(size_t)k * n + i] * Li[(size_t)k * n + j];
-      A[(size_t)i * n + j] = s;
-    }
+    for (int j = 0; j < i; ++j) A[j * N + i] = A[i * N + j];
   return true;
 }
 
@@ -262,7 +279,8 @@ int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<dou
     }
     std::vector<int> agg;
     const int na = aggregate(nn, gptr, gadj, agg);
-    if (na >= nn) break;  // no coarsening possible
+    if (na >= nn) break;                  // no coarsening possible
+    if (2 * na > nn && n <= 4096) break;  // coarsening stalls: invert this level densely
     // tentative prolongator: the near-null vector, normalised per aggregate
     std::vector<double> nrm(na, 0.0);
     for (int r = 0; r < n; ++r) nrm[agg[r / nf]] += B[r] * B[r];

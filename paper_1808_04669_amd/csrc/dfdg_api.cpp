@@ -1103,3 +1103,16 @@ extern "C" int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols, doubl
   std::memcpy(vals, ctx->hs.vals.data(), ctx->hs.vals.size() * sizeof(double));
   return DFDG_OK;
 }
+
+extern "C" int dfdg_debug_multigrid(const dfdg_ctx* ctx, int max_levels, int* n_levels, int64_t* rows,
+                                    int64_t* nnz, double* rho) {
+  if (!ctx || !n_levels || max_levels < 0 || (max_levels > 0 && (!rows || !nnz || !rho))) return DFDG_E_INVALID_ARG;
+  const int L = (int)ctx->H.lv.size();
+  *n_levels = L;
+  for (int l = 0; l < std::min(L, max_levels); ++l) {
+    rows[l] = ctx->H.lv[l].A.n;
+    nnz[l] = ctx->H.lv[l].A.nnz();
+    rho[l] = ctx->H.lv[l].lmax;
+  }
+  return DFDG_OK;
+}

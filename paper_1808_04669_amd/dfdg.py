@@ -93,6 +93,7 @@ _SIGS = {
                                         ctypes.POINTER(ctypes.c_double)]),
     "dfdg_debug_basis": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_facet_matrix": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_debug_multigrid": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P, _P, _P]),
 }
 EXPORTED = tuple(_SIGS)
 

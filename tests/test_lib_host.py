@@ -191,3 +191,43 @@ def test_facet_matrix_equals_oracle_condensation(lib, k, N):
     So_lib = So[np.ix_(idx, idx)] * np.outer(scale.ravel(), scale.ravel())
     assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
     assert np.abs(S - S.T).max() < 1e-13 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("k,N", [(1, 24), (2, 20), (3, 12)])
+def test_multigrid_hierarchy(lib, k, N):
+    """Aggregation coarsens the facet system by at least a factor 2 per level down to a
+    dense coarsest level of at most 1000 rows; the Chebyshev bound rho(D^{-1} S) of the
+    finest level exceeds 1 (the diagonal of an SPD matrix lies inside its spectrum), stays
+    below the Gershgorin bound of the oracle-checked facet matrix and is within 2 % of its
+    spectral radius."""
+    xyz, per = periodic_split_square(N, "morton")
+    rc, m = _mesh(lib, xyz, per)
+    rc, c = _ctx(lib, m, k=k, precond=2)
+    assert rc == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    E, NF = s.E, s.n_f
+    L = ctypes.c_int()
+    rows = np.zeros(16, dtype=np.int64)
+    nnz = np.zeros(16, dtype=np.int64)
+    rho = np.zeros(16)
+    assert lib.dfdg_debug_multigrid(c, 16, ctypes.byref(L), rows.ctypes.data_as(P_), nnz.ctypes.data_as(P_),
+                                    rho.ctypes.data_as(P_)) == 0
+    nl = L.value
+    cols = np.empty((5, E), dtype=np.int32)
+    vals = np.empty((5, NF, NF, E))
+    lib.dfdg_debug_facet_matrix(c, cols.ctypes.data_as(P_), vals.ctypes.data_as(P_))
+    lib.dfdg_ctx_destroy(c)
+    lib.dfdg_mesh_destroy(m)
+    assert nl >= 2 and rows[0] == E * NF
+    assert all(2 * rows[l + 1] <= rows[l] for l in range(nl - 1))
+    assert rows[nl - 1] <= 1000 and all(rows[l] > 1000 for l in range(nl - 1))
+    # Gershgorin bound of D^{-1} S from the BSR blocks
+    S = np.zeros((E * NF, E * NF))
+    for sl in range(5):
+        for F in range(E):
+            S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
+    d = np.diag(S)
+    gersh = (np.abs(S).sum(axis=1) / d).max()
+    assert 1.0 < rho[0] <= gersh * (1 + 1e-12)
+    assert abs(rho[0] - np.abs(np.linalg.eigvals(S / d[:, None])).max()) < 0.02 * rho[0]
