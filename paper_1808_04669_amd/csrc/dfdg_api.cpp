@@ -551,10 +551,12 @@ static int capture_iteration(dfdg_ctx* ctx, int parity, Step step, hipGraphExec_
 template <typename Step>
 static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[2], int* hint,
                     PcgScalars& fin) {
-  int rc = read_scalars(ctx, sc, fin);
-  if (rc) return rc;
+  // the first chunk is enqueued right after the initialisation, without reading the
+  // scalars first (a run that is already over, e.g. for a zero right-hand side, makes those
+  // launches return at once), so the GPU does not wait for a host round trip
+  int rc = DFDG_OK;
   const bool use_graph = ctx->prm.graphs != 0;
-  if (use_graph && fin.done == PCG_RUNNING)
+  if (use_graph)
     for (int j = 0; j < 2; ++j)
       if (!graph[j]) {
         rc = capture_iteration(ctx, j, step, &graph[j]);
@@ -563,6 +565,7 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   const bool amg = ctx->prm.precond == DFDG_AMG;
   // a run of n iterations takes n + 1 launches: the last one finds the stopping test met
   int chunk = *hint > 0 ? *hint + 1 : (amg ? 16 : 64);
+  fin.done = PCG_RUNNING;
   int launched = 0;
   while (fin.done == PCG_RUNNING) {
     for (int c = 0; c < chunk; ++c) {
