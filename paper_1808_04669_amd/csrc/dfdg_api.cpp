@@ -299,7 +299,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   const long G = facet_grid_size((int)E);
   for (PcgBufs* pb : {&ctx->pb, &ctx->pb32, &ctx->pbt}) {
     pb->sc = c.take<PcgScalars>(1);
-    pb->gg = c.take<double>(2 * G);
+    pb->gg = c.take<double>(3 * G);
     pb->rz[0] = c.take<double>(2 * G);
     pb->rz[1] = c.take<double>(2 * G);
     pb->pq = c.take<double>(G);
@@ -654,6 +654,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     PcgScalars o{};
     int rc = read_scalars(ctx, pb.sc, o);
     if (rc) return rc;
+    if (o.zero_rhs) HIPC(launch_fill(ctx->nL, 0.0, x, s));  // right-hand side at rounding level
     int total = 0, nref = 0, st = DFDG_OK;
     const bool fused = amg && ctx->mg.nlev >= 2;
     auto step = [&](int it, hipStream_t sm) -> hipError_t {
@@ -671,7 +672,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       if (e != hipSuccess || !amg) return e;
       return launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[it & 1], pi.sc, sm);
     };
-    while (o.gg > 0 && o.rr > o.tol2) {
+    while (!o.zero_rhs && o.rr > o.tol2) {
       if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
       HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], pi, s));
       if (amg) HIPC((launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], pi.sc, s)));

@@ -555,23 +555,26 @@ __host__ __device__ inline int facet_grid(int E) {
   return g < kMaxFacetGrid ? g : kMaxFacetGrid;
 }
 
-// g_F = q_{L,f_L} + q_{R,f_R}; partials (g,g), (zdef,g).
+// g_F = q_{L,f_L} + q_{R,f_R}; partials (g,g), (zdef,g) and (q_L,q_L) + (q_R,q_R), the size
+// of the element contributions that the sum cancels.
 template <int NF>
 __global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __restrict__ q, double* __restrict__ gv,
                                                    double* __restrict__ part) {
   const int T = g.T;
-  double v[2] = {0, 0};
+  double v[3] = {0, 0, 0};
   for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x) {
     const int a = g.qL[F], b = g.qR[F];
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
-      const double x = q[a + (size_t)m * T] + q[b + (size_t)m * T];
+      const double qa = q[a + (size_t)m * T], qb = q[b + (size_t)m * T];
+      const double x = qa + qb;
       gv[(size_t)F * NF + m] = x;
       v[0] += x * x;
       if (m == 0) v[1] += g.zdef[F] * x;
+      v[2] += qa * qa + qb * qb;
     }
   }
-  block_write_partial<2>(v, part);
+  block_write_partial<3>(v, part);
 }
 
 // (zdef, x_{.,0}) partials, one per block.
@@ -593,22 +596,25 @@ __global__ __launch_bounds__(kBlk) void k_zdeflate(DevGeo g, double* __restrict_
     x[(size_t)F * NF] -= t[0] * g.zdef[F];
 }
 
-// One block: the deflated (g,g) and the PCG stopping threshold.
+// One block: the deflated (g,g) and the PCG stopping threshold.  A right-hand side at the
+// rounding level of the contributions it is summed from (||g|| <= 1e-13 ||q||, e.g. data
+// that is already divergence-free with a continuous normal component) counts as zero: the
+// multiplier is zero up to that rounding.
 __global__ __launch_bounds__(kBlk) void k_finalize_gather(const double* __restrict__ part, int n, PcgScalars* sc,
                                                           double rtol, int maxit) {
-  double t[2];
-  block_sum_partials<2>(part, n, t);
+  double t[3];
+  block_sum_partials<3>(part, n, t);
   if (threadIdx.x == 0) {
     const double gg = t[0] - t[1] * t[1];  // ||g - (z.g) z||^2 with ||z|| = 1
     sc->gg = gg;
     sc->zg = t[1];
     sc->tol2 = rtol * rtol * gg;
     sc->maxit = maxit;
-    sc->zero_rhs = !(gg > 0.0);
+    sc->zero_rhs = !(gg > 1e-26 * t[2]);
     sc->iters = 0;
     sc->it = 1;
     sc->rr = 0;
-    sc->done = !isfinite(gg) ? PCG_NONFINITE : (!(gg > 0.0) ? PCG_CONVERGED : PCG_RUNNING);
+    sc->done = !isfinite(gg) ? PCG_NONFINITE : (sc->zero_rhs ? PCG_CONVERGED : PCG_RUNNING);
   }
 }
 

@@ -8,4 +8,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
-    config.addinivalue_line("markers", "slow: longer CPU oracle runs")
+    config.addinivalue_line("markers", "slow: longer runs (CPU oracle or full-size GPU set-up)")

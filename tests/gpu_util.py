@@ -58,3 +58,17 @@ def broken_residual_on_oracle_basis(orc, s, L_gpu):
         G = s.load_vector(to_dev(s, f)).view(2, P, T)
         out[:, :, a] = (G * Lv).sum(dim=1).T.cpu().numpy()
     return out
+
+
+def project_field(s, xyz, field):
+    """L2 projection (on the GPU, dfdg_project) of a closed-form field u(x, y) -> (u1, u2)
+    sampled at the library's projection points; also returns max |u| at those points."""
+    pts, _ = s.proj_rule()
+    x = xyz[:, None, 0, :] + (pts[None, :, 0, None] * (xyz[:, None, 1, :] - xyz[:, None, 0, :])
+                              + pts[None, :, 1, None] * (xyz[:, None, 2, :] - xyz[:, None, 0, :]))
+    u1, u2 = field(x[..., 0], x[..., 1])  # [T, nq]
+    vmax = float(np.sqrt(u1 ** 2 + u2 ** 2).max())
+    fq = torch.from_numpy(np.ascontiguousarray(np.stack([u1.T, u2.T]))).to(s.device).reshape(-1)
+    U, info = s.project(fq)
+    assert info.status == 0
+    return U, vmax

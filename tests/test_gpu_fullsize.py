@@ -1,0 +1,96 @@
+"""GPU checks at the benchmark sizes, where the oracle cannot follow: properties that hold
+at any size (exactness on constants, dissipation of the upwind and penalty terms, the
+mixed form against the FP64 path, the adjoint gradient against finite differences)."""
+import numpy as np
+import pytest
+import torch
+
+from inputs import RandomStreamField, double_shear_layer
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import make_pair, project_field  # noqa: E402
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def test_constant_field_is_exact_and_steady_at_256():
+    """A constant velocity lies in V^{k,-1}: the projection reproduces it and L vanishes
+    (no gradient, no jumps) at the 256x256 BDM_2 size, with and without viscosity."""
+    for nu in (0.0, 1e-3):
+        _, s, xyz, _ = make_pair(256, 2, nu=nu, oracle=False, cg_rtol=1e-12, precond="amg")
+        U, _ = project_field(s, xyz, lambda x, y: (np.ones_like(x), 2.0 * np.ones_like(y)))
+        pts = np.array([[0.2, 0.3], [0.6, 0.1], [0.1, 0.8]])
+        v = s.eval(U, pts).cpu().numpy()  # [2, P, T]
+        assert np.abs(v[0] - 1.0).max() < 1e-12 and np.abs(v[1] - 2.0).max() < 1e-12
+        L = s.residual(U)
+        _log("nu", nu, "max |L|", L.abs().max().item())
+        # each volume and facet contribution is of size |u|^2 = 5 (orthonormal basis); they
+        # cancel for a constant field
+        assert L.abs().max().item() < 1e-11 * 5.0
+        del s
+
+
+def test_residual_is_dissipative_at_256():
+    """Upwinding dissipates energy (u . L_0(u) <= 0, Sec. 2.2) and the penalty form is
+    non-negative for k = 2 (u . (L_nu - L_0)(u) = -nu B_h(u, u) <= 0), on the projected
+    double shear layer at 256x256."""
+    _, s0, xyz, _ = make_pair(256, 2, nu=0.0, oracle=False, cg_rtol=1e-12, precond="amg")
+    _, s1, _, _ = make_pair(256, 2, nu=1e-3, oracle=False, cg_rtol=1e-12, precond="amg")
+    U, _ = project_field(s0, xyz, double_shear_layer)
+    L0 = s0.residual(U)
+    L1 = s1.residual(U)
+    c = torch.dot(U, L0).item()
+    b = torch.dot(U, L1 - L0).item()
+    scale = U.norm().item() * L0.norm().item()
+    _log("u.L0", c, "u.(L1-L0)", b, "scale", scale)
+    assert c <= 1e-12 * scale and b < 0
+
+
+@pytest.mark.slow
+def test_mixed_step_against_fp64_at_512_bdm3():
+    """One TVD-RK3 step of the mixed form stays within 1e-6 of the FP64 path on the
+    512x512 BDM_3 double shear layer (facet solves to 1e-10), both divergence-free."""
+    out = {}
+    for prec in ("fp64", "mixed"):
+        _, s, xyz, _ = make_pair(512, 3, oracle=False, cg_rtol=1e-10, precond="amg", precision=prec,
+                                 ir_rtol=1e-10, inner_rtol=1e-3, extrapolate=2)
+        U, vmax = project_field(s, xyz, double_shear_layer)
+        dt = 0.1 / 512 / (9 * vmax)
+        info = s.rk3_step(U, dt)
+        assert info.status == 0
+        d = s.diagnostics(U)
+        _log(prec, list(info.iterations), d)
+        assert d["max_div"] < 1e-11 * np.sqrt(d["enstrophy"])
+        out[prec] = U
+        del s
+    err = ((out["mixed"] - out["fp64"]).norm() / out["fp64"].norm()).item()
+    _log("mixed vs fp64", err)
+    assert err < 1e-6
+
+
+def test_adjoint_gradient_vs_finite_differences_at_128():
+    """Gradient of the final kinetic energy after 100 TVD-RK3 steps with checkpoints every
+    10 steps (128x128 BDM_2, nu = 1e-3, random field |k| <= 8, seed 0) against central
+    differences (h = 1e-6) along random divergence-free directions."""
+    from paper_1808_04669_amd.adjoint import final_energy
+    N, k, steps, every = 128, 2, 100, 10
+    _, s, xyz, _ = make_pair(N, k, nu=1e-3, oracle=False, cg_rtol=1e-13, precond="amg", extrapolate=2)
+    U0, vmax = project_field(s, xyz, RandomStreamField(seed=0, kmax=8))
+    dt = 0.1 / N / (k * k * vmax)
+    U0 = U0.requires_grad_(True)
+    E = final_energy(s, U0, dt, steps, checkpoint_every=every)
+    E.backward()
+    g = U0.grad.detach()
+    h = 1e-6
+    for seed in (1, 2, 3):
+        d, _ = project_field(s, xyz, RandomStreamField(seed=seed, kmax=8))
+        d = d / d.norm()
+        with torch.no_grad():
+            fd = (final_energy(s, U0.detach() + h * d, dt, steps, every)
+                  - final_energy(s, U0.detach() - h * d, dt, steps, every)).item() / (2 * h)
+        adj = torch.dot(g, d).item()
+        _log("dir", seed, "adjoint", adj, "fd", fd)
+        assert abs(adj - fd) < 1e-5 * abs(fd) + 1e-8
