@@ -4,18 +4,40 @@
 The forward pass keeps the state and the solver's warm-start history every
 `checkpoint_every` steps (and all stage states of the last segment, which the reverse
 sweep needs first); the backward pass recomputes each other segment from its checkpoint
-with ``dfdg_rk3_step_stages`` (the same solves as the forward pass, keeping the
-stage states of every step of the segment) and runs ``dfdg_rk3_step_vjp_stages`` (the
+with ``dfdg_rk3_step_stages`` (the same solves as the forward pass, keeping the stage
+states of every step of the segment) and runs ``dfdg_rk3_step_vjp_stages`` (the
 hand-written adjoint of the residual and the self-adjoint mass solve) in reverse, so a
 step costs three forward and three adjoint stage solves in the reverse sweep.
+
+With a second solver context (`recompute_solver`: same mesh and parameters, its own HIP
+stream), the recomputation of the next earlier segment runs on that context, from a
+helper thread, while the reverse sweep of the current segment runs on the first one; the
+two streams share the GPU.  Both contexts restore the same checkpointed history, so the
+gradient is the same bit for bit.
 All arithmetic runs in the library's kernels; this module only orders the calls.
 """
+from concurrent.futures import ThreadPoolExecutor
+
 import torch
+
+
+def _recompute(solver, ckpt, dt, n_steps):
+    """States U^{s0..s0+n-1} and stage states of a segment, from its checkpoint."""
+    U_ck, hist = ckpt
+    solver.history_restore(hist)
+    states, stages = [U_ck], []
+    for _ in range(n_steps):
+        u = states[-1].clone()
+        U1, U2 = torch.empty_like(u), torch.empty_like(u)
+        solver.rk3_step_stages(u, dt, U1, U2)
+        states.append(u)
+        stages.append((U1, U2))
+    return states, stages
 
 
 class Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, U0, solver, dt, steps, checkpoint_every):
+    def forward(ctx, U0, solver, dt, steps, checkpoint_every, recompute_solver=None):
         U = U0.detach().clone()
         solver.reset_history()
         ckpts = {0: (U.clone(), solver.history_save())}
@@ -33,6 +55,7 @@ class Rollout(torch.autograd.Function):
                 ckpts[n + 1] = (U.clone(), solver.history_save())
         ctx.solver, ctx.dt, ctx.steps, ctx.every, ctx.ckpts = solver, dt, steps, checkpoint_every, ckpts
         ctx.tail = (last, tail)
+        ctx.recompute = recompute_solver
         return U
 
     @staticmethod
@@ -40,30 +63,52 @@ class Rollout(torch.autograd.Function):
         s, dt, steps, every = ctx.solver, ctx.dt, ctx.steps, ctx.every
         Ubar = Ubar.detach().clone().contiguous()
         s.reset_adjoint_history()
-        for s0 in sorted(ctx.ckpts, reverse=True):
-            s1 = min(s0 + every, steps)
-            # recompute the segment from its checkpoint (state and warm-start history, so
-            # that the solves repeat the forward ones), keeping every step's stage states
-            if s0 == ctx.tail[0]:
-                states, stages = ctx.tail[1]
-            else:
-                U_ck, hist = ctx.ckpts[s0]
-                s.history_restore(hist)
-                states, stages = [U_ck], []
-                for _ in range(s0, s1):
-                    u = states[-1].clone()
-                    U1, U2 = torch.empty_like(u), torch.empty_like(u)
-                    s.rk3_step_stages(u, dt, U1, U2)
-                    states.append(u)
-                    stages.append((U1, U2))
-            for n in range(s1 - 1, s0 - 1, -1):
-                U1, U2 = stages[n - s0]
-                s.rk3_step_vjp_stages(states[n - s0], U1, U2, Ubar, dt)
+        order = sorted(ctx.ckpts, reverse=True)
+        seg_len = {s0: min(s0 + every, steps) - s0 for s0 in order}
+
+        def sweep(s0, states, stages):
+            for n in range(seg_len[s0] - 1, -1, -1):
+                U1, U2 = stages[n]
+                s.rk3_step_vjp_stages(states[n], U1, U2, Ubar, dt)
+
+        r = ctx.recompute
+        if r is None:
+            for s0 in order:
+                if s0 == ctx.tail[0]:
+                    states, stages = ctx.tail[1]
+                else:
+                    states, stages = _recompute(s, ctx.ckpts[s0], dt, seg_len[s0])
+                sweep(s0, states, stages)
+        else:
+            main = s.stream  # where the reverse sweep runs
+
+            def helper(s0):
+                with torch.cuda.stream(r.stream):
+                    states, stages = _recompute(r, ctx.ckpts[s0], dt, seg_len[s0])
+                    done = torch.cuda.Event()
+                    done.record(r.stream)
+                return states, stages, done
+
+            with ThreadPoolExecutor(max_workers=1) as ex:
+                cur = ctx.tail[1] if order[0] == ctx.tail[0] else _recompute(s, ctx.ckpts[order[0]], dt,
+                                                                              seg_len[order[0]])
+                for i, s0 in enumerate(order):
+                    fut = ex.submit(helper, order[i + 1]) if i + 1 < len(order) else None
+                    sweep(s0, *cur)
+                    if fut is not None:
+                        states, stages, done = fut.result()
+                        main.wait_event(done)
+                        for t in states[1:] + [x for pair in stages for x in pair]:
+                            t.record_stream(main)  # made on the helper stream, used on this one
+                        cur = (states, stages)
+            r.reset_history()
         s.reset_history()
-        return Ubar, None, None, None, None
+        return Ubar, None, None, None, None, None
 
 
-def final_energy(solver, U0, dt, steps, checkpoint_every=10):
-    """E = 1/2 ||u_N||^2 (the basis is orthonormal), differentiable w.r.t. U0."""
-    UN = Rollout.apply(U0, solver, dt, steps, checkpoint_every)
+def final_energy(solver, U0, dt, steps, checkpoint_every=10, recompute_solver=None):
+    """E = 1/2 ||u_N||^2 (the basis is orthonormal), differentiable w.r.t. U0.
+    recompute_solver: optional second context (same mesh and parameters, another stream)
+    that recomputes checkpoint segments concurrently with the reverse sweep."""
+    UN = Rollout.apply(U0, solver, dt, steps, checkpoint_every, recompute_solver)
     return 0.5 * (UN * UN).sum()
