@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--precond", default="amg", choices=["jacobi", "block_jacobi", "amg"])
-    ap.add_argument("--extrapolate", type=int, default=2)
+    ap.add_argument("--extrapolate", type=int, default=4)
     ap.add_argument("--order", default="morton")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing and the accuracy check against the oracle")

@@ -63,6 +63,7 @@ enum {
 };
 
 enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
+#define DFDG_HISTORY_DEPTH 5  /* earlier multipliers kept per stage for warm starts */
 enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1, DFDG_AMG = 2 };  /* dfdg_params.precond */
 
 typedef struct dfdg_mesh dfdg_mesh;
@@ -82,7 +83,8 @@ typedef struct {
   double ir_rtol;    /* MIXED: outer FP64 refinement target (relative residual) */
   double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
   int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,
-                        1..2 = polynomial extrapolation of that order in time */
+                        1..4 = polynomial extrapolation of that order in time from the
+                        last extrapolate+1 steps (at most DFDG_HISTORY_DEPTH are kept) */
   int graphs;        /* 1: replay PCG iterations from captured HIP graphs (default);
                         0: launch every kernel individually.  Same results bit for bit. */
   int mg_fp32;       /* DFDG_AMG with DFDG_FP64: 1 = run the V-cycle in FP32 (default; the
@@ -102,6 +104,8 @@ typedef struct {
   int refinements;     /* MIXED: FP64 refinement steps; FP64: 0 */
   double rel_residual; /* final ||g - S lambda|| / ||g|| (FP64 recomputed for MIXED) */
   int status;          /* DFDG_OK, DFDG_E_NOT_CONVERGED, ... */
+  double initial_rel_residual; /* ||g - S lambda_0|| / ||g|| of the start value (0 for a
+                                  right-hand side at rounding level) */
 } dfdg_solve_info;
 
 typedef struct {
@@ -109,6 +113,7 @@ typedef struct {
   int max_refinements;
   double max_rel_residual;
   int status;
+  double initial_rel_residual[3]; /* of the three stage solves (warm-start quality) */
 } dfdg_step_info;
 
 typedef struct {
@@ -186,12 +191,17 @@ int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U_io_dev, double dt, double* U1_
 int dfdg_reset_history(dfdg_ctx* ctx);
 /* Forget the warm-start history of the adjoint stage solves (start of a reverse sweep). */
 int dfdg_reset_adjoint_history(dfdg_ctx* ctx);
-/* dfdg_history_save: copies the forward warm-start history (per stage, the multipliers
- *   of up to three earlier steps, newest first) into hist_dev ([3 stages][3][n_lambda],
- *   caller-owned device memory; unused entries are left alone) and the number of valid
- *   entries per stage into counts_host[3].  Asynchronous on the context stream.
- * dfdg_history_restore: the inverse (counts in 0..3), e.g. at a checkpoint before a
- *   trajectory segment is recomputed, which then repeats the original solves exactly. */
+/* dfdg_history_bytes: size of the blob of dfdg_history_save for this context,
+ *   3 * DFDG_HISTORY_DEPTH * n_lambda doubles.
+ * dfdg_history_save: copies the forward warm-start history into hist_dev (caller-owned
+ *   device memory of dfdg_history_bytes): per stage, the multipliers of up to
+ *   DFDG_HISTORY_DEPTH earlier steps, newest first ([3][DFDG_HISTORY_DEPTH][n_lambda];
+ *   unused entries are left alone), and the number of valid entries per stage into
+ *   counts_host[3].  Asynchronous on the context stream.
+ * dfdg_history_restore: the inverse (counts in 0..DFDG_HISTORY_DEPTH), e.g. at a
+ *   checkpoint before a trajectory segment is recomputed, which then repeats the
+ *   original solves exactly. */
+int dfdg_history_bytes(const dfdg_ctx* ctx, size_t* bytes);
 int dfdg_history_save(dfdg_ctx* ctx, double* hist_dev, int* counts_host);
 int dfdg_history_restore(dfdg_ctx* ctx, const double* hist_dev, const int* counts_host);
 

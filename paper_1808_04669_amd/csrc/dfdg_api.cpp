@@ -35,7 +35,7 @@ struct dfdg_ctx {
   DevBsr A{};
   // work buffers
   double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
-         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][3] = {}, *evaltab = nullptr,
+         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][kHistDepth] = {}, *evaltab = nullptr,
          *partials = nullptr, *diagres = nullptr, *r64 = nullptr;
   float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *r32b = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
         *Sp32 = nullptr;
@@ -148,7 +148,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
     if (!(p->ir_rtol > 0 && p->ir_rtol < 1)) { e = "ir_rtol must be in (0,1)"; return -1; }
     if (!(p->inner_rtol > 0 && p->inner_rtol < 1)) { e = "inner_rtol must be in (0,1)"; return -1; }
   }
-  if (p->extrapolate < 0 || p->extrapolate > 2) { e = "extrapolate must be 0, 1 or 2"; return -1; }
+  if (p->extrapolate < 0 || p->extrapolate >= kHistDepth) { e = "extrapolate must be in 0..4"; return -1; }
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   return 0;
@@ -291,7 +291,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->Sp = c.take<double>(nL);
   ctx->Ustage = c.take<double>(nU);
   for (int s = 0; s < 6; ++s)
-    for (int j = 0; j < 3; ++j) ctx->hist[s][j] = c.take<double>(nL);
+    for (int j = 0; j < kHistDepth; ++j) ctx->hist[s][j] = c.take<double>(nL);
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
   ctx->partials = c.take<double>(4 * maxblk);
@@ -643,6 +643,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     inf.iterations = fin.iters;
     inf.refinements = 0;
     inf.rel_residual = fin.gg > 0 ? std::sqrt(std::max(fin.rr, 0.0) / fin.gg) : 0.0;
+    inf.initial_rel_residual = (fin.gg > 0 && !fin.zero_rhs) ? std::sqrt(std::max(fin.rr0, 0.0) / fin.gg) : 0.0;
     inf.status = status_of(fin.done);
   } else {
     // mixed: FP64 refinement around FP32 inner PCG (S in FP32), FP64 residuals
@@ -655,6 +656,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     int rc = read_scalars(ctx, pb.sc, o);
     if (rc) return rc;
     if (o.zero_rhs) HIPC(launch_fill(ctx->nL, 0.0, x, s));  // right-hand side at rounding level
+    inf.initial_rel_residual = (o.gg > 0 && !o.zero_rhs) ? std::sqrt(std::max(o.rr, 0.0) / o.gg) : 0.0;
     int total = 0, nref = 0, st = DFDG_OK;
     const bool fused = amg && ctx->mg.nlev >= 2;
     auto step = [&](int it, hipStream_t sm) -> hipError_t {
@@ -778,14 +780,21 @@ extern "C" int dfdg_reset_adjoint_history(dfdg_ctx* ctx) {
   return DFDG_OK;
 }
 
+extern "C" int dfdg_history_bytes(const dfdg_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return DFDG_E_INVALID_ARG;
+  *bytes = (size_t)3 * kHistDepth * ctx->nL * sizeof(double);
+  return DFDG_OK;
+}
+
+// Blob layout: [3 stages][kHistDepth][nL], newest first.
 extern "C" int dfdg_history_save(dfdg_ctx* ctx, double* hist, int* counts) {
   NEED_BOUND(ctx);
   if (!hist || !counts) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  const size_t nb = ctx->nL * sizeof(double);
+  const size_t nL = ctx->nL, nb = nL * sizeof(double);
   for (int st = 0; st < 3; ++st) {
     counts[st] = ctx->hist_count[st];
     for (int j = 0; j < ctx->hist_count[st]; ++j)
-      HIPC(hipMemcpyAsync(hist + (size_t)(3 * st + j) * ctx->nL, ctx->hist[st][j], nb, hipMemcpyDeviceToDevice,
+      HIPC(hipMemcpyAsync(hist + (size_t)(kHistDepth * st + j) * nL, ctx->hist[st][j], nb, hipMemcpyDeviceToDevice,
                           ctx->stream));
   }
   return DFDG_OK;
@@ -795,11 +804,11 @@ extern "C" int dfdg_history_restore(dfdg_ctx* ctx, const double* hist, const int
   NEED_BOUND(ctx);
   if (!hist || !counts) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   for (int st = 0; st < 3; ++st)
-    if (counts[st] < 0 || counts[st] > 3) return fail(ctx, DFDG_E_INVALID_ARG, "history counts must be in 0..3");
-  const size_t nb = ctx->nL * sizeof(double);
+    if (counts[st] < 0 || counts[st] > kHistDepth) return fail(ctx, DFDG_E_INVALID_ARG, "history counts must be in 0..5");
+  const size_t nL = ctx->nL, nb = nL * sizeof(double);
   for (int st = 0; st < 3; ++st) {
     for (int j = 0; j < counts[st]; ++j)
-      HIPC(hipMemcpyAsync(ctx->hist[st][j], hist + (size_t)(3 * st + j) * ctx->nL, nb, hipMemcpyDeviceToDevice,
+      HIPC(hipMemcpyAsync(ctx->hist[st][j], hist + (size_t)(kHistDepth * st + j) * nL, nb, hipMemcpyDeviceToDevice,
                           ctx->stream));
     ctx->hist_count[st] = counts[st];
   }
@@ -812,17 +821,17 @@ static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
   *cold = (n == 0);
   if (n == 0) return DFDG_OK;
   const int order = std::min(ctx->prm.extrapolate, n - 1);
-  HIPC(launch_extrapolate(ctx->nL, order, ctx->hist[s][0], ctx->hist[s][1], ctx->hist[s][2], ctx->lamw,
-                          ctx->stream));
+  HistPtrs h;
+  for (int j = 0; j < kHistDepth; ++j) h.p[j] = ctx->hist[s][j];
+  HIPC(launch_extrapolate(ctx->nL, order, h, ctx->lamw, ctx->stream));
   return DFDG_OK;
 }
 static void stage_push(dfdg_ctx* ctx, int s) {
-  double* old = ctx->hist[s][2];
-  ctx->hist[s][2] = ctx->hist[s][1];
-  ctx->hist[s][1] = ctx->hist[s][0];
+  double* old = ctx->hist[s][kHistDepth - 1];
+  for (int j = kHistDepth - 1; j > 0; --j) ctx->hist[s][j] = ctx->hist[s][j - 1];
   ctx->hist[s][0] = ctx->lamw;
   ctx->lamw = old;
-  ctx->hist_count[s] = std::min(ctx->hist_count[s] + 1, 3);
+  ctx->hist_count[s] = std::min(ctx->hist_count[s] + 1, kHistDepth);
 }
 
 // One stage: out = a Un + b (Us + dt M^{-1} L(Us)).
@@ -852,6 +861,7 @@ static int rk3_core(dfdg_ctx* ctx, double* U, double dt, double* U1, double* U2,
   st.status = DFDG_OK;
   for (int s = 0; s < 3; ++s) {
     st.iterations[s] = si[s].iterations;
+    st.initial_rel_residual[s] = si[s].initial_rel_residual;
     st.max_refinements = std::max(st.max_refinements, si[s].refinements);
     st.max_rel_residual = std::max(st.max_rel_residual, si[s].rel_residual);
     if (si[s].status != DFDG_OK) st.status = si[s].status;

@@ -125,8 +125,11 @@ hipError_t launch_diagnostics(int K, const DevGeo& g, const DevTabs& tb, const d
                               double* res, hipStream_t s);
 // Linear combination y = a x + b y on n doubles.
 hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
-hipError_t launch_extrapolate(long n, int order, const double* h0, const double* h1, const double* h2, double* out,
-                              hipStream_t s);
+// Warm-start history: up to kHistDepth earlier multipliers, p[0] the newest.
+constexpr int kHistDepth = 5;
+struct HistPtrs { const double* p[kHistDepth]; };
+// out = extrapolation of order `order` (< kHistDepth) in time from p[0..order].
+hipError_t launch_extrapolate(long n, int order, const HistPtrs& h, double* out, hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
 
 }  // namespace dfdg

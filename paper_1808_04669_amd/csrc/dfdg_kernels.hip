@@ -1329,14 +1329,16 @@ __global__ void k_fill(long n, double v, double* __restrict__ y) {
   if (i < n) y[i] = v;
 }
 // Polynomial extrapolation in time from h0 (newest), h1, h2 (oldest), equal spacing.
-__global__ void k_extrapolate(long n, int order, const double* __restrict__ h0, const double* __restrict__ h1,
-                              const double* __restrict__ h2, double* __restrict__ out) {
+// Lagrange extrapolation to the next equally spaced time from the last order+1 values
+// (h.p[0] newest): coefficients (-1)^j C(order+1, j+1).
+__global__ void k_extrapolate(long n, int order, HistPtrs h, double* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double v;
-  if (order >= 2) v = 3.0 * h0[i] - 3.0 * h1[i] + h2[i];
-  else if (order == 1) v = 2.0 * h0[i] - h1[i];
-  else v = h0[i];
+  double v = 0, c = order + 1;  // C(order+1, 1)
+  for (int j = 0; j <= order; ++j) {
+    v += ((j & 1) ? -c : c) * h.p[j][i];
+    c = c * (order - j) / (j + 2);  // C(order+1, j+2)
+  }
   out[i] = v;
 }
 
@@ -1665,9 +1667,9 @@ hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, v, y);
   return hipGetLastError();
 }
-hipError_t launch_extrapolate(long n, int order, const double* h0, const double* h1, const double* h2, double* out,
-                              hipStream_t s) {
-  hipLaunchKernelGGL(k_extrapolate, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, order, h0, h1, h2, out);
+hipError_t launch_extrapolate(long n, int order, const HistPtrs& h, double* out, hipStream_t s) {
+  if (order < 0 || order >= kHistDepth) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_extrapolate, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, order, h, out);
   return hipGetLastError();
 }
 

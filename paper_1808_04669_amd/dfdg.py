@@ -42,12 +42,14 @@ class Sizes(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("refinements", ctypes.c_int),
-                ("rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+                ("rel_residual", ctypes.c_double), ("status", ctypes.c_int),
+                ("initial_rel_residual", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int * 3), ("max_refinements", ctypes.c_int),
-                ("max_rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+                ("max_rel_residual", ctypes.c_double), ("status", ctypes.c_int),
+                ("initial_rel_residual", ctypes.c_double * 3)]
 
 
 class Diag(ctypes.Structure):
@@ -82,6 +84,7 @@ _SIGS = {
     "dfdg_rk3_step_stages": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(StepInfo)]),
     "dfdg_reset_history": (ctypes.c_int, [_P]),
     "dfdg_reset_adjoint_history": (ctypes.c_int, [_P]),
+    "dfdg_history_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
     "dfdg_history_save": (ctypes.c_int, [_P, _P, _P]),
     "dfdg_history_restore": (ctypes.c_int, [_P, _P, _P]),
     "dfdg_dg_residual_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -262,7 +265,9 @@ class Solver:
 
     def history_save(self):
         """Snapshot of the forward warm-start history: (device tensor, counts)."""
-        buf = torch.empty(9 * self.n_lambda, dtype=torch.float64, device=self.device)
+        nb = ctypes.c_size_t()
+        self._check(self._lib.dfdg_history_bytes(self._h, ctypes.byref(nb)))
+        buf = torch.empty(nb.value // 8, dtype=torch.float64, device=self.device)
         counts = (ctypes.c_int * 3)()
         self._check(self._lib.dfdg_history_save(self._h, _ptr(buf), counts))
         return buf, tuple(counts)
@@ -270,7 +275,7 @@ class Solver:
     def history_restore(self, snap):
         buf, counts = snap
         c = (ctypes.c_int * 3)(*counts)
-        self._check(self._lib.dfdg_history_restore(self._h, self._vec(buf, 9 * self.n_lambda, "history"), c))
+        self._check(self._lib.dfdg_history_restore(self._h, self._vec(buf, buf.numel(), "history"), c))
 
     def residual_vjp(self, U, Lbar, Ubar=None):
         Ubar = self.new_vector() if Ubar is None else Ubar

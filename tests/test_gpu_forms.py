@@ -164,7 +164,7 @@ def test_history_restore_repeats_the_trajectory_bitwise():
     for _ in range(4):
         s.rk3_step(U, dt)
     snap, U_ck = s.history_save(), U.clone()
-    assert snap[1] == (3, 3, 3)
+    assert snap[1] == (4, 4, 4)
     its_a = [list(s.rk3_step(U, dt).iterations) for _ in range(3)]
     s.reset_history()  # a cold step in between must not matter after the restore
     V = U_ck.clone()
@@ -176,7 +176,7 @@ def test_history_restore_repeats_the_trajectory_bitwise():
     assert its_a == its_b
     assert torch.equal(U, V)
     with pytest.raises(Exception):
-        s.history_restore((snap[0], (4, 0, 0)))
+        s.history_restore((snap[0], (6, 0, 0)))
 
 
 def test_pipelined_reverse_sweep_equals_sequential():

@@ -99,7 +99,7 @@ def test_param_validation_and_unbound_calls(lib):
     xyz, per = periodic_split_square(2)
     rc, m = _mesh(lib, xyz, per)
     for kw in [dict(k=0), dict(k=4), dict(nu=-1.0), dict(alpha=0.0), dict(precision=7),
-               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=3), dict(graphs=2), dict(mg_fp32=3)]:
+               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=5), dict(extrapolate=-1), dict(graphs=2), dict(mg_fp32=3)]:
         assert _ctx(lib, m, **kw)[0] == -1, kw
     rc, c = _ctx(lib, m, k=2)
     assert rc == 0
@@ -231,3 +231,18 @@ def test_multigrid_hierarchy(lib, k, N):
     gersh = (np.abs(S).sum(axis=1) / d).max()
     assert 1.0 < rho[0] <= gersh * (1 + 1e-12)
     assert abs(rho[0] - np.abs(np.linalg.eigvals(S / d[:, None])).max()) < 0.02 * rho[0]
+
+
+def test_binding_covers_the_entry_points():
+    """Every hot-path entry point of the C ABI has its method on the Python binding."""
+    methods = {"dfdg_project": "project", "dfdg_load_vector": "load_vector", "dfdg_dg_residual": "residual",
+               "dfdg_hdiv_mass_solve": "mass_solve", "dfdg_rk3_step": "rk3_step",
+               "dfdg_rk3_step_stages": "rk3_step_stages", "dfdg_reset_history": "reset_history",
+               "dfdg_reset_adjoint_history": "reset_adjoint_history", "dfdg_history_save": "history_save",
+               "dfdg_history_restore": "history_restore", "dfdg_dg_residual_vjp": "residual_vjp",
+               "dfdg_rk3_step_vjp": "rk3_step_vjp", "dfdg_rk3_step_vjp_stages": "rk3_step_vjp_stages",
+               "dfdg_diagnostics": "diagnostics", "dfdg_eval": "eval", "dfdg_time_kernel": "time_kernel",
+               "dfdg_proj_rule": "proj_rule"}
+    for sym, meth in methods.items():
+        assert sym in lib_mod.EXPORTED, sym
+        assert callable(getattr(lib_mod.Solver, meth, None)), meth
