@@ -300,6 +300,39 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
     return -2;
   }
   m.E = (int)m.fL.size();
+  // Number the facets along a Morton curve of their midpoints (modulo the period), so that
+  // the facet system and the multigrid hierarchy keep neighbours close in memory whatever
+  // the element numbering of the caller.
+  {
+    const int E = m.E;
+    std::vector<uint64_t> key(E);
+    for (int F = 0; F < E; ++F) {
+      const int t = m.fL[F], f = m.fLloc[F];
+      const double* a = &m.xyz[6 * (size_t)t + 2 * ((f + 1) % 3)];
+      const double* b = &m.xyz[6 * (size_t)t + 2 * ((f + 2) % 3)];
+      uint32_t q[2];
+      for (int d = 0; d < 2; ++d) {
+        double mid = 0.5 * (a[d] + b[d]) / period[d];
+        mid -= std::floor(mid);
+        q[d] = (uint32_t)std::min(65535.0, std::floor(mid * 65536.0));
+      }
+      uint64_t k = 0;
+      for (int bit = 15; bit >= 0; --bit) k = (k << 2) | (((q[1] >> bit) & 1u) << 1) | ((q[0] >> bit) & 1u);
+      key[F] = (k << 32) | (uint32_t)F;  // ties keep the first-occurrence order
+    }
+    std::vector<int> order(E);
+    for (int F = 0; F < E; ++F) order[F] = F;
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return key[x] < key[y]; });
+    std::vector<int> newid(E);
+    for (int i = 0; i < E; ++i) newid[order[i]] = i;
+    auto perm = [&](auto& v) {
+      auto w = v;
+      for (int i = 0; i < E; ++i) w[i] = v[order[i]];
+      v.swap(w);
+    };
+    perm(m.fL); perm(m.fLloc); perm(m.fR); perm(m.fRloc); perm(m.frev);
+    for (int& F : m.efacet) F = newid[F];
+  }
   return 0;
 }
 
