@@ -256,6 +256,11 @@ int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms_per_launch,
  *   their first slot, the others hold zeros. */
 int dfdg_debug_basis(int k, int npts, const double* pts_host, double* vals_host, double* grads_host);
 int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols_host, double* vals_host);
+/* dfdg_debug_residual_rule: the volume quadrature rule of the residual for degree k on the
+ *   reference triangle {xi, eta >= 0, xi + eta <= 1} (exact for total degree 3k-1, weights
+ *   summing to the area 1/2): *npts receives the number of points; pts_host[npts][2] and
+ *   w_host[npts] (each may be NULL) receive the points and weights. */
+int dfdg_debug_residual_rule(int k, int* npts, double* pts_host, double* w_host);
 /* dfdg_debug_multigrid: the multigrid hierarchy built at context creation (DFDG_AMG):
  *   *n_levels (0 for other preconditioners) and, for the first min(n_levels, max_levels)
  *   levels, rows_host[l], nnz_host[l] and the spectral radius estimate of D^{-1} A_l in

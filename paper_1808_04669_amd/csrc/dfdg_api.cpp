@@ -1075,7 +1075,9 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
     switch (which) {
       case 0: b = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0 + 4.0 * NF * 8.0); break;       // S, cols, z, p_old, p_new, Sp
       case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
-      case 2: b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (3 * 4.0 + 4 * 8.0)); break;         // U in, L out, geometry
+      case 2:  // U in, L out, Jinv + detJ; per facet nbr, code, nx, ny, |F| (and sigma if nu != 0)
+        b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (2 * 4.0 + (ctx->prm.nu != 0.0 ? 4 : 3) * 8.0));
+        break;
       case 4: {
         // finest level: 4 BSR sweeps + 17 vector passes; transfers and coarse levels:
         // every CSR entry (8-byte value, 4-byte column) once per use, vectors once
@@ -1108,6 +1110,16 @@ extern "C" int dfdg_debug_basis(int k, int npts, const double* pts, double* vals
     dubiner(k, pts[2 * p], pts[2 * p + 1], vals + (size_t)p * P, g.data());
     if (grads) std::memcpy(grads + (size_t)p * 2 * P, g.data(), 2 * P * sizeof(double));
   }
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_residual_rule(int k, int* npts, double* pts, double* w) {
+  if (k < 1 || k > kMaxK || !npts) return DFDG_E_INVALID_ARG;
+  std::vector<double> q, qw;
+  residual_volume_rule(k, q, qw);
+  *npts = (int)qw.size();
+  if (pts) std::memcpy(pts, q.data(), q.size() * sizeof(double));
+  if (w) std::memcpy(w, qw.data(), qw.size() * sizeof(double));
   return DFDG_OK;
 }
 

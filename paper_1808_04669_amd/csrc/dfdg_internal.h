@@ -22,8 +22,9 @@ __host__ __device__ constexpr int triNu(int p) { return (p + 2) / 2; }
 __host__ __device__ constexpr int triNv(int p) { return (p + 3) / 2; }
 __host__ __device__ constexpr int triN(int p) { return triNu(p) * triNv(p); }
 // Residual rules: volume exact for degree 3K-1 ((u x u) : grad v), facet Gauss-Legendre
-// exact for degree 3K (u.n u.v on the facet).
-__host__ __device__ constexpr int nQV(int K) { return triN(3 * K - 1); }
+// exact for degree 3K (u.n u.v on the facet).  The volume rule is a fully symmetric one
+// for K = 1 (3 points, degree 2) and K = 2 (7 points, degree 5), else the collapsed rule.
+__host__ __device__ constexpr int nQV(int K) { return K == 1 ? 3 : K == 2 ? 7 : triN(3 * K - 1); }
 __host__ __device__ constexpr int nQF(int K) { return (3 * K + 2) / 2; }
 // Projection rule (initial data): exact for degree 2K+4.
 __host__ __device__ constexpr int projDeg(int K) { return 2 * K + 4; }
@@ -46,6 +47,8 @@ struct RefTables {
 };
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
 void triangle_rule(int degree, std::vector<double>& pts, std::vector<double>& w);
+// Volume rule of the residual for degree K (nQV(K) points, exact for degree 3K-1).
+void residual_volume_rule(int K, std::vector<double>& pts, std::vector<double>& w);
 void dubiner(int K, double xi, double eta, double* vals, double* grads /*[2][P] or null*/);
 double legendre01_orthonormal(int m, double s);
 void build_ref_tables(int K, RefTables& t);

@@ -179,7 +179,10 @@ __device__ inline void stage_tabs(ResTabs<K>& s, const DevTabs& tb) {
 // du = u_own - u_nbr, the facet contributes to the own test function v
 //     -(un u_up - nu {grad u} n + nu sigma du) . v  +  (nu/2) (du (x) n) : grad v
 // (upwind convection, consistency, penalty, symmetry terms of eqs. (adv), (viscous)).
-template <int K, typename R>
+// VISC = false is the instantiation for nu = 0 (the Euler equations): the viscous terms
+// vanish identically and the gradients of u, the neighbour's inverse Jacobian and the
+// penalty are neither read nor evaluated.
+template <int K, typename R, bool VISC>
 __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const double* __restrict__ U,
                                                     R* __restrict__ Lout, double nu_d) {
   constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
@@ -212,8 +215,10 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
 #pragma unroll
       for (int i = 0; i < P; ++i) {
         a += u[c][i] * (R)s.Vv[q][i];
-        b0 += u[c][i] * (R)s.Gv[q][0][i];
-        b1 += u[c][i] * (R)s.Gv[q][1][i];
+        if constexpr (VISC) {
+          b0 += u[c][i] * (R)s.Gv[q][0][i];
+          b1 += u[c][i] * (R)s.Gv[q][1][i];
+        }
       }
       uq[c] = a * isq;
       gr[c][0] = b0;
@@ -224,7 +229,10 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
     for (int c = 0; c < 2; ++c) {
       R fl[2];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fl[j] = uq[c] * uq[j] - nu * isq * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j]);
+      for (int j = 0; j < 2; ++j) {
+        fl[j] = uq[c] * uq[j];
+        if constexpr (VISC) fl[j] -= nu * isq * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j]);
+      }
 #pragma unroll
       for (int a = 0; a < 2; ++a) Gt[c][a] = fl[0] * Ji[a][0] + fl[1] * Ji[a][1];
     }
@@ -245,39 +253,44 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
     const bool rev = (code >> 2) & 1;
     const R n0 = (R)g.nx[idx], n1 = (R)g.ny[idx];
     const R len = (R)g.flen[idx];
-    const R sig = (R)g.sig[idx];
     R v[2][P];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int i = 0; i < P; ++i) v[c][i] = (R)U[(size_t)(c * P + i) * T + nb];
-    R Jn[2][2];
-    load_Jinv(g, nb, Jn);
     const R isqn = (R)(1.0 / sqrt(g.detJ[nb]));
-    R nJ[2];
+    R Jn[2][2] = {}, nJ[2] = {}, sig = 0;
+    if constexpr (VISC) {
+      sig = (R)g.sig[idx];
+      load_Jinv(g, nb, Jn);
 #pragma unroll
-    for (int a = 0; a < 2; ++a) nJ[a] = n0 * Ji[a][0] + n1 * Ji[a][1];
+      for (int a = 0; a < 2; ++a) nJ[a] = n0 * Ji[a][0] + n1 * Ji[a][1];
+    }
     for (int r = 0; r < NQF; ++r) {
       const int rn = rev ? NQF - 1 - r : r;
-      R uo[2], un[2], go[2][2], gn[2][2];
+      R uo[2], un[2], go[2][2] = {}, gn[2][2] = {};
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         R a = 0, b0 = 0, b1 = 0, an = 0, bn0 = 0, bn1 = 0;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
           a += u[c][i] * (R)s.Vf[f][r][i];
-          b0 += u[c][i] * (R)s.Gf[f][r][0][i];
-          b1 += u[c][i] * (R)s.Gf[f][r][1][i];
           an += v[c][i] * (R)s.Vf[fn][rn][i];
-          bn0 += v[c][i] * (R)s.Gf[fn][rn][0][i];
-          bn1 += v[c][i] * (R)s.Gf[fn][rn][1][i];
+          if constexpr (VISC) {
+            b0 += u[c][i] * (R)s.Gf[f][r][0][i];
+            b1 += u[c][i] * (R)s.Gf[f][r][1][i];
+            bn0 += v[c][i] * (R)s.Gf[fn][rn][0][i];
+            bn1 += v[c][i] * (R)s.Gf[fn][rn][1][i];
+          }
         }
         uo[c] = a * isq;
         un[c] = an * isqn;
+        if constexpr (VISC) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          go[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
-          gn[c][j] = isqn * (bn0 * Jn[0][j] + bn1 * Jn[1][j]);
+          for (int j = 0; j < 2; ++j) {
+            go[c][j] = isq * (b0 * Ji[0][j] + b1 * Ji[1][j]);
+            gn[c][j] = isqn * (bn0 * Jn[0][j] + bn1 * Jn[1][j]);
+          }
         }
       }
       const R unrm = (R)0.5 * ((uo[0] + un[0]) * n0 + (uo[1] + un[1]) * n1);
@@ -287,16 +300,23 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
       for (int c = 0; c < 2; ++c) {
         const R up = own_up ? uo[c] : un[c];
         du[c] = uo[c] - un[c];
-        const R avgn = (R)0.5 * ((go[c][0] + gn[c][0]) * n0 + (go[c][1] + gn[c][1]) * n1);
-        Qv[c] = unrm * up - nu * avgn + nu * sig * du[c];
+        Qv[c] = unrm * up;
+        if constexpr (VISC) {
+          const R avgn = (R)0.5 * ((go[c][0] + gn[c][0]) * n0 + (go[c][1] + gn[c][1]) * n1);
+          Qv[c] = Qv[c] - nu * avgn + nu * sig * du[c];
+        }
       }
       const R w = (R)s.Wf[r] * len * isq;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         const R h = (R)0.5 * nu * du[c];
 #pragma unroll
-        for (int i = 0; i < P; ++i)
-          acc[c][i] += w * (-Qv[c] * (R)s.Vf[f][r][i] + h * (nJ[0] * (R)s.Gf[f][r][0][i] + nJ[1] * (R)s.Gf[f][r][1][i]));
+        for (int i = 0; i < P; ++i) {
+          if constexpr (VISC)
+            acc[c][i] += w * (-Qv[c] * (R)s.Vf[f][r][i] + h * (nJ[0] * (R)s.Gf[f][r][0][i] + nJ[1] * (R)s.Gf[f][r][1][i]));
+          else
+            acc[c][i] -= w * (Qv[c] * (R)s.Vf[f][r][i]);
+        }
       }
     }
   }
@@ -1371,8 +1391,14 @@ void set_dispatch_events(hipEvent_t start, hipEvent_t stop) {
 hipError_t launch_residual(int K, bool fp32, const DevGeo& g, const DevTabs& tb, const double* U, void* L,
                            double nu, hipStream_t s) {
   DFDG_DISPATCH_K(K, {
-    if (fp32) DFDG_LAUNCH_TIMED((k_residual<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (float*)L, nu);
-    else DFDG_LAUNCH_TIMED((k_residual<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U, (double*)L, nu);
+    const dim3 grid(nblk(g.T, kEBlk)), blk(kEBlk);
+    if (nu != 0.0) {
+      if (fp32) DFDG_LAUNCH_TIMED((k_residual<KK, float, true>), grid, blk, 0, s, g, tb, U, (float*)L, nu);
+      else DFDG_LAUNCH_TIMED((k_residual<KK, double, true>), grid, blk, 0, s, g, tb, U, (double*)L, nu);
+    } else {
+      if (fp32) DFDG_LAUNCH_TIMED((k_residual<KK, float, false>), grid, blk, 0, s, g, tb, U, (float*)L, nu);
+      else DFDG_LAUNCH_TIMED((k_residual<KK, double, false>), grid, blk, 0, s, g, tb, U, (double*)L, nu);
+    }
   });
   return hipGetLastError();
 }

@@ -75,6 +75,39 @@ void triangle_rule(int p, std::vector<double>& pts, std::vector<double>& w) {
     }
 }
 
+// Fully symmetric rules with fewer points than the collapsed ones, in barycentric orbits
+// (weights relative to the area, scaled by 1/2 below):
+//   degree 2: the three points (2/3, 1/6, 1/6) and permutations, weight 1/3 each;
+//   degree 5 (Radon's seven-point rule): the centroid, weight 9/40, and the orbits
+//     (1 - 2a, a, a) for a = (6 -+ sqrt 15)/21, weights (155 -+ sqrt 15)/1200.
+void residual_volume_rule(int K, std::vector<double>& pts, std::vector<double>& w) {
+  if (K > 2) {
+    triangle_rule(3 * K - 1, pts, w);
+    return;
+  }
+  pts.clear();
+  w.clear();
+  auto orbit3 = [&](double a, double wt) {
+    const double b = 1.0 - 2.0 * a;
+    const double xy[3][2] = {{a, a}, {b, a}, {a, b}};
+    for (const auto& p : xy) {
+      pts.push_back(p[0]);
+      pts.push_back(p[1]);
+      w.push_back(0.5 * wt);
+    }
+  };
+  if (K == 1) {
+    orbit3(1.0 / 6.0, 1.0 / 3.0);
+    return;
+  }
+  const double r15 = std::sqrt(15.0);
+  pts.push_back(1.0 / 3.0);
+  pts.push_back(1.0 / 3.0);
+  w.push_back(0.5 * 9.0 / 40.0);
+  orbit3((6.0 - r15) / 21.0, (155.0 - r15) / 1200.0);
+  orbit3((6.0 + r15) / 21.0, (155.0 + r15) / 1200.0);
+}
+
 // ---------------------------------------------------------------------------------------
 // Orthonormal Dubiner basis of P^K on the reference triangle
 // ---------------------------------------------------------------------------------------
@@ -158,7 +191,7 @@ void build_ref_tables(int K, RefTables& t) {
   t.NP = nPp(K);
   t.NF = nF(K);
   const int P = t.P;
-  triangle_rule(3 * K - 1, t.vq, t.vw);
+  residual_volume_rule(K, t.vq, t.vw);
   gauss_legendre01(nQF(K), t.fs, t.fw);
   triangle_rule(projDeg(K), t.pq, t.pw);
   t.nqv = (int)t.vw.size();

@@ -95,6 +95,7 @@ _SIGS = {
     "dfdg_time_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_double)]),
     "dfdg_debug_basis": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
+    "dfdg_debug_residual_rule": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_facet_matrix": (ctypes.c_int, [_P, _P, _P]),
     "dfdg_debug_multigrid": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P, _P, _P]),
 }

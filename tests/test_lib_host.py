@@ -154,6 +154,32 @@ def test_reference_basis_orthonormal(lib, k):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
+def test_residual_volume_rule_exact(lib, k):
+    """The residual's volume rule integrates every monomial xi^a eta^b of total degree
+    <= 3k-1 exactly over the reference triangle (closed form a! b! / (a+b+2)!), has its
+    points inside the triangle and positive weights, and has 3 / 7 points for k = 1 / 2."""
+    from math import factorial
+    n = ctypes.c_int(0)
+    assert lib.dfdg_debug_residual_rule(k, ctypes.byref(n), None, None) == 0
+    pts = np.empty((n.value, 2))
+    w = np.empty(n.value)
+    assert lib.dfdg_debug_residual_rule(k, ctypes.byref(n), pts.ctypes.data_as(P_), w.ctypes.data_as(P_)) == 0
+    assert n.value == {1: 3, 2: 7, 3: 25}[k]
+    assert np.all(w > 0) and np.all(pts > 0) and np.all(pts.sum(1) < 1)
+    for a in range(3 * k):
+        for b in range(3 * k - a):
+            exact = factorial(a) * factorial(b) / factorial(a + b + 2)
+            assert abs(np.sum(w * pts[:, 0] ** a * pts[:, 1] ** b) - exact) < 1e-15
+    # one degree higher is not integrated exactly by the symmetric rules (they are minimal)
+    if k < 3:
+        d = 3 * k
+        errs = [abs(np.sum(w * pts[:, 0] ** a * pts[:, 1] ** (d - a))
+                    - factorial(a) * factorial(d - a) / factorial(d + 2)) for a in range(d + 1)]
+        assert max(errs) > 1e-8
+    assert lib.dfdg_debug_residual_rule(0, ctypes.byref(n), None, None) != 0
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
 @pytest.mark.parametrize("N", [2, 3])
 def test_facet_matrix_equals_oracle_condensation(lib, k, N):
     """The library's facet matrix S equals the static condensation of the oracle's dense
