@@ -145,6 +145,15 @@ __device__ inline void load_Jinv(const DevGeo& g, int t, R (&Ji)[2][2]) {
   Ji[1][1] = (R)g.Jinv[3 * (size_t)g.T + t];
 }
 
+// Block index remapped so that each of the 8 XCDs (which take the launched blocks round
+// robin, each with its own L2) works on one contiguous range of rows: neighbouring
+// elements and facets, whose data a block gathers, then mostly sit in the same L2.
+// A bijection of [0, gridDim.x) for every grid size.
+__device__ inline int xcd_block() {
+  const int G = gridDim.x, b = blockIdx.x, x = b & 7;
+  return x * (G >> 3) + min(x, G & 7) + (b >> 3);
+}
+
 // Stage the reference tables of the residual into LDS.
 template <int K>
 struct ResTabs {
@@ -189,7 +198,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
   __shared__ ResTabs<K> s;
   stage_tabs<K>(s, tb);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const R nu = (R)nu_d;
   R u[2][P], acc[2][P];
@@ -342,7 +351,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
   __shared__ ResTabs<K> s;
   stage_tabs<K>(s, tb);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   double u[2][P], y[2][P], acc[2][P];
 #pragma unroll
@@ -479,7 +488,7 @@ __global__ __launch_bounds__(kEBlk) void k_cond_rhs(DevGeo g, DevTabs tb, const 
                                                     double* __restrict__ q) {
   constexpr int P = nP(K), NF = nF(K);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   double y[2][P];
 #pragma unroll
@@ -521,7 +530,7 @@ __global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const F
                                                    const double* Un, double cb, const double* Us, double dt) {
   constexpr int P = nP(K), NF = nF(K);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   double y[2][P];
 #pragma unroll
@@ -685,7 +694,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
   if (done != PCG_RUNNING && !sc->zero_rhs) return;
   const double zg = sc->zg;
   double v[2] = {0, 0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     if (sc->zero_rhs) {
 #pragma unroll
       for (int m = 0; m < NF; ++m) {
@@ -756,7 +765,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   if (status != PCG_RUNNING) return;
   const V b = (V)beta;
   double v[1] = {0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, M>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -799,7 +808,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
   }
   const V alpha = (V)(t1[0] / t2[0]);
   double v[2] = {0, 0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V rr[NF], zz[NF];
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
@@ -833,7 +842,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg32_init(DevGeo g, DevBsr A, const d
                                                      double* __restrict__ rz0) {
   const int E = g.E;
   double v[2] = {0, 0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     float rr[NF], zz[NF];
 #pragma unroll
     for (int m = 0; m < NF; ++m) rr[m] = (float)r64[(size_t)F * NF + m];
@@ -857,7 +866,7 @@ __global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const 
   const int E = g.E;
   const double zg = sc->zg;
   double v[1] = {0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     double Sx[NF];
     spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
 #pragma unroll
@@ -922,7 +931,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -943,7 +952,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB
                                                     const V* __restrict__ x, V* __restrict__ r, const PcgScalars* sc) {
   if (sc->done != PCG_RUNNING) return;
   const int E = g.E;
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -962,7 +971,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th);
   const int E = g.E;
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -990,7 +999,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
   double v[1] = {0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -1121,7 +1130,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   double v[2] = {0, 0};
-  for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V y[NF];
     spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
@@ -1194,7 +1203,7 @@ __global__ __launch_bounds__(kEBlk) void k_load_vector(DevGeo g, DevTabs tb, int
                                                        double* __restrict__ F) {
   constexpr int P = nP(K);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const double sq = sqrt(g.detJ[t]);
   double acc[2][P];
@@ -1223,7 +1232,7 @@ __global__ __launch_bounds__(kEBlk) void k_eval(DevGeo g, int npts, const double
                                                 const double* __restrict__ U, double* __restrict__ out) {
   constexpr int P = nP(K);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
   const double isq = 1.0 / sqrt(g.detJ[t]);
   double u[2][P];
@@ -1248,7 +1257,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
                                                 double* __restrict__ partials) {
   constexpr int P = nP(K), NQV = nQV(K), NQF = nQF(K);
   const int T = g.T;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
   double en = 0, ens = 0, dmax = 0, jmax = 0;
   if (t < T) {
     double u[2][P];
