@@ -243,6 +243,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   g.E = (int)E;
   g.Jinv = c.take<double>(4 * T);
   g.detJ = c.take<double>(T);
+  g.isq = c.take<double>(T);
   g.nbr = c.take<int>(3 * T);
   g.code = c.take<int>(3 * T);
   g.efacet = c.take<int>(3 * T);
@@ -405,6 +406,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(hipMemsetAsync(ctx->ws, 0, ctx->ws_need - 256, s));
   HIPC(up(const_cast<double*>(ctx->g.Jinv), h.Jinv, s));
   HIPC(up(const_cast<double*>(ctx->g.detJ), h.detJ, s));
+  HIPC(up(const_cast<double*>(ctx->g.isq), h.isq, s));
   HIPC(up(const_cast<int*>(ctx->g.nbr), h.nbr, s));
   HIPC(up(const_cast<int*>(ctx->g.code), h.code, s));
   HIPC(up(const_cast<int*>(ctx->g.efacet), h.efacet, s));
@@ -1075,7 +1077,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
     switch (which) {
       case 0: b = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0 + 4.0 * NF * 8.0); break;       // S, cols, z, p_old, p_new, Sp
       case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
-      case 2:  // U in, L out, Jinv + detJ; per facet nbr, code, nx, ny, |F| (and sigma if nu != 0)
+      case 2:  // U in, L out, Jinv + 1/sqrt(detJ); per facet nbr, code, nx, ny, |F| (and sigma if nu != 0)
         b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (2 * 4.0 + (ctx->prm.nu != 0.0 ? 4 : 3) * 8.0));
         break;
       case 4: {

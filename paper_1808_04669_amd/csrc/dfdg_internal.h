@@ -58,6 +58,7 @@ struct DevGeo {
   int T, E;
   const double* Jinv;   // [4][T], Jinv[r][j] = dxi_r/dx_j at (2r+j)*T + t
   const double* detJ;   // [T]  (> 0)
+  const double* isq;    // [T]  1 / sqrt(detJ)
   const int* nbr;       // [3][T] neighbour across local facet f
   const int* code;      // [3][T] bits 0-1 neighbour's local facet, bit 2 reversed parameter,
                         //        bit 3 this element is the R side of the facet

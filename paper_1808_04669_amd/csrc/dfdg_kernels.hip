@@ -211,11 +211,11 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
     }
   R Ji[2][2];
   load_Jinv(g, t, Ji);
-  const R det = (R)g.detJ[t];
-  const R isq = (R)(1.0 / sqrt((double)det));
-  const R sq = det * isq;
+  const R isq = (R)g.isq[t];
 
-  // volume: int (u (x) u - nu grad u) : grad v
+  // volume: int (u (x) u - nu grad u) : grad v.  With a = sum_i u_i psihat_i (so that
+  // u = a / sqrt(det) at the point) and gr its reference gradient, the integrand times
+  // the Jacobian det is  [isq a (x) a - nu gr Jinv] Jinv^T : grad_ref v  (isq = 1/sqrt(det)).
   for (int q = 0; q < NQV; ++q) {
     R uq[2], gr[2][2];
 #pragma unroll
@@ -229,7 +229,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
           b1 += u[c][i] * (R)s.Gv[q][1][i];
         }
       }
-      uq[c] = a * isq;
+      uq[c] = a;
       gr[c][0] = b0;
       gr[c][1] = b1;
     }
@@ -237,19 +237,27 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
       R fl[2];
+      const R ua = isq * uq[c];
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        fl[j] = uq[c] * uq[j];
-        if constexpr (VISC) fl[j] -= nu * isq * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j]);
+        fl[j] = ua * uq[j];
+        if constexpr (VISC) fl[j] -= nu * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j]);
       }
 #pragma unroll
       for (int a = 0; a < 2; ++a) Gt[c][a] = fl[0] * Ji[a][0] + fl[1] * Ji[a][1];
     }
-    const R w = (R)s.Wv[q] * sq;
+    // the weight folded into the flux: two fused multiply-adds per test function
+    const R w = (R)s.Wv[q];
+    R wG[2][2];
 #pragma unroll
     for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int i = 0; i < P; ++i) acc[c][i] += w * (Gt[c][0] * (R)s.Gv[q][0][i] + Gt[c][1] * (R)s.Gv[q][1][i]);
+      for (int d = 0; d < 2; ++d) wG[c][d] = w * Gt[c][d];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        acc[c][i] = fma(wG[c][1], (R)s.Gv[q][1][i], fma(wG[c][0], (R)s.Gv[q][0][i], acc[c][i]));
   }
 
   // facets
@@ -267,7 +275,8 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int i = 0; i < P; ++i) v[c][i] = (R)U[(size_t)(c * P + i) * T + nb];
-    const R isqn = (R)(1.0 / sqrt(g.detJ[nb]));
+    const R isqn = (R)g.isq[nb];
+    const R li = len * isq;
     R Jn[2][2] = {}, nJ[2] = {}, sig = 0;
     if constexpr (VISC) {
       sig = (R)g.sig[idx];
@@ -315,16 +324,20 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
           Qv[c] = Qv[c] - nu * avgn + nu * sig * du[c];
         }
       }
-      const R w = (R)s.Wf[r] * len * isq;
+      const R w = (R)s.Wf[r] * li;
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
-        const R h = (R)0.5 * nu * du[c];
+        const R wq = -(w * Qv[c]);
+        if constexpr (VISC) {
+          const R wh = w * ((R)0.5 * nu * du[c]);
+          const R wh0 = wh * nJ[0], wh1 = wh * nJ[1];
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-          if constexpr (VISC)
-            acc[c][i] += w * (-Qv[c] * (R)s.Vf[f][r][i] + h * (nJ[0] * (R)s.Gf[f][r][0][i] + nJ[1] * (R)s.Gf[f][r][1][i]));
-          else
-            acc[c][i] -= w * (Qv[c] * (R)s.Vf[f][r][i]);
+          for (int i = 0; i < P; ++i)
+            acc[c][i] = fma(wq, (R)s.Vf[f][r][i],
+                            fma(wh1, (R)s.Gf[f][r][1][i], fma(wh0, (R)s.Gf[f][r][0][i], acc[c][i])));
+        } else {
+#pragma unroll
+          for (int i = 0; i < P; ++i) acc[c][i] = fma(wq, (R)s.Vf[f][r][i], acc[c][i]);
         }
       }
     }
@@ -365,7 +378,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
   double Ji[2][2];
   load_Jinv(g, t, Ji);
   const double det = g.detJ[t];
-  const double isq = 1.0 / sqrt(det);
+  const double isq = g.isq[t];
   const double sq = det * isq;
   for (int q = 0; q < NQV; ++q) {
     double uq[2], gy[2][2];
@@ -414,7 +427,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
       }
     double Jn[2][2];
     load_Jinv(g, nb, Jn);
-    const double isqn = 1.0 / sqrt(g.detJ[nb]);
+    const double isqn = g.isq[nb];
     double nJ[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) nJ[a] = n0 * Ji[a][0] + n1 * Ji[a][1];
@@ -1234,7 +1247,7 @@ __global__ __launch_bounds__(kEBlk) void k_eval(DevGeo g, int npts, const double
   const int T = g.T;
   const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  const double isq = 1.0 / sqrt(g.detJ[t]);
+  const double isq = g.isq[t];
   double u[2][P];
 #pragma unroll
   for (int c = 0; c < 2; ++c)
@@ -1270,7 +1283,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
       }
     double Ji[2][2];
     load_Jinv(g, t, Ji);
-    const double det = g.detJ[t], isq = 1.0 / sqrt(det);
+    const double det = g.detJ[t], isq = g.isq[t];
     for (int q = 0; q < NQV; ++q) {
       double gr[2][2];
 #pragma unroll
@@ -1294,7 +1307,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
       if ((code >> 3) & 1) continue;  // the L side measures the facet
       const int nb = g.nbr[idx], fn = code & 3;
       const bool rev = (code >> 2) & 1;
-      const double n0 = g.nx[idx], n1 = g.ny[idx], isqn = 1.0 / sqrt(g.detJ[nb]);
+      const double n0 = g.nx[idx], n1 = g.ny[idx], isqn = g.isq[nb];
       for (int r = 0; r < NQF; ++r) {
         const int rn = rev ? NQF - 1 - r : r;
         double jo = 0, jn = 0;

@@ -413,6 +413,7 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
   h.K = K;
   h.Jinv.assign(4 * (size_t)T, 0);
   h.detJ.assign(T, 0);
+  h.isq.assign(T, 0);
   h.nbr.assign(3 * (size_t)T, 0);
   h.code.assign(3 * (size_t)T, 0);
   h.efacet.assign(3 * (size_t)T, 0);
@@ -436,6 +437,7 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
     const double J00 = v[2] - v[0], J01 = v[4] - v[0], J10 = v[3] - v[1], J11 = v[5] - v[1];
     const double det = J00 * J11 - J01 * J10;
     h.detJ[t] = det;
+    h.isq[t] = 1.0 / std::sqrt(det);
     h.Jinv[0 * (size_t)T + t] = J11 / det;   // dxi/dx
     h.Jinv[1 * (size_t)T + t] = -J01 / det;  // dxi/dy
     h.Jinv[2 * (size_t)T + t] = -J10 / det;  // deta/dx

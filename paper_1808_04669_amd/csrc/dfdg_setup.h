@@ -21,7 +21,7 @@ struct MeshHost {
 struct HostSetup {
   int T = 0, E = 0, K = 0;
   RefTables tabs;
-  std::vector<double> Jinv, detJ, nx, ny, flen, sig, sF, G, zdef, vals, dinv, binv;
+  std::vector<double> Jinv, detJ, isq, nx, ny, flen, sig, sF, G, zdef, vals, dinv, binv;
   std::vector<int> nbr, code, efacet, qL, qR, cols;
 };
 
