@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--precond", default="amg", choices=["jacobi", "block_jacobi", "amg"])
     ap.add_argument("--extrapolate", type=int, default=4)
     ap.add_argument("--order", default="morton")
+    ap.add_argument("--no-mg-fp16", action="store_true",
+                    help="finest-level multigrid smoothing reads S in FP32 instead of FP16")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing and the accuracy check against the oracle")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
@@ -98,7 +100,7 @@ def make_solver(N, k, precision, args, order=None, rtol=None, nu=0.0, **kw):
     from paper_1808_04669_amd import Solver
     xyz, per = periodic_split_square(N, order or args.order)
     s = Solver(xyz, per, k, nu=nu, precision=precision, cg_rtol=rtol or args.rtol, precond=args.precond,
-               extrapolate=args.extrapolate, **kw)
+               extrapolate=args.extrapolate, **{"mg_fine_fp16": not args.no_mg_fp16, **kw})
     s._xyz = xyz
     return s
 

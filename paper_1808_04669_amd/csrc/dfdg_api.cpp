@@ -131,6 +131,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->extrapolate = 0;
   p->graphs = 1;
   p->mg_fp32 = 1;
+  p->mg_fine_fp16 = 1;
 }
 
 static int check_params(const dfdg_params* p, std::string& e) {
@@ -151,6 +152,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->extrapolate < 0 || p->extrapolate >= kHistDepth) { e = "extrapolate must be in 0..4"; return -1; }
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
+  if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
   return 0;
 }
 
@@ -278,6 +280,8 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.vals32 = f32 ? c.take<float>(h.vals.size()) : nullptr;
   A.dinv32 = f32 ? c.take<float>(h.dinv.size()) : nullptr;
   A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
+  const bool f16 = !mixed && ctx->prm.precond == DFDG_AMG && ctx->prm.mg_fp32 && ctx->prm.mg_fine_fp16;
+  A.vals16 = f16 ? c.take<uint16_t>(h.vals.size()) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
   ctx->q = c.take<double>(3 * NF * T);
@@ -441,6 +445,13 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     HIPC(up(const_cast<float*>(ctx->A.dinv32), d, s));
     HIPC(up(const_cast<float*>(ctx->A.binv32), b, s));
     HIPC(hipStreamSynchronize(s));
+  }
+  if (ctx->A.vals16) {
+    double smax = 0;
+    for (double v : h.vals) smax = std::max(smax, std::fabs(v));
+    if (!(smax > 0)) smax = 1;
+    ctx->A.scale16 = (float)smax;
+    HIPC(launch_to_half((long)h.vals.size(), ctx->A.vals, 1.0 / smax, const_cast<uint16_t*>(ctx->A.vals16), s));
   }
   {
     const bool mixed = ctx->A.vals32 != nullptr;  // FP32 copies were carved
@@ -1082,16 +1093,20 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
         break;
       case 4: {
         // finest level: 4 BSR sweeps + 17 vector passes; transfers and coarse levels:
-        // every CSR entry (8-byte value, 4-byte column) once per use, vectors once
-        const double sbytes = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0);
-        b = 4 * sbytes + 17.0 * E * NF * 8.0;
+        // every CSR entry (value and 4-byte column) once per use, vectors once.  Values
+        // and vectors in the cycle's precision (8 or 4 bytes; finest-level S in 2 bytes
+        // when it is stored in FP16).
+        const double vb = ctx->prm.mg_fp32 ? 4.0 : 8.0;
+        const double sv = ctx->A.vals16 ? 2.0 : vb;
+        const double sbytes = E * (kSlots * NF * NF * sv + kSlots * 4.0);
+        b = 4 * sbytes + 17.0 * E * NF * vb;
         const AmgHierarchy& H = ctx->H;
         for (size_t l = 0; l < H.lv.size(); ++l) {
           const AmgLevel& L = H.lv[l];
-          if (l > 0 && l + 1 < H.lv.size()) b += 4 * L.A.nnz() * 12.0 + 17.0 * L.A.n * 8.0;
-          if (l + 1 < H.lv.size()) b += (L.P.nnz() + L.R.nnz()) * 12.0 + 4.0 * L.A.n * 8.0;
+          if (l > 0 && l + 1 < H.lv.size()) b += 4 * L.A.nnz() * (vb + 4.0) + 17.0 * L.A.n * vb;
+          if (l + 1 < H.lv.size()) b += (L.P.nnz() + L.R.nnz()) * (vb + 4.0) + 4.0 * L.A.n * vb;
         }
-        b += H.n_coarse * (double)H.n_coarse * 8.0;
+        b += H.n_coarse * (double)H.n_coarse * vb;
         break;
       }
       default: b = E * (kSlots * NF * NF * 4.0 + kSlots * 4.0 + 4.0 * NF * 4.0); break;

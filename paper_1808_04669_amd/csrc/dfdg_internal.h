@@ -87,6 +87,8 @@ struct DevBsr {
   const float* vals32;  // [5][NF][NF][E] (MIXED)
   const float* dinv32;  // [E][NF]
   const float* binv32;  // [E][NF][NF]
+  const uint16_t* vals16;  // [5][NF][NF][E] FP16 bits of S / scale16 (finest V-cycle level), or null
+  float scale16;
 };
 
 // Scalars of one PCG run (device memory).  Written by block 0 of a kernel (or by a

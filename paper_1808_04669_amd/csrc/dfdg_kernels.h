@@ -131,5 +131,7 @@ struct HistPtrs { const double* p[kHistDepth]; };
 // out = extrapolation of order `order` (< kHistDepth) in time from p[0..order].
 hipError_t launch_extrapolate(long n, int order, const HistPtrs& h, double* out, hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
+// out[i] = FP16 bits of x[i] * scale (round to nearest even).
+hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s);
 
 }  // namespace dfdg

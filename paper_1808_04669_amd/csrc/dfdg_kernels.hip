@@ -696,6 +696,33 @@ __device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y
   }
 }
 
+// As spmv_row in FP32 for the multigrid smoothing on the finest level: S is read from its
+// FP16 copy (scaled by scale16) when there is one, else from the FP32 copy.
+template <int NF, typename V, typename Getter>
+__device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
+  if constexpr (sizeof(V) == 4) {
+    if (A.vals16) {
+      const _Float16* vals = reinterpret_cast<const _Float16*>(A.vals16);
+#pragma unroll
+      for (int a = 0; a < NF; ++a) y[a] = 0;
+#pragma unroll
+      for (int s = 0; s < kSlots; ++s) {
+        const int c = A.cols[(size_t)s * E + F];
+        V xc[NF];
+        get(c, xc);
+#pragma unroll
+        for (int a = 0; a < NF; ++a)
+#pragma unroll
+          for (int b = 0; b < NF; ++b) y[a] += (V)vals[(((size_t)s * NF + a) * NF + b) * E + F] * xc[b];
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a) y[a] *= A.scale16;
+      return;
+    }
+  }
+  spmv_row<NF, V, V>(A, E, F, get, y);
+}
+
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
 template <int NF, bool BJ>
 __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
@@ -946,7 +973,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * (V)b[(size_t)c * NF + q] * ith;
     }, y);
@@ -967,7 +994,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
     }, y);
@@ -986,7 +1013,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x3[(size_t)c * NF + q];
     }, y);
@@ -1014,7 +1041,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
   double v[1] = {0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x4[(size_t)c * NF + q];
     }, y);
@@ -1145,7 +1172,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   double v[2] = {0, 0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V y[NF];
-    spmv_row<NF, V, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
         const size_t o = (size_t)c * NF + q;
@@ -1711,6 +1738,18 @@ hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, 
   hipLaunchKernelGGL(k_axpby, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, a, x, b, y);
   return hipGetLastError();
 }
+__global__ void k_to_half(long n, const double* __restrict__ x, double scale, _Float16* __restrict__ out) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = (_Float16)(float)(x[i] * scale);
+}
+
+hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const long nb = std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_to_half, dim3((unsigned)nb), dim3(256), 0, s, n, x, scale, reinterpret_cast<_Float16*>(out));
+  return hipGetLastError();
+}
+
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, v, y);
   return hipGetLastError();

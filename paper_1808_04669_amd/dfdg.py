@@ -31,7 +31,8 @@ class Params(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("nu", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ir_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int), ("mg_fp32", ctypes.c_int)]
+                ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int), ("mg_fp32", ctypes.c_int),
+                ("mg_fine_fp16", ctypes.c_int)]
 
 
 class Sizes(ctypes.Structure):
@@ -159,6 +160,7 @@ class Solver:
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
                  precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, mg_fp32=True,
+                 mg_fine_fp16=True,
                  device="cuda:0", stream=None):
         lib = load_library()
         self._lib = lib
@@ -173,6 +175,7 @@ class Solver:
         p.ir_rtol, p.inner_rtol, p.extrapolate = float(ir_rtol), float(inner_rtol), int(extrapolate)
         p.graphs = 1 if graphs else 0
         p.mg_fp32 = 1 if mg_fp32 else 0
+        p.mg_fine_fp16 = 1 if mg_fine_fp16 else 0
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
