@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <string>
 #include <vector>
 
@@ -334,10 +335,13 @@ static void carve(dfdg_ctx* ctx, char* base) {
     const double avg = M.n ? (double)M.nnz() / M.n : 1.0;
     D.lpr = 1;
     while (D.lpr < 64 && 2 * D.lpr <= avg) D.lpr *= 2;
-    D.ptr = c.take<int>(M.ptr.size());
-    D.col = c.take<int>(M.col.size());
-    D.val = c.take<double>(M.val.size());
-    D.val32 = f32 ? c.take<float>(M.val.size()) : nullptr;
+    int wmax = 1;
+    for (int i = 0; i < M.n; ++i) wmax = std::max(wmax, M.ptr[i + 1] - M.ptr[i]);
+    D.w = (wmax + D.lpr - 1) / D.lpr * D.lpr;
+    const size_t ne = (size_t)M.n * D.w;
+    D.col = c.take<int>(ne);
+    D.val = c.take<double>(ne);
+    D.val32 = f32 ? c.take<float>(ne) : nullptr;
   };
   for (int l = 0; l < mg.nlev; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -458,15 +462,28 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     const AmgHierarchy& H = ctx->H;
     MgDev& mg = ctx->mg;
     std::vector<std::vector<float>> keep;  // float staging buffers stay alive until the sync below
+    std::deque<std::vector<double>> keep_d;  // padded copies, likewise
+    std::deque<std::vector<int>> keep_i;
     auto f32 = [&](const std::vector<double>& v) -> const std::vector<float>& {
       keep.emplace_back(v.begin(), v.end());
       return keep.back();
     };
     auto up_csr = [&](const Csr& M, const DevCsr& D) -> int {
-      HIPC(up(const_cast<int*>(D.ptr), M.ptr, s));
-      HIPC(up(const_cast<int*>(D.col), M.col, s));
-      HIPC(up(const_cast<double*>(D.val), M.val, s));
-      if (mixed) HIPC(up(const_cast<float*>(D.val32), f32(M.val), s));
+      // padded row-major copy (see DevCsr)
+      std::vector<int> ce((size_t)M.n * D.w);
+      keep_d.emplace_back((size_t)M.n * D.w, 0.0);
+      std::vector<double>& ve = keep_d.back();
+      for (int i = 0; i < M.n; ++i) {
+        const int b = M.ptr[i], len = M.ptr[i + 1] - b;
+        for (int k = 0; k < D.w; ++k) {
+          ce[(size_t)i * D.w + k] = len ? M.col[b + std::min(k, len - 1)] : 0;
+          if (k < len) ve[(size_t)i * D.w + k] = M.val[b + k];
+        }
+      }
+      keep_i.push_back(std::move(ce));
+      HIPC(up(const_cast<int*>(D.col), keep_i.back(), s));
+      HIPC(up(const_cast<double*>(D.val), ve, s));
+      if (mixed) HIPC(up(const_cast<float*>(D.val32), f32(ve), s));
       return DFDG_OK;
     };
     keep.reserve(4 * kMaxLev + 2);

@@ -967,7 +967,7 @@ __device__ inline const V* bsr_dinv(const DevBsr& A) { return (sizeof(V) == 8) ?
 template <int NF, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ b, V* __restrict__ x2,
                                                   CheB cb, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -982,7 +982,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
       const size_t o = (size_t)F * NF + a;
       const V bo = (V)b[o];
       const V x1 = dinv[o] * bo * ith;
-      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
+      if (live) x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
     }
   }
 }
@@ -990,7 +990,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
 template <int NF, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x, V* __restrict__ r, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
@@ -999,7 +999,8 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB
       for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a) r[(size_t)F * NF + a] = (V)b[(size_t)F * NF + a] - y[a];
+    for (int a = 0; a < NF; ++a)
+      if (live) r[(size_t)F * NF + a] = (V)b[(size_t)F * NF + a] - y[a];
   }
 }
 
@@ -1007,7 +1008,7 @@ template <int NF, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
                                                     CheB cb, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th);
   const int E = g.E;
@@ -1021,8 +1022,10 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
       const V dd = dinv[o] * ((V)b[o] - y[a]) * ith;
-      d[o] = dd;
-      x4[o] = x3[o] + dd;
+      if (live) {
+        d[o] = dd;
+        x4[o] = x3[o] + dd;
+      }
     }
   }
 }
@@ -1034,7 +1037,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
                                                     const V* __restrict__ x4, const V* __restrict__ d,
                                                     VB* __restrict__ z, CheB cb, double* __restrict__ rz,
                                                     const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const V* dinv = bsr_dinv<NF, V>(A);
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -1049,7 +1052,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
       const V zz = x4[o] + c1 * d[o] + c2 * dinv[o] * ((V)b[o] - y[a]);
-      z[o] = (VB)zz;
+      if (live) z[o] = (VB)zz;
       v[0] += (double)b[o] * (double)(VB)zz;
     }
   }
@@ -1057,24 +1060,26 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
   const double s = wave_sum(v[0]);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (live && threadIdx.x == 0) {
     double t = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
     rz[2 * blockIdx.x] = t;
   }
 }
 
-// Coarse levels: scalar CSR, LPR lanes (a power of two <= 64, chosen on the host from the
-// mean row length) share a row: lane j of the group takes entries j, j+LPR, ..., and the
-// group reduces with shuffles in a fixed order.
+// Coarse levels: padded rows (DevCsr), LPR lanes (a power of two <= 64, chosen on the
+// host from the mean row length) share a row: lane j of the group takes entries j, j+LPR,
+// ..., and the group reduces with shuffles in a fixed order.
 template <typename V>
 __device__ inline const V* csr_vals(const DevCsr& A) { return (sizeof(V) == 8) ? (const V*)A.val : (const V*)A.val32; }
 
 template <int LPR, typename V, typename X>
 __device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, int i, int sub, X x) {
   V s = 0;
-  if (i < A.n)
-    for (int k = A.ptr[i] + sub; k < A.ptr[i + 1]; k += LPR) s += vals[k] * x(A.col[k]);
+  if (i < A.n) {
+    const size_t base = (size_t)i * A.w;
+    for (int k = sub; k < A.w; k += LPR) s += vals[base + k] * x(A.col[base + k]);
+  }
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPR);
   return s;
@@ -1083,12 +1088,12 @@ __device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, i
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                   V* __restrict__ x2, CheB cb, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V ith = (V)(1.0 / cb.th);
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return dinv[c] * b[c] * ith; });
-  if (i < A.n && sub == 0) {
+  if (live && i < A.n && sub == 0) {
     const V x1 = dinv[i] * b[i] * ith;
     x2[i] = (1 + (V)cb.c1) * x1 + (V)cb.c2 * dinv[i] * (b[i] - s);
   }
@@ -1097,22 +1102,22 @@ __global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict_
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_resid(DevCsr A, const V* __restrict__ b, const V* __restrict__ x,
                                                     V* __restrict__ r, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x[c]; });
-  if (i < A.n && sub == 0) r[i] = b[i] - s;
+  if (live && i < A.n && sub == 0) r[i] = b[i] - s;
 }
 
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_post1(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                     const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
                                                     CheB cb, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x3[c]; });
-  if (i < A.n && sub == 0) {
+  if (live && i < A.n && sub == 0) {
     const V dd = dinv[i] * (b[i] - s) * (V)(1.0 / cb.th);
     d[i] = dd;
     x4[i] = x3[i] + dd;
@@ -1123,22 +1128,22 @@ template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
                                                     V* __restrict__ z, CheB cb, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x4[c]; });
-  if (i < A.n && sub == 0) z[i] = x4[i] + (V)cb.c1 * d[i] + (V)cb.c2 * dinv[i] * (b[i] - s);
+  if (live && i < A.n && sub == 0) z[i] = x4[i] + (V)cb.c1 * d[i] + (V)cb.c2 * dinv[i] * (b[i] - s);
 }
 
 // y = M x (restriction with M = R), or y = y0 + M x (prolongation-add, add != 0).
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restrict__ x, const V* __restrict__ y0,
                                                     V* __restrict__ y, int add, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
-  if (i < M.n && sub == 0) y[i] = add ? y0[i] + s : s;
+  if (live && i < M.n && sub == 0) y[i] = add ? y0[i] + s : s;
 }
 
 // ---- PCG update fused with the first smoothing step of the cycle ----------------------
@@ -1218,7 +1223,7 @@ __global__ __launch_bounds__(kBlk) void k_partial_dot(long n, const V* __restric
 template <typename V>
 __global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restrict__ Ainv, const float* __restrict__ Ainv32,
                                                    const V* __restrict__ b, V* __restrict__ x, const PcgScalars* sc) {
-  if (sc->done != PCG_RUNNING) return;
+  const bool live = sc->done == PCG_RUNNING;  // tested before the store only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g >> 6, lane = g & 63;
   const V* M = (sizeof(V) == 8) ? (const V*)Ainv : (const V*)Ainv32;
@@ -1227,7 +1232,7 @@ __global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restri
     for (int j = lane; j < n; j += 64) s += M[(size_t)i * n + j] * b[j];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (i < n && lane == 0) x[i] = s;
+  if (live && i < n && lane == 0) x[i] = s;
 }
 
 __global__ void k_add_f32(long n, const float* __restrict__ x, double* __restrict__ y) {

@@ -24,12 +24,15 @@ def _log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+@pytest.mark.parametrize("precond", ["jacobi", "amg", "amg_fp32_fine"])
 @pytest.mark.parametrize("k,N,order", CASES + [(1, 1, "lex"), (2, 2, "morton")])
 def test_mass_solve_parity(k, N, order, precond):
-    """Divergence-free mass inversion of a random broken polynomial functional (Theorems 1-2)."""
+    """Divergence-free mass inversion of a random broken polynomial functional (Theorems 1-2).
+    amg: the multigrid smoothing on the finest level reads S in FP16 (the default);
+    amg_fp32_fine: in FP32."""
     _log("mass_solve", k, N, order, precond)
-    orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13, precond=precond)
+    kw = dict(precond="amg", mg_fine_fp16=False) if precond == "amg_fp32_fine" else dict(precond=precond)
+    orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13, **kw)
     coef = random_broken_poly(s.T, k, seed=10 + k)
     F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
     U, info = s.mass_solve(F)
