@@ -330,6 +330,10 @@ int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<dou
     Csr R = transpose(P);
     Csr AP = matmul(L.A, P);
     Csr Ac = matmul(R, AP);
+    if (level > 0) {  // for the fused transfer kernels of the coarse levels
+      L.RA = transpose(AP);
+      L.AP = std::move(AP);
+    }
     L.P = std::move(P);
     L.R = std::move(R);
     AmgLevel next;

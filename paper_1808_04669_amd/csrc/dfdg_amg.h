@@ -21,6 +21,7 @@ struct AmgLevel {
   double lmax = 0;  // spectral radius estimate of D^{-1} A (Chebyshev upper bound)
   Csr P;            // prolongator from the next coarser level to this one (empty on the coarsest)
   Csr R;            // restriction = P^T
+  Csr AP, RA;       // A P and R A = (A P)^T, kept on levels >= 1 that have a coarser level
 };
 
 struct AmgHierarchy {

@@ -354,6 +354,10 @@ static void carve(dfdg_ctx* ctx, char* base) {
     if (l < mg.nlev - 1) {
       take_csr(L.P, mg.P[l]);
       take_csr(L.R, mg.R[l]);
+      if (l > 0) {
+        take_csr(L.AP, mg.AP[l]);
+        take_csr(L.RA, mg.RA[l]);
+      }
     }
     MgVec<double>& v = mg.v64[l];
     v.b = (l > 0) ? c.take<double>(n) : nullptr;
@@ -486,7 +490,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
       if (mixed) HIPC(up(const_cast<float*>(D.val32), f32(ve), s));
       return DFDG_OK;
     };
-    keep.reserve(4 * kMaxLev + 2);
+    keep.reserve(8 * kMaxLev + 2);
     for (int l = 0; l < mg.nlev; ++l) {
       const AmgLevel& L = H.lv[l];
       if (l > 0) {
@@ -497,6 +501,10 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
       if (l < mg.nlev - 1) {
         if (int rc = up_csr(L.P, mg.P[l])) return rc;
         if (int rc = up_csr(L.R, mg.R[l])) return rc;
+        if (l > 0) {
+          if (int rc = up_csr(L.AP, mg.AP[l])) return rc;
+          if (int rc = up_csr(L.RA, mg.RA[l])) return rc;
+        }
       }
     }
     if (mg.nlev > 0) {
@@ -1118,10 +1126,15 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
         const double sbytes = E * (kSlots * NF * NF * sv + kSlots * 4.0);
         b = 4 * sbytes + 17.0 * E * NF * vb;
         const AmgHierarchy& H = ctx->H;
-        for (size_t l = 0; l < H.lv.size(); ++l) {
+        for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
           const AmgLevel& L = H.lv[l];
-          if (l > 0 && l + 1 < H.lv.size()) b += 4 * L.A.nnz() * (vb + 4.0) + 17.0 * L.A.n * vb;
-          if (l + 1 < H.lv.size()) b += (L.P.nnz() + L.R.nnz()) * (vb + 4.0) + 4.0 * L.A.n * vb;
+          const double nn = H.lv[l + 1].A.n;
+          if (l == 0) {  // transfers of the finest level
+            b += (L.P.nnz() + L.R.nnz()) * (vb + 4.0) + (2.0 * L.A.n + 2.0 * nn) * vb;
+          } else {  // pre-smoothing, fused restriction, fused prolongation + post1, post2
+            b += (3.0 * L.A.nnz() + L.R.nnz() + L.RA.nnz() + L.AP.nnz() + L.P.nnz()) * (vb + 4.0) +
+                 15.0 * L.A.n * vb + 2.0 * nn * vb;
+          }
         }
         b += H.n_coarse * (double)H.n_coarse * vb;
         break;

@@ -49,6 +49,8 @@ struct MgDev {
   DevCsr A[kMaxLev];   // A[0] unused (the BSR facet matrix)
   DevCsr P[kMaxLev];   // prolongation from level l+1 to level l (rows: level l)
   DevCsr R[kMaxLev];   // restriction P^T
+  DevCsr AP[kMaxLev];  // A P and R A on levels >= 1 (fused transfers; unused on level 0)
+  DevCsr RA[kMaxLev];
   const double* dinv[kMaxLev];
   const float* dinv32[kMaxLev];
   CheB cheb[kMaxLev];

@@ -1073,16 +1073,25 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
 template <typename V>
 __device__ inline const V* csr_vals(const DevCsr& A) { return (sizeof(V) == 8) ? (const V*)A.val : (const V*)A.val32; }
 
+// This lane's part of row i of M x (i < M.n).
 template <int LPR, typename V, typename X>
-__device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, int i, int sub, X x) {
+__device__ inline V ell_part(const DevCsr& M, int i, int sub, X x) {
+  const V* __restrict__ vals = csr_vals<V>(M);
+  const size_t base = (size_t)i * M.w;
   V s = 0;
-  if (i < A.n) {
-    const size_t base = (size_t)i * A.w;
-    for (int k = sub; k < A.w; k += LPR) s += vals[base + k] * x(A.col[base + k]);
-  }
+  for (int k = sub; k < M.w; k += LPR) s += vals[base + k] * x(M.col[base + k]);
+  return s;
+}
+template <int LPR, typename V>
+__device__ inline V group_sum(V s) {
 #pragma unroll
   for (int off = LPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPR);
   return s;
+}
+template <int LPR, typename V, typename X>
+__device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, int i, int sub, X x) {
+  (void)vals;
+  return group_sum<LPR, V>(i < A.n ? ell_part<LPR, V>(A, i, sub, x) : (V)0);
 }
 
 template <int LPR, typename V>
@@ -1100,31 +1109,6 @@ __global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict_
 }
 
 template <int LPR, typename V>
-__global__ __launch_bounds__(kBlk) void k_mgc_resid(DevCsr A, const V* __restrict__ b, const V* __restrict__ x,
-                                                    V* __restrict__ r, const PcgScalars* sc) {
-  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = g / LPR, sub = g % LPR;
-  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x[c]; });
-  if (live && i < A.n && sub == 0) r[i] = b[i] - s;
-}
-
-template <int LPR, typename V>
-__global__ __launch_bounds__(kBlk) void k_mgc_post1(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
-                                                    const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
-                                                    CheB cb, const PcgScalars* sc) {
-  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = g / LPR, sub = g % LPR;
-  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x3[c]; });
-  if (live && i < A.n && sub == 0) {
-    const V dd = dinv[i] * (b[i] - s) * (V)(1.0 / cb.th);
-    d[i] = dd;
-    x4[i] = x3[i] + dd;
-  }
-}
-
-template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
                                                     V* __restrict__ z, CheB cb, const PcgScalars* sc) {
@@ -1133,6 +1117,50 @@ __global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restric
   const int i = g / LPR, sub = g % LPR;
   const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x4[c]; });
   if (live && i < A.n && sub == 0) z[i] = x4[i] + (V)cb.c1 * d[i] + (V)cb.c2 * dinv[i] * (b[i] - s);
+}
+
+// Coarse levels, restriction of the pre-smoothed residual in one pass:
+// b_c = R (b - A x2) = R b - (R A) x2 with R A precomputed, so that the residual of the
+// level is never stored.
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_restrict(DevCsr R, DevCsr RA, const V* __restrict__ b,
+                                                       const V* __restrict__ x2, V* __restrict__ bc,
+                                                       const PcgScalars* sc) {
+  const bool live = sc->done == PCG_RUNNING;  // tested before the store only
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  V s = 0;
+  if (i < R.n)
+    s = ell_part<LPR, V>(R, i, sub, [&](int c) { return b[c]; }) -
+        ell_part<LPR, V>(RA, i, sub, [&](int c) { return x2[c]; });
+  s = group_sum<LPR, V>(s);
+  if (live && i < R.n && sub == 0) bc[i] = s;
+}
+
+// Coarse levels, prolongation-add fused with the first post-smoothing step:
+// x3 = x2 + P e and A x3 = A x2 + (A P) e with A P precomputed; d = D^{-1} (b - A x3) / th,
+// x4 = x3 + d.
+template <int LPR, typename V>
+__global__ __launch_bounds__(kBlk) void k_mgc_post1p(DevCsr A, DevCsr AP, DevCsr P, const V* __restrict__ dinv,
+                                                     const V* __restrict__ b, const V* __restrict__ x2,
+                                                     const V* __restrict__ e, V* __restrict__ x4,
+                                                     V* __restrict__ d, CheB cb, const PcgScalars* sc) {
+  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = g / LPR, sub = g % LPR;
+  V pe = 0, ax = 0;
+  if (i < A.n) {
+    pe = ell_part<LPR, V>(P, i, sub, [&](int c) { return e[c]; });
+    ax = ell_part<LPR, V>(A, i, sub, [&](int c) { return x2[c]; }) +
+         ell_part<LPR, V>(AP, i, sub, [&](int c) { return e[c]; });
+  }
+  pe = group_sum<LPR, V>(pe);
+  ax = group_sum<LPR, V>(ax);
+  if (live && i < A.n && sub == 0) {
+    const V dd = dinv[i] * (b[i] - ax) * (V)(1.0 / cb.th);
+    d[i] = dd;
+    x4[i] = (x2[i] + pe) + dd;
+  }
 }
 
 // y = M x (restriction with M = R), or y = y0 + M x (prolongation-add, add != 0).
@@ -1631,11 +1659,13 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
     const DevCsr& Al = mg.A[l];
     const V* dinv = mg_dinv<V>(mg, l);
     const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
-    DFDG_DISPATCH_LPR(Al.lpr, {
-      hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, v.x, mg.cheb[l], sc);
-      hipLaunchKernelGGL((k_mgc_resid<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, (const V*)v.b, (const V*)v.x, v.r, sc);
-    });
-    csr_apply<V>(mg.R[l], (const V*)v.r, (const V*)nullptr, mg_vec<V>(mg, l + 1).b, 0, sc, s);
+    DFDG_DISPATCH_LPR(Al.lpr, hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv,
+                                                 (const V*)v.b, v.x, mg.cheb[l], sc));
+    const DevCsr& R = mg.R[l];
+    const DevCsr& RA = mg.RA[l];
+    DFDG_DISPATCH_LPR(std::max(R.lpr, RA.lpr),
+                      hipLaunchKernelGGL((k_mgc_restrict<LP, V>), dim3(nblk((long)R.n * LP, kBlk)), dim3(kBlk), 0, s,
+                                         R, RA, (const V*)v.b, (const V*)v.x, mg_vec<V>(mg, l + 1).b, sc));
   }
   {
     const MgVec<V>& vc = mg_vec<V>(mg, L - 1);
@@ -1647,13 +1677,14 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
     const DevCsr& Al = mg.A[l];
     const V* dinv = mg_dinv<V>(mg, l);
     const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
-    csr_apply<V>(mg.P[l], (const V*)mg_vec<V>(mg, l + 1).z, (const V*)v.x, v.x, 1, sc, s);
-    DFDG_DISPATCH_LPR(Al.lpr, {
-      hipLaunchKernelGGL((k_mgc_post1<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.x, v.y,
-                         v.d, mg.cheb[l], sc);
-      hipLaunchKernelGGL((k_mgc_post2<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv, (const V*)v.b, (const V*)v.y,
-                         (const V*)v.d, v.z, mg.cheb[l], sc);
-    });
+    const DevCsr& AP = mg.AP[l];
+    const DevCsr& P = mg.P[l];
+    DFDG_DISPATCH_LPR(std::max(Al.lpr, std::max(AP.lpr, P.lpr)),
+                      hipLaunchKernelGGL((k_mgc_post1p<LP, V>), dim3(nblk((long)Al.n * LP, kBlk)), dim3(kBlk), 0, s,
+                                         Al, AP, P, dinv, (const V*)v.b, (const V*)v.x,
+                                         (const V*)mg_vec<V>(mg, l + 1).z, v.y, v.d, mg.cheb[l], sc));
+    DFDG_DISPATCH_LPR(Al.lpr, hipLaunchKernelGGL((k_mgc_post2<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv,
+                                                 (const V*)v.b, (const V*)v.y, (const V*)v.d, v.z, mg.cheb[l], sc));
   }
   csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, sc, s);
   DFDG_DISPATCH_NF_VOID(NF, {
