@@ -1079,6 +1079,7 @@ __device__ inline V ell_part(const DevCsr& M, int i, int sub, X x) {
   const V* __restrict__ vals = csr_vals<V>(M);
   const size_t base = (size_t)i * M.w;
   V s = 0;
+#pragma unroll 4
   for (int k = sub; k < M.w; k += LPR) s += vals[base + k] * x(M.col[base + k]);
   return s;
 }
@@ -1257,6 +1258,7 @@ __global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restri
   const V* M = (sizeof(V) == 8) ? (const V*)Ainv : (const V*)Ainv32;
   V s = 0;
   if (i < n)
+#pragma unroll 4
     for (int j = lane; j < n; j += 64) s += M[(size_t)i * n + j] * b[j];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
