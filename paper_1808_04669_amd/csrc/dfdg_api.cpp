@@ -52,7 +52,9 @@ struct dfdg_ctx {
   double* lamx = nullptr;
   hipStream_t cap_stream = nullptr;
   // one graph per iteration parity ([1]: odd iterations, [0]: even), FP64 and FP32 PCG
-  hipGraphExec_t graph64[2] = {nullptr, nullptr}, graph32[2] = {nullptr, nullptr};
+  // captured PCG iterations: [0], [1] one iteration of even / odd parity; [2], [3] two
+  // consecutive iterations starting with even / odd parity
+  hipGraphExec_t graph64[4] = {}, graph32[4] = {};
   int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
   std::string err;
@@ -527,7 +529,7 @@ extern "C" const char* dfdg_last_error(const dfdg_ctx* ctx) {
 
 extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
   if (!ctx) return;
-  for (int j = 0; j < 2; ++j) {
+  for (int j = 0; j < 4; ++j) {
     if (ctx->graph64[j]) (void)hipGraphExecDestroy(ctx->graph64[j]);
     if (ctx->graph32[j]) (void)hipGraphExecDestroy(ctx->graph32[j]);
   }
@@ -563,10 +565,11 @@ static int read_scalars(dfdg_ctx* ctx, PcgScalars* dev, PcgScalars& out) {
 // alternates between odd and even iterations and is part of the launch arguments; the
 // iteration index itself is read by the kernels from the device scalars).
 template <typename Step>
-static int capture_iteration(dfdg_ctx* ctx, int parity, Step step, hipGraphExec_t* out) {
+static int capture_iteration(dfdg_ctx* ctx, int parity, int count, Step step, hipGraphExec_t* out) {
   if (!ctx->cap_stream) HIPC(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   HIPC(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
-  hipError_t e = step(parity ? 1 : 2, ctx->cap_stream);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < count && e == hipSuccess; ++i) e = step(((parity + i) & 1) ? 1 : 2, ctx->cap_stream);
   if (e != hipSuccess) {
     hipGraph_t g = nullptr;
     (void)hipStreamEndCapture(ctx->cap_stream, &g);
@@ -587,7 +590,7 @@ static int capture_iteration(dfdg_ctx* ctx, int parity, Step step, hipGraphExec_
 // later chunks follow the mean contraction of (r, r) observed so far, so that few
 // iterations run past the end (those exit at their first instruction).
 template <typename Step>
-static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[2], int* hint,
+static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[4], int* hint,
                     PcgScalars& fin) {
   // the first chunk is enqueued right after the initialisation, without reading the
   // scalars first (a run that is already over, e.g. for a zero right-hand side, makes those
@@ -595,9 +598,9 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   int rc = DFDG_OK;
   const bool use_graph = ctx->prm.graphs != 0;
   if (use_graph)
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
       if (!graph[j]) {
-        rc = capture_iteration(ctx, j, step, &graph[j]);
+        rc = capture_iteration(ctx, j & 1, j < 2 ? 1 : 2, step, &graph[j]);
         if (rc) return rc;
       }
   const bool amg = ctx->prm.precond == DFDG_AMG;
@@ -606,13 +609,16 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   fin.done = PCG_RUNNING;
   int launched = 0;
   while (fin.done == PCG_RUNNING) {
-    for (int c = 0; c < chunk; ++c) {
+    for (int c = 0; c < chunk;) {
       const int it = launched + 1 + c;
-      if (use_graph) {
-        HIPC(hipGraphLaunch(graph[it & 1], ctx->stream));
+      if (use_graph) {  // pairs of iterations where the chunk allows (fewer graph launches)
+        const int two = chunk - c >= 2;
+        HIPC(hipGraphLaunch(graph[2 * two + (it & 1)], ctx->stream));
+        c += 1 + two;
       } else {
         hipError_t e = step(it, ctx->stream);
         if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
+        ++c;
       }
     }
     launched += chunk;
