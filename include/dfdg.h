@@ -77,9 +77,10 @@ typedef struct {
   double cg_rtol;    /* PCG stop: ||g - S lambda||_2 <= cg_rtol ||g||_2 (FP64 path) */
   int cg_maxit;      /* PCG iteration limit per solve */
   int precond;       /* DFDG_JACOBI, DFDG_BLOCK_JACOBI, or DFDG_AMG: one smoothed-
-                        aggregation multigrid V-cycle (Chebyshev(2) smoothing, coarse
-                        space spanned by the constant multiplier, built on the host at
-                        context creation) */
+                        aggregation multigrid V-cycle (Chebyshev(2) smoothing on the
+                        finest level, one Chebyshev(1) step before and after the
+                        correction on the coarser levels; coarse space spanned by the
+                        constant multiplier; built on the host at context creation) */
   double ir_rtol;    /* MIXED: outer FP64 refinement target (relative residual) */
   double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
   int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,

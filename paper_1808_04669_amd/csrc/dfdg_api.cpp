@@ -364,22 +364,25 @@ static void carve(dfdg_ctx* ctx, char* base) {
     MgVec<double>& v = mg.v64[l];
     v.b = (l > 0) ? c.take<double>(n) : nullptr;
     v.z = (l > 0) ? c.take<double>(n) : nullptr;
-    const bool coarsest = (l == mg.nlev - 1);
-    v.x = coarsest ? nullptr : c.take<double>(n);
-    v.y = coarsest ? nullptr : c.take<double>(n);
-    v.d = coarsest ? nullptr : c.take<double>(n);
-    v.r = coarsest ? nullptr : c.take<double>(n);
+    // work vectors of the two-step smoothing (finest level only; the coarser levels keep
+    // only their right-hand side b and result z)
+    const bool fine = (l == 0 && mg.nlev > 1);
+    v.x = fine ? c.take<double>(n) : nullptr;
+    v.y = fine ? c.take<double>(n) : nullptr;
+    v.d = fine ? c.take<double>(n) : nullptr;
+    v.r = fine ? c.take<double>(n) : nullptr;
     MgVec<float>& w = mg.v32[l];
     w = MgVec<float>{};
     if (f32) {
       w.b = (l > 0) ? c.take<float>(n) : nullptr;
       w.z = (l > 0) ? c.take<float>(n) : nullptr;
-      w.x = coarsest ? nullptr : c.take<float>(n);
-      w.y = coarsest ? nullptr : c.take<float>(n);
-      w.d = coarsest ? nullptr : c.take<float>(n);
-      w.r = coarsest ? nullptr : c.take<float>(n);
+      w.x = fine ? c.take<float>(n) : nullptr;
+      w.y = fine ? c.take<float>(n) : nullptr;
+      w.d = fine ? c.take<float>(n) : nullptr;
+      w.r = fine ? c.take<float>(n) : nullptr;
     }
-    // Chebyshev(2) on [lmax/30, lmax], lmax = 1.05 rho(D^{-1} A)
+    // Chebyshev on [lmax/30, lmax], lmax = 1.05 rho(D^{-1} A): degree 2 on the finest level,
+    // degree 1 (damped Jacobi with weight 1/th) on the coarser ones
     const double lmax = 1.05 * L.lmax, lmin = lmax / 30.0;
     const double th = 0.5 * (lmax + lmin), de = 0.5 * (lmax - lmin);
     const double sig = th / de, rho0 = 1.0 / sig, rho1 = 1.0 / (2.0 * sig - rho0);
@@ -1137,9 +1140,9 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
           const double nn = H.lv[l + 1].A.n;
           if (l == 0) {  // transfers of the finest level
             b += (L.P.nnz() + L.R.nnz()) * (vb + 4.0) + (2.0 * L.A.n + 2.0 * nn) * vb;
-          } else {  // pre-smoothing, fused restriction, fused prolongation + post1, post2
-            b += (3.0 * L.A.nnz() + L.R.nnz() + L.RA.nnz() + L.AP.nnz() + L.P.nnz()) * (vb + 4.0) +
-                 15.0 * L.A.n * vb + 2.0 * nn * vb;
+          } else {  // restriction with the smoothing step, prolongation with the post-smoothing
+            b += (L.A.nnz() + L.R.nnz() + L.RA.nnz() + L.AP.nnz() + L.P.nnz()) * (vb + 4.0) +
+                 5.0 * L.A.n * vb + 2.0 * nn * vb;
           }
         }
         b += H.n_coarse * (double)H.n_coarse * vb;

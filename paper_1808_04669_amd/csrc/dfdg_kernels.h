@@ -30,7 +30,7 @@ int facet_grid_size(int E);  // G: blocks of the facet kernels
 
 // Multigrid hierarchy on the device (level 0 = the BSR facet matrix itself).
 constexpr int kMaxLev = 16;
-struct CheB { double th, c1, c2; };  // Chebyshev(2) smoothing constants of a level
+struct CheB { double th, c1, c2; };  // Chebyshev smoothing constants of a level
 // Coarse-level sparse matrix in padded row-major (ELL) form: row i holds its entries at
 // [i*w, i*w + w); the padding repeats a column of the row with value 0.  A fixed row
 // width lets a kernel load columns and values at once, without first reading a row pointer.

@@ -946,8 +946,9 @@ __global__ __launch_bounds__(kBlk) void k_finalize_ir(const double* __restrict__
 // ---------------------------------------------------------------------------------------
 // a5: multigrid V-cycle preconditioner for the facet PCG (smoothed aggregation)
 // ---------------------------------------------------------------------------------------
-// Per level: Chebyshev(2) smoothing with the point-Jacobi scaling D^{-1}, residual,
-// restriction R = P^T, coarse correction, prolongation, Chebyshev(2) post-smoothing.
+// Finest level: Chebyshev(2) smoothing with the point-Jacobi scaling D^{-1}, residual,
+// restriction R = P^T, coarse correction, prolongation, Chebyshev(2) post-smoothing (the
+// coarser levels use degree 1, see k_mgc_restrict).
 // With th, de the centre and half-width of the smoothing interval, c1 = rho1 rho0 and
 // c2 = 2 rho1 / de (rho0 = de/th, rho1 = 1/(2 th/de - rho0)):
 //   pre  (x0 = 0):  x1 = D^{-1} b / th,  x2 = (1 + c1) x1 + c2 D^{-1} (b - A x1)
@@ -1095,72 +1096,47 @@ __device__ inline V csr_row_group(const DevCsr& A, const V* __restrict__ vals, i
   return group_sum<LPR, V>(i < A.n ? ell_part<LPR, V>(A, i, sub, x) : (V)0);
 }
 
-template <int LPR, typename V>
-__global__ __launch_bounds__(kBlk) void k_mgc_pre(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
-                                                  V* __restrict__ x2, CheB cb, const PcgScalars* sc) {
-  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = g / LPR, sub = g % LPR;
-  const V ith = (V)(1.0 / cb.th);
-  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return dinv[c] * b[c] * ith; });
-  if (live && i < A.n && sub == 0) {
-    const V x1 = dinv[i] * b[i] * ith;
-    x2[i] = (1 + (V)cb.c1) * x1 + (V)cb.c2 * dinv[i] * (b[i] - s);
-  }
-}
-
-template <int LPR, typename V>
-__global__ __launch_bounds__(kBlk) void k_mgc_post2(DevCsr A, const V* __restrict__ dinv, const V* __restrict__ b,
-                                                    const V* __restrict__ x4, const V* __restrict__ d,
-                                                    V* __restrict__ z, CheB cb, const PcgScalars* sc) {
-  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = g / LPR, sub = g % LPR;
-  const V s = csr_row_group<LPR, V>(A, csr_vals<V>(A), i, sub, [&](int c) { return x4[c]; });
-  if (live && i < A.n && sub == 0) z[i] = x4[i] + (V)cb.c1 * d[i] + (V)cb.c2 * dinv[i] * (b[i] - s);
-}
-
-// Coarse levels, restriction of the pre-smoothed residual in one pass:
-// b_c = R (b - A x2) = R b - (R A) x2 with R A precomputed, so that the residual of the
-// level is never stored.
+// Coarse levels (below the finest) smooth with one Chebyshev(1) step, i.e. damped Jacobi
+// with weight 1/th, before and after the coarse correction: x1 = D^{-1} b / th, and after
+// the correction x3 = x1 + P e, z = x3 + D^{-1} (b - A x3) / th.  Two kernels per level:
+//   restriction of the smoothed residual, b_c = R (b - A x1) = R b - (R A) x1, with R A
+//   precomputed and x1 formed on the fly (neither x1 nor the residual is stored);
+//   prolongation fused with the post-smoothing step, A x3 = A x1 + (A P) e.
 template <int LPR, typename V>
 __global__ __launch_bounds__(kBlk) void k_mgc_restrict(DevCsr R, DevCsr RA, const V* __restrict__ b,
-                                                       const V* __restrict__ x2, V* __restrict__ bc,
+                                                       const V* __restrict__ dinv, CheB cb, V* __restrict__ bc,
                                                        const PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the store only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
+  const V ith = (V)(1.0 / cb.th);
   V s = 0;
   if (i < R.n)
     s = ell_part<LPR, V>(R, i, sub, [&](int c) { return b[c]; }) -
-        ell_part<LPR, V>(RA, i, sub, [&](int c) { return x2[c]; });
+        ell_part<LPR, V>(RA, i, sub, [&](int c) { return dinv[c] * b[c] * ith; });
   s = group_sum<LPR, V>(s);
   if (live && i < R.n && sub == 0) bc[i] = s;
 }
 
-// Coarse levels, prolongation-add fused with the first post-smoothing step:
-// x3 = x2 + P e and A x3 = A x2 + (A P) e with A P precomputed; d = D^{-1} (b - A x3) / th,
-// x4 = x3 + d.
 template <int LPR, typename V>
-__global__ __launch_bounds__(kBlk) void k_mgc_post1p(DevCsr A, DevCsr AP, DevCsr P, const V* __restrict__ dinv,
-                                                     const V* __restrict__ b, const V* __restrict__ x2,
-                                                     const V* __restrict__ e, V* __restrict__ x4,
-                                                     V* __restrict__ d, CheB cb, const PcgScalars* sc) {
-  const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
+__global__ __launch_bounds__(kBlk) void k_mgc_post(DevCsr A, DevCsr AP, DevCsr P, const V* __restrict__ dinv,
+                                                   const V* __restrict__ b, const V* __restrict__ e,
+                                                   V* __restrict__ z, CheB cb, const PcgScalars* sc) {
+  const bool live = sc->done == PCG_RUNNING;  // tested before the store only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
+  const V ith = (V)(1.0 / cb.th);
   V pe = 0, ax = 0;
   if (i < A.n) {
     pe = ell_part<LPR, V>(P, i, sub, [&](int c) { return e[c]; });
-    ax = ell_part<LPR, V>(A, i, sub, [&](int c) { return x2[c]; }) +
+    ax = ell_part<LPR, V>(A, i, sub, [&](int c) { return dinv[c] * b[c] * ith; }) +
          ell_part<LPR, V>(AP, i, sub, [&](int c) { return e[c]; });
   }
   pe = group_sum<LPR, V>(pe);
   ax = group_sum<LPR, V>(ax);
   if (live && i < A.n && sub == 0) {
-    const V dd = dinv[i] * (b[i] - ax) * (V)(1.0 / cb.th);
-    d[i] = dd;
-    x4[i] = (x2[i] + pe) + dd;
+    const V x1 = dinv[i] * b[i] * ith;
+    z[i] = (x1 + pe) + dinv[i] * (b[i] - ax) * ith;
   }
 }
 
@@ -1658,16 +1634,11 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
   csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, sc, s);
   for (int l = 1; l < L - 1; ++l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
-    const DevCsr& Al = mg.A[l];
-    const V* dinv = mg_dinv<V>(mg, l);
-    const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
-    DFDG_DISPATCH_LPR(Al.lpr, hipLaunchKernelGGL((k_mgc_pre<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv,
-                                                 (const V*)v.b, v.x, mg.cheb[l], sc));
     const DevCsr& R = mg.R[l];
     const DevCsr& RA = mg.RA[l];
     DFDG_DISPATCH_LPR(std::max(R.lpr, RA.lpr),
-                      hipLaunchKernelGGL((k_mgc_restrict<LP, V>), dim3(nblk((long)R.n * LP, kBlk)), dim3(kBlk), 0, s,
-                                         R, RA, (const V*)v.b, (const V*)v.x, mg_vec<V>(mg, l + 1).b, sc));
+                      hipLaunchKernelGGL((k_mgc_restrict<LP, V>), dim3(nblk((long)R.n * LP, kBlk)), dim3(kBlk), 0, s, R,
+                                         RA, (const V*)v.b, mg_dinv<V>(mg, l), mg.cheb[l], mg_vec<V>(mg, l + 1).b, sc));
   }
   {
     const MgVec<V>& vc = mg_vec<V>(mg, L - 1);
@@ -1677,16 +1648,12 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
   for (int l = L - 2; l >= 1; --l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
     const DevCsr& Al = mg.A[l];
-    const V* dinv = mg_dinv<V>(mg, l);
-    const unsigned nb = nblk((long)Al.n * Al.lpr, kBlk);
     const DevCsr& AP = mg.AP[l];
     const DevCsr& P = mg.P[l];
     DFDG_DISPATCH_LPR(std::max(Al.lpr, std::max(AP.lpr, P.lpr)),
-                      hipLaunchKernelGGL((k_mgc_post1p<LP, V>), dim3(nblk((long)Al.n * LP, kBlk)), dim3(kBlk), 0, s,
-                                         Al, AP, P, dinv, (const V*)v.b, (const V*)v.x,
-                                         (const V*)mg_vec<V>(mg, l + 1).z, v.y, v.d, mg.cheb[l], sc));
-    DFDG_DISPATCH_LPR(Al.lpr, hipLaunchKernelGGL((k_mgc_post2<LP, V>), dim3(nb), dim3(kBlk), 0, s, Al, dinv,
-                                                 (const V*)v.b, (const V*)v.y, (const V*)v.d, v.z, mg.cheb[l], sc));
+                      hipLaunchKernelGGL((k_mgc_post<LP, V>), dim3(nblk((long)Al.n * LP, kBlk)), dim3(kBlk), 0, s, Al,
+                                         AP, P, mg_dinv<V>(mg, l), (const V*)v.b, (const V*)mg_vec<V>(mg, l + 1).z, v.z,
+                                         mg.cheb[l], sc));
   }
   csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, sc, s);
   DFDG_DISPATCH_NF_VOID(NF, {

@@ -24,14 +24,16 @@ def _log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "amg", "amg_fp32_fine"])
+@pytest.mark.parametrize("precond", ["jacobi", "amg", "amg_fp32_fine", "amg_fp64_cycle"])
 @pytest.mark.parametrize("k,N,order", CASES + [(1, 1, "lex"), (2, 2, "morton")])
 def test_mass_solve_parity(k, N, order, precond):
     """Divergence-free mass inversion of a random broken polynomial functional (Theorems 1-2).
-    amg: the multigrid smoothing on the finest level reads S in FP16 (the default);
-    amg_fp32_fine: in FP32."""
+    amg: FP32 V-cycle whose finest-level smoothing reads S in FP16 (the default);
+    amg_fp32_fine: S in FP32 there; amg_fp64_cycle: the whole V-cycle in FP64."""
     _log("mass_solve", k, N, order, precond)
-    kw = dict(precond="amg", mg_fine_fp16=False) if precond == "amg_fp32_fine" else dict(precond=precond)
+    kw = {"jacobi": dict(precond="jacobi"), "amg": dict(precond="amg"),
+          "amg_fp32_fine": dict(precond="amg", mg_fine_fp16=False),
+          "amg_fp64_cycle": dict(precond="amg", mg_fp32=False)}[precond]
     orc, s, _, _ = make_pair(N, k, order=order, seed=N, cg_rtol=1e-13, **kw)
     coef = random_broken_poly(s.T, k, seed=10 + k)
     F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
