@@ -339,7 +339,8 @@ static void carve(dfdg_ctx* ctx, char* base) {
     while (D.lpr < 64 && 2 * D.lpr <= avg) D.lpr *= 2;
     int wmax = 1;
     for (int i = 0; i < M.n; ++i) wmax = std::max(wmax, M.ptr[i + 1] - M.ptr[i]);
-    D.w = (wmax + D.lpr - 1) / D.lpr * D.lpr;
+    if (wmax <= 4) D.lpr = 1;  // short rows: one lane reads its whole row at once (16-byte loads)
+    D.w = wmax <= 4 ? 4 : (wmax + D.lpr - 1) / D.lpr * D.lpr;
     const size_t ne = (size_t)M.n * D.w;
     D.col = c.take<int>(ne);
     D.val = c.take<double>(ne);

@@ -1147,7 +1147,16 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
-  const V s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
+  V s = 0;
+  if (LPR == 1 && M.w == 4) {  // rows of 4 entries, 16-byte aligned: vector loads
+    if (i < M.n) {
+      const int4 c = *reinterpret_cast<const int4*>(M.col + (size_t)i * 4);
+      const V* v = csr_vals<V>(M) + (size_t)i * 4;
+      s = v[0] * x[c.x] + v[1] * x[c.y] + v[2] * x[c.z] + v[3] * x[c.w];
+    }
+  } else {
+    s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
+  }
   if (live && i < M.n && sub == 0) y[i] = add ? y0[i] + s : s;
 }
 
