@@ -382,9 +382,10 @@ static void carve(dfdg_ctx* ctx, char* base) {
       w.d = fine ? c.take<float>(n) : nullptr;
       w.r = fine ? c.take<float>(n) : nullptr;
     }
-    // Chebyshev on [lmax/30, lmax], lmax = 1.05 rho(D^{-1} A): degree 2 on the finest level,
-    // degree 1 (damped Jacobi with weight 1/th) on the coarser ones
-    const double lmax = 1.05 * L.lmax, lmin = lmax / 30.0;
+    // Chebyshev on [lmin, lmax], lmax = 1.05 rho(D^{-1} A): degree 2 on [lmax/15, lmax] on the
+    // finest level, degree 1 (damped Jacobi with weight 1/th) on [lmax/30, lmax] on the
+    // coarser ones (intervals chosen by the PCG iteration count they give)
+    const double lmax = 1.05 * L.lmax, lmin = lmax / (l == 0 ? 15.0 : 30.0);
     const double th = 0.5 * (lmax + lmin), de = 0.5 * (lmax - lmin);
     const double sig = th / de, rho0 = 1.0 / sig, rho1 = 1.0 / (2.0 * sig - rho0);
     mg.cheb[l] = CheB{th, rho1 * rho0, 2.0 * rho1 / de};
