@@ -331,12 +331,12 @@ static void carve(dfdg_ctx* ctx, char* base) {
   mg = MgDev{};
   const AmgHierarchy& H = ctx->H;
   mg.nlev = (int)H.lv.size();
-  auto take_csr = [&](const Csr& M, DevCsr& D) {
+  // lanes per row: the largest power of two not above the mean row length / div (<= 64)
+  auto take_csr = [&](const Csr& M, DevCsr& D, int div) {
     D.n = M.n;
-    // lanes per row: the largest power of two not above the mean row length (<= 64)
     const double avg = M.n ? (double)M.nnz() / M.n : 1.0;
     D.lpr = 1;
-    while (D.lpr < 64 && 2 * D.lpr <= avg) D.lpr *= 2;
+    while (D.lpr < 64 && 2 * D.lpr * div <= avg) D.lpr *= 2;
     int wmax = 1;
     for (int i = 0; i < M.n; ++i) wmax = std::max(wmax, M.ptr[i + 1] - M.ptr[i]);
     if (wmax <= 4) D.lpr = 1;  // short rows: one lane reads its whole row at once (16-byte loads)
@@ -350,16 +350,18 @@ static void carve(dfdg_ctx* ctx, char* base) {
     const AmgLevel& L = H.lv[l];
     const long n = L.A.n;
     if (l > 0) {
-      take_csr(L.A, mg.A[l]);
+      take_csr(L.A, mg.A[l], 1);
       mg.dinv[l] = c.take<double>(n);
       mg.dinv32[l] = f32 ? c.take<float>(n) : nullptr;
     }
     if (l < mg.nlev - 1) {
-      take_csr(L.P, mg.P[l]);
-      take_csr(L.R, mg.R[l]);
+      // the restriction from the finest level gathers from the largest vector: a few
+      // lanes per row, each with several entries, keep more of those gathers in flight
+      take_csr(L.P, mg.P[l], 1);
+      take_csr(L.R, mg.R[l], l == 0 ? 8 : 1);
       if (l > 0) {
-        take_csr(L.AP, mg.AP[l]);
-        take_csr(L.RA, mg.RA[l]);
+        take_csr(L.AP, mg.AP[l], 1);
+        take_csr(L.RA, mg.RA[l], 1);
       }
     }
     MgVec<double>& v = mg.v64[l];
