@@ -52,9 +52,9 @@ struct dfdg_ctx {
   double* lamx = nullptr;
   hipStream_t cap_stream = nullptr;
   // one graph per iteration parity ([1]: odd iterations, [0]: even), FP64 and FP32 PCG
-  // captured PCG iterations: [0], [1] one iteration of even / odd parity; [2], [3] two
-  // consecutive iterations starting with even / odd parity
-  hipGraphExec_t graph64[4] = {}, graph32[4] = {};
+  // captured PCG iterations: [2j + p] holds 2^j consecutive iterations (j = 0, 1, 2)
+  // starting with parity p (0 even, 1 odd)
+  hipGraphExec_t graph64[6] = {}, graph32[6] = {};
   int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
   std::string err;
@@ -536,7 +536,7 @@ extern "C" const char* dfdg_last_error(const dfdg_ctx* ctx) {
 
 extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
   if (!ctx) return;
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < 6; ++j) {
     if (ctx->graph64[j]) (void)hipGraphExecDestroy(ctx->graph64[j]);
     if (ctx->graph32[j]) (void)hipGraphExecDestroy(ctx->graph32[j]);
   }
@@ -597,7 +597,7 @@ static int capture_iteration(dfdg_ctx* ctx, int parity, int count, Step step, hi
 // later chunks follow the mean contraction of (r, r) observed so far, so that few
 // iterations run past the end (those exit at their first instruction).
 template <typename Step>
-static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[4], int* hint,
+static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGraphExec_t (&graph)[6], int* hint,
                     PcgScalars& fin) {
   // the first chunk is enqueued right after the initialisation, without reading the
   // scalars first (a run that is already over, e.g. for a zero right-hand side, makes those
@@ -605,9 +605,9 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   int rc = DFDG_OK;
   const bool use_graph = ctx->prm.graphs != 0;
   if (use_graph)
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < 6; ++j)
       if (!graph[j]) {
-        rc = capture_iteration(ctx, j & 1, j < 2 ? 1 : 2, step, &graph[j]);
+        rc = capture_iteration(ctx, j & 1, 1 << (j >> 1), step, &graph[j]);
         if (rc) return rc;
       }
   const bool amg = ctx->prm.precond == DFDG_AMG;
@@ -618,10 +618,10 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   while (fin.done == PCG_RUNNING) {
     for (int c = 0; c < chunk;) {
       const int it = launched + 1 + c;
-      if (use_graph) {  // pairs of iterations where the chunk allows (fewer graph launches)
-        const int two = chunk - c >= 2;
-        HIPC(hipGraphLaunch(graph[2 * two + (it & 1)], ctx->stream));
-        c += 1 + two;
+      if (use_graph) {  // groups of 4 or 2 iterations where the chunk allows (fewer graph launches)
+        const int j = chunk - c >= 4 ? 2 : (chunk - c >= 2 ? 1 : 0);
+        HIPC(hipGraphLaunch(graph[2 * j + (it & 1)], ctx->stream));
+        c += 1 << j;
       } else {
         hipError_t e = step(it, ctx->stream);
         if (e != hipSuccess) return fail(ctx, DFDG_E_HIP, std::string("PCG launch: ") + hipGetErrorString(e));
