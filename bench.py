@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--precond", default="amg", choices=["jacobi", "block_jacobi", "amg"])
-    ap.add_argument("--extrapolate", type=int, default=4)
+    ap.add_argument("--extrapolate", default="adaptive",
+                    help="warm-start extrapolation order 0..4, or adaptive (chosen per solve)")
     ap.add_argument("--order", default="morton")
     ap.add_argument("--no-mg-fp16", action="store_true",
                     help="finest-level multigrid smoothing reads S in FP32 instead of FP16")

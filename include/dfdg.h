@@ -63,7 +63,8 @@ enum {
 };
 
 enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
-#define DFDG_HISTORY_DEPTH 5  /* earlier multipliers kept per stage for warm starts */
+#define DFDG_HISTORY_DEPTH 6  /* earlier multipliers kept per stage for warm starts */
+#define DFDG_EXTRAPOLATE_ADAPTIVE 5  /* dfdg_params.extrapolate: order chosen per solve */
 enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1, DFDG_AMG = 2 };  /* dfdg_params.precond */
 
 typedef struct dfdg_mesh dfdg_mesh;
@@ -85,7 +86,10 @@ typedef struct {
   double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
   int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,
                         1..4 = polynomial extrapolation of that order in time from the
-                        last extrapolate+1 steps (at most DFDG_HISTORY_DEPTH are kept) */
+                        last extrapolate+1 steps, DFDG_EXTRAPOLATE_ADAPTIVE = the order
+                        1..4 whose prediction of the last multiplier from the ones before
+                        it was best (decided on the device per solve, among the orders the
+                        DFDG_HISTORY_DEPTH kept multipliers allow) */
   int graphs;        /* 1: replay PCG iterations from captured HIP graphs (default);
                         0: launch every kernel individually.  Same results bit for bit. */
   int mg_fp32;       /* DFDG_AMG with DFDG_FP64: 1 = run the V-cycle in FP32 (default; the

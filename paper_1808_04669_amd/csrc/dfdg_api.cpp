@@ -37,7 +37,7 @@ struct dfdg_ctx {
   // work buffers
   double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
          *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][kHistDepth] = {}, *evaltab = nullptr,
-         *partials = nullptr, *diagres = nullptr, *r64 = nullptr;
+         *partials = nullptr, *diagres = nullptr, *r64 = nullptr, *xpart = nullptr;
   float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *r32b = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
         *Sp32 = nullptr;
   PcgBufs pb{}, pb32{}, pbt{};  // FP64 PCG / refinement, FP32 inner PCG, kernel timing
@@ -137,6 +137,9 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->mg_fine_fp16 = 1;
 }
 
+static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
+static_assert(DFDG_EXTRAPOLATE_ADAPTIVE == kExtrapAdaptive, "adaptive extrapolation value");
+
 static int check_params(const dfdg_params* p, std::string& e) {
   if (p->k < 1 || p->k > kMaxK) { e = "k must be in 1..3"; return -1; }
   if (!(p->nu >= 0) || !std::isfinite(p->nu)) { e = "nu must be finite and >= 0"; return -1; }
@@ -152,7 +155,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
     if (!(p->ir_rtol > 0 && p->ir_rtol < 1)) { e = "ir_rtol must be in (0,1)"; return -1; }
     if (!(p->inner_rtol > 0 && p->inner_rtol < 1)) { e = "inner_rtol must be in (0,1)"; return -1; }
   }
-  if (p->extrapolate < 0 || p->extrapolate >= kHistDepth) { e = "extrapolate must be in 0..4"; return -1; }
+  if (p->extrapolate < 0 || p->extrapolate > kExtrapAdaptive) { e = "extrapolate must be in 0..4 or DFDG_EXTRAPOLATE_ADAPTIVE"; return -1; }
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
@@ -304,6 +307,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
   ctx->partials = c.take<double>(4 * maxblk);
   ctx->diagres = c.take<double>(4);
+  ctx->xpart = c.take<double>(kExtrapParts);
   const long G = facet_grid_size((int)E);
   for (PcgBufs* pb : {&ctx->pb, &ctx->pb32, &ctx->pbt}) {
     pb->sc = c.take<PcgScalars>(1);
@@ -855,7 +859,7 @@ extern "C" int dfdg_history_restore(dfdg_ctx* ctx, const double* hist, const int
   NEED_BOUND(ctx);
   if (!hist || !counts) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   for (int st = 0; st < 3; ++st)
-    if (counts[st] < 0 || counts[st] > kHistDepth) return fail(ctx, DFDG_E_INVALID_ARG, "history counts must be in 0..5");
+    if (counts[st] < 0 || counts[st] > kHistDepth) return fail(ctx, DFDG_E_INVALID_ARG, "history counts must be in 0..6");
   const size_t nL = ctx->nL, nb = nL * sizeof(double);
   for (int st = 0; st < 3; ++st) {
     for (int j = 0; j < counts[st]; ++j)
@@ -871,9 +875,16 @@ static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
   const int n = ctx->hist_count[s];
   *cold = (n == 0);
   if (n == 0) return DFDG_OK;
-  const int order = std::min(ctx->prm.extrapolate, n - 1);
   HistPtrs h;
   for (int j = 0; j < kHistDepth; ++j) h.p[j] = ctx->hist[s][j];
+  if (ctx->prm.extrapolate == kExtrapAdaptive) {
+    const int omax = std::min(4, n - 2);  // a backtest of order o needs o + 2 multipliers
+    if (omax >= 1) {
+      HIPC(launch_extrapolate_adaptive(ctx->nL, omax, h, ctx->xpart, ctx->lamw, ctx->stream));
+      return DFDG_OK;
+    }
+  }
+  const int order = std::min(std::min(ctx->prm.extrapolate, 4), n - 1);
   HIPC(launch_extrapolate(ctx->nL, order, h, ctx->lamw, ctx->stream));
   return DFDG_OK;
 }

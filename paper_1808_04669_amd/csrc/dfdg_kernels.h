@@ -131,10 +131,17 @@ hipError_t launch_diagnostics(int K, const DevGeo& g, const DevTabs& tb, const d
 // Linear combination y = a x + b y on n doubles.
 hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, hipStream_t s);
 // Warm-start history: up to kHistDepth earlier multipliers, p[0] the newest.
-constexpr int kHistDepth = 5;
+constexpr int kHistDepth = 6;
+constexpr int kExtrapAdaptive = 5;  // dfdg_params.extrapolate value of the adaptive choice
 struct HistPtrs { const double* p[kHistDepth]; };
-// out = extrapolation of order `order` (< kHistDepth) in time from p[0..order].
+// out = extrapolation of order `order` (<= 4) in time from p[0..order].
 hipError_t launch_extrapolate(long n, int order, const HistPtrs& h, double* out, hipStream_t s);
+// out = extrapolation from p[0..o] with the order o in 1..omax (omax <= min(4, kHistDepth - 2))
+// whose prediction of p[0] from p[1..o+1] has the smallest squared error; part: scratch
+// for kExtrapParts doubles.
+constexpr int kExtrapParts = 4 * 1024;
+hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, double* part, double* out,
+                                       hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
 // out[i] = FP16 bits of x[i] * scale (round to nearest even).
 hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s);

@@ -1420,15 +1420,51 @@ __global__ void k_fill(long n, double v, double* __restrict__ y) {
 // Polynomial extrapolation in time from h0 (newest), h1, h2 (oldest), equal spacing.
 // Lagrange extrapolation to the next equally spaced time from the last order+1 values
 // (h.p[0] newest): coefficients (-1)^j C(order+1, j+1).
+// Extrapolation of order o in time from q[0..o] (newest first), equal time steps:
+// sum_j (-1)^j C(o+1, j+1) q[j].
+template <typename Q>
+__device__ inline double extrapolate_at(int order, Q q) {
+  double v = 0, c = order + 1;  // C(order+1, 1)
+  for (int j = 0; j <= order; ++j) {
+    v += ((j & 1) ? -c : c) * q(j);
+    c = c * (order - j) / (j + 2);  // C(order+1, j+2)
+  }
+  return v;
+}
+
 __global__ void k_extrapolate(long n, int order, HistPtrs h, double* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double v = 0, c = order + 1;  // C(order+1, 1)
-  for (int j = 0; j <= order; ++j) {
-    v += ((j & 1) ? -c : c) * h.p[j][i];
-    c = c * (order - j) / (j + 2);  // C(order+1, j+2)
+  out[i] = extrapolate_at(order, [&](int j) { return h.p[j][i]; });
+}
+
+// One-step backtest of the orders 1..omax: squared error of the prediction of p[0] from
+// p[1..o+1], one partial per block and order (grid-stride).
+__global__ __launch_bounds__(kBlk) void k_extrap_backtest(long n, int omax, HistPtrs h, double* __restrict__ part) {
+  double e[4] = {0, 0, 0, 0};
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double target = h.p[0][i];
+#pragma unroll
+    for (int o = 1; o <= 4; ++o)
+      if (o <= omax) {
+        const double d = extrapolate_at(o, [&](int j) { return h.p[j + 1][i]; }) - target;
+        e[o - 1] += d * d;
+      }
   }
-  out[i] = v;
+  block_write_partial<4>(e, part);
+}
+
+// Extrapolation with the order of least backtest error (every block sums the partials in
+// the same order, so all take the same decision; ties keep the lower order).
+__global__ __launch_bounds__(kBlk) void k_extrapolate_pick(long n, int omax, HistPtrs h, const double* __restrict__ part,
+                                                           int nparts, double* __restrict__ out) {
+  double e[4];
+  block_sum_partials<4>(part, nparts, e);
+  int best = 1;
+  for (int o = 2; o <= omax; ++o)
+    if (e[o - 1] < e[best - 1]) best = o;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    out[i] = extrapolate_at(best, [&](int j) { return h.p[j][i]; });
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1771,6 +1807,14 @@ hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
 hipError_t launch_extrapolate(long n, int order, const HistPtrs& h, double* out, hipStream_t s) {
   if (order < 0 || order >= kHistDepth) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_extrapolate, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, order, h, out);
+  return hipGetLastError();
+}
+hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, double* part, double* out,
+                                       hipStream_t s) {
+  if (omax < 1 || omax > 4 || omax > kHistDepth - 2) return hipErrorInvalidValue;
+  const int G = (int)std::min<long>(nblk(n, kBlk), kExtrapParts / 4);
+  hipLaunchKernelGGL(k_extrap_backtest, dim3(G), dim3(kBlk), 0, s, n, omax, h, part);
+  hipLaunchKernelGGL(k_extrapolate_pick, dim3(G), dim3(kBlk), 0, s, n, omax, h, (const double*)part, G, out);
   return hipGetLastError();
 }
 

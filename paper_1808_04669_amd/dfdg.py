@@ -19,6 +19,8 @@ STATUS = {0: "OK", -1: "E_INVALID_ARG", -2: "E_MESH", -3: "E_WORKSPACE", -4: "E_
           -5: "E_NOT_CONVERGED", -6: "E_NONFINITE", -7: "E_BREAKDOWN", -8: "E_UNSUPPORTED"}
 FP64, MIXED = 0, 1
 JACOBI, BLOCK_JACOBI, AMG = 0, 1, 2
+HISTORY_DEPTH = 6  # DFDG_HISTORY_DEPTH: earlier multipliers kept per stage
+EXTRAPOLATE_ADAPTIVE = 5  # extrapolate="adaptive": order chosen per solve by a one-step backtest
 
 
 class DfdgError(RuntimeError):
@@ -172,7 +174,8 @@ class Solver:
         p.precision = {"fp64": FP64, "mixed": MIXED}[precision]
         p.cg_rtol, p.cg_maxit = float(cg_rtol), int(cg_maxit)
         p.precond = {"jacobi": JACOBI, "block_jacobi": BLOCK_JACOBI, "amg": AMG}[precond]
-        p.ir_rtol, p.inner_rtol, p.extrapolate = float(ir_rtol), float(inner_rtol), int(extrapolate)
+        p.ir_rtol, p.inner_rtol = float(ir_rtol), float(inner_rtol)
+        p.extrapolate = EXTRAPOLATE_ADAPTIVE if extrapolate == "adaptive" else int(extrapolate)
         p.graphs = 1 if graphs else 0
         p.mg_fp32 = 1 if mg_fp32 else 0
         p.mg_fine_fp16 = 1 if mg_fine_fp16 else 0

@@ -175,8 +175,9 @@ def test_history_restore_repeats_the_trajectory_bitwise():
     _log("history restore", its_a, its_b)
     assert its_a == its_b
     assert torch.equal(U, V)
+    from paper_1808_04669_amd.dfdg import HISTORY_DEPTH
     with pytest.raises(Exception):
-        s.history_restore((snap[0], (6, 0, 0)))
+        s.history_restore((snap[0], (HISTORY_DEPTH + 1, 0, 0)))
 
 
 def test_pipelined_reverse_sweep_equals_sequential():

@@ -99,7 +99,7 @@ def test_param_validation_and_unbound_calls(lib):
     xyz, per = periodic_split_square(2)
     rc, m = _mesh(lib, xyz, per)
     for kw in [dict(k=0), dict(k=4), dict(nu=-1.0), dict(alpha=0.0), dict(precision=7),
-               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=5), dict(extrapolate=-1), dict(graphs=2), dict(mg_fp32=3), dict(mg_fine_fp16=2)]:
+               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=6), dict(extrapolate=-1), dict(graphs=2), dict(mg_fp32=3), dict(mg_fine_fp16=2)]:
         assert _ctx(lib, m, **kw)[0] == -1, kw
     rc, c = _ctx(lib, m, k=2)
     assert rc == 0
