@@ -226,3 +226,33 @@ def test_energy_gradient_vs_oracle_and_fd(precond):
         _log("  dE.d gpu", gpu, "oracle", ref, "fd", fd)
         assert abs(gpu - ref) < 1e-8 * abs(ref) + 1e-12
         assert abs(gpu - fd) < 1e-6 * abs(fd) + 1e-10
+
+
+def test_adaptive_warm_start_order():
+    """Adaptive warm starts (the extrapolation order chosen on the device per solve by a
+    one-step backtest): identical runs are bitwise equal, the trajectory equals a
+    fixed-order one to the solve tolerance, and once the history is full the initial
+    residuals are no larger than those of the plain previous-multiplier start."""
+    from gpu_util import project_field
+    from inputs import taylor_green_2d
+    runs = {}
+    for name, order in (("a", "adaptive"), ("b", "adaptive"), ("o0", 0), ("o2", 2)):
+        _, s, xyz, _ = make_pair(32, 2, nu=1e-3, order="morton", oracle=False, cg_rtol=1e-13, precond="amg",
+                                 extrapolate=order)
+        U, vmax = project_field(s, xyz, lambda x, y: taylor_green_2d(x, y))
+        dt = 0.1 / 32 / (4 * vmax)
+        its, r0 = [], []
+        for _ in range(12):
+            info = s.rk3_step(U, dt)
+            assert info.status == 0
+            its.append(list(info.iterations))
+            r0.append(list(info.initial_rel_residual))
+        runs[name] = (U, its, np.array(r0))
+        _log("warm start", name, "iterations", its[-3:], "initial residual", runs[name][2][-3:].mean())
+    Ua, itsa, r0a = runs["a"]
+    Ub, itsb, _ = runs["b"]
+    assert torch.equal(Ua, Ub) and itsa == itsb
+    U2 = runs["o2"][0]
+    assert (Ua - U2).norm().item() < 1e-11 * U2.norm().item()
+    # steps 7..12: six kept multipliers per stage, every order up to 4 can be backtested
+    assert r0a[6:].mean() <= runs["o0"][2][6:].mean()
