@@ -94,7 +94,8 @@ typedef struct {
                         0: launch every kernel individually.  Same results bit for bit. */
   int mg_fp32;       /* DFDG_AMG with DFDG_FP64: 1 = run the V-cycle in FP32 (default; the
                         PCG vectors, residuals and stopping test stay FP64), 0 = FP64 */
-  int mg_fine_fp16;  /* with mg_fp32 = 1: 1 = the V-cycle's smoothing on the finest level
+  int mg_fine_fp16;  /* FP32 V-cycle (mg_fp32 = 1, or a DFDG_MIXED context): 1 = the
+                        V-cycle's smoothing on the finest level
                         reads S stored in FP16 (scaled by the largest |S_ij|; arithmetic in
                         FP32), 0 = S in FP32.  The preconditioner then uses a symmetric
                         perturbation of S of relative size 2^-11; the PCG itself keeps the

@@ -286,7 +286,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.vals32 = f32 ? c.take<float>(h.vals.size()) : nullptr;
   A.dinv32 = f32 ? c.take<float>(h.dinv.size()) : nullptr;
   A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
-  const bool f16 = !mixed && ctx->prm.precond == DFDG_AMG && ctx->prm.mg_fp32 && ctx->prm.mg_fine_fp16;
+  const bool f16 = ctx->prm.precond == DFDG_AMG && (mixed || ctx->prm.mg_fp32) && ctx->prm.mg_fine_fp16;
   A.vals16 = f16 ? c.take<uint16_t>(h.vals.size()) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
