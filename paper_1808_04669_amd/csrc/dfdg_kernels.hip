@@ -62,16 +62,11 @@ __device__ inline void block_write_partial(const double (&v)[NV], double* __rest
 }
 
 // Sum n partials of NV values each; every thread of the block receives the totals.
+// Block-wide sums of per-thread values (fixed order: waves, then the waves' sums).
 template <int NV>
-__device__ inline void block_sum_partials(const double* __restrict__ buf, int n, double (&out)[NV]) {
+__device__ inline void block_sum_values(const double (&acc)[NV], double (&out)[NV]) {
   __shared__ double sh[NV][kBlk / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0;
-  for (int b = threadIdx.x; b < n; b += blockDim.x)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += buf[b * NV + i];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
     const double s = wave_sum(acc[i]);
@@ -85,6 +80,43 @@ __device__ inline void block_sum_partials(const double* __restrict__ buf, int n,
     out[i] = s;
   }
   __syncthreads();
+}
+template <int NV>
+__device__ inline void block_sum_partials(const double* __restrict__ buf, int n, double (&out)[NV]) {
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+  for (int b = threadIdx.x; b < n; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] += buf[b * NV + i];
+  block_sum_values<NV>(acc, out);
+}
+// The same sums in two steps: load this thread's partials (up to kPartsPerThread of them)
+// now, add them up later, so that the loads' latency overlaps other work.
+static constexpr int kMaxFacetGrid = 1024;
+static constexpr int kPartsPerThread = (kMaxFacetGrid + kBlk - 1) / kBlk;
+template <int NV>
+struct PartLoad { double v[kPartsPerThread][NV]; };
+template <int NV>
+__device__ inline void partials_load(const double* __restrict__ buf, int n, bool on, PartLoad<NV>& q) {
+#pragma unroll
+  for (int j = 0; j < kPartsPerThread; ++j) {
+    const int b = threadIdx.x + j * blockDim.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) q.v[j][i] = (on && b < n) ? buf[b * NV + i] : 0.0;
+  }
+}
+template <int NV>
+__device__ inline void partials_sum(const PartLoad<NV>& q, int n, double (&out)[NV]) {
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+#pragma unroll
+  for (int j = 0; j < kPartsPerThread; ++j)
+    if ((int)threadIdx.x + j * (int)blockDim.x < n)
+#pragma unroll
+      for (int i = 0; i < NV; ++i) acc[i] += q.v[j][i];
+  block_sum_values<NV>(acc, out);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -591,7 +623,6 @@ __global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const F
 
 // Facet kernels run a grid-stride loop over facet rows on a grid of at most kMaxFacetGrid
 // blocks, so that the partial buffers (and the redundant reductions) stay small.
-static constexpr int kMaxFacetGrid = 1024;
 __host__ __device__ inline int facet_grid(int E) {
   const int g = (E + kBlk - 1) / kBlk;
   return g < kMaxFacetGrid ? g : kMaxFacetGrid;
@@ -723,6 +754,42 @@ __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V 
   spmv_row<NF, V, V>(A, E, F, get, y);
 }
 
+// Two products of one row at once, y1 = S u and y2 = S w (get(c, u_c, w_c) gives the
+// column facet's two vectors), with the multigrid's copy of S as in spmv_row_mg.
+template <int NF, typename V, typename Getter>
+__device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V (&y1)[NF], V (&y2)[NF]) {
+  auto rowloop = [&](auto vals, V scale) {
+#pragma unroll
+    for (int a = 0; a < NF; ++a) y1[a] = y2[a] = 0;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+      const int c = A.cols[(size_t)s * E + F];
+      V uc[NF], wc[NF];
+      get(c, uc, wc);
+#pragma unroll
+      for (int a = 0; a < NF; ++a)
+#pragma unroll
+        for (int b = 0; b < NF; ++b) {
+          const V m = (V)vals[(((size_t)s * NF + a) * NF + b) * E + F];
+          y1[a] += m * uc[b];
+          y2[a] += m * wc[b];
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NF; ++a) {
+      y1[a] *= scale;
+      y2[a] *= scale;
+    }
+  };
+  if constexpr (sizeof(V) == 4) {
+    if (A.vals16) {
+      rowloop(reinterpret_cast<const _Float16*>(A.vals16), (V)A.scale16);
+      return;
+    }
+  }
+  rowloop(bsr_vals<NF, V>(A), (V)1);
+}
+
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
 template <int NF, bool BJ>
 __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
@@ -783,12 +850,43 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   const int it = sc->it;  // advanced only by the update kernel
   const int E = g.E;
   const int G = gridDim.x;
+  // beta is not needed before the end: S p_new = S z + beta S p_old.  The partials are
+  // loaded first and summed after this thread's first row, whose loads overlap them.
+  PartLoad<2> q1, q2;
+  partials_load<2>(rz_prev, G, true, q1);
+  partials_load<2>(rz_prev2, G, it >= 2, q2);
+  const M* vals = (sizeof(M) == 8) ? (const M*)A.vals : (const M*)A.vals32;
+  auto row = [&](int F, V (&sz)[NF], V (&sp)[NF]) {
+#pragma unroll
+    for (int a = 0; a < NF; ++a) sz[a] = sp[a] = 0;
+#pragma unroll
+    for (int s5 = 0; s5 < kSlots; ++s5) {
+      const int c = A.cols[(size_t)s5 * E + F];
+      V zc[NF], pc[NF];
+#pragma unroll
+      for (int bb = 0; bb < NF; ++bb) {
+        zc[bb] = z[(size_t)c * NF + bb];
+        pc[bb] = p_old[(size_t)c * NF + bb];
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a)
+#pragma unroll
+        for (int bb = 0; bb < NF; ++bb) {
+          const V m = (V)vals[(((size_t)s5 * NF + a) * NF + bb) * E + F];
+          sz[a] += m * zc[bb];
+          sp[a] += m * pc[bb];
+        }
+    }
+  };
+  const int F0 = xcd_block() * blockDim.x + threadIdx.x;
+  V sz[NF], sp[NF];
+  if (F0 < E) row(F0, sz, sp);
   double t1[2];
-  block_sum_partials<2>(rz_prev, G, t1);
+  partials_sum<2>(q1, G, t1);
   double beta = 0;
   if (it >= 2) {
     double t2[2];
-    block_sum_partials<2>(rz_prev2, G, t2);
+    partials_sum<2>(q2, G, t2);
     beta = t1[0] / t2[0];
   }
   int status = PCG_RUNNING;
@@ -805,19 +903,16 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   if (status != PCG_RUNNING) return;
   const V b = (V)beta;
   double v[1] = {0};
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
-    V y[NF];
-    spmv_row<NF, V, M>(A, E, F, [&](int c, V (&xc)[NF]) {
-#pragma unroll
-      for (int bb = 0; bb < NF; ++bb) xc[bb] = z[(size_t)c * NF + bb] + b * p_old[(size_t)c * NF + bb];
-    }, y);
+  for (int F = F0; F < E; F += G * blockDim.x) {
+    if (F != F0) row(F, sz, sp);
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
       const V pn = z[o] + b * p_old[o];
+      const V y = sz[a] + b * sp[a];
       p_new[o] = pn;
-      Sp[o] = y[a];
-      v[0] += (double)pn * (double)y[a];
+      Sp[o] = y;
+      v[0] += (double)pn * (double)y;
     }
   }
   block_write_partial<1>(v, pq);
@@ -1175,9 +1270,32 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   if (sc->done != PCG_RUNNING) return;
   const int E = g.E;
   const int G = gridDim.x;
+  // alpha is not needed before the end: with u = D^{-1} r_old / th and w = D^{-1} S p / th,
+  // S x1 = S u - alpha S w.  The partials are loaded first and summed after this thread's
+  // first row, whose loads overlap them.
+  PartLoad<2> q1;
+  PartLoad<1> q2;
+  partials_load<2>(rz_prev, G, true, q1);
+  partials_load<1>(pq, G, true, q2);
+  const V* dinv = bsr_dinv<NF, V>(A);
+  const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
+  auto row = [&](int F, V (&su)[NF], V (&sw)[NF]) {
+    spmv_row_mg2<NF, V>(A, E, F, [&](int c, V (&uc)[NF], V (&wc)[NF]) {
+#pragma unroll
+      for (int q = 0; q < NF; ++q) {
+        const size_t o = (size_t)c * NF + q;
+        const V d = dinv[o] * ith;
+        uc[q] = d * (V)r_old[o];
+        wc[q] = d * (V)Sp[o];
+      }
+    }, su, sw);
+  };
+  const int F0 = xcd_block() * blockDim.x + threadIdx.x;
+  V su[NF], sw[NF];
+  if (F0 < E) row(F0, su, sw);
   double t1[2], t2[1];
-  block_sum_partials<2>(rz_prev, G, t1);
-  block_sum_partials<1>(pq, G, t2);
+  partials_sum<2>(q1, G, t1);
+  partials_sum<1>(q2, G, t2);
   int status = PCG_RUNNING;
   if (!isfinite(t2[0])) status = PCG_NONFINITE;
   else if (!(t2[0] > 0)) status = PCG_BREAKDOWN;
@@ -1186,18 +1304,10 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
     return;
   }
   const VB alpha = (VB)(t1[0] / t2[0]);
-  const V* dinv = bsr_dinv<NF, V>(A);
-  const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
+  const V alv = (V)alpha;
   double v[2] = {0, 0};
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
-    V y[NF];
-    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
-#pragma unroll
-      for (int q = 0; q < NF; ++q) {
-        const size_t o = (size_t)c * NF + q;
-        xc[q] = dinv[o] * (V)(r_old[o] - alpha * Sp[o]) * ith;
-      }
-    }, y);
+  for (int F = F0; F < E; F += G * blockDim.x) {
+    if (F != F0) row(F, su, sw);
 #pragma unroll
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
@@ -1207,7 +1317,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
       v[1] += (double)rn * (double)rn;
       const V bo = (V)rn;
       const V x1 = dinv[o] * bo * ith;
-      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
+      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - (su[a] - alv * sw[a]));
     }
   }
   block_write_partial<2>(v, rz_out);
