@@ -336,7 +336,9 @@ static void carve(dfdg_ctx* ctx, char* base) {
   const AmgHierarchy& H = ctx->H;
   mg.nlev = (int)H.lv.size();
   // lanes per row: the largest power of two not above the mean row length / div (<= 64)
-  auto take_csr = [&](const Csr& M, DevCsr& D, int div) {
+  // returns whether the rows were packed (decided from the matrix, never from a pointer:
+  // the sizing pass carves with a null base)
+  auto take_csr = [&](const Csr& M, DevCsr& D, int div, bool pack = false, bool half = false) -> bool {
     D.n = M.n;
     const double avg = M.n ? (double)M.nnz() / M.n : 1.0;
     D.lpr = 1;
@@ -349,6 +351,11 @@ static void carve(dfdg_ctx* ctx, char* base) {
     D.col = c.take<int>(ne);
     D.val = c.take<double>(ne);
     D.val32 = f32 ? c.take<float>(ne) : nullptr;
+    const bool packed = pack && D.w == 4 && M.m < 65536;
+    D.pk = packed ? c.take<uint32_t>(4 * (size_t)M.n) : nullptr;
+    D.val16 = half ? c.take<uint16_t>(ne) : nullptr;
+    D.pscale = 1.0f;
+    return packed;
   };
   for (int l = 0; l < mg.nlev; ++l) {
     const AmgLevel& L = H.lv[l];
@@ -361,8 +368,9 @@ static void carve(dfdg_ctx* ctx, char* base) {
     if (l < mg.nlev - 1) {
       // the restriction from the finest level gathers from the largest vector: a few
       // lanes per row, each with several entries, keep more of those gathers in flight
-      take_csr(L.P, mg.P[l], 1);
-      take_csr(L.R, mg.R[l], l == 0 ? 8 : 1);
+      // the finest-level transfers of an FP32 cycle in FP16 (P packed, R = P^T rounded alike)
+      const bool packed = take_csr(L.P, mg.P[l], 1, l == 0 && f16);
+      take_csr(L.R, mg.R[l], l == 0 ? 8 : 1, false, packed);
       if (l > 0) {
         take_csr(L.AP, mg.AP[l], 1);
         take_csr(L.RA, mg.RA[l], 1);
@@ -485,7 +493,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
       keep.emplace_back(v.begin(), v.end());
       return keep.back();
     };
-    auto up_csr = [&](const Csr& M, const DevCsr& D) -> int {
+    auto up_csr = [&](const Csr& M, DevCsr& D) -> int {
       // padded row-major copy (see DevCsr)
       std::vector<int> ce((size_t)M.n * D.w);
       keep_d.emplace_back((size_t)M.n * D.w, 0.0);
@@ -501,6 +509,15 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
       HIPC(up(const_cast<int*>(D.col), keep_i.back(), s));
       HIPC(up(const_cast<double*>(D.val), ve, s));
       if (mixed) HIPC(up(const_cast<float*>(D.val32), f32(ve), s));
+      if (D.pk || D.val16) {  // the same values in P and R: the same scale and rounding
+        double vmax = 0;
+        for (double x : ve) vmax = std::max(vmax, std::fabs(x));
+        if (!(vmax > 0)) vmax = 1;
+        D.pscale = (float)vmax;
+        if (D.pk) HIPC(launch_pack_rows4(M.n, D.col, D.val, 1.0 / vmax, const_cast<uint32_t*>(D.pk), s));
+        if (D.val16)
+          HIPC(launch_to_half((long)ve.size(), D.val, 1.0 / vmax, const_cast<uint16_t*>(D.val16), s));
+      }
       return DFDG_OK;
     };
     keep.reserve(8 * kMaxLev + 2);

@@ -787,7 +787,7 @@ __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V
       return;
     }
   }
-  rowloop(bsr_vals<NF, V>(A), (V)1);
+  rowloop((sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32, (V)1);
 }
 
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
@@ -1243,12 +1243,30 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   V s = 0;
-  if (LPR == 1 && M.w == 4) {  // rows of 4 entries, 16-byte aligned: vector loads
+  if (sizeof(V) == 4 && LPR == 1 && M.pk) {  // packed rows: one 16-byte load per row
+    if (i < M.n) {
+      const uint4 w = *reinterpret_cast<const uint4*>(M.pk + (size_t)i * 4);
+      const _Float16 h0 = __builtin_bit_cast(_Float16, (uint16_t)(w.z & 0xffffu));
+      const _Float16 h1 = __builtin_bit_cast(_Float16, (uint16_t)(w.z >> 16));
+      const _Float16 h2 = __builtin_bit_cast(_Float16, (uint16_t)(w.w & 0xffffu));
+      const _Float16 h3 = __builtin_bit_cast(_Float16, (uint16_t)(w.w >> 16));
+      s = ((V)h0 * x[w.x & 0xffffu] + (V)h1 * x[w.x >> 16] + (V)h2 * x[w.y & 0xffffu] + (V)h3 * x[w.y >> 16]) *
+          (V)M.pscale;
+    }
+  } else if (LPR == 1 && M.w == 4) {  // rows of 4 entries, 16-byte aligned: vector loads
     if (i < M.n) {
       const int4 c = *reinterpret_cast<const int4*>(M.col + (size_t)i * 4);
       const V* v = csr_vals<V>(M) + (size_t)i * 4;
       s = v[0] * x[c.x] + v[1] * x[c.y] + v[2] * x[c.z] + v[3] * x[c.w];
     }
+  } else if (sizeof(V) == 4 && M.val16) {
+    const _Float16* __restrict__ v16 = reinterpret_cast<const _Float16*>(M.val16);
+    if (i < M.n) {
+      const size_t base = (size_t)i * M.w;
+#pragma unroll 4
+      for (int k = sub; k < M.w; k += LPR) s += (V)v16[base + k] * x[M.col[base + k]];
+    }
+    s = group_sum<LPR, V>(s) * (V)M.pscale;
   } else {
     s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
   }
@@ -1901,6 +1919,31 @@ hipError_t launch_axpby(long n, double a, const double* x, double b, double* y, 
 __global__ void k_to_half(long n, const double* __restrict__ x, double scale, _Float16* __restrict__ out) {
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
     out[i] = (_Float16)(float)(x[i] * scale);
+}
+
+__global__ void k_pack_rows4(int n, const int* __restrict__ col, const double* __restrict__ val, double inv_scale,
+                             uint32_t* __restrict__ pk) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t w[4];
+#pragma unroll
+  for (int k = 0; k < 2; ++k)
+    w[k] = (uint32_t)(col[4 * i + 2 * k] & 0xffff) | ((uint32_t)(col[4 * i + 2 * k + 1] & 0xffff) << 16);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[4 * i + 2 * k] * inv_scale));
+    const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[4 * i + 2 * k + 1] * inv_scale));
+    w[2 + k] = (uint32_t)lo | ((uint32_t)hi << 16);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) pk[4 * (size_t)i + k] = w[k];
+}
+
+hipError_t launch_pack_rows4(int n, const int* col, const double* val, double inv_scale, uint32_t* pk,
+                             hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_rows4, dim3((n + 255) / 256), dim3(256), 0, s, n, col, val, inv_scale, pk);
+  return hipGetLastError();
 }
 
 hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s) {
