@@ -430,10 +430,15 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   if (!ctx || !dev) return DFDG_E_INVALID_ARG;
   if (((uintptr_t)dev & 255) != 0) return fail(ctx, DFDG_E_WORKSPACE, "workspace must be 256-byte aligned");
   carve(ctx, nullptr);
-  if (bytes < ctx->ws_need)
-    return fail(ctx, DFDG_E_WORKSPACE, "workspace too small: need " + std::to_string(ctx->ws_need) + " bytes");
+  const size_t need = ctx->ws_need;
+  if (bytes < need)
+    return fail(ctx, DFDG_E_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
   ctx->ws = (char*)dev;
   carve(ctx, ctx->ws);
+  if (ctx->ws_need != need) {  // both passes must lay out the same arrays
+    ctx->ws = nullptr;
+    return fail(ctx, DFDG_E_WORKSPACE, "internal error: workspace layout differs between passes");
+  }
   const HostSetup& h = ctx->hs;
   hipStream_t s = ctx->stream;
   HIPC(hipMemsetAsync(ctx->ws, 0, ctx->ws_need - 256, s));
