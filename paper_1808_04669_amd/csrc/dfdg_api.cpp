@@ -637,8 +637,11 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
         if (rc) return rc;
       }
   const bool amg = ctx->prm.precond == DFDG_AMG;
-  // a run of n iterations takes n + 1 launches: the last one finds the stopping test met
-  int chunk = *hint > 0 ? *hint + 1 : (amg ? 16 : 64);
+  // With the multigrid cycle (two levels or more) the last kernel of an iteration applies
+  // the stopping test, so a run of n iterations takes n launches; otherwise the next
+  // iteration's first kernel applies it and a run takes n + 1
+  const int extra = (amg && ctx->mg.nlev >= 2) ? 0 : 1;
+  int chunk = *hint > 0 ? *hint + extra : (amg ? 16 : 64);
   fin.done = PCG_RUNNING;
   int launched = 0;
   while (fin.done == PCG_RUNNING) {

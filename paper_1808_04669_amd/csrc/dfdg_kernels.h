@@ -80,7 +80,7 @@ inline const V* mg_dinv(const MgDev& m, int l) {
 // kernel returns at once when sc->done says the PCG has stopped.
 template <typename V, typename VB>
 hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
-                         const PcgScalars* sc, hipStream_t s);
+                         PcgScalars* sc, hipStream_t s);
 // One multigrid-preconditioned PCG iteration (needs at least two levels): p_new = z_in +
 // beta p_old, Sp = S p_new; x += alpha p_new, r_new = r_old - alpha Sp fused with the
 // first smoothing step; the rest of the cycle writes z = cycle(r_new) and its partials.

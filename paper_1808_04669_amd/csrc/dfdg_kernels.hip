@@ -1132,8 +1132,12 @@ template <int NF, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
                                                     VB* __restrict__ z, CheB cb, double* __restrict__ rz,
-                                                    const PcgScalars* sc) {
+                                                    PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
+  // The stopping test of this iteration on the (r, r) partials of its update (the odd
+  // slots of rz), so that a converged run needs no further launch to find out.
+  PartLoad<2> qr;
+  partials_load<2>(rz, gridDim.x, true, qr);
   const V* dinv = bsr_dinv<NF, V>(A);
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -1152,6 +1156,8 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
       v[0] += (double)b[o] * (double)(VB)zz;
     }
   }
+  double rr[2];
+  partials_sum<2>(qr, gridDim.x, rr);  // rr[1] = (r, r); every block the same
   __shared__ double sh[kBlk / 64];
   const double s = wave_sum(v[0]);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -1160,6 +1166,13 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
     double t = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
     rz[2 * blockIdx.x] = t;
+    if (blockIdx.x == 0) {
+      const int it = sc->it;  // already advanced by this iteration's update
+      sc->iters = it - 1;
+      sc->rr = rr[1];
+      if (it == 1) sc->rr0 = rr[1];
+      if (isfinite(rr[1]) && rr[1] <= sc->tol2) sc->done = PCG_CONVERGED;
+    }
   }
 }
 
@@ -1798,7 +1811,7 @@ static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, c
 // Everything of a cycle after the first pre-smoothing step (x2 = pre(b) already in v0.x).
 template <typename V, typename VB>
 static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
-                        const PcgScalars* sc, hipStream_t s) {
+                        PcgScalars* sc, hipStream_t s) {
   const int G = facet_grid(g.E);
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
@@ -1839,7 +1852,7 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
 
 template <typename V, typename VB>
 hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
-                         const PcgScalars* sc, hipStream_t s) {
+                         PcgScalars* sc, hipStream_t s) {
   const int G = facet_grid(g.E);
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
@@ -1885,11 +1898,11 @@ template hipError_t launch_pcg_iteration_mg<float, float>(int, const DevGeo&, co
                                                           float*, float*, const float*, float*, float*, hipStream_t);
 
 template hipError_t launch_vcycle<double, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
-                                                  double*, double*, const PcgScalars*, hipStream_t);
+                                                  double*, double*, PcgScalars*, hipStream_t);
 template hipError_t launch_vcycle<float, double>(int, const DevGeo&, const DevBsr&, const MgDev&, const double*,
-                                                 double*, double*, const PcgScalars*, hipStream_t);
+                                                 double*, double*, PcgScalars*, hipStream_t);
 template hipError_t launch_vcycle<float, float>(int, const DevGeo&, const DevBsr&, const MgDev&, const float*, float*,
-                                                double*, const PcgScalars*, hipStream_t);
+                                                double*, PcgScalars*, hipStream_t);
 
 
 hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
