@@ -1135,9 +1135,11 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
                                                     PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   // The stopping test of this iteration on the (r, r) partials of its update (the odd
-  // slots of rz), so that a converged run needs no further launch to find out.
+  // slots of rz), so that a converged run needs no further launch to find out; block 0
+  // alone sums them.
+  const bool b0 = blockIdx.x == 0;
   PartLoad<2> qr;
-  partials_load<2>(rz, gridDim.x, true, qr);
+  partials_load<2>(rz, gridDim.x, b0, qr);
   const V* dinv = bsr_dinv<NF, V>(A);
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
@@ -1156,8 +1158,8 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
       v[0] += (double)b[o] * (double)(VB)zz;
     }
   }
-  double rr[2];
-  partials_sum<2>(qr, gridDim.x, rr);  // rr[1] = (r, r); every block the same
+  double rr[2] = {0, 0};
+  if (b0) partials_sum<2>(qr, gridDim.x, rr);  // rr[1] = (r, r); the branch is uniform over the block
   __shared__ double sh[kBlk / 64];
   const double s = wave_sum(v[0]);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -1166,7 +1168,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
     double t = 0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += sh[w];
     rz[2 * blockIdx.x] = t;
-    if (blockIdx.x == 0) {
+    if (b0) {
       const int it = sc->it;  // already advanced by this iteration's update
       sc->iters = it - 1;
       sc->rr = rr[1];
@@ -1182,15 +1184,54 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
 template <typename V>
 __device__ inline const V* csr_vals(const DevCsr& A) { return (sizeof(V) == 8) ? (const V*)A.val : (const V*)A.val32; }
 
+// Sum over the n entries base, base + LPR, ... of a padded row, in batches of U whose loads
+// are all issued before the first product (the short rows of the coarse levels are bound
+// by dependent memory round trips, not bandwidth).  The last batch repeats its final entry
+// and multiplies the repeats by zero; the valid products are added in entry order.
+template <int LPR, int U, typename V, typename LD, typename X>
+__device__ inline V ell_batched(size_t base, int n, LD ld, X x) {
+  V s = 0;
+  for (int j0 = 0; j0 < n; j0 += U) {
+    int c[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) ld(base + (size_t)min(j0 + u, n - 1) * LPR, c[u], v[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const V xv = x(c[u]);
+      s += v[u] * ((j0 + u < n) ? xv : (V)0);
+    }
+  }
+  return s;
+}
+
+// Entries sub, sub + LPR, ... below w: how many (w is a multiple of the matrix's own lpr,
+// which can differ from the LPR of a kernel that walks several matrices).
+template <int LPR>
+__device__ inline int lane_entries(int w, int sub) { return w > sub ? (w - sub + LPR - 1) / LPR : 0; }
+
+// ell_batched with a batch as long as the longest lane's share of a row of width w (up to
+// 4; 8 beyond), so that short rows issue no repeated loads.  The choice depends on w only,
+// the same for every lane of the launch.
+template <int LPR, typename V, typename LD, typename X>
+__device__ inline V ell_sum(int w, int sub, size_t base, LD ld, X x) {
+  const int n = lane_entries<LPR>(w, sub), nmax = (w + LPR - 1) / LPR;
+  if (nmax <= 1) return ell_batched<LPR, 1, V>(base, n, ld, x);
+  if (nmax == 2) return ell_batched<LPR, 2, V>(base, n, ld, x);
+  if (nmax == 3) return ell_batched<LPR, 3, V>(base, n, ld, x);
+  if (nmax == 4) return ell_batched<LPR, 4, V>(base, n, ld, x);
+  return ell_batched<LPR, 8, V>(base, n, ld, x);
+}
+
 // This lane's part of row i of M x (i < M.n).
 template <int LPR, typename V, typename X>
 __device__ inline V ell_part(const DevCsr& M, int i, int sub, X x) {
   const V* __restrict__ vals = csr_vals<V>(M);
-  const size_t base = (size_t)i * M.w;
-  V s = 0;
-#pragma unroll 4
-  for (int k = sub; k < M.w; k += LPR) s += vals[base + k] * x(M.col[base + k]);
-  return s;
+  const int* __restrict__ col = M.col;
+  return ell_sum<LPR, V>(M.w, sub, (size_t)i * M.w + sub, [&](size_t k, int& c, V& v) {
+    c = col[k];
+    v = vals[k];
+  }, x);
 }
 template <int LPR, typename V>
 __device__ inline V group_sum(V s) {
@@ -1274,11 +1315,12 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
     }
   } else if (sizeof(V) == 4 && M.val16) {
     const _Float16* __restrict__ v16 = reinterpret_cast<const _Float16*>(M.val16);
-    if (i < M.n) {
-      const size_t base = (size_t)i * M.w;
-#pragma unroll 4
-      for (int k = sub; k < M.w; k += LPR) s += (V)v16[base + k] * x[M.col[base + k]];
-    }
+    const int* __restrict__ col = M.col;
+    if (i < M.n)
+      s = ell_sum<LPR, V>(M.w, sub, (size_t)i * M.w + sub, [&](size_t k, int& c, V& v) {
+        c = col[k];
+        v = (V)v16[k];
+      }, [&](int c) { return x[c]; });
     s = group_sum<LPR, V>(s) * (V)M.pscale;
   } else {
     s = csr_row_group<LPR, V>(M, csr_vals<V>(M), i, sub, [&](int c) { return x[c]; });
@@ -1383,9 +1425,11 @@ __global__ __launch_bounds__(kBlk) void k_dense_mv(int n, const double* __restri
   const int i = g >> 6, lane = g & 63;
   const V* M = (sizeof(V) == 8) ? (const V*)Ainv : (const V*)Ainv32;
   V s = 0;
-  if (i < n)
-#pragma unroll 4
-    for (int j = lane; j < n; j += 64) s += M[(size_t)i * n + j] * b[j];
+  if (i < n)  // entries lane, lane + 64, ...; the column index is the entry's own
+    s = ell_batched<64, 8, V>((size_t)lane, lane_entries<64>(n, lane), [&](size_t k, int& c, V& v) {
+      c = (int)k;
+      v = M[(size_t)i * n + k];
+    }, [&](int c) { return b[c]; });
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if (live && i < n && lane == 0) x[i] = s;

@@ -192,8 +192,8 @@ def test_mass_solve_symmetric_and_idempotent_full_size(precond):
     Pf, i1 = s.mass_solve(f)
     Pg, _ = s.mass_solve(g)
     _log("  iterations", precond, i1.iterations, "rel res", i1.rel_residual)
-    if precond == "amg":
-        assert i1.iterations < 100
+    if precond == "amg":  # 28 with the cycle as built; a broken level shows as more iterations
+        assert i1.iterations <= 31
     a, b = torch.dot(g, Pf).item(), torch.dot(f, Pg).item()
     assert abs(a - b) < 1e-9 * abs(a)
     PPf, _ = s.mass_solve(Pf)
@@ -201,3 +201,19 @@ def test_mass_solve_symmetric_and_idempotent_full_size(precond):
     d = s.diagnostics(Pf)
     _log("  diag", d)
     assert d["max_div"] < 1e-11 * np.sqrt(d["enstrophy"])
+
+
+@pytest.mark.parametrize("N,k,kw,limit", [(256, 1, {}, 26), (128, 3, {}, 37),
+                                          (256, 2, {"mg_fp32": False}, 31)])
+def test_multigrid_cycle_iteration_counts(N, k, kw, limit):
+    """Cold facet solves of a random right-hand side to 1e-12 with the multigrid cycle take
+    about as many iterations as the cycle was built to give (23, 33 and 28 iterations);
+    a coarse level that drops part of its transfer or smoothing raises the count without
+    spoiling the converged result, which the parity tests alone would not notice."""
+    _, s, _, _ = make_pair(N, k, oracle=False, cg_rtol=1e-12, precond="amg", **kw)
+    g0 = torch.Generator(device="cpu").manual_seed(0)
+    f = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
+    _, info = s.mass_solve(f)
+    _log("cold solve", N, k, kw, "iterations", info.iterations, "rel res", info.rel_residual)
+    assert info.status == 0 and info.rel_residual <= 1e-12
+    assert info.iterations <= limit
