@@ -367,10 +367,11 @@ static void carve(dfdg_ctx* ctx, char* base) {
     }
     if (l < mg.nlev - 1) {
       // the restriction from the finest level gathers from the largest vector: a few
-      // lanes per row, each with several entries, keep more of those gathers in flight
+      // lanes per row (8 for rows of ~40 entries), each with one batch of entries, keep
+      // more of those gathers in flight;
       // the finest-level transfers of an FP32 cycle in FP16 (P packed, R = P^T rounded alike)
       const bool packed = take_csr(L.P, mg.P[l], 1, l == 0 && f16);
-      take_csr(L.R, mg.R[l], l == 0 ? 8 : 1, false, packed);
+      take_csr(L.R, mg.R[l], l == 0 ? 4 : 1, false, packed);
       if (l > 0) {
         take_csr(L.AP, mg.AP[l], 1);
         take_csr(L.RA, mg.RA[l], 1);
