@@ -287,7 +287,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.dinv32 = f32 ? c.take<float>(h.dinv.size()) : nullptr;
   A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
   const bool f16 = ctx->prm.precond == DFDG_AMG && (mixed || ctx->prm.mg_fp32) && ctx->prm.mg_fine_fp16;
-  A.vals16 = f16 ? c.take<uint16_t>(h.vals.size()) : nullptr;
+  A.vals16 = f16 ? c.take<uint32_t>((size_t)nPairs(NF) * E) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
   ctx->q = c.take<double>(3 * NF * T);
@@ -486,7 +486,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     for (double v : h.vals) smax = std::max(smax, std::fabs(v));
     if (!(smax > 0)) smax = 1;
     ctx->A.scale16 = (float)smax;
-    HIPC(launch_to_half((long)h.vals.size(), ctx->A.vals, 1.0 / smax, const_cast<uint16_t*>(ctx->A.vals16), s));
+    HIPC(launch_pack_half_pairs(ctx->NF, ctx->E, ctx->A.vals, 1.0 / smax, const_cast<uint32_t*>(ctx->A.vals16), s));
   }
   {
     const bool mixed = ctx->A.vals32 != nullptr;  // FP32 copies were carved
@@ -1172,7 +1172,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
         // and vectors in the cycle's precision (8 or 4 bytes; finest-level S in 2 bytes
         // when it is stored in FP16).
         const double vb = ctx->prm.mg_fp32 ? 4.0 : 8.0;
-        const double sv = ctx->A.vals16 ? 2.0 : vb;
+        const double sv = ctx->A.vals16 ? 4.0 * nPairs(NF) / (kSlots * NF * NF) : vb;
         const double sbytes = E * (kSlots * NF * NF * sv + kSlots * 4.0);
         b = 4 * sbytes + 17.0 * E * NF * vb;
         const AmgHierarchy& H = ctx->H;

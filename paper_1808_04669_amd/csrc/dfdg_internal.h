@@ -31,6 +31,8 @@ __host__ __device__ constexpr int projDeg(int K) { return 2 * K + 4; }
 __host__ __device__ constexpr int nQP(int K) { return triN(projDeg(K)); }
 constexpr int kMaxK = 3;
 constexpr int kSlots = 5;           // BSR blocks per facet row: itself + 2 + 2 neighbours
+// 32-bit words of a facet row of S in FP16, two values per word
+__host__ __device__ constexpr int nPairs(int NF) { return (kSlots * NF * NF + 1) / 2; }
 constexpr int kMaxEvalPts = 1024;
 
 // ---- reference tabulations (host, FP64) ---------------------------------------------
@@ -87,7 +89,10 @@ struct DevBsr {
   const float* vals32;  // [5][NF][NF][E] (MIXED)
   const float* dinv32;  // [E][NF]
   const float* binv32;  // [E][NF][NF]
-  const uint16_t* vals16;  // [5][NF][NF][E] FP16 bits of S / scale16 (finest V-cycle level), or null
+  // FP16 copy of S / scale16 for the finest V-cycle level, or null: [nPairs(NF)][E] words;
+  // word j of row F holds values 2j (low half) and 2j+1 (high half) of the row's
+  // [5][NF][NF] sequence (the last high half is zero when 5 NF^2 is odd)
+  const uint32_t* vals16;
   float scale16;
 };
 

@@ -155,5 +155,7 @@ hipError_t launch_pack_rows4(int n, const int* col, const double* val, double in
                              hipStream_t s);
 // out[i] = FP16 bits of x[i] * scale (round to nearest even).
 hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s);
+// S (FP64, [5][NF][NF][E]) times scale in FP16, two values per word (DevBsr::vals16)
+hipError_t launch_pack_half_pairs(int NF, int E, const double* vals, double scale, uint32_t* out, hipStream_t s);
 
 }  // namespace dfdg

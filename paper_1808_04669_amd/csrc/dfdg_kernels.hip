@@ -727,13 +727,31 @@ __device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y
   }
 }
 
+// The FP16 copy of row F of S (two values per word, see DevBsr::vals16): all the row's
+// words are loaded at once, and value j of the row's [5][NF][NF] sequence is half j & 1
+// of word j / 2.
+template <int NF>
+struct HalfRow {
+  uint32_t w[nPairs(NF)];
+  __device__ inline void load(const DevBsr& A, int E, int F) {
+    const uint32_t* __restrict__ p = A.vals16;
+#pragma unroll
+    for (int j = 0; j < nPairs(NF); ++j) w[j] = p[(size_t)j * E + F];
+  }
+  __device__ inline float at(int j) const {
+    const uint32_t v = w[j >> 1];
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)((j & 1) ? (v >> 16) : (v & 0xffffu)));
+  }
+};
+
 // As spmv_row in FP32 for the multigrid smoothing on the finest level: S is read from its
 // FP16 copy (scaled by scale16) when there is one, else from the FP32 copy.
 template <int NF, typename V, typename Getter>
 __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      const _Float16* vals = reinterpret_cast<const _Float16*>(A.vals16);
+      HalfRow<NF> m;
+      m.load(A, E, F);
 #pragma unroll
       for (int a = 0; a < NF; ++a) y[a] = 0;
 #pragma unroll
@@ -744,7 +762,7 @@ __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V 
 #pragma unroll
         for (int a = 0; a < NF; ++a)
 #pragma unroll
-          for (int b = 0; b < NF; ++b) y[a] += (V)vals[(((size_t)s * NF + a) * NF + b) * E + F] * xc[b];
+          for (int b = 0; b < NF; ++b) y[a] += (V)m.at((s * NF + a) * NF + b) * xc[b];
       }
 #pragma unroll
       for (int a = 0; a < NF; ++a) y[a] *= A.scale16;
@@ -758,7 +776,8 @@ __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V 
 // column facet's two vectors), with the multigrid's copy of S as in spmv_row_mg.
 template <int NF, typename V, typename Getter>
 __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V (&y1)[NF], V (&y2)[NF]) {
-  auto rowloop = [&](auto vals, V scale) {
+  // value(j) gives entry j of the row's [5][NF][NF] sequence
+  auto rowloop = [&](auto value, V scale) {
 #pragma unroll
     for (int a = 0; a < NF; ++a) y1[a] = y2[a] = 0;
 #pragma unroll
@@ -770,7 +789,7 @@ __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V
       for (int a = 0; a < NF; ++a)
 #pragma unroll
         for (int b = 0; b < NF; ++b) {
-          const V m = (V)vals[(((size_t)s * NF + a) * NF + b) * E + F];
+          const V m = value((s * NF + a) * NF + b);
           y1[a] += m * uc[b];
           y2[a] += m * wc[b];
         }
@@ -783,11 +802,14 @@ __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V
   };
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      rowloop(reinterpret_cast<const _Float16*>(A.vals16), (V)A.scale16);
+      HalfRow<NF> m;
+      m.load(A, E, F);
+      rowloop([&](int j) { return (V)m.at(j); }, (V)A.scale16);
       return;
     }
   }
-  rowloop((sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32, (V)1);
+  const V* vals = (sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32;
+  rowloop([&](int j) { return vals[(size_t)j * E + F]; }, (V)1);
 }
 
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
@@ -1978,6 +2000,16 @@ __global__ void k_to_half(long n, const double* __restrict__ x, double scale, _F
     out[i] = (_Float16)(float)(x[i] * scale);
 }
 
+__global__ void k_pack_half_pairs(int nv, int E, const double* __restrict__ vals, double scale,
+                                  uint32_t* __restrict__ out, long n) {
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const long j = i / E, F = i % E;
+    const _Float16 lo = (_Float16)(float)(vals[2 * j * E + F] * scale);
+    const _Float16 hi = (2 * j + 1 < nv) ? (_Float16)(float)(vals[(2 * j + 1) * E + F] * scale) : (_Float16)0.0f;
+    out[i] = (uint32_t)__builtin_bit_cast(uint16_t, lo) | ((uint32_t)__builtin_bit_cast(uint16_t, hi) << 16);
+  }
+}
+
 __global__ void k_pack_rows4(int n, const int* __restrict__ col, const double* __restrict__ val, double inv_scale,
                              uint32_t* __restrict__ pk) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2010,6 +2042,12 @@ hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, 
   return hipGetLastError();
 }
 
+hipError_t launch_pack_half_pairs(int NF, int E, const double* vals, double scale, uint32_t* out, hipStream_t s) {
+  const long n = (long)nPairs(NF) * E;
+  const long nb = std::min<long>(nblk(n, 256), 65536);
+  hipLaunchKernelGGL(k_pack_half_pairs, dim3((unsigned)nb), dim3(256), 0, s, kSlots * NF * NF, E, vals, scale, out, n);
+  return hipGetLastError();
+}
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {
   hipLaunchKernelGGL(k_fill, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, v, y);
   return hipGetLastError();
