@@ -38,6 +38,13 @@ struct dfdg_ctx {
   double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
          *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][kHistDepth] = {}, *evaltab = nullptr,
          *partials = nullptr, *diagres = nullptr, *r64 = nullptr, *xpart = nullptr;
+  // warm starts of the forward stages formed ahead: while the host waits for the end of
+  // one stage's solve, the GPU forms the next stage's start value (it depends only on that
+  // stage's history) into gbuf
+  double* gbuf[3] = {nullptr, nullptr, nullptr};
+  bool gready[3] = {false, false, false};
+  int defer_slot = -1;
+  hipEvent_t sc_event = nullptr;
   float *L32 = nullptr, *x32 = nullptr, *r32 = nullptr, *r32b = nullptr, *z32 = nullptr, *p32[2] = {nullptr, nullptr},
         *Sp32 = nullptr;
   PcgBufs pb{}, pb32{}, pbt{};  // FP64 PCG / refinement, FP32 inner PCG, kernel timing
@@ -59,6 +66,12 @@ struct dfdg_ctx {
   PcgScalars* pinned = nullptr;
   std::string err;
 };
+
+// Start values formed ahead are void once a history changes other than by a solve.
+static void invalidate_guesses(dfdg_ctx* ctx) {
+  for (int i = 0; i < 3; ++i) ctx->gready[i] = false;
+  ctx->defer_slot = -1;
+}
 
 static thread_local std::string g_mesh_err;
 
@@ -303,6 +316,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->Ustage = c.take<double>(nU);
   for (int s = 0; s < 6; ++s)
     for (int j = 0; j < kHistDepth; ++j) ctx->hist[s][j] = c.take<double>(nL);
+  for (int s = 0; s < 3; ++s) ctx->gbuf[s] = c.take<double>(nL);
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
   ctx->partials = c.take<double>(4 * maxblk);
@@ -553,6 +567,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   if (!ctx->pinned) HIPC(hipHostMalloc((void**)&ctx->pinned, 4 * sizeof(PcgScalars), hipHostMallocDefault));
   ctx->bound = true;
   for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+  invalidate_guesses(ctx);
   return DFDG_OK;
 }
 
@@ -568,6 +583,7 @@ extern "C" void dfdg_ctx_destroy(dfdg_ctx* ctx) {
     if (ctx->graph32[j]) (void)hipGraphExecDestroy(ctx->graph32[j]);
   }
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->sc_event) (void)hipEventDestroy(ctx->sc_event);
   if (ctx->pinned) {
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipHostFree(ctx->pinned);
@@ -588,9 +604,25 @@ static int status_of(int done) {
   }
 }
 
+static int extrapolate_into(dfdg_ctx* ctx, int s, double* out);
+
+// Copies the scalars to the host and waits for them.  When a forward stage's start value
+// is due (defer_slot), its kernels are enqueued behind the copy, so that the GPU forms it
+// while the host reads the scalars and enqueues the next work.
 static int read_scalars(dfdg_ctx* ctx, PcgScalars* dev, PcgScalars& out) {
   HIPC(hipMemcpyAsync(ctx->pinned, dev, sizeof(PcgScalars), hipMemcpyDeviceToHost, ctx->stream));
-  HIPC(hipStreamSynchronize(ctx->stream));
+  const int d = ctx->defer_slot;
+  if (d >= 0) {
+    ctx->defer_slot = -1;
+    if (!ctx->sc_event) HIPC(hipEventCreateWithFlags(&ctx->sc_event, hipEventDisableTiming));
+    HIPC(hipEventRecord(ctx->sc_event, ctx->stream));
+    const int rc = extrapolate_into(ctx, d, ctx->gbuf[d]);
+    if (rc) return rc;
+    ctx->gready[d] = true;
+    HIPC(hipEventSynchronize(ctx->sc_event));
+  } else {
+    HIPC(hipStreamSynchronize(ctx->stream));
+  }
   out = *ctx->pinned;
   return DFDG_OK;
 }
@@ -852,6 +884,7 @@ extern "C" int dfdg_dg_residual(dfdg_ctx* ctx, const double* U, double* L) {
 extern "C" int dfdg_reset_history(dfdg_ctx* ctx) {
   if (!ctx) return DFDG_E_INVALID_ARG;
   for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+  invalidate_guesses(ctx);
   return DFDG_OK;
 }
 
@@ -893,26 +926,40 @@ extern "C" int dfdg_history_restore(dfdg_ctx* ctx, const double* hist, const int
                           ctx->stream));
     ctx->hist_count[st] = counts[st];
   }
+  invalidate_guesses(ctx);
   return DFDG_OK;
 }
 
-// Start value (in lamw) of the facet solve of history slot s; returns whether it is a cold start.
-static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
+// Start value of the next facet solve of history slot s (which has kept multipliers) into out.
+static int extrapolate_into(dfdg_ctx* ctx, int s, double* out) {
   const int n = ctx->hist_count[s];
-  *cold = (n == 0);
-  if (n == 0) return DFDG_OK;
   HistPtrs h;
   for (int j = 0; j < kHistDepth; ++j) h.p[j] = ctx->hist[s][j];
   if (ctx->prm.extrapolate == kExtrapAdaptive) {
     const int omax = std::min(4, n - 2);  // a backtest of order o needs o + 2 multipliers
     if (omax >= 1) {
-      HIPC(launch_extrapolate_adaptive(ctx->nL, omax, h, ctx->xpart, ctx->lamw, ctx->stream));
+      HIPC(launch_extrapolate_adaptive(ctx->nL, omax, h, ctx->xpart, out, ctx->stream));
       return DFDG_OK;
     }
   }
   const int order = std::min(std::min(ctx->prm.extrapolate, 4), n - 1);
-  HIPC(launch_extrapolate(ctx->nL, order, h, ctx->lamw, ctx->stream));
+  HIPC(launch_extrapolate(ctx->nL, order, h, out, ctx->stream));
   return DFDG_OK;
+}
+
+// Start value (in lamw) of the facet solve of history slot s; returns whether it is a cold
+// start.  A forward stage's value formed ahead (gbuf) is taken over by exchanging buffers:
+// it was formed from the same history, after that slot's last update.
+static int stage_guess(dfdg_ctx* ctx, int s, bool* cold) {
+  const int n = ctx->hist_count[s];
+  *cold = (n == 0);
+  if (n == 0) return DFDG_OK;
+  if (s < 3 && ctx->gready[s]) {
+    std::swap(ctx->lamw, ctx->gbuf[s]);
+    ctx->gready[s] = false;
+    return DFDG_OK;
+  }
+  return extrapolate_into(ctx, s, ctx->lamw);
 }
 static void stage_push(dfdg_ctx* ctx, int s) {
   double* old = ctx->hist[s][kHistDepth - 1];
@@ -931,7 +978,11 @@ static int rk_stage(dfdg_ctx* ctx, int s, const double* Us, const double* Un, do
   bool cold;
   int rc = stage_guess(ctx, s, &cold);
   if (rc) return rc;
+  // the next forward stage's start value, formed while the host waits for this solve
+  const int next = (s + 1) % 3;
+  if (ctx->hist_count[next] > 0 && !ctx->gready[next]) ctx->defer_slot = next;
   rc = mass_solve_impl(ctx, L, mixed, out, ctx->lamw, cold, inf, 1, a, Un, b, Us, dt);
+  ctx->defer_slot = -1;
   if (rc) return rc;
   stage_push(ctx, s);
   return DFDG_OK;
