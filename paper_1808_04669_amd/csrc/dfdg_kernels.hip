@@ -1149,7 +1149,8 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
 }
 
 // Last post-smoothing step; z is the preconditioned PCG residual b.  Writes the (b, z)
-// partial of this block into rz[2*block] (the (r,r) slot rz[2*block+1] is left alone).
+// partial of this block into rz[2*block] (the (r,r) slot rz[2*block+1] is left alone),
+// and block 0 applies the iteration's stopping test to the (r,r) partials.
 template <int NF, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
