@@ -21,9 +21,11 @@
  *   dfdg_ctx_destroy().  Pointers named *_host are host pointers, read or written
  *   during the call only.  The library keeps one pinned host buffer per context.
  * Streams.  All device work of a context is enqueued on the HIP stream given to
- *   dfdg_ctx_create() (or dfdg_ctx_set_stream()).  Calls that return numbers to the
- *   host (solve/step info, diagnostics) synchronise that stream; the others return
- *   as soon as their work is enqueued.
+ *   dfdg_ctx_create() (or dfdg_ctx_set_stream(), which first waits for the work
+ *   queued on the previous stream).  Calls that return numbers to the host (solve/step
+ *   info, diagnostics) wait for those numbers; work that does not feed them (the final
+ *   recovery of a step, the next step's start values) may still be running on the
+ *   stream when they return, like the work of the calls that only enqueue.
  * Errors.  Every int-returning function returns DFDG_OK (0) or a negative status.
  *   Arguments, mesh and workspace are validated on the host before any device work;
  *   dfdg_last_error() gives a message for the last failing call on a context,

@@ -222,6 +222,9 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
 
 extern "C" int dfdg_ctx_set_stream(dfdg_ctx* ctx, void* stream) {
   if (!ctx) return DFDG_E_INVALID_ARG;
+  // work still queued on the previous stream (a recovery, a start value formed ahead)
+  // finishes before any work on the new one
+  if (ctx->bound && (hipStream_t)stream != ctx->stream) HIPC(hipStreamSynchronize(ctx->stream));
   ctx->stream = (hipStream_t)stream;
   return DFDG_OK;
 }
