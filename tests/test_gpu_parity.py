@@ -217,3 +217,30 @@ def test_multigrid_cycle_iteration_counts(N, k, kw, limit):
     _log("cold solve", N, k, kw, "iterations", info.iterations, "rel res", info.rel_residual)
     assert info.status == 0 and info.rel_residual <= 1e-12
     assert info.iterations <= limit
+
+
+def test_stream_switch_and_early_start_values_keep_the_trajectory():
+    """RK3 steps whose stage start values are formed ahead (while the host waits for the
+    previous solve), with the context moved to another stream half-way (the switch waits
+    for the work still queued on the old one), give the same bits as steps on one stream."""
+    import ctypes
+    from gpu_util import project_field
+    from paper_1808_04669_amd import dfdg
+    lib = dfdg.load_library()
+    runs = []
+    for switch in (False, True):
+        _, s, xyz, _ = make_pair(16, 2, oracle=False, cg_rtol=1e-12, precond="amg", extrapolate="adaptive")
+        U, vmax = project_field(s, xyz, double_shear_layer)
+        dt = 0.1 / 16 / (4 * vmax)
+        other = torch.cuda.Stream()
+        its = []
+        for n in range(6):
+            if switch and n == 3:
+                assert lib.dfdg_ctx_set_stream(s._h, ctypes.c_void_p(other.cuda_stream)) == 0
+            its.append(list(s.rk3_step(U, dt).iterations))
+        torch.cuda.synchronize()
+        runs.append((U.clone(), its))
+        del s
+    _log("iterations", runs[0][1], runs[1][1])
+    assert runs[0][1] == runs[1][1]
+    assert torch.equal(runs[0][0], runs[1][0])
