@@ -5,7 +5,7 @@ vertex coordinates), initial velocity fields and seeded random data.  Both the
 CPU oracle (``oracle/``) and the GPU library consume what it produces; neither
 side's computations live here.
 """
-from .meshes import periodic_split_square, element_order  # noqa: F401
+from .meshes import periodic_split_square, element_order, periodic_kuhn_cube  # noqa: F401
 from .fields import (  # noqa: F401
     taylor_green_2d,
     double_shear_layer,
@@ -13,4 +13,10 @@ from .fields import (  # noqa: F401
     random_broken_poly,
     eval_broken_poly,
     n_monomials,
+    taylor_green_3d,
+    abc_flow,
+    RandomVectorPotentialField,
+    random_broken_poly_3d,
+    eval_broken_poly_3d,
+    n_monomials_3d,
 )

@@ -64,3 +64,54 @@ def periodic_split_square(N, order="morton", seed=0):
     up[:, 1, 0], up[:, 1, 1] = x1, y1
     up[:, 2, 0], up[:, 2, 1] = x0, y1
     return xyz, np.array([1.0, 1.0])
+
+
+def _morton_key3(i, j, k, bits):
+    key = np.zeros_like(i, dtype=np.int64)
+    for b in range(bits):
+        key |= ((i >> b) & 1).astype(np.int64) << (3 * b)
+        key |= ((j >> b) & 1).astype(np.int64) << (3 * b + 1)
+        key |= ((k >> b) & 1).astype(np.int64) << (3 * b + 2)
+    return key
+
+
+def periodic_kuhn_cube(N, order="morton", seed=0):
+    """Return (xyz[T,4,3] float64, period[3]) for the N x N x N periodic unit cube, every
+    cube split into the 6 Kuhn tetrahedra that share its main diagonal.
+
+    The cube with lowest corner c = (i, j, k)/N gives, for every permutation s of the axes,
+    the tetrahedron c, c + h e_s0, c + h (e_s0 + e_s1), c + h (1, 1, 1) (h = 1/N); for odd
+    permutations the middle two vertices are swapped so that every element is positively
+    oriented (det J = h^3).  The split is translation invariant, hence conforming across the
+    periodic boundary.  T = 6 N^3; the six tetrahedra of one cube are consecutive, and the
+    cubes are ordered 'lex', 'morton' or 'random'.
+    """
+    if N < 1:
+        raise ValueError("N must be >= 1")
+    i, j, k = np.meshgrid(np.arange(N), np.arange(N), np.arange(N), indexing="ij")
+    i, j, k = i.ravel(), j.ravel(), k.ravel()
+    if order == "lex":
+        perm = np.lexsort((i, j, k))
+    elif order == "morton":
+        bits = max(1, int(np.ceil(np.log2(max(N, 2)))))
+        perm = np.argsort(_morton_key3(i, j, k, bits), kind="stable")
+    elif order == "random":
+        perm = np.random.default_rng(seed).permutation(N ** 3)
+    else:
+        raise ValueError(f"unknown order {order!r}")
+    i, j, k = i[perm], j[perm], k[perm]
+    h = 1.0 / N
+    corner = np.stack([i, j, k], axis=1) * h  # [C, 3]
+    perms = [(0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)]
+    odd = [False, True, True, False, False, True]
+    eye = np.eye(3)
+    xyz = np.empty((6 * N ** 3, 4, 3))
+    for p, (s, o) in enumerate(zip(perms, odd)):
+        v1 = eye[s[0]]
+        v2 = eye[s[0]] + eye[s[1]]
+        verts = [np.zeros(3), v1, v2, np.ones(3)]
+        if o:
+            verts[1], verts[2] = verts[2], verts[1]
+        for a in range(4):
+            xyz[p::6, a, :] = corner + h * verts[a]
+    return xyz, np.array([1.0, 1.0, 1.0])

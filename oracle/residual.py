@@ -12,13 +12,14 @@ eq. (viscous)).  Readings of the paper used here:
 * h in the penalty is h_F = min(h_T+, h_T-) with h_T = (d! |T|)^(1/d).
 
 The residual is returned on the broken local basis Phi_(c,a) of every element:
-R[t, c, a] = L(u)(m_a e_c restricted to element t), m_a the local polynomial basis.  It works for complex
+R[t, c, a] = L(u)(m_a e_c restricted to element t), m_a the local polynomial basis.  The
+code is the same for triangles and tetrahedra (d = 2, 3): only the rules differ.  It works for complex
 coefficients too (the upwind switch then uses the real part), which the adjoint
 module uses for complex-step derivatives.
 """
 import numpy as np
 
-from .quadrature import gauss_legendre_01, facet_rule_points, poly_basis, triangle_rule
+from .quadrature import facet_rule, poly_basis_nd, simplex_rule
 
 
 def _phys_grad(dref, Jinv):
@@ -35,14 +36,15 @@ class Residual:
         self.alpha = float(alpha)
         self.chunk = chunk
         k = self.k
-        # volume rule: degree 3k+2 (>= 3k-1 needed by (u (x) u) : grad v)
-        self.vpts, self.vw = triangle_rule(3 * k + 2)
-        self.vm, self.vdm = poly_basis(k, self.vpts[:, 0], self.vpts[:, 1])
-        self.fs, self.fw = gauss_legendre_01(facet_rule_points(k))
         m = self.mesh
+        # volume rule: degree 3k+2 (>= 3k-1 needed by (u (x) u) : grad v)
+        self.vpts, self.vw = simplex_rule(m.d, 3 * k + 2)
+        self.vm, self.vdm = poly_basis_nd(k, self.vpts)
+        # facet rule, weights summing to 1 (times the facet measure below)
+        self.fs, self.fw = facet_rule(m.d, k)
         xa, xb = m.facet_points(self.fs)
-        self.fmA, self.fdmA = poly_basis(k, xa[..., 0], xa[..., 1])  # [E,R,nm], [E,R,2,nm]
-        self.fmB, self.fdmB = poly_basis(k, xb[..., 0], xb[..., 1])
+        self.fmA, self.fdmA = poly_basis_nd(k, xa)  # [E,R,nm], [E,R,d,nm]
+        self.fmB, self.fdmB = poly_basis_nd(k, xb)
         self.sigma = self.alpha * k * k / m.hF  # penalty per facet
 
     # ---------------------------------------------------------------------------------
@@ -69,7 +71,7 @@ class Residual:
         """
         m = self.mesh
         A, B = m.fA_elem, m.fB_elem
-        n = m.normal                      # A's outward normal, [E, 2]
+        n = m.normal                      # A's outward normal, [E, d]
         nA, nB = n, -n
         uA = np.einsum("eca,era->erc", cUA, self.fmA)
         uB = np.einsum("eca,era->erc", cUB, self.fmB)

@@ -16,19 +16,22 @@ import scipy.sparse.linalg as spla
 
 from .bdm import BDMSpace, n_mono
 from .mesh import OracleMesh
-from .quadrature import gauss_legendre_01, facet_rule_points, poly_basis, triangle_rule
+from .quadrature import (facet_moment_rule, facet_rule, gauss_legendre_01, poly_basis, poly_basis_nd,
+                         simplex_rule)
 from .residual import Residual
 
 
 class Oracle:
-    """Plain FP64 reference solver on a periodic triangle mesh.
+    """Plain FP64 reference solver on a periodic simplex mesh.
 
-    xyz[T, 3, 2]: counter-clockwise element vertices; period[2] or None.
+    xyz[T, 3, 2]: counter-clockwise triangles, or xyz[T, 4, 3]: positively oriented
+    tetrahedra; period[d] or None.
     """
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0):
         self.mesh = OracleMesh(xyz, period)
         self.k = k
+        self.d = self.mesh.d
         self.space = BDMSpace(self.mesh, k)
         self.res = Residual(self.space, nu=nu, alpha=alpha)
         self._assemble()
@@ -36,15 +39,15 @@ class Oracle:
 
     # ---- matrices ----------------------------------------------------------------
     def _assemble(self):
-        sp_, m, k = self.space, self.mesh, self.k
-        pts, w = triangle_rule(2 * k)
-        vals, dref = poly_basis(k, pts[:, 0], pts[:, 1])            # [q, nm], [q, 2, nm]
+        sp_, m, k, d = self.space, self.mesh, self.k, self.d
+        pts, w = simplex_rule(d, 2 * k)
+        vals, dref = poly_basis_nd(k, pts)                           # [q, nm], [q, d, nm]
         nm, npr = sp_.nm, sp_.np_
         # element mass in the local basis (block-diagonal over components)
         Mref = np.einsum("q,qa,qb->ab", w, vals, vals)
         Mphi = np.zeros((sp_.nu, sp_.nu))
-        Mphi[:nm, :nm] = Mref
-        Mphi[nm:, nm:] = Mref
+        for c in range(d):
+            Mphi[c * nm:(c + 1) * nm, c * nm:(c + 1) * nm] = Mref
         ML = np.einsum("t,tai,ab,tbj->tij", m.detJ, sp_.A, Mphi, sp_.A)
         # divergence against the pressure basis z_p (the first dim P^{k-1} of the local basis)
         z = vals[:, :npr]
@@ -94,13 +97,14 @@ class Oracle:
     def project(self, field, degree=None):
         """L2 projection of the vector field ``field(x, y) -> (u1, u2)`` onto V^{k,-1}.
 
-        The right-hand side int u0 . psi uses a rule of degree 2k+10 by default.
+        The right-hand side int u0 . psi uses a rule of degree 2k+10 (2D) or 2k+6 (3D) by
+        default.
         """
         k = self.k
-        rule = triangle_rule(2 * k + 10 if degree is None else degree)
+        rule = simplex_rule(self.d, (2 * k + 10 if self.d == 2 else 2 * k + 6) if degree is None else degree)
         x = self.phys_points(rule[0])
-        u1, u2 = field(x[..., 0], x[..., 1])
-        R = self.space.load_vector(np.stack([u1, u2], axis=1), rule)
+        u = field(*[x[..., i] for i in range(self.d)])
+        R = self.space.load_vector(np.stack(u, axis=1), rule)
         return self.mass_solve(self.space.assemble(R))
 
     def phys_points(self, ref_pts):
@@ -131,9 +135,19 @@ class Oracle:
         return U
 
     # ---- diagnostics ------------------------------------------------------------------
+    # Each diagnostic is written on the element-local coefficients cU[T, 2, nm] of a broken
+    # field (any piecewise polynomial of degree <= k, in or outside BDM_k); the global-vector
+    # versions convert first.  Example 2 of Sec. 4 reports the energy and the enstrophy.
     def energy(self, U):
         """Kinetic energy 1/2 ||u_h||^2."""
         return 0.5 * float(U @ (self.M @ U))
+
+    def energy_local(self, cU):
+        """1/2 ||u_h||^2 of a broken field (degree-2k rule: exact)."""
+        pts, w = simplex_rule(self.d, 2 * self.k)
+        vals, _ = poly_basis_nd(self.k, pts)
+        u = np.einsum("tca,qa->tcq", cU, vals)
+        return 0.5 * float(np.einsum("q,t,tcq->", w, self.mesh.detJ, u * u))
 
     def l2_diff(self, valsA, valsB, rule):
         """L2 norm of the difference of two fields given at the points of ``rule``."""
@@ -142,81 +156,103 @@ class Oracle:
         return float(np.sqrt(np.einsum("q,t,tcq->", w, self.mesh.detJ, d * d)))
 
     def l2_error_to(self, U, field, degree=None):
-        rule = triangle_rule(2 * self.k + 10 if degree is None else degree)
+        rule = simplex_rule(self.d, (2 * self.k + 10 if self.d == 2 else 2 * self.k + 6) if degree is None
+                            else degree)
         uh = self.eval_ref(U, rule[0])
         x = self.phys_points(rule[0])
-        u1, u2 = field(x[..., 0], x[..., 1])
-        return self.l2_diff(uh, np.stack([u1, u2], axis=1), rule)
+        u = field(*[x[..., i] for i in range(self.d)])
+        return self.l2_diff(uh, np.stack(u, axis=1), rule)
 
-    def divergence_max(self, U):
-        """max over elements and points of |div u_h| (pointwise, degree-2k rule points)."""
-        pts, _ = triangle_rule(2 * self.k)
-        _, dref = poly_basis(self.k, pts[:, 0], pts[:, 1])
-        cU = self.space.local_coeffs(U)
-        g = np.einsum("tca,qra,trc->tq", cU, dref, self.mesh.Jinv)
-        return float(np.abs(g).max())
+    def _phys_gradients(self, cU, pts):
+        """g[t, q, c, j] = d u_c / d x_j of a broken field at reference points pts[Q, d]."""
+        _, dref = poly_basis_nd(self.k, pts)
+        return np.einsum("tca,qra,trj->tqcj", cU, dref, self.mesh.Jinv)
+
+    def divergence_max(self, U, pts=None):
+        """max over elements and points of |div u_h| (pointwise; by default at the points
+        of the degree-2k rule)."""
+        return self.divergence_max_local(self.space.local_coeffs(U), pts)
+
+    def divergence_max_local(self, cU, pts=None):
+        if pts is None:
+            pts, _ = simplex_rule(self.d, 2 * self.k)
+        g = self._phys_gradients(cU, np.asarray(pts, dtype=float))
+        return float(np.abs(np.einsum("tqcc->tq", g)).max())
 
     def normal_jump_max(self, U):
         """max over facet quadrature points of |u_A . n - u_B . n|."""
+        return self.normal_jump_max_local(self.space.local_coeffs(U))
+
+    def normal_jump_max_local(self, cU):
+        """max over the facet rule's points (the rule of the residual's facet integrals) of
+        the normal jump |u_A . n - u_B . n| of a broken field."""
         m = self.mesh
-        s, _ = gauss_legendre_01(facet_rule_points(self.k))
+        s, _ = facet_rule(self.d, self.k)
         xa, xb = m.facet_points(s)
-        cU = self.space.local_coeffs(U)
-        va, _ = poly_basis(self.k, xa[..., 0], xa[..., 1])
-        vb, _ = poly_basis(self.k, xb[..., 0], xb[..., 1])
+        va, _ = poly_basis_nd(self.k, xa)
+        vb, _ = poly_basis_nd(self.k, xb)
         uA = np.einsum("eca,era->erc", cU[m.fA_elem], va)
         uB = np.einsum("eca,era->erc", cU[m.fB_elem], vb)
         return float(np.abs(np.einsum("erc,ec->er", uA - uB, m.normal)).max())
 
     def enstrophy(self, U):
         """||curl_h u_h||^2 with the element-wise curl du2/dx - du1/dy."""
-        rule = triangle_rule(2 * self.k)
-        pts, w = rule
-        _, dref = poly_basis(self.k, pts[:, 0], pts[:, 1])
-        cU = self.space.local_coeffs(U)
-        g = np.einsum("tca,qra,trj->tqcj", cU, dref, self.mesh.Jinv)
-        om = g[:, :, 1, 0] - g[:, :, 0, 1]
-        return float(np.einsum("q,t,tq->", w, self.mesh.detJ, om * om))
+        return self.enstrophy_local(self.space.local_coeffs(U))
+
+    def enstrophy_local(self, cU):
+        """||curl_h u_h||^2 of a broken field (degree-2k rule: the squared curl has degree
+        2k - 2, so the integral is exact).  2D: curl = du2/dx - du1/dy; 3D: the vector
+        curl (du3/dy - du2/dz, du1/dz - du3/dx, du2/dx - du1/dy)."""
+        pts, w = simplex_rule(self.d, 2 * self.k)
+        g = self._phys_gradients(cU, pts)
+        if self.d == 2:
+            om2 = (g[:, :, 1, 0] - g[:, :, 0, 1]) ** 2
+        else:
+            om2 = ((g[:, :, 2, 1] - g[:, :, 1, 2]) ** 2 + (g[:, :, 0, 2] - g[:, :, 2, 0]) ** 2
+                   + (g[:, :, 1, 0] - g[:, :, 0, 1]) ** 2)
+        return float(np.einsum("q,t,tq->", w, self.mesh.detJ, om2))
 
 
 def hybrid_system_dense(orc):
     """Dense matrix of the hybrid-mixed system of eq. (FE3) (tiny meshes only).
 
-    Unknown order: broken velocity [T][2][nm] (local basis), broken pressure
-    [T][npr], facet multipliers [E][k+1] in the Legendre basis P_j(2s-1) of the
-    facet parameter s (side A's direction).  Rows: the three equations of (FE3),
-    signed so that the matrix is symmetric.  Returns (K, nU, nW).
+    Unknown order: broken velocity [T][d][nm] (local basis), broken pressure
+    [T][npr], facet multipliers [E][n_f] in a basis of P^k on the facet, in the facet
+    parameter (side A's direction): Legendre P_j(2s-1) on an edge, the reference
+    triangle's orthonormal basis (poly_basis) on a face.  Rows: the three equations of
+    (FE3), signed so that the matrix is symmetric.  Returns (K, nU, nW).
     """
-    m, sp_, k = orc.mesh, orc.space, orc.k
+    m, sp_, k, d = orc.mesh, orc.space, orc.k, orc.d
     T, E, nu, npr, nf = m.T, m.E, sp_.nu, sp_.np_, sp_.nf
-    pts, w = triangle_rule(2 * k)
-    vals, dref = poly_basis(k, pts[:, 0], pts[:, 1])
+    pts, w = simplex_rule(d, 2 * k)
+    vals, dref = poly_basis_nd(k, pts)
     nm = sp_.nm
     Mref = np.einsum("q,qa,qb->ab", w, vals, vals)
     z = vals[:, :npr]
     nU, nW, nL = T * nu, T * npr, E * nf
     K = np.zeros((nU + nW + nL, nU + nW + nL))
-    s, ws = gauss_legendre_01(k + 1)
+    s, ws, lbasis = facet_moment_rule(d, k)  # weights summing to 1
+    if d == 2:
+        lbasis = np.stack([np.polynomial.legendre.legval(2 * s[:, 0] - 1, np.eye(nf)[j]) for j in range(nf)], axis=1)
     for t in range(T):
         iu = slice(t * nu, (t + 1) * nu)
         iw = slice(nU + t * npr, nU + (t + 1) * npr)
-        K[iu, iu][:nm, :nm] = m.detJ[t] * Mref
-        K[iu, iu][nm:, nm:] = m.detJ[t] * Mref
+        for c in range(d):
+            K[iu, iu][c * nm:(c + 1) * nm, c * nm:(c + 1) * nm] = m.detJ[t] * Mref
         div_phi = np.einsum("qra,rc->qca", dref, m.Jinv[t])
         D = np.einsum("q,qp,qca->pca", w, z, div_phi).reshape(npr, nu) * m.detJ[t]
         K[iw, iu] = -D
         K[iu, iw] = -D.T
-        for f in range(3):
+        for f in range(d + 1):
             xh, F = m.element_facet_points(np.array([t]), np.array([f]), s)
             F = int(F[0])
-            v, _ = poly_basis(k, xh[0, :, 0], xh[0, :, 1])          # [R, nm]
+            v, _ = poly_basis_nd(k, xh[0])                             # [R, nm]
             isA = (m.fA_elem[F] == t) and (m.fA_loc[F] == f)
             nT = m.normal[F] if isA else -m.normal[F]
             for j in range(nf):
-                lj = np.polynomial.legendre.legval(2 * s - 1, np.eye(nf)[j])
-                mom = (ws * lj) @ v * m.flen[F]                       # [nm]
+                mom = (ws * lbasis[:, j]) @ v * m.flen[F]                # int_F l_j m_a dS
                 row = nU + nW + F * nf + j
-                for c in range(2):
+                for c in range(d):
                     K[t * nu + c * nm: t * nu + (c + 1) * nm, row] += mom * nT[c]
                     K[row, t * nu + c * nm: t * nu + (c + 1) * nm] += mom * nT[c]
     return K, nU, nW
@@ -225,10 +261,9 @@ def hybrid_system_dense(orc):
 def hybrid_solve_dense(orc, Fbroken):
     """Hybrid-mixed solve of eq. (FE3), written out densely (tiny meshes only).
 
-    Unknowns: broken [P^k]^2 velocity (monomial basis per element), broken
-    P^{k-1} pressure w, facet multiplier lambda in P^k(F) (Legendre basis in the
-    facet parameter).  Fbroken[T, 2, nm] holds the functional on the broken
-    local basis.  The system is singular only by the constant (w, lambda) = (c, c);
+    Unknowns: broken [P^k]^d velocity (local basis per element), broken
+    P^{k-1} pressure w, facet multiplier lambda in P^k(F) (basis of hybrid_system_dense).
+    Fbroken[T, d, nm] holds the functional on the broken local basis.  The system is singular only by the constant (w, lambda) = (c, c);
     it is solved in the least-squares sense.  Returns the velocity's local
     coefficients cU[T, 2, nm].
     """
@@ -236,4 +271,4 @@ def hybrid_solve_dense(orc, Fbroken):
     rhs = np.zeros(K.shape[0])
     rhs[:nU] = Fbroken.reshape(-1)
     sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
-    return sol[:nU].reshape(orc.mesh.T, 2, orc.space.nm)
+    return sol[:nU].reshape(orc.mesh.T, orc.d, orc.space.nm)
