@@ -102,6 +102,11 @@ typedef struct {
                         FP32), 0 = S in FP32.  The preconditioner then uses a symmetric
                         perturbation of S of relative size 2^-11; the PCG itself keeps the
                         FP64 S and its stopping test. */
+  int facet_blocks;  /* blocks of 256 threads of the facet-row kernels: 0 = ceil(E/256) up to
+                        1024 (default); 1..1024 = at most that many.  With fewer blocks
+                        than rows/256, each thread walks several facet rows in a grid-
+                        stride loop (the path every mesh above 262144 facets takes); the
+                        results are the same up to the order of the partial sums. */
 } dfdg_params;
 
 typedef struct {

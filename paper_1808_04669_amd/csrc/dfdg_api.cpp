@@ -148,6 +148,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->graphs = 1;
   p->mg_fp32 = 1;
   p->mg_fine_fp16 = 1;
+  p->facet_blocks = 0;
 }
 
 static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
@@ -172,6 +173,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
+  if (p->facet_blocks < 0 || p->facet_blocks > 1024) { e = "facet_blocks must be in 0..1024"; return -1; }
   return 0;
 }
 
@@ -265,6 +267,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   DevGeo& g = ctx->g;
   g.T = (int)T;
   g.E = (int)E;
+  g.fgrid = facet_grid_size((int)E, ctx->prm.facet_blocks);
   g.Jinv = c.take<double>(4 * T);
   g.detJ = c.take<double>(T);
   g.isq = c.take<double>(T);
@@ -325,7 +328,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->partials = c.take<double>(4 * maxblk);
   ctx->diagres = c.take<double>(4);
   ctx->xpart = c.take<double>(kExtrapParts);
-  const long G = facet_grid_size((int)E);
+  const long G = g.fgrid;
   for (PcgBufs* pb : {&ctx->pb, &ctx->pb32, &ctx->pbt}) {
     pb->sc = c.take<PcgScalars>(1);
     pb->gg = c.take<double>(3 * G);
@@ -802,7 +805,10 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
       // after some progress ends with its last iterate; the FP64 refinement residual
       // decides whether more is needed
       if (fin.done == PCG_NONFINITE || (fin.done == PCG_BREAKDOWN && fin.iters < 1)) st = status_of(fin.done);
-      HIPC(launch_ir_residual(NF, g, A, ctx->gv, x, ctx->x32, 1, ctx->r64, pb, pi.sc, inner, ctx->prm.cg_maxit, s));
+      // the next inner run may take what is left of the iteration limit, so that the device
+      // stops it before the host guard of pcg_loop would
+      HIPC(launch_ir_residual(NF, g, A, ctx->gv, x, ctx->x32, 1, ctx->r64, pb, pi.sc, inner,
+                              std::max(1, ctx->prm.cg_maxit - total), s));
       rc = read_scalars(ctx, pb.sc, o);
       if (rc) return rc;
       if (st != DFDG_OK) break;
@@ -1168,7 +1174,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   PcgScalars st{};
   st.rz = 1.0; st.rr = 1.0; st.gg = 1.0; st.tol2 = -1.0; st.maxit = 1 << 30; st.it = 2;
   HIPC(hipMemcpyAsync(pb.sc, &st, sizeof(st), hipMemcpyHostToDevice, s));
-  const long G = facet_grid_size((int)E);
+  const long G = ctx->g.fgrid;
   HIPC(launch_fill(2 * G, 1.0, pb.rz[0], s));
   HIPC(launch_fill(2 * G, 1.0, pb.rz[1], s));
   HIPC(launch_fill(G, 1.0, pb.pq, s));

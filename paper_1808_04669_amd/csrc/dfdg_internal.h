@@ -58,6 +58,7 @@ void build_ref_tables(int K, RefTables& t);
 // ---- device-side views --------------------------------------------------------------
 struct DevGeo {
   int T, E;
+  int fgrid;            // blocks of the facet-row kernels (grid-stride loops over the rows)
   const double* Jinv;   // [4][T], Jinv[r][j] = dxi_r/dx_j at (2r+j)*T + t
   const double* detJ;   // [T]  (> 0)
   const double* isq;    // [T]  1 / sqrt(detJ)

@@ -26,7 +26,8 @@ struct PcgBufs {
   double* rz[2];   // [G][2] (r,z),(r,r) partials of even / odd iterations
   double* pq;      // [G]    (p,Sp) partials
 };
-int facet_grid_size(int E);  // G: blocks of the facet kernels
+// G: blocks of the facet kernels, ceil(E/256) up to 1024, or at most cap (> 0)
+int facet_grid_size(int E, int cap);
 
 // Multigrid hierarchy on the device (level 0 = the BSR facet matrix itself).
 constexpr int kMaxLev = 16;

@@ -1763,14 +1763,14 @@ hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb
 
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
                            int maxit, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_gather_g<NN>), dim3(G), dim3(kBlk), 0, s, g, q, gv, pb.gg));
   hipLaunchKernelGGL(k_finalize_gather, dim3(1), dim3(kBlk), 0, s, (const double*)pb.gg, G, pb.sc, rtol, maxit);
   return hipGetLastError();
 }
 
 hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   DFDG_DISPATCH_NF(NF, {
     hipLaunchKernelGGL((k_zdot<NN>), dim3(G), dim3(kBlk), 0, s, g, (const double*)x, part);
     hipLaunchKernelGGL((k_zdeflate<NN>), dim3(G), dim3(kBlk), 0, s, g, x, (const double*)part, G);
@@ -1780,7 +1780,7 @@ hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipS
 
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
                            double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   DFDG_DISPATCH_NF(NF, {
     if (bj) hipLaunchKernelGGL((k_pcg_init<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
     else hipLaunchKernelGGL((k_pcg_init<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
@@ -1791,7 +1791,7 @@ hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, co
 template <typename V>
 static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z, const V* p_old, V* p_new, V* Sp,
                            const PcgBufs& pb, int it, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   const double* prev = pb.rz[(it - 1) & 1];
   const double* prev2 = pb.rz[it & 1];
   DFDG_DISPATCH_NF(NF, DFDG_LAUNCH_TIMED((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
@@ -1802,7 +1802,7 @@ static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z,
 template <typename V>
 static hipError_t update_any(int NF, int pc, const DevGeo& g, const DevBsr& A, const V* p, const V* Sp, V* x, V* r,
                              V* z, const PcgBufs& pb, int it, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   const double* prev = pb.rz[(it - 1) & 1];
   double* out = pb.rz[it & 1];
   DFDG_DISPATCH_NF(NF, {
@@ -1832,7 +1832,7 @@ hipError_t launch_pcg32_update(int NF, int pc, const DevGeo& g, const DevBsr& A,
 
 hipError_t launch_pcg32_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* r64, float* x, float* r,
                              float* z, float* p_old, const PcgBufs& pb, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   DFDG_DISPATCH_NF(NF, {
     if (bj) hipLaunchKernelGGL((k_pcg32_init<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, pb.rz[0]);
     else hipLaunchKernelGGL((k_pcg32_init<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, r64, x, r, z, p_old, pb.rz[0]);
@@ -1843,7 +1843,7 @@ hipError_t launch_pcg32_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, 
 hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const double* gv, double* lam,
                               const float* x32, int add, double* r64, const PcgBufs& pb64, PcgScalars* sc32,
                               double inner_rtol, int inner_maxit, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   if (add) {
     const long n = (long)g.E * NF;
     hipLaunchKernelGGL(k_add_f32, dim3(nblk(n, kBlk)), dim3(kBlk), 0, s, n, x32, lam);
@@ -1855,7 +1855,10 @@ hipError_t launch_ir_residual(int NF, const DevGeo& g, const DevBsr& A, const do
   return hipGetLastError();
 }
 
-int facet_grid_size(int E) { return facet_grid(E); }
+int facet_grid_size(int E, int cap) {
+  const int g = facet_grid(E);
+  return (cap > 0 && cap < g) ? cap : g;
+}
 
 // ---- multigrid launchers -------------------------------------------------------------
 #define DFDG_DISPATCH_LPR(L, ...)                                  \
@@ -1879,7 +1882,7 @@ static void csr_apply(const DevCsr& M, const V* x, const V* y0, V* y, int add, c
 template <typename V, typename VB>
 static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
                         PcgScalars* sc, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
   DFDG_DISPATCH_NF_VOID(NF, hipLaunchKernelGGL((k_mg0_resid<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b,
@@ -1920,7 +1923,7 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
 template <typename V, typename VB>
 hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const VB* b, VB* z, double* rz,
                          PcgScalars* sc, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
   if (L == 1) {  // the facet matrix itself is the coarsest level: exact (regularised) solve in VB
@@ -1941,7 +1944,7 @@ template <typename V, typename VB>
 hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, const MgDev& mg, const PcgBufs& pb,
                                    int it, const VB* z_in, const VB* p_old, VB* p_new, VB* Sp, VB* x,
                                    const VB* r_old, VB* r_new, VB* z, hipStream_t s) {
-  const int G = facet_grid(g.E);
+  const int G = g.fgrid;
   hipError_t e = spmv_any<VB>(NF, g, A, z_in, p_old, p_new, Sp, pb, it, s);
   if (e != hipSuccess) return e;
   const double* prev = pb.rz[(it - 1) & 1];

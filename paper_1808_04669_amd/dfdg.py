@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ir_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int), ("mg_fp32", ctypes.c_int),
-                ("mg_fine_fp16", ctypes.c_int)]
+                ("mg_fine_fp16", ctypes.c_int), ("facet_blocks", ctypes.c_int)]
 
 
 class Sizes(ctypes.Structure):
@@ -162,8 +162,7 @@ class Solver:
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
                  precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, mg_fp32=True,
-                 mg_fine_fp16=True,
-                 device="cuda:0", stream=None):
+                 mg_fine_fp16=True, facet_blocks=0, device="cuda:0", stream=None):
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
@@ -179,6 +178,7 @@ class Solver:
         p.graphs = 1 if graphs else 0
         p.mg_fp32 = 1 if mg_fp32 else 0
         p.mg_fine_fp16 = 1 if mg_fine_fp16 else 0
+        p.facet_blocks = int(facet_blocks)
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
@@ -218,6 +218,23 @@ class Solver:
         pts = np.empty((self.nq_proj, 2))
         w = np.empty(self.nq_proj)
         self._check(self._lib.dfdg_proj_rule(self._h, pts.ctypes.data_as(_P), w.ctypes.data_as(_P)))
+        return pts, w
+
+    def set_stream(self, stream):
+        """Move the context to another torch stream (dfdg_ctx_set_stream waits for the work
+        still queued on the previous one)."""
+        self._check(self._lib.dfdg_ctx_set_stream(self._h, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
+
+    def residual_rule(self):
+        """Points [n, 2] and weights [n] of the residual's volume rule (also the points of
+        max |div u| in the diagnostics)."""
+        n = ctypes.c_int()
+        self._check(self._lib.dfdg_debug_residual_rule(self.k, ctypes.byref(n), None, None))
+        pts = np.empty((n.value, 2))
+        w = np.empty(n.value)
+        self._check(self._lib.dfdg_debug_residual_rule(self.k, ctypes.byref(n), pts.ctypes.data_as(_P),
+                                                       w.ctypes.data_as(_P)))
         return pts, w
 
     # ---- entry points -----------------------------------------------------------------

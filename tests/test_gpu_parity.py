@@ -200,7 +200,11 @@ def test_mass_solve_symmetric_and_idempotent_full_size(precond):
     assert (PPf - Pf).norm().item() < 1e-9 * Pf.norm().item()
     d = s.diagnostics(Pf)
     _log("  diag", d)
+    # white-noise data: velocities of order sqrt(T) and gradients of order N sqrt(T), so
+    # the bounds are relative to the gradient scale (the absolute 1e-11 bound is asserted on
+    # the double shear layer trajectory in test_gpu_fullsize.py)
     assert d["max_div"] < 1e-11 * np.sqrt(d["enstrophy"])
+    assert d["max_normal_jump"] < 1e-11 * np.sqrt(d["enstrophy"])
 
 
 @pytest.mark.parametrize("N,k,kw,limit", [(256, 1, {}, 26), (128, 3, {}, 37),
@@ -223,10 +227,7 @@ def test_stream_switch_and_early_start_values_keep_the_trajectory():
     """RK3 steps whose stage start values are formed ahead (while the host waits for the
     previous solve), with the context moved to another stream half-way (the switch waits
     for the work still queued on the old one), give the same bits as steps on one stream."""
-    import ctypes
     from gpu_util import project_field
-    from paper_1808_04669_amd import dfdg
-    lib = dfdg.load_library()
     runs = []
     for switch in (False, True):
         _, s, xyz, _ = make_pair(16, 2, oracle=False, cg_rtol=1e-12, precond="amg", extrapolate="adaptive")
@@ -236,7 +237,8 @@ def test_stream_switch_and_early_start_values_keep_the_trajectory():
         its = []
         for n in range(6):
             if switch and n == 3:
-                assert lib.dfdg_ctx_set_stream(s._h, ctypes.c_void_p(other.cuda_stream)) == 0
+                s.set_stream(other)
+                assert s.stream is other
             its.append(list(s.rk3_step(U, dt).iterations))
         torch.cuda.synchronize()
         runs.append((U.clone(), its))
