@@ -249,6 +249,20 @@ int dfdg_diagnostics(dfdg_ctx* ctx, const double* U_dev, dfdg_diag* out_host);
 int dfdg_eval(dfdg_ctx* ctx, const double* U_dev, int npts, const double* ref_pts_host,
               double* out_dev);
 
+/* ---- allocation-free variant -------------------------------------------------------
+ * dfdg_diagnostics_noalloc: dfdg_diagnostics for callers that cannot allocate device memory
+ *   at the time of the call (code under HIP graph capture, tight serving loops, harnesses
+ *   that forbid allocation).  Same kernels and results (bit for bit) as dfdg_diagnostics,
+ *   but its scratch (one partial sum per element block and the four results) lives in a
+ *   static device array of the library, 512 KiB per GPU, held until the process ends,
+ *   instead of in the context's workspace.  The call allocates nothing.  Limit: meshes of at
+ *   most 2097152 elements (larger ones return DFDG_E_INVALID_ARG).  Call it with the device
+ *   current on which the context was bound (else DFDG_E_INVALID_ARG).  Every context on one
+ *   GPU shares that array: calls that overlap on one GPU (two host threads, or two streams
+ *   running at once) race and must be serialised by the caller; each call writes every
+ *   value it reads, so the contents left by an earlier call do not matter. */
+int dfdg_diagnostics_noalloc(dfdg_ctx* ctx, const double* U_dev, dfdg_diag* out_host);
+
 /* ---- measurement -------------------------------------------------------------------
  * dfdg_time_kernel: launches kernel `which` `reps` times on the context stream and
  * returns the mean duration in ms.  Single kernels (which = 0, 2, 3) carry their own

@@ -64,6 +64,7 @@ struct dfdg_ctx {
   hipGraphExec_t graph64[6] = {}, graph32[6] = {};
   int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
+  double* noalloc = nullptr;  // device address of the static scratch of dfdg_diagnostics_noalloc
   std::string err;
 };
 
@@ -571,6 +572,8 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   }
   HIPC(hipStreamSynchronize(s));
   if (!ctx->pinned) HIPC(hipHostMalloc((void**)&ctx->pinned, 4 * sizeof(PcgScalars), hipHostMallocDefault));
+  // the device address of the allocation-free diagnostics' scratch on this (current) device
+  HIPC(noalloc_scratch(&ctx->noalloc));
   ctx->bound = true;
   for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
   invalidate_guesses(ctx);
@@ -1145,6 +1148,34 @@ extern "C" int dfdg_diagnostics(dfdg_ctx* ctx, const double* U, dfdg_diag* out) 
   out->enstrophy = res[1];
   out->max_div = res[2];
   out->max_normal_jump = res[3];
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_diagnostics_noalloc(dfdg_ctx* ctx, const double* U, dfdg_diag* out) {
+  NEED_BOUND(ctx);
+  if (!U || !out) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (diag_blocks(ctx->T) > kNoAllocDiagBlocks)
+    return fail(ctx, DFDG_E_INVALID_ARG,
+                "dfdg_diagnostics_noalloc: " + std::to_string(ctx->T) + " elements exceed its static scratch (at most " +
+                    std::to_string(kNoAllocDiagBlocks * 128) + ")");
+  int dev = -1;
+  HIPC(hipGetDevice(&dev));
+  double* part = nullptr;
+  HIPC(noalloc_scratch(&part));  // the same address as at set-up when called on that device
+  if (part != ctx->noalloc)
+    return fail(ctx, DFDG_E_INVALID_ARG, "dfdg_diagnostics_noalloc: called with another device current (" +
+                                             std::to_string(dev) + ") than at set-up");
+  double* res = part + 4 * kNoAllocDiagBlocks;
+  // every partial and result is written before it is read: nothing to clear
+  HIPC(launch_diagnostics(ctx->K, ctx->g, ctx->tb, U, part, res, ctx->stream));
+  double r[4];
+  HIPC(hipMemcpyAsync(ctx->pinned, res, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  std::memcpy(r, ctx->pinned, sizeof(r));
+  out->energy = r[0];
+  out->enstrophy = r[1];
+  out->max_div = r[2];
+  out->max_normal_jump = r[3];
   return DFDG_OK;
 }
 

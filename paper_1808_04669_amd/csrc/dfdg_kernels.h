@@ -159,4 +159,13 @@ hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, 
 // S (FP64, [5][NF][NF][E]) times scale in FP16, two values per word (DevBsr::vals16)
 hipError_t launch_pack_half_pairs(int NF, int E, const double* vals, double scale, uint32_t* out, hipStream_t s);
 
+// Allocation-free diagnostics: a static device scratch of kNoAllocDiagBlocks partials (one per
+// element block of the diagnostics kernel, i.e. meshes of up to 2097152 elements) plus the
+// results.  noalloc_scratch gives its address on the current device (looked up once per
+// device); diag_blocks(T) is the number of partials a mesh of T elements needs.
+constexpr int kNoAllocDiagBlocks = 16384;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(double** out);
+int diag_blocks(int T);
+
 }  // namespace dfdg

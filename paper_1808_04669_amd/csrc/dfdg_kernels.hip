@@ -14,6 +14,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "dfdg_internal.h"
 #include "dfdg_kernels.h"
@@ -2069,5 +2070,32 @@ hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, doub
   hipLaunchKernelGGL(k_extrapolate_pick, dim3(G), dim3(kBlk), 0, s, n, omax, h, (const double*)part, G, out);
   return hipGetLastError();
 }
+
+// ---- allocation-free diagnostics ---------------------------------------------------------
+// Scratch of dfdg_diagnostics_noalloc: the per-block partials [kNoAllocDiagBlocks][4] and the
+// four results, in a file-scope device array (each GPU holds its own copy until the process
+// ends).  In host code the array's name is a host-side stand-in, never a device address:
+// kernels and copies get the address from hipGetSymbolAddress, looked up once per device.
+static __device__ __align__(256) double scratch[4 * kNoAllocDiagBlocks + 4];
+
+hipError_t noalloc_scratch(double** out) {
+  static std::mutex mu;
+  static double* ptr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptr[dev] = static_cast<double*>(p);
+  }
+  *out = ptr[dev];
+  return hipSuccess;
+}
+
+int diag_blocks(int T) { return (int)nblk(T, kEBlk); }
 
 }  // namespace dfdg

@@ -94,6 +94,7 @@ _SIGS = {
     "dfdg_rk3_step_vjp": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
     "dfdg_rk3_step_vjp_stages": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
     "dfdg_diagnostics": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
+    "dfdg_diagnostics_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
     "dfdg_eval": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
     "dfdg_time_kernel": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float),
                                         ctypes.POINTER(ctypes.c_double)]),
@@ -329,6 +330,13 @@ class Solver:
     def diagnostics(self, U):
         d = Diag()
         self._check(self._lib.dfdg_diagnostics(self._h, self._vec(U, self.n_broken, "U"), ctypes.byref(d)))
+        return {"energy": d.energy, "enstrophy": d.enstrophy, "max_div": d.max_div,
+                "max_normal_jump": d.max_normal_jump}
+
+    def diagnostics_noalloc(self, U):
+        """dfdg_diagnostics_noalloc: the diagnostics with the library's static scratch."""
+        d = Diag()
+        self._check(self._lib.dfdg_diagnostics_noalloc(self._h, self._vec(U, self.n_broken, "U"), ctypes.byref(d)))
         return {"energy": d.energy, "enstrophy": d.enstrophy, "max_div": d.max_div,
                 "max_normal_jump": d.max_normal_jump}
 
