@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-random-order", action="store_true", help="skip the randomly numbered mesh run")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D Taylor-Green run")
+    ap.add_argument("--three-d-N", type=int, default=32)
+    ap.add_argument("--three-d-steps", type=int, default=50)
     ap.add_argument("--mixed-N", type=int, default=512)
     ap.add_argument("--mixed-k", type=int, default=3)
     ap.add_argument("--mixed-steps", type=int, default=20)
@@ -84,14 +87,17 @@ def log(*a):
 
 
 def project_field(s, field):
+    """GPU L2 projection of a closed-form field sampled at the library's projection points
+    (triangles or tetrahedra); returns U, max |u| at those points and the solve info."""
     import torch
     pts, _ = s.proj_rule()
     xyz = s._xyz
-    x = xyz[:, None, 0, :] + (pts[None, :, 0, None] * (xyz[:, None, 1, :] - xyz[:, None, 0, :])
-                              + pts[None, :, 1, None] * (xyz[:, None, 2, :] - xyz[:, None, 0, :]))
-    u1, u2 = field(x[..., 0], x[..., 1])  # [T, nq]
-    vmax = float(np.sqrt(u1 ** 2 + u2 ** 2).max())
-    fq = torch.from_numpy(np.ascontiguousarray(np.stack([u1.T, u2.T]))).to(s.device).reshape(-1)
+    J = np.transpose(xyz[:, 1:] - xyz[:, :1], (0, 2, 1))
+    x = xyz[:, None, 0, :] + np.einsum("tir,qr->tqi", J, pts)
+    u = field(*[x[..., i] for i in range(s.dim)])  # d arrays [T, nq]
+    vmax = float(np.sqrt(sum(c ** 2 for c in u)).max())
+    fq = torch.from_numpy(np.ascontiguousarray(np.stack([c.T for c in u]))).to(s.device).reshape(-1)
+    del x, u
     U, info = s.project(fq)
     return U, vmax, info
 
@@ -202,12 +208,12 @@ def mixed_vs_fp64(args):
         U, vmax, _ = project_field(s, double_shear_layer)
         dt = 0.1 / N / (k ** 2 * vmax)
         t, its = timed_run(s, U, dt, steps, 2)
-        res[prec] = (t, its, U, s.n_bdm)
+        res[prec] = (t, its, U, s.n_bdm, s.diagnostics(U), s.setup_seconds)
         del s
         torch.cuda.empty_cache()
-    t64, it64, U64, n_u = res["fp64"]
-    tpl, itpl, _, _ = res["fp64_plain"]
-    tm, itm, Um, _ = res["mixed"]
+    t64, it64, U64, n_u, d64, su64 = res["fp64"]
+    tpl, itpl, _, _, _, _ = res["fp64_plain"]
+    tm, itm, Um, _, dm, sum_ = res["mixed"]
     return {"workload": f"double shear layer {N}x{N} split mesh, BDM_{k}, {steps} TVD-RK3 steps, "
                         f"FP64 PCG rtol {args.mixed_ir_rtol:g} vs mixed (FP32 residual and inner PCG, "
                         f"inner rtol {args.mixed_inner_rtol:g}, FP64 refinement to {args.mixed_ir_rtol:g})",
@@ -217,7 +223,94 @@ def mixed_vs_fp64(args):
             "note": ("fp64: FP64 PCG with the multigrid V-cycle in FP32 (the benchmark path); "
                      "fp64_plain: everything in FP64"),
             "iterations_per_stage": {"fp64": float(it64.mean()), "fp64_plain": float(itpl.mean()),
-                                     "mixed_inner_total": float(itm.mean())}}
+                                     "mixed_inner_total": float(itm.mean())},
+            "max_div": {"fp64": d64["max_div"], "mixed": dm["max_div"]},
+            "max_normal_jump": {"fp64": d64["max_normal_jump"], "mixed": dm["max_normal_jump"]},
+            "setup_s": {"fp64": su64, "mixed": sum_}}
+
+
+def three_d(args):
+    """The 3D periodic Taylor-Green vortex on the 32^3 Kuhn-split cube (196608 tetrahedra),
+    BDM_2, nu = 1/1600, FP64, Jacobi-preconditioned facet PCG, TVD-RK3 at CFL 0.1: velocity
+    DOF-stages/s, the 7-slot facet SpMV against the HBM peak (its 793 MB matrix is three
+    times the Infinity Cache), set-up time, and the FP64 error against the oracle on the
+    same workload at N = 4 (where its sparse direct solve still runs)."""
+    import torch
+    from inputs import periodic_kuhn_cube, taylor_green_3d
+    from paper_1808_04669_amd import Solver
+    N, k, nu, steps = args.three_d_N, 2, 1.0 / 1600, args.three_d_steps
+    xyz, per = periodic_kuhn_cube(N, args.order)
+    # the multigrid-preconditioned PCG on the same workload, reported beside the Jacobi one
+    sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, precond="amg", extrapolate=args.extrapolate)
+    sa._xyz = xyz
+    Ua, vmax, _ = project_field(sa, taylor_green_3d)
+    dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
+    ta, itsa = timed_run(sa, Ua, dt, steps, 2)
+    amg = {"value": sa.n_bdm * 3 * steps / ta, "ms_per_step": 1e3 * ta / steps,
+           "pcg_iterations_per_stage": float(itsa.mean()), "setup_s": sa.setup_seconds,
+           "diagnostics_final": sa.diagnostics(Ua)}
+    if sa.mg_levels():
+        amg["levels_rows"] = sa.mg_levels()
+    ms_vc, b_vc = sa.time_kernel(4, reps=20)
+    amg["vcycle"] = {"us": round(ms_vc * 1e3, 3), "GB/s": round(b_vc / ms_vc / 1e6, 1)}
+    del sa, Ua
+    torch.cuda.empty_cache()
+    s = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, precond="jacobi", extrapolate=args.extrapolate)
+    s._xyz = xyz
+    U, vmax, pinfo = project_field(s, taylor_green_3d)
+    t, its = timed_run(s, U, dt, steps, 2)
+    d = s.diagnostics(U)
+    ms_spmv, b_spmv = s.time_kernel(0, reps=50)
+    ms_res, b_res = s.time_kernel(2, reps=50)
+    spmv_gbs = b_spmv / (ms_spmv * 1e-3) / 1e9
+    out = {"workload": f"3D periodic Taylor-Green, {N}^3 Kuhn-split cube ({s.T} tetrahedra), BDM_{k}, "
+                       f"nu=1/1600, FP64, Jacobi PCG rtol {args.rtol:g}, TVD-RK3 CFL 0.1, {steps} steps",
+           "value": s.n_bdm * 3 * steps / t, "unit": "velocity DOF-stages/s", "ms_per_step": 1e3 * t / steps,
+           "N_u": s.n_bdm, "T": s.T, "E": s.E, "dt": dt, "projection_iterations": pinfo.iterations,
+           "pcg_iterations_per_stage": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min())},
+           "diagnostics_final": d, "setup_s": s.setup_seconds,
+           "spmv": {"kernel": "k_pcg_spmv<6, 7> (7-slot face BSR SpMV + p update + (p,Sp) partials)",
+                    "avg_launch_us": round(ms_spmv * 1e3, 3), "bytes_per_launch": b_spmv,
+                    "achieved_GBs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
+           "residual": {"avg_launch_us": round(ms_res * 1e3, 3), "bytes_per_launch": b_res,
+                        "GBs": round(b_res / (ms_res * 1e-3) / 1e9, 1)},
+           "amg": amg}
+    del s
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        out["accuracy"] = three_d_accuracy(args)
+    return out
+
+
+def three_d_accuracy(args):
+    """Relative L2 difference between the GPU FP64 path and the oracle after 3 steps of the
+    3D Taylor-Green workload on the 4^3 Kuhn mesh (BDM_2, nu = 1/1600), both from the
+    oracle's projected initial field."""
+    import torch
+    from inputs import periodic_kuhn_cube, taylor_green_3d
+    from oracle import Oracle
+    from oracle.quadrature import tet_rule
+    from paper_1808_04669_amd import Solver
+    N, k, nu, steps = 4, 2, 1.0 / 1600, 3
+    xyz, per = periodic_kuhn_cube(N, args.order)
+    orc = Oracle(xyz, per, k, nu=nu)
+    U0 = orc.project(taylor_green_3d)
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for _ in range(steps):
+        Uo = orc.rk3_step(Uo, dt)
+    s = Solver(xyz, per, k, nu=nu, cg_rtol=1e-13, precond="jacobi", extrapolate=2)
+    qp, _ = s.proj_rule()
+    vals = np.ascontiguousarray(np.transpose(orc.eval_ref(U0, qp), (1, 2, 0)))
+    U = s.load_vector(torch.from_numpy(vals).to(s.device).reshape(-1))
+    for _ in range(steps):
+        s.rk3_step(U, dt)
+    pts, w = tet_rule(2 * k + 2)
+    g = s.eval(U, pts).cpu().numpy().transpose(2, 0, 1)
+    o = orc.eval_ref(Uo, pts)
+    return {"rel_l2_fp64_vs_oracle": orc.l2_diff(g, o, (pts, w)) / orc.l2_diff(o, 0 * o, (pts, w)),
+            "max_div_fp64": s.diagnostics(U)["max_div"], "max_div_oracle": orc.divergence_max(Uo),
+            "sample": f"{N}^3 Kuhn mesh, BDM_{k}, nu=1/1600, {steps} steps"}
 
 
 def adjoint_cost(args):
@@ -318,6 +411,7 @@ def main():
                       "extrapolate": args.extrapolate, "order": args.order},
            "pcg_iterations_per_stage": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min())},
            "diagnostics_final": d,
+           "setup_s": s.setup_seconds,
            "roofline": roof}
     if not args.no_random_order:
         sr = make_solver(N, k, "fp64", args, order="random")
@@ -334,6 +428,9 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_cost(args)
         log("adjoint", out["adjoint"])
+    if not args.no_3d:
+        out["three_d"] = three_d(args)
+        log("3d", out["three_d"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"], (orc, U0_orc, U_orc, dt_s) = cpu_baseline(args)
         log("cpu baseline", out["cpu_baseline"])

@@ -10,7 +10,8 @@
  * hybrid-mixed Poisson problem of eq. (FE3): element-local static condensation onto
  * facet multipliers, a global symmetric positive semi-definite facet system solved by
  * preconditioned CG, and element-local recovery (Theorem 2).  Time stepping is
- * TVD-RK3 (eq. (rk3)).  Two-dimensional periodic triangle meshes are supported.
+ * TVD-RK3 (eq. (rk3)).  Periodic triangle meshes (d = 2) and periodic tetrahedral
+ * meshes (d = 3; the method is posed for d = 2, 3, Sec. 2) are supported.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -31,16 +32,21 @@
  *   dfdg_last_error() gives a message for the last failing call on a context,
  *   dfdg_mesh_last_error() for mesh creation.  A context is not thread safe.
  * Layouts (all FP64 unless stated).
- *   T elements, E facets, P = (k+1)(k+2)/2, n_f = k+1.
- *   Velocity-like vectors (U, L, F, adjoints): [2][P][T] — component c, basis
+ *   T elements, E facets, d the dimension, P = dim P^k(element) ((k+1)(k+2)/2 on
+ *   triangles, (k+1)(k+2)(k+3)/6 on tetrahedra), n_f = dim P^k(facet) (k+1 on edges,
+ *   (k+1)(k+2)/2 on faces).
+ *   Velocity-like vectors (U, L, F, adjoints): [d][P][T] — component c, basis
  *   function i, element t at index (c*P + i)*T + t.  The basis of element t is
  *   psi_i(x) = psihat_i(xhat)/sqrt(|det J_t|) e_c, with psihat_i the L2-orthonormal
- *   Dubiner polynomials of the reference triangle, so the element mass matrix is the
+ *   Dubiner polynomials of the reference simplex, so the element mass matrix is the
  *   identity, kinetic energy is 0.5*sum(U^2), and a functional F is stored by its
  *   values F(psi_i e_c).  xhat are the reference coordinates with respect to the
- *   element's vertices as passed to dfdg_mesh_create: x = v0 + xi (v1-v0) + eta (v2-v0).
- *   Facet multipliers lambda: [E][n_f], Legendre coefficients along the facet (the
- *   facet numbering is the library's; see dfdg_mesh_facets).
+ *   element's vertices as passed to dfdg_mesh_create: x = v0 + sum_r xhat_r (v_{r+1}-v0).
+ *   Facet multipliers lambda: [E][n_f], coefficients in an L2(F)-orthonormal basis of
+ *   P^k on the facet, in the parametrisation of the facet's first element (Legendre
+ *   polynomials along an edge; the triangle's Dubiner polynomials on a face spanned from
+ *   its lowest-numbered local vertex); the facet numbering is the library's (see
+ *   dfdg_mesh_facets).
  */
 #ifndef DFDG_H
 #define DFDG_H
@@ -113,8 +119,9 @@ typedef struct {
   int32_t T, E, k, P, n_f, n_p;
   int64_t n_broken;   /* 2*P*T, length of velocity-like vectors */
   int64_t n_lambda;   /* n_f*E */
-  int64_t n_bdm;      /* dim BDM_k = E*n_f + T*(2P - 3 n_f) */
+  int64_t n_bdm;      /* dim BDM_k = E*n_f + T*(d P - (d+1) n_f) */
   int32_t nq_proj;    /* points of the projection rule (dfdg_proj_rule) */
+  int32_t dim;        /* d: 2 (triangles) or 3 (tetrahedra) */
 } dfdg_sizes;
 
 typedef struct {
@@ -142,10 +149,13 @@ typedef struct {
 } dfdg_diag;
 
 /* ---- mesh (host only; a0 of the hot path) ---------------------------------------
- * dfdg_mesh_create: elem_xyz_host[T][3][2] vertex coordinates of each triangle,
- * counter-clockwise and non-degenerate; period_host[2] > 0 (both directions
- * periodic; every facet must match another one modulo the period).  Facets are
- * identified by their midpoints modulo the period.  Copies its inputs. */
+ * dfdg_mesh_create: dim = 2: elem_xyz_host[T][3][2] vertex coordinates of each triangle,
+ * counter-clockwise and non-degenerate; dim = 3: elem_xyz_host[T][4][3] of each
+ * tetrahedron, positively oriented (det[v1-v0, v2-v0, v3-v0] > 0).  period_host[dim] > 0
+ * (every direction periodic; every facet must match another one modulo the period).
+ * Facets are identified by their barycentres modulo the period; a local facet f is the
+ * edge (f+1)%3 -> (f+2)%3 of a triangle, the face opposite vertex f of a tetrahedron.
+ * Copies its inputs. */
 int dfdg_mesh_create(int dim, int n_elem, const double* elem_xyz_host,
                      const double* period_host, dfdg_mesh** out);
 void dfdg_mesh_destroy(dfdg_mesh* mesh);
@@ -156,7 +166,9 @@ int dfdg_mesh_facets(const dfdg_mesh* mesh, int32_t* facets_host);
 
 /* ---- context --------------------------------------------------------------------
  * dfdg_ctx_create validates the parameters and does the host part of setup
- * (reference tabulations, geometry, condensation matrices, facet matrix).
+ * (reference tabulations, geometry, condensation matrices, facet matrix).  On
+ * tetrahedral meshes it accepts k = 1, 2, DFDG_FP64 and the Jacobi or block-Jacobi
+ * preconditioner (other requests return DFDG_E_UNSUPPORTED).
  * hip_stream is a hipStream_t (NULL = default stream).  The mesh may be destroyed
  * afterwards. */
 void dfdg_params_default(dfdg_params* p);
@@ -172,10 +184,11 @@ const char* dfdg_last_error(const dfdg_ctx* ctx);
 void dfdg_ctx_destroy(dfdg_ctx* ctx);
 
 /* ---- initial data (a2) ------------------------------------------------------------
- * dfdg_proj_rule: reference points ref_pts_host[nq_proj][2] and weights
- * w_host[nq_proj] of the projection rule (exact for degree 2k+4).
+ * dfdg_proj_rule: reference points ref_pts_host[nq_proj][d] and weights
+ * w_host[nq_proj] of the projection rule (exact for degree 2k+4 on triangles, 2k+2 on
+ * tetrahedra).
  * dfdg_load_vector: F(psi_i e_c) = int_T f . psi_i e_c for f given by its values
- * f_at_q_dev[2][nq_proj][T] at those points (element t's point q is
+ * f_at_q_dev[d][nq_proj][T] at those points (element t's point q is
  * v0 + J xhat_q).  dfdg_project: load vector followed by dfdg_hdiv_mass_solve, i.e.
  * the L2 projection onto V_h^{k,-1} (Sec. 2.3, with u0 divergence free). */
 int dfdg_proj_rule(const dfdg_ctx* ctx, double* ref_pts_host, double* w_host);
@@ -243,7 +256,7 @@ int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un_dev, const double* 
                              const double* U2_dev, double* Ubar_io_dev, double dt, dfdg_step_info* info);
 
 /* ---- diagnostics and evaluation (a10) -----------------------------------------------
- * dfdg_eval: values out_dev[2][npts][T] of U at reference points ref_pts_host[npts][2]
+ * dfdg_eval: values out_dev[d][npts][T] of U at reference points ref_pts_host[npts][d]
  *   (npts <= 1024) of every element. */
 int dfdg_diagnostics(dfdg_ctx* ctx, const double* U_dev, dfdg_diag* out_host);
 int dfdg_eval(dfdg_ctx* ctx, const double* U_dev, int npts, const double* ref_pts_host,
@@ -283,11 +296,22 @@ int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms_per_launch,
  *   gradients at npts points pts_host[npts][2]: vals_host[npts][P],
  *   grads_host[npts][2][P] (may be NULL).
  * dfdg_debug_facet_matrix: the facet matrix S assembled on the host at context creation,
- *   as BSR: cols_host[5][E] (column facets) and vals_host[5][n_f][n_f][E]
- *   (slot, row mode, column mode, facet row).  Repeated columns of a row are merged into
- *   their first slot, the others hold zeros. */
+ *   as BSR: cols_host[ns][E] (column facets) and vals_host[ns][n_f][n_f][E]
+ *   (slot, row mode, column mode, facet row), ns = 5 blocks per row on triangles (the
+ *   facet, the other two facets of its first element, those of its second), 7 on
+ *   tetrahedra (three and three).  Repeated columns of a row are merged into their first
+ *   slot, the others hold zeros. */
 int dfdg_debug_basis(int k, int npts, const double* pts_host, double* vals_host, double* grads_host);
 int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols_host, double* vals_host);
+/* dfdg_debug_basis3: the orthonormal Dubiner basis of the reference tetrahedron (k = 1, 2) at
+ *   points pts_host[npts][3]: vals_host[npts][P], grads_host[npts][3][P] (may be NULL).
+ * dfdg_debug_rule3: the tetrahedral path's rules for degree k (1, 2): which = 0 the
+ *   residual's volume rule (exact for degree 3k-1, points [n][3], weights summing to 1/6),
+ *   1 the face rule of the facet integrals (the fully symmetric rule of degree 4 (k = 1,
+ *   6 points) or 6 (k = 2, 12 points): face parameters [n][2], weights summing to 1),
+ *   2 the projection rule; pts_host / w_host may be NULL (then only *npts is set). */
+int dfdg_debug_basis3(int k, int npts, const double* pts_host, double* vals_host, double* grads_host);
+int dfdg_debug_rule3(int k, int which, int* npts, double* pts_host, double* w_host);
 /* dfdg_debug_residual_rule: the volume quadrature rule of the residual for degree k on the
  *   reference triangle {xi, eta >= 0, xi + eta <= 1} (exact for total degree 3k-1, weights
  *   summing to the area 1/2): *npts receives the number of points; pts_host[npts][2] and

@@ -35,11 +35,11 @@ def build(verbose=True):
     inc = [f"-I{INCLUDE}", f"-I{CSRC}"]
     objs = []
     cxx = shutil.which("g++") or "g++"
-    for src in ("dfdg_setup.cpp", "dfdg_amg.cpp", "dfdg_api.cpp"):
+    for src in ("dfdg_setup.cpp", "dfdg_setup3.cpp", "dfdg_amg.cpp", "dfdg_api.cpp"):
         obj = os.path.join(objdir, src.replace(".cpp", ".o"))
         _run([cxx, *CXX_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
-    for src in ("dfdg_kernels.hip",):
+    for src in ("dfdg_kernels.hip", "dfdg_kernels3.hip"):
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, *inc, "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)

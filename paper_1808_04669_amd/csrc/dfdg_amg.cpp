@@ -16,14 +16,14 @@
 
 namespace dfdg {
 
-static Csr bsr_to_csr(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals) {
+static Csr bsr_to_csr(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals) {
   Csr A;
   A.n = A.m = E * NF;
   A.ptr.assign(A.n + 1, 0);
-  std::vector<int> cs(5);
+  std::vector<int> cs(NS);
   for (int F = 0; F < E; ++F) {
     int nu = 0;
-    for (int s = 0; s < 5; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const int c = cols[(size_t)s * E + F];
       bool seen = false;
       for (int t = 0; t < nu; ++t) seen |= (cs[t] == c);
@@ -35,7 +35,7 @@ static Csr bsr_to_csr(int E, int NF, const std::vector<int>& cols, const std::ve
       for (int t = 0; t < nu; ++t)
         for (int b = 0; b < NF; ++b) {
           double v = 0;
-          for (int s = 0; s < 5; ++s)
+          for (int s = 0; s < NS; ++s)
             if (cols[(size_t)s * E + F] == cs[t]) v += vals[(((size_t)s * NF + a) * NF + b) * E + F];
           A.col.push_back(cs[t] * NF + b);
           A.val.push_back(v);
@@ -222,11 +222,11 @@ static bool dense_spd_inverse(int n, std::vector<double>& A) {
   return true;
 }
 
-int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals,
+int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals,
               const std::vector<double>& z, double theta, int max_coarse, AmgHierarchy& H, std::string& err) {
   H.lv.clear();
   AmgLevel L0;
-  L0.A = bsr_to_csr(E, NF, cols, vals);
+  L0.A = bsr_to_csr(E, NF, NS, cols, vals);
   std::vector<double> B = z;  // near-null vector on the current level
   int nf = NF;                // unknowns per node on the current level
   H.lv.push_back(std::move(L0));

@@ -30,11 +30,11 @@ struct AmgHierarchy {
   int n_coarse = 0;
 };
 
-// Builds the hierarchy for the BSR facet matrix (cols [5][E], vals [5][NF][NF][E]) with the
+// Builds the hierarchy for the BSR facet matrix (cols [NS][E], vals [NS][NF][NF][E]) with the
 // near-null vector z (the constant multiplier, scalar length E*NF).  theta: strength threshold;
 // coarsening stops at max_coarse rows, or earlier (at most 4096 rows) when aggregation
 // no longer halves the level.
-int build_amg(int E, int NF, const std::vector<int>& cols, const std::vector<double>& vals,
+int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals,
               const std::vector<double>& z, double theta, int max_coarse, AmgHierarchy& H, std::string& err);
 
 }  // namespace dfdg

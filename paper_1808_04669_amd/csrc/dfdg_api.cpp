@@ -26,6 +26,7 @@ struct dfdg_ctx {
   dfdg_params prm{};
   hipStream_t stream = nullptr;
   HostSetup hs;
+  int dim = 2;  // 2: triangles, 3: tetrahedra
   int K = 0, P = 0, NF = 0, T = 0, E = 0;
   long nU = 0, nL = 0;
   size_t ws_need = 0;
@@ -93,21 +94,45 @@ static int fail(dfdg_ctx* c, int code, const std::string& msg) {
     if (!(ctx)->bound) return fail(ctx, DFDG_E_WORKSPACE, "no workspace bound");          \
   } while (0)
 
+// Element steps on triangles or tetrahedra (the facet kernels are shared).
+static hipError_t el_residual(dfdg_ctx* ctx, bool f32, const double* U, void* L, hipStream_t s) {
+  if (ctx->dim == 3) return launch_residual3(ctx->K, ctx->g, ctx->tb, U, (double*)L, ctx->prm.nu, s);
+  return launch_residual(ctx->K, f32, ctx->g, ctx->tb, U, L, ctx->prm.nu, s);
+}
+static hipError_t el_cond_rhs(dfdg_ctx* ctx, bool f32, const void* F, hipStream_t s) {
+  if (ctx->dim == 3) return launch_cond_rhs3(ctx->K, ctx->g, ctx->tb, (const double*)F, ctx->q, s);
+  return launch_cond_rhs(ctx->K, f32, ctx->g, ctx->tb, F, ctx->q, s);
+}
+static hipError_t el_recover(dfdg_ctx* ctx, bool f32, const void* F, const double* lam, double* out, int mode,
+                             double a, const double* Un, double b, const double* Us, double dt, hipStream_t s) {
+  if (ctx->dim == 3) return launch_recover3(ctx->K, ctx->g, ctx->tb, (const double*)F, lam, out, mode, a, Un, b, Us, dt, s);
+  return launch_recover(ctx->K, f32, ctx->g, ctx->tb, F, lam, out, mode, a, Un, b, Us, dt, s);
+}
+static hipError_t el_load_vector(dfdg_ctx* ctx, const double* fq, double* F, hipStream_t s) {
+  if (ctx->dim == 3) return launch_load_vector3(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, F, s);
+  return launch_load_vector(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, F, s);
+}
+static hipError_t el_diagnostics(dfdg_ctx* ctx, const double* U, double* part, double* res, hipStream_t s) {
+  if (ctx->dim == 3) return launch_diagnostics3(ctx->K, ctx->g, ctx->tb, U, part, res, s);
+  return launch_diagnostics(ctx->K, ctx->g, ctx->tb, U, part, res, s);
+}
+
 // ---------------------------------------------------------------------------------------
 // mesh
 // ---------------------------------------------------------------------------------------
 extern "C" int dfdg_mesh_create(int dim, int n_elem, const double* xyz, const double* period, dfdg_mesh** out) {
   if (!out) { g_mesh_err = "out is NULL"; return DFDG_E_INVALID_ARG; }
   *out = nullptr;
-  if (dim == 3) { g_mesh_err = "three-dimensional meshes are not implemented"; return DFDG_E_UNSUPPORTED; }
-  if (dim != 2) { g_mesh_err = "dim must be 2"; return DFDG_E_INVALID_ARG; }
+  if (dim != 2 && dim != 3) { g_mesh_err = "dim must be 2 or 3"; return DFDG_E_INVALID_ARG; }
   if (n_elem < 2 || !xyz || !period) { g_mesh_err = "need >= 2 elements, coordinates and a period"; return DFDG_E_INVALID_ARG; }
-  if (!(period[0] > 0) || !(period[1] > 0)) { g_mesh_err = "period must be positive"; return DFDG_E_INVALID_ARG; }
-  for (long i = 0; i < 6L * n_elem; ++i)
+  for (int d = 0; d < dim; ++d)
+    if (!(period[d] > 0) || !std::isfinite(period[d])) { g_mesh_err = "period must be positive"; return DFDG_E_INVALID_ARG; }
+  const long nco = (long)dim * (dim + 1) * n_elem;
+  for (long i = 0; i < nco; ++i)
     if (!std::isfinite(xyz[i])) { g_mesh_err = "non-finite vertex coordinate"; return DFDG_E_INVALID_ARG; }
   auto* m = new dfdg_mesh;
   std::string err;
-  int rc = build_mesh(n_elem, xyz, period, m->m, err);
+  int rc = dim == 3 ? build_mesh3(n_elem, xyz, period, m->m, err) : build_mesh(n_elem, xyz, period, m->m, err);
   if (rc) { g_mesh_err = err; delete m; return DFDG_E_MESH; }
   *out = m;
   return DFDG_OK;
@@ -185,23 +210,34 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
   auto* ctx = new dfdg_ctx;
   ctx->prm = *prm;
   ctx->stream = (hipStream_t)stream;
+  ctx->dim = mesh->m.dim;
   std::string e;
   if (check_params(prm, e)) {
     g_mesh_err = e;
     delete ctx;
     return DFDG_E_INVALID_ARG;
   }
-  if (build_setup(mesh->m, prm->k, prm->alpha, ctx->hs, e)) {
+  if (ctx->dim == 3) {  // what the tetrahedral path implements
+    const char* why = prm->k > kMaxK3 ? "tetrahedral meshes: k must be 1 or 2"
+                      : prm->precision != DFDG_FP64 ? "tetrahedral meshes: FP64 only" : nullptr;
+    if (why) {
+      g_mesh_err = why;
+      delete ctx;
+      return DFDG_E_UNSUPPORTED;
+    }
+  }
+  if ((ctx->dim == 3 ? build_setup3(mesh->m, prm->k, prm->alpha, ctx->hs, e)
+                     : build_setup(mesh->m, prm->k, prm->alpha, ctx->hs, e))) {
     g_mesh_err = e;
     delete ctx;
     return DFDG_E_MESH;
   }
   if (prm->precond == DFDG_AMG) {
     const HostSetup& h = ctx->hs;
-    const int NFk = nF(prm->k);
+    const int NFk = ctx->dim == 3 ? nF3(prm->k) : nF(prm->k);
     std::vector<double> z((size_t)h.E * NFk, 0.0);
     for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.zdef[F];
-    if (build_amg(h.E, NFk, h.cols, h.vals, z, 0.08, 1000, ctx->H, e)) {
+    if (build_amg(h.E, NFk, (int)(h.cols.size() / h.E), h.cols, h.vals, z, 0.08, 1000, ctx->H, e)) {
       g_mesh_err = e;
       delete ctx;
       return DFDG_E_MESH;
@@ -213,11 +249,11 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     }
   }
   ctx->K = prm->k;
-  ctx->P = nP(ctx->K);
-  ctx->NF = nF(ctx->K);
+  ctx->P = ctx->dim == 3 ? nP3(ctx->K) : nP(ctx->K);
+  ctx->NF = ctx->dim == 3 ? nF3(ctx->K) : nF(ctx->K);
   ctx->T = mesh->m.T;
   ctx->E = mesh->m.E;
-  ctx->nU = 2L * ctx->P * ctx->T;
+  ctx->nU = (long)ctx->dim * ctx->P * ctx->T;
   ctx->nL = (long)ctx->NF * ctx->E;
   *out = ctx;
   return DFDG_OK;
@@ -239,11 +275,12 @@ extern "C" int dfdg_ctx_sizes(const dfdg_ctx* ctx, dfdg_sizes* s) {
   s->k = ctx->K;
   s->P = ctx->P;
   s->n_f = ctx->NF;
-  s->n_p = nPp(ctx->K);
+  s->n_p = ctx->dim == 3 ? nPp3(ctx->K) : nPp(ctx->K);
   s->n_broken = ctx->nU;
   s->n_lambda = ctx->nL;
-  s->n_bdm = (long)ctx->E * ctx->NF + (long)ctx->T * (2 * ctx->P - 3 * ctx->NF);
+  s->n_bdm = (long)ctx->E * ctx->NF + (long)ctx->T * (ctx->dim * ctx->P - (ctx->dim + 1) * ctx->NF);
   s->nq_proj = ctx->hs.tabs.nqp;
+  s->dim = ctx->dim;
   return DFDG_OK;
 }
 
@@ -260,6 +297,8 @@ struct Carver {
   }
 };
 
+static int d3slots(const dfdg_ctx* ctx) { return ctx->dim == 3 ? kSlots3 : kSlots; }
+
 static void carve(dfdg_ctx* ctx, char* base) {
   Carver c{base};
   const HostSetup& h = ctx->hs;
@@ -269,17 +308,19 @@ static void carve(dfdg_ctx* ctx, char* base) {
   g.T = (int)T;
   g.E = (int)E;
   g.fgrid = facet_grid_size((int)E, ctx->prm.facet_blocks);
-  g.Jinv = c.take<double>(4 * T);
+  const long dm = ctx->dim, nfac = dm + 1;
+  g.Jinv = c.take<double>(dm * dm * T);
   g.detJ = c.take<double>(T);
   g.isq = c.take<double>(T);
-  g.nbr = c.take<int>(3 * T);
-  g.code = c.take<int>(3 * T);
-  g.efacet = c.take<int>(3 * T);
-  g.nx = c.take<double>(3 * T);
-  g.ny = c.take<double>(3 * T);
-  g.flen = c.take<double>(3 * T);
-  g.sig = c.take<double>(3 * T);
-  g.sF = c.take<double>(3 * T);
+  g.nbr = c.take<int>(nfac * T);
+  g.code = c.take<int>(nfac * T);
+  g.efacet = c.take<int>(nfac * T);
+  g.nx = c.take<double>(nfac * T);
+  g.ny = c.take<double>(nfac * T);
+  g.nz = dm == 3 ? c.take<double>(nfac * T) : nullptr;
+  g.flen = c.take<double>(nfac * T);
+  g.sig = c.take<double>(nfac * T);
+  g.sF = c.take<double>(nfac * T);
   g.G = c.take<double>(h.G.size());
   g.qL = c.take<int>(E);
   g.qR = c.take<int>(E);
@@ -295,7 +336,10 @@ static void carve(dfdg_ctx* ctx, char* base) {
   d.Wp = c.take<double>(tb.pw.size());
   d.Dh = c.take<double>(tb.Dh.size());
   d.Ch = c.take<double>(tb.Ch.size());
+  d.fpidx = tb.fpidx.empty() ? nullptr : c.take<int>(tb.fpidx.size());
+  d.Qf = tb.Qf.empty() ? nullptr : c.take<double>(tb.Qf.size());
   DevBsr& A = ctx->A;
+  A.ns = d3slots(ctx);
   A.cols = c.take<int>(h.cols.size());
   A.vals = c.take<double>(h.vals.size());
   A.dinv = c.take<double>(h.dinv.size());
@@ -307,10 +351,10 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.dinv32 = f32 ? c.take<float>(h.dinv.size()) : nullptr;
   A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
   const bool f16 = ctx->prm.precond == DFDG_AMG && (mixed || ctx->prm.mg_fp32) && ctx->prm.mg_fine_fp16;
-  A.vals16 = f16 ? c.take<uint32_t>((size_t)nPairs(NF) * E) : nullptr;
+  A.vals16 = f16 ? c.take<uint32_t>((size_t)nPairs(NF, A.ns) * E) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
-  ctx->q = c.take<double>(3 * NF * T);
+  ctx->q = c.take<double>(nfac * NF * T);
   ctx->gv = c.take<double>(nL);
   ctx->lamw = c.take<double>(nL);
   ctx->lamx = c.take<double>(nL);
@@ -472,6 +516,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<int*>(ctx->g.efacet), h.efacet, s));
   HIPC(up(const_cast<double*>(ctx->g.nx), h.nx, s));
   HIPC(up(const_cast<double*>(ctx->g.ny), h.ny, s));
+  if (ctx->g.nz) HIPC(up(const_cast<double*>(ctx->g.nz), h.nz, s));
   HIPC(up(const_cast<double*>(ctx->g.flen), h.flen, s));
   HIPC(up(const_cast<double*>(ctx->g.sig), h.sig, s));
   HIPC(up(const_cast<double*>(ctx->g.sF), h.sF, s));
@@ -490,6 +535,8 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<double*>(ctx->tb.Wp), tb.pw, s));
   HIPC(up(const_cast<double*>(ctx->tb.Dh), tb.Dh, s));
   HIPC(up(const_cast<double*>(ctx->tb.Ch), tb.Ch, s));
+  if (ctx->tb.fpidx) HIPC(up(const_cast<int*>(ctx->tb.fpidx), tb.fpidx, s));
+  if (ctx->tb.Qf) HIPC(up(const_cast<double*>(ctx->tb.Qf), tb.Qf, s));
   HIPC(up(const_cast<int*>(ctx->A.cols), h.cols, s));
   HIPC(up(const_cast<double*>(ctx->A.vals), h.vals, s));
   HIPC(up(const_cast<double*>(ctx->A.dinv), h.dinv, s));
@@ -507,7 +554,8 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
     for (double v : h.vals) smax = std::max(smax, std::fabs(v));
     if (!(smax > 0)) smax = 1;
     ctx->A.scale16 = (float)smax;
-    HIPC(launch_pack_half_pairs(ctx->NF, ctx->E, ctx->A.vals, 1.0 / smax, const_cast<uint32_t*>(ctx->A.vals16), s));
+    HIPC(launch_pack_half_pairs(ctx->NF, ctx->A.ns, ctx->E, ctx->A.vals, 1.0 / smax, const_cast<uint32_t*>(ctx->A.vals16),
+                                s));
   }
   {
     const bool mixed = ctx->A.vals32 != nullptr;  // FP32 copies were carved
@@ -834,12 +882,12 @@ static int mass_solve_impl(dfdg_ctx* ctx, const void* F, bool f32, double* U, do
                            dfdg_solve_info* info, int mode, double ca, const double* Un, double cb,
                            const double* Us, double dt) {
   hipStream_t s = ctx->stream;
-  HIPC(launch_cond_rhs(ctx->K, f32, ctx->g, ctx->tb, F, ctx->q, s));
+  HIPC(el_cond_rhs(ctx, f32, F, s));
   if (cold) HIPC(launch_fill(ctx->nL, 0.0, lam, s));
   dfdg_solve_info inf{};
   int rc = solve_facets(ctx, lam, &inf);
   if (rc) return rc;
-  HIPC(launch_recover(ctx->K, f32, ctx->g, ctx->tb, F, lam, U, mode, ca, Un, cb, Us, dt, s));
+  HIPC(el_recover(ctx, f32, F, lam, U, mode, ca, Un, cb, Us, dt, s));
   if (info) *info = inf;
   return DFDG_OK;
 }
@@ -857,7 +905,7 @@ extern "C" int dfdg_proj_rule(const dfdg_ctx* ctx, double* pts, double* w) {
 extern "C" int dfdg_load_vector(dfdg_ctx* ctx, const double* fq, double* F) {
   NEED_BOUND(ctx);
   if (!fq || !F) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  HIPC(launch_load_vector(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, F, ctx->stream));
+  HIPC(el_load_vector(ctx, fq, F, ctx->stream));
   return DFDG_OK;
 }
 
@@ -877,7 +925,7 @@ extern "C" int dfdg_hdiv_mass_solve(dfdg_ctx* ctx, const double* F, double* U, d
 extern "C" int dfdg_project(dfdg_ctx* ctx, const double* fq, double* U, dfdg_solve_info* info) {
   NEED_BOUND(ctx);
   if (!fq || !U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  HIPC(launch_load_vector(ctx->K, ctx->hs.tabs.nqp, ctx->g, ctx->tb, fq, ctx->Lbuf, ctx->stream));
+  HIPC(el_load_vector(ctx, fq, ctx->Lbuf, ctx->stream));
   dfdg_solve_info inf{};
   int rc = mass_solve_impl(ctx, ctx->Lbuf, false, U, ctx->lamw, true, &inf, 0, 0, nullptr, 0, nullptr, 0);
   if (rc) return rc;
@@ -889,7 +937,7 @@ extern "C" int dfdg_project(dfdg_ctx* ctx, const double* fq, double* U, dfdg_sol
 extern "C" int dfdg_dg_residual(dfdg_ctx* ctx, const double* U, double* L) {
   NEED_BOUND(ctx);
   if (!U || !L) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  HIPC(launch_residual(ctx->K, false, ctx->g, ctx->tb, U, L, ctx->prm.nu, ctx->stream));
+  HIPC(el_residual(ctx, false, U, L, ctx->stream));
   return DFDG_OK;
 }
 
@@ -986,7 +1034,7 @@ static int rk_stage(dfdg_ctx* ctx, int s, const double* Us, const double* Un, do
                     double* out, dfdg_solve_info* inf) {
   const bool mixed = ctx->prm.precision == DFDG_MIXED;
   void* L = mixed ? (void*)ctx->L32 : (void*)ctx->Lbuf;
-  HIPC(launch_residual(ctx->K, mixed, ctx->g, ctx->tb, Us, L, ctx->prm.nu, ctx->stream));
+  HIPC(el_residual(ctx, mixed, Us, L, ctx->stream));
   bool cold;
   int rc = stage_guess(ctx, s, &cold);
   if (rc) return rc;
@@ -1044,6 +1092,7 @@ extern "C" int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U, double dt, double*
 extern "C" int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U, const double* Lbar, double* Ubar) {
   NEED_BOUND(ctx);
   if (!U || !Lbar || !Ubar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
   HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, U, Lbar, Ubar, ctx->prm.nu, ctx->stream));
   return DFDG_OK;
 }
@@ -1109,6 +1158,7 @@ extern "C" int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un, double* Ybar, 
   if (!Un || !Ybar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
   double* U1 = ctx->Ustages[0];
   double* U2 = ctx->Ustages[1];
   dfdg_solve_info fw[2]{}, si[3]{};
@@ -1127,6 +1177,7 @@ extern "C" int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un, const d
   if (Ybar == Un || Ybar == U1 || Ybar == U2) return fail(ctx, DFDG_E_INVALID_ARG, "Ybar must not alias a state");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
+  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
   dfdg_solve_info si[3]{};
   int rc = rk3_vjp_core(ctx, Un, U1, U2, Ybar, dt, si);
   if (rc) return rc;
@@ -1139,7 +1190,7 @@ extern "C" int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un, const d
 extern "C" int dfdg_diagnostics(dfdg_ctx* ctx, const double* U, dfdg_diag* out) {
   NEED_BOUND(ctx);
   if (!U || !out) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  HIPC(launch_diagnostics(ctx->K, ctx->g, ctx->tb, U, ctx->partials, ctx->diagres, ctx->stream));
+  HIPC(el_diagnostics(ctx, U, ctx->partials, ctx->diagres, ctx->stream));
   double res[4];
   HIPC(hipMemcpyAsync(ctx->pinned, ctx->diagres, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPC(hipStreamSynchronize(ctx->stream));
@@ -1167,7 +1218,7 @@ extern "C" int dfdg_diagnostics_noalloc(dfdg_ctx* ctx, const double* U, dfdg_dia
                                              std::to_string(dev) + ") than at set-up");
   double* res = part + 4 * kNoAllocDiagBlocks;
   // every partial and result is written before it is read: nothing to clear
-  HIPC(launch_diagnostics(ctx->K, ctx->g, ctx->tb, U, part, res, ctx->stream));
+  HIPC(el_diagnostics(ctx, U, part, res, ctx->stream));
   double r[4];
   HIPC(hipMemcpyAsync(ctx->pinned, res, 4 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   HIPC(hipStreamSynchronize(ctx->stream));
@@ -1185,9 +1236,13 @@ extern "C" int dfdg_eval(dfdg_ctx* ctx, const double* U, int npts, const double*
   if (npts < 1 || npts > kMaxEvalPts) return fail(ctx, DFDG_E_INVALID_ARG, "npts must be in 1..1024");
   const int P = ctx->P;
   std::vector<double> tab((size_t)npts * P);
-  for (int p = 0; p < npts; ++p) dubiner(ctx->K, ref[2 * p], ref[2 * p + 1], &tab[(size_t)p * P], nullptr);
+  for (int p = 0; p < npts; ++p) {
+    if (ctx->dim == 3) dubiner3(ctx->K, ref[3 * p], ref[3 * p + 1], ref[3 * p + 2], &tab[(size_t)p * P], nullptr);
+    else dubiner(ctx->K, ref[2 * p], ref[2 * p + 1], &tab[(size_t)p * P], nullptr);
+  }
   HIPC(hipMemcpyAsync(ctx->evaltab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-  HIPC(launch_eval(ctx->K, npts, ctx->g, ctx->evaltab, U, out, ctx->stream));
+  if (ctx->dim == 3) HIPC(launch_eval3(ctx->K, npts, ctx->g, ctx->evaltab, U, out, ctx->stream));
+  else HIPC(launch_eval(ctx->K, npts, ctx->g, ctx->evaltab, U, out, ctx->stream));
   HIPC(hipStreamSynchronize(ctx->stream));  // tab is a host temporary
   return DFDG_OK;
 }
@@ -1199,7 +1254,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   if (which == 4 && ctx->prm.precond != DFDG_AMG) return fail(ctx, DFDG_E_INVALID_ARG, "V-cycle needs an AMG context");
   if (which < 0 || which > 4) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
   hipStream_t s = ctx->stream;
-  const long T = ctx->T, E = ctx->E, NF = ctx->NF, P = ctx->P;
+  const long T = ctx->T, E = ctx->E, NF = ctx->NF, P = ctx->P, NS = ctx->A.ns;
   // a running PCG state whose stopping test never fires, and finite partials
   const PcgBufs& pb = ctx->pbt;
   PcgScalars st{};
@@ -1214,7 +1269,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
       case 0: return launch_pcg_spmv(NF, ctx->g, ctx->A, ctx->z, ctx->p[0], ctx->p[1], ctx->Sp, pb, 2, s);
       case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI ? 1 : 0, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
                                        ctx->gv, ctx->r, ctx->z, pb, 1, s);  // writes rz[1], reads rz[0]
-      case 2: return launch_residual(ctx->K, false, ctx->g, ctx->tb, ctx->Ustage, ctx->Lbuf, ctx->prm.nu, s);
+      case 2: return el_residual(ctx, false, ctx->Ustage, ctx->Lbuf, s);
       case 4:
         if (ctx->prm.mg_fp32) return launch_vcycle<float, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
         return launch_vcycle<double, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
@@ -1252,10 +1307,14 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   if (bytes) {
     double b = 0;
     switch (which) {
-      case 0: b = E * (kSlots * NF * NF * 8.0 + kSlots * 4.0 + 4.0 * NF * 8.0); break;       // S, cols, z, p_old, p_new, Sp
+      case 0: b = E * (NS * NF * NF * 8.0 + NS * 4.0 + 4.0 * NF * 8.0); break;  // S, cols, z, p_old, p_new, Sp
       case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
-      case 2:  // U in, L out, Jinv + 1/sqrt(detJ); per facet nbr, code, nx, ny, |F| (and sigma if nu != 0)
-        b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (2 * 4.0 + (ctx->prm.nu != 0.0 ? 4 : 3) * 8.0));
+      case 2:  // U (own + neighbours) in, L out, Jinv + 1/sqrt(detJ); per facet nbr, code, normal,
+               // |F| (and sigma if nu != 0)
+        if (ctx->dim == 3)
+          b = T * (2.0 * 3 * P * 8.0 + 10 * 8.0 + 4 * (2 * 4.0 + (ctx->prm.nu != 0.0 ? 5 : 4) * 8.0));
+        else
+          b = T * (2.0 * 2 * P * 8.0 + 5 * 8.0 + 3 * (2 * 4.0 + (ctx->prm.nu != 0.0 ? 4 : 3) * 8.0));
         break;
       case 4: {
         // finest level: 4 BSR sweeps + 17 vector passes; transfers and coarse levels:
@@ -1263,8 +1322,8 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
         // and vectors in the cycle's precision (8 or 4 bytes; finest-level S in 2 bytes
         // when it is stored in FP16).
         const double vb = ctx->prm.mg_fp32 ? 4.0 : 8.0;
-        const double sv = ctx->A.vals16 ? 4.0 * nPairs(NF) / (kSlots * NF * NF) : vb;
-        const double sbytes = E * (kSlots * NF * NF * sv + kSlots * 4.0);
+        const double sv = ctx->A.vals16 ? 4.0 * nPairs(NF, NS) / (NS * NF * NF) : vb;
+        const double sbytes = E * (NS * NF * NF * sv + NS * 4.0);
         b = 4 * sbytes + 17.0 * E * NF * vb;
         const AmgHierarchy& H = ctx->H;
         for (size_t l = 0; l + 1 < H.lv.size(); ++l) {
@@ -1280,7 +1339,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
         b += H.n_coarse * (double)H.n_coarse * vb;
         break;
       }
-      default: b = E * (kSlots * NF * NF * 4.0 + kSlots * 4.0 + 4.0 * NF * 4.0); break;
+      default: b = E * (NS * NF * NF * 4.0 + NS * 4.0 + 4.0 * NF * 4.0); break;
     }
     *bytes = b;
   }
@@ -1305,6 +1364,29 @@ extern "C" int dfdg_debug_residual_rule(int k, int* npts, double* pts, double* w
   if (k < 1 || k > kMaxK || !npts) return DFDG_E_INVALID_ARG;
   std::vector<double> q, qw;
   residual_volume_rule(k, q, qw);
+  *npts = (int)qw.size();
+  if (pts) std::memcpy(pts, q.data(), q.size() * sizeof(double));
+  if (w) std::memcpy(w, qw.data(), qw.size() * sizeof(double));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_basis3(int k, int npts, const double* pts, double* vals, double* grads) {
+  if (k < 1 || k > kMaxK3 || npts < 1 || !pts || !vals) return DFDG_E_INVALID_ARG;
+  const int P = nP3(k);
+  std::vector<double> g(3 * P);
+  for (int p = 0; p < npts; ++p) {
+    dubiner3(k, pts[3 * p], pts[3 * p + 1], pts[3 * p + 2], vals + (size_t)p * P, g.data());
+    if (grads) std::memcpy(grads + (size_t)p * 3 * P, g.data(), 3 * P * sizeof(double));
+  }
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_rule3(int k, int which, int* npts, double* pts, double* w) {
+  if (k < 1 || k > kMaxK3 || !npts || which < 0 || which > 2) return DFDG_E_INVALID_ARG;
+  RefTables t;
+  build_ref_tables3(k, t);
+  const std::vector<double>& q = which == 0 ? t.vq : which == 1 ? t.fs : t.pq;
+  const std::vector<double>& qw = which == 0 ? t.vw : which == 1 ? t.fw : t.pw;
   *npts = (int)qw.size();
   if (pts) std::memcpy(pts, q.data(), q.size() * sizeof(double));
   if (w) std::memcpy(w, qw.data(), qw.size() * sizeof(double));

@@ -31,12 +31,26 @@ __host__ __device__ constexpr int projDeg(int K) { return 2 * K + 4; }
 __host__ __device__ constexpr int nQP(int K) { return triN(projDeg(K)); }
 constexpr int kMaxK = 3;
 constexpr int kSlots = 5;           // BSR blocks per facet row: itself + 2 + 2 neighbours
+// Tetrahedra (d = 3): P = dim P^K(T), NP = dim P^{K-1}(T), NF = dim P^K(F); seven BSR blocks
+// per face row (itself + the 3 other faces of each neighbour).  K = 1, 2.
+__host__ __device__ constexpr int nP3(int K) { return (K + 1) * (K + 2) * (K + 3) / 6; }
+__host__ __device__ constexpr int nPp3(int K) { return K * (K + 1) * (K + 2) / 6; }
+__host__ __device__ constexpr int nF3(int K) { return (K + 1) * (K + 2) / 2; }
+__host__ __device__ constexpr int nGpk3(int K) { return nPp3(K) * (nPp3(K) + 1) / 2; }
+// Gauss-Jacobi collapsed tetrahedron rule exact for degree p: n^3 points, n = (p+2)/2
+__host__ __device__ constexpr int tetN(int p) { return ((p + 2) / 2) * ((p + 2) / 2) * ((p + 2) / 2); }
+__host__ __device__ constexpr int nQV3(int K) { return tetN(3 * K - 1); }       // residual volume rule
+__host__ __device__ constexpr int nQF3(int K) { return K == 1 ? 6 : 12; }      // symmetric face rule
+__host__ __device__ constexpr int nQP3(int K) { return tetN(2 * K + 2); }      // projection rule
+constexpr int kMaxK3 = 2;
+constexpr int kSlots3 = 7;
 // 32-bit words of a facet row of S in FP16, two values per word
-__host__ __device__ constexpr int nPairs(int NF) { return (kSlots * NF * NF + 1) / 2; }
+__host__ __device__ constexpr int nPairs(int NF, int NS) { return (NS * NF * NF + 1) / 2; }
 constexpr int kMaxEvalPts = 1024;
 
 // ---- reference tabulations (host, FP64) ---------------------------------------------
 struct RefTables {
+  int dim = 2;
   int K = 0, P = 0, NP = 0, NF = 0, nqv = 0, nqf = 0, nqp = 0;
   std::vector<double> vq, vw;        // volume rule points [nqv][2], weights (sum 1/2)
   std::vector<double> fs, fw;        // facet rule on [0,1], symmetric
@@ -46,19 +60,37 @@ struct RefTables {
   std::vector<double> Vp;            // projection points [q][i]
   std::vector<double> Dh;            // [a][j][i] = int dpsi_i/dxi_a psi_j, j < NP
   std::vector<double> Ch;            // [f][m][i] = int_0^1 l_m(s) psi_i(xhat_f(s)) ds
+  // tetrahedra: rules in 3 reference coordinates ([n][3]), 4 faces; a face point r seen from
+  // the neighbour through vertex permutation p (0..5) is the neighbour's point fpidx[p][r];
+  // Qf[p][m][n] = <mu_m(face param q), mu_n(own face param)> for the face parameter q that
+  // permutation p maps the own one to (orthogonal change of the face basis)
+  std::vector<int> fpidx;            // [6][nqf]
+  std::vector<double> Qf;            // [6][NF][NF]
 };
 void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w);
 void triangle_rule(int degree, std::vector<double>& pts, std::vector<double>& w);
 // Volume rule of the residual for degree K (nQV(K) points, exact for degree 3K-1).
 void residual_volume_rule(int K, std::vector<double>& pts, std::vector<double>& w);
 void dubiner(int K, double xi, double eta, double* vals, double* grads /*[2][P] or null*/);
+// Jacobi polynomial P_n^{(a,b)}(x) and its derivative (three-term recurrence)
+void jacobi_poly(int n, double a, double b, double x, double* val, double* der);
 double legendre01_orthonormal(int m, double s);
 void build_ref_tables(int K, RefTables& t);
+// tetrahedra
+void dubiner3(int K, double xi, double eta, double zeta, double* vals, double* grads /*[3][P] or null*/);
+void tet_rule(int degree, std::vector<double>& pts, std::vector<double>& w);
+void sym_face_rule(int degree, std::vector<double>& pts, std::vector<double>& w);
+void build_ref_tables3(int K, RefTables& t);
+bool spd_inverse(int n, double* A);
 
 // ---- device-side views --------------------------------------------------------------
 struct DevGeo {
   int T, E;
   int fgrid;            // blocks of the facet-row kernels (grid-stride loops over the rows)
+  // triangles unless stated; tetrahedra: Jinv [9][T] at (3r+j)*T + t, per-face arrays
+  // [4][T], code bits 0-1 neighbour's local face, 2-4 the permutation p (0..5) carrying
+  // this element's face vertices to the neighbour's, bit 5 this element is the R side;
+  // qL/qR offsets into a [4][NF][T] array; nz the normal's third component
   const double* Jinv;   // [4][T], Jinv[r][j] = dxi_r/dx_j at (2r+j)*T + t
   const double* detJ;   // [T]  (> 0)
   const double* isq;    // [T]  1 / sqrt(detJ)
@@ -68,6 +100,7 @@ struct DevGeo {
   const int* efacet;    // [3][T] facet id
   const double* nx;     // [3][T] outward normal
   const double* ny;
+  const double* nz;     // tetrahedra: [4][T]
   const double* flen;   // [3][T] |F|
   const double* sig;    // [3][T] alpha k^2 / h_F
   const double* sF;     // [3][T] sqrt(|F| / detJ)
@@ -81,8 +114,10 @@ struct DevTabs {
   const double* Vf; const double* Gf; const double* Wf;
   const double* Vp; const double* Wp;
   const double* Dh; const double* Ch;
+  const int* fpidx; const double* Qf;  // tetrahedra: face point and face basis permutations
 };
 struct DevBsr {
+  int ns;               // blocks per row: 5 (triangles) or 7 (tetrahedra)
   const int* cols;      // [5][E]
   const double* vals;   // [5][NF][NF][E]
   const double* dinv;   // [E][NF]       point Jacobi
@@ -90,7 +125,7 @@ struct DevBsr {
   const float* vals32;  // [5][NF][NF][E] (MIXED)
   const float* dinv32;  // [E][NF]
   const float* binv32;  // [E][NF][NF]
-  // FP16 copy of S / scale16 for the finest V-cycle level, or null: [nPairs(NF)][E] words;
+  // FP16 copy of S / scale16 for the finest V-cycle level, or null: [nPairs(NF, ns)][E] words;
   // word j of row F holds values 2j (low half) and 2j+1 (high half) of the row's
   // [5][NF][NF] sequence (the last high half is zero when 5 NF^2 is odd)
   const uint32_t* vals16;

@@ -95,6 +95,23 @@ hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, con
 // Start/stop events for the dispatch packet of the next SpMV or residual launch (kernel
 // execution only; nullptr restores plain launches).
 void set_dispatch_events(hipEvent_t start, hipEvent_t stop);
+void get_dispatch_events(hipEvent_t* start, hipEvent_t* stop);
+// Sum of the per-block diagnostics partials into res[4] (one block).
+hipError_t launch_diag_finish(int nb, const double* partials, double* res, hipStream_t s);
+
+// ---- tetrahedra (dfdg_kernels3.hip): the element steps; the facet kernels above are shared
+// (DevBsr::ns = 7).  FP64 only, K = 1, 2.
+hipError_t launch_residual3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* L, double nu,
+                            hipStream_t s);
+hipError_t launch_cond_rhs3(int K, const DevGeo& g, const DevTabs& tb, const double* F, double* q, hipStream_t s);
+hipError_t launch_recover3(int K, const DevGeo& g, const DevTabs& tb, const double* F, const double* lam, double* out,
+                           int mode, double a, const double* Un, double b, const double* Us, double dt, hipStream_t s);
+hipError_t launch_load_vector3(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
+                               hipStream_t s);
+hipError_t launch_eval3(int K, int npts, const DevGeo& g, const double* tab, const double* U, double* out,
+                        hipStream_t s);
+hipError_t launch_diagnostics3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* partials,
+                               double* res, hipStream_t s);
 // x_{.,0} -= (zdef, x_{.,0}) zdef (part: scratch for one partial per facet block).
 hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipStream_t s);
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
@@ -157,7 +174,8 @@ hipError_t launch_pack_rows4(int n, const int* col, const double* val, double in
 // out[i] = FP16 bits of x[i] * scale (round to nearest even).
 hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s);
 // S (FP64, [5][NF][NF][E]) times scale in FP16, two values per word (DevBsr::vals16)
-hipError_t launch_pack_half_pairs(int NF, int E, const double* vals, double scale, uint32_t* out, hipStream_t s);
+hipError_t launch_pack_half_pairs(int NF, int ns, int E, const double* vals, double scale, uint32_t* out,
+                                  hipStream_t s);
 
 // Allocation-free diagnostics: a static device scratch of kNoAllocDiagBlocks partials (one per
 // element block of the diagnostics kernel, i.e. meshes of up to 2097152 elements) plus the

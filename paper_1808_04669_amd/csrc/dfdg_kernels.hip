@@ -16,28 +16,15 @@
 #include <cmath>
 #include <mutex>
 
+#include "dfdg_device.h"
 #include "dfdg_internal.h"
 #include "dfdg_kernels.h"
 
 namespace dfdg {
 
-static constexpr int kBlk = 256;     // facet kernels
-static constexpr int kEBlk = 128;    // element kernels
-
 // ---------------------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------------------
-
-__device__ inline double wave_sum(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-  return x;
-}
-__device__ inline double wave_max(double x) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) x = fmax(x, __shfl_xor(x, off, 64));
-  return x;
-}
 
 // Reductions without atomics or fences: a kernel writes one partial per block; the next
 // kernel on the stream (after the kernel boundary has made them visible) sums all partials
@@ -176,15 +163,6 @@ __device__ inline void load_Jinv(const DevGeo& g, int t, R (&Ji)[2][2]) {
   Ji[0][1] = (R)g.Jinv[(size_t)g.T + t];
   Ji[1][0] = (R)g.Jinv[2 * (size_t)g.T + t];
   Ji[1][1] = (R)g.Jinv[3 * (size_t)g.T + t];
-}
-
-// Block index remapped so that each of the 8 XCDs (which take the launched blocks round
-// robin, each with its own L2) works on one contiguous range of rows: neighbouring
-// elements and facets, whose data a block gathers, then mostly sit in the same L2.
-// A bijection of [0, gridDim.x) for every grid size.
-__device__ inline int xcd_block() {
-  const int G = gridDim.x, b = blockIdx.x, x = b & 7;
-  return x * (G >> 3) + min(x, G & 7) + (b >> 3);
 }
 
 // Stage the reference tables of the residual into LDS.
@@ -710,14 +688,15 @@ __device__ inline void precond(const DevBsr& A, int F, const V (&r)[NF], V (&z)[
   }
 }
 
-// y = S x for row F (x given by a functor returning the NF-vector of a column facet).
-template <int NF, typename V, typename M, typename Getter>
+// y = S x for row F (x given by a functor returning the NF-vector of a column facet); NS
+// blocks per row.
+template <int NF, int NS, typename V, typename M, typename Getter>
 __device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
   const M* vals = (sizeof(M) == 8) ? (const M*)A.vals : (const M*)A.vals32;
 #pragma unroll
   for (int a = 0; a < NF; ++a) y[a] = 0;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
+  for (int s = 0; s < NS; ++s) {
     const int c = A.cols[(size_t)s * E + F];
     V xc[NF];
     get(c, xc);
@@ -731,13 +710,13 @@ __device__ inline void spmv_row(const DevBsr& A, int E, int F, Getter get, V (&y
 // The FP16 copy of row F of S (two values per word, see DevBsr::vals16): all the row's
 // words are loaded at once, and value j of the row's [5][NF][NF] sequence is half j & 1
 // of word j / 2.
-template <int NF>
+template <int NF, int NS>
 struct HalfRow {
-  uint32_t w[nPairs(NF)];
+  uint32_t w[nPairs(NF, NS)];
   __device__ inline void load(const DevBsr& A, int E, int F) {
     const uint32_t* __restrict__ p = A.vals16;
 #pragma unroll
-    for (int j = 0; j < nPairs(NF); ++j) w[j] = p[(size_t)j * E + F];
+    for (int j = 0; j < nPairs(NF, NS); ++j) w[j] = p[(size_t)j * E + F];
   }
   __device__ inline float at(int j) const {
     const uint32_t v = w[j >> 1];
@@ -747,16 +726,16 @@ struct HalfRow {
 
 // As spmv_row in FP32 for the multigrid smoothing on the finest level: S is read from its
 // FP16 copy (scaled by scale16) when there is one, else from the FP32 copy.
-template <int NF, typename V, typename Getter>
+template <int NF, int NS, typename V, typename Getter>
 __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      HalfRow<NF> m;
+      HalfRow<NF, NS> m;
       m.load(A, E, F);
 #pragma unroll
       for (int a = 0; a < NF; ++a) y[a] = 0;
 #pragma unroll
-      for (int s = 0; s < kSlots; ++s) {
+      for (int s = 0; s < NS; ++s) {
         const int c = A.cols[(size_t)s * E + F];
         V xc[NF];
         get(c, xc);
@@ -770,19 +749,19 @@ __device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V 
       return;
     }
   }
-  spmv_row<NF, V, V>(A, E, F, get, y);
+  spmv_row<NF, NS, V, V>(A, E, F, get, y);
 }
 
 // Two products of one row at once, y1 = S u and y2 = S w (get(c, u_c, w_c) gives the
 // column facet's two vectors), with the multigrid's copy of S as in spmv_row_mg.
-template <int NF, typename V, typename Getter>
+template <int NF, int NS, typename V, typename Getter>
 __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V (&y1)[NF], V (&y2)[NF]) {
   // value(j) gives entry j of the row's [5][NF][NF] sequence
   auto rowloop = [&](auto value, V scale) {
 #pragma unroll
     for (int a = 0; a < NF; ++a) y1[a] = y2[a] = 0;
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
+    for (int s = 0; s < NS; ++s) {
       const int c = A.cols[(size_t)s * E + F];
       V uc[NF], wc[NF];
       get(c, uc, wc);
@@ -803,7 +782,7 @@ __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V
   };
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      HalfRow<NF> m;
+      HalfRow<NF, NS> m;
       m.load(A, E, F);
       rowloop([&](int j) { return (V)m.at(j); }, (V)A.scale16);
       return;
@@ -814,7 +793,7 @@ __device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V
 }
 
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
-template <int NF, bool BJ>
+template <int NF, int NS, bool BJ>
 __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
                                                    double* __restrict__ x, double* __restrict__ r,
                                                    double* __restrict__ z, double* __restrict__ p_old,
@@ -834,7 +813,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
       continue;
     }
     double Sx[NF];
-    spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
+    spmv_row<NF, NS, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
 #pragma unroll
       for (int b = 0; b < NF; ++b) xc[b] = x[(size_t)c * NF + b];
     }, Sx);
@@ -863,7 +842,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
 // replayed from a graph).  From the partials of the previous update (rz_{it-1}, rr_{it-1})
 // and of the one before (rz_{it-2}): stopping test, beta; then p_new = z + beta p_old,
 // Sp = S p_new and partials (p_new, Sp).
-template <int NF, typename V, typename M>
+template <int NF, int NS, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* __restrict__ z,
                                                    const V* __restrict__ p_old, V* __restrict__ p_new,
                                                    V* __restrict__ Sp, PcgScalars* sc,
@@ -883,7 +862,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
 #pragma unroll
     for (int a = 0; a < NF; ++a) sz[a] = sp[a] = 0;
 #pragma unroll
-    for (int s5 = 0; s5 < kSlots; ++s5) {
+    for (int s5 = 0; s5 < NS; ++s5) {
       const int c = A.cols[(size_t)s5 * E + F];
       V zc[NF], pc[NF];
 #pragma unroll
@@ -1026,7 +1005,7 @@ __global__ __launch_bounds__(kBlk) void k_ir_residual(DevGeo g, DevBsr A, const 
   double v[1] = {0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     double Sx[NF];
-    spmv_row<NF, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
+    spmv_row<NF, kSlots, double, double>(A, E, F, [&](int c, double (&xc)[NF]) {
 #pragma unroll
       for (int b = 0; b < NF; ++b) xc[b] = lam[(size_t)c * NF + b];
     }, Sx);
@@ -1083,7 +1062,7 @@ __device__ inline const V* bsr_dinv(const DevBsr& A) { return (sizeof(V) == 8) ?
 // V: arithmetic and storage type of the cycle; VB: type of the PCG vectors b (in) and z
 // (out), so that an FP32 cycle can precondition an FP64 PCG.  Every kernel of the cycle
 // returns at once when the PCG has already stopped (iterations replayed past the end).
-template <int NF, typename V, typename VB>
+template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ b, V* __restrict__ x2,
                                                   CheB cb, const PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
@@ -1092,7 +1071,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * (V)b[(size_t)c * NF + q] * ith;
     }, y);
@@ -1106,14 +1085,14 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
   }
 }
 
-template <int NF, typename V, typename VB>
+template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x, V* __restrict__ r, const PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
     }, y);
@@ -1123,7 +1102,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB
   }
 }
 
-template <int NF, typename V, typename VB>
+template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x3, V* __restrict__ x4, V* __restrict__ d,
                                                     CheB cb, const PcgScalars* sc) {
@@ -1133,7 +1112,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
   const int E = g.E;
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x3[(size_t)c * NF + q];
     }, y);
@@ -1152,7 +1131,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
 // Last post-smoothing step; z is the preconditioned PCG residual b.  Writes the (b, z)
 // partial of this block into rz[2*block] (the (r,r) slot rz[2*block+1] is left alone),
 // and block 0 applies the iteration's stopping test to the (r,r) partials.
-template <int NF, typename V, typename VB>
+template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB* __restrict__ b,
                                                     const V* __restrict__ x4, const V* __restrict__ d,
                                                     VB* __restrict__ z, CheB cb, double* __restrict__ rz,
@@ -1170,7 +1149,7 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
   double v[1] = {0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     V y[NF];
-    spmv_row_mg<NF, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x4[(size_t)c * NF + q];
     }, y);
@@ -1357,7 +1336,7 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
 // double-buffered: r_new = r_old - alpha Sp for the own rows, and the neighbours' new
 // residual, needed by S x1, is formed on the fly from r_old and Sp.  Also x += alpha p,
 // the (r,r) partial, and the iteration counter.
-template <int NF, typename V, typename VB>
+template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ p,
                                                           const VB* __restrict__ Sp, VB* __restrict__ x,
                                                           const VB* __restrict__ r_old, VB* __restrict__ r_new,
@@ -1377,7 +1356,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   auto row = [&](int F, V (&su)[NF], V (&sw)[NF]) {
-    spmv_row_mg2<NF, V>(A, E, F, [&](int c, V (&uc)[NF], V (&wc)[NF]) {
+    spmv_row_mg2<NF, NS, V>(A, E, F, [&](int c, V (&uc)[NF], V (&wc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
         const size_t o = (size_t)c * NF + q;
@@ -1679,7 +1658,6 @@ __global__ __launch_bounds__(kBlk) void k_extrapolate_pick(long n, int omax, His
 // ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
-static inline unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 // Events attached to the dispatch packet of the next single-kernel launch of the SpMV or
 // the residual (kernel-only start and end times, for the measurement entry point).
@@ -1687,6 +1665,10 @@ static thread_local hipEvent_t t_ev0 = nullptr, t_ev1 = nullptr;
 void set_dispatch_events(hipEvent_t start, hipEvent_t stop) {
   t_ev0 = start;
   t_ev1 = stop;
+}
+void get_dispatch_events(hipEvent_t* start, hipEvent_t* stop) {
+  *start = t_ev0;
+  *stop = t_ev1;
 }
 #define DFDG_LAUNCH_TIMED(KER, GRID, BLK, SH, S, ...)                                   \
   do {                                                                                  \
@@ -1759,7 +1741,38 @@ hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb
     case 2: { constexpr int NN = 2; __VA_ARGS__; } break;         \
     case 3: { constexpr int NN = 3; __VA_ARGS__; } break;         \
     case 4: { constexpr int NN = 4; __VA_ARGS__; } break;         \
+    case 6: { constexpr int NN = 6; __VA_ARGS__; } break;         \
     default: return hipErrorInvalidValue;                         \
+  }
+
+// (n_f, blocks per row) in a function returning void: triangles (2|3|4, 5), tetrahedra (3|6, 7)
+#define DFDG_DISPATCH_NFS_VOID(NF, NS, ...)                                            \
+  if ((NS) == kSlots3) {                                                               \
+    if ((NF) == 3) { constexpr int NN = 3, SS = kSlots3; __VA_ARGS__; }                \
+    else { constexpr int NN = 6, SS = kSlots3; __VA_ARGS__; }                          \
+  } else {                                                                             \
+    switch (NF) {                                                                      \
+      case 2: { constexpr int NN = 2, SS = kSlots; __VA_ARGS__; } break;               \
+      case 3: { constexpr int NN = 3, SS = kSlots; __VA_ARGS__; } break;               \
+      default: { constexpr int NN = 4, SS = kSlots; __VA_ARGS__; } break;              \
+    }                                                                                  \
+  }
+
+// (n_f, blocks per row): triangles (2|3|4, 5), tetrahedra (3|6, 7)
+#define DFDG_DISPATCH_NFS(NF, NS, ...)                                                 \
+  if ((NS) == kSlots3) {                                                               \
+    switch (NF) {                                                                      \
+      case 3: { constexpr int NN = 3, SS = kSlots3; __VA_ARGS__; } break;              \
+      case 6: { constexpr int NN = 6, SS = kSlots3; __VA_ARGS__; } break;              \
+      default: return hipErrorInvalidValue;                                            \
+    }                                                                                  \
+  } else {                                                                             \
+    switch (NF) {                                                                      \
+      case 2: { constexpr int NN = 2, SS = kSlots; __VA_ARGS__; } break;               \
+      case 3: { constexpr int NN = 3, SS = kSlots; __VA_ARGS__; } break;               \
+      case 4: { constexpr int NN = 4, SS = kSlots; __VA_ARGS__; } break;               \
+      default: return hipErrorInvalidValue;                                            \
+    }                                                                                  \
   }
 
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,
@@ -1782,9 +1795,9 @@ hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipS
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
                            double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
   const int G = g.fgrid;
-  DFDG_DISPATCH_NF(NF, {
-    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
-    else hipLaunchKernelGGL((k_pcg_init<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
+  DFDG_DISPATCH_NFS(NF, A.ns, {
+    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, SS, true>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
+    else hipLaunchKernelGGL((k_pcg_init<NN, SS, false>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
   });
   return hipGetLastError();
 }
@@ -1795,8 +1808,9 @@ static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z,
   const int G = g.fgrid;
   const double* prev = pb.rz[(it - 1) & 1];
   const double* prev2 = pb.rz[it & 1];
-  DFDG_DISPATCH_NF(NF, DFDG_LAUNCH_TIMED((k_pcg_spmv<NN, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old, p_new, Sp,
-                                         pb.sc, prev, prev2, pb.pq));
+  if (sizeof(V) == 4 && A.ns != kSlots) return hipErrorInvalidValue;  // FP32 copies: triangles only
+  DFDG_DISPATCH_NFS(NF, A.ns, DFDG_LAUNCH_TIMED((k_pcg_spmv<NN, SS, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old,
+                                                p_new, Sp, pb.sc, prev, prev2, pb.pq));
   return hipGetLastError();
 }
 
@@ -1886,8 +1900,8 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
   const int G = g.fgrid;
   const int L = mg.nlev;
   const MgVec<V>& v0 = mg_vec<V>(mg, 0);
-  DFDG_DISPATCH_NF_VOID(NF, hipLaunchKernelGGL((k_mg0_resid<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b,
-                                               (const V*)v0.x, v0.r, sc));
+  DFDG_DISPATCH_NFS_VOID(NF, A.ns, hipLaunchKernelGGL((k_mg0_resid<NN, SS, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A,
+                                                       b, (const V*)v0.x, v0.r, sc));
   csr_apply<V>(mg.R[0], (const V*)v0.r, (const V*)nullptr, mg_vec<V>(mg, 1).b, 0, sc, s);
   for (int l = 1; l < L - 1; ++l) {
     const MgVec<V>& v = mg_vec<V>(mg, l);
@@ -1913,11 +1927,11 @@ static void vcycle_body(int NF, const DevGeo& g, const DevBsr& A, const MgDev& m
                                          mg.cheb[l], sc));
   }
   csr_apply<V>(mg.P[0], (const V*)mg_vec<V>(mg, 1).z, (const V*)v0.x, v0.x, 1, sc, s);
-  DFDG_DISPATCH_NF_VOID(NF, {
-    hipLaunchKernelGGL((k_mg0_post1<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d,
+  DFDG_DISPATCH_NFS_VOID(NF, A.ns, {
+    hipLaunchKernelGGL((k_mg0_post1<NN, SS, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.x, v0.y, v0.d,
                        mg.cheb[0], sc);
-    hipLaunchKernelGGL((k_mg0_post2<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y, (const V*)v0.d, z,
-                       mg.cheb[0], rz, sc);
+    hipLaunchKernelGGL((k_mg0_post2<NN, SS, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, (const V*)v0.y,
+                       (const V*)v0.d, z, mg.cheb[0], rz, sc);
   });
 }
 
@@ -1933,8 +1947,8 @@ hipError_t launch_vcycle(int NF, const DevGeo& g, const DevBsr& A, const MgDev& 
     hipLaunchKernelGGL((k_partial_dot<VB>), dim3(G), dim3(kBlk), 0, s, (long)g.E * NF, b, (const VB*)z, rz, sc);
     return hipGetLastError();
   }
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b, v0.x,
-                                          mg.cheb[0], sc));
+  DFDG_DISPATCH_NFS(NF, A.ns, hipLaunchKernelGGL((k_mg0_pre<NN, SS, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A, b,
+                                                 v0.x, mg.cheb[0], sc));
   vcycle_body<V, VB>(NF, g, A, mg, b, z, rz, sc, s);
   return hipGetLastError();
 }
@@ -1950,7 +1964,7 @@ hipError_t launch_pcg_iteration_mg(int NF, const DevGeo& g, const DevBsr& A, con
   if (e != hipSuccess) return e;
   const double* prev = pb.rz[(it - 1) & 1];
   double* out = pb.rz[it & 1];
-  DFDG_DISPATCH_NF(NF, hipLaunchKernelGGL((k_pcg_upd_mg0_pre<NN, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A,
+  DFDG_DISPATCH_NFS(NF, A.ns, hipLaunchKernelGGL((k_pcg_upd_mg0_pre<NN, SS, V, VB>), dim3(G), dim3(kBlk), 0, s, g, A,
                                           (const VB*)p_new, (const VB*)Sp, x, r_old, r_new, mg_vec<V>(mg, 0).x,
                                           mg.cheb[0], pb.sc, prev, (const double*)pb.pq, out));
   vcycle_body<V, VB>(NF, g, A, mg, (const VB*)r_new, z, out, pb.sc, s);
@@ -1985,6 +1999,11 @@ hipError_t launch_load_vector(int K, int nqp, const DevGeo& g, const DevTabs& tb
 hipError_t launch_eval(int K, int npts, const DevGeo& g, const double* tab, const double* U, double* out,
                        hipStream_t s) {
   DFDG_DISPATCH_K(K, hipLaunchKernelGGL((k_eval<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, npts, tab, U, out));
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_finish(int nb, const double* partials, double* res, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_finish, dim3(1), dim3(kBlk), 0, s, nb, partials, res);
   return hipGetLastError();
 }
 
@@ -2047,10 +2066,11 @@ hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, 
   return hipGetLastError();
 }
 
-hipError_t launch_pack_half_pairs(int NF, int E, const double* vals, double scale, uint32_t* out, hipStream_t s) {
-  const long n = (long)nPairs(NF) * E;
+hipError_t launch_pack_half_pairs(int NF, int ns, int E, const double* vals, double scale, uint32_t* out,
+                                  hipStream_t s) {
+  const long n = (long)nPairs(NF, ns) * E;
   const long nb = std::min<long>(nblk(n, 256), 65536);
-  hipLaunchKernelGGL(k_pack_half_pairs, dim3((unsigned)nb), dim3(256), 0, s, kSlots * NF * NF, E, vals, scale, out, n);
+  hipLaunchKernelGGL(k_pack_half_pairs, dim3((unsigned)nb), dim3(256), 0, s, ns * NF * NF, E, vals, scale, out, n);
   return hipGetLastError();
 }
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s) {

@@ -1,0 +1,562 @@
+// HIP kernels of the element steps on tetrahedra (d = 3) for gfx950.
+//
+// One thread per element; velocity-like vectors are SoA [3][P][T] (consecutive lanes,
+// consecutive elements).  The reference tables of the residual (basis values and gradients
+// at the volume and face points, the face-point permutations) are staged in LDS.  A face
+// integral is evaluated by both neighbours at the same points of the fully symmetric face
+// rule: the neighbour's point is found through the permutation of the face's vertices, so
+// both sides carry out the same operations in mirrored order (no atomics).  The facet
+// kernels (PCG) are shared with the triangle path (7 BSR blocks per face row).
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dfdg_device.h"
+#include "dfdg_internal.h"
+#include "dfdg_kernels.h"
+
+namespace dfdg {
+
+template <int K>
+struct ResTabs3 {
+  static constexpr int P = nP3(K), NQV = nQV3(K), NQF = nQF3(K);
+  double Vv[NQV][P], Gv[NQV][3][P], Wv[NQV];
+  double Vf[4][NQF][P], Gf[4][NQF][3][P], Wf[NQF];
+  int pidx[6][NQF];
+};
+template <int K>
+__device__ inline void stage_tabs3(ResTabs3<K>& s, const DevTabs& tb) {
+  constexpr int P = nP3(K), NQV = nQV3(K), NQF = nQF3(K);
+  double* d = &s.Vv[0][0];
+  for (int i = threadIdx.x; i < NQV * P; i += blockDim.x) d[i] = tb.Vv[i];
+  d = &s.Gv[0][0][0];
+  for (int i = threadIdx.x; i < NQV * 3 * P; i += blockDim.x) d[i] = tb.Gv[i];
+  for (int i = threadIdx.x; i < NQV; i += blockDim.x) s.Wv[i] = tb.Wv[i];
+  d = &s.Vf[0][0][0];
+  for (int i = threadIdx.x; i < 4 * NQF * P; i += blockDim.x) d[i] = tb.Vf[i];
+  d = &s.Gf[0][0][0][0];
+  for (int i = threadIdx.x; i < 4 * NQF * 3 * P; i += blockDim.x) d[i] = tb.Gf[i];
+  for (int i = threadIdx.x; i < NQF; i += blockDim.x) s.Wf[i] = tb.Wf[i];
+  int* p = &s.pidx[0][0];
+  for (int i = threadIdx.x; i < 6 * NQF; i += blockDim.x) p[i] = tb.fpidx[i];
+  __syncthreads();
+}
+
+__device__ inline void load_Jinv3(const DevGeo& g, int t, double (&Ji)[3][3]) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Ji[r][j] = g.Jinv[(size_t)(3 * r + j) * g.T + t];
+}
+
+// ---------------------------------------------------------------------------------------
+// a3: DG residual L(u)(v) = -C_h(u;u,v) - B_h(u,v) on the broken basis (eqs. (adv),
+// (viscous)).  Per own face (outward normal n, neighbour values at the same points),
+// un = {u}.n, u_up the outflow-side value, du = u_own - u_nbr; the face contributes to the
+// own test function v
+//     -(un u_up - nu {grad u} n + nu sigma du) . v  +  (nu/2) (du (x) n) : grad v.
+// The volume term is int (u (x) u - nu grad u) : grad v.  VISC = false: nu = 0.
+// ---------------------------------------------------------------------------------------
+template <int K, bool VISC>
+__global__ __launch_bounds__(kEBlk) void k_residual3(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                     double* __restrict__ Lout, double nu) {
+  constexpr int P = nP3(K), NQV = nQV3(K), NQF = nQF3(K);
+  __shared__ ResTabs3<K> s;
+  stage_tabs3<K>(s, tb);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double u[3][P], acc[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      u[c][i] = U[(size_t)(c * P + i) * T + t];
+      acc[c][i] = 0;
+    }
+  double Ji[3][3];
+  load_Jinv3(g, t, Ji);
+  const double isq = g.isq[t];
+
+  // volume: with a = sum_i u_i psihat_i (u = isq a at the point) and gr its reference
+  // gradient, the integrand times det J is [isq a (x) a - nu gr Jinv] Jinv^T : grad_ref v
+  for (int q = 0; q < NQV; ++q) {
+    double uq[3], gr[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double a = 0, b0 = 0, b1 = 0, b2 = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        a += u[c][i] * s.Vv[q][i];
+        if constexpr (VISC) {
+          b0 += u[c][i] * s.Gv[q][0][i];
+          b1 += u[c][i] * s.Gv[q][1][i];
+          b2 += u[c][i] * s.Gv[q][2][i];
+        }
+      }
+      uq[c] = a;
+      gr[c][0] = b0;
+      gr[c][1] = b1;
+      gr[c][2] = b2;
+    }
+    const double w = s.Wv[q];
+    double wG[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double fl[3];
+      const double ua = isq * uq[c];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        fl[j] = ua * uq[j];
+        if constexpr (VISC) fl[j] -= nu * (gr[c][0] * Ji[0][j] + gr[c][1] * Ji[1][j] + gr[c][2] * Ji[2][j]);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) wG[c][a] = w * (fl[0] * Ji[a][0] + fl[1] * Ji[a][1] + fl[2] * Ji[a][2]);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        acc[c][i] = fma(wG[c][2], s.Gv[q][2][i], fma(wG[c][1], s.Gv[q][1][i], fma(wG[c][0], s.Gv[q][0][i], acc[c][i])));
+  }
+
+  // faces
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int nb = g.nbr[idx];
+    const int code = g.code[idx];
+    const int fn = code & 3, pid = (code >> 2) & 7;
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+    double v[3][P];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) v[c][i] = U[(size_t)(c * P + i) * T + nb];
+    const double isqn = g.isq[nb];
+    const double li = g.flen[idx] * isq;
+    double Jn[3][3] = {}, nJ[3] = {}, sig = 0;
+    if constexpr (VISC) {
+      sig = g.sig[idx];
+      load_Jinv3(g, nb, Jn);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) nJ[a] = n[0] * Ji[a][0] + n[1] * Ji[a][1] + n[2] * Ji[a][2];
+    }
+    for (int r = 0; r < NQF; ++r) {
+      const int rn = s.pidx[pid][r];
+      double uo[3], un[3], go[3][3] = {}, gn[3][3] = {};
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double a = 0, an = 0, b[3] = {0, 0, 0}, bn[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          a += u[c][i] * s.Vf[f][r][i];
+          an += v[c][i] * s.Vf[fn][rn][i];
+          if constexpr (VISC) {
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+              b[e] += u[c][i] * s.Gf[f][r][e][i];
+              bn[e] += v[c][i] * s.Gf[fn][rn][e][i];
+            }
+          }
+        }
+        uo[c] = a * isq;
+        un[c] = an * isqn;
+        if constexpr (VISC) {
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            go[c][j] = isq * (b[0] * Ji[0][j] + b[1] * Ji[1][j] + b[2] * Ji[2][j]);
+            gn[c][j] = isqn * (bn[0] * Jn[0][j] + bn[1] * Jn[1][j] + bn[2] * Jn[2][j]);
+          }
+        }
+      }
+      const double unrm = 0.5 * ((uo[0] + un[0]) * n[0] + (uo[1] + un[1]) * n[1] + (uo[2] + un[2]) * n[2]);
+      const bool own_up = unrm >= 0.0;
+      double Qv[3], du[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double up = own_up ? uo[c] : un[c];
+        du[c] = uo[c] - un[c];
+        Qv[c] = unrm * up;
+        if constexpr (VISC) {
+          const double avgn = 0.5 * ((go[c][0] + gn[c][0]) * n[0] + (go[c][1] + gn[c][1]) * n[1] + (go[c][2] + gn[c][2]) * n[2]);
+          Qv[c] = Qv[c] - nu * avgn + nu * sig * du[c];
+        }
+      }
+      const double w = s.Wf[r] * li;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double wq = -(w * Qv[c]);
+        if constexpr (VISC) {
+          const double wh = w * (0.5 * nu * du[c]);
+          const double h0 = wh * nJ[0], h1 = wh * nJ[1], h2 = wh * nJ[2];
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            acc[c][i] = fma(wq, s.Vf[f][r][i],
+                            fma(h2, s.Gf[f][r][2][i], fma(h1, s.Gf[f][r][1][i], fma(h0, s.Gf[f][r][0][i], acc[c][i]))));
+        } else {
+#pragma unroll
+          for (int i = 0; i < P; ++i) acc[c][i] = fma(wq, s.Vf[f][r][i], acc[c][i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) Lout[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+// ---------------------------------------------------------------------------------------
+// a4 / a6: element condensation and recovery (eq. (FE3), orthonormal basis: M_T = I)
+// ---------------------------------------------------------------------------------------
+// y <- W_T y = y - D_T^T (D_T D_T^T)^{-1} D_T y, D_T = sum_a Jinv[a][c] Dh[a]
+template <int K>
+__device__ inline void apply_W3(double (&y)[3][nP3(K)], const double (&Ji)[3][3], const double* __restrict__ G, int T,
+                                int t, const double* __restrict__ Dh) {
+  constexpr int P = nP3(K), NP = nPp3(K);
+  double d[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    double s = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double a[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) a[e] += Dh[(e * NP + j) * P + i] * y[c][i];
+      s += Ji[0][c] * a[0] + Ji[1][c] * a[1] + Ji[2][c] * a[2];
+    }
+    d[j] = s;
+  }
+  double e[NP];
+#pragma unroll
+  for (int j = 0; j < NP; ++j) e[j] = 0;
+#pragma unroll
+  for (int j = 0, p = 0; j < NP; ++j)
+#pragma unroll
+    for (int l = 0; l <= j; ++l, ++p) {
+      const double gv = G[(size_t)p * T + t];
+      e[j] += gv * d[l];
+      if (l != j) e[l] += gv * d[j];
+    }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < NP; ++j)
+        s += (Ji[0][c] * Dh[(0 * NP + j) * P + i] + Ji[1][c] * Dh[(1 * NP + j) * P + i] + Ji[2][c] * Dh[(2 * NP + j) * P + i]) * e[j];
+      y[c][i] -= s;
+    }
+}
+
+// q[4][NF][T] = C_T W_T F_T per element and local face, in the L side's face basis (the
+// R side maps its own face moments through the orthogonal matrix Qf of the permutation).
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_cond_rhs3(DevGeo g, DevTabs tb, const double* __restrict__ F,
+                                                     double* __restrict__ q) {
+  constexpr int P = nP3(K), NF = nF3(K);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double y[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[c][i] = F[(size_t)(c * P + i) * T + t];
+  double Ji[3][3];
+  load_Jinv3(g, t, Ji);
+  apply_W3<K>(y, Ji, g.G, T, t, tb.Dh);
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const double sc = g.sF[idx];
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+    const int code = g.code[idx];
+    double m[NF];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) s += tb.Ch[(f * NF + mm) * P + i] * (n[0] * y[0][i] + n[1] * y[1][i] + n[2] * y[2][i]);
+      m[mm] = sc * s;
+    }
+    if ((code >> 5) & 1) {
+      const double* Q = tb.Qf + ((code >> 2) & 7) * NF * NF;
+      double o[NF];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        double s = 0;
+#pragma unroll
+        for (int b = 0; b < NF; ++b) s += Q[a * NF + b] * m[b];
+        o[a] = s;
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a) m[a] = o[a];
+    }
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) q[(size_t)(f * NF + mm) * T + t] = m[mm];
+  }
+}
+
+// u = W_T (F_T - C_T^T lambda_T); out = u (mode 0) or a Un + b (Us + dt u) (mode 1).
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_recover3(DevGeo g, DevTabs tb, const double* __restrict__ F,
+                                                    const double* __restrict__ lam, double* __restrict__ out, int mode,
+                                                    double ca, const double* __restrict__ Un, double cb,
+                                                    const double* __restrict__ Us, double dt) {
+  constexpr int P = nP3(K), NF = nF3(K);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double y[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[c][i] = F[(size_t)(c * P + i) * T + t];
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int Fc = g.efacet[idx];
+    const int code = g.code[idx];
+    double lm[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) lm[a] = lam[(size_t)Fc * NF + a];
+    if ((code >> 5) & 1) {  // own face coefficients: Qf^T times the L side's
+      const double* Q = tb.Qf + ((code >> 2) & 7) * NF * NF;
+      double o[NF];
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < NF; ++a) s += Q[a * NF + b] * lm[a];
+        o[b] = s;
+      }
+#pragma unroll
+      for (int b = 0; b < NF; ++b) lm[b] = o[b];
+    }
+    const double sc = g.sF[idx];
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) s += lm[mm] * tb.Ch[(f * NF + mm) * P + i];
+      s *= sc;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c][i] -= n[c] * s;
+    }
+  }
+  double Ji[3][3];
+  load_Jinv3(g, t, Ji);
+  apply_W3<K>(y, Ji, g.G, T, t, tb.Dh);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const size_t o = (size_t)(c * P + i) * T + t;
+      if (mode == 0) out[o] = y[c][i];
+      else out[o] = ca * Un[o] + cb * (Us[o] + dt * y[c][i]);
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// a2 / a10: load vector, evaluation and diagnostics
+// ---------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_load_vector3(DevGeo g, DevTabs tb, int nqp, const double* __restrict__ fq,
+                                                        double* __restrict__ F) {
+  constexpr int P = nP3(K);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double sq = sqrt(g.detJ[t]);
+  double acc[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) acc[c][i] = 0;
+  for (int q = 0; q < nqp; ++q) {
+    const double w = tb.Wp[q] * sq;
+    double f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[c] = fq[(size_t)(c * nqp + q) * T + t] * w;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const double v = tb.Vp[q * P + i];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[c][i] += f[c] * v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) F[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_eval3(DevGeo g, int npts, const double* __restrict__ tab,
+                                                 const double* __restrict__ U, double* __restrict__ out) {
+  constexpr int P = nP3(K);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double isq = g.isq[t];
+  double u[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[c][i] = U[(size_t)(c * P + i) * T + t];
+  for (int p = 0; p < npts; ++p)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) s += u[c][i] * tab[p * P + i];
+      out[(size_t)(c * npts + p) * T + t] = s * isq;
+    }
+}
+
+// Per block: sum 0.5 U^2, sum |curl u|^2 (volume rule), max |div u| (volume points),
+// max |[[u.n]]| (face points, faces this element owns as L side).
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_diag3(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                 double* __restrict__ partials) {
+  constexpr int P = nP3(K), NQV = nQV3(K), NQF = nQF3(K);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  double en = 0, ens = 0, dmax = 0, jmax = 0;
+  if (t < T) {
+    double u[3][P];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        u[c][i] = U[(size_t)(c * P + i) * T + t];
+        en += 0.5 * u[c][i] * u[c][i];
+      }
+    double Ji[3][3];
+    load_Jinv3(g, t, Ji);
+    const double det = g.detJ[t], isq = g.isq[t];
+    for (int q = 0; q < NQV; ++q) {
+      double gr[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double b[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+          for (int e = 0; e < 3; ++e) b[e] += u[c][i] * tb.Gv[(q * 3 + e) * P + i];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gr[c][j] = isq * (b[0] * Ji[0][j] + b[1] * Ji[1][j] + b[2] * Ji[2][j]);
+      }
+      const double w0 = gr[2][1] - gr[1][2], w1 = gr[0][2] - gr[2][0], w2 = gr[1][0] - gr[0][1];
+      ens += tb.Wv[q] * det * (w0 * w0 + w1 * w1 + w2 * w2);
+      dmax = fmax(dmax, fabs(gr[0][0] + gr[1][1] + gr[2][2]));
+    }
+    for (int f = 0; f < 4; ++f) {
+      const size_t idx = (size_t)f * T + t;
+      const int code = g.code[idx];
+      if ((code >> 5) & 1) continue;  // the L side measures the face
+      const int nb = g.nbr[idx], fn = code & 3, pid = (code >> 2) & 7;
+      const double n0 = g.nx[idx], n1 = g.ny[idx], n2 = g.nz[idx], isqn = g.isq[nb];
+      for (int r = 0; r < NQF; ++r) {
+        const int rn = tb.fpidx[pid * NQF + r];
+        double jo = 0, jn = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const double vo = tb.Vf[(f * NQF + r) * P + i], vn = tb.Vf[(fn * NQF + rn) * P + i];
+          jo += (u[0][i] * n0 + u[1][i] * n1 + u[2][i] * n2) * vo;
+          jn += (U[(size_t)i * T + nb] * n0 + U[(size_t)(P + i) * T + nb] * n1 + U[(size_t)(2 * P + i) * T + nb] * n2) * vn;
+        }
+        jmax = fmax(jmax, fabs(jo * isq - jn * isqn));
+      }
+    }
+  }
+  __shared__ double sh[4][kEBlk / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  en = wave_sum(en);
+  ens = wave_sum(ens);
+  dmax = wave_max(dmax);
+  jmax = wave_max(jmax);
+  if (lane == 0) { sh[0][wid] = en; sh[1][wid] = ens; sh[2][wid] = dmax; sh[3][wid] = jmax; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0, c = 0, d = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      a += sh[0][w]; b += sh[1][w]; c = fmax(c, sh[2][w]); d = fmax(d, sh[3][w]);
+    }
+    partials[4 * blockIdx.x + 0] = a;
+    partials[4 * blockIdx.x + 1] = b;
+    partials[4 * blockIdx.x + 2] = c;
+    partials[4 * blockIdx.x + 3] = d;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+#define DFDG_DISPATCH_K3(K, ...)                                  \
+  switch (K) {                                                    \
+    case 1: { constexpr int KK = 1; __VA_ARGS__; } break;         \
+    case 2: { constexpr int KK = 2; __VA_ARGS__; } break;         \
+    default: return hipErrorInvalidValue;                         \
+  }
+
+// A launch that carries the start/stop events set by set_dispatch_events (kernel timing).
+#define DFDG_LAUNCH_TIMED3(KER, GRID, BLK, S, ...)                                       \
+  do {                                                                                  \
+    hipEvent_t e0_, e1_;                                                                \
+    get_dispatch_events(&e0_, &e1_);                                                    \
+    if (e0_) hipExtLaunchKernelGGL(KER, GRID, BLK, 0, S, e0_, e1_, 0, __VA_ARGS__);     \
+    else hipLaunchKernelGGL(KER, GRID, BLK, 0, S, __VA_ARGS__);                         \
+  } while (0)
+
+hipError_t launch_residual3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* L, double nu,
+                            hipStream_t s) {
+  const dim3 grid(nblk(g.T, kEBlk)), blk(kEBlk);
+  DFDG_DISPATCH_K3(K, {
+    if (nu != 0.0) DFDG_LAUNCH_TIMED3((k_residual3<KK, true>), grid, blk, s, g, tb, U, L, nu);
+    else DFDG_LAUNCH_TIMED3((k_residual3<KK, false>), grid, blk, s, g, tb, U, L, nu);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_cond_rhs3(int K, const DevGeo& g, const DevTabs& tb, const double* F, double* q, hipStream_t s) {
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_cond_rhs3<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, F, q));
+  return hipGetLastError();
+}
+
+hipError_t launch_recover3(int K, const DevGeo& g, const DevTabs& tb, const double* F, const double* lam, double* out,
+                           int mode, double a, const double* Un, double b, const double* Us, double dt, hipStream_t s) {
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_recover3<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, F, lam,
+                                         out, mode, a, Un, b, Us, dt));
+  return hipGetLastError();
+}
+
+hipError_t launch_load_vector3(int K, int nqp, const DevGeo& g, const DevTabs& tb, const double* fq, double* F,
+                               hipStream_t s) {
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_load_vector3<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, nqp,
+                                         fq, F));
+  return hipGetLastError();
+}
+
+hipError_t launch_eval3(int K, int npts, const DevGeo& g, const double* tab, const double* U, double* out,
+                        hipStream_t s) {
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_eval3<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, npts, tab, U,
+                                         out));
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* partials,
+                               double* res, hipStream_t s) {
+  const unsigned nb = nblk(g.T, kEBlk);
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_diag3<KK>), dim3(nb), dim3(kEBlk), 0, s, g, tb, U, partials));
+  return launch_diag_finish((int)nb, partials, res, s);
+}
+
+}  // namespace dfdg

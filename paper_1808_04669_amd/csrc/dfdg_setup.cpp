@@ -117,7 +117,7 @@ void residual_volume_rule(int K, std::vector<double>& pts, std::vector<double>& 
 // R_q(eta) = Jacobi_q^{(2p+1, 0)}(2 eta - 1).  Ordered by total degree d = p + q, then q:
 // the first dim P^j functions span P^j.
 
-static void jacobi(int n, double a, double b, double x, double* val, double* der) {
+void jacobi_poly(int n, double a, double b, double x, double* val, double* der) {
   // P_n^{(a,b)}(x) and its derivative by the three-term recurrence.
   auto eval = [](int n, double a, double b, double x) {
     if (n == 0) return 1.0;
@@ -154,7 +154,7 @@ void dubiner(int K, double xi, double eta, double* vals, double* grads) {
     for (int q = 0; q <= d; ++q, ++idx) {
       const int p = d - q;
       double R, Rd;
-      jacobi(q, 2 * p + 1, 0, 2 * eta - 1, &R, &Rd);
+      jacobi_poly(q, 2 * p + 1, 0, 2 * eta - 1, &R, &Rd);
       const double c = std::sqrt((2.0 * p + 1) * (2.0 * p + 2.0 * q + 2));
       vals[idx] = c * Q[p] * R;
       if (grads) {
@@ -374,7 +374,7 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
 // ---------------------------------------------------------------------------------------
 
 // Cholesky inverse of a small SPD matrix (row-major n x n) in place; false if not SPD.
-static bool spd_inverse(int n, double* A) {
+bool spd_inverse(int n, double* A) {
   std::vector<double> L(n * n, 0.0), Li(n * n, 0.0);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j <= i; ++j) {

@@ -7,6 +7,7 @@ is no fallback path.
 """
 import ctypes
 import os
+import time
 
 import numpy as np
 import torch
@@ -40,7 +41,8 @@ class Params(ctypes.Structure):
 class Sizes(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("E", ctypes.c_int32), ("k", ctypes.c_int32), ("P", ctypes.c_int32),
                 ("n_f", ctypes.c_int32), ("n_p", ctypes.c_int32), ("n_broken", ctypes.c_int64),
-                ("n_lambda", ctypes.c_int64), ("n_bdm", ctypes.c_int64), ("nq_proj", ctypes.c_int32)]
+                ("n_lambda", ctypes.c_int64), ("n_bdm", ctypes.c_int64), ("nq_proj", ctypes.c_int32),
+                ("dim", ctypes.c_int32)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -101,6 +103,8 @@ _SIGS = {
     "dfdg_debug_basis": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_residual_rule": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_facet_matrix": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_debug_basis3": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
+    "dfdg_debug_rule3": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_multigrid": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P, _P, _P]),
 }
 EXPORTED = tuple(_SIGS)
@@ -126,15 +130,35 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def rule3(k, which):
+    """dfdg_debug_rule3: (points, weights) of the tetrahedral path's volume (which = 0),
+    face (1) or projection (2) rule."""
+    lib = load_library()
+    n = ctypes.c_int()
+    rc = lib.dfdg_debug_rule3(int(k), int(which), ctypes.byref(n), None, None)
+    if rc != DFDG_OK:
+        raise DfdgError(rc, "dfdg_debug_rule3")
+    d = 2 if which == 1 else 3
+    pts = np.empty((n.value, d))
+    w = np.empty(n.value)
+    lib.dfdg_debug_rule3(int(k), int(which), ctypes.byref(n), pts.ctypes.data_as(_P), w.ctypes.data_as(_P))
+    return pts, w
+
+
 class Mesh:
-    """A periodic triangle mesh (host object of the library)."""
+    """A periodic simplex mesh (host object of the library): xyz[T, 3, 2] triangles or
+    xyz[T, 4, 3] tetrahedra."""
 
     def __init__(self, xyz, period):
         lib = load_library()
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         per = np.ascontiguousarray(period, dtype=np.float64)
+        self.dim = xyz.shape[2]
+        if xyz.ndim != 3 or xyz.shape[1] != self.dim + 1 or per.shape != (self.dim,):
+            raise ValueError("xyz must be [T, 3, 2] or [T, 4, 3] and period [dim]")
         h = ctypes.c_void_p()
-        rc = lib.dfdg_mesh_create(2, xyz.shape[0], xyz.ctypes.data_as(_P), per.ctypes.data_as(_P), ctypes.byref(h))
+        rc = lib.dfdg_mesh_create(self.dim, xyz.shape[0], xyz.ctypes.data_as(_P), per.ctypes.data_as(_P),
+                                  ctypes.byref(h))
         if rc != DFDG_OK:
             raise DfdgError(rc, lib.dfdg_mesh_last_error().decode())
         self._h = h
@@ -158,7 +182,7 @@ class Solver:
     """One discretisation context on one GPU: mesh + parameters + bound workspace.
 
     Vectors are torch float64 CUDA tensors of length n_broken (velocity-like,
-    layout [2][P][T]) or n_lambda (facet multipliers, [E][n_f]).
+    layout [d][P][T]) or n_lambda (facet multipliers, [E][n_f]).
     """
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
@@ -167,7 +191,9 @@ class Solver:
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
+        t0 = time.perf_counter()
         self.mesh = Mesh(xyz, period)
+        t1 = time.perf_counter()
         p = Params()
         lib.dfdg_params_default(ctypes.byref(p))
         p.k, p.nu, p.alpha = int(k), float(nu), float(alpha)
@@ -187,11 +213,12 @@ class Solver:
                                  ctypes.byref(h))
         if rc != DFDG_OK:
             raise DfdgError(rc, lib.dfdg_last_error(None).decode())
+        t2 = time.perf_counter()
         self._h = h
         s = Sizes()
         self._check(lib.dfdg_ctx_sizes(h, ctypes.byref(s)))
         self.sizes = s
-        self.T, self.E, self.k, self.P = s.T, s.E, s.k, s.P
+        self.T, self.E, self.k, self.P, self.dim = s.T, s.E, s.k, s.P, s.dim
         self.n_broken, self.n_lambda, self.n_bdm, self.nq_proj = s.n_broken, s.n_lambda, s.n_bdm, s.nq_proj
         nb = ctypes.c_size_t()
         self._check(lib.dfdg_ctx_workspace_bytes(h, ctypes.byref(nb)))
@@ -199,6 +226,11 @@ class Solver:
         base = self.workspace.data_ptr()
         off = (-base) % 256
         self._check(lib.dfdg_ctx_bind_workspace(h, ctypes.c_void_p(base + off), nb.value))
+        t3 = time.perf_counter()
+        # wall-clock seconds of the set-up calls: mesh (facet matching), context (host set-up:
+        # tabulations, geometry, element condensation, facet matrix, multigrid hierarchy),
+        # workspace (allocation, upload, device-side packing)
+        self.setup_seconds = {"mesh": t1 - t0, "context": t2 - t1, "workspace": t3 - t2}
 
     # ---- helpers ------------------------------------------------------------------
     def _check(self, rc):
@@ -216,7 +248,7 @@ class Solver:
         return torch.zeros(n, dtype=torch.float64, device=self.device)
 
     def proj_rule(self):
-        pts = np.empty((self.nq_proj, 2))
+        pts = np.empty((self.nq_proj, self.dim))
         w = np.empty(self.nq_proj)
         self._check(self._lib.dfdg_proj_rule(self._h, pts.ctypes.data_as(_P), w.ctypes.data_as(_P)))
         return pts, w
@@ -228,8 +260,10 @@ class Solver:
         self.stream = stream
 
     def residual_rule(self):
-        """Points [n, 2] and weights [n] of the residual's volume rule (also the points of
+        """Points [n, d] and weights [n] of the residual's volume rule (also the points of
         max |div u| in the diagnostics)."""
+        if self.dim == 3:
+            return rule3(self.k, 0)
         n = ctypes.c_int()
         self._check(self._lib.dfdg_debug_residual_rule(self.k, ctypes.byref(n), None, None))
         pts = np.empty((n.value, 2))
@@ -242,7 +276,7 @@ class Solver:
     def load_vector(self, f_at_q, F=None):
         F = self.new_vector() if F is None else F
         fq = f_at_q.contiguous()
-        self._check(self._lib.dfdg_load_vector(self._h, self._vec(fq, 2 * self.nq_proj * self.T, "f_at_q"),
+        self._check(self._lib.dfdg_load_vector(self._h, self._vec(fq, self.dim * self.nq_proj * self.T, "f_at_q"),
                                                self._vec(F, self.n_broken, "F")))
         return F
 
@@ -250,7 +284,7 @@ class Solver:
         U = self.new_vector() if U is None else U
         info = SolveInfo()
         fq = f_at_q.contiguous()
-        self._check(self._lib.dfdg_project(self._h, self._vec(fq, 2 * self.nq_proj * self.T, "f_at_q"),
+        self._check(self._lib.dfdg_project(self._h, self._vec(fq, self.dim * self.nq_proj * self.T, "f_at_q"),
                                            self._vec(U, self.n_broken, "U"), ctypes.byref(info)))
         return U, info
 
@@ -343,10 +377,22 @@ class Solver:
     def eval(self, U, ref_pts):
         ref = np.ascontiguousarray(ref_pts, dtype=np.float64)
         n = ref.shape[0]
-        out = torch.empty(2 * n * self.T, dtype=torch.float64, device=self.device)
+        if ref.shape != (n, self.dim):
+            raise ValueError(f"ref_pts must be [n, {self.dim}]")
+        out = torch.empty(self.dim * n * self.T, dtype=torch.float64, device=self.device)
         self._check(self._lib.dfdg_eval(self._h, self._vec(U, self.n_broken, "U"), n, ref.ctypes.data_as(_P),
                                         _ptr(out)))
-        return out.view(2, n, self.T)
+        return out.view(self.dim, n, self.T)
+
+    def mg_levels(self):
+        """Rows of the multigrid levels (empty unless precond="amg")."""
+        L = ctypes.c_int()
+        rows = np.zeros(16, dtype=np.int64)
+        nnz = np.zeros(16, dtype=np.int64)
+        rho = np.zeros(16)
+        self._check(self._lib.dfdg_debug_multigrid(self._h, 16, ctypes.byref(L), rows.ctypes.data_as(_P),
+                                                   nnz.ctypes.data_as(_P), rho.ctypes.data_as(_P)))
+        return [int(r) for r in rows[:L.value]]
 
     def time_kernel(self, which, reps=50):
         ms = ctypes.c_float()
@@ -356,8 +402,8 @@ class Solver:
 
     # ---- layout helpers -----------------------------------------------------------------
     def to_tcp(self, U):
-        """View [2, P, T] of a broken vector."""
-        return U.view(2, self.P, self.T)
+        """View [d, P, T] of a broken vector."""
+        return U.view(self.dim, self.P, self.T)
 
     def __del__(self):
         if getattr(self, "_h", None):

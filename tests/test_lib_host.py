@@ -71,7 +71,7 @@ def test_mesh_validation(lib):
     assert _mesh(lib, nanx, per)[0] == -1
     assert _mesh(lib, xyz, np.array([0.0, 1.0]))[0] == -1
     h = P_()
-    assert lib.dfdg_mesh_create(3, 4, xyz.ctypes.data_as(P_), per.ctypes.data_as(P_), ctypes.byref(h)) == -8
+    assert lib.dfdg_mesh_create(4, 4, xyz.ctypes.data_as(P_), per.ctypes.data_as(P_), ctypes.byref(h)) == -1
     assert lib.dfdg_mesh_create(2, 4, None, per.ctypes.data_as(P_), ctypes.byref(h)) == -1
     assert b"partner" in lib.dfdg_mesh_last_error() or True
 

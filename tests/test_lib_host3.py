@@ -1,0 +1,223 @@
+"""CPU tests of the library's host set-up on periodic tetrahedral meshes against the oracle:
+reference basis and rules, face matching, and the condensed facet matrix S (eq. (FE3)),
+plus the host-side rejections of what the tetrahedral path does not implement."""
+import ctypes
+import os
+from math import factorial
+
+import numpy as np
+import pytest
+
+from inputs import periodic_kuhn_cube
+from oracle import Oracle
+from oracle.mesh import OracleMesh
+from oracle.quadrature import poly_basis, symmetric_triangle_rule, tet_rule, triangle_rule
+from oracle.scheme import hybrid_system_dense
+
+lib_mod = pytest.importorskip("paper_1808_04669_amd.dfdg")
+P_ = ctypes.c_void_p
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(lib_mod.LIB_PATH):
+        from paper_1808_04669_amd import build
+        build.build()
+    return lib_mod.load_library()
+
+
+def _mesh(lib, xyz, per):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    per = np.ascontiguousarray(per, dtype=np.float64)
+    h = P_()
+    rc = lib.dfdg_mesh_create(3, xyz.shape[0], xyz.ctypes.data_as(P_), per.ctypes.data_as(P_), ctypes.byref(h))
+    return rc, h
+
+
+def _ctx(lib, mesh, **kw):
+    p = lib_mod.Params()
+    lib.dfdg_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    h = P_()
+    rc = lib.dfdg_ctx_create(mesh, ctypes.byref(p), None, ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_tet_basis_orthonormal_hierarchical(lib, k):
+    pts, w = tet_rule(2 * k + 1)
+    P = (k + 1) * (k + 2) * (k + 3) // 6
+    vals = np.empty((len(w), P))
+    grads = np.empty((len(w), 3, P))
+    assert lib.dfdg_debug_basis3(k, len(w), np.ascontiguousarray(pts).ctypes.data_as(P_), vals.ctypes.data_as(P_),
+                                 grads.ctypes.data_as(P_)) == 0
+    assert np.abs(np.einsum("q,qa,qb->ab", w, vals, vals) - np.eye(P)).max() < 1e-13
+    # hierarchical: the first dim P^{k-1} functions are orthonormal under a degree 2k-2 rule
+    npk = k * (k + 1) * (k + 2) // 6
+    p2, w2 = tet_rule(2 * k - 2)
+    v2 = np.empty((len(w2), P))
+    lib.dfdg_debug_basis3(k, len(w2), np.ascontiguousarray(p2).ctypes.data_as(P_), v2.ctypes.data_as(P_), None)
+    assert np.abs(np.einsum("q,qa,qb->ab", w2, v2[:, :npk], v2[:, :npk]) - np.eye(npk)).max() < 1e-13
+    # gradients against central differences
+    x0 = np.array([[0.2, 0.15, 0.33]])
+    h = 1e-6
+    g0 = np.empty((1, 3, P))
+    v0 = np.empty((1, P))
+    lib.dfdg_debug_basis3(k, 1, x0.ctypes.data_as(P_), v0.ctypes.data_as(P_), g0.ctypes.data_as(P_))
+    for r in range(3):
+        vp, vm = np.empty((1, P)), np.empty((1, P))
+        e = np.zeros((1, 3))
+        e[0, r] = h
+        lib.dfdg_debug_basis3(k, 1, np.ascontiguousarray(x0 + e).ctypes.data_as(P_), vp.ctypes.data_as(P_), None)
+        lib.dfdg_debug_basis3(k, 1, np.ascontiguousarray(x0 - e).ctypes.data_as(P_), vm.ctypes.data_as(P_), None)
+        assert np.abs((vp - vm) / (2 * h) - g0[:, r]).max() < 1e-7
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_tet_rules_exact_and_face_rule_equals_oracle(lib, k):
+    for which, deg in ((0, 3 * k - 1), (2, 2 * k + 2)):
+        pts, w = lib_mod.rule3(k, which)
+        assert abs(w.sum() - 1.0 / 6.0) < 1e-15
+        for p in range(deg + 1):
+            for q in range(deg + 1 - p):
+                for r in range(deg + 1 - p - q):
+                    exact = factorial(p) * factorial(q) * factorial(r) / factorial(p + q + r + 3)
+                    got = np.sum(w * pts[:, 0] ** p * pts[:, 1] ** q * pts[:, 2] ** r)
+                    assert abs(got - exact) < 1e-14 * exact
+    # the face rule: the same fully symmetric rule the oracle solves for on its own
+    fp, fw = lib_mod.rule3(k, 1)
+    op, ow = symmetric_triangle_rule(4 if k == 1 else 6)
+    assert len(fw) == len(ow) and abs(fw.sum() - 1.0) < 1e-15
+    for x, wx in zip(fp, fw):
+        j = np.argmin(np.abs(op - x).sum(axis=1))
+        assert np.abs(op[j] - x).max() < 1e-14 and abs(2 * ow[j] - wx) < 1e-14
+
+
+@pytest.mark.parametrize("N,order", [(2, "random"), (3, "morton")])
+def test_face_matching_agrees_with_oracle(lib, N, order):
+    xyz, per = periodic_kuhn_cube(N, order, seed=N)
+    rc, m = _mesh(lib, xyz, per)
+    assert rc == 0
+    T, E = ctypes.c_int(), ctypes.c_int()
+    lib.dfdg_mesh_counts(m, ctypes.byref(T), ctypes.byref(E))
+    fac = np.empty((E.value, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(m, fac.ctypes.data_as(P_))
+    lib.dfdg_mesh_destroy(m)
+    om = OracleMesh(xyz, per)
+    assert (T.value, E.value) == (om.T, om.E) == (6 * N ** 3, 12 * N ** 3)
+    lib_pairs = {frozenset([(a, b), (c, d)]) for a, b, c, d in fac}
+    orc_pairs = {frozenset([(a, b), (c, d)]) for a, b, c, d in zip(om.fA_elem, om.fA_loc, om.fB_elem, om.fB_loc)}
+    assert lib_pairs == orc_pairs
+    # the first element of a face (the library's L side) is the oracle's A side
+    key = {(a, b): F for F, (a, b) in enumerate(zip(om.fA_elem, om.fA_loc))}
+    assert all((f[0], f[1]) in key for f in fac)
+
+
+def _lib_S(lib, xyz, per, k):
+    rc, m = _mesh(lib, xyz, per)
+    rc, c = _ctx(lib, m, k=k)
+    assert rc == 0, lib.dfdg_last_error(None)
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    E, NF = s.E, s.n_f
+    cols = np.empty((7, E), dtype=np.int32)
+    vals = np.empty((7, NF, NF, E))
+    assert lib.dfdg_debug_facet_matrix(c, cols.ctypes.data_as(P_), vals.ctypes.data_as(P_)) == 0
+    fac = np.empty((E, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(m, fac.ctypes.data_as(P_))
+    lib.dfdg_ctx_destroy(c)
+    lib.dfdg_mesh_destroy(m)
+    S = np.zeros((E * NF, E * NF))
+    for sl in range(7):
+        for F in range(E):
+            S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
+    return S, fac, s
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_facet_matrix_equals_oracle_condensation_3d(lib, k):
+    """The library's 7-slot S equals the static condensation of the oracle's dense
+    hybrid-mixed system onto the multipliers, after the change of face basis: the library's
+    multiplier functions are the triangle's Dubiner polynomials / sqrt(2|F|), the oracle's
+    its orthonormalised monomials, both in the face parameter of the face's first element
+    (a face's vertices in increasing local order)."""
+    xyz, per = periodic_kuhn_cube(2, "random", seed=5 + k)
+    S, fac, s = _lib_S(lib, xyz, per, k)
+    E, NF = s.E, s.n_f
+    orc = Oracle(xyz, per, k)
+    K, nU, nW = hybrid_system_dense(orc)
+    nx = nU + nW
+    So = K[nx:, :nx] @ np.linalg.solve(K[:nx, :nx], K[:nx, nx:])
+    om = orc.mesh
+    key = {(a, b): F for F, (a, b) in enumerate(zip(om.fA_elem, om.fA_loc))}
+    perm = np.array([key[(fac[F, 0], fac[F, 1])] for F in range(E)])
+    # Q[m, j] = int_Fhat mu_m l_j over the reference triangle (area 1/2): library Dubiner
+    # mu_m, oracle l_j; lambda_orc = B lambda_lib with B[j, m] = Q[m, j] / sqrt(2|F|)
+    tp, tw = triangle_rule(2 * k)
+    mu = np.empty((len(tw), NF))
+    lib.dfdg_debug_basis(k, len(tw), np.ascontiguousarray(tp).ctypes.data_as(P_), mu.ctypes.data_as(P_), None)
+    lj, _ = poly_basis(k, tp[:, 0], tp[:, 1])
+    Q = np.einsum("q,qm,qj->mj", tw, mu, lj)
+    B = np.zeros((E * NF, E * NF))
+    for F in range(E):
+        Fo = perm[F]
+        B[Fo * NF:(Fo + 1) * NF, F * NF:(F + 1) * NF] = Q.T / np.sqrt(2 * om.flen[Fo])
+    So_lib = B.T @ So @ B
+    assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
+    assert np.abs(S - S.T).max() < 1e-13 * np.abs(S).max()
+    # the constant multiplier (sqrt|F| on mode 0) spans the kernel
+    z = np.zeros((E, NF))
+    z[:, 0] = np.sqrt(om.flen[perm])
+    assert np.abs(S @ z.ravel()).max() < 1e-11 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("k,N", [(1, 8), (2, 6)])
+def test_multigrid_hierarchy_3d(lib, k, N):
+    """Smoothed aggregation on the 7-slot face matrix coarsens by at least 2 per level down
+    to a dense coarsest level of at most 1000 rows, with a Chebyshev bound rho(D^{-1} S) above
+    1 (the diagonal of an SPD matrix lies inside its spectrum)."""
+    xyz, per = periodic_kuhn_cube(N)
+    rc, m = _mesh(lib, xyz, per)
+    rc, c = _ctx(lib, m, k=k, precond=2)
+    assert rc == 0
+    L = ctypes.c_int()
+    rows = np.zeros(16, dtype=np.int64)
+    nnz = np.zeros(16, dtype=np.int64)
+    rho = np.zeros(16)
+    assert lib.dfdg_debug_multigrid(c, 16, ctypes.byref(L), rows.ctypes.data_as(P_), nnz.ctypes.data_as(P_),
+                                    rho.ctypes.data_as(P_)) == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    lib.dfdg_ctx_destroy(c)
+    lib.dfdg_mesh_destroy(m)
+    nl = L.value
+    assert nl >= 2 and rows[0] == s.E * s.n_f
+    assert all(2 * rows[l + 1] <= rows[l] for l in range(nl - 1))
+    assert rows[nl - 1] <= 1000
+    assert rho[0] > 1.0
+
+
+def test_tetrahedral_requests_validated_on_the_host(lib):
+    xyz, per = periodic_kuhn_cube(2)
+    rc, m = _mesh(lib, xyz, per)
+    assert rc == 0
+    for kw in (dict(k=3), dict(k=2, precision=1)):
+        rc, c = _ctx(lib, m, **kw)
+        assert rc == -8, kw  # DFDG_E_UNSUPPORTED
+    rc, c = _ctx(lib, m, k=2)
+    assert rc == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    assert (s.dim, s.T, s.E, s.P, s.n_f, s.n_p) == (3, 48, 96, 10, 6, 4)
+    assert s.n_broken == 3 * 10 * 48 and s.n_lambda == 6 * 96
+    assert s.n_bdm == 96 * 6 + 48 * (30 - 24)
+    # the adjoint form is not implemented on tetrahedra (nor are calls before binding)
+    assert lib.dfdg_dg_residual_vjp(c, P_(8), P_(8), P_(8)) == -3
+    lib.dfdg_ctx_destroy(c)
+    # an inverted element and a non-periodic mesh are rejected
+    bad = xyz.copy()
+    bad[0, [1, 2]] = bad[0, [2, 1]]
+    assert _mesh(lib, bad, per)[0] == -2
+    assert _mesh(lib, xyz[:-6], per)[0] == -2
+    lib.dfdg_mesh_destroy(m)
