@@ -240,21 +240,30 @@ def three_d(args):
     from paper_1808_04669_amd import Solver
     N, k, nu, steps = args.three_d_N, 2, 1.0 / 1600, args.three_d_steps
     xyz, per = periodic_kuhn_cube(N, args.order)
-    # the multigrid-preconditioned PCG on the same workload, reported beside the Jacobi one
-    sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, precond="amg", extrapolate=args.extrapolate)
-    sa._xyz = xyz
-    Ua, vmax, _ = project_field(sa, taylor_green_3d)
-    dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
-    ta, itsa = timed_run(sa, Ua, dt, steps, 2)
-    amg = {"value": sa.n_bdm * 3 * steps / ta, "ms_per_step": 1e3 * ta / steps,
-           "pcg_iterations_per_stage": float(itsa.mean()), "setup_s": sa.setup_seconds,
-           "diagnostics_final": sa.diagnostics(Ua)}
-    if sa.mg_levels():
-        amg["levels_rows"] = sa.mg_levels()
-    ms_vc, b_vc = sa.time_kernel(4, reps=20)
-    amg["vcycle"] = {"us": round(ms_vc * 1e3, 3), "GB/s": round(b_vc / ms_vc / 1e6, 1)}
-    del sa, Ua
-    torch.cuda.empty_cache()
+    # other solver variants on the same workload: the multigrid-preconditioned PCG, and
+    # matrix-free products of the facet system in both
+    variants = {}
+    dt = None
+    for name, kw in (("amg", dict(precond="amg")), ("amg_matrix_free", dict(precond="amg", matrix_free=True)),
+                     ("jacobi_matrix_free", dict(precond="jacobi", matrix_free=True))):
+        sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, extrapolate=args.extrapolate, **kw)
+        sa._xyz = xyz
+        Ua, vmax, _ = project_field(sa, taylor_green_3d)
+        dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
+        ta, itsa = timed_run(sa, Ua, dt, steps, 2)
+        v = {"value": sa.n_bdm * 3 * steps / ta, "ms_per_step": 1e3 * ta / steps,
+             "pcg_iterations_per_stage": float(itsa.mean()), "setup_s": sa.setup_seconds,
+             "diagnostics_final": sa.diagnostics(Ua)}
+        if kw["precond"] == "amg":
+            v["levels_rows"] = sa.mg_levels()
+            ms_vc, b_vc = sa.time_kernel(4, reps=20)
+            v["vcycle"] = {"us": round(ms_vc * 1e3, 3), "GB/s": round(b_vc / ms_vc / 1e6, 1)}
+        ms_sp, b_sp = sa.time_kernel(0, reps=20)
+        v["spmv"] = {"us": round(ms_sp * 1e3, 3), "bytes": b_sp, "GB/s": round(b_sp / ms_sp / 1e6, 1)}
+        variants[name] = v
+        log("3d variant", name, v)
+        del sa, Ua
+        torch.cuda.empty_cache()
     s = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, precond="jacobi", extrapolate=args.extrapolate)
     s._xyz = xyz
     U, vmax, pinfo = project_field(s, taylor_green_3d)
@@ -274,7 +283,7 @@ def three_d(args):
                     "achieved_GBs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
            "residual": {"avg_launch_us": round(ms_res * 1e3, 3), "bytes_per_launch": b_res,
                         "GBs": round(b_res / (ms_res * 1e-3) / 1e9, 1)},
-           "amg": amg}
+           "variants": variants}
     del s
     torch.cuda.empty_cache()
     if not args.no_cpu_baseline:

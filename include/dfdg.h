@@ -113,6 +113,10 @@ typedef struct {
                         than rows/256, each thread walks several facet rows in a grid-
                         stride loop (the path every mesh above 262144 facets takes); the
                         results are the same up to the order of the partial sums. */
+  int matrix_free;   /* tetrahedral meshes, FP64 PCG: 1 = form S p element by element as
+                        sum_T C_T W_T C_T^T p from the element data (two passes, no matrix
+                        read) instead of reading the assembled S; 0 = assembled S (default).
+                        The multigrid smoothing still reads S.  Triangle meshes: must be 0. */
 } dfdg_params;
 
 typedef struct {

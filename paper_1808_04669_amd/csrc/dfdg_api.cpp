@@ -175,6 +175,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->mg_fp32 = 1;
   p->mg_fine_fp16 = 1;
   p->facet_blocks = 0;
+  p->matrix_free = 0;
 }
 
 static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
@@ -200,6 +201,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
   if (p->facet_blocks < 0 || p->facet_blocks > 1024) { e = "facet_blocks must be in 0..1024"; return -1; }
+  if (p->matrix_free != 0 && p->matrix_free != 1) { e = "matrix_free must be 0 or 1"; return -1; }
   return 0;
 }
 
@@ -225,6 +227,10 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
       delete ctx;
       return DFDG_E_UNSUPPORTED;
     }
+  } else if (prm->matrix_free) {
+    g_mesh_err = "matrix_free: tetrahedral meshes only";
+    delete ctx;
+    return DFDG_E_UNSUPPORTED;
   }
   if ((ctx->dim == 3 ? build_setup3(mesh->m, prm->k, prm->alpha, ctx->hs, e)
                      : build_setup(mesh->m, prm->k, prm->alpha, ctx->hs, e))) {
@@ -355,6 +361,13 @@ static void carve(dfdg_ctx* ctx, char* base) {
   // work
   ctx->Lbuf = c.take<double>(nU);
   ctx->q = c.take<double>(nfac * NF * T);
+  // the matrix-free products use q for the face contributions: the condensation right-hand
+  // side in it has been gathered into g before the PCG runs, and nothing reads it after
+  A.mfq = ctx->prm.matrix_free ? ctx->q : nullptr;
+  A.mfCh = d.Ch;
+  A.mfDh = d.Dh;
+  A.mfQf = d.Qf;
+  A.mfK = ctx->K;
   ctx->gv = c.take<double>(nL);
   ctx->lamw = c.take<double>(nL);
   ctx->lamx = c.take<double>(nL);
@@ -1307,7 +1320,15 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   if (bytes) {
     double b = 0;
     switch (which) {
-      case 0: b = E * (NS * NF * NF * 8.0 + NS * 4.0 + 4.0 * NF * 8.0); break;  // S, cols, z, p_old, p_new, Sp
+      case 0:
+        if (ctx->A.mfq)  // element pass: Jinv, (D D^T)^{-1}, per face id, code, sqrt(|F|/det), normal,
+                         // z and p_old gathered, contributions out; face pass: 2 offsets, both
+                         // contributions, z, p_old in, p_new, Sp out
+          b = T * (9 * 8.0 + nGpk3(ctx->K) * 8.0 + 4 * (2 * 4.0 + 4 * 8.0) + 4 * NF * 2 * 8.0 + 4 * NF * 8.0) +
+              E * (2 * 4.0 + 6.0 * NF * 8.0);
+        else
+          b = E * (NS * NF * NF * 8.0 + NS * 4.0 + 4.0 * NF * 8.0);  // S, cols, z, p_old, p_new, Sp
+        break;
       case 1: b = E * NF * 8.0 * 8.0; break;                                                  // p, Sp, x, r, M^{-1} in; x, r, z out
       case 2:  // U (own + neighbours) in, L out, Jinv + 1/sqrt(detJ); per facet nbr, code, normal,
                // |F| (and sigma if nu != 0)

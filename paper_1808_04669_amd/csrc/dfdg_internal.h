@@ -118,6 +118,12 @@ struct DevTabs {
 };
 struct DevBsr {
   int ns;               // blocks per row: 5 (triangles) or 7 (tetrahedra)
+  // matrix-free products of the FP64 PCG (tetrahedra, dfdg_params.matrix_free): S p is formed
+  // element by element as sum_T C_T W_T C_T^T p from the element data and the reference
+  // tables below, through the per-element face contributions mfq [4][NF][T]; null = BSR
+  double* mfq;
+  const double* mfCh; const double* mfDh; const double* mfQf;
+  int mfK;
   const int* cols;      // [5][E]
   const double* vals;   // [5][NF][NF][E]
   const double* dinv;   // [E][NF]       point Jacobi

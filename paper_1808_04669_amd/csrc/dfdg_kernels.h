@@ -112,6 +112,10 @@ hipError_t launch_eval3(int K, int npts, const DevGeo& g, const double* tab, con
                         hipStream_t s);
 hipError_t launch_diagnostics3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* partials,
                                double* res, hipStream_t s);
+// The PCG product p_new = z + beta p_old, Sp = S p_new and its (p, Sp) partials, matrix free
+// (A.mfq set): an element pass and a face pass (same role and arguments as launch_pcg_spmv).
+hipError_t launch_mf_spmv3(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
+                           double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s);
 // x_{.,0} -= (zdef, x_{.,0}) zdef (part: scratch for one partial per facet block).
 hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipStream_t s);
 hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv, const PcgBufs& pb, double rtol,

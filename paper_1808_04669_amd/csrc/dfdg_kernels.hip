@@ -26,87 +26,6 @@ namespace dfdg {
 // reductions
 // ---------------------------------------------------------------------------------------
 
-// Reductions without atomics or fences: a kernel writes one partial per block; the next
-// kernel on the stream (after the kernel boundary has made them visible) sums all partials
-// redundantly in every block, in a fixed order, so every block gets the same bits.
-template <int NV>
-__device__ inline void block_write_partial(const double (&v)[NV], double* __restrict__ buf) {
-  __shared__ double sh[NV][kBlk / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(v[i]);
-    if (lane == 0) sh[i][wid] = s;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-      double s = 0;
-      for (int w = 0; w < nw; ++w) s += sh[i][w];
-      buf[blockIdx.x * NV + i] = s;
-    }
-  }
-}
-
-// Sum n partials of NV values each; every thread of the block receives the totals.
-// Block-wide sums of per-thread values (fixed order: waves, then the waves' sums).
-template <int NV>
-__device__ inline void block_sum_values(const double (&acc)[NV], double (&out)[NV]) {
-  __shared__ double sh[NV][kBlk / 64];
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    const double s = wave_sum(acc[i]);
-    if (lane == 0) sh[i][wid] = s;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) {
-    double s = 0;
-    for (int w = 0; w < nw; ++w) s += sh[i][w];
-    out[i] = s;
-  }
-  __syncthreads();
-}
-template <int NV>
-__device__ inline void block_sum_partials(const double* __restrict__ buf, int n, double (&out)[NV]) {
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0;
-  for (int b = threadIdx.x; b < n; b += blockDim.x)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] += buf[b * NV + i];
-  block_sum_values<NV>(acc, out);
-}
-// The same sums in two steps: load this thread's partials (up to kPartsPerThread of them)
-// now, add them up later, so that the loads' latency overlaps other work.
-static constexpr int kMaxFacetGrid = 1024;
-static constexpr int kPartsPerThread = (kMaxFacetGrid + kBlk - 1) / kBlk;
-template <int NV>
-struct PartLoad { double v[kPartsPerThread][NV]; };
-template <int NV>
-__device__ inline void partials_load(const double* __restrict__ buf, int n, bool on, PartLoad<NV>& q) {
-#pragma unroll
-  for (int j = 0; j < kPartsPerThread; ++j) {
-    const int b = threadIdx.x + j * blockDim.x;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) q.v[j][i] = (on && b < n) ? buf[b * NV + i] : 0.0;
-  }
-}
-template <int NV>
-__device__ inline void partials_sum(const PartLoad<NV>& q, int n, double (&out)[NV]) {
-  double acc[NV];
-#pragma unroll
-  for (int i = 0; i < NV; ++i) acc[i] = 0;
-#pragma unroll
-  for (int j = 0; j < kPartsPerThread; ++j)
-    if ((int)threadIdx.x + j * (int)blockDim.x < n)
-#pragma unroll
-      for (int i = 0; i < NV; ++i) acc[i] += q.v[j][i];
-  block_sum_values<NV>(acc, out);
-}
-
 // ---------------------------------------------------------------------------------------
 // element helpers
 // ---------------------------------------------------------------------------------------
@@ -1808,6 +1727,10 @@ static hipError_t spmv_any(int NF, const DevGeo& g, const DevBsr& A, const V* z,
   const int G = g.fgrid;
   const double* prev = pb.rz[(it - 1) & 1];
   const double* prev2 = pb.rz[it & 1];
+  if constexpr (sizeof(V) == 8) {
+    if (A.mfq) return launch_mf_spmv3(NF, g, A, (const double*)z, (const double*)p_old, (double*)p_new, (double*)Sp, pb,
+                                      it, s);
+  }
   if (sizeof(V) == 4 && A.ns != kSlots) return hipErrorInvalidValue;  // FP32 copies: triangles only
   DFDG_DISPATCH_NFS(NF, A.ns, DFDG_LAUNCH_TIMED((k_pcg_spmv<NN, SS, V, V>), dim3(G), dim3(kBlk), 0, s, g, A, z, p_old,
                                                 p_new, Sp, pb.sc, prev, prev2, pb.pq));

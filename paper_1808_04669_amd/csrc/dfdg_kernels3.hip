@@ -365,6 +365,188 @@ __global__ __launch_bounds__(kEBlk) void k_recover3(DevGeo g, DevTabs tb, const 
 }
 
 // ---------------------------------------------------------------------------------------
+// a5: matrix-free product of the facet system, S p = sum_T C_T W_T C_T^T p (eq. (FE3)
+// condensed), in the PCG iteration it (read from the scalars): beta and the stopping test
+// from the partials of the previous updates, exactly as the BSR kernel forms them.
+// ---------------------------------------------------------------------------------------
+// beta of iteration it from the (r, z) partials of iterations it-1 and it-2 (every block of
+// every kernel that calls this sums them in the same order: the same bits); false when the
+// run has stopped (block 0 records the stopping test for the host and later kernels)
+__device__ inline bool pcg_beta(PcgScalars* sc, const double* __restrict__ rz_prev,
+                                const double* __restrict__ rz_prev2, int G, bool test, double& beta) {
+  if (sc->done != PCG_RUNNING) return false;
+  const int it = sc->it;
+  double t1[2];
+  block_sum_partials<2>(rz_prev, G, t1);
+  beta = 0;
+  if (it >= 2) {
+    double t2[2];
+    block_sum_partials<2>(rz_prev2, G, t2);
+    beta = t1[0] / t2[0];
+  }
+  int status = PCG_RUNNING;
+  if (!isfinite(t1[0]) || !isfinite(t1[1]) || !isfinite(beta)) status = PCG_NONFINITE;
+  else if (t1[1] <= sc->tol2) status = PCG_CONVERGED;
+  else if (it - 1 >= sc->maxit) status = PCG_MAXIT;
+  if (test && blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->iters = it - 1;
+    sc->rr = t1[1];
+    sc->rz = t1[0];
+    if (it == 1) sc->rr0 = t1[1];
+    if (status != PCG_RUNNING) sc->done = status;
+  }
+  return status == PCG_RUNNING;
+}
+
+// Element pass: p = z + beta p_old at the element's four faces (the L side's face basis,
+// mapped to the own one on R faces), y = W_T C_T^T p, and the face contributions C_T y
+// (mapped back) into A.mfq.
+template <int K>
+__global__ __launch_bounds__(kBlk) void k_mf_apply3(DevGeo g, DevBsr A, const double* __restrict__ z,
+                                                    const double* __restrict__ p_old, PcgScalars* sc,
+                                                    const double* __restrict__ rz_prev,
+                                                    const double* __restrict__ rz_prev2, int G) {
+  constexpr int P = nP3(K), NF = nF3(K);
+  double beta;
+  if (!pcg_beta(sc, rz_prev, rz_prev2, G, true, beta)) return;
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const double* __restrict__ Ch = A.mfCh;
+  double y[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) y[c][i] = 0;
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int Fc = g.efacet[idx];
+    const int code = g.code[idx];
+    double lm[NF];
+#pragma unroll
+    for (int a = 0; a < NF; ++a) lm[a] = z[(size_t)Fc * NF + a] + beta * p_old[(size_t)Fc * NF + a];
+    if ((code >> 5) & 1) {
+      const double* Q = A.mfQf + ((code >> 2) & 7) * NF * NF;
+      double o[NF];
+#pragma unroll
+      for (int b = 0; b < NF; ++b) {
+        double s = 0;
+#pragma unroll
+        for (int a = 0; a < NF; ++a) s += Q[a * NF + b] * lm[a];
+        o[b] = s;
+      }
+#pragma unroll
+      for (int b = 0; b < NF; ++b) lm[b] = o[b];
+    }
+    const double sc2 = g.sF[idx];
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int mm = 0; mm < NF; ++mm) s += lm[mm] * Ch[(f * NF + mm) * P + i];
+      s *= sc2;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) y[c][i] += n[c] * s;
+    }
+  }
+  double Ji[3][3];
+  load_Jinv3(g, t, Ji);
+  apply_W3<K>(y, Ji, g.G, T, t, A.mfDh);
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const double sc2 = g.sF[idx];
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+    const int code = g.code[idx];
+    double m[NF];
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) s += Ch[(f * NF + mm) * P + i] * (n[0] * y[0][i] + n[1] * y[1][i] + n[2] * y[2][i]);
+      m[mm] = sc2 * s;
+    }
+    if ((code >> 5) & 1) {
+      const double* Q = A.mfQf + ((code >> 2) & 7) * NF * NF;
+      double o[NF];
+#pragma unroll
+      for (int a = 0; a < NF; ++a) {
+        double s = 0;
+#pragma unroll
+        for (int b = 0; b < NF; ++b) s += Q[a * NF + b] * m[b];
+        o[a] = s;
+      }
+#pragma unroll
+      for (int a = 0; a < NF; ++a) m[a] = o[a];
+    }
+#pragma unroll
+    for (int mm = 0; mm < NF; ++mm) A.mfq[(size_t)(f * NF + mm) * T + t] = m[mm];
+  }
+}
+
+// Face pass: S p = the two sides' contributions, p_new = z + beta p_old, (p_new, S p)
+// partials (grid-stride over the face rows, one partial per block).
+template <int NF>
+__global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const double* __restrict__ z,
+                                                    const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                    double* __restrict__ Sp, PcgScalars* sc,
+                                                    const double* __restrict__ rz_prev,
+                                                    const double* __restrict__ rz_prev2, double* __restrict__ pq) {
+  double beta;
+  if (!pcg_beta(sc, rz_prev, rz_prev2, gridDim.x, false, beta)) return;
+  const int T = g.T;
+  double v[1] = {0};
+  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x) {
+    const int a = g.qL[F], b = g.qR[F];
+#pragma unroll
+    for (int m = 0; m < NF; ++m) {
+      const size_t o = (size_t)F * NF + m;
+      const double y = A.mfq[a + (size_t)m * T] + A.mfq[b + (size_t)m * T];
+      const double pn = z[o] + beta * p_old[o];
+      p_new[o] = pn;
+      Sp[o] = y;
+      v[0] += pn * y;
+    }
+  }
+  block_write_partial<1>(v, pq);
+}
+
+hipError_t launch_mf_spmv3(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,
+                           double* p_new, double* Sp, const PcgBufs& pb, int it, hipStream_t s) {
+  const int G = g.fgrid;
+  const double* prev = pb.rz[(it - 1) & 1];
+  const double* prev2 = pb.rz[it & 1];
+  hipEvent_t e0, e1;  // kernel timing: start of the element pass to the end of the face pass
+  get_dispatch_events(&e0, &e1);
+  const dim3 eg(nblk(g.T, kBlk)), blk(kBlk);
+  switch (A.mfK) {
+    case 1:
+      if (e0) hipExtLaunchKernelGGL((k_mf_apply3<1>), eg, blk, 0, s, e0, nullptr, 0, g, A, z, p_old, pb.sc, prev, prev2, G);
+      else hipLaunchKernelGGL((k_mf_apply3<1>), eg, blk, 0, s, g, A, z, p_old, pb.sc, prev, prev2, G);
+      break;
+    case 2:
+      if (e0) hipExtLaunchKernelGGL((k_mf_apply3<2>), eg, blk, 0, s, e0, nullptr, 0, g, A, z, p_old, pb.sc, prev, prev2, G);
+      else hipLaunchKernelGGL((k_mf_apply3<2>), eg, blk, 0, s, g, A, z, p_old, pb.sc, prev, prev2, G);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  switch (NF) {
+    case 3:
+      if (e1) hipExtLaunchKernelGGL((k_mf_gather<3>), dim3(G), blk, 0, s, nullptr, e1, 0, g, A, z, p_old, p_new, Sp, pb.sc, prev, prev2, pb.pq);
+      else hipLaunchKernelGGL((k_mf_gather<3>), dim3(G), blk, 0, s, g, A, z, p_old, p_new, Sp, pb.sc, prev, prev2, pb.pq);
+      break;
+    case 6:
+      if (e1) hipExtLaunchKernelGGL((k_mf_gather<6>), dim3(G), blk, 0, s, nullptr, e1, 0, g, A, z, p_old, p_new, Sp, pb.sc, prev, prev2, pb.pq);
+      else hipLaunchKernelGGL((k_mf_gather<6>), dim3(G), blk, 0, s, g, A, z, p_old, p_new, Sp, pb.sc, prev, prev2, pb.pq);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // a2 / a10: load vector, evaluation and diagnostics
 // ---------------------------------------------------------------------------------------
 template <int K>

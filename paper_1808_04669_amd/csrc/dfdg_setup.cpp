@@ -7,6 +7,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
+#include <thread>
 #include <unordered_map>
 
 namespace dfdg {
@@ -476,77 +478,36 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
   }
   for (int F = 0; F < E; ++F) h.zdef[F] /= std::sqrt(zz);
 
-  // Element condensation.  With the orthonormal basis the element mass matrix is I and
-  //   W_T = I - D_T^T (D_T D_T^T)^{-1} D_T          (velocity block of K_T^{-1})
-  //   S_T = C_T W_T C_T^T,   S = sum_T S_T            (eq. (FE3) condensed)
-  std::vector<double> D(NP * NU), DDt(NP * NP), W(NU * NU), C(3 * NF * NU), CW(3 * NF * NU),
-      ST(9 * NF * NF);
-  for (int t = 0; t < T; ++t) {
-    const double Ji[2][2] = {{h.Jinv[0 * (size_t)T + t], h.Jinv[1 * (size_t)T + t]},
-                             {h.Jinv[2 * (size_t)T + t], h.Jinv[3 * (size_t)T + t]}};
-    for (int j = 0; j < NP; ++j)
-      for (int c = 0; c < 2; ++c)
-        for (int i = 0; i < P; ++i)
-          D[j * NU + c * P + i] =
-              Ji[0][c] * tb.Dh[(0 * NP + j) * P + i] + Ji[1][c] * tb.Dh[(1 * NP + j) * P + i];
-    for (int j = 0; j < NP; ++j)
-      for (int l = 0; l < NP; ++l) {
-        double s = 0;
-        for (int x = 0; x < NU; ++x) s += D[j * NU + x] * D[l * NU + x];
-        DDt[j * NP + l] = s;
-      }
-    if (!spd_inverse(NP, DDt.data())) {
-      err = "divergence matrix of element " + std::to_string(t) + " is rank deficient";
-      return -2;
-    }
-    for (int j = 0, p = 0; j < NP; ++j)
-      for (int l = 0; l <= j; ++l, ++p) h.G[(size_t)p * T + t] = DDt[j * NP + l];
-    for (int x = 0; x < NU; ++x)
-      for (int y = 0; y < NU; ++y) {
-        double s = (x == y) ? 1.0 : 0.0;
-        for (int j = 0; j < NP; ++j)
-          for (int l = 0; l < NP; ++l) s -= D[j * NU + x] * DDt[j * NP + l] * D[l * NU + y];
-        W[x * NU + y] = s;
-      }
-    for (int f = 0; f < 3; ++f) {
-      const size_t idx = (size_t)f * T + t;
-      const bool flip = ((h.code[idx] >> 3) & 1) && ((h.code[idx] >> 2) & 1);
-      const double n[2] = {h.nx[idx], h.ny[idx]};
-      for (int mm = 0; mm < NF; ++mm) {
-        const double sg = (flip && (mm & 1)) ? -1.0 : 1.0;
+  // Element condensation (eq. (FE3)): D_T = sum_a Jinv[a][c] Dh[a], C_T rows of face f are
+  // sqrt(|F|/det J) n_c Ch[f] (sign (-1)^m on the R side of a reversed facet: the L side's
+  // Legendre parameter runs the other way)
+  struct Tri : CondenseElement {
+    const HostSetup& h;
+    int T, NP, P, NF, NU;
+    Tri(const HostSetup& hh, int t, int np, int p, int nf) : h(hh), T(t), NP(np), P(p), NF(nf), NU(2 * p) {}
+    bool isR(int t, int f) const override { return (h.code[(size_t)f * T + t] >> 3) & 1; }
+    void build(int t, double* D, double* C) const override {
+      const RefTables& tb = h.tabs;
+      const double Ji[2][2] = {{h.Jinv[0 * (size_t)T + t], h.Jinv[1 * (size_t)T + t]},
+                               {h.Jinv[2 * (size_t)T + t], h.Jinv[3 * (size_t)T + t]}};
+      for (int j = 0; j < NP; ++j)
         for (int c = 0; c < 2; ++c)
           for (int i = 0; i < P; ++i)
-            C[(f * NF + mm) * NU + c * P + i] = sg * h.sF[idx] * n[c] * tb.Ch[(f * NF + mm) * P + i];
+            D[j * NU + c * P + i] = Ji[0][c] * tb.Dh[(0 * NP + j) * P + i] + Ji[1][c] * tb.Dh[(1 * NP + j) * P + i];
+      for (int f = 0; f < 3; ++f) {
+        const size_t idx = (size_t)f * T + t;
+        const bool flip = ((h.code[idx] >> 3) & 1) && ((h.code[idx] >> 2) & 1);
+        const double n[2] = {h.nx[idx], h.ny[idx]};
+        for (int mm = 0; mm < NF; ++mm) {
+          const double sg = (flip && (mm & 1)) ? -1.0 : 1.0;
+          for (int c = 0; c < 2; ++c)
+            for (int i = 0; i < P; ++i)
+              C[(f * NF + mm) * NU + c * P + i] = sg * h.sF[idx] * n[c] * tb.Ch[(f * NF + mm) * P + i];
+        }
       }
     }
-    for (int r = 0; r < 3 * NF; ++r)
-      for (int y = 0; y < NU; ++y) {
-        double s = 0;
-        for (int x = 0; x < NU; ++x) s += C[r * NU + x] * W[x * NU + y];
-        CW[r * NU + y] = s;
-      }
-    for (int r = 0; r < 3 * NF; ++r)
-      for (int c2 = 0; c2 < 3 * NF; ++c2) {
-        double s = 0;
-        for (int y = 0; y < NU; ++y) s += CW[r * NU + y] * C[c2 * NU + y];
-        ST[r * 3 * NF + c2] = s;
-      }
-    // scatter into the facet rows: slot 0 = the facet itself, slots 1-2 the other facets
-    // of its L element, slots 3-4 those of its R element (in local order f+1, f+2)
-    for (int f = 0; f < 3; ++f) {
-      const int F = h.efacet[(size_t)f * T + t];
-      const bool isR = (h.code[(size_t)f * T + t] >> 3) & 1;
-      for (int f2 = 0; f2 < 3; ++f2) {
-        const int F2 = h.efacet[(size_t)f2 * T + t];
-        int slot = 0;
-        if (f2 != f) slot = (isR ? 3 : 1) + ((f2 - f + 3) % 3) - 1;
-        h.cols[(size_t)slot * E + F] = F2;
-        for (int a = 0; a < NF; ++a)
-          for (int b = 0; b < NF; ++b)
-            h.vals[(((size_t)slot * NF + a) * NF + b) * E + F] += ST[(f * NF + a) * 3 * NF + f2 * NF + b];
-      }
-    }
-  }
+  } el(h, T, NP, P, NF);
+  if (condense_elements(h, 3, NP, NU, NF, el, err)) return -2;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)
     for (int s = 1; s < kSlots; ++s)
@@ -575,6 +536,95 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
     }
     for (int a = 0; a < NF * NF; ++a) h.binv[(size_t)F * NF * NF + a] = B[a];
   }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Element condensation on the host's cores
+// ---------------------------------------------------------------------------------------
+int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const CondenseElement& el, std::string& err) {
+  const int T = h.T, E = h.E, NR = nfac * NF;
+  // the R side's diagonal block of a face row is written here and added after the
+  // parallel loop (the L side writes slot 0 itself), so no two threads write one value
+  std::vector<double> diagR((size_t)E * NF * NF, 0.0);
+  std::atomic<int> bad(-1);
+  auto work = [&](int t0, int t1) {
+    std::vector<double> D((size_t)NP * NU), DDt((size_t)NP * NP), C((size_t)NR * NU), CDt((size_t)NR * NP),
+        X((size_t)NR * NP), ST((size_t)NR * NR);
+    for (int t = t0; t < t1; ++t) {
+      el.build(t, D.data(), C.data());
+      for (int j = 0; j < NP; ++j)
+        for (int l = 0; l < NP; ++l) {
+          double s = 0;
+          for (int x = 0; x < NU; ++x) s += D[(size_t)j * NU + x] * D[(size_t)l * NU + x];
+          DDt[(size_t)j * NP + l] = s;
+        }
+      if (!spd_inverse(NP, DDt.data())) {
+        int exp = -1;
+        bad.compare_exchange_strong(exp, t);
+        return;
+      }
+      for (int j = 0, p = 0; j < NP; ++j)
+        for (int l = 0; l <= j; ++l, ++p) h.G[(size_t)p * T + t] = DDt[(size_t)j * NP + l];
+      for (int r = 0; r < NR; ++r)
+        for (int j = 0; j < NP; ++j) {
+          double s = 0;
+          for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * D[(size_t)j * NU + x];
+          CDt[(size_t)r * NP + j] = s;
+        }
+      for (int r = 0; r < NR; ++r)
+        for (int j = 0; j < NP; ++j) {
+          double s = 0;
+          for (int l = 0; l < NP; ++l) s += CDt[(size_t)r * NP + l] * DDt[(size_t)l * NP + j];
+          X[(size_t)r * NP + j] = s;
+        }
+      for (int r = 0; r < NR; ++r)
+        for (int c2 = 0; c2 <= r; ++c2) {
+          double s = 0;
+          for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * C[(size_t)c2 * NU + x];
+          for (int j = 0; j < NP; ++j) s -= X[(size_t)r * NP + j] * CDt[(size_t)c2 * NP + j];
+          ST[(size_t)r * NR + c2] = ST[(size_t)c2 * NR + r] = s;
+        }
+      for (int f = 0; f < nfac; ++f) {
+        const int F = h.efacet[(size_t)f * T + t];
+        const bool isR = el.isR(t, f);
+        for (int f2 = 0; f2 < nfac; ++f2) {
+          const int F2 = h.efacet[(size_t)f2 * T + t];
+          if (f2 == f) {
+            double* dst = isR ? &diagR[(size_t)F * NF * NF] : nullptr;
+            for (int a = 0; a < NF; ++a)
+              for (int b = 0; b < NF; ++b) {
+                const double v = ST[((size_t)f * NF + a) * NR + f2 * NF + b];
+                if (isR) dst[a * NF + b] = v;
+                else h.vals[(((size_t)0 * NF + a) * NF + b) * E + F] = v;
+              }
+            if (!isR) h.cols[F] = F;
+            continue;
+          }
+          const int slot = (isR ? nfac : 1) + ((f2 - f + nfac) % nfac) - 1;
+          h.cols[(size_t)slot * E + F] = F2;
+          for (int a = 0; a < NF; ++a)
+            for (int b = 0; b < NF; ++b)
+              h.vals[(((size_t)slot * NF + a) * NF + b) * E + F] = ST[((size_t)f * NF + a) * NR + f2 * NF + b];
+        }
+      }
+    }
+  };
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if ((long)T < 4096L * nt) nt = std::max<long>(1, T / 4096) < nt ? (unsigned)std::max<long>(1, T / 4096) : nt;
+  std::vector<std::thread> pool;
+  const int chunk = (T + (int)nt - 1) / (int)nt;
+  for (unsigned i = 0; i < nt; ++i) {
+    const int t0 = (int)i * chunk, t1 = std::min(T, t0 + chunk);
+    if (t0 < t1) pool.emplace_back(work, t0, t1);
+  }
+  for (auto& th : pool) th.join();
+  if (bad.load() >= 0) {
+    err = "divergence matrix of element " + std::to_string(bad.load()) + " is rank deficient";
+    return -2;
+  }
+  for (int F = 0; F < E; ++F)
+    for (int a = 0; a < NF * NF; ++a) h.vals[(size_t)a * E + F] += diagR[(size_t)F * NF * NF + a];
   return 0;
 }
 

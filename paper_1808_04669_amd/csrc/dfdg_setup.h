@@ -34,6 +34,20 @@ struct HostSetup {
 };
 
 int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std::string& err);
+
+// Element condensation of eq. (FE3) with the orthonormal basis (M_T = I), for all elements on
+// the host's cores: build(t, D, C) fills element t's divergence matrix D [NP][NU] and face rows
+// C [nfac*NF][NU] (each face's rows in its L side's basis); the packed (D D^T)^{-1} goes to
+// h.G and S_T = C W_T C^T = C C^T - (C D^T)(D D^T)^{-1}(D C^T) (W_T = I - D^T (D D^T)^{-1} D
+// is never formed) into the face rows of h.vals / h.cols: slot 0 the face itself, slots
+// 1..nfac-1 the other faces of its L element, nfac..2nfac-2 those of its R element (in local
+// order f+1, f+2, ...).  isR(t, f): element t is the R side of its local face f.
+struct CondenseElement {
+  virtual void build(int t, double* D, double* C) const = 0;
+  virtual bool isR(int t, int f) const = 0;
+  virtual ~CondenseElement() = default;
+};
+int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const CondenseElement& el, std::string& err);
 int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::string& err);
 int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std::string& err);
 int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::string& err);

@@ -654,88 +654,48 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
   }
   for (int F = 0; F < E; ++F) h.zdef[F] /= std::sqrt(zz);
 
-  // Element condensation with the orthonormal basis (M_T = I):
-  //   W_T = I - D_T^T (D_T D_T^T)^{-1} D_T,  S_T = C_T W_T C_T^T,  S = sum_T S_T  (eq. (FE3))
-  // C_T rows of a face whose L side is the other element are expressed in L's face basis.
-  std::vector<double> D((size_t)NP * NU), DDt((size_t)NP * NP), W((size_t)NU * NU), Cl((size_t)NF * NU),
-      C((size_t)4 * NF * NU), CW((size_t)4 * NF * NU), ST((size_t)16 * NF * NF);
-  for (int t = 0; t < T; ++t) {
-    double Ji[3][3];
-    for (int r = 0; r < 3; ++r)
-      for (int j = 0; j < 3; ++j) Ji[r][j] = h.Jinv[(size_t)(3 * r + j) * T + t];
-    for (int j = 0; j < NP; ++j)
-      for (int c = 0; c < 3; ++c)
-        for (int i = 0; i < P; ++i) {
-          double s = 0;
-          for (int a = 0; a < 3; ++a) s += Ji[a][c] * tb.Dh[((size_t)a * NP + j) * P + i];
-          D[(size_t)j * NU + c * P + i] = s;
-        }
-    for (int j = 0; j < NP; ++j)
-      for (int l = 0; l < NP; ++l) {
-        double s = 0;
-        for (int x = 0; x < NU; ++x) s += D[(size_t)j * NU + x] * D[(size_t)l * NU + x];
-        DDt[(size_t)j * NP + l] = s;
-      }
-    if (!spd_inverse(NP, DDt.data())) {
-      err = "divergence matrix of element " + std::to_string(t) + " is rank deficient";
-      return -2;
-    }
-    for (int j = 0, p = 0; j < NP; ++j)
-      for (int l = 0; l <= j; ++l, ++p) h.G[(size_t)p * T + t] = DDt[(size_t)j * NP + l];
-    for (int x = 0; x < NU; ++x)
-      for (int y = 0; y < NU; ++y) {
-        double s = (x == y) ? 1.0 : 0.0;
-        for (int j = 0; j < NP; ++j)
-          for (int l = 0; l < NP; ++l) s -= D[(size_t)j * NU + x] * DDt[(size_t)j * NP + l] * D[(size_t)l * NU + y];
-        W[(size_t)x * NU + y] = s;
-      }
-    for (int f = 0; f < 4; ++f) {
-      const size_t idx = (size_t)f * T + t;
-      const double n[3] = {h.nx[idx], h.ny[idx], h.nz[idx]};
-      for (int mm = 0; mm < NF; ++mm)
+  // Element condensation (eq. (FE3)): D_T = sum_a Jinv[a][c] Dh[a]; the rows of face f are
+  // sqrt(2|F|/det J) n_c Ch[f], mapped to the L side's face basis (Qf) on the R side
+  struct Tet : CondenseElement {
+    const HostSetup& h;
+    int T, NP, P, NF, NU;
+    Tet(const HostSetup& hh, int t, int np, int p, int nf) : h(hh), T(t), NP(np), P(p), NF(nf), NU(3 * p) {}
+    bool isR(int t, int f) const override { return (h.code[(size_t)f * T + t] >> 5) & 1; }
+    void build(int t, double* D, double* C) const override {
+      const RefTables& tb = h.tabs;
+      double Ji[3][3];
+      for (int r = 0; r < 3; ++r)
+        for (int j = 0; j < 3; ++j) Ji[r][j] = h.Jinv[(size_t)(3 * r + j) * T + t];
+      for (int j = 0; j < NP; ++j)
         for (int c = 0; c < 3; ++c)
-          for (int i = 0; i < P; ++i)
-            Cl[(size_t)mm * NU + c * P + i] = h.sF[idx] * n[c] * tb.Ch[((size_t)f * NF + mm) * P + i];
-      const bool isR = (h.code[idx] >> 5) & 1;
-      const int pid = (h.code[idx] >> 2) & 7;
-      for (int mm = 0; mm < NF; ++mm)
-        for (int x = 0; x < NU; ++x) {
-          double s = 0;
-          if (isR)
-            for (int n2 = 0; n2 < NF; ++n2) s += tb.Qf[((size_t)pid * NF + mm) * NF + n2] * Cl[(size_t)n2 * NU + x];
-          else
-            s = Cl[(size_t)mm * NU + x];
-          C[((size_t)f * NF + mm) * NU + x] = s;
-        }
-    }
-    for (int r = 0; r < 4 * NF; ++r)
-      for (int y = 0; y < NU; ++y) {
-        double s = 0;
-        for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * W[(size_t)x * NU + y];
-        CW[(size_t)r * NU + y] = s;
-      }
-    for (int r = 0; r < 4 * NF; ++r)
-      for (int c2 = 0; c2 < 4 * NF; ++c2) {
-        double s = 0;
-        for (int y = 0; y < NU; ++y) s += CW[(size_t)r * NU + y] * C[(size_t)c2 * NU + y];
-        ST[(size_t)r * 4 * NF + c2] = s;
-      }
-    // scatter into the face rows: slot 0 = the face itself, slots 1-3 the other faces of its
-    // L element, slots 4-6 those of its R element (in local order f+1, f+2, f+3)
-    for (int f = 0; f < 4; ++f) {
-      const int F = h.efacet[(size_t)f * T + t];
-      const bool isR = (h.code[(size_t)f * T + t] >> 5) & 1;
-      for (int f2 = 0; f2 < 4; ++f2) {
-        const int F2 = h.efacet[(size_t)f2 * T + t];
-        int slot = 0;
-        if (f2 != f) slot = (isR ? 4 : 1) + ((f2 - f + 4) % 4) - 1;
-        h.cols[(size_t)slot * E + F] = F2;
-        for (int a = 0; a < NF; ++a)
-          for (int b = 0; b < NF; ++b)
-            h.vals[(((size_t)slot * NF + a) * NF + b) * E + F] += ST[((size_t)f * NF + a) * 4 * NF + f2 * NF + b];
+          for (int i = 0; i < P; ++i) {
+            double s = 0;
+            for (int a = 0; a < 3; ++a) s += Ji[a][c] * tb.Dh[((size_t)a * NP + j) * P + i];
+            D[(size_t)j * NU + c * P + i] = s;
+          }
+      std::vector<double> Cl((size_t)NF * NU);
+      for (int f = 0; f < 4; ++f) {
+        const size_t idx = (size_t)f * T + t;
+        const double n[3] = {h.nx[idx], h.ny[idx], h.nz[idx]};
+        for (int mm = 0; mm < NF; ++mm)
+          for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < P; ++i)
+              Cl[(size_t)mm * NU + c * P + i] = h.sF[idx] * n[c] * tb.Ch[((size_t)f * NF + mm) * P + i];
+        const bool R = (h.code[idx] >> 5) & 1;
+        const int pid = (h.code[idx] >> 2) & 7;
+        for (int mm = 0; mm < NF; ++mm)
+          for (int x = 0; x < NU; ++x) {
+            double s = 0;
+            if (R)
+              for (int n2 = 0; n2 < NF; ++n2) s += tb.Qf[((size_t)pid * NF + mm) * NF + n2] * Cl[(size_t)n2 * NU + x];
+            else
+              s = Cl[(size_t)mm * NU + x];
+            C[((size_t)f * NF + mm) * NU + x] = s;
+          }
       }
     }
-  }
+  } el(h, T, NP, P, NF);
+  if (condense_elements(h, 4, NP, NU, NF, el, err)) return -2;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)
     for (int s = 1; s < NS; ++s)

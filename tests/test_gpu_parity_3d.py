@@ -24,14 +24,15 @@ def _log(*a):
     print(*a, flush=True)
 
 
-@pytest.mark.parametrize("precond", ["jacobi", "block_jacobi", "amg", "amg_fp64_cycle"])
+@pytest.mark.parametrize("precond", ["jacobi", "block_jacobi", "amg", "amg_fp64_cycle", "jacobi_mf", "amg_mf"])
 @pytest.mark.parametrize("k,N,order", [(1, 2, "lex"), (1, 3, "random"), (2, 2, "random"), (2, 3, "morton"),
                                        (1, 4, "morton")])
 def test_mass_solve_parity_3d(k, N, order, precond):
     """Divergence-free mass inversion of a random broken functional on tetrahedra
     (Theorems 1-2)."""
     _log("mass solve 3d", k, N, order, precond)
-    kw = dict(precond="amg", mg_fp32=False) if precond == "amg_fp64_cycle" else dict(precond=precond)
+    kw = {"amg_fp64_cycle": dict(precond="amg", mg_fp32=False), "jacobi_mf": dict(precond="jacobi", matrix_free=True),
+          "amg_mf": dict(precond="amg", matrix_free=True)}.get(precond, dict(precond=precond))
     orc, s, _, _ = make_pair(N, k, order=order, seed=N, dim=3, cg_rtol=1e-13, **kw)
     coef = random_broken_poly_3d(s.T, k, seed=10 + k)
     F = values_to_lib(s, lambda pts: eval_broken_poly_3d(coef, pts))
@@ -82,17 +83,18 @@ def test_residual_parity_broken_field_3d(k):
     assert err < 1e-11
 
 
-@pytest.mark.parametrize("k,N,nu,field,steps,precond", [
-    (2, 3, 1.0 / 1600, "tg", 3, "jacobi"),   # the 3D Taylor-Green workload's parameters on a small mesh
-    (2, 4, 1.0 / 1600, "tg", 3, "amg"),
-    (1, 4, 0.0, "abc", 3, "jacobi"),
-    (2, 2, 1e-2, "rand", 2, "amg"),
+@pytest.mark.parametrize("k,N,nu,field,steps,precond,mf", [
+    (2, 3, 1.0 / 1600, "tg", 3, "jacobi", False),   # the 3D Taylor-Green workload's parameters, small mesh
+    (2, 4, 1.0 / 1600, "tg", 3, "amg", False),
+    (2, 4, 1.0 / 1600, "tg", 3, "amg", True),
+    (1, 4, 0.0, "abc", 3, "jacobi", True),
+    (2, 2, 1e-2, "rand", 2, "amg", False),
 ])
-def test_rk3_trajectory_parity_3d(k, N, nu, field, steps, precond):
+def test_rk3_trajectory_parity_3d(k, N, nu, field, steps, precond, mf):
     """TVD-RK3 trajectories (eq. (rk3)) on tetrahedra from the oracle's projected field."""
-    _log("rk3 3d", k, N, nu, field, precond)
+    _log("rk3 3d", k, N, nu, field, precond, "matrix free" if mf else "")
     orc, s, _, _ = make_pair(N, k, nu=nu, order="morton", dim=3, cg_rtol=1e-13, precond=precond,
-                             extrapolate="adaptive")
+                             extrapolate="adaptive", matrix_free=mf)
     f = {"tg": taylor_green_3d, "abc": abc_flow, "rand": RandomVectorPotentialField(seed=1, kmax=2)}[field]
     U0 = orc.project(f)
     U = transfer(orc, U0, s)
@@ -198,6 +200,32 @@ def test_mass_solve_symmetric_idempotent_and_divergence_free_at_32(precond):
     assert abs(e0 - 0.125) < 1e-6  # 1/2 ||u0||^2 = 1/2 (1/8 + 1/8) for the 3D Taylor-Green field
 
 
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_matrix_free_products_equal_the_assembled_matrix(precond):
+    """The matrix-free products sum_T C_T W_T C_T^T p give the solves of the assembled S
+    (12^3 BDM_2: same iteration count within one, velocities within 1e-12), and replaying
+    their iterations from captured graphs repeats the eager launches bit for bit."""
+    outs = {}
+    for mf in (False, True):
+        for graphs in ((True, False) if mf else (True,)):
+            _, s, xyz, _ = make_pair(12, 2, nu=1e-3, oracle=False, dim=3, cg_rtol=1e-12, precond=precond,
+                                     matrix_free=mf, graphs=graphs, extrapolate=2)
+            g0 = torch.Generator(device="cpu").manual_seed(1)
+            f = torch.randn(s.n_broken, generator=g0, dtype=torch.float64).to(s.device)
+            Pf, info = s.mass_solve(f)
+            U, _ = project_field(s, xyz, taylor_green_3d)
+            its = [list(s.rk3_step(U, 0.002).iterations) for _ in range(3)]
+            outs[(mf, graphs)] = (Pf.clone(), info.iterations, U.clone(), its)
+            del s
+    (P0, i0, U0, _), (P1, i1, U1, its1) = outs[(False, True)], outs[(True, True)]
+    _log(precond, "assembled", i0, "matrix free", i1, "diff", ((P1 - P0).norm() / P0.norm()).item())
+    assert abs(i1 - i0) <= 1
+    assert ((P1 - P0).norm() / P0.norm()).item() < 1e-12
+    assert ((U1 - U0).norm() / U0.norm()).item() < 1e-12
+    P2, i2, U2, its2 = outs[(True, False)]
+    assert torch.equal(P1, P2) and i1 == i2 and torch.equal(U1, U2) and its1 == its2
+
+
 def test_time_kernel_and_binding_3d():
     """The measurement entry point runs the 7-slot SpMV and the tetrahedral residual."""
     _, s, xyz, _ = make_pair(8, 2, oracle=False, dim=3, precond="jacobi")
@@ -207,5 +235,8 @@ def test_time_kernel_and_binding_3d():
     assert ms > 0 and b == s.E * (7 * 36 * 8 + 7 * 4 + 4 * 6 * 8)
     ms, b = s.time_kernel(2, reps=5)
     assert ms > 0 and b > 0
+    _, smf, _, _ = make_pair(8, 2, oracle=False, dim=3, precond="jacobi", matrix_free=True)
+    ms, b = smf.time_kernel(0, reps=5)
+    assert ms > 0 and b == smf.T * (72 + 80 + 4 * 40 + 4 * 6 * 16 + 4 * 6 * 8) + smf.E * (8 + 6 * 6 * 8)
     assert s.to_tcp(U).shape == (3, 10, s.T)
     assert to_dev(s, np.zeros((s.T, 3, 2))).numel() == 6 * s.T

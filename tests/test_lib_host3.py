@@ -205,6 +205,15 @@ def test_tetrahedral_requests_validated_on_the_host(lib):
     for kw in (dict(k=3), dict(k=2, precision=1)):
         rc, c = _ctx(lib, m, **kw)
         assert rc == -8, kw  # DFDG_E_UNSUPPORTED
+    # matrix-free products: tetrahedral meshes only
+    from inputs import periodic_split_square
+    x2, p2 = periodic_split_square(3)
+    x2 = np.ascontiguousarray(x2)
+    p2 = np.ascontiguousarray(p2)
+    h2 = P_()
+    assert lib.dfdg_mesh_create(2, x2.shape[0], x2.ctypes.data_as(P_), p2.ctypes.data_as(P_), ctypes.byref(h2)) == 0
+    assert _ctx(lib, h2, k=2, matrix_free=1)[0] == -8
+    lib.dfdg_mesh_destroy(h2)
     rc, c = _ctx(lib, m, k=2)
     assert rc == 0
     s = lib_mod.Sizes()
