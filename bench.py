@@ -66,6 +66,10 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-random-order", action="store_true", help="skip the randomly numbered mesh run")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Taylor-Green run")
+    ap.add_argument("--only-3d", action="store_true",
+                    help="run only the 3D Taylor-Green leg and print its object (profiling)")
+    ap.add_argument("--three-d-variants", default="amg,amg_matrix_free,jacobi_matrix_free",
+                    help="comma list of the extra 3D solver variants to run beside Jacobi PCG")
     ap.add_argument("--three-d-N", type=int, default=32)
     ap.add_argument("--three-d-steps", type=int, default=50)
     ap.add_argument("--mixed-N", type=int, default=512)
@@ -243,9 +247,12 @@ def three_d(args):
     # other solver variants on the same workload: the multigrid-preconditioned PCG, and
     # matrix-free products of the facet system in both
     variants = {}
-    dt = None
-    for name, kw in (("amg", dict(precond="amg")), ("amg_matrix_free", dict(precond="amg", matrix_free=True)),
-                     ("jacobi_matrix_free", dict(precond="jacobi", matrix_free=True))):
+    all_variants = (("amg", dict(precond="amg")), ("amg_matrix_free", dict(precond="amg", matrix_free=True)),
+                    ("jacobi_matrix_free", dict(precond="jacobi", matrix_free=True)))
+    wanted = [v for v in args.three_d_variants.split(",") if v]
+    for name, kw in all_variants:
+        if name not in wanted:
+            continue
         sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, extrapolate=args.extrapolate, **kw)
         sa._xyz = xyz
         Ua, vmax, _ = project_field(sa, taylor_green_3d)
@@ -267,6 +274,7 @@ def three_d(args):
     s = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, precond="jacobi", extrapolate=args.extrapolate)
     s._xyz = xyz
     U, vmax, pinfo = project_field(s, taylor_green_3d)
+    dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
     t, its = timed_run(s, U, dt, steps, 2)
     d = s.diagnostics(U)
     ms_spmv, b_spmv = s.time_kernel(0, reps=50)
@@ -374,6 +382,9 @@ def main():
         sys.exit(2)
     import torch
     from inputs import double_shear_layer
+    if args.only_3d:
+        print(json.dumps({"three_d": three_d(args)}), flush=True)
+        return
     if args.copy_calib_mb > 0:
         n = args.copy_calib_mb * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda:0")

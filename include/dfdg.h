@@ -146,6 +146,12 @@ typedef struct {
 } dfdg_step_info;
 
 typedef struct {
+  int iterations[4];   /* PCG iterations of the four stage solves of dfdg_rk4_step */
+  double max_rel_residual;
+  int status;
+} dfdg_rk4_info;
+
+typedef struct {
   double energy;         /* 0.5 ||u_h||^2 */
   double enstrophy;      /* ||curl_h u_h||^2 (element-wise curl) */
   double max_div;        /* max |div u_h| over element quadrature points */
@@ -216,6 +222,17 @@ int dfdg_dg_residual(dfdg_ctx* ctx, const double* U_dev, double* L_dev);
 int dfdg_hdiv_mass_solve(dfdg_ctx* ctx, const double* F_dev, double* U_dev,
                          double* lambda_io_dev, dfdg_solve_info* info);
 int dfdg_rk3_step(dfdg_ctx* ctx, double* U_io_dev, double dt, dfdg_step_info* info);
+/* dfdg_rk4_step: one step of the classical four-stage RK4 (Sec. 4, Example 1b compares it
+ *   with TVD-RK3) in place on U_io_dev: k_i = M^{-1}L(u_i) (one residual and one facet
+ *   solve each), u_2 = u^n + dt/2 k_1, u_3 = u^n + dt/2 k_2, u_4 = u^n + dt k_3,
+ *   u^{n+1} = u^n + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4).
+ * dfdg_fe_step: one forward-Euler step u^{n+1} = u^n + dt M^{-1}L(u^n) in place (eq. (FE);
+ *   Example 5 steps this way).
+ * Each integrator warm-starts its stage solves from its own earlier steps: calling another
+ * integrator on the context (or dfdg_reset_history) starts from an empty history.
+ * dfdg_history_save/_restore cover TVD-RK3's history. */
+int dfdg_rk4_step(dfdg_ctx* ctx, double* U_io_dev, double dt, dfdg_rk4_info* info);
+int dfdg_fe_step(dfdg_ctx* ctx, double* U_io_dev, double dt, dfdg_solve_info* info);
 /* dfdg_rk3_step_stages: dfdg_rk3_step that also leaves the states entering the second
  *   and third stages in U1_dev and U2_dev (caller-owned, length n_broken, distinct from
  *   U_io_dev and from each other), for dfdg_rk3_step_vjp_stages. */

@@ -127,9 +127,26 @@ class Oracle:
         U2 = self.mass_solve(0.75 * MU + 0.25 * (M @ U1 + dt * self.L(U1)))
         return self.mass_solve(MU / 3.0 + 2.0 / 3.0 * (M @ U2 + dt * self.L(U2)))
 
-    def run(self, U, dt, steps, callback=None):
+    def rk4_step(self, U, dt):
+        """One step of the classical four-stage RK4 (Sec. 4, Example 1b) for M du/dt = L(u):
+        k_i = M^{-1} L(u_i) by the divergence-free mass inversion of L(u_i), u_1 = u^n,
+        u_2 = u^n + dt/2 k_1, u_3 = u^n + dt/2 k_2, u_4 = u^n + dt k_3,
+        u^{n+1} = u^n + dt/6 (k_1 + 2 k_2 + 2 k_3 + k_4)."""
+        k1 = self.mass_solve(self.L(U))
+        k2 = self.mass_solve(self.L(U + 0.5 * dt * k1))
+        k3 = self.mass_solve(self.L(U + 0.5 * dt * k2))
+        k4 = self.mass_solve(self.L(U + dt * k3))
+        return U + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+
+    def fe_step(self, U, dt):
+        """One forward-Euler step, eq. (FE): (u^{n+1}, v) = (u^n, v) + dt L(u^n)(v) for all v
+        in the divergence-free space (the time stepping of Example 5)."""
+        return self.mass_solve(self.M @ U + dt * self.L(U))
+
+    def run(self, U, dt, steps, callback=None, step=None):
+        step = self.rk3_step if step is None else step
         for n in range(steps):
-            U = self.rk3_step(U, dt)
+            U = step(U, dt)
             if callback is not None:
                 callback(n + 1, U)
         return U

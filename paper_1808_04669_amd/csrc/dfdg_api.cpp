@@ -22,6 +22,8 @@ struct dfdg_mesh {
   MeshHost m;
 };
 
+constexpr int kHistSlots = 7;
+
 struct dfdg_ctx {
   dfdg_params prm{};
   hipStream_t stream = nullptr;
@@ -37,7 +39,7 @@ struct dfdg_ctx {
   DevBsr A{};
   // work buffers
   double *Lbuf = nullptr, *q = nullptr, *gv = nullptr, *lamw = nullptr, *r = nullptr, *rb = nullptr, *z = nullptr,
-         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[6][kHistDepth] = {}, *evaltab = nullptr,
+         *p[2] = {nullptr, nullptr}, *Sp = nullptr, *Ustage = nullptr, *hist[kHistSlots][kHistDepth] = {}, *evaltab = nullptr,
          *partials = nullptr, *diagres = nullptr, *r64 = nullptr, *xpart = nullptr;
   // warm starts of the forward stages formed ahead: while the host waits for the end of
   // one stage's solve, the GPU forms the next stage's start value (it depends only on that
@@ -51,8 +53,12 @@ struct dfdg_ctx {
   PcgBufs pb{}, pb32{}, pbt{};  // FP64 PCG / refinement, FP32 inner PCG, kernel timing
   // adjoint buffers
   double *Ustages[3] = {nullptr, nullptr, nullptr}, *Ybar = nullptr, *Wbuf = nullptr;
-  // multiplier history per slot: 0-2 the forward stages, 3-5 the adjoint stage solves
-  int hist_count[6] = {0, 0, 0, 0, 0, 0};
+  // multiplier history per slot: 0-2 the forward stages (TVD-RK3; the first three of RK4, the
+  // single one of forward Euler), 3-5 the adjoint stage solves, 6 RK4's fourth stage
+  int hist_count[kHistSlots] = {};
+  // the forward integrator whose stage solves the history 0-2, 6 holds (0 none, 1 TVD-RK3,
+  // 2 RK4, 3 forward Euler): another one starts from an empty history
+  int integrator = 0;
   // multigrid preconditioner
   AmgHierarchy H;
   MgDev mg;
@@ -378,7 +384,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   ctx->p[1] = c.take<double>(nL);
   ctx->Sp = c.take<double>(nL);
   ctx->Ustage = c.take<double>(nU);
-  for (int s = 0; s < 6; ++s)
+  for (int s = 0; s < kHistSlots; ++s)
     for (int j = 0; j < kHistDepth; ++j) ctx->hist[s][j] = c.take<double>(nL);
   for (int s = 0; s < 3; ++s) ctx->gbuf[s] = c.take<double>(nL);
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
@@ -957,8 +963,19 @@ extern "C" int dfdg_dg_residual(dfdg_ctx* ctx, const double* U, double* L) {
 extern "C" int dfdg_reset_history(dfdg_ctx* ctx) {
   if (!ctx) return DFDG_E_INVALID_ARG;
   for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+  ctx->hist_count[6] = 0;
   invalidate_guesses(ctx);
   return DFDG_OK;
+}
+
+// The forward history belongs to one integrator; switching starts from an empty one.
+static void use_integrator(dfdg_ctx* ctx, int id) {
+  if (ctx->integrator != id) {
+    for (int i = 0; i < 3; ++i) ctx->hist_count[i] = 0;
+    ctx->hist_count[6] = 0;
+    invalidate_guesses(ctx);
+    ctx->integrator = id;
+  }
 }
 
 extern "C" int dfdg_reset_adjoint_history(dfdg_ctx* ctx) {
@@ -1000,6 +1017,7 @@ extern "C" int dfdg_history_restore(dfdg_ctx* ctx, const double* hist, const int
     ctx->hist_count[st] = counts[st];
   }
   invalidate_guesses(ctx);
+  ctx->integrator = 1;
   return DFDG_OK;
 }
 
@@ -1087,7 +1105,73 @@ extern "C" int dfdg_rk3_step(dfdg_ctx* ctx, double* U, double dt, dfdg_step_info
   NEED_BOUND(ctx);
   if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  use_integrator(ctx, 1);
   return rk3_core(ctx, U, dt, ctx->Ustage, ctx->Ustage, info);
+}
+
+// out = M^{-1} L(Us), warm-started from history slot s (one stage of RK4).
+static int pl_stage(dfdg_ctx* ctx, int s, const double* Us, double* out, dfdg_solve_info* inf) {
+  const bool mixed = ctx->prm.precision == DFDG_MIXED;
+  void* L = mixed ? (void*)ctx->L32 : (void*)ctx->Lbuf;
+  HIPC(el_residual(ctx, mixed, Us, L, ctx->stream));
+  bool cold;
+  int rc = stage_guess(ctx, s, &cold);
+  if (rc) return rc;
+  rc = mass_solve_impl(ctx, L, mixed, out, ctx->lamw, cold, inf, 0, 0, nullptr, 0, nullptr, 0);
+  if (rc) return rc;
+  stage_push(ctx, s);
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_rk4_step(dfdg_ctx* ctx, double* U, double dt, dfdg_rk4_info* info) {
+  NEED_BOUND(ctx);
+  if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  use_integrator(ctx, 2);
+  hipStream_t s = ctx->stream;
+  const long n = ctx->nU;
+  const size_t nb = n * sizeof(double);
+  double* K[4] = {ctx->Ustages[0], ctx->Ustages[1], ctx->Ustages[2], ctx->Ybar};
+  double* Ui = ctx->Wbuf;
+  const int slot[4] = {0, 1, 2, 6};
+  const double c[4] = {0.5, 0.5, 1.0, 0.0};  // u_{i+1} = u^n + c_i dt k_i
+  dfdg_solve_info si[4]{};
+  const double* Us = U;
+  for (int i = 0; i < 4; ++i) {
+    int rc = pl_stage(ctx, slot[i], Us, K[i], &si[i]);
+    if (rc) return rc;
+    if (i < 3) {
+      HIPC(hipMemcpyAsync(Ui, U, nb, hipMemcpyDeviceToDevice, s));
+      HIPC(launch_axpby(n, c[i] * dt, K[i], 1.0, Ui, s));
+      Us = Ui;
+    }
+  }
+  // u^{n+1} = u^n + dt/6 (k1 + 2 k2 + 2 k3 + k4)
+  const double w[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+  for (int i = 0; i < 4; ++i) HIPC(launch_axpby(n, w[i], K[i], 1.0, U, s));
+  dfdg_rk4_info st{};
+  st.status = DFDG_OK;
+  for (int i = 0; i < 4; ++i) {
+    st.iterations[i] = si[i].iterations;
+    st.max_rel_residual = std::max(st.max_rel_residual, si[i].rel_residual);
+    if (si[i].status != DFDG_OK) st.status = si[i].status;
+  }
+  if (info) *info = st;
+  if (st.status != DFDG_OK) return fail(ctx, st.status, "a stage's facet solve did not converge");
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_fe_step(dfdg_ctx* ctx, double* U, double dt, dfdg_solve_info* info) {
+  NEED_BOUND(ctx);
+  if (!U) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  use_integrator(ctx, 3);
+  dfdg_solve_info inf{};
+  int rc = rk_stage(ctx, 0, U, U, 0.0, 1.0, dt, U, &inf);  // U <- U + dt M^{-1} L(U)
+  if (rc) return rc;
+  if (info) *info = inf;
+  if (inf.status != DFDG_OK) return fail(ctx, inf.status, "the facet solve did not converge");
+  return DFDG_OK;
 }
 
 extern "C" int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U, double dt, double* U1, double* U2,
@@ -1096,6 +1180,7 @@ extern "C" int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U, double dt, double*
   if (!U || !U1 || !U2) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   if (U1 == U || U2 == U || U1 == U2) return fail(ctx, DFDG_E_INVALID_ARG, "U, U1 and U2 must be distinct buffers");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
+  use_integrator(ctx, 1);
   return rk3_core(ctx, U, dt, U1, U2, info);
 }
 
@@ -1172,6 +1257,7 @@ extern "C" int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un, double* Ybar, 
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
   if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
+  use_integrator(ctx, 1);
   double* U1 = ctx->Ustages[0];
   double* U2 = ctx->Ustages[1];
   dfdg_solve_info fw[2]{}, si[3]{};

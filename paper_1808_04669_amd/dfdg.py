@@ -57,6 +57,10 @@ class StepInfo(ctypes.Structure):
                 ("initial_rel_residual", ctypes.c_double * 3)]
 
 
+class Rk4Info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int * 4), ("max_rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
 class Diag(ctypes.Structure):
     _fields_ = [("energy", ctypes.c_double), ("enstrophy", ctypes.c_double), ("max_div", ctypes.c_double),
                 ("max_normal_jump", ctypes.c_double)]
@@ -87,6 +91,8 @@ _SIGS = {
     "dfdg_hdiv_mass_solve": (ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(SolveInfo)]),
     "dfdg_rk3_step": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
     "dfdg_rk3_step_stages": (ctypes.c_int, [_P, _P, ctypes.c_double, _P, _P, ctypes.POINTER(StepInfo)]),
+    "dfdg_rk4_step": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(Rk4Info)]),
+    "dfdg_fe_step": (ctypes.c_int, [_P, _P, ctypes.c_double, ctypes.POINTER(SolveInfo)]),
     "dfdg_reset_history": (ctypes.c_int, [_P]),
     "dfdg_reset_adjoint_history": (ctypes.c_int, [_P]),
     "dfdg_history_bytes": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_size_t)]),
@@ -307,6 +313,20 @@ class Solver:
         info = StepInfo()
         self._check(self._lib.dfdg_rk3_step(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(dt),
                                             ctypes.byref(info)))
+        return info
+
+    def rk4_step(self, U, dt):
+        """One classical RK4 step in place (dfdg_rk4_step)."""
+        info = Rk4Info()
+        self._check(self._lib.dfdg_rk4_step(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(dt),
+                                            ctypes.byref(info)))
+        return info
+
+    def fe_step(self, U, dt):
+        """One forward-Euler step in place (dfdg_fe_step)."""
+        info = SolveInfo()
+        self._check(self._lib.dfdg_fe_step(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(dt),
+                                           ctypes.byref(info)))
         return info
 
     def rk3_step_stages(self, U, dt, U1, U2):

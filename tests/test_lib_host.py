@@ -263,6 +263,7 @@ def test_binding_covers_the_entry_points():
     """Every hot-path entry point of the C ABI has its method on the Python binding."""
     methods = {"dfdg_project": "project", "dfdg_load_vector": "load_vector", "dfdg_dg_residual": "residual",
                "dfdg_hdiv_mass_solve": "mass_solve", "dfdg_rk3_step": "rk3_step",
+               "dfdg_rk4_step": "rk4_step", "dfdg_fe_step": "fe_step",
                "dfdg_rk3_step_stages": "rk3_step_stages", "dfdg_reset_history": "reset_history",
                "dfdg_reset_adjoint_history": "reset_adjoint_history", "dfdg_history_save": "history_save",
                "dfdg_history_restore": "history_restore", "dfdg_dg_residual_vjp": "residual_vjp",

@@ -55,6 +55,46 @@ def test_rk3_temporal_order():
     assert abs(rates[-1] - paper[-1]) < 0.2, (errs, rates)
 
 
+def _temporal_errors(step_name, ns):
+    xyz, per = periodic_split_square(4)
+    o = Oracle(xyz, per, 2, nu=0.02)
+    U0 = o.project(taylor_green_2d)
+    U0 = U0 + 0.5 * o.project(lambda x, y: (np.sin(2 * np.pi * y), 0 * x))
+    tend = 0.2
+    step = getattr(o, step_name)
+    ref = o.run(U0, tend / 512, 512, step=o.rk4_step)
+    errs = []
+    for n in ns:
+        d = o.run(U0, tend / n, n, step=step) - ref
+        errs.append(np.sqrt(d @ (o.M @ d)))
+    return np.array(errs)
+
+
+def test_rk4_temporal_order():
+    """Sec. 4 Example 1b / Table 2: the classical RK4 converges at fourth order in time."""
+    with open(os.path.join(GOLDEN, "table2_eoc.json")) as f:
+        paper = json.load(f)["rk4_eoc"]
+    errs = _temporal_errors("rk4_step", (8, 16, 32))
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert abs(rates[-1] - paper[-1]) < 0.2, (errs, rates)
+
+
+def test_forward_euler_first_order_and_rk_consistency():
+    """Forward Euler (eq. (FE), Example 5) converges at first order; one forward-Euler step
+    equals the first TVD-RK3 stage, and all three integrators agree to their orders."""
+    errs = _temporal_errors("fe_step", (64, 128, 256))
+    rates = np.log2(errs[:-1] / errs[1:])
+    assert abs(rates[-1] - 1.0) < 0.1, (errs, rates)
+    xyz, per = periodic_split_square(3)
+    o = Oracle(xyz, per, 2, nu=0.01)
+    U = o.project(taylor_green_2d)
+    dt = 1e-3
+    stage1 = o.mass_solve(o.M @ U + dt * o.L(U))
+    assert np.abs(o.fe_step(U, dt) - stage1).max() == 0.0
+    a, b = o.rk3_step(U, dt), o.rk4_step(U, dt)
+    assert np.abs(a - b).max() < 1e-7 * np.abs(a).max()
+
+
 def test_inviscid_energy_non_increasing():
     """Sec. 2.2 energy stability; Sec. 4 Example 2: energy decays monotonically."""
     xyz, per = periodic_split_square(8)
