@@ -116,7 +116,10 @@ def make_solver(N, k, precision, args, order=None, rtol=None, nu=0.0, **kw):
     return s
 
 
-def timed_run(s, U, dt, steps, warmup):
+def timed_run(s, U, dt, steps, warmup, start_residuals=None):
+    """Times `steps` TVD-RK3 steps after `warmup` untimed ones; returns the seconds and the
+    PCG iterations per stage. The stages' start-value relative residuals are appended to
+    `start_residuals` when given."""
     import torch
     its = []
     for _ in range(warmup):
@@ -126,6 +129,8 @@ def timed_run(s, U, dt, steps, warmup):
     for _ in range(steps):
         info = s.rk3_step(U, dt)
         its.append(list(info.iterations))
+        if start_residuals is not None:
+            start_residuals.extend(info.initial_rel_residual)
     torch.cuda.synchronize()
     return time.perf_counter() - t0, np.array(its)
 
@@ -203,33 +208,45 @@ def mixed_vs_fp64(args):
     import torch
     from inputs import double_shear_layer
     N, k, steps = args.mixed_N, args.mixed_k, args.mixed_steps
-    res = {}
-    for prec in ("fp64", "fp64_plain", "mixed"):
-        kw = dict(ir_rtol=args.mixed_ir_rtol, inner_rtol=args.mixed_inner_rtol) if prec == "mixed" else {}
+    res, start_res = {}, {}
+    for prec in ("fp64", "fp64_plain", "mixed", "mixed_restarted"):
+        kw = dict(ir_rtol=args.mixed_ir_rtol, inner_rtol=args.mixed_inner_rtol) if prec.startswith("mixed") else {}
         if prec == "fp64_plain":
             kw["mg_fp32"] = False
-        s = make_solver(N, k, "fp64" if prec == "fp64_plain" else prec, args, rtol=args.mixed_ir_rtol, **kw)
+        if prec == "mixed_restarted":
+            kw["mixed_solver"] = "restarted"
+        s = make_solver(N, k, "mixed" if prec.startswith("mixed") else "fp64", args, rtol=args.mixed_ir_rtol, **kw)
         U, vmax, _ = project_field(s, double_shear_layer)
         dt = 0.1 / N / (k ** 2 * vmax)
-        t, its = timed_run(s, U, dt, steps, 2)
+        r0 = []
+        t, its = timed_run(s, U, dt, steps, 2, r0)
+        start_res[prec] = float(np.exp(np.mean(np.log(np.maximum(r0, 1e-300)))))
         res[prec] = (t, its, U, s.n_bdm, s.diagnostics(U), s.setup_seconds)
         del s
         torch.cuda.empty_cache()
     t64, it64, U64, n_u, d64, su64 = res["fp64"]
     tpl, itpl, _, _, _, _ = res["fp64_plain"]
     tm, itm, Um, _, dm, sum_ = res["mixed"]
+    tr, itr, Ur, _, dr, _ = res["mixed_restarted"]
     return {"workload": f"double shear layer {N}x{N} split mesh, BDM_{k}, {steps} TVD-RK3 steps, "
-                        f"FP64 PCG rtol {args.mixed_ir_rtol:g} vs mixed (FP32 residual and inner PCG, "
-                        f"inner rtol {args.mixed_inner_rtol:g}, FP64 refinement to {args.mixed_ir_rtol:g})",
+                        f"FP64 PCG rtol {args.mixed_ir_rtol:g} vs mixed (FP32 residual, FP32 inner iterations, "
+                        f"FP64 refinement to {args.mixed_ir_rtol:g})",
             "value": n_u * 3 * steps / tm, "fp64_value": n_u * 3 * steps / t64, "unit": "velocity DOF-stages/s",
             "speedup_vs_fp64": t64 / tm, "rel_l2_vs_fp64_gpu": ((Um - U64).norm() / U64.norm()).item(),
             "fp64_plain_value": n_u * 3 * steps / tpl, "speedup_vs_fp64_plain": tpl / tm,
-            "note": ("fp64: FP64 PCG with the multigrid V-cycle in FP32 (the benchmark path); "
-                     "fp64_plain: everything in FP64"),
+            "restarted_value": n_u * 3 * steps / tr, "restarted_speedup_vs_fp64_plain": tpl / tr,
+            "restarted_rel_l2_vs_fp64_gpu": ((Ur - U64).norm() / U64.norm()).item(),
+            "note": ("mixed: FP32 residual, FP64 PCG refining to the FP64 tolerance with the multigrid "
+                     "cycle in FP32 (FP16 S on the finest level) as the inner FP32 iterations; "
+                     "mixed_restarted: FP32 residual, FP32 inner PCG on an FP32 S to inner rtol, "
+                     "restarted FP64 refinement; fp64: FP64 residual, FP64 PCG with the FP32 cycle "
+                     "(the benchmark path); fp64_plain: everything in FP64"),
             "iterations_per_stage": {"fp64": float(it64.mean()), "fp64_plain": float(itpl.mean()),
-                                     "mixed_inner_total": float(itm.mean())},
-            "max_div": {"fp64": d64["max_div"], "mixed": dm["max_div"]},
-            "max_normal_jump": {"fp64": d64["max_normal_jump"], "mixed": dm["max_normal_jump"]},
+                                     "mixed": float(itm.mean()), "mixed_restarted_inner_total": float(itr.mean())},
+            "max_div": {"fp64": d64["max_div"], "mixed": dm["max_div"], "mixed_restarted": dr["max_div"]},
+            "max_normal_jump": {"fp64": d64["max_normal_jump"], "mixed": dm["max_normal_jump"],
+                                "mixed_restarted": dr["max_normal_jump"]},
+            "start_rel_residual_geomean": start_res,
             "setup_s": {"fp64": su64, "mixed": sum_}}
 
 

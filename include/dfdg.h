@@ -91,7 +91,7 @@ typedef struct {
                         correction on the coarser levels; coarse space spanned by the
                         constant multiplier; built on the host at context creation) */
   double ir_rtol;    /* MIXED: outer FP64 refinement target (relative residual) */
-  double inner_rtol; /* MIXED: FP32 inner PCG reduction per refinement step */
+  double inner_rtol; /* MIXED, mixed_solver = 0: FP32 inner PCG reduction per refinement step */
   int extrapolate;   /* rk3_step: 0 = warm start from the last same-stage multiplier,
                         1..4 = polynomial extrapolation of that order in time from the
                         last extrapolate+1 steps, DFDG_EXTRAPOLATE_ADAPTIVE = the order
@@ -117,6 +117,13 @@ typedef struct {
                         sum_T C_T W_T C_T^T p from the element data (two passes, no matrix
                         read) instead of reading the assembled S; 0 = assembled S (default).
                         The multigrid smoothing still reads S.  Triangle meshes: must be 0. */
+  int mixed_solver;  /* MIXED facet solves (the residual is FP32 in both):
+                        1 = Krylov refinement (default): FP64 PCG iterations (FP64 S, vectors,
+                        dot products, stopping test at ir_rtol) whose preconditioner, the
+                        multigrid cycle, runs in FP32 (FP16 S on the finest level with
+                        mg_fine_fp16); with Jacobi the FP32 part is the residual alone;
+                        0 = restarted refinement: FP32 PCG on an FP32 copy of S to inner_rtol,
+                        FP64 refinement residual g - S lambda, restarted until ir_rtol. */
 } dfdg_params;
 
 typedef struct {
@@ -129,8 +136,10 @@ typedef struct {
 } dfdg_sizes;
 
 typedef struct {
-  int iterations;      /* PCG iterations (FP64) or total inner FP32 iterations (MIXED) */
-  int refinements;     /* MIXED: FP64 refinement steps; FP64: 0 */
+  int iterations;      /* PCG iterations (FP64, and MIXED with the Krylov refinement) or the
+                          total inner FP32 iterations (MIXED, restarted refinement) */
+  int refinements;     /* MIXED: FP64 refinement steps (= the FP64 iterations of the Krylov
+                          refinement); FP64: 0 */
   double rel_residual; /* final ||g - S lambda|| / ||g|| (FP64 recomputed for MIXED) */
   int status;          /* DFDG_OK, DFDG_E_NOT_CONVERGED, ... */
   double initial_rel_residual; /* ||g - S lambda_0|| / ||g|| of the start value (0 for a

@@ -182,6 +182,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->mg_fine_fp16 = 1;
   p->facet_blocks = 0;
   p->matrix_free = 0;
+  p->mixed_solver = 1;
 }
 
 static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
@@ -208,6 +209,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
   if (p->facet_blocks < 0 || p->facet_blocks > 1024) { e = "facet_blocks must be in 0..1024"; return -1; }
   if (p->matrix_free != 0 && p->matrix_free != 1) { e = "matrix_free must be 0 or 1"; return -1; }
+  if (p->mixed_solver != 0 && p->mixed_solver != 1) { e = "mixed_solver must be 0 or 1"; return -1; }
   return 0;
 }
 
@@ -798,11 +800,16 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
   dfdg_solve_info inf{};
   const bool amg = ctx->prm.precond == DFDG_AMG;
   const int pc = amg ? 2 : (bj ? 1 : 0);
-  if (ctx->prm.precision == DFDG_FP64) {
+  // the FP64 PCG: the FP64 path, and the mixed form's Krylov refinement (mixed_solver = 1),
+  // whose FP64 outer iterations refine to ir_rtol with the FP32 multigrid cycle as the inner
+  // FP32 work
+  const bool krylov = ctx->prm.precision == DFDG_FP64 || ctx->prm.mixed_solver == 1;
+  if (krylov) {
     const PcgBufs& pb = ctx->pb;
-    HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
+    const bool mixed = ctx->prm.precision == DFDG_MIXED;
+    HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, mixed ? ctx->prm.ir_rtol : ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
     HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
-    const bool c32 = ctx->prm.mg_fp32 != 0;
+    const bool c32 = mixed || ctx->prm.mg_fp32 != 0;
     const bool fused = amg && ctx->mg.nlev >= 2;
     if (amg) {
       if (c32) HIPC((launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
@@ -830,7 +837,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, ctx->graph64, &ctx->iters_hint[0], fin);
     if (rc) return rc;
     inf.iterations = fin.iters;
-    inf.refinements = 0;
+    inf.refinements = mixed ? fin.iters : 0;  // each outer FP64 iteration refines once
     inf.rel_residual = fin.gg > 0 ? std::sqrt(std::max(fin.rr, 0.0) / fin.gg) : 0.0;
     inf.initial_rel_residual = (fin.gg > 0 && !fin.zero_rhs) ? std::sqrt(std::max(fin.rr0, 0.0) / fin.gg) : 0.0;
     inf.status = status_of(fin.done);

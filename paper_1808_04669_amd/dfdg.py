@@ -35,7 +35,8 @@ class Params(ctypes.Structure):
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int),
                 ("precond", ctypes.c_int), ("ir_rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int), ("mg_fp32", ctypes.c_int),
-                ("mg_fine_fp16", ctypes.c_int), ("facet_blocks", ctypes.c_int), ("matrix_free", ctypes.c_int)]
+                ("mg_fine_fp16", ctypes.c_int), ("facet_blocks", ctypes.c_int), ("matrix_free", ctypes.c_int),
+                ("mixed_solver", ctypes.c_int)]
 
 
 class Sizes(ctypes.Structure):
@@ -193,7 +194,8 @@ class Solver:
 
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
                  precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, mg_fp32=True,
-                 mg_fine_fp16=True, facet_blocks=0, matrix_free=False, device="cuda:0", stream=None):
+                 mg_fine_fp16=True, facet_blocks=0, matrix_free=False, mixed_solver="krylov", device="cuda:0",
+                 stream=None):
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
@@ -213,6 +215,7 @@ class Solver:
         p.mg_fine_fp16 = 1 if mg_fine_fp16 else 0
         p.facet_blocks = int(facet_blocks)
         p.matrix_free = 1 if matrix_free else 0
+        p.mixed_solver = {"krylov": 1, "restarted": 0}[mixed_solver]
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()

@@ -16,13 +16,15 @@ def _log(*a):
 
 
 # ---------------------------------------------------------------------------------------
-# mixed precision: FP32 residual and inner PCG, FP64 refinement / recovery
+# mixed precision: FP32 residual and inner iterations, FP64 refinement / recovery; both
+# refinements (Krylov: FP64 PCG with the FP32 cycle; restarted: FP32 PCG + FP64 refinement)
 # ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("solver", ["krylov", "restarted"])
 @pytest.mark.parametrize("k,N,precond", [(1, 6, "jacobi"), (2, 8, "jacobi"), (3, 5, "jacobi"), (2, 16, "amg"),
                                          (3, 10, "amg")])
-def test_mixed_mass_solve_parity(k, N, precond):
+def test_mixed_mass_solve_parity(k, N, precond, solver):
     orc, s, _, _ = make_pair(N, k, order="random", seed=1, precision="mixed", ir_rtol=1e-11, inner_rtol=1e-3,
-                             precond=precond)
+                             precond=precond, mixed_solver=solver)
     coef = random_broken_poly(s.T, k, seed=7)
     F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
     U, info = s.mass_solve(F)
@@ -38,10 +40,11 @@ def test_mixed_mass_solve_parity(k, N, precond):
     assert d["max_div"] < 1e-11 * np.sqrt(d["enstrophy"])
 
 
+@pytest.mark.parametrize("solver", ["krylov", "restarted"])
 @pytest.mark.parametrize("k,N,steps,precond", [(2, 8, 6, "jacobi"), (3, 6, 4, "jacobi"), (2, 16, 4, "amg")])
-def test_mixed_trajectory_within_1e6_of_oracle(k, N, steps, precond):
+def test_mixed_trajectory_within_1e6_of_oracle(k, N, steps, precond, solver):
     orc, s, _, _ = make_pair(N, k, order="morton", precision="mixed", ir_rtol=1e-10, inner_rtol=1e-3,
-                             precond=precond)
+                             precond=precond, mixed_solver=solver)
     U0 = orc.project(lambda x, y: double_shear_layer(x, y, sharpness=20.0))
     U = transfer(orc, U0, s)
     dt = 0.1 / N / k ** 2

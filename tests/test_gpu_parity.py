@@ -158,14 +158,16 @@ def _constant_multiplier(s, xyz):
 
 
 @pytest.mark.parametrize("precond", ["jacobi", "amg"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_restarted"])
 def test_graph_replay_equals_eager_launches(precond, precision):
     """PCG iterations replayed from captured HIP graphs give the eager result bit for bit,
     over several solves and RK3 steps with other work and synchronisations in between."""
     outs = []
     for graphs in (False, True):
+        kw = dict(precision="mixed", mixed_solver="restarted") if precision == "mixed_restarted" else dict(
+            precision=precision)
         orc, s, _, _ = make_pair(12, 2, nu=1e-3, oracle=(not graphs), order="morton", precond=precond,
-                                 precision=precision, graphs=graphs)
+                                 graphs=graphs, **kw)
         if not graphs:
             U0o = orc.project(RandomStreamField(seed=2, kmax=4))
             U0 = transfer(orc, U0o, s)
