@@ -321,7 +321,8 @@ static void carve(dfdg_ctx* ctx, char* base) {
   DevGeo& g = ctx->g;
   g.T = (int)T;
   g.E = (int)E;
-  g.fgrid = facet_grid_size((int)E, ctx->prm.facet_blocks);
+  // one thread per facet row, or two for split rows (facet_split)
+  g.fgrid = facet_grid_size((int)(E * facet_split((int)NF, d3slots(ctx))), ctx->prm.facet_blocks);
   const long dm = ctx->dim, nfac = dm + 1;
   g.Jinv = c.take<double>(dm * dm * T);
   g.detJ = c.take<double>(T);

@@ -29,6 +29,15 @@ __device__ inline int xcd_block() {
   return x * (G >> 3) + min(x, G & 7) + (b >> 3);
 }
 
+// A read-only table (reference-element matrices) seen through the constant address
+// space: reads at wave-uniform indices then compile to scalar loads into SGPRs.  Through
+// a plain pointer the compiler cannot prove that the kernel's own stores leave the table
+// alone, and loads it into vector registers of every lane instead.
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
 // Reductions without atomics or fences: a kernel writes one partial per block; the next
 // kernel on the stream (after the kernel boundary has made them visible) sums all partials
 // redundantly in every block, in a fixed order, so every block gets the same bits.

@@ -46,6 +46,9 @@ constexpr int kMaxK3 = 2;
 constexpr int kSlots3 = 7;
 // 32-bit words of a facet row of S in FP16, two values per word
 __host__ __device__ constexpr int nPairs(int NF, int NS) { return (NS * NF * NF + 1) / 2; }
+// Threads per facet row in the facet-system kernels: 2 for the 252-value rows of
+// tetrahedral meshes at k = 2 (each thread takes half the row's outputs), else 1.
+__host__ __device__ constexpr int facet_split(int NF, int NS) { return (NF % 2 == 0 && NS * NF * NF > 128) ? 2 : 1; }
 constexpr int kMaxEvalPts = 1024;
 
 // ---- reference tabulations (host, FP64) ---------------------------------------------

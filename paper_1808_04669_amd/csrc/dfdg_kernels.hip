@@ -643,72 +643,142 @@ struct HalfRow {
   }
 };
 
-// As spmv_row in FP32 for the multigrid smoothing on the finest level: S is read from its
-// FP16 copy (scaled by scale16) when there is one, else from the FP32 copy.
-template <int NF, int NS, typename V, typename Getter>
-__device__ inline void spmv_row_mg(const DevBsr& A, int E, int F, Getter get, V (&y)[NF]) {
+// Facet rows of tetrahedral meshes (six modes, seven slots: 252 values) are shared by two
+// threads, each computing three of the row's six outputs: half the registers per thread,
+// twice the threads in flight, and the pair's column gathers fall on the same addresses.
+// Rows of triangle meshes (at most 80 values) keep one thread each.  Thread unit u works
+// on row u / kSplit and its outputs [NA (u % kSplit), NA (u % kSplit + 1)), NA = NF / kSplit.
+template <int NF, int NS>
+constexpr int kSplit = facet_split(NF, NS);
+
+__device__ inline float half_at(const uint32_t* w, int j) {
+  const uint32_t v = w[j >> 1];
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)((j & 1) ? (v >> 16) : (v & 0xffffu)));
+}
+
+// Outputs [a0, a0 + NA) of row F of S x in the multigrid's arithmetic V (get(c, x_c) gives
+// the column facet's vector): S is read from its FP16 copy (scaled by scale16) when V is
+// float and there is one, else from the FP32 (V float) or FP64 copy.  For split rows the
+// thread's part of slot s is the NA NF values from (s NF + a0) NF on: whole words of the
+// FP16 copy, since NF is even.
+template <int NF, int NS, int NA, typename V, typename Getter>
+__device__ inline void spmv_part_mg(const DevBsr& A, int E, int F, int a0, Getter get, V (&y)[NA]) {
+#pragma unroll
+  for (int a = 0; a < NA; ++a) y[a] = 0;
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      HalfRow<NF, NS> m;
-      m.load(A, E, F);
+      if constexpr (NA < NF) {
+        static_assert(NF % 2 == 0, "split rows need whole FP16 words per part");
+        constexpr int kW = NA * NF / 2;
 #pragma unroll
-      for (int a = 0; a < NF; ++a) y[a] = 0;
+        for (int s = 0; s < NS; ++s) {
+          const uint32_t* __restrict__ p = A.vals16 + (size_t)((s * NF * NF + a0 * NF) / 2) * E + F;
+          uint32_t w[kW];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        const int c = A.cols[(size_t)s * E + F];
-        V xc[NF];
-        get(c, xc);
+          for (int j = 0; j < kW; ++j) w[j] = p[(size_t)j * E];
+          const int c = A.cols[(size_t)s * E + F];
+          V xc[NF];
+          get(c, xc);
 #pragma unroll
-        for (int a = 0; a < NF; ++a)
+          for (int a = 0; a < NA; ++a)
 #pragma unroll
-          for (int b = 0; b < NF; ++b) y[a] += (V)m.at((s * NF + a) * NF + b) * xc[b];
+            for (int b = 0; b < NF; ++b) y[a] += (V)half_at(w, a * NF + b) * xc[b];
+        }
+      } else {
+        HalfRow<NF, NS> m;
+        m.load(A, E, F);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int c = A.cols[(size_t)s * E + F];
+          V xc[NF];
+          get(c, xc);
+#pragma unroll
+          for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int b = 0; b < NF; ++b) y[a] += (V)m.at((s * NF + a) * NF + b) * xc[b];
+        }
       }
 #pragma unroll
-      for (int a = 0; a < NF; ++a) y[a] *= A.scale16;
+      for (int a = 0; a < NA; ++a) y[a] *= A.scale16;
       return;
     }
   }
-  spmv_row<NF, NS, V, V>(A, E, F, get, y);
+  const V* vals = (sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int c = A.cols[(size_t)s * E + F];
+    V xc[NF];
+    get(c, xc);
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NF; ++b) y[a] += vals[(((size_t)s * NF + a0 + a) * NF + b) * E + F] * xc[b];
+  }
 }
 
-// Two products of one row at once, y1 = S u and y2 = S w (get(c, u_c, w_c) gives the
-// column facet's two vectors), with the multigrid's copy of S as in spmv_row_mg.
-template <int NF, int NS, typename V, typename Getter>
-__device__ inline void spmv_row_mg2(const DevBsr& A, int E, int F, Getter get, V (&y1)[NF], V (&y2)[NF]) {
-  // value(j) gives entry j of the row's [5][NF][NF] sequence
-  auto rowloop = [&](auto value, V scale) {
+// Two products of one row part at once, y1 = S u and y2 = S w (get(c, u_c, w_c) gives the
+// column facet's two vectors), with the multigrid's copy of S as in spmv_part_mg.
+template <int NF, int NS, int NA, typename V, typename Getter>
+__device__ inline void spmv_part_mg2(const DevBsr& A, int E, int F, int a0, Getter get, V (&y1)[NA],
+                                     V (&y2)[NA]) {
 #pragma unroll
-    for (int a = 0; a < NF; ++a) y1[a] = y2[a] = 0;
+  for (int a = 0; a < NA; ++a) y1[a] = y2[a] = 0;
+  // value(s, a, b) gives entry (a0 + a, b) of block s of the row
+  auto rowloop = [&](auto value) {
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       const int c = A.cols[(size_t)s * E + F];
       V uc[NF], wc[NF];
       get(c, uc, wc);
 #pragma unroll
-      for (int a = 0; a < NF; ++a)
+      for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < NF; ++b) {
-          const V m = value((s * NF + a) * NF + b);
+          const V m = value(s, a, b);
           y1[a] += m * uc[b];
           y2[a] += m * wc[b];
         }
     }
-#pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      y1[a] *= scale;
-      y2[a] *= scale;
-    }
   };
   if constexpr (sizeof(V) == 4) {
     if (A.vals16) {
-      HalfRow<NF, NS> m;
-      m.load(A, E, F);
-      rowloop([&](int j) { return (V)m.at(j); }, (V)A.scale16);
+      if constexpr (NA < NF) {
+        static_assert(NF % 2 == 0, "split rows need whole FP16 words per part");
+        constexpr int kW = NA * NF / 2;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const uint32_t* __restrict__ p = A.vals16 + (size_t)((s * NF * NF + a0 * NF) / 2) * E + F;
+          uint32_t w[kW];
+#pragma unroll
+          for (int j = 0; j < kW; ++j) w[j] = p[(size_t)j * E];
+          const int c = A.cols[(size_t)s * E + F];
+          V uc[NF], wc[NF];
+          get(c, uc, wc);
+#pragma unroll
+          for (int a = 0; a < NA; ++a)
+#pragma unroll
+            for (int b = 0; b < NF; ++b) {
+              const V m = (V)half_at(w, a * NF + b);
+              y1[a] += m * uc[b];
+              y2[a] += m * wc[b];
+            }
+        }
+      } else {
+        HalfRow<NF, NS> m;
+        m.load(A, E, F);
+        rowloop([&](int s, int a, int b) { return (V)m.at((s * NF + a) * NF + b); });
+      }
+      const V sc16 = (V)A.scale16;
+#pragma unroll
+      for (int a = 0; a < NA; ++a) {
+        y1[a] *= sc16;
+        y2[a] *= sc16;
+      }
       return;
     }
   }
   const V* vals = (sizeof(V) == 8) ? (const V*)A.vals : (const V*)A.vals32;
-  rowloop([&](int j) { return vals[(size_t)j * E + F]; }, (V)1);
+  rowloop([&](int s, int a, int b) { return vals[(((size_t)s * NF + a0 + a) * NF + b) * E + F]; });
 }
 
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
@@ -777,9 +847,12 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   partials_load<2>(rz_prev, G, true, q1);
   partials_load<2>(rz_prev2, G, it >= 2, q2);
   const M* vals = (sizeof(M) == 8) ? (const M*)A.vals : (const M*)A.vals32;
-  auto row = [&](int F, V (&sz)[NF], V (&sp)[NF]) {
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
+  // outputs [a0, a0 + NA) of row F
+  auto row = [&](int u, V (&sz)[NA], V (&sp)[NA]) {
+    const int F = u / SPL, a0 = (u % SPL) * NA;
 #pragma unroll
-    for (int a = 0; a < NF; ++a) sz[a] = sp[a] = 0;
+    for (int a = 0; a < NA; ++a) sz[a] = sp[a] = 0;
 #pragma unroll
     for (int s5 = 0; s5 < NS; ++s5) {
       const int c = A.cols[(size_t)s5 * E + F];
@@ -790,18 +863,18 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
         pc[bb] = p_old[(size_t)c * NF + bb];
       }
 #pragma unroll
-      for (int a = 0; a < NF; ++a)
+      for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int bb = 0; bb < NF; ++bb) {
-          const V m = (V)vals[(((size_t)s5 * NF + a) * NF + bb) * E + F];
+          const V m = (V)vals[(((size_t)s5 * NF + a0 + a) * NF + bb) * E + F];
           sz[a] += m * zc[bb];
           sp[a] += m * pc[bb];
         }
     }
   };
-  const int F0 = xcd_block() * blockDim.x + threadIdx.x;
-  V sz[NF], sp[NF];
-  if (F0 < E) row(F0, sz, sp);
+  const int u0 = xcd_block() * blockDim.x + threadIdx.x;
+  V sz[NA], sp[NA];
+  if (u0 < E * SPL) row(u0, sz, sp);
   double t1[2];
   partials_sum<2>(q1, G, t1);
   double beta = 0;
@@ -824,11 +897,12 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   if (status != PCG_RUNNING) return;
   const V b = (V)beta;
   double v[1] = {0};
-  for (int F = F0; F < E; F += G * blockDim.x) {
-    if (F != F0) row(F, sz, sp);
+  for (int u = u0; u < E * SPL; u += G * blockDim.x) {
+    if (u != u0) row(u, sz, sp);
+    const int F = u / SPL, a0 = (u % SPL) * NA;
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      const size_t o = (size_t)F * NF + a;
+    for (int a = 0; a < NA; ++a) {
+      const size_t o = (size_t)F * NF + a0 + a;
       const V pn = z[o] + b * p_old[o];
       const V y = sz[a] + b * sp[a];
       p_new[o] = pn;
@@ -988,15 +1062,17 @@ __global__ __launch_bounds__(kBlk) void k_mg0_pre(DevGeo g, DevBsr A, const VB* 
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
-    V y[NF];
-    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
+  for (int u = xcd_block() * blockDim.x + threadIdx.x; u < E * SPL; u += gridDim.x * blockDim.x) {
+    const int F = u / SPL, a0 = (u % SPL) * NA;
+    V y[NA];
+    spmv_part_mg<NF, NS, NA, V>(A, E, F, a0, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = dinv[(size_t)c * NF + q] * (V)b[(size_t)c * NF + q] * ith;
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      const size_t o = (size_t)F * NF + a;
+    for (int a = 0; a < NA; ++a) {
+      const size_t o = (size_t)F * NF + a0 + a;
       const V bo = (V)b[o];
       const V x1 = dinv[o] * bo * ith;
       if (live) x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - y[a]);
@@ -1009,15 +1085,17 @@ __global__ __launch_bounds__(kBlk) void k_mg0_resid(DevGeo g, DevBsr A, const VB
                                                     const V* __restrict__ x, V* __restrict__ r, const PcgScalars* sc) {
   const bool live = sc->done == PCG_RUNNING;  // tested before the stores only
   const int E = g.E;
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
-    V y[NF];
-    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
+  for (int u = xcd_block() * blockDim.x + threadIdx.x; u < E * SPL; u += gridDim.x * blockDim.x) {
+    const int F = u / SPL, a0 = (u % SPL) * NA;
+    V y[NA];
+    spmv_part_mg<NF, NS, NA, V>(A, E, F, a0, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x[(size_t)c * NF + q];
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a)
-      if (live) r[(size_t)F * NF + a] = (V)b[(size_t)F * NF + a] - y[a];
+    for (int a = 0; a < NA; ++a)
+      if (live) r[(size_t)F * NF + a0 + a] = (V)b[(size_t)F * NF + a0 + a] - y[a];
   }
 }
 
@@ -1029,15 +1107,17 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post1(DevGeo g, DevBsr A, const VB
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th);
   const int E = g.E;
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
-    V y[NF];
-    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
+  for (int u = xcd_block() * blockDim.x + threadIdx.x; u < E * SPL; u += gridDim.x * blockDim.x) {
+    const int F = u / SPL, a0 = (u % SPL) * NA;
+    V y[NA];
+    spmv_part_mg<NF, NS, NA, V>(A, E, F, a0, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x3[(size_t)c * NF + q];
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      const size_t o = (size_t)F * NF + a;
+    for (int a = 0; a < NA; ++a) {
+      const size_t o = (size_t)F * NF + a0 + a;
       const V dd = dinv[o] * ((V)b[o] - y[a]) * ith;
       if (live) {
         d[o] = dd;
@@ -1065,16 +1145,18 @@ __global__ __launch_bounds__(kBlk) void k_mg0_post2(DevGeo g, DevBsr A, const VB
   const V* dinv = bsr_dinv<NF, V>(A);
   const V c1 = (V)cb.c1, c2 = (V)cb.c2;
   const int E = g.E;
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
   double v[1] = {0};
-  for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
-    V y[NF];
-    spmv_row_mg<NF, NS, V>(A, E, F, [&](int c, V (&xc)[NF]) {
+  for (int u = xcd_block() * blockDim.x + threadIdx.x; u < E * SPL; u += gridDim.x * blockDim.x) {
+    const int F = u / SPL, a0 = (u % SPL) * NA;
+    V y[NA];
+    spmv_part_mg<NF, NS, NA, V>(A, E, F, a0, [&](int c, V (&xc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) xc[q] = x4[(size_t)c * NF + q];
     }, y);
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      const size_t o = (size_t)F * NF + a;
+    for (int a = 0; a < NA; ++a) {
+      const size_t o = (size_t)F * NF + a0 + a;
       const V zz = x4[o] + c1 * d[o] + c2 * dinv[o] * ((V)b[o] - y[a]);
       if (live) z[o] = (VB)zz;
       v[0] += (double)b[o] * (double)(VB)zz;
@@ -1274,8 +1356,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   partials_load<1>(pq, G, true, q2);
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
-  auto row = [&](int F, V (&su)[NF], V (&sw)[NF]) {
-    spmv_row_mg2<NF, NS, V>(A, E, F, [&](int c, V (&uc)[NF], V (&wc)[NF]) {
+  constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
+  auto row = [&](int u, V (&su)[NA], V (&sw)[NA]) {
+    spmv_part_mg2<NF, NS, NA, V>(A, E, u / SPL, (u % SPL) * NA, [&](int c, V (&uc)[NF], V (&wc)[NF]) {
 #pragma unroll
       for (int q = 0; q < NF; ++q) {
         const size_t o = (size_t)c * NF + q;
@@ -1285,9 +1368,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
       }
     }, su, sw);
   };
-  const int F0 = xcd_block() * blockDim.x + threadIdx.x;
-  V su[NF], sw[NF];
-  if (F0 < E) row(F0, su, sw);
+  const int u0 = xcd_block() * blockDim.x + threadIdx.x;
+  V su[NA], sw[NA];
+  if (u0 < E * SPL) row(u0, su, sw);
   double t1[2], t2[1];
   partials_sum<2>(q1, G, t1);
   partials_sum<1>(q2, G, t2);
@@ -1301,11 +1384,12 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   const VB alpha = (VB)(t1[0] / t2[0]);
   const V alv = (V)alpha;
   double v[2] = {0, 0};
-  for (int F = F0; F < E; F += G * blockDim.x) {
-    if (F != F0) row(F, su, sw);
+  for (int u = u0; u < E * SPL; u += G * blockDim.x) {
+    if (u != u0) row(u, su, sw);
+    const int F = u / SPL, a0 = (u % SPL) * NA;
 #pragma unroll
-    for (int a = 0; a < NF; ++a) {
-      const size_t o = (size_t)F * NF + a;
+    for (int a = 0; a < NA; ++a) {
+      const size_t o = (size_t)F * NF + a0 + a;
       x[o] += alpha * p[o];
       const VB rn = r_old[o] - alpha * Sp[o];
       r_new[o] = rn;

@@ -216,6 +216,7 @@ template <int K>
 __device__ inline void apply_W3(double (&y)[3][nP3(K)], const double (&Ji)[3][3], const double* __restrict__ G, int T,
                                 int t, const double* __restrict__ Dh) {
   constexpr int P = nP3(K), NP = nPp3(K);
+  const auto Dc = cst(Dh);
   double d[NP];
 #pragma unroll
   for (int j = 0; j < NP; ++j) {
@@ -226,7 +227,7 @@ __device__ inline void apply_W3(double (&y)[3][nP3(K)], const double (&Ji)[3][3]
 #pragma unroll
       for (int i = 0; i < P; ++i)
 #pragma unroll
-        for (int e = 0; e < 3; ++e) a[e] += Dh[(e * NP + j) * P + i] * y[c][i];
+        for (int e = 0; e < 3; ++e) a[e] += Dc[(e * NP + j) * P + i] * y[c][i];
       s += Ji[0][c] * a[0] + Ji[1][c] * a[1] + Ji[2][c] * a[2];
     }
     d[j] = s;
@@ -249,7 +250,7 @@ __device__ inline void apply_W3(double (&y)[3][nP3(K)], const double (&Ji)[3][3]
       double s = 0;
 #pragma unroll
       for (int j = 0; j < NP; ++j)
-        s += (Ji[0][c] * Dh[(0 * NP + j) * P + i] + Ji[1][c] * Dh[(1 * NP + j) * P + i] + Ji[2][c] * Dh[(2 * NP + j) * P + i]) * e[j];
+        s += (Ji[0][c] * Dc[(0 * NP + j) * P + i] + Ji[1][c] * Dc[(1 * NP + j) * P + i] + Ji[2][c] * Dc[(2 * NP + j) * P + i]) * e[j];
       y[c][i] -= s;
     }
 }
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(kEBlk) void k_cond_rhs3(DevGeo g, DevTabs tb, const
     for (int mm = 0; mm < NF; ++mm) {
       double s = 0;
 #pragma unroll
-      for (int i = 0; i < P; ++i) s += tb.Ch[(f * NF + mm) * P + i] * (n[0] * y[0][i] + n[1] * y[1][i] + n[2] * y[2][i]);
+      for (int i = 0; i < P; ++i) s += cst(tb.Ch)[(f * NF + mm) * P + i] * (n[0] * y[0][i] + n[1] * y[1][i] + n[2] * y[2][i]);
       m[mm] = sc * s;
     }
     if ((code >> 5) & 1) {
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(kEBlk) void k_recover3(DevGeo g, DevTabs tb, const 
     for (int i = 0; i < P; ++i) {
       double s = 0;
 #pragma unroll
-      for (int mm = 0; mm < NF; ++mm) s += lm[mm] * tb.Ch[(f * NF + mm) * P + i];
+      for (int mm = 0; mm < NF; ++mm) s += lm[mm] * cst(tb.Ch)[(f * NF + mm) * P + i];
       s *= sc;
 #pragma unroll
       for (int c = 0; c < 3; ++c) y[c][i] -= n[c] * s;
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(kBlk) void k_mf_apply3(DevGeo g, DevBsr A, const do
   const int T = g.T;
   const int t = xcd_block() * blockDim.x + threadIdx.x;
   if (t >= T) return;
-  const double* __restrict__ Ch = A.mfCh;
+  const auto Ch = cst(A.mfCh);
   double y[3][P];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
