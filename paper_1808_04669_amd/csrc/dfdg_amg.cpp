@@ -7,7 +7,8 @@
 // neighbourhood is free, then attachment, then leftovers), a tentative prolongator carrying
 // the near-null vector aggregate by aggregate, one damped-Jacobi smoothing step of the
 // prolongator (weight 4/(3 rho(D^{-1}A))), and the Galerkin product R A P with R = P^T.
-// The coarsest operator is inverted densely after adding its (near-)kernel direction.
+// The coarsest operator is inverted densely after adding its (near-)kernel direction; the
+// inverse is then projected onto the complement of that direction (a pseudo-inverse).
 #include "dfdg_amg.h"
 
 #include <algorithm>
@@ -365,6 +366,25 @@ int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::ve
   if (!dense_spd_inverse(nc, D)) {
     err = "multigrid: coarsest operator is not positive definite";
     return -1;
+  }
+  // Pseudo-inverse of A_c: Q D Q with Q = I - B B^T / (B.B), so that the coarse solve
+  // neither reads nor returns a kernel component.  The inverse of the shifted operator
+  // alone returns the residual's kernel component (pure rounding) divided by s, the mean
+  // coarse diagonal, which is small after several Galerkin products; near the attainable
+  // accuracy that component dominates the search direction, (p, S p) loses its sign and
+  // the PCG diverges.
+  if (bb > 0) {
+    std::vector<double> Db((size_t)nc, 0.0);
+    double bDb = 0;
+    for (int i = 0; i < nc; ++i) {
+      double t = 0;
+      for (int j = 0; j < nc; ++j) t += D[(size_t)i * nc + j] * B[j];
+      Db[i] = t;
+    }
+    for (int i = 0; i < nc; ++i) bDb += B[i] * Db[i];
+    for (int i = 0; i < nc; ++i)
+      for (int j = 0; j < nc; ++j)
+        D[(size_t)i * nc + j] += (-Db[i] * B[j] - B[i] * Db[j] + B[i] * B[j] * bDb / bb) / bb;
   }
   H.coarse_inv = std::move(D);
   H.n_coarse = nc;

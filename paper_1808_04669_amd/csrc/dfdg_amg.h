@@ -26,7 +26,7 @@ struct AmgLevel {
 
 struct AmgHierarchy {
   std::vector<AmgLevel> lv;          // lv[0] = fine operator S
-  std::vector<double> coarse_inv;    // dense inverse (n_c x n_c) of the regularised coarsest operator
+  std::vector<double> coarse_inv;    // dense pseudo-inverse (n_c x n_c) of the coarsest operator
   int n_coarse = 0;
 };
 

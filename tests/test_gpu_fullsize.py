@@ -87,6 +87,22 @@ def test_mixed_step_against_fp64_at_512_bdm3():
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("mg_fp32", [True, False])
+def test_multigrid_pcg_reaches_1e12_at_512_bdm3(mg_fp32):
+    """The multigrid-preconditioned PCG (FP32 or FP64 cycle) takes the 512x512 BDM_3 facet
+    solve from a zero start to 1e-12 with (p, S p) > 0 throughout: the coarsest solve is a
+    pseudo-inverse, so rounding along the kernel of S is not amplified into the search
+    directions (a regularised inverse alone lets the residual grow again past 2e-12 until
+    (p, S p) changes sign)."""
+    _, s, xyz, _ = make_pair(512, 3, oracle=False, cg_rtol=1e-12, precond="amg", mg_fp32=mg_fp32)
+    U, _ = project_field(s, xyz, double_shear_layer)
+    F = s.residual(U)
+    _, info = s.mass_solve(F)
+    _log("512x512 BDM_3 mass solve, FP32 cycle" if mg_fp32 else "FP64 cycle", info.iterations, info.rel_residual)
+    assert info.status == 0 and info.rel_residual <= 1e-12 and info.iterations < 80
+    del s
+
+
 def test_adjoint_gradient_vs_finite_differences_at_128():
     """Gradient of the final kinetic energy after 100 TVD-RK3 steps with checkpoints every
     10 steps (128x128 BDM_2, nu = 1e-3, random field |k| <= 8, seed 0) against central
