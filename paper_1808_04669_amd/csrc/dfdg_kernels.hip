@@ -938,6 +938,46 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
   }
   const V alpha = (V)(t1[0] / t2[0]);
   double v[2] = {0, 0};
+  if constexpr (PC != 1) {
+    // point Jacobi or no preconditioner: entrywise over the E n_f entries, two per thread
+    // and access (16- or 8-byte loads, coalesced across the wave)
+    static_assert(sizeof(M) == sizeof(V), "point Jacobi reads D^{-1} in the vector type");
+    using V2 = typename std::conditional<sizeof(V) == 8, double2, float2>::type;
+    const V* dv = (sizeof(V) == 8) ? (const V*)A.dinv : (const V*)A.dinv32;
+    const long n = (long)E * NF, n2 = n / 2;
+    const long t0 = (long)xcd_block() * blockDim.x + threadIdx.x, st = (long)G * blockDim.x;
+    auto entry = [&](V& xe, V& re, V pe, V se, V de, V& ze) {
+      xe += alpha * pe;
+      re = re - alpha * se;
+      v[1] += (double)re * (double)re;
+      if (PC == 0) {
+        ze = de * re;
+        v[0] += (double)re * (double)ze;
+      }
+    };
+    for (long q = t0; q < n2; q += st) {
+      const V2 pv = ((const V2*)p)[q], sv = ((const V2*)Sp)[q];
+      V2 xv = ((V2*)x)[q], rv = ((V2*)r)[q], zv;
+      V2 dd = {};
+      if (PC == 0) dd = ((const V2*)dv)[q];
+      entry(xv.x, rv.x, pv.x, sv.x, dd.x, zv.x);
+      entry(xv.y, rv.y, pv.y, sv.y, dd.y, zv.y);
+      ((V2*)x)[q] = xv;
+      ((V2*)r)[q] = rv;
+      if (PC == 0) ((V2*)z)[q] = zv;
+    }
+    if ((n & 1) && t0 == (n2 % st)) {  // the odd last entry, by the thread whose turn it is
+      const long i = n - 1;
+      V xe = x[i], re = r[i], ze = 0;
+      entry(xe, re, p[i], Sp[i], PC == 0 ? dv[i] : (V)0, ze);
+      x[i] = xe;
+      r[i] = re;
+      if (PC == 0) z[i] = ze;
+    }
+    block_write_partial<2>(v, rz_out);
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->it = sc->it + 1;
+    return;
+  }
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
     V rr[NF], zz[NF];
 #pragma unroll
@@ -1825,6 +1865,11 @@ template <typename V>
 static hipError_t update_any(int NF, int pc, const DevGeo& g, const DevBsr& A, const V* p, const V* Sp, V* x, V* r,
                              V* z, const PcgBufs& pb, int it, hipStream_t s) {
   const int G = g.fgrid;
+  // the entrywise form (point Jacobi, multigrid) reads and writes entry pairs
+  const uintptr_t al = 2 * sizeof(V) - 1;
+  if (pc != 1 && (((uintptr_t)p | (uintptr_t)Sp | (uintptr_t)x | (uintptr_t)r | (uintptr_t)z |
+                   (uintptr_t)(sizeof(V) == 8 ? (const void*)A.dinv : (const void*)A.dinv32)) & al))
+    return hipErrorInvalidValue;
   const double* prev = pb.rz[(it - 1) & 1];
   double* out = pb.rz[it & 1];
   DFDG_DISPATCH_NF(NF, {
