@@ -353,6 +353,22 @@ int dfdg_debug_residual_rule(int k, int* npts, double* pts_host, double* w_host)
  *   rho_host[l].  The last level is inverted densely. */
 int dfdg_debug_multigrid(const dfdg_ctx* ctx, int max_levels, int* n_levels, int64_t* rows_host,
                          int64_t* nnz_host, double* rho_host);
+/* dfdg_debug_multigrid_matrix: one matrix of that hierarchy in CSR (host copies, FP64):
+ *   which = 0 the operator A_level (level 0 is S, rows in facet-major order F*n_f + m),
+ *   which = 1 the prolongator from level + 1 to level (rows: level's unknowns),
+ *   which = 2 the dense pseudo-inverse of the coarsest operator (level = last), all n^2
+ *   entries, which = 3 and 4 the products A P and R A = P^T A kept for levels 1 .. last - 1.  *n_rows, *n_cols, *nnz are always written; ptr_host[n_rows + 1],
+ *   cols_host[nnz] and vals_host[nnz] are filled when all three are non-null (call once
+ *   with nulls to size them).  DFDG_E_INVALID_ARG for a level or kind that does not exist. */
+/* dfdg_debug_vcycle: z = one multigrid V-cycle (the context's preconditioner, FP32 or FP64
+ *   cycle as configured) applied to b; b and z are device vectors of n_lambda doubles in
+ *   the facet layout.  DFDG_AMG contexts only; synchronises the context stream. */
+int dfdg_debug_vcycle(dfdg_ctx* ctx, const double* b_dev, double* z_dev);
+/* dfdg_debug_facet_rhs: the facet right-hand side g = sum_T C_T W_T F_T of the last facet
+ *   solve (before deflation), n_lambda doubles into a device vector; synchronises. */
+int dfdg_debug_facet_rhs(dfdg_ctx* ctx, double* g_dev);
+int dfdg_debug_multigrid_matrix(const dfdg_ctx* ctx, int level, int which, int64_t* n_rows, int64_t* n_cols,
+                                int64_t* nnz, int64_t* ptr_host, int32_t* cols_host, double* vals_host);
 
 #ifdef __cplusplus
 }

@@ -367,6 +367,9 @@ static void carve(dfdg_ctx* ctx, char* base) {
   A.binv32 = f32 ? c.take<float>(h.binv.size()) : nullptr;
   const bool f16 = ctx->prm.precond == DFDG_AMG && (mixed || ctx->prm.mg_fp32) && ctx->prm.mg_fine_fp16;
   A.vals16 = f16 ? c.take<uint32_t>((size_t)nPairs(NF, A.ns) * E) : nullptr;
+  const bool amg = ctx->prm.precond == DFDG_AMG;
+  A.tdef = amg ? c.take<double>(nL) : nullptr;
+  A.tdef32 = amg && f32 ? c.take<float>(nL) : nullptr;
   // work
   ctx->Lbuf = c.take<double>(nU);
   ctx->q = c.take<double>(nfac * NF * T);
@@ -401,7 +404,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
     pb->gg = c.take<double>(3 * G);
     pb->rz[0] = c.take<double>(2 * G);
     pb->rz[1] = c.take<double>(2 * G);
-    pb->pq = c.take<double>(G);
+    pb->pq = c.take<double>(2 * G);
   }
   if (mixed) {
     ctx->L32 = c.take<float>(nU);
@@ -563,6 +566,21 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<double*>(ctx->A.vals), h.vals, s));
   HIPC(up(const_cast<double*>(ctx->A.dinv), h.dinv, s));
   HIPC(up(const_cast<double*>(ctx->A.binv), h.binv, s));
+  if (ctx->A.tdef) {  // S D^{-1} z, z = zdef on mode 0 (FP64 on the host)
+    const int NS = ctx->A.ns;
+    const long E = ctx->E, NF = ctx->NF;
+    std::vector<double> t((size_t)E * NF, 0.0);
+    for (long F = 0; F < E; ++F)
+      for (int sl = 0; sl < NS; ++sl) {
+        const long cc = h.cols[(size_t)sl * E + F];
+        const double w = h.dinv[(size_t)cc * NF] * h.zdef[cc];
+        for (long a = 0; a < NF; ++a) t[(size_t)F * NF + a] += h.vals[(((size_t)sl * NF + a) * NF + 0) * E + F] * w;
+      }
+    std::vector<float> t32(t.begin(), t.end());
+    HIPC(up(const_cast<double*>(ctx->A.tdef), t, s));
+    if (ctx->A.tdef32) HIPC(up(const_cast<float*>(ctx->A.tdef32), t32, s));
+    HIPC(hipStreamSynchronize(s));  // the host copies end with this block
+  }
   if (ctx->A.vals32) {
     std::vector<float> v(h.vals.begin(), h.vals.end()), d(h.dinv.begin(), h.dinv.end()),
         b(h.binv.begin(), h.binv.end());
@@ -1354,6 +1372,34 @@ extern "C" int dfdg_eval(dfdg_ctx* ctx, const double* U, int npts, const double*
   return DFDG_OK;
 }
 
+extern "C" int dfdg_debug_facet_rhs(dfdg_ctx* ctx, double* g) {
+  NEED_BOUND(ctx);
+  if (!g) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  HIPC(hipMemcpyAsync(g, ctx->gv, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  HIPC(hipStreamSynchronize(ctx->stream));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_vcycle(dfdg_ctx* ctx, const double* b, double* z) {
+  NEED_BOUND(ctx);
+  if (!b || !z) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (ctx->prm.precond != DFDG_AMG) return fail(ctx, DFDG_E_INVALID_ARG, "V-cycle needs an AMG context");
+  hipStream_t s = ctx->stream;
+  const long NF = ctx->NF;
+  const PcgBufs& pb = ctx->pbt;
+  PcgScalars st{};  // a running state whose stopping test never fires
+  st.rz = 1.0; st.rr = 1.0; st.gg = 1.0; st.tol2 = -1.0; st.maxit = 1 << 30; st.it = 2;
+  HIPC(hipMemcpyAsync(pb.sc, &st, sizeof(st), hipMemcpyHostToDevice, s));
+  const long G = ctx->g.fgrid;
+  HIPC(launch_fill(2 * G, 1.0, pb.rz[0], s));
+  HIPC(hipMemcpyAsync(ctx->r, b, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (ctx->prm.mg_fp32) HIPC((launch_vcycle<float, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
+  else HIPC((launch_vcycle<double, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s)));
+  HIPC(hipMemcpyAsync(z, ctx->z, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPC(hipStreamSynchronize(s));
+  return DFDG_OK;
+}
+
 extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, double* bytes) {
   NEED_BOUND(ctx);
   if (!ms || reps < 1) return fail(ctx, DFDG_E_INVALID_ARG, "bad arguments");
@@ -1370,7 +1416,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   const long G = ctx->g.fgrid;
   HIPC(launch_fill(2 * G, 1.0, pb.rz[0], s));
   HIPC(launch_fill(2 * G, 1.0, pb.rz[1], s));
-  HIPC(launch_fill(G, 1.0, pb.pq, s));
+  HIPC(launch_fill(2 * G, 1.0, pb.pq, s));
   auto launch = [&]() -> hipError_t {
     switch (which) {
       case 0: return launch_pcg_spmv(NF, ctx->g, ctx->A, ctx->z, ctx->p[0], ctx->p[1], ctx->Sp, pb, 2, s);
@@ -1512,6 +1558,43 @@ extern "C" int dfdg_debug_facet_matrix(const dfdg_ctx* ctx, int32_t* cols, doubl
   if (!ctx || !cols || !vals) return DFDG_E_INVALID_ARG;
   std::memcpy(cols, ctx->hs.cols.data(), ctx->hs.cols.size() * sizeof(int32_t));
   std::memcpy(vals, ctx->hs.vals.data(), ctx->hs.vals.size() * sizeof(double));
+  return DFDG_OK;
+}
+
+extern "C" int dfdg_debug_multigrid_matrix(const dfdg_ctx* ctx, int level, int which, int64_t* n_rows,
+                                           int64_t* n_cols, int64_t* nnz, int64_t* ptr, int32_t* cols,
+                                           double* vals) {
+  if (!ctx || !n_rows || !n_cols || !nnz) return DFDG_E_INVALID_ARG;
+  const int L = (int)ctx->H.lv.size();
+  if (level < 0 || level >= L || which < 0 || which > 4) return DFDG_E_INVALID_ARG;
+  if (which == 2) {  // dense coarsest pseudo-inverse, as a full CSR
+    if (level != L - 1) return DFDG_E_INVALID_ARG;
+    const long n = ctx->H.n_coarse;
+    *n_rows = *n_cols = n;
+    *nnz = n * n;
+    if (ptr && cols && vals) {
+      for (long i = 0; i <= n; ++i) ptr[i] = i * n;
+      for (long i = 0; i < n * n; ++i) {
+        cols[i] = (int32_t)(i % n);
+        vals[i] = ctx->H.coarse_inv[i];
+      }
+    }
+    return DFDG_OK;
+  }
+  const AmgLevel& lv = ctx->H.lv[level];
+  const Csr& M = which == 0 ? lv.A : which == 1 ? lv.P : which == 3 ? lv.AP : lv.RA;
+  if (which != 0 && level == L - 1) return DFDG_E_INVALID_ARG;
+  if (which >= 3 && M.n == 0) return DFDG_E_INVALID_ARG;
+  *n_rows = M.n;
+  *n_cols = M.m;
+  *nnz = M.nnz();
+  if (ptr && cols && vals) {
+    for (int i = 0; i <= M.n; ++i) ptr[i] = M.ptr[i];
+    for (long k = 0; k < M.nnz(); ++k) {
+      cols[k] = M.col[k];
+      vals[k] = M.val[k];
+    }
+  }
   return DFDG_OK;
 }
 

@@ -139,6 +139,11 @@ struct DevBsr {
   // [5][NF][NF] sequence (the last high half is zero when 5 NF^2 is odd)
   const uint32_t* vals16;
   float scale16;
+  // S D^{-1} z for the kernel vector z of S (zdef on mode 0), [E][NF] in FP64 and in FP32
+  // (multigrid contexts, else null): the fused update and first smoothing step removes the
+  // kernel component of S p from the residual and needs S D^{-1} of it
+  const double* tdef;
+  const float* tdef32;
 };
 
 // Scalars of one PCG run (device memory).  Written by block 0 of a kernel (or by a

@@ -24,7 +24,7 @@ struct PcgBufs {
   PcgScalars* sc;
   double* gg;      // [G][2] (g,g),(z,g) partials; reused for the FP64 refinement residual
   double* rz[2];   // [G][2] (r,z),(r,r) partials of even / odd iterations
-  double* pq;      // [G]    (p,Sp) partials
+  double* pq;      // [G][2] (p,Sp), (z,Sp) partials (z the normalised kernel vector of S)
 };
 // G: blocks of the facet kernels, ceil(E/256) up to 1024, or at most cap (> 0)
 int facet_grid_size(int E, int cap);

@@ -781,17 +781,19 @@ __device__ inline void spmv_part_mg2(const DevBsr& A, int E, int F, int a0, Gett
   rowloop([&](int s, int a, int b) { return vals[(((size_t)s * NF + a0 + a) * NF + b) * E + F]; });
 }
 
-// r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials (r,z), (r,r) into rz0.
-template <int NF, int NS, bool BJ>
+// r = g - zg zdef - S x (x already orthogonal to the kernel vector z), p_old = 0; the
+// (z, r) partial into zr (the rounding of S x leaves a kernel component in r, which
+// k_pcg_init_defl removes).
+template <int NF, int NS>
 __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const double* __restrict__ gv,
                                                    double* __restrict__ x, double* __restrict__ r,
                                                    double* __restrict__ z, double* __restrict__ p_old,
-                                                   const PcgScalars* sc, double* __restrict__ rz0) {
+                                                   const PcgScalars* sc, double* __restrict__ zr) {
   const int E = g.E;
   const int done = sc->done;
   if (done != PCG_RUNNING && !sc->zero_rhs) return;
   const double zg = sc->zg;
-  double v[2] = {0, 0};
+  double v[1] = {0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += gridDim.x * blockDim.x) {
     if (sc->zero_rhs) {
 #pragma unroll
@@ -806,31 +808,55 @@ __global__ __launch_bounds__(kBlk) void k_pcg_init(DevGeo g, DevBsr A, const dou
 #pragma unroll
       for (int b = 0; b < NF; ++b) xc[b] = x[(size_t)c * NF + b];
     }, Sx);
-    double rr[NF], zz[NF];
-#pragma unroll
-    for (int m = 0; m < NF; ++m) {
-      double gm = gv[(size_t)F * NF + m];
-      if (m == 0) gm -= zg * g.zdef[F];
-      rr[m] = gm - Sx[m];
-    }
-    precond<NF, BJ, double, double>(A, F, rr, zz);
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       const size_t o = (size_t)F * NF + m;
-      r[o] = rr[m];
-      z[o] = zz[m];
+      double gm = gv[o];
+      if (m == 0) gm -= zg * g.zdef[F];
+      r[o] = gm - Sx[m];
       p_old[o] = 0;
-      v[0] += rr[m] * zz[m];
-      v[1] += rr[m] * rr[m];
     }
+    v[0] += g.zdef[F] * r[(size_t)F * NF];
   }
+  block_write_partial<1>(v, zr);
+}
+
+// r -= (z, r) z, z = M^{-1} r (point or facet-block Jacobi; the multigrid cycle overwrites
+// z and the (r,z) partial afterwards); partials (r,z), (r,r) into rz0.
+template <int NF, bool BJ>
+__global__ __launch_bounds__(kBlk) void k_pcg_init_defl(DevGeo g, DevBsr A, double* __restrict__ r,
+                                                        double* __restrict__ z, const PcgScalars* sc,
+                                                        const double* __restrict__ zr, double* __restrict__ rz0) {
+  const int E = g.E, G = gridDim.x;
+  if (sc->done != PCG_RUNNING && !sc->zero_rhs) return;
+  double c0[1];
+  block_sum_partials<1>(zr, G, c0);
+  double v[2] = {0, 0};
+  if (!sc->zero_rhs)
+    for (int F = xcd_block() * blockDim.x + threadIdx.x; F < E; F += G * blockDim.x) {
+      double rr[NF], zz[NF];
+#pragma unroll
+      for (int m = 0; m < NF; ++m) rr[m] = r[(size_t)F * NF + m];
+      rr[0] -= c0[0] * g.zdef[F];
+      precond<NF, BJ, double, double>(A, F, rr, zz);
+#pragma unroll
+      for (int m = 0; m < NF; ++m) {
+        const size_t o = (size_t)F * NF + m;
+        r[o] = rr[m];
+        z[o] = zz[m];
+        v[0] += rr[m] * zz[m];
+        v[1] += rr[m] * rr[m];
+      }
+    }
   block_write_partial<2>(v, rz0);
 }
 
 // Iteration it >= 1 (it read from the scalars, so that the same launch sequence can be
 // replayed from a graph).  From the partials of the previous update (rz_{it-1}, rr_{it-1})
 // and of the one before (rz_{it-2}): stopping test, beta; then p_new = z + beta p_old,
-// Sp = S p_new and partials (p_new, Sp).
+// Sp = S p_new and partials (p_new, Sp) and (z, Sp), z the normalised kernel vector of S
+// (zdef on mode 0): in exact arithmetic S p is orthogonal to z, in floating point its
+// rounding is not, and the update removes that component from the residual.
 template <int NF, int NS, typename V, typename M>
 __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* __restrict__ z,
                                                    const V* __restrict__ p_old, V* __restrict__ p_new,
@@ -896,7 +922,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
   }
   if (status != PCG_RUNNING) return;
   const V b = (V)beta;
-  double v[1] = {0};
+  double v[2] = {0, 0};
   for (int u = u0; u < E * SPL; u += G * blockDim.x) {
     if (u != u0) row(u, sz, sp);
     const int F = u / SPL, a0 = (u % SPL) * NA;
@@ -908,13 +934,17 @@ __global__ __launch_bounds__(kBlk) void k_pcg_spmv(DevGeo g, DevBsr A, const V* 
       p_new[o] = pn;
       Sp[o] = y;
       v[0] += (double)pn * (double)y;
+      if (a0 + a == 0) v[1] += g.zdef[F] * (double)y;
     }
   }
-  block_write_partial<1>(v, pq);
+  block_write_partial<2>(v, pq);
 }
 
-// x += alpha p, r -= alpha Sp, z = M^{-1} r with alpha = rz_{it-1} / (p, Sp); partials
-// (r,z), (r,r) of iteration it.
+// x += alpha p, r -= alpha (Sp - (z, Sp) z), z = M^{-1} r with alpha = rz_{it-1} / (p, Sp);
+// partials (r,z), (r,r) of iteration it.  Removing the kernel component of S p keeps the
+// recursive residual in the range of S: left in, the rounding of S p accumulates there, the
+// system the PCG sees becomes inconsistent at that level, and once the residual reaches it
+// the iteration diverges and (p, S p) changes sign.
 // PC: 0 point Jacobi, 1 facet-block Jacobi, 2 none (z comes from the multigrid V-cycle,
 // which then overwrites the (r,z) partial).
 template <int NF, int PC, typename V, typename M>
@@ -926,9 +956,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
   if (sc->done != PCG_RUNNING) return;
   const int E = g.E;
   const int G = gridDim.x;
-  double t1[2], t2[1];
+  double t1[2], t2[2];
   block_sum_partials<2>(rz_prev, G, t1);
-  block_sum_partials<1>(pq, G, t2);
+  block_sum_partials<2>(pq, G, t2);
   int status = PCG_RUNNING;
   if (!isfinite(t2[0])) status = PCG_NONFINITE;
   else if (!(t2[0] > 0)) status = PCG_BREAKDOWN;
@@ -937,6 +967,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
     return;
   }
   const V alpha = (V)(t1[0] / t2[0]);
+  const double dz = t2[1];  // (z, S p), z normalised
   double v[2] = {0, 0};
   if constexpr (PC != 1) {
     // point Jacobi or no preconditioner: entrywise over the E n_f entries, two per thread
@@ -955,13 +986,15 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
         v[0] += (double)re * (double)ze;
       }
     };
+    // S p less its kernel component, at entry i (mode i % NF of facet i / NF)
+    auto sdef = [&](long i, V sp) { return (i % NF == 0) ? (V)((double)sp - dz * g.zdef[i / NF]) : sp; };
     for (long q = t0; q < n2; q += st) {
       const V2 pv = ((const V2*)p)[q], sv = ((const V2*)Sp)[q];
       V2 xv = ((V2*)x)[q], rv = ((V2*)r)[q], zv;
       V2 dd = {};
       if (PC == 0) dd = ((const V2*)dv)[q];
-      entry(xv.x, rv.x, pv.x, sv.x, dd.x, zv.x);
-      entry(xv.y, rv.y, pv.y, sv.y, dd.y, zv.y);
+      entry(xv.x, rv.x, pv.x, sdef(2 * q, sv.x), dd.x, zv.x);
+      entry(xv.y, rv.y, pv.y, sdef(2 * q + 1, sv.y), dd.y, zv.y);
       ((V2*)x)[q] = xv;
       ((V2*)r)[q] = rv;
       if (PC == 0) ((V2*)z)[q] = zv;
@@ -969,7 +1002,7 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
     if ((n & 1) && t0 == (n2 % st)) {  // the odd last entry, by the thread whose turn it is
       const long i = n - 1;
       V xe = x[i], re = r[i], ze = 0;
-      entry(xe, re, p[i], Sp[i], PC == 0 ? dv[i] : (V)0, ze);
+      entry(xe, re, p[i], sdef(i, Sp[i]), PC == 0 ? dv[i] : (V)0, ze);
       x[i] = xe;
       r[i] = re;
       if (PC == 0) z[i] = ze;
@@ -984,7 +1017,8 @@ __global__ __launch_bounds__(kBlk) void k_pcg_update(DevGeo g, DevBsr A, const V
     for (int a = 0; a < NF; ++a) {
       const size_t o = (size_t)F * NF + a;
       x[o] += alpha * p[o];
-      rr[a] = r[o] - alpha * Sp[o];
+      const V spd = a == 0 ? (V)((double)Sp[o] - dz * g.zdef[F]) : Sp[o];
+      rr[a] = r[o] - alpha * spd;
       r[o] = rr[a];
     }
     if (PC == 2) {
@@ -1374,9 +1408,10 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
 
 // ---- PCG update fused with the first smoothing step of the cycle ----------------------
 // PCG update fused with the first pre-smoothing step of the cycle.  The residual is
-// double-buffered: r_new = r_old - alpha Sp for the own rows, and the neighbours' new
-// residual, needed by S x1, is formed on the fly from r_old and Sp.  Also x += alpha p,
-// the (r,r) partial, and the iteration counter.
+// double-buffered: r_new = r_old - alpha (Sp - (z, Sp) z) for the own rows (the kernel
+// component of S p removed, as in k_pcg_update), and the neighbours' new residual, needed
+// by S x1, is formed on the fly from r_old, Sp and the precomputed S D^{-1} z.  Also
+// x += alpha p, the (r,r) partial, and the iteration counter.
 template <int NF, int NS, typename V, typename VB>
 __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, const VB* __restrict__ p,
                                                           const VB* __restrict__ Sp, VB* __restrict__ x,
@@ -1390,10 +1425,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   // alpha is not needed before the end: with u = D^{-1} r_old / th and w = D^{-1} S p / th,
   // S x1 = S u - alpha S w.  The partials are loaded first and summed after this thread's
   // first row, whose loads overlap them.
-  PartLoad<2> q1;
-  PartLoad<1> q2;
+  PartLoad<2> q1, q2;
   partials_load<2>(rz_prev, G, true, q1);
-  partials_load<1>(pq, G, true, q2);
+  partials_load<2>(pq, G, true, q2);
   const V* dinv = bsr_dinv<NF, V>(A);
   const V ith = (V)(1.0 / cb.th), c1 = (V)cb.c1, c2 = (V)cb.c2;
   constexpr int SPL = kSplit<NF, NS>, NA = NF / SPL;
@@ -1411,9 +1445,9 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   const int u0 = xcd_block() * blockDim.x + threadIdx.x;
   V su[NA], sw[NA];
   if (u0 < E * SPL) row(u0, su, sw);
-  double t1[2], t2[1];
+  double t1[2], t2[2];
   partials_sum<2>(q1, G, t1);
-  partials_sum<1>(q2, G, t2);
+  partials_sum<2>(q2, G, t2);
   int status = PCG_RUNNING;
   if (!isfinite(t2[0])) status = PCG_NONFINITE;
   else if (!(t2[0] > 0)) status = PCG_BREAKDOWN;
@@ -1423,6 +1457,11 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
   }
   const VB alpha = (VB)(t1[0] / t2[0]);
   const V alv = (V)alpha;
+  // the kernel component of S p leaves the residual: r_new = r_old - alpha (Sp - dz z), and
+  // S x1 gains alpha dz (S D^{-1} z) / th
+  const double dz = t2[1];
+  const V* __restrict__ tdef = (sizeof(V) == 8) ? (const V*)A.tdef : (const V*)A.tdef32;
+  const V azt = (V)((double)alpha * dz) * ith;
   double v[2] = {0, 0};
   for (int u = u0; u < E * SPL; u += G * blockDim.x) {
     if (u != u0) row(u, su, sw);
@@ -1431,12 +1470,13 @@ __global__ __launch_bounds__(kBlk) void k_pcg_upd_mg0_pre(DevGeo g, DevBsr A, co
     for (int a = 0; a < NA; ++a) {
       const size_t o = (size_t)F * NF + a0 + a;
       x[o] += alpha * p[o];
-      const VB rn = r_old[o] - alpha * Sp[o];
+      const VB spd = (a0 + a == 0) ? (VB)((double)Sp[o] - dz * g.zdef[F]) : Sp[o];
+      const VB rn = r_old[o] - alpha * spd;
       r_new[o] = rn;
       v[1] += (double)rn * (double)rn;
       const V bo = (V)rn;
       const V x1 = dinv[o] * bo * ith;
-      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - (su[a] - alv * sw[a]));
+      x2[o] = (1 + c1) * x1 + c2 * dinv[o] * (bo - (su[a] - alv * sw[a] + azt * tdef[o]));
     }
   }
   block_write_partial<2>(v, rz_out);
@@ -1838,9 +1878,16 @@ hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipS
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
                            double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
   const int G = g.fgrid;
-  DFDG_DISPATCH_NFS(NF, A.ns, {
-    if (bj) hipLaunchKernelGGL((k_pcg_init<NN, SS, true>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
-    else hipLaunchKernelGGL((k_pcg_init<NN, SS, false>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z, p_old, (const PcgScalars*)pb.sc, pb.rz[0]);
+  // the start without its kernel component (a start far along it would leave a kernel
+  // component of its rounding in r that no iteration removes), then r and its deflation;
+  // the right-hand side's partials in pb.gg are consumed by now and hold (z, .) partials
+  hipError_t e = launch_deflate(NF, g, x, pb.gg, s);
+  if (e != hipSuccess) return e;
+  DFDG_DISPATCH_NFS(NF, A.ns, hipLaunchKernelGGL((k_pcg_init<NN, SS>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z,
+                                                 p_old, (const PcgScalars*)pb.sc, pb.gg));
+  DFDG_DISPATCH_NF(NF, {
+    if (bj) hipLaunchKernelGGL((k_pcg_init_defl<NN, true>), dim3(G), dim3(kBlk), 0, s, g, A, r, z, (const PcgScalars*)pb.sc, (const double*)pb.gg, pb.rz[0]);
+    else hipLaunchKernelGGL((k_pcg_init_defl<NN, false>), dim3(G), dim3(kBlk), 0, s, g, A, r, z, (const PcgScalars*)pb.sc, (const double*)pb.gg, pb.rz[0]);
   });
   return hipGetLastError();
 }

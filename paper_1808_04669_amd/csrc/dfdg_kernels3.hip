@@ -487,8 +487,9 @@ __global__ __launch_bounds__(kBlk) void k_mf_apply3(DevGeo g, DevBsr A, const do
   }
 }
 
-// Face pass: S p = the two sides' contributions, p_new = z + beta p_old, (p_new, S p)
-// partials (grid-stride over the face rows, one partial per block).
+// Face pass: S p = the two sides' contributions, p_new = z + beta p_old, (p_new, S p) and
+// (z, S p) partials (z the kernel vector; grid-stride over the face rows, one partial per
+// block).
 template <int NF>
 __global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const double* __restrict__ z,
                                                     const double* __restrict__ p_old, double* __restrict__ p_new,
@@ -498,7 +499,7 @@ __global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const do
   double beta;
   if (!pcg_beta(sc, rz_prev, rz_prev2, gridDim.x, false, beta)) return;
   const int T = g.T;
-  double v[1] = {0};
+  double v[2] = {0, 0};
   for (int F = xcd_block() * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x) {
     const int a = g.qL[F], b = g.qR[F];
 #pragma unroll
@@ -509,9 +510,10 @@ __global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const do
       p_new[o] = pn;
       Sp[o] = y;
       v[0] += pn * y;
+      if (m == 0) v[1] += g.zdef[F] * y;
     }
   }
-  block_write_partial<1>(v, pq);
+  block_write_partial<2>(v, pq);
 }
 
 hipError_t launch_mf_spmv3(int NF, const DevGeo& g, const DevBsr& A, const double* z, const double* p_old,

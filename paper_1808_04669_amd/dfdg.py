@@ -113,6 +113,9 @@ _SIGS = {
     "dfdg_debug_basis3": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_rule3": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P]),
     "dfdg_debug_multigrid": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int), _P, _P, _P]),
+    "dfdg_debug_multigrid_matrix": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P]),
+    "dfdg_debug_vcycle": (ctypes.c_int, [_P, _P, _P]),
+    "dfdg_debug_facet_rhs": (ctypes.c_int, [_P, _P]),
 }
 EXPORTED = tuple(_SIGS)
 
@@ -417,6 +420,34 @@ class Solver:
         self._check(self._lib.dfdg_debug_multigrid(self._h, 16, ctypes.byref(L), rows.ctypes.data_as(_P),
                                                    nnz.ctypes.data_as(_P), rho.ctypes.data_as(_P)))
         return [int(r) for r in rows[:L.value]]
+
+    def mg_matrix(self, level, which):
+        """dfdg_debug_multigrid_matrix as a scipy CSR matrix (which: 0 A_level, 1 P, 2 the
+        dense coarsest pseudo-inverse)."""
+        import scipy.sparse as sp
+        n, m, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.dfdg_debug_multigrid_matrix(self._h, int(level), int(which), ctypes.byref(n),
+                                                           ctypes.byref(m), ctypes.byref(nz), None, None, None))
+        ptr = np.empty(n.value + 1, dtype=np.int64)
+        col = np.empty(nz.value, dtype=np.int32)
+        val = np.empty(nz.value)
+        self._check(self._lib.dfdg_debug_multigrid_matrix(self._h, int(level), int(which), ctypes.byref(n),
+                                                           ctypes.byref(m), ctypes.byref(nz), ptr.ctypes.data_as(_P),
+                                                           col.ctypes.data_as(_P), val.ctypes.data_as(_P)))
+        return sp.csr_matrix((val, col, ptr), shape=(n.value, m.value))
+
+    def vcycle(self, b):
+        """dfdg_debug_vcycle: one V-cycle of the context's multigrid applied to b."""
+        z = torch.empty_like(b)
+        self._check(self._lib.dfdg_debug_vcycle(self._h, self._vec(b, self.n_lambda, "b"),
+                                                self._vec(z, self.n_lambda, "z")))
+        return z
+
+    def facet_rhs(self):
+        """dfdg_debug_facet_rhs: the facet right-hand side of the last solve."""
+        g = torch.empty(self.n_lambda, dtype=torch.float64, device=self.device)
+        self._check(self._lib.dfdg_debug_facet_rhs(self._h, self._vec(g, self.n_lambda, "g")))
+        return g
 
     def time_kernel(self, which, reps=50):
         ms = ctypes.c_float()

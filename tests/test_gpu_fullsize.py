@@ -103,6 +103,25 @@ def test_multigrid_pcg_reaches_1e12_at_512_bdm3(mg_fp32):
     del s
 
 
+def test_multigrid_pcg_iterations_do_not_grow_with_the_mesh():
+    """Cold multigrid-preconditioned facet solves to 1e-12 on 64^2 ... 448^2 BDM_2 (powers
+    of two and not) take 30-40 iterations: at most 1.2x more per halving of h, and none
+    breaks down.  The kernel component of S p is removed from the recursive residual (and
+    from the start's residual): left in, its rounding made the system inconsistent near
+    1e-12, and at 192^2 and 448^2 the PCG diverged there until (p, S p) <= 0."""
+    its = {}
+    for N in (64, 128, 192, 320, 448):
+        _, s, xyz, _ = make_pair(N, 2, oracle=False, cg_rtol=1e-12, precond="amg", cg_maxit=200)
+        U, _ = project_field(s, xyz, double_shear_layer)
+        _, info = s.mass_solve(s.residual(U))
+        assert info.status == 0 and info.rel_residual <= 1e-12
+        its[N] = info.iterations
+        del s
+    _log("cold multigrid PCG iterations by N", its)
+    assert max(its.values()) <= 40
+    assert its[448] <= 1.2 ** 3 * its[64]
+
+
 def test_adjoint_gradient_vs_finite_differences_at_128():
     """Gradient of the final kinetic energy after 100 TVD-RK3 steps with checkpoints every
     10 steps (128x128 BDM_2, nu = 1e-3, random field |k| <= 8, seed 0) against central
