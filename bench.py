@@ -399,9 +399,6 @@ def main():
         sys.exit(2)
     import torch
     from inputs import double_shear_layer
-    if args.only_3d:
-        print(json.dumps({"three_d": three_d(args)}), flush=True)
-        return
     if args.copy_calib_mb > 0:
         n = args.copy_calib_mb * (1 << 20) // 8
         a = torch.ones(n, dtype=torch.float64, device="cuda:0")
@@ -411,6 +408,9 @@ def main():
         torch.cuda.synchronize()
         log(f"copy calibration: {n * 8} bytes read, {n * 8} bytes written")
         del a, b
+    if args.only_3d:
+        print(json.dumps({"three_d": three_d(args)}), flush=True)
+        return
     N, k = args.N, args.k
     s = make_solver(N, k, "fp64", args)
     U, vmax, pinfo = project_field(s, double_shear_layer)
