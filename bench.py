@@ -26,15 +26,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_pcg_spmv_dsl256_bdm2_counters.md")
+COUNTERS_3D = os.path.join(ROOT, "profiles", "k_pcg_spmv_tg3d32_bdm2_counters.md")
 KERNEL_SRC = os.path.join(ROOT, "paper_1808_04669_amd", "csrc", "dfdg_kernels.hip")
 
 
-def measured_traffic():
+def measured_traffic(path=COUNTERS):
     """HBM bytes per k_pcg_spmv launch from the committed counter runs, or None when the
     kernel source changed since they were taken."""
     import hashlib
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             txt = f.read()
         with open(KERNEL_SRC, "rb") as f:
             sha = hashlib.sha256(f.read()).hexdigest()[:16]
@@ -305,7 +306,8 @@ def three_d(args):
            "diagnostics_final": d, "setup_s": s.setup_seconds,
            "spmv": {"kernel": "k_pcg_spmv<6, 7> (7-slot face BSR SpMV + p update + (p,Sp) partials)",
                     "avg_launch_us": round(ms_spmv * 1e3, 3), "bytes_per_launch": b_spmv,
-                    "achieved_GBs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4)},
+                    "achieved_GBs": round(spmv_gbs, 1), "frac": round(spmv_gbs / HBM_PEAK_GBS, 4),
+                    "traffic": measured_traffic(COUNTERS_3D)},
            "residual": {"avg_launch_us": round(ms_res * 1e3, 3), "bytes_per_launch": b_res,
                         "GBs": round(b_res / (ms_res * 1e-3) / 1e9, 1)},
            "variants": variants}
