@@ -10,7 +10,9 @@ parameter, plus interior functions with zero normal moments.  With N_T the eleme
 moment matrix, the local basis is Phi [pinv(N_T) | null(N_T)]: functions carrying one facet
 moment each, followed by a basis of the moment-free (interior) functions.  Two elements
 that share a facet DOF then have the same normal trace there, so the assembled functions
-are in H(div).
+are in H(div).  On a mesh with walls (boundary facets) the normal moments of the boundary
+facets are not degrees of freedom: they are zero, so the space is BDM_k in H_0(div) of eq.
+(space-3) (no flow through the walls); local DOFs there map to -1.
 """
 import numpy as np
 
@@ -44,7 +46,12 @@ class BDMSpace:
         self.nfac = d + 1                # facets per element
         self.nint = self.nu - self.nfac * self.nf
         T, E = mesh.T, mesh.E
-        self.ndof = E * self.nf + T * self.nint
+        bnd = getattr(mesh, "bnd", np.zeros(E, dtype=bool))
+        # slot of each facet among the facets that carry moments (-1: boundary facet)
+        self.fslot = np.full(E, -1, dtype=np.int64)
+        self.fslot[~bnd] = np.arange(int((~bnd).sum()))
+        self.Eint = int((~bnd).sum())
+        self.ndof = self.Eint * self.nf + T * self.nint
         self.npres = T * self.np_
         self._build_local_bases()
 
@@ -71,25 +78,27 @@ class BDMSpace:
         # local -> global numbering
         dofs = np.empty((T, self.nu), dtype=np.int64)
         for f in range(self.nfac):
-            F = m.elem_facet[:, f]
+            sl = self.fslot[m.elem_facet[:, f]]
             for j in range(self.nf):
-                dofs[:, f * self.nf + j] = F * self.nf + j
-        E = m.E
-        dofs[:, nr:] = E * self.nf + tt[:, None] * self.nint + np.arange(self.nint)[None, :]
+                dofs[:, f * self.nf + j] = np.where(sl >= 0, sl * self.nf + j, -1)
+        dofs[:, nr:] = self.Eint * self.nf + tt[:, None] * self.nint + np.arange(self.nint)[None, :]
         self.dofs = dofs
+        # gather/scatter index: -1 (a zero boundary moment) goes to a trailing zero slot
+        self.dofs_x = np.where(dofs >= 0, dofs, self.ndof)
 
     # ---- coefficient conversions -------------------------------------------------
     def local_coeffs(self, U):
         """Local coefficients cU[T, d, nm] of the global BDM vector U (any dtype)."""
-        c = np.einsum("tab,tb->ta", self.A, U[self.dofs])
+        Ux = np.concatenate([U, np.zeros(1, dtype=U.dtype)])
+        c = np.einsum("tab,tb->ta", self.A, Ux[self.dofs_x])
         return c.reshape(self.mesh.T, self.d, self.nm)
 
     def assemble(self, R):
         """Functional on the global basis from its values R[T, d, nm] on the local Phi."""
         Rl = np.einsum("tab,ta->tb", self.A, R.reshape(self.mesh.T, self.nu))
-        out = np.zeros(self.ndof, dtype=Rl.dtype)
-        np.add.at(out, self.dofs.ravel(), Rl.ravel())
-        return out
+        out = np.zeros(self.ndof + 1, dtype=Rl.dtype)
+        np.add.at(out, self.dofs_x.ravel(), Rl.ravel())
+        return out[:self.ndof]
 
     def eval_ref(self, U, ref_pts):
         """Values [T, d, P] of the BDM function U at reference points ref_pts[P, d]."""

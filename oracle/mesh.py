@@ -1,7 +1,9 @@
 """Oracle mesh topology: affine maps, facets and periodic facet matching.
 
 Notation follows Sec. 2.1 of the paper: T_h the triangulation of Omega in R^d (d = 2, 3),
-F_h its facets; on a periodic mesh every facet is interior and has two sides.
+F_h its facets; on a periodic mesh every facet is interior and has two sides.  A period
+component 0 makes the domain non-periodic in that direction: its boundary facets (one side
+only) carry the no-flow condition u . n = 0 of eq. (euler-3) with g = 0.
 """
 from math import factorial
 
@@ -24,7 +26,9 @@ class OracleMesh:
     period.  For each facet the first element found is side A, the second side B; the
     facet normal n is A's outward normal and the facet parameter s (s in [0, 1] in 2D,
     (s, t) in the reference triangle in 3D) runs along A's local facet vertices:
-    x = a_0 + sum_r s_r (a_{r+1} - a_0).
+    x = a_0 + sum_r s_r (a_{r+1} - a_0).  Where a period component is 0, facets left
+    without a partner are boundary facets: bnd[F] is set and side B repeats side A (the
+    operators give boundary facets their own terms).
     """
 
     def __init__(self, xyz, period=None):
@@ -50,14 +54,12 @@ class OracleMesh:
     def _key(self, mid):
         d = self.d
         m = mid.copy()
-        if self.period is not None:
-            m = np.mod(m, self.period)
-            scale = self.period
-        else:
-            scale = np.ones(d)
+        per = self.period if self.period is not None else np.zeros(d)
+        ext = np.abs(self.xyz).reshape(-1, d).max(axis=0) + 1.0
+        scale = np.where(per > 0, per, ext)
+        m = np.where(per > 0, np.mod(m, np.where(per > 0, per, 1.0)), m)
         q = np.round(m / scale * 2 ** 30).astype(np.int64)
-        if self.period is not None:
-            q = np.mod(q, 2 ** 30)
+        q = np.where(per > 0, np.mod(q, 2 ** 30), q)
         return [tuple(r) for r in q]
 
     def _match_facets(self):
@@ -78,16 +80,24 @@ class OracleMesh:
                 sideB.append((t, f))
             else:
                 first[key] = (t, f)
-        if first:
+        walls = self.period is not None and np.any(self.period == 0)
+        if first and not walls:
             raise ValueError("oracle mesh: %d unmatched facets (non-periodic boundary)" % len(first))
+        nb = len(first)
+        for key in sorted(first, key=lambda k_: first[k_]):  # boundary facets: side B := side A
+            sideA.append(first[key])
+            sideB.append(first[key])
         sideA = np.array(sideA)
         sideB = np.array(sideB)
         self.E = len(sideA)
+        self.bnd = np.zeros(self.E, dtype=bool)
+        if nb:
+            self.bnd[self.E - nb:] = True
         self.fA_elem, self.fA_loc = sideA[:, 0], sideA[:, 1]
         self.fB_elem, self.fB_loc = sideB[:, 0], sideB[:, 1]
         self.elem_facet = np.empty((T, nfac), dtype=np.int64)
-        self.elem_facet[self.fA_elem, self.fA_loc] = np.arange(self.E)
         self.elem_facet[self.fB_elem, self.fB_loc] = np.arange(self.E)
+        self.elem_facet[self.fA_elem, self.fA_loc] = np.arange(self.E)
         # facet geometry in A's coordinates
         PA = pv[self.fA_elem, self.fA_loc]  # [E, d, d]
         self.PA = PA

@@ -9,7 +9,10 @@ eq. (viscous)).  Readings of the paper used here:
   average (identical to either side for H(div) velocities);
 * jumps of vectors and tensors are the tensor jumps [[u (x) n]] = u+ (x) n+ + u- (x) n-,
   (grad u)_ij = du_i/dx_j and ":" the Frobenius product;
-* h in the penalty is h_F = min(h_T+, h_T-) with h_T = (d! |T|)^(1/d).
+* h in the penalty is h_F = min(h_T+, h_T-) with h_T = (d! |T|)^(1/d);
+* walls (boundary facets): u . n = 0 there, so the convective boundary term vanishes, and
+  the viscous facet terms run over interior facets only (eq. (viscous), free-slip
+  condition (ns-4) natural): boundary facets contribute nothing.
 
 The residual is returned on the broken local basis Phi_(c,a) of every element:
 R[t, c, a] = L(u)(m_a e_c restricted to element t), m_a the local polynomial basis.  The
@@ -104,7 +107,8 @@ class Residual:
         # -nu alpha k^2/h [[u (x) n]] : [[v (x) n]]
         viscA -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nA, self.fmA)
         viscB -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nB, self.fmB)
-        return convA + viscA, convB + viscB
+        inner = (~m.bnd).astype(float)[:, None, None]  # boundary facets: no terms
+        return (convA + viscA) * inner, (convB + viscB) * inner
 
     def facets(self, cU, out):
         m = self.mesh

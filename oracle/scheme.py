@@ -58,11 +58,13 @@ class Oracle:
         T = m.T
         rows = np.repeat(sp_.dofs, sp_.nu, axis=1).ravel()
         cols = np.tile(sp_.dofs, (1, sp_.nu)).ravel()
-        self.M = sp.csr_matrix((ML.ravel(), (rows, cols)), shape=(sp_.ndof, sp_.ndof))
+        keep = (rows >= 0) & (cols >= 0)  # zero boundary moments (walls) are not unknowns
+        self.M = sp.csr_matrix((ML.ravel()[keep], (rows[keep], cols[keep])), shape=(sp_.ndof, sp_.ndof))
         prow = (np.arange(T)[:, None] * npr + np.arange(npr)[None, :])
         brow = np.repeat(prow, sp_.nu, axis=1).ravel()
         bcol = np.tile(sp_.dofs, (1, npr)).ravel()
-        self.B = sp.csr_matrix((BL.ravel(), (brow, bcol)), shape=(sp_.npres, sp_.ndof))
+        keep = bcol >= 0
+        self.B = sp.csr_matrix((BL.ravel()[keep], (brow[keep], bcol[keep])), shape=(sp_.npres, sp_.ndof))
         self.c = cmean.ravel()
 
     def saddle_matrix(self):
@@ -210,6 +212,7 @@ class Oracle:
         vb, _ = poly_basis_nd(self.k, xb)
         uA = np.einsum("eca,era->erc", cU[m.fA_elem], va)
         uB = np.einsum("eca,era->erc", cU[m.fB_elem], vb)
+        uB = np.where(m.bnd[:, None, None], 0.0, uB)  # walls: the jump is u . n itself
         return float(np.abs(np.einsum("erc,ec->er", uA - uB, m.normal)).max())
 
     def enstrophy(self, U):
