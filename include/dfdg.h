@@ -10,8 +10,10 @@
  * hybrid-mixed Poisson problem of eq. (FE3): element-local static condensation onto
  * facet multipliers, a global symmetric positive semi-definite facet system solved by
  * preconditioned CG, and element-local recovery (Theorem 2).  Time stepping is
- * TVD-RK3 (eq. (rk3)).  Periodic triangle meshes (d = 2) and periodic tetrahedral
- * meshes (d = 3; the method is posed for d = 2, 3, Sec. 2) are supported.
+ * TVD-RK3 (eq. (rk3)).  Periodic triangle meshes (d = 2), triangle meshes with walls in
+ * the directions without period (no-flow, eq. (euler-3) with g = 0; free-slip for nu > 0,
+ * eq. (ns-3)-(ns-4)), and periodic tetrahedral meshes (d = 3; the method is posed for
+ * d = 2, 3, Sec. 2) are supported.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -170,8 +172,14 @@ typedef struct {
 /* ---- mesh (host only; a0 of the hot path) ---------------------------------------
  * dfdg_mesh_create: dim = 2: elem_xyz_host[T][3][2] vertex coordinates of each triangle,
  * counter-clockwise and non-degenerate; dim = 3: elem_xyz_host[T][4][3] of each
- * tetrahedron, positively oriented (det[v1-v0, v2-v0, v3-v0] > 0).  period_host[dim] > 0
- * (every direction periodic; every facet must match another one modulo the period).
+ * tetrahedron, positively oriented (det[v1-v0, v2-v0, v3-v0] > 0).  period_host[dim]:
+ * > 0 for a periodic direction (every facet must then match another one modulo the
+ * period); dim = 2 only: 0 for a direction with walls, where the facets without a partner
+ * are boundary facets (element R = -1 in dfdg_mesh_facets).  On a wall the velocity space
+ * has u.n = 0 (BDM_k in H_0(div), eq. (space-3)), enforced by the facet multiplier of the
+ * boundary facet in the hybrid-mixed solve; the residual has no term there: the
+ * convective flux vanishes with u.n, and the viscous facet terms of eq. (viscous) run
+ * over interior facets only, which makes the free-slip condition (ns-4) natural (Sec. 3).
  * Facets are identified by their barycentres modulo the period; a local facet f is the
  * edge (f+1)%3 -> (f+2)%3 of a triangle, the face opposite vertex f of a tetrahedron.
  * Copies its inputs. */
@@ -179,7 +187,8 @@ int dfdg_mesh_create(int dim, int n_elem, const double* elem_xyz_host,
                      const double* period_host, dfdg_mesh** out);
 void dfdg_mesh_destroy(dfdg_mesh* mesh);
 const char* dfdg_mesh_last_error(void);
-/* facets_host[E][4]: element L, local facet of L, element R, local facet of R. */
+/* facets_host[E][4]: element L, local facet of L, element R, local facet of R (R and its
+ * local facet -1 for a boundary facet). */
 int dfdg_mesh_counts(const dfdg_mesh* mesh, int* T, int* E);
 int dfdg_mesh_facets(const dfdg_mesh* mesh, int32_t* facets_host);
 

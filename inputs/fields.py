@@ -35,6 +35,20 @@ def double_shear_layer(x, y, sharpness=80.0, delta=0.05):
     return u1, u2
 
 
+def channel_shear_layer(x, y, sharpness=80.0, delta=0.05):
+    """Double shear layer in the channel [0, 1) x [0, 1] with walls at y = 0 and 1:
+    exactly divergence free and tangent to the walls.
+
+    u1 = tanh profile of ``double_shear_layer`` + (delta/2) cos(2 pi x) sin(2 pi y);
+    u2 = delta sin(2 pi x) sin^2(pi y), which vanishes on both walls.
+    """
+    x, y = np.asarray(x) * 1.0, np.asarray(y) * 1.0  # complex arguments pass through
+    base = np.where(np.real(y) <= 0.5, np.tanh(sharpness * (y - 0.25)), np.tanh(sharpness * (0.75 - y)))
+    u1 = base + 0.5 * delta * np.cos(TWO_PI * x) * np.sin(TWO_PI * y)
+    u2 = delta * np.sin(TWO_PI * x) * np.sin(np.pi * y) ** 2
+    return u1, u2
+
+
 class RandomStreamField:
     """u0 = (d psi/dy, -d psi/dx) for a seeded random trigonometric stream function.
 

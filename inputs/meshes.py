@@ -66,6 +66,13 @@ def periodic_split_square(N, order="morton", seed=0):
     return xyz, np.array([1.0, 1.0])
 
 
+def channel_split_square(N, order="morton", seed=0):
+    """The N x N split unit square as a channel: periodic in x, walls at y = 0 and y = 1
+    (period[1] = 0).  Same triangles as periodic_split_square."""
+    xyz, _ = periodic_split_square(N, order, seed)
+    return xyz, np.array([1.0, 0.0])
+
+
 def _morton_key3(i, j, k, bits):
     key = np.zeros_like(i, dtype=np.int64)
     for b in range(bits):

@@ -44,7 +44,9 @@ def residual_jacobian(orc, U):
         RA, RB = res.facet_terms(cA.astype(complex), zb)
         JAB[:, :, j] = RA.imag.reshape(E, nu) / H_CS
         JBB[:, :, j] = RB.imag.reshape(E, nu) / H_CS
-    Aloc, dofs = space.A, space.dofs
+    # dofs_x sends the normal moments on walls (not in BDM_k with u.n = 0) to a trailing
+    # slot that is cut off below
+    Aloc, dofs = space.A, space.dofs_x
     rows, cols, vals = [], [], []
 
     def add(blocks, te_out, te_in):
@@ -61,7 +63,8 @@ def residual_jacobian(orc, U):
     add(JAB, m.fA_elem, m.fB_elem)
     add(JBB, m.fB_elem, m.fB_elem)
     n = space.ndof
-    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n, n))
+    J = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(n + 1, n + 1))
+    return J[:n, :n]
 
 
 def energy_and_gradient(orc, U0, dt, steps, checkpoint_every=10):

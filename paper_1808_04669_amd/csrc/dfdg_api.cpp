@@ -131,8 +131,12 @@ extern "C" int dfdg_mesh_create(int dim, int n_elem, const double* xyz, const do
   *out = nullptr;
   if (dim != 2 && dim != 3) { g_mesh_err = "dim must be 2 or 3"; return DFDG_E_INVALID_ARG; }
   if (n_elem < 2 || !xyz || !period) { g_mesh_err = "need >= 2 elements, coordinates and a period"; return DFDG_E_INVALID_ARG; }
+  // dim = 2: a period component 0 gives that direction walls (boundary facets, no flow)
   for (int d = 0; d < dim; ++d)
-    if (!(period[d] > 0) || !std::isfinite(period[d])) { g_mesh_err = "period must be positive"; return DFDG_E_INVALID_ARG; }
+    if (!std::isfinite(period[d]) || period[d] < 0 || (dim == 3 && !(period[d] > 0))) {
+      g_mesh_err = dim == 3 ? "period must be positive (tetrahedral meshes are periodic)" : "period must be >= 0";
+      return DFDG_E_INVALID_ARG;
+    }
   const long nco = (long)dim * (dim + 1) * n_elem;
   for (long i = 0; i < nco; ++i)
     if (!std::isfinite(xyz[i])) { g_mesh_err = "non-finite vertex coordinate"; return DFDG_E_INVALID_ARG; }

@@ -195,6 +195,9 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
   for (int f = 0; f < 3; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
+    // a wall (boundary facet, nbr = -1): u.n = 0 there, so no convective flux, and the
+    // viscous facet terms run over interior facets only (free-slip natural)
+    if (nb < 0) continue;
     const int code = g.code[idx];
     const int fn = code & 3;
     const bool rev = (code >> 2) & 1;
@@ -343,6 +346,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
   for (int f = 0; f < 3; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
+    if (nb < 0) continue;  // walls contribute nothing to the residual, nor to its transpose
     const int code = g.code[idx];
     const int fn = code & 3;
     const bool rev = (code >> 2) & 1;
@@ -534,10 +538,10 @@ __global__ __launch_bounds__(kBlk) void k_gather_g(DevGeo g, const double* __res
   const int T = g.T;
   double v[3] = {0, 0, 0};
   for (int F = blockIdx.x * blockDim.x + threadIdx.x; F < g.E; F += gridDim.x * blockDim.x) {
-    const int a = g.qL[F], b = g.qR[F];
+    const int a = g.qL[F], b = g.qR[F];  // b = -1: boundary facet, one side
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
-      const double qa = q[a + (size_t)m * T], qb = q[b + (size_t)m * T];
+      const double qa = q[a + (size_t)m * T], qb = b >= 0 ? q[b + (size_t)m * T] : 0.0;
       const double x = qa + qb;
       gv[(size_t)F * NF + m] = x;
       v[0] += x * x;
@@ -1625,7 +1629,9 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
       if ((code >> 3) & 1) continue;  // the L side measures the facet
       const int nb = g.nbr[idx], fn = code & 3;
       const bool rev = (code >> 2) & 1;
-      const double n0 = g.nx[idx], n1 = g.ny[idx], isqn = g.isq[nb];
+      const bool wall = nb < 0;  // the jump across a wall is u.n itself
+      const int nbs = wall ? t : nb;
+      const double n0 = g.nx[idx], n1 = g.ny[idx], isqn = g.isq[nbs];
       for (int r = 0; r < NQF; ++r) {
         const int rn = rev ? NQF - 1 - r : r;
         double jo = 0, jn = 0;
@@ -1633,7 +1639,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
         for (int i = 0; i < P; ++i) {
           const double vo = tb.Vf[(f * NQF + r) * P + i], vn = tb.Vf[(fn * NQF + rn) * P + i];
           jo += (u[0][i] * n0 + u[1][i] * n1) * vo;
-          jn += (U[(size_t)i * T + nb] * n0 + U[(size_t)(P + i) * T + nb] * n1) * vn;
+          if (!wall) jn += (U[(size_t)i * T + nbs] * n0 + U[(size_t)(P + i) * T + nbs] * n1) * vn;
         }
         jmax = fmax(jmax, fabs(jo * isq - jn * isqn));
       }

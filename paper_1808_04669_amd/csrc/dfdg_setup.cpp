@@ -255,10 +255,16 @@ void build_ref_tables(int K, RefTables& t) {
 // Mesh: periodic facet matching
 // ---------------------------------------------------------------------------------------
 
-static bool same_mod(const double* a, const double* b, const double* per, double tol) {
+// a == b modulo the period (per[d] = 0: no period in direction d; then relative to ext[d])
+static bool same_mod(const double* a, const double* b, const double* per, const double* ext, double tol) {
   for (int d = 0; d < 2; ++d) {
-    double x = (a[d] - b[d]) / per[d];
-    x -= std::nearbyint(x);
+    double x;
+    if (per[d] > 0) {
+      x = (a[d] - b[d]) / per[d];
+      x -= std::nearbyint(x);
+    } else {
+      x = (a[d] - b[d]) / ext[d];
+    }
     if (std::fabs(x) > tol) return false;
   }
   return true;
@@ -272,6 +278,23 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
   double scale = 0;
   for (size_t i = 0; i < m.xyz.size(); ++i) scale = std::max(scale, std::fabs(m.xyz[i]));
   scale = std::max(scale, std::max(period[0], period[1]));
+  // a direction without period (period 0) has walls: facets there keep one side; keys and
+  // the facet ordering use the coordinate relative to the mesh's extent instead
+  double ext[2] = {period[0], period[1]};
+  for (int d = 0; d < 2; ++d)
+    if (!(period[d] > 0)) {
+      double mx = 0;
+      for (size_t i = d; i < m.xyz.size(); i += 2) mx = std::max(mx, std::fabs(m.xyz[i]));
+      ext[d] = 2.0 * mx + 1.0;
+    }
+  const bool walls = !(period[0] > 0) || !(period[1] > 0);
+  auto rel = [&](double x, int d) {  // position in [0, 1): modulo the period, or within the extent
+    if (period[d] > 0) {
+      const double r = x / period[d];
+      return r - std::floor(r);
+    }
+    return x / ext[d] + 0.5;
+  };
   for (int t = 0; t < T; ++t) {
     const double* v = &m.xyz[6 * (size_t)t];
     double det = (v[2] - v[0]) * (v[5] - v[1]) - (v[4] - v[0]) * (v[3] - v[1]);
@@ -292,8 +315,7 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
       const double* b = &m.xyz[6 * (size_t)t + 2 * ((f + 2) % 3)];
       uint64_t key = 0;
       for (int d = 0; d < 2; ++d) {
-        double mid = 0.5 * (a[d] + b[d]) / period[d];
-        mid -= std::floor(mid);
+        const double mid = rel(0.5 * (a[d] + b[d]), d);
         long long q = std::llround(mid * Q) % (long long)Q;
         key = (key << 32) | (uint64_t)q;
       }
@@ -318,8 +340,8 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
         const double* la = &m.xyz[6 * (size_t)L + 2 * ((fl + 1) % 3)];
         const double* lb = &m.xyz[6 * (size_t)L + 2 * ((fl + 2) % 3)];
         int rev;
-        if (same_mod(a, lb, period, 1e-9) && same_mod(b, la, period, 1e-9)) rev = 1;
-        else if (same_mod(a, la, period, 1e-9) && same_mod(b, lb, period, 1e-9)) rev = 0;
+        if (same_mod(a, lb, period, ext, 1e-9) && same_mod(b, la, period, ext, 1e-9)) rev = 1;
+        else if (same_mod(a, la, period, ext, 1e-9) && same_mod(b, lb, period, ext, 1e-9)) rev = 0;
         else {
           err = "facet endpoints of elements " + std::to_string(L) + " and " + std::to_string(t) +
                 " do not match modulo the period";
@@ -330,8 +352,8 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
         first.erase(it);
       }
     }
-  if (!first.empty()) {
-    err = std::to_string(first.size()) + " facets have no periodic partner (boundary facets are not supported)";
+  if (!first.empty() && !walls) {
+    err = std::to_string(first.size()) + " facets have no periodic partner (a boundary needs a period component 0)";
     return -2;
   }
   m.E = (int)m.fL.size();
@@ -347,9 +369,8 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
       const double* b = &m.xyz[6 * (size_t)t + 2 * ((f + 2) % 3)];
       uint32_t q[2];
       for (int d = 0; d < 2; ++d) {
-        double mid = 0.5 * (a[d] + b[d]) / period[d];
-        mid -= std::floor(mid);
-        q[d] = (uint32_t)std::min(65535.0, std::floor(mid * 65536.0));
+        const double mid = rel(0.5 * (a[d] + b[d]), d);
+        q[d] = (uint32_t)std::min(65535.0, std::max(0.0, std::floor(mid * 65536.0)));
       }
       uint64_t k = 0;
       for (int bit = 15; bit >= 0; --bit) k = (k << 2) | (((q[1] >> bit) & 1u) << 1) | ((q[0] >> bit) & 1u);
@@ -451,8 +472,9 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
     for (int f = 0; f < 3; ++f) {
       const int F = m.efacet[3 * t + f];
       const bool isR = (m.fR[F] == t && m.fRloc[F] == f);
+      const bool wall = m.fR[F] < 0;  // boundary facet: one side, nbr = -1
       const int nb = isR ? m.fL[F] : m.fR[F];
-      const int nbf = isR ? m.fLloc[F] : m.fRloc[F];
+      const int nbf = wall ? 0 : (isR ? m.fLloc[F] : m.fRloc[F]);
       const double* a = v + 2 * ((f + 1) % 3);
       const double* b = v + 2 * ((f + 2) % 3);
       const double tx = b[0] - a[0], ty = b[1] - a[1];
@@ -464,14 +486,14 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
       h.nx[idx] = ty / len;
       h.ny[idx] = -tx / len;
       h.flen[idx] = len;
-      h.sig[idx] = alpha * K * K / std::min(hT[t], hT[nb]);
+      h.sig[idx] = alpha * K * K / (wall ? hT[t] : std::min(hT[t], hT[nb]));
       h.sF[idx] = std::sqrt(len / h.detJ[t]);
     }
   }
   double zz = 0;
   for (int F = 0; F < E; ++F) {
     h.qL[F] = m.fLloc[F] * NF * T + m.fL[F];
-    h.qR[F] = m.fRloc[F] * NF * T + m.fR[F];
+    h.qR[F] = m.fR[F] < 0 ? -1 : m.fRloc[F] * NF * T + m.fR[F];  // -1: boundary facet
     const double len = h.flen[(size_t)m.fLloc[F] * T + m.fL[F]];
     h.zdef[F] = std::sqrt(len);
     zz += len;
@@ -507,6 +529,10 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
       }
     }
   } el(h, T, NP, P, NF);
+  // boundary facets have no R side: its two blocks stay zero, with the row's own column
+  for (int F = 0; F < E; ++F)
+    if (m.fR[F] < 0)
+      for (int s = 3; s < kSlots; ++s) h.cols[(size_t)s * E + F] = F;
   if (condense_elements(h, 3, NP, NU, NF, el, err)) return -2;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)

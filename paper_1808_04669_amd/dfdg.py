@@ -156,8 +156,8 @@ def rule3(k, which):
 
 
 class Mesh:
-    """A periodic simplex mesh (host object of the library): xyz[T, 3, 2] triangles or
-    xyz[T, 4, 3] tetrahedra."""
+    """A simplex mesh (host object of the library): xyz[T, 3, 2] triangles or xyz[T, 4, 3]
+    tetrahedra; period[dim] > 0 periodic, 0 (triangles) walls in that direction."""
 
     def __init__(self, xyz, period):
         lib = load_library()

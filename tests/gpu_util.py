@@ -3,14 +3,17 @@
 import numpy as np
 import torch
 
-from inputs import periodic_kuhn_cube, periodic_split_square
+from inputs import channel_split_square, periodic_kuhn_cube, periodic_split_square
 from oracle import Oracle
 from oracle.quadrature import poly_basis_nd, simplex_rule
 
 
-def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, **kw):
+def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=False, **kw):
+    """Oracle and library solver on the same mesh: the periodic unit square (or cube), or
+    with walls=True the channel periodic in x with walls at y = 0 and 1."""
     from paper_1808_04669_amd import Solver
-    xyz, per = (periodic_split_square if dim == 2 else periodic_kuhn_cube)(N, order, seed)
+    gen = channel_split_square if walls else (periodic_split_square if dim == 2 else periodic_kuhn_cube)
+    xyz, per = gen(N, order, seed)
     orc = Oracle(xyz, per, k, nu=nu) if oracle else None
     s = Solver(xyz, per, k, nu=nu, device="cuda:0", **kw)
     return orc, s, xyz, per

@@ -69,7 +69,8 @@ def test_mesh_validation(lib):
     nanx = xyz.copy()
     nanx[1, 1, 1] = np.nan
     assert _mesh(lib, nanx, per)[0] == -1
-    assert _mesh(lib, xyz, np.array([0.0, 1.0]))[0] == -1
+    assert _mesh(lib, xyz, np.array([-1.0, 1.0]))[0] == -1
+    assert _mesh(lib, xyz, np.array([np.inf, 1.0]))[0] == -1
     h = P_()
     assert lib.dfdg_mesh_create(4, 4, xyz.ctypes.data_as(P_), per.ctypes.data_as(P_), ctypes.byref(h)) == -1
     assert lib.dfdg_mesh_create(2, 4, None, per.ctypes.data_as(P_), ctypes.byref(h)) == -1
@@ -217,6 +218,69 @@ def test_facet_matrix_equals_oracle_condensation(lib, k, N):
     So_lib = So[np.ix_(idx, idx)] * np.outer(scale.ravel(), scale.ravel())
     assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
     assert np.abs(S - S.T).max() < 1e-13 * np.abs(S).max()
+
+
+@pytest.mark.parametrize("k,N", [(1, 3), (2, 4), (3, 3)])
+def test_facet_matrix_with_walls_equals_oracle_condensation(lib, k, N):
+    """On the channel (period (1, 0): walls at y = 0, 1) the boundary facets have one side
+    (element R = -1); the facet matrix still equals the condensation of the oracle's dense
+    FE3 system, whose boundary multipliers enforce u.n = 0, and keeps the constant
+    multiplier as its only kernel."""
+    from inputs import channel_split_square
+    xyz, per = channel_split_square(N, "random", seed=N + k)
+    rc, m = _mesh(lib, xyz, per)
+    assert rc == 0
+    rc, c = _ctx(lib, m, k=k)
+    assert rc == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    E, NF = s.E, s.n_f
+    cols = np.empty((5, E), dtype=np.int32)
+    vals = np.empty((5, NF, NF, E))
+    assert lib.dfdg_debug_facet_matrix(c, cols.ctypes.data_as(P_), vals.ctypes.data_as(P_)) == 0
+    lib.dfdg_ctx_destroy(c)
+    fac = np.empty((E, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(m, fac.ctypes.data_as(P_))
+    lib.dfdg_mesh_destroy(m)
+    assert E == 3 * N * N + N and (fac[:, 2] < 0).sum() == 2 * N and (fac[:, 3] < 0).sum() == 2 * N
+    S = np.zeros((E * NF, E * NF))
+    for sl in range(5):
+        for F in range(E):
+            S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
+    orc = Oracle(xyz, per, k)
+    K, nU, nW = hybrid_system_dense(orc)
+    nx = nU + nW
+    So = K[:nx, nx:].T @ np.linalg.solve(K[:nx, :nx], K[:nx, nx:])
+    om = orc.mesh
+    key = {(a, b): F for F, (a, b) in enumerate(zip(om.fA_elem, om.fA_loc))}
+    perm = np.array([key[(fac[F, 0], fac[F, 1])] for F in range(E)])
+    assert np.array_equal(om.bnd[perm], fac[:, 2] < 0)
+    scale = np.sqrt(2 * np.arange(NF) + 1)[None, :] / np.sqrt(om.flen[perm])[:, None]
+    idx = (perm[:, None] * NF + np.arange(NF)[None, :]).ravel()
+    So_lib = So[np.ix_(idx, idx)] * np.outer(scale.ravel(), scale.ravel())
+    assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
+    w = np.linalg.eigvalsh(S)
+    assert abs(w[0]) < 1e-10 * w[-1] < w[1]
+
+
+def test_mesh_periods(lib):
+    """A period component 0 means walls on triangles; negative periods, and tetrahedral
+    meshes with walls, are rejected."""
+    xyz, _ = periodic_split_square(3)
+    assert _mesh(lib, xyz, np.array([1.0, -1.0]))[0] == -1
+    rc, m = _mesh(lib, xyz, np.array([0.0, 0.0]))  # walls on all four sides
+    assert rc == 0
+    E = ctypes.c_int()
+    T = ctypes.c_int()
+    lib.dfdg_mesh_counts(m, ctypes.byref(T), ctypes.byref(E))
+    assert E.value == 3 * 9 + 2 * 3  # 3 N^2 + 2 N facets on the square with four walls
+    lib.dfdg_mesh_destroy(m)
+    from inputs import periodic_kuhn_cube
+    xyz3, _ = periodic_kuhn_cube(2)
+    h = P_()
+    per3 = np.array([1.0, 1.0, 0.0])
+    assert lib.dfdg_mesh_create(3, xyz3.shape[0], np.ascontiguousarray(xyz3).ctypes.data_as(P_),
+                                per3.ctypes.data_as(P_), ctypes.byref(h)) == -1
 
 
 @pytest.mark.parametrize("k,N", [(1, 24), (2, 20), (3, 12)])

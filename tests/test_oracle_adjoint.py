@@ -8,9 +8,9 @@ from oracle import Oracle
 from oracle.adjoint import energy_and_gradient, residual_jacobian
 
 
-def _setup(N=5, k=2, nu=1e-3):
+def _setup(N=5, k=2, nu=1e-3, walls=False):
     xyz, per = periodic_split_square(N, "random", seed=1)
-    orc = Oracle(xyz, per, k, nu=nu)
+    orc = Oracle(xyz, np.array([1.0, 0.0]) if walls else per, k, nu=nu)
     U0 = orc.project(RandomStreamField(seed=0, kmax=3))
     return orc, U0
 
@@ -24,9 +24,13 @@ def _directions(orc, n, seed=1):
     return out
 
 
+@pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("k", [1, 2, 3])
-def test_residual_jacobian_matches_finite_differences(k):
-    orc, U0 = _setup(N=4, k=k, nu=0.01)
+def test_residual_jacobian_matches_finite_differences(k, walls):
+    """Also on the channel with walls at y = 0, 1, where the space has no normal moments on
+    the wall facets."""
+    orc, U0 = _setup(N=4, k=k, nu=0.01, walls=walls)
+    assert orc.mesh.bnd.any() == walls
     J = residual_jacobian(orc, U0)
     for d in _directions(orc, 3):
         h = 1e-6

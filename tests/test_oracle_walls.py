@@ -102,3 +102,17 @@ def test_viscous_form_symmetric_and_dissipative_with_walls():
     bVU = float(U @ (o1.L(V) - o0.L(V)))
     assert abs(bUV - bVU) < 1e-10 * max(abs(bUV), 1e-30)
     assert float(U @ (o1.L(U) - o0.L(U))) < 0
+
+
+def test_channel_shear_layer_input_is_divergence_free_and_tangent():
+    """The channel's shear-layer input: div u = 0 (complex-step derivatives, exact to
+    rounding) and u.n = u2 = 0 on both walls."""
+    from inputs import channel_shear_layer
+    rng = np.random.default_rng(5)
+    x, y = rng.random(200), rng.random(200)
+    h = 1e-30
+    du1dx = channel_shear_layer(x + 1j * h, y)[0].imag / h
+    du2dy = channel_shear_layer(x, y + 1j * h)[1].imag / h
+    assert np.abs(du1dx + du2dy).max() < 1e-14
+    for yw in (0.0, 1.0):
+        assert np.abs(channel_shear_layer(x, np.full_like(x, yw))[1]).max() < 1e-17
