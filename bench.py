@@ -67,6 +67,9 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-random-order", action="store_true", help="skip the randomly numbered mesh run")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Taylor-Green run")
+    ap.add_argument("--no-local-spaces", action="store_true",
+                    help="skip the FE3 / FE4 local-space comparison")
+    ap.add_argument("--local-steps", type=int, default=50)
     ap.add_argument("--only-3d", action="store_true",
                     help="run only the 3D Taylor-Green leg and print its object (profiling)")
     ap.add_argument("--three-d-variants", default="amg,amg_matrix_free,jacobi_matrix_free",
@@ -349,6 +352,34 @@ def three_d_accuracy(args):
             "sample": f"{N}^3 Kuhn mesh, BDM_{k}, nu=1/1600, {steps} steps"}
 
 
+def local_spaces(args):
+    """The two element-local spaces of the condensation on the headline workload: FE3
+    (broken velocity + P^{k-1} pressure, projector I - D^T (D D^T)^{-1} D) and FE4 (locally
+    divergence-free velocity, projector Z (Z^T Z)^{-1} Z^T), same steps from the same state:
+    time per step, the two element kernels they differ in, and the difference of the results."""
+    from inputs import double_shear_layer
+    N, k = args.N, args.k
+    out, Us = {}, {}
+    for ls in ("fe3", "fe4"):
+        s = make_solver(N, k, "fp64", args, local_space=ls)
+        U, vmax, _ = project_field(s, double_shear_layer)
+        dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
+        t, its = timed_run(s, U, dt, args.local_steps, 2)
+        d = s.diagnostics(U)
+        rec = {"ms_per_step": 1e3 * t / args.local_steps, "pcg_iterations_per_stage": float(its.mean()),
+               "max_div": d["max_div"], "max_normal_jump": d["max_normal_jump"],
+               "setup_s": s.setup_seconds}
+        for name, which in (("k_cond_rhs", 5), ("k_recover", 6)):
+            ms, b = s.time_kernel(which, reps=100)
+            rec[name] = {"us": round(ms * 1e3, 3), "bytes": b, "GB/s": round(b / ms / 1e6, 1)}
+        out[ls] = rec
+        Us[ls] = U
+        del s
+    out["rel_diff_fe4_fe3"] = float(((Us["fe4"] - Us["fe3"]).norm() / Us["fe3"].norm()).item())
+    out["steps"] = args.local_steps
+    return out
+
+
 def adjoint_cost(args):
     """Gradient of the final kinetic energy through checkpointed TVD-RK3 steps (random
     divergence-free field, nu = 1e-3): time of the plain forward rollout, of the forward
@@ -461,6 +492,9 @@ def main():
                                    "pcg_iterations_per_stage": float(itr.mean())}
         log("random numbering", out["random_numbering"])
         del sr
+    if not args.no_local_spaces:
+        out["local_spaces"] = local_spaces(args)
+        log("local spaces", out["local_spaces"])
     if not args.no_mixed:
         out["mixed"] = mixed_vs_fp64(args)
         log("mixed", out["mixed"])

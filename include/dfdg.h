@@ -76,6 +76,7 @@ enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
 #define DFDG_HISTORY_DEPTH 6  /* earlier multipliers kept per stage for warm starts */
 #define DFDG_EXTRAPOLATE_ADAPTIVE 5  /* dfdg_params.extrapolate: order chosen per solve */
 enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1, DFDG_AMG = 2 };  /* dfdg_params.precond */
+enum { DFDG_LOCAL_FE3 = 0, DFDG_LOCAL_FE4 = 1 };  /* dfdg_params.local_space */
 
 typedef struct dfdg_mesh dfdg_mesh;
 typedef struct dfdg_ctx dfdg_ctx;
@@ -126,6 +127,17 @@ typedef struct {
                         mg_fine_fp16); with Jacobi the FP32 part is the residual alone;
                         0 = restarted refinement: FP32 PCG on an FP32 copy of S to inner_rtol,
                         FP64 refinement residual g - S lambda, restarted until ir_rtol. */
+  int local_space;   /* element-local unknowns of the condensation (triangle meshes):
+                        DFDG_LOCAL_FE3 (default): broken [P^k]^2 velocity with the P^{k-1}
+                        pressure w of eq. (FE3), the local projector applied as
+                        I - D^T (D D^T)^{-1} D (per element: packed (D D^T)^{-1});
+                        DFDG_LOCAL_FE4: the locally divergence-free velocity of eq. (FE4)
+                        (remark "More efficient implementation", Sec. 2.4) without w, in the
+                        basis Z_T = Piola image of the orthonormalised reference curls of
+                        P^{k+1}, the projector applied as Z (Z^T Z)^{-1} Z^T (per element:
+                        packed (Z^T Z)^{-1}, (2P-n_p)(2P-n_p+1)/2 doubles).  Same facet
+                        system and velocity up to rounding.  Tetrahedral meshes: must be
+                        DFDG_LOCAL_FE3 (else DFDG_E_UNSUPPORTED). */
 } dfdg_params;
 
 typedef struct {
@@ -317,12 +329,14 @@ int dfdg_diagnostics_noalloc(dfdg_ctx* ctx, const double* U_dev, dfdg_diag* out_
 
 /* ---- measurement -------------------------------------------------------------------
  * dfdg_time_kernel: launches kernel `which` `reps` times on the context stream and
- * returns the mean duration in ms.  Single kernels (which = 0, 2, 3) carry their own
- * start/stop events in the dispatch (kernel execution time, as a profiler reports it);
- * 1 and 4 are bracketed by a pair of events recorded on the stream.
+ * returns the mean duration in ms.  Single kernels (which = 0, 2, 3, and 5, 6 on triangle
+ * meshes) carry their own start/stop events in the dispatch (kernel execution time, as a
+ * profiler reports it); the others are bracketed by a pair of events recorded on the stream.
  *   which = 0: facet SpMV + (p, S p) partials (FP64);  1: PCG vector update (FP64);
  *   2: DG residual (FP64); 3: facet SpMV (FP32, MIXED contexts only);
- *   4: multigrid V-cycle (AMG contexts only).
+ *   4: multigrid V-cycle (AMG contexts only);
+ *   5: condensation right-hand side (element kernel, in the context's local space);
+ *   6: element recovery with the stage epilogue, in place on a work vector.
  * The kernels run on the context's current work vectors with a separate set of PCG
  * scalars whose stopping test never fires; the work vectors (not the warm-start
  * history) are clobbered.  bytes_out (may be NULL) receives the algorithmic bytes one

@@ -122,3 +122,27 @@ def periodic_kuhn_cube(N, order="morton", seed=0):
         for a in range(4):
             xyz[p::6, a, :] = corner + h * verts[a]
     return xyz, np.array([1.0, 1.0, 1.0])
+
+
+def distort_split_square(xyz, period, N, amplitude=0.15, seed=0):
+    """Move every vertex of an N x N split-square mesh (periodic or channel) by a seeded uniform
+    displacement in [-amplitude, amplitude] * h per coordinate, the same for every triangle
+    that shares the vertex (periodic images included), so the mesh stays conforming and its
+    triangles become all different.  Vertices on a wall (a direction with period 0) keep
+    that coordinate.  amplitude <= 0.2 keeps every triangle counter-clockwise."""
+    xyz = np.asarray(xyz, dtype=float)
+    lat = np.rint(xyz * N).astype(np.int64)  # lattice indices of the vertices
+    rng = np.random.default_rng(seed)
+    disp = rng.uniform(-amplitude, amplitude, size=(N + 1, N + 1, 2)) / N
+    out = xyz.copy()
+    for d in range(2):
+        idx = [lat[..., 0], lat[..., 1]]
+        for e in range(2):
+            if period[e] > 0:
+                idx[e] = np.mod(idx[e], N)  # periodic images share the displacement
+        move = disp[idx[0], idx[1], d]
+        if period[d] == 0:
+            wall = (lat[..., d] == 0) | (lat[..., d] == N)
+            move = np.where(wall, 0.0, move)
+        out[..., d] += move
+    return out

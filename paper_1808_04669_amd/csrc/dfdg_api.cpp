@@ -187,6 +187,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->facet_blocks = 0;
   p->matrix_free = 0;
   p->mixed_solver = 1;
+  p->local_space = DFDG_LOCAL_FE3;
 }
 
 static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
@@ -214,6 +215,10 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->facet_blocks < 0 || p->facet_blocks > 1024) { e = "facet_blocks must be in 0..1024"; return -1; }
   if (p->matrix_free != 0 && p->matrix_free != 1) { e = "matrix_free must be 0 or 1"; return -1; }
   if (p->mixed_solver != 0 && p->mixed_solver != 1) { e = "mixed_solver must be 0 or 1"; return -1; }
+  if (p->local_space != DFDG_LOCAL_FE3 && p->local_space != DFDG_LOCAL_FE4) {
+    e = "local_space must be DFDG_LOCAL_FE3 or DFDG_LOCAL_FE4";
+    return -1;
+  }
   return 0;
 }
 
@@ -233,7 +238,9 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
   }
   if (ctx->dim == 3) {  // what the tetrahedral path implements
     const char* why = prm->k > kMaxK3 ? "tetrahedral meshes: k must be 1 or 2"
-                      : prm->precision != DFDG_FP64 ? "tetrahedral meshes: FP64 only" : nullptr;
+                      : prm->precision != DFDG_FP64 ? "tetrahedral meshes: FP64 only"
+                      : prm->local_space != DFDG_LOCAL_FE3 ? "tetrahedral meshes: local_space must be DFDG_LOCAL_FE3"
+                                                           : nullptr;
     if (why) {
       g_mesh_err = why;
       delete ctx;
@@ -244,6 +251,7 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     delete ctx;
     return DFDG_E_UNSUPPORTED;
   }
+  ctx->hs.fe4 = ctx->dim == 2 && prm->local_space == DFDG_LOCAL_FE4;
   if ((ctx->dim == 3 ? build_setup3(mesh->m, prm->k, prm->alpha, ctx->hs, e)
                      : build_setup(mesh->m, prm->k, prm->alpha, ctx->hs, e))) {
     g_mesh_err = e;
@@ -341,6 +349,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   g.sig = c.take<double>(nfac * T);
   g.sF = c.take<double>(nfac * T);
   g.G = c.take<double>(h.G.size());
+  g.G4 = h.G4.empty() ? nullptr : c.take<double>(h.G4.size());
   g.qL = c.take<int>(E);
   g.qR = c.take<int>(E);
   g.zdef = c.take<double>(E);
@@ -355,6 +364,7 @@ static void carve(dfdg_ctx* ctx, char* base) {
   d.Wp = c.take<double>(tb.pw.size());
   d.Dh = c.take<double>(tb.Dh.size());
   d.Ch = c.take<double>(tb.Ch.size());
+  d.Zh = tb.Zh.empty() ? nullptr : c.take<double>(tb.Zh.size());
   d.fpidx = tb.fpidx.empty() ? nullptr : c.take<int>(tb.fpidx.size());
   d.Qf = tb.Qf.empty() ? nullptr : c.take<double>(tb.Qf.size());
   DevBsr& A = ctx->A;
@@ -550,6 +560,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<double*>(ctx->g.sig), h.sig, s));
   HIPC(up(const_cast<double*>(ctx->g.sF), h.sF, s));
   HIPC(up(const_cast<double*>(ctx->g.G), h.G, s));
+  if (ctx->g.G4) HIPC(up(const_cast<double*>(ctx->g.G4), h.G4, s));
   HIPC(up(const_cast<int*>(ctx->g.qL), h.qL, s));
   HIPC(up(const_cast<int*>(ctx->g.qR), h.qR, s));
   HIPC(up(const_cast<double*>(ctx->g.zdef), h.zdef, s));
@@ -564,6 +575,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
   HIPC(up(const_cast<double*>(ctx->tb.Wp), tb.pw, s));
   HIPC(up(const_cast<double*>(ctx->tb.Dh), tb.Dh, s));
   HIPC(up(const_cast<double*>(ctx->tb.Ch), tb.Ch, s));
+  if (ctx->tb.Zh) HIPC(up(const_cast<double*>(ctx->tb.Zh), tb.Zh, s));
   if (ctx->tb.fpidx) HIPC(up(const_cast<int*>(ctx->tb.fpidx), tb.fpidx, s));
   if (ctx->tb.Qf) HIPC(up(const_cast<double*>(ctx->tb.Qf), tb.Qf, s));
   HIPC(up(const_cast<int*>(ctx->A.cols), h.cols, s));
@@ -1409,7 +1421,7 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   if (!ms || reps < 1) return fail(ctx, DFDG_E_INVALID_ARG, "bad arguments");
   if (which == 3 && ctx->prm.precision != DFDG_MIXED) return fail(ctx, DFDG_E_INVALID_ARG, "FP32 SpMV needs a MIXED context");
   if (which == 4 && ctx->prm.precond != DFDG_AMG) return fail(ctx, DFDG_E_INVALID_ARG, "V-cycle needs an AMG context");
-  if (which < 0 || which > 4) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
+  if (which < 0 || which > 6) return fail(ctx, DFDG_E_INVALID_ARG, "unknown kernel id");
   hipStream_t s = ctx->stream;
   const long T = ctx->T, E = ctx->E, NF = ctx->NF, P = ctx->P, NS = ctx->A.ns;
   // a running PCG state whose stopping test never fires, and finite partials
@@ -1427,6 +1439,10 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
       case 1: return launch_pcg_update(NF, ctx->prm.precond == DFDG_BLOCK_JACOBI ? 1 : 0, ctx->g, ctx->A, ctx->p[1], ctx->Sp,
                                        ctx->gv, ctx->r, ctx->z, pb, 1, s);  // writes rz[1], reads rz[0]
       case 2: return el_residual(ctx, false, ctx->Ustage, ctx->Lbuf, s);
+      case 5: return el_cond_rhs(ctx, false, ctx->Lbuf, s);
+      case 6:  // the stage epilogue u = a U^n + b (U^s + dt W(F - C^T lambda)), in place
+        return el_recover(ctx, false, ctx->Lbuf, ctx->lamx, ctx->Ustage, 1, 0.5, ctx->Ustage, 0.5, ctx->Ustage, 1e-30,
+                          s);
       case 4:
         if (ctx->prm.mg_fp32) return launch_vcycle<float, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
         return launch_vcycle<double, double>(NF, ctx->g, ctx->A, ctx->mg, ctx->r, ctx->z, pb.rz[0], pb.sc, s);
@@ -1437,7 +1453,8 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
   // single-kernel measurements (SpMV, residual) attach the events to the dispatch itself,
   // so that end - start is the kernel's execution; the V-cycle (several kernels) is
   // bracketed by events recorded on the stream
-  const bool single = which != 1 && which != 4;
+  // (the tetrahedral condensation kernels do not take dispatch events)
+  const bool single = which == 0 || which == 2 || which == 3 || ((which == 5 || which == 6) && ctx->dim == 2);
   std::vector<hipEvent_t> ev(2 * (size_t)reps);
   for (auto& e : ev) HIPC(hipEventCreate(&e));
   for (int i = 0; i < reps; ++i) {
@@ -1502,6 +1519,15 @@ extern "C" int dfdg_time_kernel(dfdg_ctx* ctx, int which, int reps, float* ms, d
           }
         }
         b += H.n_coarse * (double)H.n_coarse * vb;
+        break;
+      }
+      case 5:    // F in, face coefficients out; Jinv; the packed local inverse (FE4: and det J,
+      case 6: {  // 1/sqrt(det J)); per face code, sqrt(|F|/det), normal (6: face id and the
+                 // face's multipliers in, and the stage state U in and out, as timed here)
+        const int dm = ctx->dim, nfac = dm + 1;
+        const double loc = ctx->g.G4 ? nG4pk(ctx->K) * 8.0 + 16.0 : (dm == 3 ? nGpk3(ctx->K) : nGpk(ctx->K)) * 8.0;
+        const double per_face = which == 5 ? 4.0 + (1 + dm) * 8.0 + NF * 8.0 : 2 * 4.0 + (1 + dm) * 8.0 + NF * 8.0;
+        b = T * (dm * P * 8.0 + dm * dm * 8.0 + loc + nfac * per_face + (which == 6 ? 2.0 * dm * P * 8.0 : 0.0));
         break;
       }
       default: b = E * (NS * NF * NF * 4.0 + NS * 4.0 + 4.0 * NF * 4.0); break;

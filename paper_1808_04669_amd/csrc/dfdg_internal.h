@@ -17,6 +17,10 @@ __host__ __device__ constexpr int nP(int K) { return (K + 1) * (K + 2) / 2; }   
 __host__ __device__ constexpr int nPp(int K) { return K * (K + 1) / 2; }         // dim P^{K-1}(T)
 __host__ __device__ constexpr int nF(int K) { return K + 1; }                    // dim P^K(F)
 __host__ __device__ constexpr int nGpk(int K) { return nPp(K) * (nPp(K) + 1) / 2; }  // packed (D D^T)^{-1}
+// dim of the locally divergence-free [P^K(T)]^2 (curls of P^{K+1} modulo constants), and its
+// packed Gram inverse (the reduced local space of eq. (FE4))
+__host__ __device__ constexpr int nDF(int K) { return 2 * nP(K) - nPp(K); }
+__host__ __device__ constexpr int nG4pk(int K) { return nDF(K) * (nDF(K) + 1) / 2; }
 // Collapsed Gauss-Legendre triangle rule exact for degree p: nu x nv points.
 __host__ __device__ constexpr int triNu(int p) { return (p + 2) / 2; }
 __host__ __device__ constexpr int triNv(int p) { return (p + 3) / 2; }
@@ -63,6 +67,9 @@ struct RefTables {
   std::vector<double> Vp;            // projection points [q][i]
   std::vector<double> Dh;            // [a][j][i] = int dpsi_i/dxi_a psi_j, j < NP
   std::vector<double> Ch;            // [f][m][i] = int_0^1 l_m(s) psi_i(xhat_f(s)) ds
+  // triangles: orthonormal basis of the reference element's divergence-free [P^K]^2 (the
+  // reference curls of the P^{K+1} modes, orthonormalised), [r][c][i], r < nDF(K)
+  std::vector<double> Zh;
   // tetrahedra: rules in 3 reference coordinates ([n][3]), 4 faces; a face point r seen from
   // the neighbour through vertex permutation p (0..5) is the neighbour's point fpidx[p][r];
   // Qf[p][m][n] = <mu_m(face param q), mu_n(own face param)> for the face parameter q that
@@ -108,6 +115,10 @@ struct DevGeo {
   const double* sig;    // [3][T] alpha k^2 / h_F
   const double* sF;     // [3][T] sqrt(|F| / detJ)
   const double* G;      // [nGpk][T] packed lower triangle of (D_T D_T^T)^{-1}
+  // reduced local space of eq. (FE4) (triangles, dfdg_params.local_space), else null:
+  // [nG4pk][T] packed lower triangle of (Z_T^T Z_T)^{-1}, Z_T = (J (x) I_P) Zhat / sqrt(det J)
+  // the element's locally divergence-free basis (Piola image of Zhat)
+  const double* G4;
   const int* qL;        // [E] f_L*NF*T + L : base of L's contribution in a [3][NF][T] array
   const int* qR;        // [E]
   const double* zdef;   // [E] normalised kernel vector of S (component m = 0)
@@ -117,6 +128,7 @@ struct DevTabs {
   const double* Vf; const double* Gf; const double* Wf;
   const double* Vp; const double* Wp;
   const double* Dh; const double* Ch;
+  const double* Zh;                    // triangles: RefTables::Zh
   const int* fpidx; const double* Qf;  // tetrahedra: face point and face basis permutations
 };
 struct DevBsr {

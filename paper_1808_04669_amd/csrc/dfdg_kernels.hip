@@ -76,6 +76,54 @@ __device__ inline void apply_W(R (&y)[2][nP(K)], const R (&Ji)[2][2], const doub
   }
 }
 
+// The same projector computed on the reduced local space of eq. (FE4):
+// W_T = Z_T (Z_T^T Z_T)^{-1} Z_T^T with the element's locally divergence-free basis
+// Z_T = (J (x) I_P) Zhat / sqrt(det J) (the Piola image of the reference basis Zhat, so only
+// J and the packed Gram inverse G4 are per element), J = det J adj(Jinv).
+template <int K>
+__device__ inline void apply_W4(double (&y)[2][nP(K)], const double (&Ji)[2][2], double det, double isq,
+                                const double* __restrict__ G4, int T, int t, const double* Zh) {
+  constexpr int P = nP(K), ND = nDF(K);
+  const auto Z = cst(Zh);
+  const double J[2][2] = {{det * Ji[1][1], -det * Ji[0][1]}, {-det * Ji[1][0], det * Ji[0][0]}};
+  double x[2][P];  // J^T y: the reference components
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    x[0][i] = J[0][0] * y[0][i] + J[1][0] * y[1][i];
+    x[1][i] = J[0][1] * y[0][i] + J[1][1] * y[1][i];
+  }
+  double h[ND];
+#pragma unroll
+  for (int r = 0; r < ND; ++r) {
+    double s = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) s += Z[(r * 2 + 0) * P + i] * x[0][i] + Z[(r * 2 + 1) * P + i] * x[1][i];
+    h[r] = isq * s;
+  }
+  double e[ND];
+#pragma unroll
+  for (int r = 0; r < ND; ++r) e[r] = 0;
+#pragma unroll
+  for (int j = 0, p = 0; j < ND; ++j)
+#pragma unroll
+    for (int l = 0; l <= j; ++l, ++p) {
+      const double gv = G4[(size_t)p * T + t];
+      e[j] += gv * h[l];
+      if (l != j) e[l] += gv * h[j];
+    }
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    double z0 = 0, z1 = 0;
+#pragma unroll
+    for (int r = 0; r < ND; ++r) {
+      z0 += Z[(r * 2 + 0) * P + i] * e[r];
+      z1 += Z[(r * 2 + 1) * P + i] * e[r];
+    }
+    y[0][i] = isq * (J[0][0] * z0 + J[0][1] * z1);
+    y[1][i] = isq * (J[1][0] * z0 + J[1][1] * z1);
+  }
+}
+
 template <typename R>
 __device__ inline void load_Jinv(const DevGeo& g, int t, R (&Ji)[2][2]) {
   Ji[0][0] = (R)g.Jinv[t];
@@ -430,7 +478,7 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
 // ---------------------------------------------------------------------------------------
 // C_{T,f}: (C y)_m = sgn_m sqrt(|F|/detJ) sum_c n_c sum_i Chat_f[m][i] y[c][i], with
 // sgn_m = (-1)^m when the element traverses the facet against the facet's parameter.
-template <int K, typename FT>
+template <int K, typename FT, bool FE4>
 __global__ __launch_bounds__(kEBlk) void k_cond_rhs(DevGeo g, DevTabs tb, const FT* __restrict__ F,
                                                     double* __restrict__ q) {
   constexpr int P = nP(K), NF = nF(K);
@@ -444,7 +492,8 @@ __global__ __launch_bounds__(kEBlk) void k_cond_rhs(DevGeo g, DevTabs tb, const 
     for (int i = 0; i < P; ++i) y[c][i] = (double)F[(size_t)(c * P + i) * T + t];
   double Ji[2][2];
   load_Jinv(g, t, Ji);
-  apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
+  if constexpr (FE4) apply_W4<K>(y, Ji, g.detJ[t], g.isq[t], g.G4, T, t, tb.Zh);
+  else apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
 #pragma unroll
   for (int f = 0; f < 3; ++f) {
     const size_t idx = (size_t)f * T + t;
@@ -470,7 +519,7 @@ __global__ __launch_bounds__(kEBlk) void k_cond_rhs(DevGeo g, DevTabs tb, const 
 // ---------------------------------------------------------------------------------------
 // a6: recovery u_T = W_T (F_T - C_T^T lambda_T) with the RK3 combination epilogue
 // ---------------------------------------------------------------------------------------
-template <int K, typename FT>
+template <int K, typename FT, bool FE4>
 // out may alias Un or Us: each thread reads its own entries before writing them.
 __global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const FT* __restrict__ F,
                                                    const double* __restrict__ lam, double* out, int mode, double ca,
@@ -508,7 +557,8 @@ __global__ __launch_bounds__(kEBlk) void k_recover(DevGeo g, DevTabs tb, const F
   }
   double Ji[2][2];
   load_Jinv(g, t, Ji);
-  apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
+  if constexpr (FE4) apply_W4<K>(y, Ji, g.detJ[t], g.isq[t], g.G4, T, t, tb.Zh);
+  else apply_W<K, double>(y, Ji, g.G, T, t, tb.Dh);
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
@@ -1797,9 +1847,16 @@ hipError_t launch_residual_vjp(int K, const DevGeo& g, const DevTabs& tb, const 
 
 hipError_t launch_cond_rhs(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, double* q,
                            hipStream_t s) {
+  // the reduced local space (g.G4 set) is one more template instance
+  const dim3 gr(nblk(g.T, kEBlk)), bl(kEBlk);
   DFDG_DISPATCH_K(K, {
-    if (fp32in) hipLaunchKernelGGL((k_cond_rhs<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const float*)F, q);
-    else hipLaunchKernelGGL((k_cond_rhs<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const double*)F, q);
+    if (g.G4) {
+      if (fp32in) DFDG_LAUNCH_TIMED((k_cond_rhs<KK, float, true>), gr, bl, 0, s, g, tb, (const float*)F, q);
+      else DFDG_LAUNCH_TIMED((k_cond_rhs<KK, double, true>), gr, bl, 0, s, g, tb, (const double*)F, q);
+    } else {
+      if (fp32in) DFDG_LAUNCH_TIMED((k_cond_rhs<KK, float, false>), gr, bl, 0, s, g, tb, (const float*)F, q);
+      else DFDG_LAUNCH_TIMED((k_cond_rhs<KK, double, false>), gr, bl, 0, s, g, tb, (const double*)F, q);
+    }
   });
   return hipGetLastError();
 }
@@ -1807,13 +1864,23 @@ hipError_t launch_cond_rhs(int K, bool fp32in, const DevGeo& g, const DevTabs& t
 hipError_t launch_recover(int K, bool fp32in, const DevGeo& g, const DevTabs& tb, const void* F, const double* lam,
                           double* out, int mode, double a, const double* Un, double b, const double* Us, double dt,
                           hipStream_t s) {
+  const dim3 gr(nblk(g.T, kEBlk)), bl(kEBlk);
   DFDG_DISPATCH_K(K, {
-    if (fp32in)
-      hipLaunchKernelGGL((k_recover<KK, float>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const float*)F, lam, out,
-                         mode, a, Un, b, Us, dt);
-    else
-      hipLaunchKernelGGL((k_recover<KK, double>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, (const double*)F, lam,
-                         out, mode, a, Un, b, Us, dt);
+    if (g.G4) {
+      if (fp32in)
+        DFDG_LAUNCH_TIMED((k_recover<KK, float, true>), gr, bl, 0, s, g, tb, (const float*)F, lam, out, mode, a, Un, b,
+                           Us, dt);
+      else
+        DFDG_LAUNCH_TIMED((k_recover<KK, double, true>), gr, bl, 0, s, g, tb, (const double*)F, lam, out, mode, a, Un,
+                           b, Us, dt);
+    } else {
+      if (fp32in)
+        DFDG_LAUNCH_TIMED((k_recover<KK, float, false>), gr, bl, 0, s, g, tb, (const float*)F, lam, out, mode, a, Un,
+                           b, Us, dt);
+      else
+        DFDG_LAUNCH_TIMED((k_recover<KK, double, false>), gr, bl, 0, s, g, tb, (const double*)F, lam, out, mode, a, Un,
+                           b, Us, dt);
+    }
   });
   return hipGetLastError();
 }

@@ -249,6 +249,40 @@ void build_ref_tables(int K, RefTables& t) {
         for (int i = 0; i < P; ++i) t.Ch[(f * t.NF + m) * P + i] += cw[r] * l * v[i];
       }
     }
+  // Zh: the divergence-free [P^K]^2 of the reference element is spanned by the curls
+  // (d psi/d eta, -d psi/d xi) of the non-constant modes psi of P^{K+1} (the local basis of
+  // eq. (FE4) built from stream functions).  Coefficients on the orthonormal P^K modes by
+  // exact quadrature (degree 2K), then orthonormalised by modified Gram-Schmidt, twice.
+  {
+    const int P1 = nP(K + 1), ND = nDF(K), NU = 2 * P;
+    std::vector<double> zp, zw, v1(P1), g1(2 * P1);
+    triangle_rule(2 * K, zp, zw);
+    std::vector<double> Zc((size_t)(P1 - 1) * NU, 0.0);
+    for (size_t q = 0; q < zw.size(); ++q) {
+      dubiner(K, zp[2 * q], zp[2 * q + 1], v.data(), nullptr);
+      dubiner(K + 1, zp[2 * q], zp[2 * q + 1], v1.data(), g1.data());
+      for (int b = 1; b < P1; ++b)
+        for (int i = 0; i < P; ++i) {
+          Zc[(size_t)(b - 1) * NU + 0 * P + i] += zw[q] * g1[P1 + b] * v[i];
+          Zc[(size_t)(b - 1) * NU + 1 * P + i] -= zw[q] * g1[b] * v[i];
+        }
+    }
+    for (int r = 0; r < ND; ++r) {
+      double* zr = &Zc[(size_t)r * NU];
+      for (int pass = 0; pass < 2; ++pass)
+        for (int l = 0; l < r; ++l) {
+          const double* zl = &Zc[(size_t)l * NU];
+          double d = 0;
+          for (int x = 0; x < NU; ++x) d += zl[x] * zr[x];
+          for (int x = 0; x < NU; ++x) zr[x] -= d * zl[x];
+        }
+      double n2 = 0;
+      for (int x = 0; x < NU; ++x) n2 += zr[x] * zr[x];
+      const double inv = 1.0 / std::sqrt(n2);  // n2 > 0: the curl is injective modulo constants
+      for (int x = 0; x < NU; ++x) zr[x] *= inv;
+    }
+    t.Zh = Zc;  // [r][c][i] with r < ND = P1 - 1
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -446,6 +480,8 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
   h.sig.assign(3 * (size_t)T, 0);
   h.sF.assign(3 * (size_t)T, 0);
   h.G.assign((size_t)nGpk(K) * T, 0);
+  if (h.fe4) h.G4.assign((size_t)nG4pk(K) * T, 0);
+  else h.G4.clear();
   h.qL.assign(E, 0);
   h.qR.assign(E, 0);
   h.zdef.assign(E, 0);
@@ -528,6 +564,21 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
         }
       }
     }
+    // Z_T = (J (x) I_P) Zhat / sqrt(det J): the Piola image of the reference basis, which the
+    // map keeps divergence-free; J = det J adj(Jinv)
+    bool build_Z(int t, double* Z) const override {
+      const RefTables& tb = h.tabs;
+      const int ND = nDF(h.K);
+      const double dt = h.detJ[t], is = h.isq[t];
+      const double J[2][2] = {{dt * h.Jinv[3 * (size_t)T + t], -dt * h.Jinv[1 * (size_t)T + t]},
+                              {-dt * h.Jinv[2 * (size_t)T + t], dt * h.Jinv[0 * (size_t)T + t]}};
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < P; ++i)
+          for (int r = 0; r < ND; ++r)
+            Z[(size_t)(c * P + i) * ND + r] =
+                is * (J[c][0] * tb.Zh[((size_t)r * 2 + 0) * P + i] + J[c][1] * tb.Zh[((size_t)r * 2 + 1) * P + i]);
+      return true;
+    }
   } el(h, T, NP, P, NF);
   // boundary facets have no R side: its two blocks stay zero, with the row's own column
   for (int F = 0; F < E; ++F)
@@ -574,9 +625,11 @@ int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const Cond
   // parallel loop (the L side writes slot 0 itself), so no two threads write one value
   std::vector<double> diagR((size_t)E * NF * NF, 0.0);
   std::atomic<int> bad(-1);
+  const int ND = h.fe4 ? NU - NP : 0;
   auto work = [&](int t0, int t1) {
     std::vector<double> D((size_t)NP * NU), DDt((size_t)NP * NP), C((size_t)NR * NU), CDt((size_t)NR * NP),
-        X((size_t)NR * NP), ST((size_t)NR * NR);
+        X((size_t)NR * NP), ST((size_t)NR * NR), Z((size_t)NU * ND), ZZ((size_t)ND * ND), CZ((size_t)NR * ND),
+        XZ((size_t)NR * ND);
     for (int t = t0; t < t1; ++t) {
       el.build(t, D.data(), C.data());
       for (int j = 0; j < NP; ++j)
@@ -592,19 +645,57 @@ int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const Cond
       }
       for (int j = 0, p = 0; j < NP; ++j)
         for (int l = 0; l <= j; ++l, ++p) h.G[(size_t)p * T + t] = DDt[(size_t)j * NP + l];
-      for (int r = 0; r < NR; ++r)
+      if (h.fe4) {  // eq. (FE4): S_T = (C Z)(Z^T Z)^{-1}(C Z)^T on the locally divergence-free basis
+        if (!el.build_Z(t, Z.data())) {
+          int exp = -1;
+          bad.compare_exchange_strong(exp, t);
+          return;
+        }
+        for (int a = 0; a < ND; ++a)
+          for (int b = 0; b < ND; ++b) {
+            double s = 0;
+            for (int x = 0; x < NU; ++x) s += Z[(size_t)x * ND + a] * Z[(size_t)x * ND + b];
+            ZZ[(size_t)a * ND + b] = s;
+          }
+        if (!spd_inverse(ND, ZZ.data())) {
+          int exp = -1;
+          bad.compare_exchange_strong(exp, t);
+          return;
+        }
+        for (int j = 0, p = 0; j < ND; ++j)
+          for (int l = 0; l <= j; ++l, ++p) h.G4[(size_t)p * T + t] = ZZ[(size_t)j * ND + l];
+        for (int r = 0; r < NR; ++r)
+          for (int a = 0; a < ND; ++a) {
+            double s = 0;
+            for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * Z[(size_t)x * ND + a];
+            CZ[(size_t)r * ND + a] = s;
+          }
+        for (int r = 0; r < NR; ++r)
+          for (int a = 0; a < ND; ++a) {
+            double s = 0;
+            for (int b = 0; b < ND; ++b) s += CZ[(size_t)r * ND + b] * ZZ[(size_t)b * ND + a];
+            XZ[(size_t)r * ND + a] = s;
+          }
+        for (int r = 0; r < NR; ++r)
+          for (int c2 = 0; c2 <= r; ++c2) {
+            double s = 0;
+            for (int a = 0; a < ND; ++a) s += XZ[(size_t)r * ND + a] * CZ[(size_t)c2 * ND + a];
+            ST[(size_t)r * NR + c2] = ST[(size_t)c2 * NR + r] = s;
+          }
+      }
+      for (int r = 0; r < NR && !h.fe4; ++r)
         for (int j = 0; j < NP; ++j) {
           double s = 0;
           for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * D[(size_t)j * NU + x];
           CDt[(size_t)r * NP + j] = s;
         }
-      for (int r = 0; r < NR; ++r)
+      for (int r = 0; r < NR && !h.fe4; ++r)
         for (int j = 0; j < NP; ++j) {
           double s = 0;
           for (int l = 0; l < NP; ++l) s += CDt[(size_t)r * NP + l] * DDt[(size_t)l * NP + j];
           X[(size_t)r * NP + j] = s;
         }
-      for (int r = 0; r < NR; ++r)
+      for (int r = 0; r < NR && !h.fe4; ++r)
         for (int c2 = 0; c2 <= r; ++c2) {
           double s = 0;
           for (int x = 0; x < NU; ++x) s += C[(size_t)r * NU + x] * C[(size_t)c2 * NU + x];
@@ -646,7 +737,8 @@ int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const Cond
   }
   for (auto& th : pool) th.join();
   if (bad.load() >= 0) {
-    err = "divergence matrix of element " + std::to_string(bad.load()) + " is rank deficient";
+    err = (h.fe4 ? "local divergence-free basis of element " : "divergence matrix of element ") +
+          std::to_string(bad.load()) + " is rank deficient";
     return -2;
   }
   for (int F = 0; F < E; ++F)

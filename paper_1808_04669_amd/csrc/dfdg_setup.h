@@ -30,6 +30,9 @@ struct HostSetup {
   RefTables tabs;
   int dim = 2;
   std::vector<double> Jinv, detJ, isq, nx, ny, nz, flen, sig, sF, G, zdef, vals, dinv, binv;
+  // reduced local space (eq. (FE4)): set before build_setup; G4 as DevGeo::G4
+  bool fe4 = false;
+  std::vector<double> G4;
   std::vector<int> nbr, code, efacet, qL, qR, cols;
 };
 
@@ -42,9 +45,14 @@ int build_mesh(int T, const double* xyz, const double* period, MeshHost& m, std:
 // is never formed) into the face rows of h.vals / h.cols: slot 0 the face itself, slots
 // 1..nfac-1 the other faces of its L element, nfac..2nfac-2 those of its R element (in local
 // order f+1, f+2, ...).  isR(t, f): element t is the R side of its local face f.
+//
+// With h.fe4 the condensation takes the route of eq. (FE4) instead: build_Z(t, Z) fills the
+// element's locally divergence-free basis Z [NU][ND], the packed (Z^T Z)^{-1} goes to h.G4
+// and S_T = (C Z)(Z^T Z)^{-1}(C Z)^T (the same operator: Z (Z^T Z)^{-1} Z^T = W_T).
 struct CondenseElement {
   virtual void build(int t, double* D, double* C) const = 0;
   virtual bool isR(int t, int f) const = 0;
+  virtual bool build_Z(int /*t*/, double* /*Z*/) const { return false; }
   virtual ~CondenseElement() = default;
 };
 int condense_elements(HostSetup& h, int nfac, int NP, int NU, int NF, const CondenseElement& el, std::string& err);

@@ -3,17 +3,20 @@
 import numpy as np
 import torch
 
-from inputs import channel_split_square, periodic_kuhn_cube, periodic_split_square
+from inputs import channel_split_square, distort_split_square, periodic_kuhn_cube, periodic_split_square
 from oracle import Oracle
 from oracle.quadrature import poly_basis_nd, simplex_rule
 
 
-def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=False, **kw):
+def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=False, distort=0.0, **kw):
     """Oracle and library solver on the same mesh: the periodic unit square (or cube), or
-    with walls=True the channel periodic in x with walls at y = 0 and 1."""
+    with walls=True the channel periodic in x with walls at y = 0 and 1; distort > 0 moves
+    the triangle mesh's vertices by up to that fraction of h (seeded)."""
     from paper_1808_04669_amd import Solver
     gen = channel_split_square if walls else (periodic_split_square if dim == 2 else periodic_kuhn_cube)
     xyz, per = gen(N, order, seed)
+    if distort > 0:
+        xyz = distort_split_square(xyz, per, N, distort, seed=seed + 101)
     orc = Oracle(xyz, per, k, nu=nu) if oracle else None
     s = Solver(xyz, per, k, nu=nu, device="cuda:0", **kw)
     return orc, s, xyz, per

@@ -220,6 +220,74 @@ def test_facet_matrix_equals_oracle_condensation(lib, k, N):
     assert np.abs(S - S.T).max() < 1e-13 * np.abs(S).max()
 
 
+def _lib_facet_matrix(lib, xyz, per, **kw):
+    """Dense facet matrix of a library context and the mesh's facet table."""
+    rc, m = _mesh(lib, xyz, per)
+    assert rc == 0
+    rc, c = _ctx(lib, m, **kw)
+    assert rc == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    E, NF = s.E, s.n_f
+    cols = np.empty((5, E), dtype=np.int32)
+    vals = np.empty((5, NF, NF, E))
+    assert lib.dfdg_debug_facet_matrix(c, cols.ctypes.data_as(P_), vals.ctypes.data_as(P_)) == 0
+    lib.dfdg_ctx_destroy(c)
+    fac = np.empty((E, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(m, fac.ctypes.data_as(P_))
+    lib.dfdg_mesh_destroy(m)
+    S = np.zeros((E * NF, E * NF))
+    for sl in range(5):
+        for F in range(E):
+            S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
+    return S, fac
+
+
+def _to_lib_facets(orc, S_orc, fac):
+    """An oracle facet matrix in the library's facet numbering and facet basis."""
+    om, NF = orc.mesh, orc.space.nf
+    key = {(a, b): F for F, (a, b) in enumerate(zip(om.fA_elem, om.fA_loc))}
+    perm = np.array([key[(fac[F, 0], fac[F, 1])] for F in range(fac.shape[0])])
+    scale = np.sqrt(2 * np.arange(NF) + 1)[None, :] / np.sqrt(om.flen[perm])[:, None]
+    idx = (perm[:, None] * NF + np.arange(NF)[None, :]).ravel()
+    return S_orc[np.ix_(idx, idx)] * np.outer(scale.ravel(), scale.ravel())
+
+
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_fe4_facet_matrix_equals_oracle_fe4(lib, k, walls):
+    """local_space = DFDG_LOCAL_FE4 (eq. (FE4): Piola images of the orthonormalised
+    reference curls, per-element Gram inverse) gives the facet matrix of the oracle's FE4
+    (its own stream-function basis per element) and of the library's FE3 route, on a mesh
+    with distorted vertices, so that every element has its own Gram matrix."""
+    from inputs import channel_split_square, distort_split_square
+    from oracle.fe4 import fe4_facet_matrix
+    N = 3
+    xyz, per = (channel_split_square if walls else periodic_split_square)(N, "random", seed=k)
+    xyz = distort_split_square(xyz, per, N, 0.15, seed=7 + k)
+    S4, fac = _lib_facet_matrix(lib, xyz, per, k=k, local_space=1)
+    S3, _ = _lib_facet_matrix(lib, xyz, per, k=k, local_space=0)
+    orc = Oracle(xyz, per, k)
+    So = _to_lib_facets(orc, fe4_facet_matrix(orc), fac)
+    assert np.abs(S4 - So).max() < 1e-11 * np.abs(So).max()
+    assert np.abs(S4 - S3).max() < 1e-12 * np.abs(S3).max()
+    assert np.abs(S4 - S4.T).max() < 1e-13 * np.abs(S4).max()
+
+
+def test_local_space_parameter(lib):
+    xyz, per = periodic_split_square(2)
+    rc, m = _mesh(lib, xyz, per)
+    assert _ctx(lib, m, local_space=2)[0] == -1
+    lib.dfdg_mesh_destroy(m)
+    from inputs import periodic_kuhn_cube
+    xyz3, per3 = periodic_kuhn_cube(2)
+    h = P_()
+    assert lib.dfdg_mesh_create(3, xyz3.shape[0], np.ascontiguousarray(xyz3).ctypes.data_as(P_),
+                                np.ascontiguousarray(per3, dtype=float).ctypes.data_as(P_), ctypes.byref(h)) == 0
+    assert _ctx(lib, h, local_space=1)[0] == -8  # tetrahedra: FE3 only
+    lib.dfdg_mesh_destroy(h)
+
+
 @pytest.mark.parametrize("k,N", [(1, 3), (2, 4), (3, 3)])
 def test_facet_matrix_with_walls_equals_oracle_condensation(lib, k, N):
     """On the channel (period (1, 0): walls at y = 0, 1) the boundary facets have one side
