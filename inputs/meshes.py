@@ -146,3 +146,16 @@ def distort_split_square(xyz, period, N, amplitude=0.15, seed=0):
             move = np.where(wall, 0.0, move)
         out[..., d] += move
     return out
+
+
+def inout_split_square(N, order="morton", seed=0):
+    """The N x N split unit square with an inflow boundary at x = 0 and an outflow
+    boundary at x = 1, periodic in y (period[0] = 0).  Same triangles as
+    periodic_split_square; ``outflow_at_right`` marks the outflow facets."""
+    xyz, _ = periodic_split_square(N, order, seed)
+    return xyz, np.array([0.0, 1.0])
+
+
+def outflow_at_right(mid):
+    """Boundary-facet barycentres [n, 2] -> True on the outflow boundary x = 1."""
+    return np.asarray(mid)[:, 0] > 0.5

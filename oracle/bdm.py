@@ -12,7 +12,10 @@ moment each, followed by a basis of the moment-free (interior) functions.  Two e
 that share a facet DOF then have the same normal trace there, so the assembled functions
 are in H(div).  On a mesh with walls (boundary facets) the normal moments of the boundary
 facets are not degrees of freedom: they are zero, so the space is BDM_k in H_0(div) of eq.
-(space-3) (no flow through the walls); local DOFs there map to -1.
+(space-3) (no flow through the walls); local DOFs there map to -1.  The same holds on an
+inflow boundary for the space of increments (the normal velocity is given there, Sec.
+2.5); on an outflow boundary (mesh.open) the normal moments are degrees of freedom of the
+one element that has the facet.
 """
 import numpy as np
 
@@ -47,10 +50,11 @@ class BDMSpace:
         self.nint = self.nu - self.nfac * self.nf
         T, E = mesh.T, mesh.E
         bnd = getattr(mesh, "bnd", np.zeros(E, dtype=bool))
-        # slot of each facet among the facets that carry moments (-1: boundary facet)
+        carry = ~bnd | getattr(mesh, "open", np.zeros(E, dtype=bool))
+        # slot of each facet among the facets that carry moments (-1: closed boundary facet)
         self.fslot = np.full(E, -1, dtype=np.int64)
-        self.fslot[~bnd] = np.arange(int((~bnd).sum()))
-        self.Eint = int((~bnd).sum())
+        self.fslot[carry] = np.arange(int(carry.sum()))
+        self.Eint = int(carry.sum())
         self.ndof = self.Eint * self.nf + T * self.nint
         self.npres = T * self.np_
         self._build_local_bases()

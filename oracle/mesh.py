@@ -28,10 +28,13 @@ class OracleMesh:
     (s, t) in the reference triangle in 3D) runs along A's local facet vertices:
     x = a_0 + sum_r s_r (a_{r+1} - a_0).  Where a period component is 0, facets left
     without a partner are boundary facets: bnd[F] is set and side B repeats side A (the
-    operators give boundary facets their own terms).
+    operators give boundary facets their own terms).  A boundary facet is closed (a wall,
+    or an inflow boundary: the normal velocity is given there) unless ``outflow(mid)``,
+    called with the boundary facets' barycentres [n, d], marks it open (an outflow
+    boundary of Sec. 2.5, where the pressure is zero and u.n is free): open[F].
     """
 
-    def __init__(self, xyz, period=None):
+    def __init__(self, xyz, period=None, outflow=None):
         xyz = np.asarray(xyz, dtype=float)
         self.xyz = xyz
         self.T, nv, self.d = xyz.shape
@@ -50,6 +53,10 @@ class OracleMesh:
         # h_T = (d! |T|)^(1/d): the mesh-size reading used in the penalty
         self.hT = self.detJ ** (1.0 / d)
         self._match_facets()
+        self.open = np.zeros(self.E, dtype=bool)
+        if outflow is not None and self.bnd.any():
+            F = np.nonzero(self.bnd)[0]
+            self.open[F] = np.asarray(outflow(self.PA[F].mean(axis=1)), dtype=bool)
 
     def _key(self, mid):
         d = self.d

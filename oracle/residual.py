@@ -107,8 +107,14 @@ class Residual:
         # -nu alpha k^2/h [[u (x) n]] : [[v (x) n]]
         viscA -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nA, self.fmA)
         viscB -= nu * np.einsum("er,er,ercj,ej,era->eca", wq, sig, jump_u, nB, self.fmB)
-        inner = (~m.bnd).astype(float)[:, None, None]  # boundary facets: no terms
-        return (convA + viscA) * inner, (convB + viscB) * inner
+        inner = (~m.bnd).astype(float)[:, None, None]  # boundary facets: no terms, except
+        # on an outflow boundary: -int max(u.n, 0) (u . v) with the own trace (the exterior
+        # state of backflow is zero; no viscous facet terms on any boundary)
+        opn = m.open.astype(float)[:, None, None]
+        uAn = np.einsum("erc,ec->er", uA, nA)
+        out = np.where(np.real(uAn) > 0.0, uAn, 0.0)
+        convO = -np.einsum("er,er,erc,era->eca", wq, out, uA, self.fmA)
+        return (convA + viscA) * inner + convO * opn, (convB + viscB) * inner
 
     def facets(self, cU, out):
         m = self.mesh

@@ -28,14 +28,32 @@ class Oracle:
     tetrahedra; period[d] or None.
     """
 
-    def __init__(self, xyz, period, k, nu=0.0, alpha=2.0):
-        self.mesh = OracleMesh(xyz, period)
+    def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, outflow=None, inflow=None):
+        self.mesh = OracleMesh(xyz, period, outflow)
         self.k = k
         self.d = self.mesh.d
         self.space = BDMSpace(self.mesh, k)
         self.res = Residual(self.space, nu=nu, alpha=alpha)
         self._assemble()
         self._lu = None
+        # Inflow data (Sec. 2.5): the state is u = lift + U with U in the space whose normal
+        # moments vanish on the closed boundary (walls and inflow), the lift a fixed
+        # divergence-free polynomial field of degree <= k (``inflow(x, y)``) carrying the
+        # inflow's normal velocity; the stages change U only.
+        self.cLift = None if inflow is None else self._broken_exact(inflow)
+
+    def _broken_exact(self, field):
+        """Local coefficients [T, d, nm] of a polynomial field of degree <= k (element-wise
+        L2 projection with the reference-orthonormal modes: exact)."""
+        rule = simplex_rule(self.d, 2 * self.k + 2)
+        x = self.phys_points(rule[0])
+        R = self.space.load_vector(np.stack(field(*[x[..., i] for i in range(self.d)]), axis=1), rule)
+        return R / self.mesh.detJ[:, None, None]
+
+    def state_local(self, U):
+        """Local coefficients of the state: lift (if any) + U."""
+        c = self.space.local_coeffs(U)
+        return c if self.cLift is None else c + self.cLift
 
     # ---- matrices ----------------------------------------------------------------
     def _assemble(self):
@@ -69,6 +87,12 @@ class Oracle:
 
     def saddle_matrix(self):
         n, p = self.space.ndof, self.space.npres
+        if self.mesh.open.any():
+            # an outflow boundary fixes the pressure (p = 0 there, Sec. 2.5): no mean constraint;
+            # the unused mean multiplier keeps the unknowns' layout (an identity row)
+            K = sp.bmat([[self.M, -self.B.T, None], [-self.B, None, None], [None, None, sp.identity(1)]],
+                        format="csc")
+            return K
         c = sp.csr_matrix(self.c.reshape(-1, 1))
         K = sp.bmat([[self.M, -self.B.T, None],
                      [-self.B, None, c],
@@ -115,11 +139,16 @@ class Oracle:
         return m.xyz[:, None, 0, :] + np.einsum("tir,pr->tpi", m.J, ref_pts)
 
     def eval_ref(self, U, ref_pts):
-        return self.space.eval_ref(U, ref_pts)
+        if self.cLift is None:
+            return self.space.eval_ref(U, ref_pts)
+        vals, _ = poly_basis_nd(self.k, ref_pts)
+        return np.einsum("tca,pa->tcp", self.state_local(U), vals)
 
     # ---- time stepping (eq. (rk3), mass-matrix form) ------------------------------
     def L(self, U):
-        return self.res(U)
+        if self.cLift is None:
+            return self.res(U)
+        return self.space.assemble(self.res.broken(self.state_local(U)))
 
     def rk3_step(self, U, dt):
         """One TVD-RK3 step: each stage solves M u^(s) = (combination of M u + dt L(u))."""
@@ -213,7 +242,8 @@ class Oracle:
         uA = np.einsum("eca,era->erc", cU[m.fA_elem], va)
         uB = np.einsum("eca,era->erc", cU[m.fB_elem], vb)
         uB = np.where(m.bnd[:, None, None], 0.0, uB)  # walls: the jump is u . n itself
-        return float(np.abs(np.einsum("erc,ec->er", uA - uB, m.normal)).max())
+        jn = np.abs(np.einsum("erc,ec->er", uA - uB, m.normal))
+        return float(np.where(m.open[:, None], 0.0, jn).max())  # outflow: u . n is free
 
     def enstrophy(self, U):
         """||curl_h u_h||^2 with the element-wise curl du2/dx - du1/dy."""
@@ -240,7 +270,8 @@ def hybrid_system_dense(orc):
     [T][npr], facet multipliers [E][n_f] in a basis of P^k on the facet, in the facet
     parameter (side A's direction): Legendre P_j(2s-1) on an edge, the reference
     triangle's orthonormal basis (poly_basis) on a face.  Rows: the three equations of
-    (FE3), signed so that the matrix is symmetric.  Returns (K, nU, nW).
+    (FE3), signed so that the matrix is symmetric.  An outflow facet has no multiplier (the
+    pressure is zero there, Sec. 2.5): its rows and columns stay zero.  Returns (K, nU, nW).
     """
     m, sp_, k, d = orc.mesh, orc.space, orc.k, orc.d
     T, E, nu, npr, nf = m.T, m.E, sp_.nu, sp_.np_, sp_.nf
@@ -266,6 +297,8 @@ def hybrid_system_dense(orc):
         for f in range(d + 1):
             xh, F = m.element_facet_points(np.array([t]), np.array([f]), s)
             F = int(F[0])
+            if m.open[F]:
+                continue
             v, _ = poly_basis_nd(k, xh[0])                             # [R, nm]
             isA = (m.fA_elem[F] == t) and (m.fA_loc[F] == f)
             nT = m.normal[F] if isA else -m.normal[F]
