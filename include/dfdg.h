@@ -178,7 +178,9 @@ typedef struct {
   double energy;         /* 0.5 ||u_h||^2 */
   double enstrophy;      /* ||curl_h u_h||^2 (element-wise curl) */
   double max_div;        /* max |div u_h| over element quadrature points */
-  double max_normal_jump;/* max |[[u_h . n]]| over facet quadrature points */
+  double max_normal_jump;/* max |[[u_h . n]]| over facet quadrature points (on a closed
+                            boundary facet |u_h . n|, the inflow speed on an inflow; outflow
+                            facets are skipped) */
 } dfdg_diag;
 
 /* ---- mesh (host only; a0 of the hot path) ---------------------------------------
@@ -203,6 +205,20 @@ const char* dfdg_mesh_last_error(void);
  * local facet -1 for a boundary facet). */
 int dfdg_mesh_counts(const dfdg_mesh* mesh, int* T, int* E);
 int dfdg_mesh_facets(const dfdg_mesh* mesh, int32_t* facets_host);
+/* dfdg_mesh_set_outflow: marks boundary facets as an outflow boundary (Sec. 2.5):
+ * open_host[E] (the library's facet numbering), 1 = outflow, 0 = closed; nonzero entries
+ * only on boundary facets (else DFDG_E_INVALID_ARG, and the mesh is left unchanged); a
+ * later call replaces the marks.  Contexts created afterwards use them.  A closed boundary
+ * facet is a wall or an inflow boundary: its normal velocity is fixed, so the stage
+ * increments have u.n = 0 there (an inflow's normal velocity u_in enters through the
+ * initial state, which the stages keep; a caller builds it as a lift carrying u.n = u_in
+ * plus the projection of the rest).  On an outflow facet the pressure is zero: it has no
+ * multiplier (its row of the facet matrix is the identity with a zero right-hand side, so
+ * the facet system has no kernel and no deflation) and u.n is free; the residual keeps
+ * the outgoing convective flux -int max(u.n, 0) (u . v) with the element's own trace (the
+ * exterior state of backflow is zero) and, as on every boundary, no viscous facet terms.
+ * The normal-jump diagnostic skips outflow facets. */
+int dfdg_mesh_set_outflow(dfdg_mesh* mesh, const int32_t* open_host);
 
 /* ---- context --------------------------------------------------------------------
  * dfdg_ctx_create validates the parameters and does the host part of setup

@@ -18,7 +18,7 @@ def residual_jacobian(orc, U):
     """Sparse d L / d U on the global BDM basis at the state U."""
     space, res, m = orc.space, orc.res, orc.mesh
     T, nm, nu = m.T, space.nm, space.nu
-    cU = space.local_coeffs(U)
+    cU = orc.state_local(U)  # with the inflow lift, if any (Sec. 2.5)
     # element (volume) blocks Jv[t, out, in] in the local basis
     Jv = np.zeros((T, nu, nu))
     for j in range(nu):

@@ -224,7 +224,8 @@ static bool dense_spd_inverse(int n, std::vector<double>& A) {
 }
 
 int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals,
-              const std::vector<double>& z, double theta, int max_coarse, AmgHierarchy& H, std::string& err) {
+              const std::vector<double>& z, bool singular, double theta, int max_coarse, AmgHierarchy& H,
+              std::string& err) {
   H.lv.clear();
   AmgLevel L0;
   L0.A = bsr_to_csr(E, NF, NS, cols, vals);
@@ -358,7 +359,8 @@ int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::ve
       if (C.A.col[k] == i) tr += C.A.val[k];
     }
   double bb = 0;
-  for (int i = 0; i < nc; ++i) bb += B[i] * B[i];
+  if (singular)
+    for (int i = 0; i < nc; ++i) bb += B[i] * B[i];
   const double s = tr / nc;
   if (bb > 0)
     for (int i = 0; i < nc; ++i)

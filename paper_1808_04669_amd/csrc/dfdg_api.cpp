@@ -166,6 +166,27 @@ extern "C" int dfdg_mesh_facets(const dfdg_mesh* m, int32_t* f) {
   return DFDG_OK;
 }
 
+extern "C" int dfdg_mesh_set_outflow(dfdg_mesh* m, const int32_t* open) {
+  if (!m || !open) {
+    g_mesh_err = "null pointer";
+    return DFDG_E_INVALID_ARG;
+  }
+  std::vector<uint8_t> f(m->m.E, 0);
+  for (int F = 0; F < m->m.E; ++F) {
+    if (open[F] != 0 && open[F] != 1) {
+      g_mesh_err = "outflow marks must be 0 or 1";
+      return DFDG_E_INVALID_ARG;
+    }
+    if (open[F] && m->m.fR[F] >= 0) {
+      g_mesh_err = "facet " + std::to_string(F) + " is not a boundary facet";
+      return DFDG_E_INVALID_ARG;
+    }
+    f[F] = (uint8_t)open[F];
+  }
+  m->m.fopen = std::move(f);
+  return DFDG_OK;
+}
+
 // ---------------------------------------------------------------------------------------
 // context and workspace
 // ---------------------------------------------------------------------------------------
@@ -262,8 +283,8 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     const HostSetup& h = ctx->hs;
     const int NFk = ctx->dim == 3 ? nF3(prm->k) : nF(prm->k);
     std::vector<double> z((size_t)h.E * NFk, 0.0);
-    for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.zdef[F];
-    if (build_amg(h.E, NFk, (int)(h.cols.size() / h.E), h.cols, h.vals, z, 0.08, 1000, ctx->H, e)) {
+    for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.nearnull.empty() ? h.zdef[F] : h.nearnull[F];
+    if (build_amg(h.E, NFk, (int)(h.cols.size() / h.E), h.cols, h.vals, z, h.singular, 0.08, 1000, ctx->H, e)) {
       g_mesh_err = e;
       delete ctx;
       return DFDG_E_MESH;

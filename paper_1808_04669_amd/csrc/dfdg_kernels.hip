@@ -243,10 +243,36 @@ __global__ __launch_bounds__(kEBlk) void k_residual(DevGeo g, DevTabs tb, const 
   for (int f = 0; f < 3; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
-    // a wall (boundary facet, nbr = -1): u.n = 0 there, so no convective flux, and the
-    // viscous facet terms run over interior facets only (free-slip natural)
-    if (nb < 0) continue;
     const int code = g.code[idx];
+    // a boundary facet (nbr = -1) closed by a wall or an inflow: no term (u.n = 0 on a
+    // wall; on an inflow the term acts on v.n only, which the stage increments keep 0);
+    // the viscous facet terms run over interior facets only (free-slip natural)
+    if (nb < 0 && !((code >> 4) & 1)) continue;
+    if (nb < 0) {  // outflow: -int max(u.n, 0) (u . v), own trace (backflow sees zero)
+      const R n0 = (R)g.nx[idx], n1 = (R)g.ny[idx];
+      const R li = (R)g.flen[idx] * isq;
+      for (int r = 0; r < NQF; ++r) {
+        R uo[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          R a = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) a += u[c][i] * (R)s.Vf[f][r][i];
+          uo[c] = a * isq;
+        }
+        const R un = uo[0] * n0 + uo[1] * n1;
+        if (un > (R)0) {
+          const R w = (R)s.Wf[r] * li;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const R wq = -(w * un * uo[c]);
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] = fma(wq, (R)s.Vf[f][r][i], acc[c][i]);
+          }
+        }
+      }
+      continue;
+    }
     const int fn = code & 3;
     const bool rev = (code >> 2) & 1;
     const R n0 = (R)g.nx[idx], n1 = (R)g.ny[idx];
@@ -394,8 +420,37 @@ __global__ __launch_bounds__(kEBlk) void k_residual_vjp(DevGeo g, DevTabs tb, co
   for (int f = 0; f < 3; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
-    if (nb < 0) continue;  // walls contribute nothing to the residual, nor to its transpose
     const int code = g.code[idx];
+    // closed boundary facets contribute nothing to the residual, nor to its transpose
+    if (nb < 0 && !((code >> 4) & 1)) continue;
+    if (nb < 0) {  // outflow: d/du of -int max(u.n, 0) (u . y) = -int H(u.n) [(phi.n)(u.y) + u.n (phi.y)]
+      const double n0 = g.nx[idx], n1 = g.ny[idx];
+      const double li = g.flen[idx] * isq;
+      for (int r = 0; r < NQF; ++r) {
+        double uo[2], yo[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          double a = 0, ya = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            a += u[c][i] * s.Vf[f][r][i];
+            ya += y[c][i] * s.Vf[f][r][i];
+          }
+          uo[c] = a * isq;
+          yo[c] = ya * isq;
+        }
+        const double un = uo[0] * n0 + uo[1] * n1;
+        if (un > 0.0) {
+          const double w = s.Wf[r] * li, uy = uo[0] * yo[0] + uo[1] * yo[1];
+          const double Av[2] = {-(n0 * uy + un * yo[0]), -(n1 * uy + un * yo[1])};
+#pragma unroll
+          for (int c = 0; c < 2; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] += w * Av[c] * s.Vf[f][r][i];
+        }
+      }
+      continue;
+    }
     const int fn = code & 3;
     const bool rev = (code >> 2) & 1;
     const double n0 = g.nx[idx], n1 = g.ny[idx], len = g.flen[idx], sig = g.sig[idx];
@@ -1677,6 +1732,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag(DevGeo g, DevTabs tb, const doub
       const size_t idx = (size_t)f * T + t;
       const int code = g.code[idx];
       if ((code >> 3) & 1) continue;  // the L side measures the facet
+      if ((code >> 4) & 1) continue;  // outflow boundary: u.n is free there
       const int nb = g.nbr[idx], fn = code & 3;
       const bool rev = (code >> 2) & 1;
       const bool wall = nb < 0;  // the jump across a wall is u.n itself

@@ -509,6 +509,7 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
       const int F = m.efacet[3 * t + f];
       const bool isR = (m.fR[F] == t && m.fRloc[F] == f);
       const bool wall = m.fR[F] < 0;  // boundary facet: one side, nbr = -1
+      const bool open = wall && !m.fopen.empty() && m.fopen[F];  // outflow boundary
       const int nb = isR ? m.fL[F] : m.fR[F];
       const int nbf = wall ? 0 : (isR ? m.fLloc[F] : m.fRloc[F]);
       const double* a = v + 2 * ((f + 1) % 3);
@@ -517,13 +518,14 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
       const double len = std::sqrt(tx * tx + ty * ty);
       const size_t idx = (size_t)f * T + t;
       h.nbr[idx] = nb;
-      h.code[idx] = nbf | (m.frev[F] << 2) | ((isR ? 1 : 0) << 3);
+      h.code[idx] = nbf | (m.frev[F] << 2) | ((isR ? 1 : 0) << 3) | ((open ? 1 : 0) << 4);
       h.efacet[idx] = F;
       h.nx[idx] = ty / len;
       h.ny[idx] = -tx / len;
       h.flen[idx] = len;
       h.sig[idx] = alpha * K * K / (wall ? hT[t] : std::min(hT[t], hT[nb]));
-      h.sF[idx] = std::sqrt(len / h.detJ[t]);
+      // the face rows of C_T: none on an outflow facet (no multiplier there, p = 0)
+      h.sF[idx] = open ? 0.0 : std::sqrt(len / h.detJ[t]);
     }
   }
   double zz = 0;
@@ -535,6 +537,11 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
     zz += len;
   }
   for (int F = 0; F < E; ++F) h.zdef[F] /= std::sqrt(zz);
+  h.nearnull = h.zdef;
+  h.singular = true;
+  for (int F = 0; F < E; ++F)
+    if (!m.fopen.empty() && m.fopen[F]) h.singular = false;
+  if (!h.singular) std::fill(h.zdef.begin(), h.zdef.end(), 0.0);  // S is definite: no kernel
 
   // Element condensation (eq. (FE3)): D_T = sum_a Jinv[a][c] Dh[a], C_T rows of face f are
   // sqrt(|F|/det J) n_c Ch[f] (sign (-1)^m on the R side of a reversed facet: the L side's
@@ -585,6 +592,11 @@ int build_setup(const MeshHost& m, int K, double alpha, HostSetup& h, std::strin
     if (m.fR[F] < 0)
       for (int s = 3; s < kSlots; ++s) h.cols[(size_t)s * E + F] = F;
   if (condense_elements(h, 3, NP, NU, NF, el, err)) return -2;
+  // an outflow facet's row (and column) of S is zero: its multiplier is fixed to 0 by an
+  // identity diagonal block and the zero right-hand side the element rows give it
+  for (int F = 0; F < E; ++F)
+    if (!m.fopen.empty() && m.fopen[F])
+      for (int a = 0; a < NF; ++a) h.vals[(((size_t)0 * NF + a) * NF + a) * E + F] = 1.0;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)
     for (int s = 1; s < kSlots; ++s)

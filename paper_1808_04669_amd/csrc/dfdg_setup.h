@@ -15,6 +15,7 @@ struct MeshHost {
   double period[3] = {1, 1, 1};
   std::vector<int> efacet;  // [T][3] or [T][4]
   std::vector<int> fL, fLloc, fR, fRloc;
+  std::vector<uint8_t> fopen;  // [E] or empty: 1 = outflow boundary facet (open), else closed
   std::vector<uint8_t> frev;  // triangles: R traverses the facet in the opposite direction;
                               // tetrahedra: permutation id p (L's face vertex i is R's
                               // face vertex kFacePerm[p][i])
@@ -30,6 +31,10 @@ struct HostSetup {
   RefTables tabs;
   int dim = 2;
   std::vector<double> Jinv, detJ, isq, nx, ny, nz, flen, sig, sF, G, zdef, vals, dinv, binv;
+  // sqrt|F| on mode 0, normalised: the kernel vector of S on meshes without an outflow
+  // boundary (then zdef = nearnull), the multigrid's near-null vector on every mesh
+  std::vector<double> nearnull;
+  bool singular = true;  // S has the constant multiplier as its kernel (no outflow facet)
   // reduced local space (eq. (FE4)): set before build_setup; G4 as DevGeo::G4
   bool fe4 = false;
   std::vector<double> G4;

@@ -78,6 +78,7 @@ _SIGS = {
     "dfdg_mesh_last_error": (ctypes.c_char_p, []),
     "dfdg_mesh_counts": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "dfdg_mesh_facets": (ctypes.c_int, [_P, _P]),
+    "dfdg_mesh_set_outflow": (ctypes.c_int, [_P, _P]),
     "dfdg_params_default": (None, [ctypes.POINTER(Params)]),
     "dfdg_ctx_create": (ctypes.c_int, [_P, ctypes.POINTER(Params), _P, ctypes.POINTER(_P)]),
     "dfdg_ctx_set_stream": (ctypes.c_int, [_P, _P]),
@@ -158,9 +159,11 @@ def rule3(k, which):
 
 class Mesh:
     """A simplex mesh (host object of the library): xyz[T, 3, 2] triangles or xyz[T, 4, 3]
-    tetrahedra; period[dim] > 0 periodic, 0 (triangles) walls in that direction."""
+    tetrahedra; period[dim] > 0 periodic, 0 (triangles) boundary facets in that direction,
+    closed (walls, inflow) unless ``outflow(barycentres[n, 2]) -> bool[n]`` marks them as an
+    outflow boundary."""
 
-    def __init__(self, xyz, period):
+    def __init__(self, xyz, period, outflow=None):
         lib = load_library()
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         per = np.ascontiguousarray(period, dtype=np.float64)
@@ -177,6 +180,18 @@ class Mesh:
         T, E = ctypes.c_int(), ctypes.c_int()
         lib.dfdg_mesh_counts(h, ctypes.byref(T), ctypes.byref(E))
         self.T, self.E = T.value, E.value
+        self.open = np.zeros(self.E, dtype=bool)
+        if outflow is not None:
+            fac = self.facets()
+            b = np.nonzero(fac[:, 2] < 0)[0]
+            if b.size:
+                L, f = fac[b, 0], fac[b, 1]
+                mid = 0.5 * (xyz[L, (f + 1) % 3] + xyz[L, (f + 2) % 3])  # local facet f: edge (f+1) -> (f+2)
+                self.open[b] = np.asarray(outflow(mid), dtype=bool)
+            marks = np.ascontiguousarray(self.open, dtype=np.int32)
+            rc = lib.dfdg_mesh_set_outflow(h, marks.ctypes.data_as(_P))
+            if rc != DFDG_OK:
+                raise DfdgError(rc, lib.dfdg_mesh_last_error().decode())
 
     def facets(self):
         out = np.empty((self.E, 4), dtype=np.int32)
@@ -199,12 +214,12 @@ class Solver:
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
                  precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, mg_fp32=True,
                  mg_fine_fp16=True, facet_blocks=0, matrix_free=False, mixed_solver="krylov", local_space="fe3",
-                 device="cuda:0", stream=None):
+                 outflow=None, device="cuda:0", stream=None):
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
         t0 = time.perf_counter()
-        self.mesh = Mesh(xyz, period)
+        self.mesh = Mesh(xyz, period, outflow)
         t1 = time.perf_counter()
         p = Params()
         lib.dfdg_params_default(ctypes.byref(p))

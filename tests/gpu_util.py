@@ -3,22 +3,28 @@
 import numpy as np
 import torch
 
-from inputs import channel_split_square, distort_split_square, periodic_kuhn_cube, periodic_split_square
+from inputs import (channel_split_square, distort_split_square, inout_split_square, outflow_at_right,
+                    periodic_kuhn_cube, periodic_split_square)
 from oracle import Oracle
 from oracle.quadrature import poly_basis_nd, simplex_rule
 
 
-def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=False, distort=0.0, **kw):
+def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=False, distort=0.0, inout=False,
+              inflow=None, **kw):
     """Oracle and library solver on the same mesh: the periodic unit square (or cube), or
-    with walls=True the channel periodic in x with walls at y = 0 and 1; distort > 0 moves
-    the triangle mesh's vertices by up to that fraction of h (seeded)."""
+    with walls=True the channel periodic in x with walls at y = 0 and 1, or with inout=True
+    the square periodic in y with an inflow boundary at x = 0 (the oracle's lift: the
+    polynomial field ``inflow``) and an outflow boundary at x = 1; distort > 0 moves the
+    triangle mesh's vertices by up to that fraction of h (seeded)."""
     from paper_1808_04669_amd import Solver
-    gen = channel_split_square if walls else (periodic_split_square if dim == 2 else periodic_kuhn_cube)
+    gen = (inout_split_square if inout else channel_split_square if walls
+           else (periodic_split_square if dim == 2 else periodic_kuhn_cube))
     xyz, per = gen(N, order, seed)
     if distort > 0:
         xyz = distort_split_square(xyz, per, N, distort, seed=seed + 101)
-    orc = Oracle(xyz, per, k, nu=nu) if oracle else None
-    s = Solver(xyz, per, k, nu=nu, device="cuda:0", **kw)
+    out = outflow_at_right if inout else None
+    orc = Oracle(xyz, per, k, nu=nu, outflow=out, inflow=inflow) if oracle else None
+    s = Solver(xyz, per, k, nu=nu, device="cuda:0", outflow=out, **kw)
     return orc, s, xyz, per
 
 

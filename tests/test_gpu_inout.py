@@ -1,0 +1,149 @@
+"""GPU parity with the oracle on the square with an inflow boundary at x = 0 and an outflow
+boundary at x = 1, periodic in y (Sec. 2.5): the state is a lift carrying the inflow's
+normal velocity plus an increment closed at the inflow; outflow facets have no multiplier
+(p = 0) and keep the outgoing convective flux."""
+import numpy as np
+import pytest
+import torch
+
+from inputs import RandomStreamField, eval_broken_poly, random_broken_poly
+from oracle.quadrature import triangle_rule
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import (broken_residual_on_oracle_basis, make_pair, project_field, rel_l2, transfer,  # noqa: E402
+                      values_to_lib)
+
+
+def _log(*a):
+    print(*a, flush=True)
+
+
+def _lift(x, y):  # uniform: u.n = -0.8 on the inflow boundary
+    return 0.8 + 0 * x, 0.15 + 0 * y
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+@pytest.mark.parametrize("k,N", [(1, 5), (2, 4), (3, 3), (2, 16)])
+def test_inout_mass_solve_parity(k, N, precond):
+    orc, s, _, _ = make_pair(N, k, order="random", seed=N, inout=True, cg_rtol=1e-13, precond=precond)
+    assert s.mesh.open.sum() == N
+    coef = random_broken_poly(s.T, k, seed=50 + k)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U, info = s.mass_solve(F)
+    assert info.status == 0 and info.rel_residual <= 1e-13
+    rule = triangle_rule(2 * k)
+    U_orc = orc.mass_solve(orc.space.assemble(orc.space.load_vector(eval_broken_poly(coef, rule[0]), rule)))
+    err = rel_l2(orc, s, U, U_orc)
+    d = s.diagnostics(U)
+    _log("inout mass solve", k, N, precond, "iters", info.iterations, "rel L2", err, d)
+    assert err < 1e-10
+    scale = np.sqrt(d["enstrophy"])
+    assert d["max_div"] < 1e-11 * scale and d["max_normal_jump"] < 1e-11 * scale
+
+
+@pytest.mark.parametrize("k,N", [(1, 5), (2, 4), (3, 3)])
+@pytest.mark.parametrize("nu", [0.0, 0.05])
+def test_inout_residual_parity(k, N, nu):
+    """Residual of a state with inflow, outflow and backflow (the random part exceeds the
+    mean flow in places) on every broken test function."""
+    orc, s, _, _ = make_pair(N, k, nu=nu, order="random", seed=N, inout=True, inflow=_lift)
+    U_orc = orc.project(RandomStreamField(seed=k + N, kmax=3))
+    U = transfer(orc, U_orc, s)
+    R_gpu = broken_residual_on_oracle_basis(orc, s, s.residual(U))
+    R_orc = orc.res.broken(orc.state_local(U_orc))
+    err = np.abs(R_gpu - R_orc).max() / np.abs(R_orc).max()
+    _log("inout residual", k, N, nu, err)
+    assert err < 1e-11
+
+
+@pytest.mark.parametrize("k,N,nu,steps,precond", [(1, 8, 1e-2, 5, "jacobi"), (2, 6, 0.0, 4, "amg"),
+                                                  (3, 5, 1e-3, 3, "amg")])
+def test_inout_rk3_trajectory_parity(k, N, nu, steps, precond):
+    orc, s, _, _ = make_pair(N, k, nu=nu, inout=True, inflow=_lift, cg_rtol=1e-13, precond=precond,
+                             extrapolate="adaptive")
+    U0 = orc.project(RandomStreamField(seed=7, kmax=2, norm=0.3))
+    U = transfer(orc, U0, s)  # the full state: lift + increment
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for _ in range(steps):
+        assert s.rk3_step(U, dt).status == 0
+        Uo = orc.rk3_step(Uo, dt)
+    err = rel_l2(orc, s, U, Uo)
+    _log("inout rk3", k, N, nu, err)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("k,N", [(1, 5), (2, 4)])
+def test_inout_residual_vjp_parity(k, N):
+    from oracle.adjoint import residual_jacobian
+    orc, s, _, _ = make_pair(N, k, nu=0.01, order="random", seed=4, inout=True, inflow=_lift)
+    U0 = orc.project(RandomStreamField(seed=3, kmax=2))
+    U = transfer(orc, U0, s)
+    J = residual_jacobian(orc, U0)
+    rng = np.random.default_rng(12)
+    for _ in range(2):
+        y_g, d_g = (orc.mass_solve(rng.standard_normal(orc.space.ndof)) for _ in range(2))
+        y, d = (s.load_vector(values_to_lib_raw(orc, s, v)) for v in (y_g, d_g))
+        gpu = torch.dot(s.residual_vjp(U, y), d).item()
+        ref = float(y_g @ (J @ d_g))
+        _log("inout vjp", k, N, gpu, ref)
+        assert abs(gpu - ref) < 1e-10 * (abs(ref) + 1e-3)
+
+
+def values_to_lib_raw(orc, s, V):
+    """Values at the projection points of an increment V alone (no lift)."""
+    from gpu_util import to_dev
+    pts, _ = s.proj_rule()
+    return to_dev(s, orc.space.eval_ref(V, pts))
+
+
+def test_uniform_flow_steady_at_256_bdm2():
+    """u = (1, 0) through the 256x256 BDM_2 square, inflow at x = 0, outflow at x = 1: five
+    TVD-RK3 steps keep it to rounding (an exact steady solution)."""
+    _, s, xyz, _ = make_pair(256, 2, oracle=False, inout=True, cg_rtol=1e-12, precond="amg", extrapolate="adaptive")
+    U = values_to_lib(s, lambda pts: np.stack([np.ones((s.T, len(pts))), np.zeros((s.T, len(pts)))], axis=1))
+    U0 = U.clone()
+    for _ in range(5):
+        assert s.rk3_step(U, 0.1 / 256 / 4).status == 0
+    err = ((U - U0).norm() / U0.norm()).item()
+    _log("uniform flow 256", err)
+    assert err < 1e-12
+
+
+def test_inflow_outflow_shear_layer_at_256_bdm2():
+    """A perturbed stream through the 256x256 BDM_2 square for 10 steps: the uniform lift
+    (1, 0) plus 0.2 times the channel shear layer turned by 90 degrees (divergence-free,
+    u1 = 0 on x = 0 and x = 1).  Converged solves, divergence at rounding, interior normal
+    jumps at rounding (the diagnostic's maximum is the inflow's |u.n| = 1, a closed
+    boundary facet's u.n), and the inflow's normal velocity unchanged."""
+    from inputs import channel_shear_layer
+    _, s, xyz, _ = make_pair(256, 2, oracle=False, inout=True, cg_rtol=1e-12, precond="amg", extrapolate="adaptive")
+    lift = values_to_lib(s, lambda pts: np.stack([np.ones((s.T, len(pts))), np.zeros((s.T, len(pts)))], axis=1))
+
+    def turned(x, y):
+        u, v = channel_shear_layer(y, x)
+        return 0.2 * v, 0.2 * u
+
+    P, vmax = project_field(s, xyz, turned)
+    U = lift + P
+    U_init = U.clone()
+    its = []
+    for _ in range(10):
+        info = s.rk3_step(U, 0.1 / 256 / (4 * (1 + vmax)))
+        assert info.status == 0
+        its.append(list(info.iterations))
+    d = s.diagnostics(U)
+    _log("inout 256", its, d)
+    assert d["max_div"] < 1e-11 and abs(d["max_normal_jump"] - 1.0) < 1e-11
+    # the inflow's normal velocity is the initial state's: the change of u1 at the midpoints
+    # of the facets on x = 0 vanishes (local facet f joins reference vertices f+1 and f+2)
+    from gpu_util import gpu_vals
+    refmid = np.array([[0.5, 0.5], [0.0, 0.5], [0.5, 0.0]])
+    dv = gpu_vals(s, U - U_init, refmid)  # [T, 2, 3]
+    fac = s.mesh.facets()
+    inflow = np.nonzero((fac[:, 2] < 0) & ~s.mesh.open)[0]
+    assert inflow.size == 256
+    change = np.abs(dv[fac[inflow, 0], 0, fac[inflow, 1]]).max()
+    _log("inflow normal velocity change", change, "state change", float((U - U_init).abs().max()))
+    assert change < 1e-12

@@ -274,6 +274,53 @@ def test_fe4_facet_matrix_equals_oracle_fe4(lib, k, walls):
     assert np.abs(S4 - S4.T).max() < 1e-13 * np.abs(S4).max()
 
 
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_facet_matrix_with_outflow_equals_oracle_condensation(lib, k):
+    """Inflow at x = 0 (closed), outflow at x = 1 (open), periodic in y: the library's S
+    equals the oracle's condensed FE3 system, which has no multiplier on the outflow facets,
+    with identity blocks on those rows; S is then definite."""
+    from inputs import inout_split_square, outflow_at_right
+    N = 3
+    xyz, per = inout_split_square(N, "random", seed=k)
+    rc, m = _mesh(lib, xyz, per)
+    assert rc == 0
+    E = ctypes.c_int()
+    T = ctypes.c_int()
+    lib.dfdg_mesh_counts(m, ctypes.byref(T), ctypes.byref(E))
+    fac = np.empty((E.value, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(m, fac.ctypes.data_as(P_))
+    b = fac[:, 2] < 0
+    mid = 0.5 * (xyz[fac[:, 0], (fac[:, 1] + 1) % 3] + xyz[fac[:, 0], (fac[:, 1] + 2) % 3])
+    opn = (b & outflow_at_right(mid)).astype(np.int32)
+    assert opn.sum() == N and b.sum() == 2 * N
+    bad = np.zeros(E.value, dtype=np.int32)
+    bad[np.nonzero(~b)[0][0]] = 1  # an interior facet cannot be an outflow facet
+    assert lib.dfdg_mesh_set_outflow(m, bad.ctypes.data_as(P_)) == -1
+    assert lib.dfdg_mesh_set_outflow(m, opn.ctypes.data_as(P_)) == 0
+    rc, c = _ctx(lib, m, k=k)
+    assert rc == 0
+    s = lib_mod.Sizes()
+    lib.dfdg_ctx_sizes(c, ctypes.byref(s))
+    NF = s.n_f
+    cols = np.empty((5, E.value), dtype=np.int32)
+    vals = np.empty((5, NF, NF, E.value))
+    assert lib.dfdg_debug_facet_matrix(c, cols.ctypes.data_as(P_), vals.ctypes.data_as(P_)) == 0
+    lib.dfdg_ctx_destroy(c)
+    lib.dfdg_mesh_destroy(m)
+    S = np.zeros((E.value * NF, E.value * NF))
+    for sl in range(5):
+        for F in range(E.value):
+            S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
+    orc = Oracle(xyz, per, k, outflow=outflow_at_right)
+    K, nU, nW = hybrid_system_dense(orc)
+    nx = nU + nW
+    So = _to_lib_facets(orc, K[:nx, nx:].T @ np.linalg.solve(K[:nx, :nx], K[:nx, nx:]), fac)
+    for F in np.nonzero(opn)[0]:
+        So[F * NF:(F + 1) * NF, F * NF:(F + 1) * NF] = np.eye(NF)
+    assert np.abs(S - So).max() < 1e-11 * np.abs(So).max()
+    assert np.linalg.eigvalsh(S)[0] > 1e-8 * np.abs(S).max()
+
+
 def test_local_space_parameter(lib):
     xyz, per = periodic_split_square(2)
     rc, m = _mesh(lib, xyz, per)

@@ -117,3 +117,18 @@ def test_energy_balance_closed_form():
     rhs = -(interior[~m.bnd].sum() + outflow[m.open].sum() + inflow[m.bnd & ~m.open].sum())
     assert abs(lhs - rhs) < 1e-12 * abs(rhs)
     assert inflow[m.bnd & ~m.open].sum() > 0  # the inflow carries energy in
+
+
+def test_residual_jacobian_with_outflow_matches_finite_differences():
+    """The Jacobian of L at a state with inflow and outflow (the outflow term's max(u.n, 0)
+    included) against central differences of the forward residual."""
+    from oracle.adjoint import residual_jacobian
+    o = _oracle(3, 2, nu=0.01, inflow=lambda x, y: (0.7 + 0 * x, 0 * y))
+    U0 = o.project(RandomStreamField(seed=4, kmax=2))
+    J = residual_jacobian(o, U0)
+    rng = np.random.default_rng(9)
+    for _ in range(3):
+        d = o.mass_solve(rng.standard_normal(o.space.ndof))
+        h = 1e-6
+        fd = (o.L(U0 + h * d) - o.L(U0 - h * d)) / (2 * h)
+        assert np.abs(J @ d - fd).max() < 1e-6 * np.abs(fd).max()
