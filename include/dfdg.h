@@ -10,11 +10,10 @@
  * hybrid-mixed Poisson problem of eq. (FE3): element-local static condensation onto
  * facet multipliers, a global symmetric positive semi-definite facet system solved by
  * preconditioned CG, and element-local recovery (Theorem 2).  Time stepping is
- * TVD-RK3 (eq. (rk3)).  Periodic triangle meshes (d = 2), triangle meshes with walls in
- * the directions without period (no-flow, eq. (euler-3) with g = 0; free-slip for nu > 0,
- * eq. (ns-3)-(ns-4)) or with inflow and outflow boundaries there (Sec. 2.5,
- * dfdg_mesh_set_outflow), and periodic tetrahedral meshes (d = 3; the method is posed for
- * d = 2, 3, Sec. 2) are supported.  The element-local unknowns of the condensation are
+ * TVD-RK3 (eq. (rk3)).  Triangle (d = 2) and tetrahedral (d = 3; the method is posed for
+ * d = 2, 3, Sec. 2) meshes, periodic or with walls in the directions without period
+ * (no-flow, eq. (euler-3) with g = 0; free-slip for nu > 0, eq. (ns-3)-(ns-4)); on
+ * triangles also inflow and outflow boundaries there (Sec. 2.5, dfdg_mesh_set_outflow).  The element-local unknowns of the condensation are
  * those of eq. (FE3) or, on triangles, the locally divergence-free ones of eq. (FE4)
  * (dfdg_params.local_space).
  *
@@ -191,9 +190,9 @@ typedef struct {
  * counter-clockwise and non-degenerate; dim = 3: elem_xyz_host[T][4][3] of each
  * tetrahedron, positively oriented (det[v1-v0, v2-v0, v3-v0] > 0).  period_host[dim]:
  * > 0 for a periodic direction (every facet must then match another one modulo the
- * period); dim = 2 only: 0 for a direction with walls, where the facets without a partner
- * are boundary facets (element R = -1 in dfdg_mesh_facets), closed (walls or inflows)
- * unless dfdg_mesh_set_outflow marks them as outflow.  On a wall the velocity space
+ * period); 0 for a direction with walls, where the facets without a partner are boundary
+ * facets (element R = -1 in dfdg_mesh_facets), closed (walls or inflows) unless
+ * dfdg_mesh_set_outflow marks them as outflow (triangles only).  On a wall the velocity space
  * has u.n = 0 (BDM_k in H_0(div), eq. (space-3)), enforced by the facet multiplier of the
  * boundary facet in the hybrid-mixed solve; the residual has no term there: the
  * convective flux vanishes with u.n, and the viscous facet terms of eq. (viscous) run

@@ -159,3 +159,10 @@ def inout_split_square(N, order="morton", seed=0):
 def outflow_at_right(mid):
     """Boundary-facet barycentres [n, 2] -> True on the outflow boundary x = 1."""
     return np.asarray(mid)[:, 0] > 0.5
+
+
+def channel_kuhn_cube(N, order="morton", seed=0):
+    """The N^3 Kuhn-split unit cube as a channel: periodic in x and y, walls at z = 0 and
+    z = 1 (period[2] = 0).  Same tetrahedra as periodic_kuhn_cube."""
+    xyz, _ = periodic_kuhn_cube(N, order, seed)
+    return xyz, np.array([1.0, 1.0, 0.0])

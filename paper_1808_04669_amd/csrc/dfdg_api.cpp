@@ -131,10 +131,10 @@ extern "C" int dfdg_mesh_create(int dim, int n_elem, const double* xyz, const do
   *out = nullptr;
   if (dim != 2 && dim != 3) { g_mesh_err = "dim must be 2 or 3"; return DFDG_E_INVALID_ARG; }
   if (n_elem < 2 || !xyz || !period) { g_mesh_err = "need >= 2 elements, coordinates and a period"; return DFDG_E_INVALID_ARG; }
-  // dim = 2: a period component 0 gives that direction walls (boundary facets, no flow)
+  // a period component 0 gives that direction walls (boundary facets, no flow)
   for (int d = 0; d < dim; ++d)
-    if (!std::isfinite(period[d]) || period[d] < 0 || (dim == 3 && !(period[d] > 0))) {
-      g_mesh_err = dim == 3 ? "period must be positive (tetrahedral meshes are periodic)" : "period must be >= 0";
+    if (!std::isfinite(period[d]) || period[d] < 0) {
+      g_mesh_err = "period must be finite and >= 0";
       return DFDG_E_INVALID_ARG;
     }
   const long nco = (long)dim * (dim + 1) * n_elem;
@@ -173,6 +173,10 @@ extern "C" int dfdg_mesh_set_outflow(dfdg_mesh* m, const int32_t* open) {
   }
   std::vector<uint8_t> f(m->m.E, 0);
   for (int F = 0; F < m->m.E; ++F) {
+    if (open[F] && m->m.dim == 3) {
+      g_mesh_err = "outflow boundaries: triangle meshes only";
+      return DFDG_E_UNSUPPORTED;
+    }
     if (open[F] != 0 && open[F] != 1) {
       g_mesh_err = "outflow marks must be 0 or 1";
       return DFDG_E_INVALID_ARG;

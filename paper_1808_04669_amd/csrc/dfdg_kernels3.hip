@@ -126,6 +126,9 @@ __global__ __launch_bounds__(kEBlk) void k_residual3(DevGeo g, DevTabs tb, const
   for (int f = 0; f < 4; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
+    // a wall (boundary face, nbr = -1): no convective flux (u.n = 0) and no viscous face
+    // terms (interior faces only: free slip)
+    if (nb < 0) continue;
     const int code = g.code[idx];
     const int fn = code & 3, pid = (code >> 2) & 7;
     const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
@@ -505,7 +508,7 @@ __global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const do
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       const size_t o = (size_t)F * NF + m;
-      const double y = A.mfq[a + (size_t)m * T] + A.mfq[b + (size_t)m * T];
+      const double y = A.mfq[a + (size_t)m * T] + (b >= 0 ? A.mfq[b + (size_t)m * T] : 0.0);  // b < 0: boundary
       const double pn = z[o] + beta * p_old[o];
       p_new[o] = pn;
       Sp[o] = y;
@@ -648,7 +651,9 @@ __global__ __launch_bounds__(kEBlk) void k_diag3(DevGeo g, DevTabs tb, const dou
       const int code = g.code[idx];
       if ((code >> 5) & 1) continue;  // the L side measures the face
       const int nb = g.nbr[idx], fn = code & 3, pid = (code >> 2) & 7;
-      const double n0 = g.nx[idx], n1 = g.ny[idx], n2 = g.nz[idx], isqn = g.isq[nb];
+      const bool wall = nb < 0;  // the jump across a wall is u.n itself
+      const int nbs = wall ? t : nb;
+      const double n0 = g.nx[idx], n1 = g.ny[idx], n2 = g.nz[idx], isqn = g.isq[nbs];
       for (int r = 0; r < NQF; ++r) {
         const int rn = tb.fpidx[pid * NQF + r];
         double jo = 0, jn = 0;
@@ -656,7 +661,8 @@ __global__ __launch_bounds__(kEBlk) void k_diag3(DevGeo g, DevTabs tb, const dou
         for (int i = 0; i < P; ++i) {
           const double vo = tb.Vf[(f * NQF + r) * P + i], vn = tb.Vf[(fn * NQF + rn) * P + i];
           jo += (u[0][i] * n0 + u[1][i] * n1 + u[2][i] * n2) * vo;
-          jn += (U[(size_t)i * T + nb] * n0 + U[(size_t)(P + i) * T + nb] * n1 + U[(size_t)(2 * P + i) * T + nb] * n2) * vn;
+          if (!wall)
+            jn += (U[(size_t)i * T + nbs] * n0 + U[(size_t)(P + i) * T + nbs] * n1 + U[(size_t)(2 * P + i) * T + nbs] * n2) * vn;
         }
         jmax = fmax(jmax, fabs(jo * isq - jn * isqn));
       }

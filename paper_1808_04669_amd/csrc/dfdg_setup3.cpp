@@ -446,10 +446,11 @@ void build_ref_tables3(int K, RefTables& t) {
 // ---------------------------------------------------------------------------------------
 // Mesh: periodic face matching
 // ---------------------------------------------------------------------------------------
-static bool same_mod3(const double* a, const double* b, const double* per, double tol) {
+// a == b modulo the period (per[d] = 0: no period in direction d; then relative to ext[d])
+static bool same_mod3(const double* a, const double* b, const double* per, const double* ext, double tol) {
   for (int d = 0; d < 3; ++d) {
-    double x = (a[d] - b[d]) / per[d];
-    x -= std::nearbyint(x);
+    double x = (a[d] - b[d]) / (per[d] > 0 ? per[d] : ext[d]);
+    if (per[d] > 0) x -= std::nearbyint(x);
     if (std::fabs(x) > tol) return false;
   }
   return true;
@@ -462,6 +463,22 @@ int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std
   for (int d = 0; d < 3; ++d) m.period[d] = period[d];
   double scale = std::max(period[0], std::max(period[1], period[2]));
   for (double v : m.xyz) scale = std::max(scale, std::fabs(v));
+  // directions without a period (walls): coordinates relative to an extent that covers the
+  // mesh, so that (x + ext) / (2 ext) lies in (0, 1)
+  const bool walls = period[0] == 0 || period[1] == 0 || period[2] == 0;
+  double ext[3];
+  for (int d = 0; d < 3; ++d) {
+    ext[d] = 1.0;
+    for (int t = 0; t < T; ++t)
+      for (int j = 0; j < 4; ++j) ext[d] = std::max(ext[d], 2.0 * std::fabs(m.xyz[12 * (size_t)t + 3 * j + d]));
+  }
+  auto unit = [&](double x, int d) {  // position in [0, 1): modulo the period, else in the extent
+    if (period[d] > 0) {
+      x /= period[d];
+      return x - std::floor(x);
+    }
+    return (x + ext[d]) / (2.0 * ext[d]);
+  };
   for (int t = 0; t < T; ++t) {
     const double* v = &m.xyz[12 * (size_t)t];
     double J[3][3];
@@ -485,8 +502,7 @@ int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std
     for (int f = 0; f < 4; ++f) {
       uint64_t key = 0;
       for (int d = 0; d < 3; ++d) {
-        double mid = (vert(t, f, 0)[d] + vert(t, f, 1)[d] + vert(t, f, 2)[d]) / (3.0 * period[d]);
-        mid -= std::floor(mid);
+        const double mid = unit((vert(t, f, 0)[d] + vert(t, f, 1)[d] + vert(t, f, 2)[d]) / 3.0, d);
         const long long q = std::llround(mid * Q) % (long long)Q;
         key = (key << 21) | (uint64_t)q;
       }
@@ -507,7 +523,7 @@ int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std
         int p[3] = {-1, -1, -1};
         for (int i = 0; i < 3; ++i)
           for (int j = 0; j < 3; ++j)
-            if (same_mod3(vert(L, fl, i), vert(t, f, j), period, 1e-9)) p[i] = j;
+            if (same_mod3(vert(L, fl, i), vert(t, f, j), period, ext, 1e-9)) p[i] = j;
         const int pid = face_perm_id(p);
         if (pid < 0) {
           err = "face vertices of elements " + std::to_string(L) + " and " + std::to_string(t) +
@@ -519,8 +535,8 @@ int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std
         first.erase(it);
       }
     }
-  if (!first.empty()) {
-    err = std::to_string(first.size()) + " faces have no periodic partner (boundary faces are not supported)";
+  if (!first.empty() && !walls) {  // faces left without a partner are boundary faces with walls
+    err = std::to_string(first.size()) + " faces have no periodic partner";
     return -2;
   }
   m.E = (int)m.fL.size();
@@ -532,8 +548,7 @@ int build_mesh3(int T, const double* xyz, const double* period, MeshHost& m, std
       const int t = m.fL[F], f = m.fLloc[F];
       uint32_t q[3];
       for (int d = 0; d < 3; ++d) {
-        double mid = (vert(t, f, 0)[d] + vert(t, f, 1)[d] + vert(t, f, 2)[d]) / (3.0 * period[d]);
-        mid -= std::floor(mid);
+        const double mid = unit((vert(t, f, 0)[d] + vert(t, f, 1)[d] + vert(t, f, 2)[d]) / 3.0, d);
         q[d] = (uint32_t)std::min(65535.0, std::floor(mid * 65536.0));
       }
       uint64_t k = 0;
@@ -619,10 +634,11 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
     for (int f = 0; f < 4; ++f) {
       const int F = m.efacet[4 * (size_t)t + f];
       const bool isR = (m.fR[F] == t && m.fRloc[F] == f);
+      const bool wall = m.fR[F] < 0;  // boundary face: one side, nbr = -1
       const int nb = isR ? m.fL[F] : m.fR[F];
-      const int nbf = isR ? m.fLloc[F] : m.fRloc[F];
+      const int nbf = wall ? 0 : (isR ? m.fLloc[F] : m.fRloc[F]);
       // permutation carrying this element's face vertices to the neighbour's
-      const int pid = isR ? face_perm_inverse(m.frev[F]) : (int)m.frev[F];
+      const int pid = wall ? 0 : (isR ? face_perm_inverse(m.frev[F]) : (int)m.frev[F]);
       const double* a = v + 3 * kFaceV[f][0];
       const double* b = v + 3 * kFaceV[f][1];
       const double* c = v + 3 * kFaceV[f][2];
@@ -640,14 +656,14 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
       h.ny[idx] = sgn * n[1] / nn;
       h.nz[idx] = sgn * n[2] / nn;
       h.flen[idx] = 0.5 * nn;
-      h.sig[idx] = alpha * K * K / std::min(hT[t], hT[nb]);
+      h.sig[idx] = alpha * K * K / (wall ? hT[t] : std::min(hT[t], hT[nb]));
       h.sF[idx] = std::sqrt(nn / h.detJ[t]);  // sqrt(|F| / |Fhat| / det J), |Fhat| = 1/2
     }
   }
   double zz = 0;
   for (int F = 0; F < E; ++F) {
     h.qL[F] = m.fLloc[F] * NF * T + m.fL[F];
-    h.qR[F] = m.fRloc[F] * NF * T + m.fR[F];
+    h.qR[F] = m.fR[F] < 0 ? -1 : m.fRloc[F] * NF * T + m.fR[F];  // -1: boundary face
     const double area = h.flen[(size_t)m.fLloc[F] * T + m.fL[F]];
     h.zdef[F] = std::sqrt(area);  // the constant multiplier on mode 0 of the orthonormal face basis
     zz += area;
@@ -695,6 +711,10 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
       }
     }
   } el(h, T, NP, P, NF);
+  // boundary faces have no R side: its three blocks stay zero, with the row's own column
+  for (int F = 0; F < E; ++F)
+    if (m.fR[F] < 0)
+      for (int s = 4; s < NS; ++s) h.cols[(size_t)s * E + F] = F;
   if (condense_elements(h, 4, NP, NU, NF, el, err)) return -2;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)

@@ -141,3 +141,49 @@ def test_rk3_step_vjp_with_walls_matches_finite_differences():
         adj = torch.dot(Ub, d).item()
         _log("walls step vjp", adj, fd)
         assert abs(adj - fd) < 1e-6 * abs(fd) + 1e-10
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+@pytest.mark.parametrize("k,N,mf", [(1, 3, False), (2, 2, False), (2, 3, True)])
+def test_walls_3d_mass_solve_parity(k, N, mf, precond):
+    """Tetrahedral channel (walls at z = 0, 1): mass inversion against the oracle, also
+    with the matrix-free product (boundary faces have one side in the face pass)."""
+    orc, s, _, _ = make_pair(N, k, dim=3, order="random", seed=N, walls=True, cg_rtol=1e-13, precond=precond,
+                             matrix_free=mf)
+    assert (s.mesh.facets()[:, 2] < 0).sum() == 4 * N * N
+    from gpu_util import to_dev
+    from oracle.quadrature import poly_basis_nd
+    Fb = np.random.default_rng(k).standard_normal((orc.mesh.T, 3, orc.space.nm))
+    U_orc = orc.mass_solve(orc.space.assemble(Fb))
+    pts, _ = s.proj_rule()
+    vals, _ = poly_basis_nd(k, pts)
+    # the functional Fb on the oracle's local basis, as values of a broken field whose
+    # L2 products with m_a e_c are Fb (reference-orthonormal m_a: the field sum_a Fb m_a / det J)
+    F = s.load_vector(to_dev(s, np.einsum("tca,qa->tcq", Fb / orc.mesh.detJ[:, None, None], vals)))
+    U, info = s.mass_solve(F)
+    assert info.status == 0 and info.rel_residual <= 1e-13
+    err = rel_l2(orc, s, U, U_orc)
+    d = s.diagnostics(U)
+    _log("walls 3d mass solve", k, N, mf, precond, "iters", info.iterations, "rel L2", err, d)
+    assert err < 1e-10
+    scale = np.sqrt(d["enstrophy"])
+    assert d["max_div"] < 1e-11 * scale and d["max_normal_jump"] < 1e-11 * scale
+
+
+@pytest.mark.parametrize("k,N,nu,steps", [(1, 3, 0.0, 3), (2, 2, 1e-2, 2)])
+def test_walls_3d_rk3_trajectory_parity(k, N, nu, steps):
+    from inputs import taylor_green_3d
+    orc, s, _, _ = make_pair(N, k, dim=3, nu=nu, walls=True, cg_rtol=1e-13, precond="amg", extrapolate="adaptive")
+    U0 = orc.project(taylor_green_3d)
+    U = transfer(orc, U0, s)
+    R_gpu = broken_residual_on_oracle_basis(orc, s, s.residual(U))
+    R_orc = orc.res.broken(orc.space.local_coeffs(U0))
+    rerr = np.abs(R_gpu - R_orc).max() / np.abs(R_orc).max()
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for _ in range(steps):
+        assert s.rk3_step(U, dt).status == 0
+        Uo = orc.rk3_step(Uo, dt)
+    err = rel_l2(orc, s, U, Uo)
+    _log("walls 3d residual", rerr, "rk3", k, N, nu, err)
+    assert rerr < 1e-11 and err < 1e-10

@@ -136,13 +136,16 @@ def _lib_S(lib, xyz, per, k):
 
 
 @pytest.mark.parametrize("k", [1, 2])
-def test_facet_matrix_equals_oracle_condensation_3d(lib, k):
+@pytest.mark.parametrize("walls", [False, True])
+def test_facet_matrix_equals_oracle_condensation_3d(lib, k, walls):
     """The library's 7-slot S equals the static condensation of the oracle's dense
     hybrid-mixed system onto the multipliers, after the change of face basis: the library's
     multiplier functions are the triangle's Dubiner polynomials / sqrt(2|F|), the oracle's
     its orthonormalised monomials, both in the face parameter of the face's first element
-    (a face's vertices in increasing local order)."""
-    xyz, per = periodic_kuhn_cube(2, "random", seed=5 + k)
+    (a face's vertices in increasing local order).  Also on the channel with walls at
+    z = 0, 1 (one-sided boundary rows)."""
+    from inputs import channel_kuhn_cube
+    xyz, per = (channel_kuhn_cube if walls else periodic_kuhn_cube)(2, "random", seed=5 + k)
     S, fac, s = _lib_S(lib, xyz, per, k)
     E, NF = s.E, s.n_f
     orc = Oracle(xyz, per, k)
@@ -166,6 +169,7 @@ def test_facet_matrix_equals_oracle_condensation_3d(lib, k):
     So_lib = B.T @ So @ B
     assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
     assert np.abs(S - S.T).max() < 1e-13 * np.abs(S).max()
+    assert (fac[:, 2] < 0).sum() == (16 if walls else 0)
     # the constant multiplier (sqrt|F| on mode 0) spans the kernel
     z = np.zeros((E, NF))
     z[:, 0] = np.sqrt(om.flen[perm])

@@ -116,3 +116,42 @@ def test_channel_shear_layer_input_is_divergence_free_and_tangent():
     assert np.abs(du1dx + du2dy).max() < 1e-14
     for yw in (0.0, 1.0):
         assert np.abs(channel_shear_layer(x, np.full_like(x, yw))[1]).max() < 1e-17
+
+
+def _oracle3(N, k, nu=0.0):
+    from inputs import channel_kuhn_cube
+    xyz, per = channel_kuhn_cube(N, "random", seed=2)
+    return Oracle(xyz, per, k, nu=nu)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_walls_3d_mass_solve_svd_and_theorem2(k):
+    """Tetrahedral channel (periodic in x, y; walls at z = 0, 1): the mass inversion equals
+    the SVD null-space projection, and the hybrid-mixed velocity the mixed one (Theorem 2);
+    no flow through the walls."""
+    o = _oracle3(2, k)
+    assert o.mesh.bnd.sum() == 16
+    Z = sla.null_space(o.B.toarray())
+    M = o.M.toarray()
+    f = np.random.default_rng(4).standard_normal(o.space.ndof)
+    u = o.mass_solve(f)
+    ub = Z @ np.linalg.solve(Z.T @ M @ Z, Z.T @ f)
+    assert np.abs(u - ub).max() < 1e-11 * np.abs(ub).max()
+    assert o.normal_jump_max(u) < 1e-11 * np.abs(u).max() * 3
+    Fb = np.random.default_rng(5).standard_normal((o.mesh.T, 3, o.space.nm))
+    cu_h = hybrid_solve_dense(o, Fb)
+    cu_m = o.space.local_coeffs(o.mass_solve(o.space.assemble(Fb)))
+    assert np.abs(cu_h - cu_m).max() < 1e-10 * np.abs(cu_m).max()
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_walls_3d_channel_flow_steady_and_energy(k):
+    """u = (a, b, 0) is tangent to the walls: projected exactly and steady; a random
+    divergence-free field loses energy through the upwind jumps only (no wall term)."""
+    o = _oracle3(2, k, nu=0.01)
+    U = o.project(lambda x, y, z: (0.7 + 0 * x, -0.3 + 0 * y, 0 * z))
+    assert np.abs(o.L(U)).max() < 1e-12
+    o0 = _oracle3(2, k)
+    V = o0.mass_solve(np.random.default_rng(6).standard_normal(o0.space.ndof))
+    e = float(V @ o0.L(V))
+    assert e < 0
