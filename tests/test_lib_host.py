@@ -379,8 +379,8 @@ def test_facet_matrix_with_walls_equals_oracle_condensation(lib, k, N):
 
 
 def test_mesh_periods(lib):
-    """A period component 0 means walls on triangles; negative periods, and tetrahedral
-    meshes with walls, are rejected."""
+    """A period component 0 means walls (triangles and tetrahedra); negative periods are
+    rejected."""
     xyz, _ = periodic_split_square(3)
     assert _mesh(lib, xyz, np.array([1.0, -1.0]))[0] == -1
     rc, m = _mesh(lib, xyz, np.array([0.0, 0.0]))  # walls on all four sides
@@ -394,6 +394,16 @@ def test_mesh_periods(lib):
     xyz3, _ = periodic_kuhn_cube(2)
     h = P_()
     per3 = np.array([1.0, 1.0, 0.0])
+    assert lib.dfdg_mesh_create(3, xyz3.shape[0], np.ascontiguousarray(xyz3).ctypes.data_as(P_),
+                                per3.ctypes.data_as(P_), ctypes.byref(h)) == 0
+    E3 = ctypes.c_int()
+    T3 = ctypes.c_int()
+    lib.dfdg_mesh_counts(h, ctypes.byref(T3), ctypes.byref(E3))
+    fac = np.empty((E3.value, 4), dtype=np.int32)
+    lib.dfdg_mesh_facets(h, fac.ctypes.data_as(P_))
+    assert T3.value == 48 and (fac[:, 2] < 0).sum() == 16  # two walls of 2 x 2 squares, 2 faces each
+    lib.dfdg_mesh_destroy(h)
+    per3[2] = -1.0
     assert lib.dfdg_mesh_create(3, xyz3.shape[0], np.ascontiguousarray(xyz3).ctypes.data_as(P_),
                                 per3.ctypes.data_as(P_), ctypes.byref(h)) == -1
 
