@@ -12,8 +12,8 @@
  * preconditioned CG, and element-local recovery (Theorem 2).  Time stepping is
  * TVD-RK3 (eq. (rk3)).  Triangle (d = 2) and tetrahedral (d = 3; the method is posed for
  * d = 2, 3, Sec. 2) meshes, periodic or with walls in the directions without period
- * (no-flow, eq. (euler-3) with g = 0; free-slip for nu > 0, eq. (ns-3)-(ns-4)); on
- * triangles also inflow and outflow boundaries there (Sec. 2.5, dfdg_mesh_set_outflow).  The element-local unknowns of the condensation are
+ * (no-flow, eq. (euler-3) with g = 0; free-slip for nu > 0, eq. (ns-3)-(ns-4)), or with
+ * inflow and outflow boundaries there (Sec. 2.5, dfdg_mesh_set_outflow).  The element-local unknowns of the condensation are
  * those of eq. (FE3) or, on triangles, the locally divergence-free ones of eq. (FE4)
  * (dfdg_params.local_space).
  *
@@ -192,7 +192,7 @@ typedef struct {
  * > 0 for a periodic direction (every facet must then match another one modulo the
  * period); 0 for a direction with walls, where the facets without a partner are boundary
  * facets (element R = -1 in dfdg_mesh_facets), closed (walls or inflows) unless
- * dfdg_mesh_set_outflow marks them as outflow (triangles only).  On a wall the velocity space
+ * dfdg_mesh_set_outflow marks them as outflow.  On a wall the velocity space
  * has u.n = 0 (BDM_k in H_0(div), eq. (space-3)), enforced by the facet multiplier of the
  * boundary facet in the hybrid-mixed solve; the residual has no term there: the
  * convective flux vanishes with u.n, and the viscous facet terms of eq. (viscous) run

@@ -6,7 +6,8 @@ CPU oracle (``oracle/``) and the GPU library consume what it produces; neither
 side's computations live here.
 """
 from .meshes import (periodic_split_square, channel_split_square, distort_split_square, element_order,  # noqa: F401
-                     inout_split_square, outflow_at_right, periodic_kuhn_cube, channel_kuhn_cube)
+                     inout_split_square, outflow_at_right, periodic_kuhn_cube, channel_kuhn_cube,
+                     inout_kuhn_cube)
 from .fields import (  # noqa: F401
     taylor_green_2d,
     channel_shear_layer,

@@ -157,7 +157,7 @@ def inout_split_square(N, order="morton", seed=0):
 
 
 def outflow_at_right(mid):
-    """Boundary-facet barycentres [n, 2] -> True on the outflow boundary x = 1."""
+    """Boundary-facet barycentres [n, d] -> True on the outflow boundary x = 1."""
     return np.asarray(mid)[:, 0] > 0.5
 
 
@@ -166,3 +166,11 @@ def channel_kuhn_cube(N, order="morton", seed=0):
     z = 1 (period[2] = 0).  Same tetrahedra as periodic_kuhn_cube."""
     xyz, _ = periodic_kuhn_cube(N, order, seed)
     return xyz, np.array([1.0, 1.0, 0.0])
+
+
+def inout_kuhn_cube(N, order="morton", seed=0):
+    """The N^3 Kuhn-split unit cube with an inflow boundary at x = 0 and an outflow
+    boundary at x = 1, periodic in y and z (period[0] = 0); ``outflow_at_right`` marks the
+    outflow faces."""
+    xyz, _ = periodic_kuhn_cube(N, order, seed)
+    return xyz, np.array([0.0, 1.0, 1.0])

@@ -173,10 +173,6 @@ extern "C" int dfdg_mesh_set_outflow(dfdg_mesh* m, const int32_t* open) {
   }
   std::vector<uint8_t> f(m->m.E, 0);
   for (int F = 0; F < m->m.E; ++F) {
-    if (open[F] && m->m.dim == 3) {
-      g_mesh_err = "outflow boundaries: triangle meshes only";
-      return DFDG_E_UNSUPPORTED;
-    }
     if (open[F] != 0 && open[F] != 1) {
       g_mesh_err = "outflow marks must be 0 or 1";
       return DFDG_E_INVALID_ARG;

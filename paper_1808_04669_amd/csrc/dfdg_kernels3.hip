@@ -126,10 +126,36 @@ __global__ __launch_bounds__(kEBlk) void k_residual3(DevGeo g, DevTabs tb, const
   for (int f = 0; f < 4; ++f) {
     const size_t idx = (size_t)f * T + t;
     const int nb = g.nbr[idx];
-    // a wall (boundary face, nbr = -1): no convective flux (u.n = 0) and no viscous face
-    // terms (interior faces only: free slip)
-    if (nb < 0) continue;
     const int code = g.code[idx];
+    // a closed boundary face (wall or inflow, nbr = -1): no term (u.n = 0 on a wall; on an
+    // inflow the term acts on v.n only, which the increments keep 0); no viscous face terms
+    // on any boundary (interior faces only: free slip)
+    if (nb < 0 && !((code >> 6) & 1)) continue;
+    if (nb < 0) {  // outflow: -int max(u.n, 0) (u . v), own trace (backflow sees zero)
+      const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+      const double li = g.flen[idx] * isq;
+      for (int r = 0; r < NQF; ++r) {
+        double uo[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double a = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) a += u[c][i] * s.Vf[f][r][i];
+          uo[c] = a * isq;
+        }
+        const double un = uo[0] * n[0] + uo[1] * n[1] + uo[2] * n[2];
+        if (un > 0.0) {
+          const double w = s.Wf[r] * li;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double wq = -(w * un * uo[c]);
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] = fma(wq, s.Vf[f][r][i], acc[c][i]);
+          }
+        }
+      }
+      continue;
+    }
     const int fn = code & 3, pid = (code >> 2) & 7;
     const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
     double v[3][P];
@@ -508,7 +534,10 @@ __global__ __launch_bounds__(kBlk) void k_mf_gather(DevGeo g, DevBsr A, const do
 #pragma unroll
     for (int m = 0; m < NF; ++m) {
       const size_t o = (size_t)F * NF + m;
-      const double y = A.mfq[a + (size_t)m * T] + (b >= 0 ? A.mfq[b + (size_t)m * T] : 0.0);  // b < 0: boundary
+      // b = -1: a closed boundary face, one side; b = -2: an outflow face, whose row of S
+      // is the identity (no multiplier) and whose element contributions vanish
+      const double y = b == -2 ? z[o] + beta * p_old[o]
+                               : A.mfq[a + (size_t)m * T] + (b >= 0 ? A.mfq[b + (size_t)m * T] : 0.0);
       const double pn = z[o] + beta * p_old[o];
       p_new[o] = pn;
       Sp[o] = y;
@@ -650,6 +679,7 @@ __global__ __launch_bounds__(kEBlk) void k_diag3(DevGeo g, DevTabs tb, const dou
       const size_t idx = (size_t)f * T + t;
       const int code = g.code[idx];
       if ((code >> 5) & 1) continue;  // the L side measures the face
+      if ((code >> 6) & 1) continue;  // outflow boundary: u.n is free there
       const int nb = g.nbr[idx], fn = code & 3, pid = (code >> 2) & 7;
       const bool wall = nb < 0;  // the jump across a wall is u.n itself
       const int nbs = wall ? t : nb;

@@ -635,6 +635,7 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
       const int F = m.efacet[4 * (size_t)t + f];
       const bool isR = (m.fR[F] == t && m.fRloc[F] == f);
       const bool wall = m.fR[F] < 0;  // boundary face: one side, nbr = -1
+      const bool open = wall && !m.fopen.empty() && m.fopen[F];  // outflow boundary
       const int nb = isR ? m.fL[F] : m.fR[F];
       const int nbf = wall ? 0 : (isR ? m.fLloc[F] : m.fRloc[F]);
       // permutation carrying this element's face vertices to the neighbour's
@@ -650,25 +651,32 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
       double sgn = (n[0] * (a[0] - o[0]) + n[1] * (a[1] - o[1]) + n[2] * (a[2] - o[2])) > 0 ? 1.0 : -1.0;
       const size_t idx = (size_t)f * T + t;
       h.nbr[idx] = nb;
-      h.code[idx] = nbf | (pid << 2) | ((isR ? 1 : 0) << 5);
+      h.code[idx] = nbf | (pid << 2) | ((isR ? 1 : 0) << 5) | ((open ? 1 : 0) << 6);
       h.efacet[idx] = F;
       h.nx[idx] = sgn * n[0] / nn;
       h.ny[idx] = sgn * n[1] / nn;
       h.nz[idx] = sgn * n[2] / nn;
       h.flen[idx] = 0.5 * nn;
       h.sig[idx] = alpha * K * K / (wall ? hT[t] : std::min(hT[t], hT[nb]));
-      h.sF[idx] = std::sqrt(nn / h.detJ[t]);  // sqrt(|F| / |Fhat| / det J), |Fhat| = 1/2
+      // sqrt(|F| / |Fhat| / det J), |Fhat| = 1/2; no face rows of C_T on an outflow face
+      h.sF[idx] = open ? 0.0 : std::sqrt(nn / h.detJ[t]);
     }
   }
   double zz = 0;
   for (int F = 0; F < E; ++F) {
     h.qL[F] = m.fLloc[F] * NF * T + m.fL[F];
-    h.qR[F] = m.fR[F] < 0 ? -1 : m.fRloc[F] * NF * T + m.fR[F];  // -1: boundary face
+    // -1: closed boundary face, -2: outflow face (the matrix-free product tells them apart)
+    h.qR[F] = m.fR[F] < 0 ? ((!m.fopen.empty() && m.fopen[F]) ? -2 : -1) : m.fRloc[F] * NF * T + m.fR[F];
     const double area = h.flen[(size_t)m.fLloc[F] * T + m.fL[F]];
     h.zdef[F] = std::sqrt(area);  // the constant multiplier on mode 0 of the orthonormal face basis
     zz += area;
   }
   for (int F = 0; F < E; ++F) h.zdef[F] /= std::sqrt(zz);
+  h.nearnull = h.zdef;
+  h.singular = true;
+  for (int F = 0; F < E; ++F)
+    if (!m.fopen.empty() && m.fopen[F]) h.singular = false;
+  if (!h.singular) std::fill(h.zdef.begin(), h.zdef.end(), 0.0);  // S is definite: no kernel
 
   // Element condensation (eq. (FE3)): D_T = sum_a Jinv[a][c] Dh[a]; the rows of face f are
   // sqrt(2|F|/det J) n_c Ch[f], mapped to the L side's face basis (Qf) on the R side
@@ -716,6 +724,10 @@ int build_setup3(const MeshHost& m, int K, double alpha, HostSetup& h, std::stri
     if (m.fR[F] < 0)
       for (int s = 4; s < NS; ++s) h.cols[(size_t)s * E + F] = F;
   if (condense_elements(h, 4, NP, NU, NF, el, err)) return -2;
+  // an outflow face's row and column of S vanish: an identity block fixes its multiplier to 0
+  for (int F = 0; F < E; ++F)
+    if (!m.fopen.empty() && m.fopen[F])
+      for (int a = 0; a < NF; ++a) h.vals[(((size_t)0 * NF + a) * NF + a) * E + F] = 1.0;
   // merge repeated columns of a row (tiny periodic meshes) into their first slot
   for (int F = 0; F < E; ++F)
     for (int s = 1; s < NS; ++s)

@@ -159,8 +159,8 @@ def rule3(k, which):
 
 class Mesh:
     """A simplex mesh (host object of the library): xyz[T, 3, 2] triangles or xyz[T, 4, 3]
-    tetrahedra; period[dim] > 0 periodic, 0 (triangles) boundary facets in that direction,
-    closed (walls, inflow) unless ``outflow(barycentres[n, 2]) -> bool[n]`` marks them as an
+    tetrahedra; period[dim] > 0 periodic, 0 boundary facets in that direction, closed
+    (walls, inflow) unless ``outflow(barycentres[n, dim]) -> bool[n]`` marks them as an
     outflow boundary."""
 
     def __init__(self, xyz, period, outflow=None):
@@ -186,7 +186,10 @@ class Mesh:
             b = np.nonzero(fac[:, 2] < 0)[0]
             if b.size:
                 L, f = fac[b, 0], fac[b, 1]
-                mid = 0.5 * (xyz[L, (f + 1) % 3] + xyz[L, (f + 2) % 3])  # local facet f: edge (f+1) -> (f+2)
+                if self.dim == 2:  # local facet f: the edge (f+1) -> (f+2)
+                    mid = 0.5 * (xyz[L, (f + 1) % 3] + xyz[L, (f + 2) % 3])
+                else:  # local face f: the face opposite vertex f
+                    mid = (xyz[L].sum(axis=1) - xyz[L, f]) / 3.0
                 self.open[b] = np.asarray(outflow(mid), dtype=bool)
             marks = np.ascontiguousarray(self.open, dtype=np.int32)
             rc = lib.dfdg_mesh_set_outflow(h, marks.ctypes.data_as(_P))

@@ -3,7 +3,8 @@
 import numpy as np
 import torch
 
-from inputs import (channel_kuhn_cube, channel_split_square, distort_split_square, inout_split_square, outflow_at_right,
+from inputs import (channel_kuhn_cube, channel_split_square, distort_split_square, inout_kuhn_cube,
+                    inout_split_square, outflow_at_right,
                     periodic_kuhn_cube, periodic_split_square)
 from oracle import Oracle
 from oracle.quadrature import poly_basis_nd, simplex_rule
@@ -17,7 +18,7 @@ def make_pair(N, k, nu=0.0, order="morton", seed=0, oracle=True, dim=2, walls=Fa
     polynomial field ``inflow``) and an outflow boundary at x = 1; distort > 0 moves the
     triangle mesh's vertices by up to that fraction of h (seeded)."""
     from paper_1808_04669_amd import Solver
-    gen = (inout_split_square if inout
+    gen = ((inout_split_square if dim == 2 else inout_kuhn_cube) if inout
            else (channel_split_square if dim == 2 else channel_kuhn_cube) if walls
            else (periodic_split_square if dim == 2 else periodic_kuhn_cube))
     xyz, per = gen(N, order, seed)

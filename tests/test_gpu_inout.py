@@ -147,3 +147,49 @@ def test_inflow_outflow_shear_layer_at_256_bdm2():
     change = np.abs(dv[fac[inflow, 0], 0, fac[inflow, 1]]).max()
     _log("inflow normal velocity change", change, "state change", float((U - U_init).abs().max()))
     assert change < 1e-12
+
+
+def _lift3(x, y, z):
+    return 0.8 + 0 * x, 0.15 + 0 * y, -0.1 + 0 * z
+
+
+@pytest.mark.parametrize("precond,mf", [("jacobi", False), ("amg", False), ("amg", True)])
+@pytest.mark.parametrize("k,N", [(1, 3), (2, 2)])
+def test_inout_3d_mass_solve_parity(k, N, precond, mf):
+    """Tetrahedra, inflow at x = 0 and outflow at x = 1: mass inversion against the oracle,
+    also with the matrix-free product (the outflow rows' identity blocks in the face pass)."""
+    from gpu_util import to_dev
+    from oracle.quadrature import poly_basis_nd
+    orc, s, _, _ = make_pair(N, k, dim=3, order="random", seed=N, inout=True, cg_rtol=1e-13, precond=precond,
+                             matrix_free=mf)
+    assert s.mesh.open.sum() == 2 * N * N
+    Fb = np.random.default_rng(k).standard_normal((orc.mesh.T, 3, orc.space.nm))
+    U_orc = orc.mass_solve(orc.space.assemble(Fb))
+    pts, _ = s.proj_rule()
+    vals, _ = poly_basis_nd(k, pts)
+    F = s.load_vector(to_dev(s, np.einsum("tca,qa->tcq", Fb / orc.mesh.detJ[:, None, None], vals)))
+    U, info = s.mass_solve(F)
+    assert info.status == 0 and info.rel_residual <= 1e-13
+    err = rel_l2(orc, s, U, U_orc)
+    _log("inout 3d mass solve", k, N, precond, mf, "iters", info.iterations, "rel L2", err)
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("k,N,nu,steps", [(1, 3, 0.0, 3), (2, 2, 1e-2, 2)])
+def test_inout_3d_residual_and_rk3_parity(k, N, nu, steps):
+    from inputs import abc_flow
+    orc, s, _, _ = make_pair(N, k, dim=3, nu=nu, inout=True, inflow=_lift3, cg_rtol=1e-13, precond="amg",
+                             extrapolate="adaptive")
+    U0 = orc.project(lambda x, y, z: tuple(0.3 * c for c in abc_flow(x, y, z)))
+    U = transfer(orc, U0, s)
+    R_gpu = broken_residual_on_oracle_basis(orc, s, s.residual(U))
+    R_orc = orc.res.broken(orc.state_local(U0))
+    rerr = np.abs(R_gpu - R_orc).max() / np.abs(R_orc).max()
+    dt = 0.1 / N / k ** 2
+    Uo = U0
+    for _ in range(steps):
+        assert s.rk3_step(U, dt).status == 0
+        Uo = orc.rk3_step(Uo, dt)
+    err = rel_l2(orc, s, U, Uo)
+    _log("inout 3d residual", rerr, "rk3", k, N, nu, err)
+    assert rerr < 1e-11 and err < 1e-10

@@ -114,8 +114,17 @@ def test_face_matching_agrees_with_oracle(lib, N, order):
     assert all((f[0], f[1]) in key for f in fac)
 
 
-def _lib_S(lib, xyz, per, k):
+def _lib_S(lib, xyz, per, k, outflow=None):
     rc, m = _mesh(lib, xyz, per)
+    if outflow is not None:  # mark the boundary faces whose barycentre the predicate picks
+        E0 = ctypes.c_int()
+        T0 = ctypes.c_int()
+        lib.dfdg_mesh_counts(m, ctypes.byref(T0), ctypes.byref(E0))
+        fac0 = np.empty((E0.value, 4), dtype=np.int32)
+        lib.dfdg_mesh_facets(m, fac0.ctypes.data_as(P_))
+        mid = (xyz[fac0[:, 0]].sum(axis=1) - xyz[fac0[:, 0], fac0[:, 1]]) / 3.0
+        marks = ((fac0[:, 2] < 0) & outflow(mid)).astype(np.int32)
+        assert lib.dfdg_mesh_set_outflow(m, marks.ctypes.data_as(P_)) == 0
     rc, c = _ctx(lib, m, k=k)
     assert rc == 0, lib.dfdg_last_error(None)
     s = lib_mod.Sizes()
@@ -133,6 +142,39 @@ def _lib_S(lib, xyz, per, k):
         for F in range(E):
             S[F * NF:(F + 1) * NF, cols[sl, F] * NF:(cols[sl, F] + 1) * NF] += vals[sl, :, :, F]
     return S, fac, s
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_facet_matrix_with_outflow_3d(lib, k):
+    """Inflow at x = 0, outflow at x = 1 on the Kuhn cube: S equals the oracle's condensed
+    system (no multiplier on the outflow faces) with identity blocks on the outflow rows,
+    and is definite."""
+    from inputs import inout_kuhn_cube, outflow_at_right
+    xyz, per = inout_kuhn_cube(2, "random", seed=k)
+    S, fac, s = _lib_S(lib, xyz, per, k, outflow=outflow_at_right)
+    E, NF = s.E, s.n_f
+    orc = Oracle(xyz, per, k, outflow=outflow_at_right)
+    assert orc.mesh.open.sum() == 8 and orc.mesh.bnd.sum() == 16
+    K, nU, nW = hybrid_system_dense(orc)
+    nx = nU + nW
+    So = K[nx:, :nx] @ np.linalg.solve(K[:nx, :nx], K[:nx, nx:])
+    om = orc.mesh
+    key = {(a, b): F for F, (a, b) in enumerate(zip(om.fA_elem, om.fA_loc))}
+    perm = np.array([key[(fac[F, 0], fac[F, 1])] for F in range(E)])
+    tp, tw = triangle_rule(2 * k)
+    mu = np.empty((len(tw), NF))
+    lib.dfdg_debug_basis(k, len(tw), np.ascontiguousarray(tp).ctypes.data_as(P_), mu.ctypes.data_as(P_), None)
+    lj, _ = poly_basis(k, tp[:, 0], tp[:, 1])
+    Q = np.einsum("q,qm,qj->mj", tw, mu, lj)
+    B = np.zeros((E * NF, E * NF))
+    for F in range(E):
+        Fo = perm[F]
+        B[Fo * NF:(Fo + 1) * NF, F * NF:(F + 1) * NF] = Q.T / np.sqrt(2 * om.flen[Fo])
+    So_lib = B.T @ So @ B
+    for F in np.nonzero(om.open[perm])[0]:
+        So_lib[F * NF:(F + 1) * NF, F * NF:(F + 1) * NF] = np.eye(NF)
+    assert np.abs(S - So_lib).max() < 1e-11 * np.abs(So_lib).max()
+    assert np.linalg.eigvalsh(S)[0] > 1e-8 * np.abs(S).max()
 
 
 @pytest.mark.parametrize("k", [1, 2])

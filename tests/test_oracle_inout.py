@@ -92,17 +92,43 @@ def test_uniform_flow_is_steady(k, nu):
     assert np.abs(U1).max() < 1e-12
 
 
-def test_energy_balance_closed_form():
+def _oracle3(N, k, nu=0.0, inflow=None):
+    from inputs import inout_kuhn_cube
+    xyz, per = inout_kuhn_cube(N, "random", seed=3)
+    return Oracle(xyz, per, k, nu=nu, outflow=outflow_at_right, inflow=inflow)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_tetrahedra_hybrid_equals_mixed_and_uniform_flow_steady(k):
+    """On the Kuhn cube with inflow at x = 0 and outflow at x = 1 (periodic in y, z):
+    Theorem 2 without outflow multipliers, and u = (c, 0, 0) is steady."""
+    o = _oracle3(2, k)
+    assert o.mesh.open.sum() == 8 and o.mesh.bnd.sum() == 16
+    Fb = np.random.default_rng(k).standard_normal((o.mesh.T, 3, o.space.nm))
+    cu_h = hybrid_solve_dense(o, Fb)
+    cu_m = o.space.local_coeffs(o.mass_solve(o.space.assemble(Fb)))
+    assert np.abs(cu_h - cu_m).max() < 1e-10 * np.abs(cu_m).max()
+    o = _oracle3(2, k, nu=0.01, inflow=lambda x, y, z: (0.8 + 0 * x, 0 * y, 0 * z))
+    U = np.zeros(o.space.ndof)
+    assert np.abs(o.mass_solve(o.L(U))).max() < 1e-12
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_energy_balance_closed_form(dim):
     """u . L_0(u) = -(1/2 sum_interior int |u.n| |[u]|^2 + 1/2 int_out |u.n| |u|^2
     - 1/2 int_in (u.n) |u|^2) for u = lift + increment (div u = 0 element-wise; the facet
     integrals with the residual's facet rule)."""
     k = 2
-    o = _oracle(4, k, inflow=lambda x, y: (0.6 + 0.1 * np.sin(0 * x), 0 * y + 0.2))
-    U = o.project(RandomStreamField(seed=2, kmax=2))
+    if dim == 2:
+        o = _oracle(4, k, inflow=lambda x, y: (0.6 + 0 * x, 0 * y + 0.2))
+        U = o.project(RandomStreamField(seed=2, kmax=2))
+    else:
+        o = _oracle3(2, k, inflow=lambda x, y, z: (0.6 + 0 * x, 0 * y + 0.2, 0 * z - 0.1))
+        U = o.mass_solve(np.random.default_rng(3).standard_normal(o.space.ndof))
     cU = o.state_local(U)
     lhs = float(np.sum(o.res.broken(cU) * cU))
     m = o.mesh
-    s, w = facet_rule(2, k)
+    s, w = facet_rule(dim, k)
     xa, xb = m.facet_points(s)
     va, _ = poly_basis_nd(k, xa)
     vb, _ = poly_basis_nd(k, xb)
