@@ -14,53 +14,105 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <thread>
 
 namespace dfdg {
+
+// fn(chunk, begin, end) over kChunks fixed row ranges of [0, n), on up to 16 host threads.
+// The ranges do not depend on the thread count, so per-chunk partial results combined in
+// chunk order give the same bits on every host.
+static constexpr int kChunks = 64;
+template <typename Fn>
+static void parallel_chunks(int n, Fn fn) {
+  const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto range = [&](int c, int& b, int& e) {
+    b = (int)((long)n * c / kChunks);
+    e = (int)((long)n * (c + 1) / kChunks);
+  };
+  if (nt == 1 || n < 2 * kChunks) {
+    for (int c = 0; c < kChunks; ++c) {
+      int b, e;
+      range(c, b, e);
+      fn(c, b, e);
+    }
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (int w = 0; w < nt; ++w)
+    pool.emplace_back([&, w]() {
+      for (int c = w; c < kChunks; c += nt) {
+        int b, e;
+        range(c, b, e);
+        fn(c, b, e);
+      }
+    });
+  for (auto& th : pool) th.join();
+}
+
+// distinct columns of facet row F, sorted (tiny periodic meshes repeat a column in two slots)
+static int row_columns(int E, int NS, const std::vector<int>& cols, int F, int* cs) {
+  int nu = 0;
+  for (int s = 0; s < NS; ++s) {
+    const int c = cols[(size_t)s * E + F];
+    bool seen = false;
+    for (int t = 0; t < nu; ++t) seen |= (cs[t] == c);
+    if (!seen) cs[nu++] = c;
+  }
+  std::sort(cs, cs + nu);
+  return nu;
+}
 
 static Csr bsr_to_csr(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals) {
   Csr A;
   A.n = A.m = E * NF;
   A.ptr.assign(A.n + 1, 0);
-  std::vector<int> cs(NS);
-  for (int F = 0; F < E; ++F) {
-    int nu = 0;
-    for (int s = 0; s < NS; ++s) {
-      const int c = cols[(size_t)s * E + F];
-      bool seen = false;
-      for (int t = 0; t < nu; ++t) seen |= (cs[t] == c);
-      if (!seen) cs[nu++] = c;
+  std::vector<int> nus(E);
+  parallel_chunks(E, [&](int, int b, int e) {
+    std::vector<int> cs(NS);
+    for (int F = b; F < e; ++F) nus[F] = row_columns(E, NS, cols, F, cs.data());
+  });
+  for (int F = 0; F < E; ++F)
+    for (int a = 0; a < NF; ++a) A.ptr[F * NF + a + 1] = A.ptr[F * NF + a] + nus[F] * NF;
+  A.col.resize(A.ptr[A.n]);
+  A.val.resize(A.ptr[A.n]);
+  parallel_chunks(E, [&](int, int b, int e) {
+    std::vector<int> cs(NS);
+    for (int F = b; F < e; ++F) {
+      const int nu = row_columns(E, NS, cols, F, cs.data());
+      for (int a = 0; a < NF; ++a) {
+        int k = A.ptr[F * NF + a];
+        for (int t = 0; t < nu; ++t)
+          for (int bb = 0; bb < NF; ++bb, ++k) {
+            double v = 0;
+            for (int s = 0; s < NS; ++s)
+              if (cols[(size_t)s * E + F] == cs[t]) v += vals[(((size_t)s * NF + a) * NF + bb) * E + F];
+            A.col[k] = cs[t] * NF + bb;
+            A.val[k] = v;
+          }
+      }
     }
-    std::sort(cs.begin(), cs.begin() + nu);
-    for (int a = 0; a < NF; ++a) {
-      const int row = F * NF + a;
-      for (int t = 0; t < nu; ++t)
-        for (int b = 0; b < NF; ++b) {
-          double v = 0;
-          for (int s = 0; s < NS; ++s)
-            if (cols[(size_t)s * E + F] == cs[t]) v += vals[(((size_t)s * NF + a) * NF + b) * E + F];
-          A.col.push_back(cs[t] * NF + b);
-          A.val.push_back(v);
-        }
-      A.ptr[row + 1] = (int)A.col.size();
-    }
-  }
+  });
   return A;
 }
 
 static void spmv(const Csr& A, const std::vector<double>& x, std::vector<double>& y) {
   y.assign(A.n, 0.0);
-  for (int i = 0; i < A.n; ++i) {
-    double s = 0;
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
-    y[i] = s;
-  }
+  parallel_chunks(A.n, [&](int, int b, int e) {
+    for (int i = b; i < e; ++i) {
+      double s = 0;
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) s += A.val[k] * x[A.col[k]];
+      y[i] = s;
+    }
+  });
 }
 
 static std::vector<double> diag_inv(const Csr& A) {
   std::vector<double> d(A.n, 0.0);
-  for (int i = 0; i < A.n; ++i)
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
-      if (A.col[k] == i) d[i] = 1.0 / A.val[k];
+  parallel_chunks(A.n, [&](int, int b, int e) {
+    for (int i = b; i < e; ++i)
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k)
+        if (A.col[k] == i) d[i] = 1.0 / A.val[k];
+  });
   return d;
 }
 
@@ -73,13 +125,23 @@ static double rho_dinv_a(const Csr& A, const std::vector<double>& dinv, int iter
     x[i] = (double)(s >> 11) / 9007199254740992.0 - 0.5;
   }
   double lam = 0;
+  std::vector<double> pny(kChunks), pnx(kChunks);
   for (int it = 0; it < iters; ++it) {
     spmv(A, x, y);
+    parallel_chunks(A.n, [&](int c, int b, int e) {
+      double sy = 0, sx = 0;
+      for (int i = b; i < e; ++i) {
+        y[i] *= dinv[i];
+        sy += y[i] * y[i];
+        sx += x[i] * x[i];
+      }
+      pny[c] = sy;
+      pnx[c] = sx;
+    });
     double ny = 0, nx = 0;
-    for (int i = 0; i < A.n; ++i) {
-      y[i] *= dinv[i];
-      ny += y[i] * y[i];
-      nx += x[i] * x[i];
+    for (int c = 0; c < kChunks; ++c) {
+      ny += pny[c];
+      nx += pnx[c];
     }
     lam = std::sqrt(ny / nx);
     const double inv = 1.0 / std::sqrt(ny);
@@ -88,54 +150,87 @@ static double rho_dinv_a(const Csr& A, const std::vector<double>& dinv, int iter
   return lam;
 }
 
+// T = A^T with the entries of each row of T in increasing column order (the serial
+// scatter's order): each chunk of A's rows counts its columns, the chunks' offsets within
+// every row of T follow in chunk order, and each chunk then scatters its own entries.
 static Csr transpose(const Csr& A) {
   Csr T;
   T.n = A.m;
   T.m = A.n;
   T.ptr.assign(T.n + 1, 0);
-  for (int c : A.col) T.ptr[c + 1]++;
-  for (int i = 0; i < T.n; ++i) T.ptr[i + 1] += T.ptr[i];
+  std::vector<std::vector<int>> cnt(kChunks);
+  parallel_chunks(A.n, [&](int ch, int b, int e) {
+    cnt[ch].assign(A.m, 0);
+    for (int k = A.ptr[b]; k < A.ptr[e]; ++k) cnt[ch][A.col[k]]++;
+  });
+  for (int c = 0; c < A.m; ++c) {  // cnt becomes each chunk's start in row c of T
+    int run = 0;
+    for (int ch = 0; ch < kChunks; ++ch) {
+      const int n = cnt[ch].empty() ? 0 : cnt[ch][c];
+      if (!cnt[ch].empty()) cnt[ch][c] = run;
+      run += n;
+    }
+    T.ptr[c + 1] = T.ptr[c] + run;
+  }
   T.col.resize(A.col.size());
   T.val.resize(A.val.size());
-  std::vector<int> pos(T.ptr.begin(), T.ptr.end() - 1);
-  for (int i = 0; i < A.n; ++i)
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      const int p = pos[A.col[k]]++;
-      T.col[p] = i;
-      T.val[p] = A.val[k];
-    }
+  parallel_chunks(A.n, [&](int ch, int b, int e) {
+    std::vector<int>& pos = cnt[ch];
+    for (int i = b; i < e; ++i)
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int c = A.col[k];
+        const int p = T.ptr[c] + pos[c]++;
+        T.col[p] = i;
+        T.val[p] = A.val[k];
+      }
+  });
   return T;
 }
 
-// C = A B (Gustavson with a dense accumulator); columns of each row sorted.
+// C = A B (Gustavson with a dense accumulator); columns of each row sorted.  Row ranges
+// run on the host's threads, each into its own buffers, joined in row order.
 static Csr matmul(const Csr& A, const Csr& B) {
   Csr C;
   C.n = A.n;
   C.m = B.m;
   C.ptr.assign(C.n + 1, 0);
-  std::vector<double> acc(B.m, 0.0);
-  std::vector<int> mark(B.m, -1), touched;
-  for (int i = 0; i < A.n; ++i) {
-    touched.clear();
-    for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
-      const int j = A.col[k];
-      const double a = A.val[k];
-      for (int l = B.ptr[j]; l < B.ptr[j + 1]; ++l) {
-        const int c = B.col[l];
-        if (mark[c] != i) {
-          mark[c] = i;
-          acc[c] = 0;
-          touched.push_back(c);
+  std::vector<std::vector<int>> pc(kChunks);
+  std::vector<std::vector<double>> pv(kChunks);
+  std::vector<int> rowlen(A.n);
+  parallel_chunks(A.n, [&](int ch, int b, int e) {
+    std::vector<double> acc(B.m, 0.0);
+    std::vector<int> mark(B.m, -1), touched;
+    auto& oc = pc[ch];
+    auto& ov = pv[ch];
+    for (int i = b; i < e; ++i) {
+      touched.clear();
+      for (int k = A.ptr[i]; k < A.ptr[i + 1]; ++k) {
+        const int j = A.col[k];
+        const double a = A.val[k];
+        for (int l = B.ptr[j]; l < B.ptr[j + 1]; ++l) {
+          const int c = B.col[l];
+          if (mark[c] != i) {
+            mark[c] = i;
+            acc[c] = 0;
+            touched.push_back(c);
+          }
+          acc[c] += a * B.val[l];
         }
-        acc[c] += a * B.val[l];
       }
+      std::sort(touched.begin(), touched.end());
+      for (int c : touched) {
+        oc.push_back(c);
+        ov.push_back(acc[c]);
+      }
+      rowlen[i] = (int)touched.size();
     }
-    std::sort(touched.begin(), touched.end());
-    for (int c : touched) {
-      C.col.push_back(c);
-      C.val.push_back(acc[c]);
-    }
-    C.ptr[i + 1] = (int)C.col.size();
+  });
+  for (int i = 0; i < A.n; ++i) C.ptr[i + 1] = C.ptr[i] + rowlen[i];
+  C.col.reserve(C.ptr[C.n]);
+  C.val.reserve(C.ptr[C.n]);
+  for (int ch = 0; ch < kChunks; ++ch) {
+    C.col.insert(C.col.end(), pc[ch].begin(), pc[ch].end());
+    C.val.insert(C.val.end(), pv[ch].begin(), pv[ch].end());
   }
   return C;
 }
@@ -336,6 +431,7 @@ int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::ve
       L.RA = transpose(AP);
       L.AP = std::move(AP);
     }
+   
     L.P = std::move(P);
     L.R = std::move(R);
     AmgLevel next;
