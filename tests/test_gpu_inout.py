@@ -193,3 +193,39 @@ def test_inout_3d_residual_and_rk3_parity(k, N, nu, steps):
     err = rel_l2(orc, s, U, Uo)
     _log("inout 3d residual", rerr, "rk3", k, N, nu, err)
     assert rerr < 1e-11 and err < 1e-10
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_inout_grid_stride_and_mixed(precond):
+    """Grid-stride facet kernels (facet_blocks = 1) with outflow rows, against the oracle;
+    the mixed-precision form of a stream through the square within 1e-6 of FP64."""
+    orc, s, _, _ = make_pair(16, 2, order="random", seed=5, inout=True, cg_rtol=1e-13, precond=precond,
+                             facet_blocks=1)
+    coef = random_broken_poly(s.T, 2, seed=62)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U, info = s.mass_solve(F)
+    rule = triangle_rule(4)
+    U_orc = orc.mass_solve(orc.space.assemble(orc.space.load_vector(eval_broken_poly(coef, rule[0]), rule)))
+    err = rel_l2(orc, s, U, U_orc)
+    _log("inout grid stride", precond, info.iterations, err)
+    assert info.status == 0 and err < 1e-10
+    from inputs import channel_shear_layer
+    out = {}
+    for prec in ("fp64", "mixed"):
+        _, sm, xyz2, _ = make_pair(32, 2, nu=1e-3, oracle=False, inout=True, cg_rtol=1e-10, precond=precond,
+                                   precision=prec, ir_rtol=1e-10)
+        lift = values_to_lib(sm, lambda pts: np.stack([np.ones((sm.T, len(pts))), np.zeros((sm.T, len(pts)))], axis=1))
+
+        def turned(x, y):
+            u, v = channel_shear_layer(y, x)
+            return 0.2 * v, 0.2 * u
+
+        P, vmax = project_field(sm, xyz2, turned)
+        V = lift + P
+        for _ in range(3):
+            assert sm.rk3_step(V, 0.1 / 32 / (4 * (1 + vmax))).status == 0
+        out[prec] = V
+        del sm
+    errm = ((out["mixed"] - out["fp64"]).norm() / out["fp64"].norm()).item()
+    _log("inout mixed vs fp64", precond, errm)
+    assert errm < 1e-6

@@ -187,3 +187,32 @@ def test_walls_3d_rk3_trajectory_parity(k, N, nu, steps):
     err = rel_l2(orc, s, U, Uo)
     _log("walls 3d residual", rerr, "rk3", k, N, nu, err)
     assert rerr < 1e-11 and err < 1e-10
+
+
+@pytest.mark.parametrize("precond", ["jacobi", "amg"])
+def test_walls_grid_stride_and_mixed(precond):
+    """The facet kernels' grid-stride path (facet_blocks = 1: one block walks all rows,
+    boundary rows included) gives the single-pass result; the mixed-precision form on the
+    channel stays within 1e-6 of FP64."""
+    orc, s, xyz, _ = make_pair(16, 2, order="random", seed=3, walls=True, cg_rtol=1e-13, precond=precond,
+                               facet_blocks=1)
+    coef = random_broken_poly(s.T, 2, seed=61)
+    F = values_to_lib(s, lambda pts: eval_broken_poly(coef, pts))
+    U, info = s.mass_solve(F)
+    rule = triangle_rule(4)
+    U_orc = orc.mass_solve(orc.space.assemble(orc.space.load_vector(eval_broken_poly(coef, rule[0]), rule)))
+    err = rel_l2(orc, s, U, U_orc)
+    _log("walls grid stride", precond, info.iterations, err)
+    assert info.status == 0 and err < 1e-10
+    out = {}
+    for prec in ("fp64", "mixed"):
+        _, sm, xyz2, _ = make_pair(32, 2, nu=1e-3, oracle=False, walls=True, cg_rtol=1e-10, precond=precond,
+                                   precision=prec, ir_rtol=1e-10)
+        V, vmax = project_field(sm, xyz2, channel_shear_layer)
+        for _ in range(3):
+            assert sm.rk3_step(V, 0.1 / 32 / (4 * vmax)).status == 0
+        out[prec] = V
+        del sm
+    errm = ((out["mixed"] - out["fp64"]).norm() / out["fp64"].norm()).item()
+    _log("walls mixed vs fp64", precond, errm)
+    assert errm < 1e-6
