@@ -67,6 +67,8 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-random-order", action="store_true", help="skip the randomly numbered mesh run")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D Taylor-Green run")
+    ap.add_argument("--mg-fine-smooth", type=int, default=None,
+                    help="damped-Jacobi steps of the finest multigrid prolongator")
     ap.add_argument("--no-local-spaces", action="store_true",
                     help="skip the FE3 / FE4 local-space comparison")
     ap.add_argument("--local-steps", type=int, default=50)
@@ -115,7 +117,8 @@ def make_solver(N, k, precision, args, order=None, rtol=None, nu=0.0, **kw):
     from paper_1808_04669_amd import Solver
     xyz, per = periodic_split_square(N, order or args.order)
     s = Solver(xyz, per, k, nu=nu, precision=precision, cg_rtol=rtol or args.rtol, precond=args.precond,
-               extrapolate=args.extrapolate, **{"mg_fine_fp16": not args.no_mg_fp16, **kw})
+               extrapolate=args.extrapolate,
+               **{"mg_fine_fp16": not args.no_mg_fp16, "mg_fine_smooth": args.mg_fine_smooth, **kw})
     s._xyz = xyz
     return s
 
@@ -274,7 +277,8 @@ def three_d(args):
     for name, kw in all_variants:
         if name not in wanted:
             continue
-        sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, extrapolate=args.extrapolate, **kw)
+        sa = Solver(xyz, per, k, nu=nu, cg_rtol=args.rtol, extrapolate=args.extrapolate,
+                    mg_fine_smooth=args.mg_fine_smooth, **kw)
         sa._xyz = xyz
         Ua, vmax, _ = project_field(sa, taylor_green_3d)
         dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)

@@ -129,6 +129,11 @@ typedef struct {
                         mg_fine_fp16); with Jacobi the FP32 part is the residual alone;
                         0 = restarted refinement: FP32 PCG on an FP32 copy of S to inner_rtol,
                         FP64 refinement residual g - S lambda, restarted until ir_rtol. */
+  int mg_fine_smooth;/* DFDG_AMG: damped-Jacobi steps smoothing the finest level's tentative
+                        prolongator, 1..3 (default 2; the coarser levels take one): more steps
+                        give a wider interpolation, fewer PCG iterations and costlier
+                        finest-level transfers (rows of up to 16 entries stay packed in FP16
+                        when the next level has fewer than 65536 unknowns) */
   int local_space;   /* element-local unknowns of the condensation (triangle meshes):
                         DFDG_LOCAL_FE3 (default): broken [P^k]^2 velocity with the P^{k-1}
                         pressure w of eq. (FE3), the local projector applied as

@@ -5,8 +5,9 @@
 // must represent.  Each level: a strength graph (|a_ij| >= theta sqrt(a_ii a_jj), on the
 // mode-0 entries of the facet blocks for the finest level), greedy aggregation (roots whose
 // neighbourhood is free, then attachment, then leftovers), a tentative prolongator carrying
-// the near-null vector aggregate by aggregate, one damped-Jacobi smoothing step of the
-// prolongator (weight 4/(3 rho(D^{-1}A))), and the Galerkin product R A P with R = P^T.
+// the near-null vector aggregate by aggregate, damped-Jacobi smoothing of the prolongator
+// (weight 4/(3 rho(D^{-1}A)); a set number of steps on the finest level, one below), and
+// the Galerkin product R A P with R = P^T.
 // The coarsest operator is inverted densely after adding its (near-)kernel direction; the
 // inverse is then projected onto the complement of that direction (a pseudo-inverse).
 #include "dfdg_amg.h"
@@ -235,6 +236,50 @@ static Csr matmul(const Csr& A, const Csr& B) {
   return C;
 }
 
+// One damped-Jacobi step on a prolongator: (I - omega D^{-1} A) P, rows merged in column
+// order (both operands' rows are sorted), exact zeros dropped; row ranges on the host's threads.
+static Csr smooth_prolongator(const Csr& A, const std::vector<double>& dinv, double omega, const Csr& Pin) {
+  const Csr AP = matmul(A, Pin);
+  Csr P;
+  P.n = Pin.n;
+  P.m = Pin.m;
+  P.ptr.assign(P.n + 1, 0);
+  std::vector<std::vector<int>> pc(kChunks);
+  std::vector<std::vector<double>> pv(kChunks);
+  std::vector<int> rowlen(P.n);
+  parallel_chunks(P.n, [&](int ch, int b0, int e0) {
+    for (int r = b0; r < e0; ++r) {
+      int a = Pin.ptr[r], b = AP.ptr[r], len = 0;
+      while (a < Pin.ptr[r + 1] || b < AP.ptr[r + 1]) {
+        int c;
+        double v = 0;
+        if (b >= AP.ptr[r + 1] || (a < Pin.ptr[r + 1] && Pin.col[a] < AP.col[b])) {
+          c = Pin.col[a];
+          v = Pin.val[a++];
+        } else if (a >= Pin.ptr[r + 1] || AP.col[b] < Pin.col[a]) {
+          c = AP.col[b];
+          v = -omega * dinv[r] * AP.val[b++];
+        } else {
+          c = Pin.col[a];
+          v = Pin.val[a++] - omega * dinv[r] * AP.val[b++];
+        }
+        if (v != 0.0) {
+          pc[ch].push_back(c);
+          pv[ch].push_back(v);
+          ++len;
+        }
+      }
+      rowlen[r] = len;
+    }
+  });
+  for (int r = 0; r < P.n; ++r) P.ptr[r + 1] = P.ptr[r] + rowlen[r];
+  for (int ch = 0; ch < kChunks; ++ch) {
+    P.col.insert(P.col.end(), pc[ch].begin(), pc[ch].end());
+    P.val.insert(P.val.end(), pv[ch].begin(), pv[ch].end());
+  }
+  return P;
+}
+
 // Greedy aggregation of the nodes of a symmetric strength graph (adjacency lists).
 static int aggregate(int n, const std::vector<int>& gptr, const std::vector<int>& gadj, std::vector<int>& agg) {
   agg.assign(n, -1);
@@ -319,8 +364,8 @@ static bool dense_spd_inverse(int n, std::vector<double>& A) {
 }
 
 int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals,
-              const std::vector<double>& z, bool singular, double theta, int max_coarse, AmgHierarchy& H,
-              std::string& err) {
+              const std::vector<double>& z, bool singular, double theta, int max_coarse, int fine_smooth,
+              AmgHierarchy& H, std::string& err) {
   H.lv.clear();
   AmgLevel L0;
   L0.A = bsr_to_csr(E, NF, NS, cols, vals);
@@ -394,36 +439,12 @@ int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::ve
       }
       Pt.ptr[r + 1] = (int)Pt.col.size();
     }
-    // smoothed prolongator P = (I - omega D^{-1} A) Pt
+    // smoothed prolongator P = (I - omega D^{-1} A)^m Pt: m = fine_smooth steps on the
+    // finest level (a wider, better interpolation where the two-grid rate is set), one below
     const double omega = 4.0 / (3.0 * L.lmax);
-    Csr APt = matmul(L.A, Pt);
-    Csr P;
-    P.n = n;
-    P.m = na;
-    P.ptr.assign(n + 1, 0);
-    for (int r = 0; r < n; ++r) {
-      // merge row r of Pt and -omega dinv_r (A Pt)_r (both sorted)
-      int a = Pt.ptr[r], b = APt.ptr[r];
-      while (a < Pt.ptr[r + 1] || b < APt.ptr[r + 1]) {
-        int c;
-        double v = 0;
-        if (b >= APt.ptr[r + 1] || (a < Pt.ptr[r + 1] && Pt.col[a] < APt.col[b])) {
-          c = Pt.col[a];
-          v = Pt.val[a++];
-        } else if (a >= Pt.ptr[r + 1] || APt.col[b] < Pt.col[a]) {
-          c = APt.col[b];
-          v = -omega * L.dinv[r] * APt.val[b++];
-        } else {
-          c = Pt.col[a];
-          v = Pt.val[a++] - omega * L.dinv[r] * APt.val[b++];
-        }
-        if (v != 0.0) {
-          P.col.push_back(c);
-          P.val.push_back(v);
-        }
-      }
-      P.ptr[r + 1] = (int)P.col.size();
-    }
+    Csr P = std::move(Pt);
+    const int steps = level == 0 ? fine_smooth : 1;
+    for (int st = 0; st < steps; ++st) P = smooth_prolongator(L.A, L.dinv, omega, P);
     Csr R = transpose(P);
     Csr AP = matmul(L.A, P);
     Csr Ac = matmul(R, AP);
@@ -431,7 +452,6 @@ int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::ve
       L.RA = transpose(AP);
       L.AP = std::move(AP);
     }
-   
     L.P = std::move(P);
     L.R = std::move(R);
     AmgLevel next;

@@ -33,11 +33,13 @@ struct AmgHierarchy {
 // Builds the hierarchy for the BSR facet matrix (cols [NS][E], vals [NS][NF][NF][E]) with the
 // near-null vector z (the constant multiplier, scalar length E*NF); singular: z spans the
 // kernel of S (the coarsest level is then inverted as a pseudo-inverse that leaves out the
-// coarse image of z), else S is definite and so is every level.  theta: strength threshold;
+// coarse image of z), else S is definite and so is every level.  fine_smooth: damped-Jacobi
+// steps applied to the finest level's tentative prolongator (1 or more; one below it).
+// theta: strength threshold;
 // coarsening stops at max_coarse rows, or earlier (at most 4096 rows) when aggregation
 // no longer halves the level.
 int build_amg(int E, int NF, int NS, const std::vector<int>& cols, const std::vector<double>& vals,
-              const std::vector<double>& z, bool singular, double theta, int max_coarse, AmgHierarchy& H,
-              std::string& err);
+              const std::vector<double>& z, bool singular, double theta, int max_coarse, int fine_smooth,
+              AmgHierarchy& H, std::string& err);
 
 }  // namespace dfdg

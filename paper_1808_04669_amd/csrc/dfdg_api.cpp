@@ -209,6 +209,7 @@ extern "C" void dfdg_params_default(dfdg_params* p) {
   p->matrix_free = 0;
   p->mixed_solver = 1;
   p->local_space = DFDG_LOCAL_FE3;
+  p->mg_fine_smooth = 2;
 }
 
 static_assert(DFDG_HISTORY_DEPTH == kHistDepth, "history depth of the ABI and the kernels");
@@ -236,6 +237,7 @@ static int check_params(const dfdg_params* p, std::string& e) {
   if (p->facet_blocks < 0 || p->facet_blocks > 1024) { e = "facet_blocks must be in 0..1024"; return -1; }
   if (p->matrix_free != 0 && p->matrix_free != 1) { e = "matrix_free must be 0 or 1"; return -1; }
   if (p->mixed_solver != 0 && p->mixed_solver != 1) { e = "mixed_solver must be 0 or 1"; return -1; }
+  if (p->mg_fine_smooth < 1 || p->mg_fine_smooth > 3) { e = "mg_fine_smooth must be in 1..3"; return -1; }
   if (p->local_space != DFDG_LOCAL_FE3 && p->local_space != DFDG_LOCAL_FE4) {
     e = "local_space must be DFDG_LOCAL_FE3 or DFDG_LOCAL_FE4";
     return -1;
@@ -284,7 +286,8 @@ extern "C" int dfdg_ctx_create(const dfdg_mesh* mesh, const dfdg_params* prm, vo
     const int NFk = ctx->dim == 3 ? nF3(prm->k) : nF(prm->k);
     std::vector<double> z((size_t)h.E * NFk, 0.0);
     for (int F = 0; F < h.E; ++F) z[(size_t)F * NFk] = h.nearnull.empty() ? h.zdef[F] : h.nearnull[F];
-    if (build_amg(h.E, NFk, (int)(h.cols.size() / h.E), h.cols, h.vals, z, h.singular, 0.08, 1000, ctx->H, e)) {
+    if (build_amg(h.E, NFk, (int)(h.cols.size() / h.E), h.cols, h.vals, z, h.singular, 0.08, 1000,
+                  prm->mg_fine_smooth, ctx->H, e)) {
       g_mesh_err = e;
       delete ctx;
       return DFDG_E_MESH;
@@ -470,14 +473,17 @@ static void carve(dfdg_ctx* ctx, char* base) {
     while (D.lpr < 64 && 2 * D.lpr * div <= avg) D.lpr *= 2;
     int wmax = 1;
     for (int i = 0; i < M.n; ++i) wmax = std::max(wmax, M.ptr[i + 1] - M.ptr[i]);
-    if (wmax <= 4) D.lpr = 1;  // short rows: one lane reads its whole row at once (16-byte loads)
-    D.w = wmax <= 4 ? 4 : (wmax + D.lpr - 1) / D.lpr * D.lpr;
+    // short rows: one lane reads its whole row at once (16-byte loads; rows of up to 16
+    // entries when they are packed into FP16 with 16-bit columns, 4 entries per load)
+    const bool pack16 = pack && wmax <= 16 && M.m < 65536;
+    if (wmax <= 4 || pack16) D.lpr = 1;
+    D.w = wmax <= 4 ? 4 : pack16 ? (wmax + 3) / 4 * 4 : (wmax + D.lpr - 1) / D.lpr * D.lpr;
     const size_t ne = (size_t)M.n * D.w;
     D.col = c.take<int>(ne);
     D.val = c.take<double>(ne);
     D.val32 = f32 ? c.take<float>(ne) : nullptr;
-    const bool packed = pack && D.w == 4 && M.m < 65536;
-    D.pk = packed ? c.take<uint32_t>(4 * (size_t)M.n) : nullptr;
+    const bool packed = pack && D.w % 4 == 0 && D.w <= 16 && D.lpr == 1 && M.m < 65536;
+    D.pk = packed ? c.take<uint32_t>((size_t)D.w * M.n) : nullptr;
     D.val16 = half ? c.take<uint16_t>(ne) : nullptr;
     D.pscale = 1.0f;
     return packed;
@@ -666,7 +672,7 @@ extern "C" int dfdg_ctx_bind_workspace(dfdg_ctx* ctx, void* dev, size_t bytes) {
         for (double x : ve) vmax = std::max(vmax, std::fabs(x));
         if (!(vmax > 0)) vmax = 1;
         D.pscale = (float)vmax;
-        if (D.pk) HIPC(launch_pack_rows4(M.n, D.col, D.val, 1.0 / vmax, const_cast<uint32_t*>(D.pk), s));
+        if (D.pk) HIPC(launch_pack_rows(M.n, D.w, D.col, D.val, 1.0 / vmax, const_cast<uint32_t*>(D.pk), s));
         if (D.val16)
           HIPC(launch_to_half((long)ve.size(), D.val, 1.0 / vmax, const_cast<uint16_t*>(D.val16), s));
       }

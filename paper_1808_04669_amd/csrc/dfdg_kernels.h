@@ -42,8 +42,9 @@ struct DevCsr {
   const int* col;
   const double* val;
   const float* val32;
-  // rows of 4 entries in an FP32 cycle with fewer than 65536 columns: one 16-byte word per
-  // row, 4 16-bit column ids then 4 FP16 values of val / pscale (or null)
+  // rows of 4, 8, 12 or 16 entries (w) in an FP32 cycle with fewer than 65536 columns: one 16-byte
+  // word per 4 entries of a row, 4 16-bit column ids then 4 FP16 values of val / pscale (or
+  // null)
   const uint32_t* pk;
   float pscale;
   // FP16 values / pscale in the padded layout (the finest-level restriction of an FP32
@@ -173,7 +174,7 @@ hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, doub
                                        hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
 // pk[4i..4i+3] = row i of a 4-wide padded matrix packed as above (columns < 65536).
-hipError_t launch_pack_rows4(int n, const int* col, const double* val, double inv_scale, uint32_t* pk,
+hipError_t launch_pack_rows(int n, int w, const int* col, const double* val, double inv_scale, uint32_t* pk,
                              hipStream_t s);
 // out[i] = FP16 bits of x[i] * scale (round to nearest even).
 hipError_t launch_to_half(long n, const double* x, double scale, uint16_t* out, hipStream_t s);

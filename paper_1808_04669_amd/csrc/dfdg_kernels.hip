@@ -1484,15 +1484,18 @@ __global__ __launch_bounds__(kBlk) void k_csr_apply(DevCsr M, const V* __restric
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = g / LPR, sub = g % LPR;
   V s = 0;
-  if (sizeof(V) == 4 && LPR == 1 && M.pk) {  // packed rows: one 16-byte load per row
+  if (sizeof(V) == 4 && LPR == 1 && M.pk) {  // packed rows: one 16-byte load per 4 entries
     if (i < M.n) {
-      const uint4 w = *reinterpret_cast<const uint4*>(M.pk + (size_t)i * 4);
-      const _Float16 h0 = __builtin_bit_cast(_Float16, (uint16_t)(w.z & 0xffffu));
-      const _Float16 h1 = __builtin_bit_cast(_Float16, (uint16_t)(w.z >> 16));
-      const _Float16 h2 = __builtin_bit_cast(_Float16, (uint16_t)(w.w & 0xffffu));
-      const _Float16 h3 = __builtin_bit_cast(_Float16, (uint16_t)(w.w >> 16));
-      s = ((V)h0 * x[w.x & 0xffffu] + (V)h1 * x[w.x >> 16] + (V)h2 * x[w.y & 0xffffu] + (V)h3 * x[w.y >> 16]) *
-          (V)M.pscale;
+      const int ng = M.w >> 2;  // 1 to 4 groups of 4 entries
+      for (int gi = 0; gi < ng; ++gi) {
+        const uint4 w = *reinterpret_cast<const uint4*>(M.pk + ((size_t)i * ng + gi) * 4);
+        const _Float16 h0 = __builtin_bit_cast(_Float16, (uint16_t)(w.z & 0xffffu));
+        const _Float16 h1 = __builtin_bit_cast(_Float16, (uint16_t)(w.z >> 16));
+        const _Float16 h2 = __builtin_bit_cast(_Float16, (uint16_t)(w.w & 0xffffu));
+        const _Float16 h3 = __builtin_bit_cast(_Float16, (uint16_t)(w.w >> 16));
+        s += (V)h0 * x[w.x & 0xffffu] + (V)h1 * x[w.x >> 16] + (V)h2 * x[w.y & 0xffffu] + (V)h3 * x[w.y >> 16];
+      }
+      s *= (V)M.pscale;
     }
   } else if (LPR == 1 && M.w == 4) {  // rows of 4 entries, 16-byte aligned: vector loads
     if (i < M.n) {
@@ -2262,28 +2265,35 @@ __global__ void k_pack_half_pairs(int nv, int E, const double* __restrict__ vals
   }
 }
 
-__global__ void k_pack_rows4(int n, const int* __restrict__ col, const double* __restrict__ val, double inv_scale,
-                             uint32_t* __restrict__ pk) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t w[4];
+// Packed rows of w = 4 ng entries (ng = 1..4): group g of row i is one 16-byte word (4 16-bit column ids,
+// then the 4 values in FP16, scaled), entries 4g .. 4g+3 of the padded row.
+__global__ void k_pack_rows(int n, int w, const int* __restrict__ col, const double* __restrict__ val,
+                            double inv_scale, uint32_t* __restrict__ pk) {
+  const long u = (long)blockIdx.x * blockDim.x + threadIdx.x;  // one group per thread
+  const int ng = w >> 2;
+  if (u >= (long)n * ng) return;
+  const long e = 4 * u;  // the group's first entry in the padded row-major layout
+  uint32_t q[4];
 #pragma unroll
   for (int k = 0; k < 2; ++k)
-    w[k] = (uint32_t)(col[4 * i + 2 * k] & 0xffff) | ((uint32_t)(col[4 * i + 2 * k + 1] & 0xffff) << 16);
+    q[k] = (uint32_t)(col[e + 2 * k] & 0xffff) | ((uint32_t)(col[e + 2 * k + 1] & 0xffff) << 16);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[4 * i + 2 * k] * inv_scale));
-    const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[4 * i + 2 * k + 1] * inv_scale));
-    w[2 + k] = (uint32_t)lo | ((uint32_t)hi << 16);
+    const uint16_t lo = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[e + 2 * k] * inv_scale));
+    const uint16_t hi = __builtin_bit_cast(uint16_t, (_Float16)(float)(val[e + 2 * k + 1] * inv_scale));
+    q[2 + k] = (uint32_t)lo | ((uint32_t)hi << 16);
   }
 #pragma unroll
-  for (int k = 0; k < 4; ++k) pk[4 * (size_t)i + k] = w[k];
+  for (int k = 0; k < 4; ++k) pk[4 * u + k] = q[k];
 }
 
-hipError_t launch_pack_rows4(int n, const int* col, const double* val, double inv_scale, uint32_t* pk,
-                             hipStream_t s) {
+hipError_t launch_pack_rows(int n, int w, const int* col, const double* val, double inv_scale, uint32_t* pk,
+                            hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pack_rows4, dim3((n + 255) / 256), dim3(256), 0, s, n, col, val, inv_scale, pk);
+  if (w % 4 != 0 || w < 4 || w > 16) return hipErrorInvalidValue;
+  const long groups = (long)n * (w / 4);
+  hipLaunchKernelGGL(k_pack_rows, dim3((unsigned)((groups + 255) / 256)), dim3(256), 0, s, n, w, col, val, inv_scale,
+                     pk);
   return hipGetLastError();
 }
 

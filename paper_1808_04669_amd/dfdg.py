@@ -37,6 +37,7 @@ class Params(ctypes.Structure):
                 ("extrapolate", ctypes.c_int), ("graphs", ctypes.c_int), ("mg_fp32", ctypes.c_int),
                 ("mg_fine_fp16", ctypes.c_int), ("facet_blocks", ctypes.c_int), ("matrix_free", ctypes.c_int),
                 ("mixed_solver", ctypes.c_int),
+                ("mg_fine_smooth", ctypes.c_int),
                 ("local_space", ctypes.c_int)]
 
 
@@ -217,7 +218,7 @@ class Solver:
     def __init__(self, xyz, period, k, nu=0.0, alpha=2.0, precision="fp64", cg_rtol=1e-12, cg_maxit=20000,
                  precond="jacobi", ir_rtol=1e-10, inner_rtol=1e-4, extrapolate=0, graphs=True, mg_fp32=True,
                  mg_fine_fp16=True, facet_blocks=0, matrix_free=False, mixed_solver="krylov", local_space="fe3",
-                 outflow=None, device="cuda:0", stream=None):
+                 outflow=None, mg_fine_smooth=None, device="cuda:0", stream=None):
         lib = load_library()
         self._lib = lib
         self.device = torch.device(device)
@@ -239,6 +240,8 @@ class Solver:
         p.matrix_free = 1 if matrix_free else 0
         p.mixed_solver = {"krylov": 1, "restarted": 0}[mixed_solver]
         p.local_space = {"fe3": 0, "fe4": 1}[local_space]
+        if mg_fine_smooth is not None:
+            p.mg_fine_smooth = int(mg_fine_smooth)
         self.params = p
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         h = ctypes.c_void_p()
