@@ -229,3 +229,35 @@ def test_inout_grid_stride_and_mixed(precond):
     errm = ((out["mixed"] - out["fp64"]).norm() / out["fp64"].norm()).item()
     _log("inout mixed vs fp64", precond, errm)
     assert errm < 1e-6
+
+
+def test_inout_rk3_step_vjp_matches_finite_differences():
+    """The RK3-step vector-Jacobian product with inflow and outflow (mass inversions closed
+    at the inflow, open at the outflow; outgoing flux in the residual's transpose) against
+    central differences along increments."""
+    orc, s, _, _ = make_pair(6, 2, nu=1e-3, inout=True, inflow=_lift, cg_rtol=1e-14)
+    U0 = transfer(orc, orc.project(RandomStreamField(seed=1, kmax=2, norm=0.3)), s)
+    dt = 0.1 / 6 / 4
+    rng = np.random.default_rng(21)
+
+    def incr():
+        d = orc.mass_solve(rng.standard_normal(orc.space.ndof))
+        return s.load_vector(values_to_lib_raw(orc, s, d / np.sqrt(d @ (orc.M @ d))))
+
+    w = incr()
+    for _ in range(2):
+        d = incr()
+        h = 1e-6
+
+        def step(u):
+            v = u.clone()
+            s.reset_history()
+            s.rk3_step(v, dt)
+            return v
+
+        fd = torch.dot(w, step(U0 + h * d) - step(U0 - h * d)).item() / (2 * h)
+        Ub = w.clone()
+        s.rk3_step_vjp(U0, Ub, dt)
+        adj = torch.dot(Ub, d).item()
+        _log("inout step vjp", adj, fd)
+        assert abs(adj - fd) < 1e-6 * abs(fd) + 1e-10
