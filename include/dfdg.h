@@ -322,7 +322,8 @@ int dfdg_history_restore(dfdg_ctx* ctx, const double* hist_dev, const int* count
  *   left by dfdg_rk3_step_stages from U^n), so only the three adjoint solves run.
  *   Ubar_io_dev must not alias a state.
  * The adjoint solves are warm-started from those of the same stage in the previously
- * processed step (see dfdg_reset_adjoint_history); FP64 contexts only. */
+ * processed step (see dfdg_reset_adjoint_history); FP64 contexts only, triangle and
+ * tetrahedral meshes. */
 int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U_dev, const double* Lbar_dev,
                          double* Ubar_dev);
 int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un_dev, double* Ubar_io_dev, double dt,

@@ -1256,11 +1256,15 @@ extern "C" int dfdg_rk3_step_stages(dfdg_ctx* ctx, double* U, double dt, double*
 // ---------------------------------------------------------------------------------------
 // adjoint form
 // ---------------------------------------------------------------------------------------
+static hipError_t residual_vjp(dfdg_ctx* ctx, const double* U, const double* Lbar, double* Ubar, hipStream_t s) {
+  if (ctx->dim == 3) return launch_residual_vjp3(ctx->K, ctx->g, ctx->tb, U, Lbar, Ubar, ctx->prm.nu, s);
+  return launch_residual_vjp(ctx->K, ctx->g, ctx->tb, U, Lbar, Ubar, ctx->prm.nu, s);
+}
+
 extern "C" int dfdg_dg_residual_vjp(dfdg_ctx* ctx, const double* U, const double* Lbar, double* Ubar) {
   NEED_BOUND(ctx);
   if (!U || !Lbar || !Ubar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
-  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
-  HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, U, Lbar, Ubar, ctx->prm.nu, ctx->stream));
+  HIPC(residual_vjp(ctx, U, Lbar, Ubar, ctx->stream));
   return DFDG_OK;
 }
 
@@ -1279,7 +1283,7 @@ static int fe_transpose(dfdg_ctx* ctx, int stage, const double* u, const double*
   rc = mass_solve_impl(ctx, y, false, ctx->Wbuf, ctx->lamw, cold, si, 0, 0, nullptr, 0, nullptr, 0);
   if (rc) return rc;
   stage_push(ctx, 3 + stage);
-  HIPC(launch_residual_vjp(ctx->K, ctx->g, ctx->tb, u, ctx->Wbuf, out, ctx->prm.nu, s));
+  HIPC(residual_vjp(ctx, u, ctx->Wbuf, out, s));
   HIPC(launch_axpby(ctx->nU, 1.0, y, dt, out, s));  // out = y + dt J^T P y
   return DFDG_OK;
 }
@@ -1325,7 +1329,6 @@ extern "C" int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un, double* Ybar, 
   if (!Un || !Ybar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
-  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
   use_integrator(ctx, 1);
   double* U1 = ctx->Ustages[0];
   double* U2 = ctx->Ustages[1];
@@ -1345,7 +1348,6 @@ extern "C" int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un, const d
   if (Ybar == Un || Ybar == U1 || Ybar == U2) return fail(ctx, DFDG_E_INVALID_ARG, "Ybar must not alias a state");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(ctx, DFDG_E_INVALID_ARG, "dt must be finite and > 0");
   if (ctx->prm.precision != DFDG_FP64) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint runs in FP64 only");
-  if (ctx->dim == 3) return fail(ctx, DFDG_E_UNSUPPORTED, "the adjoint form runs on triangle meshes");
   dfdg_solve_info si[3]{};
   int rc = rk3_vjp_core(ctx, Un, U1, U2, Ybar, dt, si);
   if (rc) return rc;

@@ -102,6 +102,8 @@ hipError_t launch_diag_finish(int nb, const double* partials, double* res, hipSt
 
 // ---- tetrahedra (dfdg_kernels3.hip): the element steps; the facet kernels above are shared
 // (DevBsr::ns = 7).  FP64 only, K = 1, 2.
+hipError_t launch_residual_vjp3(int K, const DevGeo& g, const DevTabs& tb, const double* U, const double* Lbar,
+                                double* Ubar, double nu, hipStream_t s);
 hipError_t launch_residual3(int K, const DevGeo& g, const DevTabs& tb, const double* U, double* L, double nu,
                             hipStream_t s);
 hipError_t launch_cond_rhs3(int K, const DevGeo& g, const DevTabs& tb, const double* F, double* q, hipStream_t s);

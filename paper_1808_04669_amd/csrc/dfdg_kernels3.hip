@@ -238,6 +238,173 @@ __global__ __launch_bounds__(kEBlk) void k_residual3(DevGeo g, DevTabs tb, const
 }
 
 // ---------------------------------------------------------------------------------------
+// adjoint form on tetrahedra: Ubar = J_L(U)^T Lbar, as on triangles (upwind side frozen):
+// with y the broken field of coefficients Lbar, the own coefficients receive
+//   volume  int phi . (grad y u + grad y^T u) - nu grad y : grad phi,
+//   face    -int [1/2 (phi.n)(u_up . dy) + un (phi . dy) (own side upwind)]
+//           + the viscous face terms of y (B_h symmetric), dy = y_own - y_nbr;
+// an outflow face -int H(u.n) [(phi.n)(u.y) + (u.n)(phi.y)]; walls and inflows nothing.
+// ---------------------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(kEBlk) void k_residual_vjp3(DevGeo g, DevTabs tb, const double* __restrict__ U,
+                                                         const double* __restrict__ Y, double* __restrict__ Ubar,
+                                                         double nu) {
+  constexpr int P = nP3(K), NQV = nQV3(K), NQF = nQF3(K);
+  __shared__ ResTabs3<K> s;
+  stage_tabs3<K>(s, tb);
+  const int T = g.T;
+  const int t = xcd_block() * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double u[3][P], y[3][P], acc[3][P];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      u[c][i] = U[(size_t)(c * P + i) * T + t];
+      y[c][i] = Y[(size_t)(c * P + i) * T + t];
+      acc[c][i] = 0;
+    }
+  double Ji[3][3];
+  load_Jinv3(g, t, Ji);
+  const double det = g.detJ[t], isq = g.isq[t], sq = det * isq;
+  for (int q = 0; q < NQV; ++q) {
+    double uq[3], gy[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double a = 0, b[3] = {0, 0, 0};
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        a += u[c][i] * s.Vv[q][i];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) b[e] += y[c][i] * s.Gv[q][e][i];
+      }
+      uq[c] = a * isq;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) gy[c][j] = isq * (b[0] * Ji[0][j] + b[1] * Ji[1][j] + b[2] * Ji[2][j]);
+    }
+    double av[3], Gt[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      av[c] = 0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) av[c] += gy[c][j] * uq[j] + gy[j][c] * uq[j];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        Gt[c][a] = -nu * (gy[c][0] * Ji[a][0] + gy[c][1] * Ji[a][1] + gy[c][2] * Ji[a][2]);
+    }
+    const double w = s.Wv[q] * sq;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        acc[c][i] += w * (av[c] * s.Vv[q][i] + Gt[c][0] * s.Gv[q][0][i] + Gt[c][1] * s.Gv[q][1][i] +
+                          Gt[c][2] * s.Gv[q][2][i]);
+  }
+#pragma unroll 1
+  for (int f = 0; f < 4; ++f) {
+    const size_t idx = (size_t)f * T + t;
+    const int nb = g.nbr[idx];
+    const int code = g.code[idx];
+    if (nb < 0 && !((code >> 6) & 1)) continue;  // closed boundary face: nothing
+    const double n[3] = {g.nx[idx], g.ny[idx], g.nz[idx]};
+    const double li = g.flen[idx] * isq;
+    if (nb < 0) {  // outflow face
+      for (int r = 0; r < NQF; ++r) {
+        double uo[3], yo[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double a = 0, ya = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            a += u[c][i] * s.Vf[f][r][i];
+            ya += y[c][i] * s.Vf[f][r][i];
+          }
+          uo[c] = a * isq;
+          yo[c] = ya * isq;
+        }
+        const double un = uo[0] * n[0] + uo[1] * n[1] + uo[2] * n[2];
+        if (un > 0.0) {
+          const double w = s.Wf[r] * li, uy = uo[0] * yo[0] + uo[1] * yo[1] + uo[2] * yo[2];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double av = -(n[c] * uy + un * yo[c]);
+#pragma unroll
+            for (int i = 0; i < P; ++i) acc[c][i] += w * av * s.Vf[f][r][i];
+          }
+        }
+      }
+      continue;
+    }
+    const int fn = code & 3, pid = (code >> 2) & 7;
+    const double sig = g.sig[idx], isqn = g.isq[nb];
+    double Jn[3][3];
+    load_Jinv3(g, nb, Jn);
+    double nJ[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nJ[a] = n[0] * Ji[a][0] + n[1] * Ji[a][1] + n[2] * Ji[a][2];
+    for (int r = 0; r < NQF; ++r) {
+      const int rn = s.pidx[pid][r];
+      double uo[3], un[3], yo[3], ynb[3], go[3][3], gn[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double a = 0, an = 0, ya = 0, yan = 0, b[3] = {0, 0, 0}, bn[3] = {0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const double vn = U[(size_t)(c * P + i) * T + nb], wn = Y[(size_t)(c * P + i) * T + nb];
+          a += u[c][i] * s.Vf[f][r][i];
+          an += vn * s.Vf[fn][rn][i];
+          ya += y[c][i] * s.Vf[f][r][i];
+          yan += wn * s.Vf[fn][rn][i];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) {
+            b[e] += y[c][i] * s.Gf[f][r][e][i];
+            bn[e] += wn * s.Gf[fn][rn][e][i];
+          }
+        }
+        uo[c] = a * isq;
+        un[c] = an * isqn;
+        yo[c] = ya * isq;
+        ynb[c] = yan * isqn;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          go[c][j] = isq * (b[0] * Ji[0][j] + b[1] * Ji[1][j] + b[2] * Ji[2][j]);
+          gn[c][j] = isqn * (bn[0] * Jn[0][j] + bn[1] * Jn[1][j] + bn[2] * Jn[2][j]);
+        }
+      }
+      const double unrm = 0.5 * ((uo[0] + un[0]) * n[0] + (uo[1] + un[1]) * n[1] + (uo[2] + un[2]) * n[2]);
+      const bool own_up = unrm >= 0.0;
+      double dy[3], updy = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        dy[c] = yo[c] - ynb[c];
+        updy += (own_up ? uo[c] : un[c]) * dy[c];
+      }
+      double Av[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double avgn = 0.5 * ((go[c][0] + gn[c][0]) * n[0] + (go[c][1] + gn[c][1]) * n[1] +
+                                   (go[c][2] + gn[c][2]) * n[2]);
+        const double conv = -(0.5 * n[c] * updy + (own_up ? unrm * dy[c] : 0.0));
+        Av[c] = conv + nu * avgn - nu * sig * dy[c];  // minus the viscous flux Q(y)
+      }
+      const double w = s.Wf[r] * li;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double h = 0.5 * nu * dy[c];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          acc[c][i] += w * (Av[c] * s.Vf[f][r][i] +
+                            h * (nJ[0] * s.Gf[f][r][0][i] + nJ[1] * s.Gf[f][r][1][i] + nJ[2] * s.Gf[f][r][2][i]));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < P; ++i) Ubar[(size_t)(c * P + i) * T + t] = acc[c][i];
+}
+
+// ---------------------------------------------------------------------------------------
 // a4 / a6: element condensation and recovery (eq. (FE3), orthonormal basis: M_T = I)
 // ---------------------------------------------------------------------------------------
 // y <- W_T y = y - D_T^T (D_T D_T^T)^{-1} D_T y, D_T = sum_a Jinv[a][c] Dh[a]
@@ -744,6 +911,13 @@ hipError_t launch_residual3(int K, const DevGeo& g, const DevTabs& tb, const dou
     if (nu != 0.0) DFDG_LAUNCH_TIMED3((k_residual3<KK, true>), grid, blk, s, g, tb, U, L, nu);
     else DFDG_LAUNCH_TIMED3((k_residual3<KK, false>), grid, blk, s, g, tb, U, L, nu);
   });
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_vjp3(int K, const DevGeo& g, const DevTabs& tb, const double* U, const double* Lbar,
+                                double* Ubar, double nu, hipStream_t s) {
+  DFDG_DISPATCH_K3(K, hipLaunchKernelGGL((k_residual_vjp3<KK>), dim3(nblk(g.T, kEBlk)), dim3(kEBlk), 0, s, g, tb, U,
+                                         Lbar, Ubar, nu));
   return hipGetLastError();
 }
 
