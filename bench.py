@@ -56,8 +56,9 @@ def parse():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--rtol", type=float, default=1e-12)
     ap.add_argument("--precond", default="amg", choices=["jacobi", "block_jacobi", "amg"])
-    ap.add_argument("--extrapolate", default="adaptive",
-                    help="warm-start extrapolation order 0..4, or adaptive (chosen per solve)")
+    ap.add_argument("--extrapolate", default="project",
+                    help="warm-start extrapolation order 0..4, adaptive (chosen per solve), or project "
+                         "(projection onto earlier solutions)")
     ap.add_argument("--order", default="morton")
     ap.add_argument("--no-mg-fp16", action="store_true",
                     help="finest-level multigrid smoothing reads S in FP32 instead of FP16")
@@ -116,8 +117,12 @@ def make_solver(N, k, precision, args, order=None, rtol=None, nu=0.0, **kw):
     from inputs import periodic_split_square
     from paper_1808_04669_amd import Solver
     xyz, per = periodic_split_square(N, order or args.order)
+    # the projected start values run in FP64 contexts; mixed ones extrapolate
+    ex = kw.pop("extrapolate", args.extrapolate)
+    if precision == "mixed" and ex == "project":
+        ex = "adaptive"
     s = Solver(xyz, per, k, nu=nu, precision=precision, cg_rtol=rtol or args.rtol, precond=args.precond,
-               extrapolate=args.extrapolate,
+               extrapolate=ex,
                **{"mg_fine_fp16": not args.no_mg_fp16, "mg_fine_smooth": args.mg_fine_smooth, **kw})
     s._xyz = xyz
     return s
@@ -392,7 +397,9 @@ def adjoint_cost(args):
     from inputs import RandomStreamField
     from paper_1808_04669_amd.adjoint import final_energy
     N, k, steps, every = args.adjoint_N, 2, args.adjoint_steps, 10
-    s = make_solver(N, k, "fp64", args, nu=1e-3)
+    # extrapolated start values: the checkpointed recomputation repeats the original solves
+    # bit for bit (the projection basis is not part of the saved history)
+    s = make_solver(N, k, "fp64", args, nu=1e-3, extrapolate="adaptive")
     U0, vmax, _ = project_field(s, RandomStreamField(seed=0, kmax=8))
     dt = 0.1 / N / (k ** 2 * vmax)
     U = U0.clone()
@@ -402,7 +409,7 @@ def adjoint_cost(args):
     torch.cuda.synchronize()
     t_fwd, _ = timed_run(s, U0.clone(), dt, steps, 0)
     # second context on its own stream: recomputes checkpoint segments during the sweep
-    r = make_solver(N, k, "fp64", args, nu=1e-3, stream=torch.cuda.Stream())
+    r = make_solver(N, k, "fp64", args, nu=1e-3, stream=torch.cuda.Stream(), extrapolate="adaptive")
     times = {}
     for name, rec in (("sequential", None), ("pipelined", r)):
         U0r = U0.clone().requires_grad_(True)

@@ -77,6 +77,7 @@ enum {
 enum { DFDG_FP64 = 0, DFDG_MIXED = 1 };            /* dfdg_params.precision */
 #define DFDG_HISTORY_DEPTH 6  /* earlier multipliers kept per stage for warm starts */
 #define DFDG_EXTRAPOLATE_ADAPTIVE 5  /* dfdg_params.extrapolate: order chosen per solve */
+#define DFDG_EXTRAPOLATE_PROJECT 6   /* dfdg_params.extrapolate: projection onto earlier solutions */
 enum { DFDG_JACOBI = 0, DFDG_BLOCK_JACOBI = 1, DFDG_AMG = 2 };  /* dfdg_params.precond */
 enum { DFDG_LOCAL_FE3 = 0, DFDG_LOCAL_FE4 = 1 };  /* dfdg_params.local_space */
 
@@ -102,7 +103,14 @@ typedef struct {
                         last extrapolate+1 steps, DFDG_EXTRAPOLATE_ADAPTIVE = the order
                         1..4 whose prediction of the last multiplier from the ones before
                         it was best (decided on the device per solve, among the orders the
-                        DFDG_HISTORY_DEPTH kept multipliers allow) */
+                        DFDG_HISTORY_DEPTH kept multipliers allow), DFDG_EXTRAPOLATE_PROJECT
+                        (FP64 contexts) = the element closest in the S-norm to the solution
+                        among the combinations of up to 24 earlier forward stage solutions
+                        (of any stage): an S-orthogonal basis of them, grown by two
+                        Gram-Schmidt passes per solve and rebuilt from the latest 8 when
+                        full; its start value needs the new right-hand side only.  Costs
+                        65 vectors of n_lambda doubles of workspace.  The
+                        adjoint's stage solves keep the extrapolation of order 4. */
   int graphs;        /* 1: replay PCG iterations from captured HIP graphs (default);
                         0: launch every kernel individually.  Same results bit for bit. */
   int mg_fp32;       /* DFDG_AMG with DFDG_FP64: 1 = run the V-cycle in FP32 (default; the
@@ -306,7 +314,10 @@ int dfdg_reset_adjoint_history(dfdg_ctx* ctx);
  *   counts_host[3].  Asynchronous on the context stream.
  * dfdg_history_restore: the inverse (counts in 0..DFDG_HISTORY_DEPTH), e.g. at a
  *   checkpoint before a trajectory segment is recomputed, which then repeats the
- *   original solves exactly. */
+ *   original solves exactly.  With DFDG_EXTRAPOLATE_PROJECT the blob holds no forward
+ *   history (the projection basis is not part of it) and a restore empties the basis:
+ *   a recomputed segment then starts its solves from other start values and repeats the
+ *   original to the solver tolerance, not bit for bit. */
 int dfdg_history_bytes(const dfdg_ctx* ctx, size_t* bytes);
 int dfdg_history_save(dfdg_ctx* ctx, double* hist_dev, int* counts_host);
 int dfdg_history_restore(dfdg_ctx* ctx, const double* hist_dev, const int* counts_host);

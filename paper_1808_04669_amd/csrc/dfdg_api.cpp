@@ -69,6 +69,14 @@ struct dfdg_ctx {
   // captured PCG iterations: [2j + p] holds 2^j consecutive iterations (j = 0, 1, 2)
   // starting with parity p (0 even, 1 odd)
   hipGraphExec_t graph64[6] = {}, graph32[6] = {};
+  // start values of the forward stage solves projected onto earlier solutions
+  // (DFDG_EXTRAPOLATE_PROJECT): basis X (images SX, S-norms squared pjnrm) of proj_nb
+  // vectors, and a ring of the latest proj_raw solutions and right-hand sides (next slot
+  // proj_head) that the basis is rebuilt from when full
+  bool proj_on = false, proj_req = false;
+  int proj_nb = 0, proj_raw = 0, proj_head = 0;
+  double *pjX[kProjMax] = {}, *pjSX[kProjMax] = {}, *pjRawL[kProjKeep] = {}, *pjRawG[kProjKeep] = {};
+  double *pjx0 = nullptr, *pjnrm = nullptr, *pjcA = nullptr, *pjcB = nullptr, *pjpart = nullptr;
   int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
   double* noalloc = nullptr;  // device address of the static scratch of dfdg_diagnostics_noalloc
@@ -79,6 +87,8 @@ struct dfdg_ctx {
 static void invalidate_guesses(dfdg_ctx* ctx) {
   for (int i = 0; i < 3; ++i) ctx->gready[i] = false;
   ctx->defer_slot = -1;
+  // the projection basis holds the same history
+  ctx->proj_nb = ctx->proj_raw = ctx->proj_head = 0;
 }
 
 static thread_local std::string g_mesh_err;
@@ -230,7 +240,14 @@ static int check_params(const dfdg_params* p, std::string& e) {
     if (!(p->ir_rtol > 0 && p->ir_rtol < 1)) { e = "ir_rtol must be in (0,1)"; return -1; }
     if (!(p->inner_rtol > 0 && p->inner_rtol < 1)) { e = "inner_rtol must be in (0,1)"; return -1; }
   }
-  if (p->extrapolate < 0 || p->extrapolate > kExtrapAdaptive) { e = "extrapolate must be in 0..4 or DFDG_EXTRAPOLATE_ADAPTIVE"; return -1; }
+  if (p->extrapolate < 0 || p->extrapolate > DFDG_EXTRAPOLATE_PROJECT) {
+    e = "extrapolate must be in 0..4, DFDG_EXTRAPOLATE_ADAPTIVE or DFDG_EXTRAPOLATE_PROJECT";
+    return -1;
+  }
+  if (p->extrapolate == DFDG_EXTRAPOLATE_PROJECT && p->precision != DFDG_FP64) {
+    e = "DFDG_EXTRAPOLATE_PROJECT needs an FP64 context";
+    return -1;
+  }
   if (p->graphs != 0 && p->graphs != 1) { e = "graphs must be 0 or 1"; return -1; }
   if (p->mg_fp32 != 0 && p->mg_fp32 != 1) { e = "mg_fp32 must be 0 or 1"; return -1; }
   if (p->mg_fine_fp16 != 0 && p->mg_fine_fp16 != 1) { e = "mg_fine_fp16 must be 0 or 1"; return -1; }
@@ -431,6 +448,22 @@ static void carve(dfdg_ctx* ctx, char* base) {
   for (int s = 0; s < kHistSlots; ++s)
     for (int j = 0; j < kHistDepth; ++j) ctx->hist[s][j] = c.take<double>(nL);
   for (int s = 0; s < 3; ++s) ctx->gbuf[s] = c.take<double>(nL);
+  ctx->proj_on = ctx->prm.extrapolate == DFDG_EXTRAPOLATE_PROJECT;
+  if (ctx->proj_on) {
+    for (int i = 0; i < kProjMax; ++i) {
+      ctx->pjX[i] = c.take<double>(nL);
+      ctx->pjSX[i] = c.take<double>(nL);
+    }
+    for (int i = 0; i < kProjKeep; ++i) {
+      ctx->pjRawL[i] = c.take<double>(nL);
+      ctx->pjRawG[i] = c.take<double>(nL);
+    }
+    ctx->pjx0 = c.take<double>(nL);
+    ctx->pjnrm = c.take<double>(kProjMax);
+    ctx->pjcA = c.take<double>(kProjMax);
+    ctx->pjcB = c.take<double>(kProjMax);
+    ctx->pjpart = c.take<double>((size_t)kProjGrid * kProjMax);
+  }
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
   ctx->partials = c.take<double>(4 * maxblk);
@@ -848,6 +881,84 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   return DFDG_OK;
 }
 
+// ---- start values projected onto earlier forward stage solutions ----------------------
+static PjVecs pj_vecs(double* const* v, int n) {
+  PjVecs p{};
+  for (int i = 0; i < n; ++i) p.p[i] = v[i];
+  return p;
+}
+
+// x = the element of span X closest in the S-norm to the solution of S x = g (g in ctx->gv);
+// also kept in pjx0, with its coefficients in pjcA, for proj_push.
+static int proj_start(dfdg_ctx* ctx, double* x) {
+  hipStream_t s = ctx->stream;
+  const long n = ctx->nL;
+  const int nb = ctx->proj_nb;
+  if (nb == 0) {
+    HIPC(launch_fill(n, 0.0, x, s));
+    return DFDG_OK;
+  }
+  const PjVecs X = pj_vecs(ctx->pjX, nb);
+  HIPC(launch_pj_dots(n, nb, X, ctx->gv, ctx->pjpart, s));
+  HIPC(launch_pj_coef(n, nb, 0, 0, ctx->pjpart, ctx->pjnrm, ctx->pjcA, s));
+  HIPC(launch_pj_combine(n, nb, X, ctx->pjcA, x, ctx->pjx0, s));
+  return DFDG_OK;
+}
+
+// Basis vector `slot` from the solution a of S a = Sa (Sa its right-hand side): the part of
+// a S-orthogonal to X_0..X_{slot-1}, by two classical Gram-Schmidt passes (the first with
+// the coefficients of the start value when a0 = the start value is given: a - a0 is then
+// that part up to rounding).  ca, cSa (optional) receive copies of a and Sa.
+static int proj_add(dfdg_ctx* ctx, int slot, const double* a, const double* a0, const double* Sa, double* ca,
+                    double* cSa) {
+  hipStream_t s = ctx->stream;
+  const long n = ctx->nL;
+  const PjVecs X = pj_vecs(ctx->pjX, slot), SX = pj_vecs(ctx->pjSX, slot);
+  double* v = ctx->pjX[slot];
+  double* Sv = ctx->pjSX[slot];
+  double* part = ctx->pjpart;
+  if (slot > 0) {
+    if (!a0) {
+      HIPC(launch_pj_dots(n, slot, X, Sa, part, s));
+      HIPC(launch_pj_coef(n, slot, 0, 0, part, ctx->pjnrm, ctx->pjcA, s));
+    }
+    HIPC(launch_pj_update(n, slot, X, SX, ctx->pjcA, a, a0, Sa, v, Sv, ca, cSa, 0, part, s));
+    HIPC(launch_pj_coef(n, slot, 0, 0, part, ctx->pjnrm, ctx->pjcB, s));
+    HIPC(launch_pj_update(n, slot, X, SX, ctx->pjcB, v, nullptr, Sv, v, Sv, nullptr, nullptr, 1, part, s));
+  } else {
+    HIPC(launch_pj_update(n, 0, X, SX, ctx->pjcA, a, nullptr, Sa, v, Sv, ca, cSa, 1, part, s));
+  }
+  HIPC(launch_pj_coef(n, 1, 1, slot, part, ctx->pjnrm, ctx->pjcB, s));
+  return DFDG_OK;
+}
+
+// After a converged forward stage solve with solution x (start value from proj_start, the
+// right-hand side in ctx->gv): keep (x, g) in the ring, and extend the basis, or rebuild it
+// from the ring (oldest first) when it is full.
+static int proj_push(dfdg_ctx* ctx, const double* x) {
+  hipStream_t s = ctx->stream;
+  const int h = ctx->proj_head;
+  ctx->proj_head = (h + 1) % kProjKeep;
+  ctx->proj_raw = std::min(ctx->proj_raw + 1, kProjKeep);
+  if (ctx->proj_nb < kProjMax) {
+    const int slot = ctx->proj_nb;
+    const int rc = proj_add(ctx, slot, x, slot > 0 ? ctx->pjx0 : nullptr, ctx->gv, ctx->pjRawL[h], ctx->pjRawG[h]);
+    if (!rc) ctx->proj_nb = slot + 1;
+    return rc;
+  }
+  const size_t bytes = (size_t)ctx->nL * sizeof(double);
+  HIPC(hipMemcpyAsync(ctx->pjRawL[h], x, bytes, hipMemcpyDeviceToDevice, s));
+  HIPC(hipMemcpyAsync(ctx->pjRawG[h], ctx->gv, bytes, hipMemcpyDeviceToDevice, s));
+  ctx->proj_nb = 0;
+  int rc = DFDG_OK;
+  for (int j = 0; j < ctx->proj_raw && !rc; ++j) {
+    const int r = (ctx->proj_head - ctx->proj_raw + j + kProjKeep) % kProjKeep;
+    rc = proj_add(ctx, j, ctx->pjRawL[r], nullptr, ctx->pjRawG[r], nullptr, nullptr);
+    if (!rc) ctx->proj_nb = j + 1;
+  }
+  return rc;
+}
+
 // Solve S lam = g for the q currently in ctx->q; lam holds the start on entry.  The PCG
 // runs in the fixed buffer lamx (captured graphs keep their arguments).
 static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
@@ -857,7 +968,9 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
   const DevGeo& g = ctx->g;
   const DevBsr& A = ctx->A;
   double* x = ctx->lamx;
-  if (lam != x) HIPC(hipMemcpyAsync(x, lam, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // a forward stage solve with projected start values forms its start once g is known
+  const bool proj = ctx->proj_on && ctx->proj_req && ctx->prm.precision == DFDG_FP64;
+  if (lam != x && !proj) HIPC(hipMemcpyAsync(x, lam, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
   PcgScalars fin{};
   dfdg_solve_info inf{};
   const bool amg = ctx->prm.precond == DFDG_AMG;
@@ -870,6 +983,10 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
     const PcgBufs& pb = ctx->pb;
     const bool mixed = ctx->prm.precision == DFDG_MIXED;
     HIPC(launch_gather_g(NF, g, ctx->q, ctx->gv, pb, mixed ? ctx->prm.ir_rtol : ctx->prm.cg_rtol, ctx->prm.cg_maxit, s));
+    if (proj) {
+      const int rc = proj_start(ctx, x);
+      if (rc) return rc;
+    }
     HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
     const bool c32 = mixed || ctx->prm.mg_fp32 != 0;
     const bool fused = amg && ctx->mg.nlev >= 2;
@@ -962,6 +1079,10 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
   // it, so that warm starts built from earlier solutions cannot let it drift
   HIPC(launch_deflate(NF, g, x, ctx->pb.gg, s));
   if (lam != x) HIPC(hipMemcpyAsync(lam, x, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (proj && inf.status == DFDG_OK && !fin.zero_rhs) {
+    const int rc = proj_push(ctx, x);
+    if (rc) return rc;
+  }
   if (info) *info = inf;
   return DFDG_OK;
 }
@@ -1135,6 +1256,12 @@ static int rk_stage(dfdg_ctx* ctx, int s, const double* Us, const double* Un, do
   const bool mixed = ctx->prm.precision == DFDG_MIXED;
   void* L = mixed ? (void*)ctx->L32 : (void*)ctx->Lbuf;
   HIPC(el_residual(ctx, mixed, Us, L, ctx->stream));
+  if (ctx->proj_on) {  // start value projected inside the solve, once its right-hand side is known
+    ctx->proj_req = true;
+    const int rc = mass_solve_impl(ctx, L, mixed, out, ctx->lamw, false, inf, 1, a, Un, b, Us, dt);
+    ctx->proj_req = false;
+    return rc;
+  }
   bool cold;
   int rc = stage_guess(ctx, s, &cold);
   if (rc) return rc;
@@ -1183,6 +1310,12 @@ static int pl_stage(dfdg_ctx* ctx, int s, const double* Us, double* out, dfdg_so
   const bool mixed = ctx->prm.precision == DFDG_MIXED;
   void* L = mixed ? (void*)ctx->L32 : (void*)ctx->Lbuf;
   HIPC(el_residual(ctx, mixed, Us, L, ctx->stream));
+  if (ctx->proj_on) {
+    ctx->proj_req = true;
+    const int rc = mass_solve_impl(ctx, L, mixed, out, ctx->lamw, false, inf, 0, 0, nullptr, 0, nullptr, 0);
+    ctx->proj_req = false;
+    return rc;
+  }
   bool cold;
   int rc = stage_guess(ctx, s, &cold);
   if (rc) return rc;

@@ -175,6 +175,21 @@ constexpr int kExtrapParts = 4 * 1024;
 hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, double* part, double* out,
                                        hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
+
+// Start values projected onto earlier solutions (S-orthogonal basis X_i with images S X_i
+// and S-norms squared nrm[i]; block partials in part[kProjGrid][kProjMax]).
+constexpr int kProjMax = 24;   // basis vectors kept
+constexpr int kProjKeep = 8;   // latest solutions the basis is rebuilt from when full
+constexpr int kProjGrid = 512;
+struct PjVecs { const double* p[kProjMax]; };
+hipError_t launch_pj_dots(long n, int nb, const PjVecs& Y, const double* w, double* part, hipStream_t s);
+hipError_t launch_pj_coef(long n, int nb, int mode, int slot, const double* part, double* nrm, double* coef,
+                          hipStream_t s);
+hipError_t launch_pj_combine(long n, int nb, const PjVecs& X, const double* coef, double* x, double* x0,
+                             hipStream_t s);
+hipError_t launch_pj_update(long n, int nb, const PjVecs& X, const PjVecs& SX, const double* coef, const double* a,
+                            const double* a0, const double* Sa, double* v, double* Sv, double* ca, double* cSa,
+                            int mode, double* part, hipStream_t s);
 // pk[4i..4i+3] = row i of a 4-wide padded matrix packed as above (columns < 65536).
 hipError_t launch_pack_rows(int n, int w, const int* col, const double* val, double inv_scale, uint32_t* pk,
                              hipStream_t s);

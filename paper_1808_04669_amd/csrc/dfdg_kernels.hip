@@ -13,7 +13,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <mutex>
 
 #include "dfdg_device.h"
@@ -1817,6 +1819,190 @@ __device__ inline double extrapolate_at(int order, Q q) {
   }
   return v;
 }
+
+// ---- start values by projection onto earlier solutions (energy norm of S) ---------------
+// The stage solves of a time integration share S; their solutions lie close to the span of
+// the last few.  With a basis X_i of that span, S-orthogonal (X_i . S X_j = 0 for i != j,
+// n_i = X_i . S X_i) and stored with its images S X_i, the element of the span closest to
+// the solution of S x = g in the S-norm is sum_i (X_i . g / n_i) X_i: it needs g, not the
+// solution.  Basis vectors are kept unnormalised; a vector whose n_i failed the test of
+// k_pj_coef has n_i = +inf and drops out of every sum.
+
+// Thread i < M of the block gets the block total of acc[i] (others 0).  The kernels below
+// are instantiated for each basis size NB (0..kProjMax), so that the loads of all basis
+// vectors at an entry are issued together.
+template <int M>
+__device__ inline double pj_block_rows(const double (&acc)[M > 0 ? M : 1]) {
+  __shared__ double sh[kBlk / 64][kProjMax];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < M; ++i) {
+    const double v = wave_sum(acc[i]);
+    if (lane == 0) sh[wv][i] = v;
+  }
+  __syncthreads();
+  double t = 0;
+  if ((int)threadIdx.x < M)
+#pragma unroll
+    for (int w = 0; w < kBlk / 64; ++w) t += sh[w][threadIdx.x];
+  return t;
+}
+
+// part[block][i] = this block's share of Y_i . w, i < NB.
+template <int NB>
+__global__ __launch_bounds__(kBlk) void k_pj_dots(long n, PjVecs Y, const double* __restrict__ w,
+                                                  double* __restrict__ part) {
+  double acc[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) acc[i] = 0;
+  for (long e = (long)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const double we = w[e];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) acc[i] += Y.p[i][e] * we;
+  }
+  const double t = pj_block_rows<NB>(acc);
+  if ((int)threadIdx.x < NB) part[(size_t)blockIdx.x * kProjMax + threadIdx.x] = t;
+}
+
+// One block.  mode 0 (M = nb): coef[i] = (sum of the G block partials of i) / nrm[i].
+// mode 1 (M = 1): n = the summed partial 0 is the S-norm squared of basis vector `slot`;
+// kept in nrm[slot] when finite and above 1e-20 times n_0 (positive for slot 0), else +inf.
+template <int M>
+__global__ __launch_bounds__(kBlk) void k_pj_coef(int G, int mode, int slot, const double* __restrict__ part,
+                                                  double* __restrict__ nrm, double* __restrict__ coef) {
+  double acc[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc[i] = 0;
+  for (int b = threadIdx.x; b < G; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < M; ++i) acc[i] += part[(size_t)b * kProjMax + i];
+  const double t = pj_block_rows<M>(acc);
+  if (mode == 0) {
+    if ((int)threadIdx.x < M) coef[threadIdx.x] = t / nrm[threadIdx.x];
+  } else if (threadIdx.x == 0) {
+    const double ref = slot > 0 && isfinite(nrm[0]) ? 1e-20 * nrm[0] : 0.0;
+    nrm[slot] = (isfinite(t) && t > ref) ? t : INFINITY;
+  }
+}
+
+// x = x0 = sum_i coef[i] X_i, i < NB.
+template <int NB>
+__global__ __launch_bounds__(kBlk) void k_pj_combine(long n, PjVecs X, const double* __restrict__ coef,
+                                                     double* __restrict__ x, double* __restrict__ x0) {
+  __shared__ double c[kProjMax];
+  if ((int)threadIdx.x < NB) c[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  for (long e = (long)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    double xv[NB], v = 0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i) xv[i] = X.p[i][e];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v += c[i] * xv[i];
+    x[e] = v;
+    x0[e] = v;
+  }
+}
+
+// v = a - a0 (a0 given) or a - sum_i coef[i] X_i, and Sv = Sa - sum_i coef[i] S X_i (i < NB;
+// v, Sv may be a, Sa); ca, cSa (optional) receive copies of a and Sa.  mode 0: partials of
+// S X_i . v (i < NB) for a second pass; mode 1: partial of v . Sv (the new vector's S-norm
+// squared) into slot 0.
+template <int NB>
+__global__ __launch_bounds__(kBlk) void k_pj_update(long n, PjVecs X, PjVecs SX, const double* coef, const double* a,
+                                                    const double* a0, const double* Sa, double* v, double* Sv,
+                                                    double* ca, double* cSa, int mode, double* __restrict__ part) {
+  __shared__ double c[kProjMax];
+  if ((int)threadIdx.x < NB) c[threadIdx.x] = coef[threadIdx.x];
+  __syncthreads();
+  constexpr int M = NB > 0 ? NB : 1;
+  double acc[M];
+#pragma unroll
+  for (int i = 0; i < M; ++i) acc[i] = 0;
+  for (long e = (long)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    double sx[M], xv[M];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sx[i] = SX.p[i][e];
+    const double ae = a[e], sae = Sa[e];
+    double ve = ae, sve = sae;
+    if (a0) {
+      ve -= a0[e];
+    } else {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) xv[i] = X.p[i][e];
+#pragma unroll
+      for (int i = 0; i < NB; ++i) ve -= c[i] * xv[i];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) sve -= c[i] * sx[i];
+    v[e] = ve;
+    Sv[e] = sve;
+    if (ca) {
+      ca[e] = ae;
+      cSa[e] = sae;
+    }
+    if (mode == 0) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) acc[i] += sx[i] * ve;
+    } else {
+      acc[0] += ve * sve;
+    }
+  }
+  double t;
+  if (mode == 0) t = pj_block_rows<NB>(acc);
+  else t = pj_block_rows<1>(*reinterpret_cast<double(*)[1]>(acc));
+  const int m = mode == 0 ? NB : 1;
+  if ((int)threadIdx.x < m) part[(size_t)blockIdx.x * kProjMax + threadIdx.x] = t;
+}
+
+int pj_grid(long n) { return (int)std::min<long>(kProjGrid, (long)nblk(n, kBlk)); }
+
+// Calls f(std::integral_constant<int, NB>) for NB = nb in [LO, kProjMax].
+template <int NB, typename F>
+static hipError_t pj_dispatch(int nb, F f) {
+  if constexpr (NB > kProjMax) {
+    return hipErrorInvalidValue;
+  } else {
+    if (nb == NB) return f(std::integral_constant<int, NB>{});
+    return pj_dispatch<NB + 1>(nb, f);
+  }
+}
+
+hipError_t launch_pj_dots(long n, int nb, const PjVecs& Y, const double* w, double* part, hipStream_t s) {
+  return pj_dispatch<1>(nb, [&](auto c) {
+    constexpr int NB = decltype(c)::value;
+    hipLaunchKernelGGL((k_pj_dots<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, Y, w, part);
+    return hipGetLastError();
+  });
+}
+hipError_t launch_pj_coef(long n, int nb, int mode, int slot, const double* part, double* nrm, double* coef,
+                          hipStream_t s) {
+  if (slot < 0 || slot >= kProjMax) return hipErrorInvalidValue;
+  return pj_dispatch<1>(mode == 0 ? nb : 1, [&](auto c) {
+    constexpr int M = decltype(c)::value;
+    hipLaunchKernelGGL((k_pj_coef<M>), dim3(1), dim3(kBlk), 0, s, pj_grid(n), mode, slot, part, nrm, coef);
+    return hipGetLastError();
+  });
+}
+hipError_t launch_pj_combine(long n, int nb, const PjVecs& X, const double* coef, double* x, double* x0,
+                             hipStream_t s) {
+  return pj_dispatch<1>(nb, [&](auto c) {
+    constexpr int NB = decltype(c)::value;
+    hipLaunchKernelGGL((k_pj_combine<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, X, coef, x, x0);
+    return hipGetLastError();
+  });
+}
+hipError_t launch_pj_update(long n, int nb, const PjVecs& X, const PjVecs& SX, const double* coef, const double* a,
+                            const double* a0, const double* Sa, double* v, double* Sv, double* ca, double* cSa,
+                            int mode, double* part, hipStream_t s) {
+  if ((ca == nullptr) != (cSa == nullptr)) return hipErrorInvalidValue;
+  return pj_dispatch<0>(nb, [&](auto c) {
+    constexpr int NB = decltype(c)::value;
+    hipLaunchKernelGGL((k_pj_update<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, X, SX, coef, a, a0, Sa, v, Sv, ca,
+                       cSa, mode, part);
+    return hipGetLastError();
+  });
+}
+
 
 __global__ void k_extrapolate(long n, int order, HistPtrs h, double* __restrict__ out) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;

@@ -22,6 +22,7 @@ FP64, MIXED = 0, 1
 JACOBI, BLOCK_JACOBI, AMG = 0, 1, 2
 HISTORY_DEPTH = 6  # DFDG_HISTORY_DEPTH: earlier multipliers kept per stage
 EXTRAPOLATE_ADAPTIVE = 5  # extrapolate="adaptive": order chosen per solve by a one-step backtest
+EXTRAPOLATE_PROJECT = 6  # extrapolate="project": projection onto earlier solutions (S-norm)
 
 
 class DfdgError(RuntimeError):
@@ -232,7 +233,8 @@ class Solver:
         p.cg_rtol, p.cg_maxit = float(cg_rtol), int(cg_maxit)
         p.precond = {"jacobi": JACOBI, "block_jacobi": BLOCK_JACOBI, "amg": AMG}[precond]
         p.ir_rtol, p.inner_rtol = float(ir_rtol), float(inner_rtol)
-        p.extrapolate = EXTRAPOLATE_ADAPTIVE if extrapolate == "adaptive" else int(extrapolate)
+        p.extrapolate = {"adaptive": EXTRAPOLATE_ADAPTIVE, "project": EXTRAPOLATE_PROJECT}.get(extrapolate, extrapolate)
+        p.extrapolate = int(p.extrapolate)
         p.graphs = 1 if graphs else 0
         p.mg_fp32 = 1 if mg_fp32 else 0
         p.mg_fine_fp16 = 1 if mg_fine_fp16 else 0

@@ -100,8 +100,19 @@ def test_param_validation_and_unbound_calls(lib):
     xyz, per = periodic_split_square(2)
     rc, m = _mesh(lib, xyz, per)
     for kw in [dict(k=0), dict(k=4), dict(nu=-1.0), dict(alpha=0.0), dict(precision=7),
-               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=6), dict(extrapolate=-1), dict(graphs=2), dict(mg_fp32=3), dict(mg_fine_fp16=2)]:
+               dict(cg_rtol=0.0), dict(cg_maxit=0), dict(precond=5), dict(extrapolate=7), dict(extrapolate=-1),
+               dict(extrapolate=6, precision=1), dict(graphs=2), dict(mg_fp32=3), dict(mg_fine_fp16=2)]:
         assert _ctx(lib, m, **kw)[0] == -1, kw
+    # projected start values (FP64): accepted, with 65 vectors of n_lambda doubles more workspace
+    rc, c0 = _ctx(lib, m, k=2, extrapolate=5)
+    rc6, c6 = _ctx(lib, m, k=2, extrapolate=6)
+    assert rc == 0 and rc6 == 0
+    b0, b6 = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.dfdg_ctx_workspace_bytes(c0, ctypes.byref(b0)) == 0
+    assert lib.dfdg_ctx_workspace_bytes(c6, ctypes.byref(b6)) == 0
+    assert 65 * 36 * 8 <= b6.value - b0.value <= 65 * 36 * 8 + 256 * 80 + 8 * 512 * 24 + 3 * 8 * 24
+    lib.dfdg_ctx_destroy(c0)
+    lib.dfdg_ctx_destroy(c6)
     rc, c = _ctx(lib, m, k=2)
     assert rc == 0
     s = lib_mod.Sizes()
