@@ -76,7 +76,7 @@ struct dfdg_ctx {
   bool proj_on = false, proj_req = false;
   int proj_nb = 0, proj_raw = 0, proj_head = 0;
   double *pjX[kProjMax] = {}, *pjSX[kProjMax] = {}, *pjRawL[kProjKeep] = {}, *pjRawG[kProjKeep] = {};
-  double *pjx0 = nullptr, *pjnrm = nullptr, *pjcA = nullptr, *pjcB = nullptr, *pjpart = nullptr;
+  double *pjx0 = nullptr, *pjnrm = nullptr, *pjT = nullptr, *pjcA = nullptr, *pjcB = nullptr, *pjpart = nullptr;
   int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
   PcgScalars* pinned = nullptr;
   double* noalloc = nullptr;  // device address of the static scratch of dfdg_diagnostics_noalloc
@@ -460,9 +460,10 @@ static void carve(dfdg_ctx* ctx, char* base) {
     }
     ctx->pjx0 = c.take<double>(nL);
     ctx->pjnrm = c.take<double>(kProjMax);
+    ctx->pjT = c.take<double>((size_t)kProjMax * kProjMax);
     ctx->pjcA = c.take<double>(kProjMax);
     ctx->pjcB = c.take<double>(kProjMax);
-    ctx->pjpart = c.take<double>((size_t)kProjGrid * kProjMax);
+    ctx->pjpart = c.take<double>((size_t)kProjGrid * kProjPart);
   }
   ctx->evaltab = c.take<double>((size_t)kMaxEvalPts * ctx->P);
   const long maxblk = std::max((T + 127) / 128, (E + 255) / 256) + 1;
@@ -889,7 +890,7 @@ static PjVecs pj_vecs(double* const* v, int n) {
 }
 
 // x = the element of span X closest in the S-norm to the solution of S x = g (g in ctx->gv);
-// also kept in pjx0, with its coefficients in pjcA, for proj_push.
+// also kept in pjx0, with its coefficients on the stored vectors in pjcA, for proj_push.
 static int proj_start(dfdg_ctx* ctx, double* x) {
   hipStream_t s = ctx->stream;
   const long n = ctx->nL;
@@ -898,37 +899,30 @@ static int proj_start(dfdg_ctx* ctx, double* x) {
     HIPC(launch_fill(n, 0.0, x, s));
     return DFDG_OK;
   }
-  const PjVecs X = pj_vecs(ctx->pjX, nb);
-  HIPC(launch_pj_dots(n, nb, X, ctx->gv, ctx->pjpart, s));
-  HIPC(launch_pj_coef(n, nb, 0, 0, ctx->pjpart, ctx->pjnrm, ctx->pjcA, s));
-  HIPC(launch_pj_combine(n, nb, X, ctx->pjcA, x, ctx->pjx0, s));
+  const PjVecs B = pj_vecs(ctx->pjX, nb);
+  HIPC(launch_pj_dots(n, nb, B, ctx->gv, ctx->pjpart, s));
+  HIPC(launch_pj_small(n, nb, 0, ctx->pjpart, ctx->pjT, ctx->pjnrm, ctx->pjcA, s));
+  HIPC(launch_pj_combine(n, nb, B, ctx->pjcA, x, ctx->pjx0, s));
   return DFDG_OK;
 }
 
 // Basis vector `slot` from the solution a of S a = Sa (Sa its right-hand side): the part of
-// a S-orthogonal to X_0..X_{slot-1}, by two classical Gram-Schmidt passes (the first with
-// the coefficients of the start value when a0 = the start value is given: a - a0 is then
-// that part up to rounding).  ca, cSa (optional) receive copies of a and Sa.
+// a S-orthogonal to X_0..X_{slot-1}.  First Gram-Schmidt pass on the vectors (with the
+// start value's coefficients when a0 = the start value is given: a - a0 is then that part
+// up to rounding), second pass as a column of T.  ca, cSa (optional) receive copies of a, Sa.
 static int proj_add(dfdg_ctx* ctx, int slot, const double* a, const double* a0, const double* Sa, double* ca,
                     double* cSa) {
   hipStream_t s = ctx->stream;
   const long n = ctx->nL;
-  const PjVecs X = pj_vecs(ctx->pjX, slot), SX = pj_vecs(ctx->pjSX, slot);
-  double* v = ctx->pjX[slot];
-  double* Sv = ctx->pjSX[slot];
-  double* part = ctx->pjpart;
-  if (slot > 0) {
-    if (!a0) {
-      HIPC(launch_pj_dots(n, slot, X, Sa, part, s));
-      HIPC(launch_pj_coef(n, slot, 0, 0, part, ctx->pjnrm, ctx->pjcA, s));
-    }
-    HIPC(launch_pj_update(n, slot, X, SX, ctx->pjcA, a, a0, Sa, v, Sv, ca, cSa, 0, part, s));
-    HIPC(launch_pj_coef(n, slot, 0, 0, part, ctx->pjnrm, ctx->pjcB, s));
-    HIPC(launch_pj_update(n, slot, X, SX, ctx->pjcB, v, nullptr, Sv, v, Sv, nullptr, nullptr, 1, part, s));
-  } else {
-    HIPC(launch_pj_update(n, 0, X, SX, ctx->pjcA, a, nullptr, Sa, v, Sv, ca, cSa, 1, part, s));
+  const PjVecs B = pj_vecs(ctx->pjX, slot), SB = pj_vecs(ctx->pjSX, slot);
+  const double* w = ctx->pjcA;
+  if (slot > 0 && !a0) {
+    HIPC(launch_pj_dots(n, slot, B, Sa, ctx->pjpart, s));
+    HIPC(launch_pj_small(n, slot, 0, ctx->pjpart, ctx->pjT, ctx->pjnrm, ctx->pjcB, s));
+    w = ctx->pjcB;
   }
-  HIPC(launch_pj_coef(n, 1, 1, slot, part, ctx->pjnrm, ctx->pjcB, s));
+  HIPC(launch_pj_update(n, slot, B, SB, w, a, a0, Sa, ctx->pjX[slot], ctx->pjSX[slot], ca, cSa, ctx->pjpart, s));
+  HIPC(launch_pj_small(n, slot, 1, ctx->pjpart, ctx->pjT, ctx->pjnrm, nullptr, s));
   return DFDG_OK;
 }
 
@@ -961,7 +955,7 @@ static int proj_push(dfdg_ctx* ctx, const double* x) {
 
 // Solve S lam = g for the q currently in ctx->q; lam holds the start on entry.  The PCG
 // runs in the fixed buffer lamx (captured graphs keep their arguments).
-static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
+static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info, const double** sol = nullptr) {
   const int NF = ctx->NF;
   const bool bj = ctx->prm.precond == DFDG_BLOCK_JACOBI;
   hipStream_t s = ctx->stream;
@@ -1078,7 +1072,10 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info) {
   // the multiplier is fixed up to the kernel of S: keep the representative orthogonal to
   // it, so that warm starts built from earlier solutions cannot let it drift
   HIPC(launch_deflate(NF, g, x, ctx->pb.gg, s));
-  if (lam != x) HIPC(hipMemcpyAsync(lam, x, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // a projected solve leaves its multiplier in lamx (*sol), which nothing overwrites before
+  // the recovery reads it
+  if (lam != x && !proj) HIPC(hipMemcpyAsync(lam, x, ctx->nL * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (sol) *sol = proj ? x : lam;
   if (proj && inf.status == DFDG_OK && !fin.zero_rhs) {
     const int rc = proj_push(ctx, x);
     if (rc) return rc;
@@ -1094,9 +1091,10 @@ static int mass_solve_impl(dfdg_ctx* ctx, const void* F, bool f32, double* U, do
   HIPC(el_cond_rhs(ctx, f32, F, s));
   if (cold) HIPC(launch_fill(ctx->nL, 0.0, lam, s));
   dfdg_solve_info inf{};
-  int rc = solve_facets(ctx, lam, &inf);
+  const double* sol = lam;
+  int rc = solve_facets(ctx, lam, &inf, &sol);
   if (rc) return rc;
-  HIPC(el_recover(ctx, f32, F, lam, U, mode, ca, Un, cb, Us, dt, s));
+  HIPC(el_recover(ctx, f32, F, sol, U, mode, ca, Un, cb, Us, dt, s));
   if (info) *info = inf;
   return DFDG_OK;
 }

@@ -176,20 +176,28 @@ hipError_t launch_extrapolate_adaptive(long n, int omax, const HistPtrs& h, doub
                                        hipStream_t s);
 hipError_t launch_fill(long n, double v, double* y, hipStream_t s);
 
-// Start values projected onto earlier solutions (S-orthogonal basis X_i with images S X_i
-// and S-norms squared nrm[i]; block partials in part[kProjGrid][kProjMax]).
+// Start values projected onto earlier solutions: basis X = B T of stored vectors B_j with
+// images S B_j, a unit upper triangular T (column-major, kProjMax x kProjMax) and S-norms
+// squared nrm[i]; block partials in part[kProjGrid][kProjPart].
 constexpr int kProjMax = 24;   // basis vectors kept
 constexpr int kProjKeep = 8;   // latest solutions the basis is rebuilt from when full
 constexpr int kProjGrid = 512;
+constexpr int kProjPart = 32;  // >= kProjMax + 1
 struct PjVecs { const double* p[kProjMax]; };
+// part = block partials of Y_i . w, i < nb (1..kProjMax)
 hipError_t launch_pj_dots(long n, int nb, const PjVecs& Y, const double* w, double* part, hipStream_t s);
-hipError_t launch_pj_coef(long n, int nb, int mode, int slot, const double* part, double* nrm, double* coef,
-                          hipStream_t s);
-hipError_t launch_pj_combine(long n, int nb, const PjVecs& X, const double* coef, double* x, double* x0,
+// x = x0 = sum_i w_i B_i, i < nb (1..kProjMax)
+hipError_t launch_pj_combine(long n, int nb, const PjVecs& B, const double* w, double* x, double* x0,
                              hipStream_t s);
-hipError_t launch_pj_update(long n, int nb, const PjVecs& X, const PjVecs& SX, const double* coef, const double* a,
+// v = a - a0 (a0 given) or a - sum_i w_i B_i, Sv = Sa - sum_i w_i S B_i (i < nb <
+// kProjMax); optional copies ca, cSa of a, Sa; partials S B_i . v (i < nb) and v . Sv (nb)
+hipError_t launch_pj_update(long n, int nb, const PjVecs& B, const PjVecs& SB, const double* w, const double* a,
                             const double* a0, const double* Sa, double* v, double* Sv, double* ca, double* cSa,
-                            int mode, double* part, hipStream_t s);
+                            double* part, hipStream_t s);
+// the dense part: mode 0 start-value coefficients w from the partials B_j . g; mode 1
+// column nb of T and nrm[nb] from the partials of launch_pj_update
+hipError_t launch_pj_small(long n, int nb, int mode, const double* part, double* T, double* nrm, double* w,
+                           hipStream_t s);
 // pk[4i..4i+3] = row i of a 4-wide padded matrix packed as above (columns < 65536).
 hipError_t launch_pack_rows(int n, int w, const int* col, const double* val, double inv_scale, uint32_t* pk,
                              hipStream_t s);

@@ -1823,17 +1823,18 @@ __device__ inline double extrapolate_at(int order, Q q) {
 // ---- start values by projection onto earlier solutions (energy norm of S) ---------------
 // The stage solves of a time integration share S; their solutions lie close to the span of
 // the last few.  With a basis X_i of that span, S-orthogonal (X_i . S X_j = 0 for i != j,
-// n_i = X_i . S X_i) and stored with its images S X_i, the element of the span closest to
-// the solution of S x = g in the S-norm is sum_i (X_i . g / n_i) X_i: it needs g, not the
-// solution.  Basis vectors are kept unnormalised; a vector whose n_i failed the test of
-// k_pj_coef has n_i = +inf and drops out of every sum.
+// n_i = X_i . S X_i), the element of the span closest to the solution of S x = g in the
+// S-norm is sum_i (X_i . g / n_i) X_i: it needs g, not the solution.  The basis is kept as
+// X = B T with stored vectors B_j, their images S B_j and a unit upper triangular T (the
+// second Gram-Schmidt pass of each new vector is a column of T, not a pass over the
+// vectors); a vector whose n_i failed the test of k_pj_small has n_i = +inf and drops out.
 
 // Thread i < M of the block gets the block total of acc[i] (others 0).  The kernels below
 // are instantiated for each basis size NB (0..kProjMax), so that the loads of all basis
 // vectors at an entry are issued together.
 template <int M>
-__device__ inline double pj_block_rows(const double (&acc)[M > 0 ? M : 1]) {
-  __shared__ double sh[kBlk / 64][kProjMax];
+__device__ inline double pj_block_rows(const double (&acc)[M]) {
+  __shared__ double sh[kBlk / 64][kProjPart];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < M; ++i) {
@@ -1861,102 +1862,123 @@ __global__ __launch_bounds__(kBlk) void k_pj_dots(long n, PjVecs Y, const double
     for (int i = 0; i < NB; ++i) acc[i] += Y.p[i][e] * we;
   }
   const double t = pj_block_rows<NB>(acc);
-  if ((int)threadIdx.x < NB) part[(size_t)blockIdx.x * kProjMax + threadIdx.x] = t;
+  if ((int)threadIdx.x < NB) part[(size_t)blockIdx.x * kProjPart + threadIdx.x] = t;
 }
 
-// One block.  mode 0 (M = nb): coef[i] = (sum of the G block partials of i) / nrm[i].
-// mode 1 (M = 1): n = the summed partial 0 is the S-norm squared of basis vector `slot`;
-// kept in nrm[slot] when finite and above 1e-20 times n_0 (positive for slot 0), else +inf.
-template <int M>
-__global__ __launch_bounds__(kBlk) void k_pj_coef(int G, int mode, int slot, const double* __restrict__ part,
-                                                  double* __restrict__ nrm, double* __restrict__ coef) {
-  double acc[M];
-#pragma unroll
-  for (int i = 0; i < M; ++i) acc[i] = 0;
-  for (int b = threadIdx.x; b < G; b += blockDim.x)
-#pragma unroll
-    for (int i = 0; i < M; ++i) acc[i] += part[(size_t)b * kProjMax + i];
-  const double t = pj_block_rows<M>(acc);
-  if (mode == 0) {
-    if ((int)threadIdx.x < M) coef[threadIdx.x] = t / nrm[threadIdx.x];
-  } else if (threadIdx.x == 0) {
-    const double ref = slot > 0 && isfinite(nrm[0]) ? 1e-20 * nrm[0] : 0.0;
-    nrm[slot] = (isfinite(t) && t > ref) ? t : INFINITY;
-  }
-}
-
-// x = x0 = sum_i coef[i] X_i, i < NB.
+// x = x0 = sum_i w[i] B_i, i < NB.
 template <int NB>
-__global__ __launch_bounds__(kBlk) void k_pj_combine(long n, PjVecs X, const double* __restrict__ coef,
+__global__ __launch_bounds__(kBlk) void k_pj_combine(long n, PjVecs B, const double* __restrict__ w,
                                                      double* __restrict__ x, double* __restrict__ x0) {
   __shared__ double c[kProjMax];
-  if ((int)threadIdx.x < NB) c[threadIdx.x] = coef[threadIdx.x];
+  if ((int)threadIdx.x < NB) c[threadIdx.x] = w[threadIdx.x];
   __syncthreads();
   for (long e = (long)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    double xv[NB], v = 0;
+    double bv[NB], v = 0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) xv[i] = X.p[i][e];
+    for (int i = 0; i < NB; ++i) bv[i] = B.p[i][e];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) v += c[i] * xv[i];
+    for (int i = 0; i < NB; ++i) v += c[i] * bv[i];
     x[e] = v;
     x0[e] = v;
   }
 }
 
-// v = a - a0 (a0 given) or a - sum_i coef[i] X_i, and Sv = Sa - sum_i coef[i] S X_i (i < NB;
-// v, Sv may be a, Sa); ca, cSa (optional) receive copies of a and Sa.  mode 0: partials of
-// S X_i . v (i < NB) for a second pass; mode 1: partial of v . Sv (the new vector's S-norm
-// squared) into slot 0.
+// New stored vector v = a - a0 (a0 given) or a - sum_i w[i] B_i, Sv = Sa - sum_i w[i] S B_i
+// (i < NB); ca, cSa (optional) receive copies of a and Sa.  Partials: S B_i . v (i < NB)
+// and v . Sv (slot NB).
 template <int NB>
-__global__ __launch_bounds__(kBlk) void k_pj_update(long n, PjVecs X, PjVecs SX, const double* coef, const double* a,
-                                                    const double* a0, const double* Sa, double* v, double* Sv,
-                                                    double* ca, double* cSa, int mode, double* __restrict__ part) {
+__global__ __launch_bounds__(kBlk) void k_pj_update(long n, PjVecs B, PjVecs SB, const double* __restrict__ w,
+                                                    const double* __restrict__ a, const double* __restrict__ a0,
+                                                    const double* __restrict__ Sa, double* __restrict__ v,
+                                                    double* __restrict__ Sv, double* __restrict__ ca,
+                                                    double* __restrict__ cSa, double* __restrict__ part) {
   __shared__ double c[kProjMax];
-  if ((int)threadIdx.x < NB) c[threadIdx.x] = coef[threadIdx.x];
+  if ((int)threadIdx.x < NB) c[threadIdx.x] = w[threadIdx.x];
   __syncthreads();
-  constexpr int M = NB > 0 ? NB : 1;
-  double acc[M];
+  double acc[NB + 1];
 #pragma unroll
-  for (int i = 0; i < M; ++i) acc[i] = 0;
+  for (int i = 0; i <= NB; ++i) acc[i] = 0;
   for (long e = (long)xcd_block() * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-    double sx[M], xv[M];
+    double sb[NB + 1], bv[NB + 1];
 #pragma unroll
-    for (int i = 0; i < NB; ++i) sx[i] = SX.p[i][e];
+    for (int i = 0; i < NB; ++i) sb[i] = SB.p[i][e];
     const double ae = a[e], sae = Sa[e];
     double ve = ae, sve = sae;
     if (a0) {
       ve -= a0[e];
     } else {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) xv[i] = X.p[i][e];
+      for (int i = 0; i < NB; ++i) bv[i] = B.p[i][e];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) ve -= c[i] * xv[i];
+      for (int i = 0; i < NB; ++i) ve -= c[i] * bv[i];
     }
 #pragma unroll
-    for (int i = 0; i < NB; ++i) sve -= c[i] * sx[i];
+    for (int i = 0; i < NB; ++i) sve -= c[i] * sb[i];
     v[e] = ve;
     Sv[e] = sve;
     if (ca) {
       ca[e] = ae;
       cSa[e] = sae;
     }
-    if (mode == 0) {
 #pragma unroll
-      for (int i = 0; i < NB; ++i) acc[i] += sx[i] * ve;
-    } else {
-      acc[0] += ve * sve;
-    }
+    for (int i = 0; i < NB; ++i) acc[i] += sb[i] * ve;
+    acc[NB] += ve * sve;
   }
-  double t;
-  if (mode == 0) t = pj_block_rows<NB>(acc);
-  else t = pj_block_rows<1>(*reinterpret_cast<double(*)[1]>(acc));
-  const int m = mode == 0 ? NB : 1;
-  if ((int)threadIdx.x < m) part[(size_t)blockIdx.x * kProjMax + threadIdx.x] = t;
+  const double t = pj_block_rows<NB + 1>(acc);
+  if ((int)threadIdx.x <= NB) part[(size_t)blockIdx.x * kProjPart + threadIdx.x] = t;
+}
+
+// One block, the small dense part (T column-major, T[j + kProjMax i] = T_ji, norms nrm).
+// mode 0 (start value): d = the summed partials B_j . g (j < nb); y = T^T d, c = y / n,
+//   w = T c: the start value is sum_j w_j B_j.
+// mode 1 (append vector nb): q = the summed partials S B_j . v (j < nb), vv = v . S v;
+//   e = T^T q / n, column nb of T = -T e (diagonal 1), and n_nb = vv - sum_i e_i^2 n_i,
+//   kept when finite and above 1e-20 n_0 (positive for nb = 0), else +inf.
+__global__ __launch_bounds__(kBlk) void k_pj_small(int G, int nb, int mode, const double* __restrict__ part,
+                                                   double* __restrict__ T, double* __restrict__ nrm,
+                                                   double* __restrict__ w) {
+  __shared__ double tot[kProjPart], y[kProjMax], Ts[kProjMax * kProjMax], ns[kProjMax];
+  const int m = mode == 0 ? nb : nb + 1;
+  // T and the norms into LDS: the serial part below then reads no device memory
+  for (int k = threadIdx.x; k < kProjMax * nb; k += blockDim.x) Ts[k] = T[k];
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) ns[k] = nrm[k];
+  // column sums of the G x m partials: a wave per column
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  for (int i = wv; i < m; i += blockDim.x >> 6) {
+    double sacc = 0;
+    for (int b = lane; b < G; b += 64) sacc += part[(size_t)b * kProjPart + i];
+    sacc = wave_sum(sacc);
+    if (lane == 0) tot[i] = sacc;
+  }
+  __syncthreads();
+  // y_i = (T^T tot)_i / n_i (zero for dropped vectors): a thread per i
+  const int t0 = threadIdx.x;
+  if (t0 < nb) {
+    double t = tot[t0];
+    for (int j = 0; j < t0; ++j) t += Ts[j + kProjMax * t0] * tot[j];
+    y[t0] = isfinite(ns[t0]) ? t / ns[t0] : 0.0;
+  }
+  __syncthreads();
+  // (T y)_j: a thread per j; mode 0 returns it as w, mode 1 stores -(T y) as column nb of T
+  if (t0 < nb) {
+    double t = y[t0];
+    for (int i = t0 + 1; i < nb; ++i) t += Ts[t0 + kProjMax * i] * y[i];
+    if (mode == 0) w[t0] = t;
+    else T[t0 + kProjMax * nb] = -t;
+  }
+  if (mode == 1 && t0 == 0) {
+    double nn = tot[nb];
+    for (int i = 0; i < nb; ++i)
+      if (isfinite(ns[i])) nn -= y[i] * y[i] * ns[i];
+    T[nb + kProjMax * nb] = 1.0;
+    const double ref = nb > 0 && isfinite(ns[0]) ? 1e-20 * ns[0] : 0.0;
+    nrm[nb] = (isfinite(nn) && nn > ref) ? nn : INFINITY;
+  }
 }
 
 int pj_grid(long n) { return (int)std::min<long>(kProjGrid, (long)nblk(n, kBlk)); }
 
-// Calls f(std::integral_constant<int, NB>) for NB = nb in [LO, kProjMax].
+// Calls f(std::integral_constant<int, NB>) for NB = nb in [NB, kProjMax].
 template <int NB, typename F>
 static hipError_t pj_dispatch(int nb, F f) {
   if constexpr (NB > kProjMax) {
@@ -1974,33 +1996,34 @@ hipError_t launch_pj_dots(long n, int nb, const PjVecs& Y, const double* w, doub
     return hipGetLastError();
   });
 }
-hipError_t launch_pj_coef(long n, int nb, int mode, int slot, const double* part, double* nrm, double* coef,
-                          hipStream_t s) {
-  if (slot < 0 || slot >= kProjMax) return hipErrorInvalidValue;
-  return pj_dispatch<1>(mode == 0 ? nb : 1, [&](auto c) {
-    constexpr int M = decltype(c)::value;
-    hipLaunchKernelGGL((k_pj_coef<M>), dim3(1), dim3(kBlk), 0, s, pj_grid(n), mode, slot, part, nrm, coef);
-    return hipGetLastError();
-  });
-}
-hipError_t launch_pj_combine(long n, int nb, const PjVecs& X, const double* coef, double* x, double* x0,
+hipError_t launch_pj_combine(long n, int nb, const PjVecs& B, const double* w, double* x, double* x0,
                              hipStream_t s) {
   return pj_dispatch<1>(nb, [&](auto c) {
     constexpr int NB = decltype(c)::value;
-    hipLaunchKernelGGL((k_pj_combine<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, X, coef, x, x0);
+    hipLaunchKernelGGL((k_pj_combine<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, B, w, x, x0);
     return hipGetLastError();
   });
 }
-hipError_t launch_pj_update(long n, int nb, const PjVecs& X, const PjVecs& SX, const double* coef, const double* a,
+hipError_t launch_pj_update(long n, int nb, const PjVecs& B, const PjVecs& SB, const double* w, const double* a,
                             const double* a0, const double* Sa, double* v, double* Sv, double* ca, double* cSa,
-                            int mode, double* part, hipStream_t s) {
+                            double* part, hipStream_t s) {
   if ((ca == nullptr) != (cSa == nullptr)) return hipErrorInvalidValue;
   return pj_dispatch<0>(nb, [&](auto c) {
     constexpr int NB = decltype(c)::value;
-    hipLaunchKernelGGL((k_pj_update<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, X, SX, coef, a, a0, Sa, v, Sv, ca,
-                       cSa, mode, part);
-    return hipGetLastError();
+    if constexpr (NB >= kProjMax) {
+      return hipErrorInvalidValue;  // the new vector takes slot NB
+    } else {
+      hipLaunchKernelGGL((k_pj_update<NB>), dim3(pj_grid(n)), dim3(kBlk), 0, s, n, B, SB, w, a, a0, Sa, v, Sv, ca,
+                         cSa, part);
+      return hipGetLastError();
+    }
   });
+}
+hipError_t launch_pj_small(long n, int nb, int mode, const double* part, double* T, double* nrm, double* w,
+                           hipStream_t s) {
+  if (nb < 0 || nb > kProjMax || (mode == 1 && nb >= kProjMax) || (mode == 0 && nb < 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_pj_small, dim3(1), dim3(kBlk), 0, s, pj_grid(n), nb, mode, part, T, nrm, w);
+  return hipGetLastError();
 }
 
 

@@ -110,7 +110,7 @@ def test_param_validation_and_unbound_calls(lib):
     b0, b6 = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.dfdg_ctx_workspace_bytes(c0, ctypes.byref(b0)) == 0
     assert lib.dfdg_ctx_workspace_bytes(c6, ctypes.byref(b6)) == 0
-    assert 65 * 36 * 8 <= b6.value - b0.value <= 65 * 36 * 8 + 256 * 80 + 8 * 512 * 24 + 3 * 8 * 24
+    assert 65 * 36 * 8 <= b6.value - b0.value <= 65 * 36 * 8 + 256 * 80 + 8 * 512 * 32 + 8 * 24 * 24 + 3 * 8 * 24
     lib.dfdg_ctx_destroy(c0)
     lib.dfdg_ctx_destroy(c6)
     rc, c = _ctx(lib, m, k=2)
