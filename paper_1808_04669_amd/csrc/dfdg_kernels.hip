@@ -1934,7 +1934,8 @@ __global__ __launch_bounds__(kBlk) void k_pj_update(long n, PjVecs B, PjVecs SB,
 // mode 1 (append vector nb): q = the summed partials S B_j . v (j < nb), vv = v . S v;
 //   e = T^T q / n, column nb of T = -T e (diagonal 1), and n_nb = vv - sum_i e_i^2 n_i,
 //   kept when finite and above 1e-20 n_0 (positive for nb = 0), else +inf.
-__global__ __launch_bounds__(kBlk) void k_pj_small(int G, int nb, int mode, const double* __restrict__ part,
+constexpr int kSmallBlk = 1024;
+__global__ __launch_bounds__(kSmallBlk) void k_pj_small(int G, int nb, int mode, const double* __restrict__ part,
                                                    double* __restrict__ T, double* __restrict__ nrm,
                                                    double* __restrict__ w) {
   __shared__ double tot[kProjPart], y[kProjMax], Ts[kProjMax * kProjMax], ns[kProjMax];
@@ -1942,13 +1943,26 @@ __global__ __launch_bounds__(kBlk) void k_pj_small(int G, int nb, int mode, cons
   // T and the norms into LDS: the serial part below then reads no device memory
   for (int k = threadIdx.x; k < kProjMax * nb; k += blockDim.x) Ts[k] = T[k];
   for (int k = threadIdx.x; k < nb; k += blockDim.x) ns[k] = nrm[k];
-  // column sums of the G x m partials: a wave per column
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int i = wv; i < m; i += blockDim.x >> 6) {
-    double sacc = 0;
-    for (int b = lane; b < G; b += 64) sacc += part[(size_t)b * kProjPart + i];
-    sacc = wave_sum(sacc);
-    if (lane == 0) tot[i] = sacc;
+  // column sums of the G x m partials (G <= kProjGrid): thread t sums column t % kProjPart
+  // over the rows congruent to t / kProjPart modulo kRowGroups, all its loads issued at once
+  // (clamped rows, masked sums), then the groups
+  constexpr int kRowGroups = kSmallBlk / kProjPart, kRows = kProjGrid / kRowGroups;
+  __shared__ double grp[kRowGroups][kProjPart];
+  {
+    const int col = threadIdx.x % kProjPart, r0 = threadIdx.x / kProjPart;
+    double v[kRows], t = 0;
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) v[u] = part[(size_t)min(r0 + u * kRowGroups, G - 1) * kProjPart + col];
+#pragma unroll
+    for (int u = 0; u < kRows; ++u) t += r0 + u * kRowGroups < G ? v[u] : 0.0;
+    grp[r0][col] = t;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < m) {
+    double t = 0;
+#pragma unroll
+    for (int r = 0; r < kRowGroups; ++r) t += grp[r][threadIdx.x];
+    tot[threadIdx.x] = t;
   }
   __syncthreads();
   // y_i = (T^T tot)_i / n_i (zero for dropped vectors): a thread per i
@@ -2022,7 +2036,7 @@ hipError_t launch_pj_update(long n, int nb, const PjVecs& B, const PjVecs& SB, c
 hipError_t launch_pj_small(long n, int nb, int mode, const double* part, double* T, double* nrm, double* w,
                            hipStream_t s) {
   if (nb < 0 || nb > kProjMax || (mode == 1 && nb >= kProjMax) || (mode == 0 && nb < 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_pj_small, dim3(1), dim3(kBlk), 0, s, pj_grid(n), nb, mode, part, T, nrm, w);
+  hipLaunchKernelGGL(k_pj_small, dim3(1), dim3(kSmallBlk), 0, s, pj_grid(n), nb, mode, part, T, nrm, w);
   return hipGetLastError();
 }
 
