@@ -24,6 +24,8 @@ struct dfdg_mesh {
 
 constexpr int kHistSlots = 7;
 
+constexpr int kHintRuns = 3;  // PCG runs whose iteration counts size the first chunk
+
 struct dfdg_ctx {
   dfdg_params prm{};
   hipStream_t stream = nullptr;
@@ -77,7 +79,8 @@ struct dfdg_ctx {
   int proj_nb = 0, proj_raw = 0, proj_head = 0;
   double *pjX[kProjMax] = {}, *pjSX[kProjMax] = {}, *pjRawL[kProjKeep] = {}, *pjRawG[kProjKeep] = {};
   double *pjx0 = nullptr, *pjnrm = nullptr, *pjT = nullptr, *pjcA = nullptr, *pjcB = nullptr, *pjpart = nullptr;
-  int iters_hint[2] = {0, 0};  // iterations of the last run (FP64 solve / FP32 inner solve)
+  // iterations of the last kHintRuns runs, newest first (FP64 solve / FP32 inner solve)
+  int iters_hint[2][kHintRuns] = {};
   PcgScalars* pinned = nullptr;
   double* noalloc = nullptr;  // device address of the static scratch of dfdg_diagnostics_noalloc
   std::string err;
@@ -848,7 +851,14 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
   // the stopping test, so a run of n iterations takes n launches; otherwise the next
   // iteration's first kernel applies it and a run takes n + 1
   const int extra = (amg && ctx->mg.nlev >= 2) ? 0 : 1;
-  int chunk = *hint > 0 ? *hint + extra : (amg ? 16 : 64);
+  // the first chunk: the fewest iterations among the last kHintRuns runs.  With start
+  // values that vary in quality the count varies from solve to solve; a chunk that falls
+  // short costs one host round trip, while each iteration enqueued past the end still runs
+  // the multigrid cycle's loads (its kernels test the stop flag only before their stores)
+  int h = hint[0];
+  for (int j = 1; j < kHintRuns; ++j)
+    if (hint[j] > 0) h = std::min(h, hint[j]);
+  int chunk = h > 0 ? h + extra : (amg ? 16 : 64);
   fin.done = PCG_RUNNING;
   int launched = 0;
   while (fin.done == PCG_RUNNING) {
@@ -878,7 +888,8 @@ static int pcg_loop(dfdg_ctx* ctx, PcgScalars* sc, int maxit, Step step, hipGrap
     }
     chunk = std::min(std::max(next, 1), 1024);
   }
-  *hint = fin.iters;
+  for (int j = kHintRuns - 1; j > 0; --j) hint[j] = hint[j - 1];
+  hint[0] = fin.iters;
   return DFDG_OK;
 }
 
@@ -1007,7 +1018,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info, const
       if (c32) return launch_vcycle<float, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
       return launch_vcycle<double, double>(NF, g, A, ctx->mg, ctx->r, ctx->z, pb.rz[it & 1], pb.sc, st);
     };
-    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, ctx->graph64, &ctx->iters_hint[0], fin);
+    int rc = pcg_loop(ctx, pb.sc, ctx->prm.cg_maxit, step, ctx->graph64, ctx->iters_hint[0], fin);
     if (rc) return rc;
     inf.iterations = fin.iters;
     inf.refinements = mixed ? fin.iters : 0;  // each outer FP64 iteration refines once
@@ -1047,7 +1058,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info, const
       if (nref >= 30 || total >= ctx->prm.cg_maxit) { st = DFDG_E_NOT_CONVERGED; break; }
       HIPC(launch_pcg32_init(NF, bj, g, A, ctx->r64, ctx->x32, ctx->r32, ctx->z32, ctx->p32[0], pi, s));
       if (amg) HIPC((launch_vcycle<float, float>(NF, g, A, ctx->mg, ctx->r32, ctx->z32, pi.rz[0], pi.sc, s)));
-      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, ctx->graph32, &ctx->iters_hint[1], fin);
+      rc = pcg_loop(ctx, pi.sc, ctx->prm.cg_maxit - total, step, ctx->graph32, ctx->iters_hint[1], fin);
       if (rc) return rc;
       total += fin.iters;
       ++nref;
