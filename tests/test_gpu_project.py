@@ -23,15 +23,19 @@ def _log(*a):
 @pytest.mark.parametrize("dim,k,N,kind,precond", [
     (2, 2, 8, "periodic", "amg"), (2, 1, 10, "periodic", "jacobi"), (2, 3, 5, "walls", "amg"),
     (2, 2, 6, "inout", "amg"), (3, 1, 3, "periodic", "amg"), (3, 2, 2, "walls", "jacobi"),
+    (3, 2, 2, "inout", "amg_mf"),
 ])
 def test_project_rk3_trajectory_parity(dim, k, N, kind, precond):
-    """Twelve steps (36 solves: the basis fills and is rebuilt) against the oracle."""
+    """Twelve steps (36 solves: the basis fills and is rebuilt) against the oracle (on
+    tetrahedra also with the matrix-free product of the facet system)."""
     _log("project rk3", dim, k, N, kind, precond)
+    mf = precond.endswith("_mf")
+    precond = precond.replace("_mf", "")
     lift = {2: lambda x, y: (0.8 + 0 * x, 0.15 + 0 * y),
             3: lambda x, y, z: (0.8 + 0 * x, 0.15 + 0 * y, -0.1 + 0 * z)}[dim]
     extra = dict(walls=True) if kind == "walls" else dict(inout=True, inflow=lift) if kind == "inout" else {}
     orc, s, _, _ = make_pair(N, k, nu=1e-3, dim=dim, order="random", seed=N, cg_rtol=1e-13, precond=precond,
-                             extrapolate="project", **extra)
+                             extrapolate="project", matrix_free=mf, **extra)
     f = RandomStreamField(seed=3, kmax=2, norm=0.5) if dim == 2 else RandomVectorPotentialField(seed=3, kmax=2, norm=0.5)
     U0 = orc.project(f)
     U = transfer(orc, U0, s)
