@@ -341,6 +341,12 @@ int dfdg_rk3_step_vjp(dfdg_ctx* ctx, const double* Un_dev, double* Ubar_io_dev, 
                       dfdg_step_info* info);
 int dfdg_rk3_step_vjp_stages(dfdg_ctx* ctx, const double* Un_dev, const double* U1_dev,
                              const double* U2_dev, double* Ubar_io_dev, double dt, dfdg_step_info* info);
+/* dfdg_energy_vjp: Ubar_dev = Ebar U_dev, the cotangent of the kinetic energy
+ *   E = 1/2 int |u|^2 (the energy of Sec. 4, Example 2; dfdg_diagnostics' energy) for a scalar
+ *   cotangent Ebar: the broken basis is orthonormal (M_T = I), so E = 1/2 U . U and
+ *   dE/dU = U.  U_dev and Ubar_dev hold n_broken doubles and may be the same buffer;
+ *   asynchronous on the context stream. */
+int dfdg_energy_vjp(dfdg_ctx* ctx, const double* U_dev, double Ebar, double* Ubar_dev);
 
 /* ---- diagnostics and evaluation (a10) -----------------------------------------------
  * dfdg_eval: values out_dev[d][npts][T] of U at reference points ref_pts_host[npts][d]

@@ -106,9 +106,25 @@ class Rollout(torch.autograd.Function):
         return Ubar, None, None, None, None, None
 
 
+class KineticEnergy(torch.autograd.Function):
+    """E = 1/2 int |u|^2 of a state (dfdg_diagnostics), with its cotangent from
+    dfdg_energy_vjp."""
+
+    @staticmethod
+    def forward(ctx, U, solver):
+        ctx.solver = solver
+        ctx.save_for_backward(U)
+        return torch.tensor(solver.diagnostics(U)["energy"], dtype=torch.float64, device=U.device)
+
+    @staticmethod
+    def backward(ctx, gE):
+        (U,) = ctx.saved_tensors
+        return ctx.solver.energy_vjp(U, float(gE)), None
+
+
 def final_energy(solver, U0, dt, steps, checkpoint_every=10, recompute_solver=None):
     """E = 1/2 ||u_N||^2 (the basis is orthonormal), differentiable w.r.t. U0.
     recompute_solver: optional second context (same mesh and parameters, another stream)
     that recomputes checkpoint segments concurrently with the reverse sweep."""
     UN = Rollout.apply(U0, solver, dt, steps, checkpoint_every, recompute_solver)
-    return 0.5 * (UN * UN).sum()
+    return KineticEnergy.apply(UN, solver)

@@ -1450,6 +1450,15 @@ static int rk3_vjp_core(dfdg_ctx* ctx, const double* Un, const double* U1, const
   return DFDG_OK;
 }
 
+// Cotangent of E = 1/2 U . U (orthonormal broken basis: the kinetic energy of the state).
+extern "C" int dfdg_energy_vjp(dfdg_ctx* ctx, const double* U, double Ebar, double* Ubar) {
+  NEED_BOUND(ctx);
+  if (!U || !Ubar) return fail(ctx, DFDG_E_INVALID_ARG, "null pointer");
+  if (!std::isfinite(Ebar)) return fail(ctx, DFDG_E_INVALID_ARG, "Ebar must be finite");
+  HIPC(launch_axpby(ctx->nU, Ebar, U, 0.0, Ubar, ctx->stream));
+  return DFDG_OK;
+}
+
 static int vjp_info(dfdg_ctx* ctx, const dfdg_solve_info (&si)[3], const dfdg_solve_info* fw, int nfw,
                     dfdg_step_info* info) {
   dfdg_step_info st{};

@@ -106,6 +106,7 @@ _SIGS = {
     "dfdg_dg_residual_vjp": (ctypes.c_int, [_P, _P, _P, _P]),
     "dfdg_rk3_step_vjp": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
     "dfdg_rk3_step_vjp_stages": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_double, ctypes.POINTER(StepInfo)]),
+    "dfdg_energy_vjp": (ctypes.c_int, [_P, _P, ctypes.c_double, _P]),
     "dfdg_diagnostics": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
     "dfdg_diagnostics_noalloc": (ctypes.c_int, [_P, _P, ctypes.POINTER(Diag)]),
     "dfdg_eval": (ctypes.c_int, [_P, _P, ctypes.c_int, _P, _P]),
@@ -402,6 +403,13 @@ class Solver:
                                                 self._vec(Ubar, self.n_broken, "Ubar"), ctypes.c_double(dt),
                                                 ctypes.byref(info)))
         return info
+
+    def energy_vjp(self, U, Ebar, Ubar=None):
+        """dfdg_energy_vjp: the cotangent Ebar U of the kinetic energy 1/2 U . U."""
+        Ubar = self.new_vector() if Ubar is None else Ubar
+        self._check(self._lib.dfdg_energy_vjp(self._h, self._vec(U, self.n_broken, "U"), ctypes.c_double(Ebar),
+                                              self._vec(Ubar, self.n_broken, "Ubar")))
+        return Ubar
 
     def rk3_step_vjp_stages(self, Un, U1, U2, Ubar, dt):
         """rk3_step_vjp with the stage states given (from rk3_step_stages)."""

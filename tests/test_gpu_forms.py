@@ -231,6 +231,22 @@ def test_energy_gradient_vs_oracle_and_fd(precond):
         assert abs(gpu - fd) < 1e-6 * abs(fd) + 1e-10
 
 
+def test_energy_and_its_cotangent_from_the_library():
+    """The objective of the adjoint form: dfdg_diagnostics' energy is 1/2 U . U (orthonormal
+    broken basis), and dfdg_energy_vjp gives Ebar U exactly (also in place)."""
+    from paper_1808_04669_amd.adjoint import KineticEnergy
+    orc, s, _, _ = make_pair(6, 2, order="random", seed=3)
+    U = transfer(orc, orc.project(RandomStreamField(seed=0, kmax=3)), s)
+    E = KineticEnergy.apply(U, s).item()
+    ref = 0.5 * torch.dot(U, U).item()
+    assert abs(E - ref) < 1e-14 * ref and abs(E - orc.energy(orc.project(RandomStreamField(seed=0, kmax=3)))) < 1e-12 * ref
+    Ub = s.energy_vjp(U, 2.5)
+    assert torch.equal(Ub, 2.5 * U)
+    V = U.clone()
+    s.energy_vjp(V, -0.5, V)
+    assert torch.equal(V, -0.5 * U)
+
+
 def test_adaptive_warm_start_order():
     """Adaptive warm starts (the extrapolation order chosen on the device per solve by a
     one-step backtest): identical runs are bitwise equal, the trajectory equals a

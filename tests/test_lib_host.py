@@ -468,6 +468,7 @@ def test_binding_covers_the_entry_points():
                "dfdg_reset_adjoint_history": "reset_adjoint_history", "dfdg_history_save": "history_save",
                "dfdg_history_restore": "history_restore", "dfdg_dg_residual_vjp": "residual_vjp",
                "dfdg_rk3_step_vjp": "rk3_step_vjp", "dfdg_rk3_step_vjp_stages": "rk3_step_vjp_stages",
+               "dfdg_energy_vjp": "energy_vjp",
                "dfdg_diagnostics": "diagnostics", "dfdg_eval": "eval", "dfdg_time_kernel": "time_kernel",
                "dfdg_proj_rule": "proj_rule"}
     for sym, meth in methods.items():
