@@ -992,7 +992,7 @@ static int solve_facets(dfdg_ctx* ctx, double* lam, dfdg_solve_info* info, const
       const int rc = proj_start(ctx, x);
       if (rc) return rc;
     }
-    HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s));
+    HIPC(launch_pcg_init(NF, bj, g, A, ctx->gv, x, ctx->r, ctx->z, ctx->p[0], pb, s, !proj));
     const bool c32 = mixed || ctx->prm.mg_fp32 != 0;
     const bool fused = amg && ctx->mg.nlev >= 2;
     if (amg) {

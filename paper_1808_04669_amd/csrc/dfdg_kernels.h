@@ -125,7 +125,7 @@ hipError_t launch_gather_g(int NF, const DevGeo& g, const double* q, double* gv,
                            int maxit, hipStream_t s);
 // r = g - zg zdef - S x, z = M^{-1} r, p_old = 0; partials of iteration 0.
 hipError_t launch_pcg_init(int NF, bool block_jacobi, const DevGeo& g, const DevBsr& A, const double* gv, double* x,
-                           double* r, double* z, double* p_old, const PcgBufs& pb, hipStream_t s);
+                           double* r, double* z, double* p_old, const PcgBufs& pb, hipStream_t s, bool deflate_start = true);
 // Iteration it >= 1: stopping test on iteration it-1, beta, p_new = z + beta p_old, Sp = S p_new.
 // `it` selects the parity of the partial buffers (the kernels read the iteration count
 // itself from pb.sc, so a captured launch sequence can be replayed).

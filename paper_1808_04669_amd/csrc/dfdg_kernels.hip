@@ -2231,13 +2231,16 @@ hipError_t launch_deflate(int NF, const DevGeo& g, double* x, double* part, hipS
 }
 
 hipError_t launch_pcg_init(int NF, bool bj, const DevGeo& g, const DevBsr& A, const double* gv, double* x, double* r,
-                           double* z, double* p_old, const PcgBufs& pb, hipStream_t s) {
+                           double* z, double* p_old, const PcgBufs& pb, hipStream_t s, bool deflate_start) {
   const int G = g.fgrid;
   // the start without its kernel component (a start far along it would leave a kernel
-  // component of its rounding in r that no iteration removes), then r and its deflation;
-  // the right-hand side's partials in pb.gg are consumed by now and hold (z, .) partials
-  hipError_t e = launch_deflate(NF, g, x, pb.gg, s);
-  if (e != hipSuccess) return e;
+  // component of its rounding in r that no iteration removes; a combination of earlier,
+  // deflated solutions has none to remove), then r and its deflation; the right-hand
+  // side's partials in pb.gg are consumed by now and hold (z, .) partials
+  if (deflate_start) {
+    hipError_t e = launch_deflate(NF, g, x, pb.gg, s);
+    if (e != hipSuccess) return e;
+  }
   DFDG_DISPATCH_NFS(NF, A.ns, hipLaunchKernelGGL((k_pcg_init<NN, SS>), dim3(G), dim3(kBlk), 0, s, g, A, gv, x, r, z,
                                                  p_old, (const PcgScalars*)pb.sc, pb.gg));
   DFDG_DISPATCH_NF(NF, {
