@@ -1941,7 +1941,8 @@ __global__ __launch_bounds__(kSmallBlk) void k_pj_small(int G, int nb, int mode,
   __shared__ double tot[kProjPart], y[kProjMax], Ts[kProjMax * kProjMax], ns[kProjMax];
   const int m = mode == 0 ? nb : nb + 1;
   // T and the norms into LDS: the serial part below then reads no device memory
-  for (int k = threadIdx.x; k < kProjMax * nb; k += blockDim.x) Ts[k] = T[k];
+  for (int k = threadIdx.x; k < kProjMax * nb; k += blockDim.x)
+    if (k % kProjMax < k / kProjMax) Ts[k] = T[k];  // T_ji, j < i: the part written and read
   for (int k = threadIdx.x; k < nb; k += blockDim.x) ns[k] = nrm[k];
   // column sums of the G x m partials (G <= kProjGrid): thread t sums column t % kProjPart
   // over the rows congruent to t / kProjPart modulo kRowGroups, all its loads issued at once
@@ -1951,10 +1952,12 @@ __global__ __launch_bounds__(kSmallBlk) void k_pj_small(int G, int nb, int mode,
   {
     const int col = threadIdx.x % kProjPart, r0 = threadIdx.x / kProjPart;
     double v[kRows], t = 0;
+    if (col < m) {  // columns in use only (the others were never written)
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) v[u] = part[(size_t)min(r0 + u * kRowGroups, G - 1) * kProjPart + col];
+      for (int u = 0; u < kRows; ++u) v[u] = part[(size_t)min(r0 + u * kRowGroups, G - 1) * kProjPart + col];
 #pragma unroll
-    for (int u = 0; u < kRows; ++u) t += r0 + u * kRowGroups < G ? v[u] : 0.0;
+      for (int u = 0; u < kRows; ++u) t += r0 + u * kRowGroups < G ? v[u] : 0.0;
+    }
     grp[r0][col] = t;
   }
   __syncthreads();
