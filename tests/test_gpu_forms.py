@@ -245,6 +245,9 @@ def test_energy_and_its_cotangent_from_the_library():
     V = U.clone()
     s.energy_vjp(V, -0.5, V)
     assert torch.equal(V, -0.5 * U)
+    from paper_1808_04669_amd.dfdg import DfdgError
+    with pytest.raises(DfdgError):
+        s.energy_vjp(U, float("nan"))
 
 
 def test_adaptive_warm_start_order():

@@ -129,6 +129,8 @@ def test_param_validation_and_unbound_calls(lib):
     # entry points refuse to run without a workspace
     assert lib.dfdg_dg_residual(c, P_(0x100000), P_(0x100000)) == -3
     assert lib.dfdg_rk3_step(c, P_(0x100000), ctypes.c_double(0.1), None) == -3
+    assert lib.dfdg_energy_vjp(c, P_(0x100000), ctypes.c_double(1.0), P_(0x100000)) == -3
+    assert lib.dfdg_dg_residual_vjp(c, P_(0x100000), P_(0x100000), P_(0x100000)) == -3
     assert b"workspace" in lib.dfdg_last_error(c)
     lib.dfdg_ctx_destroy(c)
     lib.dfdg_mesh_destroy(m)
