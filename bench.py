@@ -460,7 +460,8 @@ def main():
     U, vmax, pinfo = project_field(s, double_shear_layer)
     dt = 0.1 * (1.0 / N) / (k ** 2 * vmax)
     log(f"workload: N={N} k={k} T={s.T} E={s.E} N_u={s.n_bdm} dt={dt:.4e} projection iters={pinfo.iterations}")
-    t, its = timed_run(s, U, dt, args.steps, args.warmup)
+    r0 = []
+    t, its = timed_run(s, U, dt, args.steps, args.warmup, r0)
     value = s.n_bdm * 3 * args.steps / t
     d = s.diagnostics(U)
     log(f"fp64: {t:.3f} s for {args.steps} steps, mean PCG iterations/stage {its.mean():.1f}, diag {d}")
@@ -491,6 +492,7 @@ def main():
                       "N": N, "k": k, "N_u": s.n_bdm, "T": s.T, "E": s.E, "precond": args.precond,
                       "extrapolate": args.extrapolate, "order": args.order},
            "pcg_iterations_per_stage": {"mean": float(its.mean()), "max": int(its.max()), "min": int(its.min())},
+           "start_rel_residual_geomean": float(np.exp(np.mean(np.log(np.maximum(r0, 1e-300))))),
            "diagnostics_final": d,
            "setup_s": s.setup_seconds,
            "roofline": roof}
